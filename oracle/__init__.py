@@ -1,0 +1,370 @@
+"""FP64 CPU oracle for the Gaussian X-ray rasterizer and voxelizer.
+
+TEST INFRASTRUCTURE ONLY. The test suite, the smoke check and the
+benchmark's CPU-baseline leg are the only callers. The product path (the
+HIP library and its Python binding) never imports this package, and this
+package never imports the product: the two share nothing but the seeded
+input generators in ``synth_inputs``.
+
+The numerical core is ``oracle.c`` (plain double-precision C, built with
+gcc into ``liboracle.so``); this module wraps it with ctypes and adds the
+pieces that are clearer in NumPy: Gauss-Legendre quadrature of the ray
+integral (Eq. 3), the integer tile-binning reference, the L1 loss and its
+gradient (Eq. 5), Adam, PSNR and finite differences.
+
+Parity status of each function (what pins it in ``tests/test_oracle_pins.py``):
+
+* ``project`` / ``project_points`` (Eq. 4, method splat M): pinned by
+  parallel-beam equality with the exact line integral and quadrature, by the
+  mu identity at the splat centre in cone beam, by the small-Gaussian limit
+  M -> E, by the 2D splat-mass closed form and by brute force.
+* ``exact_points`` (Eq. 3): pinned by quadrature.
+* ``voxelize`` (Eq. 2, Sec. 3.3): pinned by the 3D mass closed form and
+  brute force.
+* ``project_bwd`` / ``voxelize_bwd``: pinned by Richardson finite
+  differences of the forward functions.
+* ``phantom_project`` / ``phantom_volume``: pinned by the sphere chord and
+  by quadrature of the indicator.
+* ``bin_tiles``: pinned by the superset property against FP64 support pairs.
+* ``l1_loss_grad``, ``adam_step``, ``psnr``: pinned by hand-computed values.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+KAPPA = 3.0
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so with gcc (OpenMP, -O2, no fast-math)."""
+    src = os.path.join(_HERE, "oracle.c")
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                               "-ffp-contract=off", src, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        _lib = ctypes.CDLL(_LIB_PATH)
+    return _lib
+
+
+def _d(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _geom_vec(geom: dict) -> np.ndarray:
+    return np.array([1.0 if geom["mode"] == "parallel" else 0.0, geom["sod"], geom["sdd"],
+                     geom["det_w"], geom["det_h"], geom["pitch_u"], geom["pitch_v"],
+                     geom["off_u"], geom["off_v"], geom["near"]], dtype=np.float64)
+
+
+def _grid_vec(grid: dict) -> np.ndarray:
+    return np.array(list(grid["origin"]) + list(grid["spacing"]) + list(grid["dims"]),
+                    dtype=np.float64)
+
+
+def _gauss_args(gs: dict):
+    n = gs["density"].shape[0]
+    keep = []
+    ptrs = []
+    for k in ("mean", "log_scale", "quat", "density"):
+        a, p = _d(gs[k])
+        keep.append(a)
+        ptrs.append(p)
+    return n, keep, ptrs
+
+
+# ---------------------------------------------------------------- Eq. 4 (M)
+
+def splat_records(gs: dict, geom: dict, angles) -> dict:
+    """Per-(view, Gaussian) splat quantities, record r = v * n + i."""
+    lib = _load()
+    n, keep, p = _gauss_args(gs)
+    ang, pa = _d(angles)
+    V = ang.shape[0]
+    R = V * n
+    uv = np.zeros(2 * R); sh = np.zeros(3 * R); co = np.zeros(3 * R)
+    mu = np.zeros(R); w = np.zeros(R); cul = np.zeros(R, dtype=np.int32)
+    g, pg = _d(_geom_vec(geom))
+    lib.orc_splat_records(pg, ctypes.c_int(V), pa, ctypes.c_long(n), *p,
+                          _ptr(uv),
+                          _ptr(sh), _ptr(co), _ptr(mu), _ptr(w),
+                          cul.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    return dict(uv=uv.reshape(R, 2), shat=sh.reshape(R, 3), conic=co.reshape(R, 3), mu=mu, w=w,
+                culled=cul.astype(bool))
+
+
+def project(gs: dict, geom: dict, angles, kappa: float = KAPPA, brute: bool = False) -> np.ndarray:
+    """Method projection M for every pixel of every view: [V][H][W] float64."""
+    lib = _load()
+    n, keep, p = _gauss_args(gs)
+    ang, pa = _d(angles)
+    V = ang.shape[0]
+    img = np.zeros((V, geom["det_h"], geom["det_w"]))
+    g, pg = _d(_geom_vec(geom))
+    fn = lib.orc_project_brute if brute else lib.orc_project
+    fn(pg, ctypes.c_double(kappa), ctypes.c_int(V), pa, ctypes.c_long(n), *p,
+       img.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return img
+
+
+def project_points(gs: dict, geom: dict, angle: float, u, v, kappa: float = KAPPA) -> np.ndarray:
+    """M of one view at arbitrary detector points (pixel coordinates)."""
+    lib = _load()
+    n, keep, p = _gauss_args(gs)
+    uu, pu = _d(u); vv, pv = _d(v)
+    out = np.zeros(uu.shape[0])
+    g, pg = _d(_geom_vec(geom))
+    lib.orc_project_points(pg, ctypes.c_double(kappa), ctypes.c_double(angle), ctypes.c_long(n), *p,
+                           ctypes.c_long(uu.shape[0]), pu, pv,
+                           out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return out
+
+
+# ---------------------------------------------------------------- Eq. 3 (E)
+
+def exact_points(gs: dict, geom: dict, angle: float, u, v) -> np.ndarray:
+    """Exact line integral of the Gaussian field (no cutoff) along the ray
+    through each detector point."""
+    lib = _load()
+    n, keep, p = _gauss_args(gs)
+    uu, pu = _d(u); vv, pv = _d(v)
+    out = np.zeros(uu.shape[0])
+    g, pg = _d(_geom_vec(geom))
+    lib.orc_exact_points(pg, ctypes.c_double(angle), ctypes.c_long(n), *p, ctypes.c_long(uu.shape[0]),
+                         pu, pv, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return out
+
+
+def rays(geom: dict, angle: float, u, v):
+    """Origin and unit direction of the ray through each detector point."""
+    lib = _load()
+    uu, pu = _d(u); vv, pv = _d(v)
+    m = uu.shape[0]
+    o = np.zeros(3 * m); d = np.zeros(3 * m)
+    g, pg = _d(_geom_vec(geom))
+    lib.orc_rays(pg, ctypes.c_double(angle), ctypes.c_long(m), pu, pv,
+                 o.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                 d.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return o.reshape(m, 3), d.reshape(m, 3)
+
+
+def field_points(gs: dict, x, kappa: float = float("inf")) -> np.ndarray:
+    """Density field sigma(x) (Eq. 2) at points x[m][3]; kappa=inf: no cutoff."""
+    lib = _load()
+    n, keep, p = _gauss_args(gs)
+    xx, px = _d(np.asarray(x).reshape(-1, 3))
+    out = np.zeros(xx.shape[0])
+    lib.orc_field_points(ctypes.c_double(kappa), ctypes.c_long(n), *p, ctypes.c_long(xx.shape[0]), px,
+                         out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return out
+
+
+def quadrature_points(gs: dict, geom: dict, angle: float, u, v, t_lo: float, t_hi: float,
+                      order: int = 400, panels: int = 8) -> np.ndarray:
+    """Composite Gauss-Legendre quadrature of Eq. 3 along each ray over the
+    ray parameter interval [t_lo, t_hi] (no cutoff)."""
+    o, d = rays(geom, angle, u, v)
+    xg, wg = np.polynomial.legendre.leggauss(order)
+    edges = np.linspace(t_lo, t_hi, panels + 1)
+    ts, ws = [], []
+    for a, b in zip(edges[:-1], edges[1:]):
+        ts.append(0.5 * (b - a) * xg + 0.5 * (a + b))
+        ws.append(0.5 * (b - a) * wg)
+    ts = np.concatenate(ts); ws = np.concatenate(ws)
+    out = np.zeros(o.shape[0])
+    for k in range(o.shape[0]):
+        pts = o[k][None, :] + ts[:, None] * d[k][None, :]
+        out[k] = np.dot(ws, field_points(gs, pts))
+    return out
+
+
+# ---------------------------------------------------------------- voxelizer
+
+def voxelize(gs: dict, grid: dict, kappa: float = KAPPA, brute: bool = False) -> np.ndarray:
+    """Density sum at voxel centres: [nz][ny][nx] float64."""
+    lib = _load()
+    n, keep, p = _gauss_args(gs)
+    nx, ny, nz = grid["dims"]
+    vol = np.zeros((nz, ny, nx))
+    gr, pgr = _d(_grid_vec(grid))
+    fn = lib.orc_voxelize_brute if brute else lib.orc_voxelize
+    fn(ctypes.c_double(kappa), pgr, ctypes.c_long(n), *p,
+       vol.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return vol
+
+
+# ---------------------------------------------------------------- gradients
+
+def _bwd_out(n_sel):
+    return (np.zeros((3, n_sel)), np.zeros((3, n_sel)), np.zeros((4, n_sel)), np.zeros(n_sel))
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def project_bwd(gs: dict, geom: dict, angles, grad_img, kappa: float = KAPPA, sel=None) -> dict:
+    """Gradient of sum(grad_img * M) w.r.t. mean, log_scale, quat, density of
+    the Gaussians in ``sel`` (default all), support held fixed."""
+    lib = _load()
+    n, keep, p = _gauss_args(gs)
+    ang, pa = _d(angles)
+    gi, pgi = _d(grad_img)
+    sel = np.arange(n, dtype=np.int64) if sel is None else np.ascontiguousarray(sel, dtype=np.int64)
+    dm, dl, dq, dr = _bwd_out(sel.shape[0])
+    g, pg = _d(_geom_vec(geom))
+    lib.orc_project_bwd(pg, ctypes.c_double(kappa), ctypes.c_int(ang.shape[0]), pa, ctypes.c_long(n), *p,
+                        pgi, ctypes.c_long(sel.shape[0]), sel.ctypes.data_as(ctypes.POINTER(ctypes.c_long)),
+                        _ptr(dm), _ptr(dl), _ptr(dq), _ptr(dr))
+    return dict(mean=dm, log_scale=dl, quat=dq, density=dr)
+
+
+def voxelize_bwd(gs: dict, grid: dict, grad_vol, kappa: float = KAPPA, sel=None) -> dict:
+    lib = _load()
+    n, keep, p = _gauss_args(gs)
+    gv, pgv = _d(grad_vol)
+    gr, pgr = _d(_grid_vec(grid))
+    sel = np.arange(n, dtype=np.int64) if sel is None else np.ascontiguousarray(sel, dtype=np.int64)
+    dm, dl, dq, dr = _bwd_out(sel.shape[0])
+    lib.orc_voxelize_bwd(ctypes.c_double(kappa), pgr, ctypes.c_long(n), *p, pgv, ctypes.c_long(sel.shape[0]),
+                         sel.ctypes.data_as(ctypes.POINTER(ctypes.c_long)),
+                         _ptr(dm), _ptr(dl), _ptr(dq), _ptr(dr))
+    return dict(mean=dm, log_scale=dl, quat=dq, density=dr)
+
+
+# ---------------------------------------------------------------- phantom
+
+def _phantom_args(ph: dict):
+    keep = [np.ascontiguousarray(ph[k], dtype=np.float64) for k in ("centre", "semi", "quat", "amp")]
+    return keep, [_ptr(a) for a in keep]
+
+
+def phantom_volume(ph: dict, grid: dict) -> np.ndarray:
+    lib = _load()
+    keep, p = _phantom_args(ph)
+    nx, ny, nz = grid["dims"]
+    vol = np.zeros((nz, ny, nx))
+    gr, pgr = _d(_grid_vec(grid))
+    lib.orc_phantom_volume(ctypes.c_long(ph["amp"].shape[0]), *p, pgr, _ptr(vol))
+    return vol
+
+
+def phantom_project(ph: dict, geom: dict, angles) -> np.ndarray:
+    lib = _load()
+    keep, p = _phantom_args(ph)
+    ang, pa = _d(angles)
+    img = np.zeros((ang.shape[0], geom["det_h"], geom["det_w"]))
+    g, pg = _d(_geom_vec(geom))
+    lib.orc_phantom_project(pg, ctypes.c_int(ang.shape[0]), pa, ctypes.c_long(ph["amp"].shape[0]), *p,
+                            _ptr(img))
+    return img
+
+
+# ---------------------------------------------------------------- binning
+
+def bin_tiles(uv32, r32, det_w: int, det_h: int, tile: int = 16, cull=None, n_views: int = 1):
+    """Integer tile binning from FP32 splat centres and support half-extents.
+
+    uv32[R][2], r32[R][2] are float32 (centre and kappa-scaled half-extents in
+    pixels). A record covers the tiles whose pixel-centre columns lie in
+    [floor(u - ru - 1/2), floor(u + ru - 1/2)] (and likewise for rows),
+    clipped to the image; all arithmetic is float32 subtraction followed by
+    floor, the same decision the GPU takes. Records are r = v * n + i.
+    Returns dict with rect[R][4] (tx0, ty0, tx1, ty1; empty when tx0 > tx1),
+    count[R], offset[R+1], keys (view * tiles_per_view + tile id, emitted in
+    record order, row-major inside each rect), vals (record index), the
+    stably sorted keys/vals and the per-tile start array.
+    """
+    uv32 = np.asarray(uv32, dtype=np.float32)
+    r32 = np.asarray(r32, dtype=np.float32)
+    R = uv32.shape[0]
+    n = R // n_views
+    tx_n = (det_w + tile - 1) // tile
+    ty_n = (det_h + tile - 1) // tile
+    half = np.float32(0.5)
+    lim = np.float32(1 << 24)
+
+    def span(c, r, n_tiles):
+        lo = np.floor(np.clip((c - r) - half, -lim, lim)).astype(np.int64)
+        hi = np.floor(np.clip((c + r) - half, -lim, lim)).astype(np.int64)
+        t0 = np.maximum(np.floor_divide(lo, tile), 0)
+        t1 = np.minimum(np.floor_divide(hi, tile), n_tiles - 1)
+        return t0, t1
+
+    tx0, tx1 = span(uv32[:, 0], r32[:, 0], tx_n)
+    ty0, ty1 = span(uv32[:, 1], r32[:, 1], ty_n)
+    empty = (tx0 > tx1) | (ty0 > ty1)
+    if cull is not None:
+        empty |= np.asarray(cull, dtype=bool)
+    count = np.where(empty, 0, (tx1 - tx0 + 1) * (ty1 - ty0 + 1)).astype(np.int64)
+    offset = np.zeros(R + 1, dtype=np.int64)
+    np.cumsum(count, out=offset[1:])
+    keys = np.empty(offset[-1], dtype=np.int64)
+    vals = np.empty(offset[-1], dtype=np.int64)
+    tpv = tx_n * ty_n
+    for r in np.nonzero(count)[0]:
+        v = r // n
+        ys, xs = np.meshgrid(np.arange(ty0[r], ty1[r] + 1), np.arange(tx0[r], tx1[r] + 1), indexing="ij")
+        k = v * tpv + (ys * tx_n + xs).ravel()
+        keys[offset[r]:offset[r + 1]] = k
+        vals[offset[r]:offset[r + 1]] = r
+    order = np.argsort(keys, kind="stable")
+    skeys = keys[order]
+    svals = vals[order]
+    start = np.searchsorted(skeys, np.arange(n_views * tpv + 1), side="left")
+    rect = np.stack([tx0, ty0, tx1, ty1], axis=1)
+    return dict(rect=rect, count=count, offset=offset, keys=keys, vals=vals, sorted_keys=skeys,
+                sorted_vals=svals, tile_start=start, tiles_x=tx_n, tiles_y=ty_n)
+
+
+# ---------------------------------------------------------------- losses
+
+def l1_loss_grad(img, gt):
+    """Eq. 5's L1 term: mean |I - I_gt| over the pixels of each view, summed
+    over views; gradient sign(I - I_gt) / P with sign(0) = 0."""
+    img = np.asarray(img, dtype=np.float64)
+    gt = np.asarray(gt, dtype=np.float64)
+    P = img[0].size if img.ndim >= 3 else img.size
+    diff = img - gt
+    loss = np.abs(diff).sum() / P
+    return loss, np.sign(diff) / P
+
+
+def adam_step(param, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-15):
+    """One Adam update (Kingma and Ba, Algorithm 1) with bias correction."""
+    m = beta1 * m + (1 - beta1) * grad
+    v = beta2 * v + (1 - beta2) * grad * grad
+    mh = m / (1 - beta1 ** step)
+    vh = v / (1 - beta2 ** step)
+    return param - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def psnr(vol, gt):
+    """10 log10(max(gt)^2 / MSE) over the whole grid."""
+    vol = np.asarray(vol, dtype=np.float64)
+    gt = np.asarray(gt, dtype=np.float64)
+    mse = np.mean((vol - gt) ** 2)
+    return 10.0 * np.log10(gt.max() ** 2 / mse)
+
+
+def rel_l2(a, b) -> float:
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))

@@ -1,0 +1,459 @@
+"""Pins of the FP64 oracle against facts the paper and mathematics fix.
+
+None of these tests re-types an oracle formula. Each compares the oracle
+with something independent of it: the exact line integral and its
+quadrature (Eq. 3), closed-form Gaussian masses, SciPy's rotation
+convention, brute force, exact geometric symmetries and finite differences.
+Each pin is chosen so that a plausible slip in the oracle (a dropped
+Jacobian term, a wrong sign, a transposed rotation, a mis-scaled mu) fails
+at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.optimize import brentq
+from scipy.spatial.transform import Rotation
+from scipy.special import erfc
+
+import oracle
+import synth_inputs as si
+
+
+def one(mean, log_scale, quat, density):
+    return dict(mean=np.array(mean, dtype=np.float64).reshape(3, 1),
+                log_scale=np.array(log_scale, dtype=np.float64).reshape(3, 1),
+                quat=np.array(quat, dtype=np.float64).reshape(4, 1),
+                density=np.array([density], dtype=np.float64))
+
+
+def subset(gs, idx):
+    idx = np.asarray(idx)
+    return {k: (v[..., idx] if v.ndim > 1 else v[idx]) for k, v in gs.items()}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _build():
+    oracle.build(force=False)
+
+
+# --------------------------------------------------------------- Eq. 1 conventions
+
+def test_quaternion_and_covariance_convention_matches_scipy():
+    """The field of one Gaussian along its principal axis j, taken from
+    SciPy's rotation of the same (w, x, y, z) quaternion, falls off with
+    the j-th scale: rho * exp(-delta^2 / (2 s_j^2)). A transposed rotation,
+    a scalar-last/first mix-up or a scale squared twice fails this."""
+    rng = np.random.default_rng(5)
+    for _ in range(5):
+        q = rng.normal(size=4)
+        ls = np.log(rng.uniform(0.02, 0.08, size=3))
+        p = rng.uniform(-0.2, 0.2, size=3)
+        g = one(p, ls, q, 0.7)
+        R = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()
+        for j in range(3):
+            delta = 1.3 * math.exp(ls[j])
+            x = p + delta * R[:, j]
+            val = oracle.field_points(g, x[None, :])[0]
+            assert val == pytest.approx(0.7 * math.exp(-0.5 * 1.3 ** 2), rel=1e-12)
+
+
+# --------------------------------------------------------------- Eq. 3 / Eq. 4
+
+def _random_scene(n, seed, sigma=0.04):
+    rng = np.random.default_rng(seed)
+    return dict(mean=rng.uniform(-0.25, 0.25, size=(3, n)),
+                log_scale=np.log(sigma) + 0.3 * rng.normal(size=(3, n)),
+                quat=rng.normal(size=(4, n)),
+                density=rng.uniform(0.2, 1.0, size=n))
+
+
+def test_exact_integral_matches_quadrature_cone_and_parallel():
+    """Eq. 3's closed-form line integral equals Gauss-Legendre quadrature of
+    the density field along the same physical ray."""
+    gs = _random_scene(4, 1)
+    for mode in ("cone", "parallel"):
+        geom = si.geometry(64, mode=mode)
+        ang = 0.7
+        rec = oracle.splat_records(gs, geom, [ang])
+        u = rec["uv"][:, 0] + np.array([0.3, -1.1, 2.0, 0.0])
+        v = rec["uv"][:, 1] + np.array([-0.4, 0.9, 0.0, 1.7])
+        e = oracle.exact_points(gs, geom, ang, u, v)
+        if mode == "cone":
+            lo, hi = 1.5 - 1.0, 1.5 + 1.0
+        else:
+            lo, hi = 2.0 - 1.0, 2.0 + 1.0
+        q = oracle.quadrature_points(gs, geom, ang, u, v, lo, hi)
+        np.testing.assert_allclose(e, q, rtol=1e-9, atol=1e-14)
+
+
+def test_parallel_beam_splat_equals_exact_integral():
+    """In parallel beam the projection of a 3D Gaussian is exactly a 2D
+    Gaussian (Eq. 3 -> Eq. 4), so M with no cutoff equals E everywhere."""
+    gs = _random_scene(6, 2)
+    geom = si.geometry(64, mode="parallel")
+    rng = np.random.default_rng(3)
+    for ang in (0.0, 1.1, 4.0):
+        u = rng.uniform(16, 48, size=200)
+        v = rng.uniform(16, 48, size=200)
+        m = oracle.project_points(gs, geom, ang, u, v, kappa=1e6)
+        e = oracle.exact_points(gs, geom, ang, u, v)
+        np.testing.assert_allclose(m, e, rtol=1e-10, atol=1e-14)
+
+
+def test_cone_beam_mu_identity_at_splat_centre():
+    """At the projected centre the ray passes through the mean, where the
+    exact integral is rho * sqrt(2 pi / (d^T Sigma^-1 d)). M there is
+    rho * mu, so the two agree for any Gaussian and view (pins mu)."""
+    gs = _random_scene(8, 4, sigma=0.06)
+    geom = si.geometry(64, mode="cone")
+    for ang in (0.3, 2.2):
+        rec = oracle.splat_records(gs, geom, [ang])
+        for i in range(8):
+            g1 = subset(gs, [i])
+            u, v = rec["uv"][i]
+            e = oracle.exact_points(g1, geom, ang, [u], [v])[0]
+            m = oracle.project_points(g1, geom, ang, [u], [v], kappa=1e6)[0]
+            assert m == pytest.approx(rec["w"][i], rel=1e-14)
+            assert m == pytest.approx(e, rel=1e-11)
+
+
+def test_cone_beam_splat_converges_to_exact_integral_for_small_gaussians():
+    """The splat is a local affine approximation of the cone-beam integral:
+    its footprint error relative to E must vanish as the Gaussian shrinks.
+    A wrong ray-space Jacobian gives an O(1) footprint error that does not."""
+    gaps = []
+    base = _random_scene(1, 7, sigma=1.0)
+    for sigma in (0.04, 0.02, 0.01, 0.005):
+        g = dict(base)
+        g["log_scale"] = base["log_scale"] + math.log(sigma)
+        g["mean"] = np.array([[0.21], [-0.13], [0.17]])
+        geom = si.geometry(2048, mode="cone")
+        ang = 0.9
+        rec = oracle.splat_records(g, geom, [ang])
+        u0, v0 = rec["uv"][0]
+        a, b, c = rec["shat"][0]
+        su, sv = math.sqrt(a), math.sqrt(c)
+        uu, vv = np.meshgrid(np.linspace(-2.5, 2.5, 21), np.linspace(-2.5, 2.5, 21))
+        u = u0 + su * uu.ravel()
+        v = v0 + sv * vv.ravel()
+        m = oracle.project_points(g, geom, ang, u, v, kappa=1e6)
+        e = oracle.exact_points(g, geom, ang, u, v)
+        gaps.append(oracle.rel_l2(m, e))
+    assert gaps[-1] < 2e-3
+    for g0, g1 in zip(gaps[:-1], gaps[1:]):
+        assert g1 < 0.6 * g0
+
+
+def test_splat_mass_closed_form():
+    """Sum over pixels of one splat = w 2 pi sqrt(det S^) times the mass
+    inside the support ellipse (1 - e^-kappa^2/2)."""
+    g = one([0.05, -0.03, 0.02], np.log([0.03, 0.05, 0.04]), [0.9, 0.2, -0.3, 0.1], 0.8)
+    geom = si.geometry(256, mode="cone")
+    ang = 0.4
+    rec = oracle.splat_records(g, geom, [ang])
+    a, b, c = rec["shat"][0]
+    w = rec["w"][0]
+    full = w * 2 * math.pi * math.sqrt(a * c - b * b)
+    img6 = oracle.project(g, geom, [ang], kappa=6.0)
+    assert img6.sum() == pytest.approx(full * (1 - math.exp(-18.0)), rel=1e-9)
+    img3 = oracle.project(g, geom, [ang], kappa=3.0)
+    assert img3.sum() == pytest.approx(full * (1 - math.exp(-4.5)), rel=2e-3)
+
+
+def test_projection_brute_force_equals_box_variant():
+    gs = si.gaussians(300, 11)
+    geom = si.geometry(48, mode="cone")
+    ang = si.angles(3)
+    a = oracle.project(gs, geom, ang)
+    b = oracle.project(gs, geom, ang, brute=True)
+    np.testing.assert_allclose(a, b, rtol=1e-13, atol=1e-15)
+
+
+# --------------------------------------------------------------- Eq. 2, Sec. 3.3
+
+def test_voxel_mass_closed_form():
+    """Sum of voxel values times voxel volume = rho (2 pi)^(3/2) sqrt(det S)
+    times the chi-square(3) mass inside kappa."""
+    ls = np.log([0.03, 0.045, 0.035])
+    g = one([0.02, -0.01, 0.03], ls, [0.3, -0.5, 0.7, 0.2], 0.9)
+    grid = si.grid(64)
+    h3 = np.prod(grid["spacing"])
+    full = 0.9 * (2 * math.pi) ** 1.5 * math.exp(ls.sum())
+    v8 = oracle.voxelize(g, grid, kappa=8.0)
+    assert v8.sum() * h3 == pytest.approx(full, rel=1e-8)
+    tail = erfc(3 / math.sqrt(2)) + math.sqrt(2 / math.pi) * 3 * math.exp(-4.5)
+    v3 = oracle.voxelize(g, grid, kappa=3.0)
+    assert v3.sum() * h3 == pytest.approx(full * (1 - tail), rel=5e-3)
+
+
+def test_voxelizer_brute_force_equals_box_variant():
+    gs = si.gaussians(300, 12)
+    grid = dict(origin=(-0.5, -0.4, -0.45), spacing=(1 / 40, 1 / 36, 1 / 44), dims=(40, 29, 37))
+    a = oracle.voxelize(gs, grid)
+    b = oracle.voxelize(gs, grid, brute=True)
+    np.testing.assert_allclose(a, b, rtol=1e-13, atol=1e-15)
+
+
+# --------------------------------------------------------------- invariances
+
+def _qmul(a, b):
+    w1, x1, y1, z1 = a
+    w2, x2, y2, z2 = b
+    return np.array([w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2,
+                     w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
+                     w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2,
+                     w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2])
+
+
+def test_invariances():
+    gs = {k: v.astype(np.float64) for k, v in si.gaussians(200, 13).items()}
+    geom = si.geometry(40, mode="cone")
+    ang = [0.8]
+    base = oracle.project(gs, geom, ang)
+    # quaternion sign and scale
+    for f in (-1.0, 3.0):
+        g2 = dict(gs); g2["quat"] = f * gs["quat"]
+        np.testing.assert_allclose(oracle.project(g2, geom, ang), base, rtol=1e-12, atol=1e-14)
+    # permutation
+    perm = np.random.default_rng(0).permutation(200)
+    np.testing.assert_allclose(oracle.project(subset(gs, perm), geom, ang), base, rtol=1e-12, atol=1e-14)
+    # linearity in density and additivity over subsets
+    g2 = dict(gs); g2["density"] = 2.5 * gs["density"]
+    np.testing.assert_allclose(oracle.project(g2, geom, ang), 2.5 * base, rtol=1e-12, atol=1e-14)
+    a = oracle.project(subset(gs, np.arange(0, 80)), geom, ang)
+    b = oracle.project(subset(gs, np.arange(80, 200)), geom, ang)
+    np.testing.assert_allclose(a + b, base, rtol=1e-12, atol=1e-14)
+
+
+def test_rotation_about_axis_equals_view_shift():
+    """Rotating every Gaussian by phi about z and viewing at theta equals the
+    unrotated scene at theta - phi (the orbit is a rotation about z)."""
+    gs = {k: v.astype(np.float64) for k, v in si.gaussians(150, 14).items()}
+    phi, theta = 0.61, 1.9
+    Rz = np.array([[math.cos(phi), -math.sin(phi), 0], [math.sin(phi), math.cos(phi), 0], [0, 0, 1]])
+    qz = np.array([math.cos(phi / 2), 0, 0, math.sin(phi / 2)])
+    rot = dict(gs)
+    rot["mean"] = Rz @ gs["mean"]
+    rot["quat"] = np.stack([_qmul(qz, gs["quat"][:, i]) for i in range(150)], axis=1)
+    geom = si.geometry(48, mode="cone")
+    a = oracle.project(rot, geom, [theta])
+    b = oracle.project(gs, geom, [theta - phi])
+    np.testing.assert_allclose(a, b, rtol=1e-9, atol=1e-12)
+
+
+# --------------------------------------------------------------- gradients
+
+def _fd_check(fwd, gs, analytic, h, rtol):
+    for key in ("mean", "log_scale", "quat", "density"):
+        arr = gs[key]
+        num = np.zeros_like(arr)
+        flat = arr.reshape(-1)
+        for j in range(flat.size):
+            def f(step):
+                g2 = {k: v.copy() for k, v in gs.items()}
+                g2[key].reshape(-1)[j] += step
+                return fwd(g2)
+            d1 = (f(h) - f(-h)) / (2 * h)
+            d2 = (f(h / 2) - f(-h / 2)) / h
+            num.reshape(-1)[j] = (4 * d2 - d1) / 3
+        ana = analytic[key].reshape(num.shape)
+        err = np.linalg.norm(ana - num) / max(np.linalg.norm(num), 1e-30)
+        assert err < rtol, (key, err)
+
+
+def test_projection_gradient_matches_finite_differences():
+    """Analytic gradient of <c, M> (support held fixed: kappa = 8 makes the
+    cutoff invisible at FD step size) vs Richardson central differences."""
+    gs = _random_scene(4, 21, sigma=0.05)
+    for mode in ("cone", "parallel"):
+        geom = si.geometry(32, mode=mode)
+        ang = [0.35, 2.4]
+        c = np.random.default_rng(2).normal(size=(2, 32, 32))
+        fwd = lambda g: float(np.sum(c * oracle.project(g, geom, ang, kappa=8.0)))
+        ana = oracle.project_bwd(gs, geom, ang, c, kappa=8.0)
+        _fd_check(fwd, gs, ana, 1e-4, 1e-7)
+
+
+def test_voxelizer_gradient_matches_finite_differences():
+    gs = _random_scene(4, 22, sigma=0.06)
+    grid = si.grid(24)
+    c = np.random.default_rng(3).normal(size=(24, 24, 24))
+    fwd = lambda g: float(np.sum(c * oracle.voxelize(g, grid, kappa=8.0)))
+    ana = oracle.voxelize_bwd(gs, grid, c, kappa=8.0)
+    _fd_check(fwd, gs, ana, 1e-4, 1e-7)
+
+
+def test_gradient_subset_selection_is_consistent():
+    gs = si.gaussians(100, 23)
+    geom = si.geometry(32)
+    ang = si.angles(3)
+    c = np.random.default_rng(4).normal(size=(3, 32, 32))
+    full = oracle.project_bwd(gs, geom, ang, c)
+    sel = np.array([5, 17, 99, 0])
+    part = oracle.project_bwd(gs, geom, ang, c, sel=sel)
+    for k in full:
+        np.testing.assert_array_equal(part[k], full[k][..., sel])
+
+
+# --------------------------------------------------------------- phantom
+
+def test_phantom_sphere_chord():
+    """A sphere of radius r projects to amp * 2 sqrt(r^2 - b^2), b = distance
+    of the ray from the centre."""
+    ph = dict(centre=np.array([[0.05, -0.02, 0.03]]), semi=np.array([[0.2, 0.2, 0.2]]),
+              quat=np.array([[0.3, 0.1, -0.4, 0.8]]), amp=np.array([0.7]))
+    geom = si.geometry(64, mode="cone")
+    ang = 1.2
+    img = oracle.phantom_project(ph, geom, [ang])[0]
+    ys, xs = np.nonzero(np.ones((64, 64)))
+    o, d = oracle.rays(geom, ang, xs + 0.5, ys + 0.5)
+    c = ph["centre"][0]
+    oc = o - c
+    b2 = np.sum(oc * oc, axis=1) - np.sum(oc * d, axis=1) ** 2
+    expect = np.where(b2 < 0.04, 0.7 * 2 * np.sqrt(np.maximum(0.04 - b2, 0)), 0.0)
+    np.testing.assert_allclose(img[ys, xs], expect, rtol=1e-10, atol=1e-12)
+
+
+def test_phantom_ellipsoid_chord_by_root_finding():
+    """Chord of a rotated ellipsoid = distance between the two roots of
+    f(t) = |diag(1/a) R^T (o + t d - c)|^2 - 1, found numerically (SciPy
+    rotation of the (w, x, y, z) quaternion)."""
+    ph = dict(centre=np.array([[0.02, 0.05, -0.04]]), semi=np.array([[0.25, 0.1, 0.15]]),
+              quat=np.array([[0.6, -0.3, 0.5, 0.2]]), amp=np.array([1.0]))
+    geom = si.geometry(96, mode="cone")
+    ang = 0.5
+    img = oracle.phantom_project(ph, geom, [ang])[0]
+    q = ph["quat"][0]
+    R = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()
+    a = ph["semi"][0]
+    inside = np.argwhere(img > 0)
+    assert len(inside) > 20
+    rng = np.random.default_rng(0)
+    picks = list(inside[rng.choice(len(inside), 25, replace=False)])
+    picks += [np.array([y, x]) for y, x in rng.integers(0, 96, size=(25, 2))]
+    checked = 0
+    for y, x in picks:
+        o, d = oracle.rays(geom, ang, [x + 0.5], [y + 0.5])
+        o, d = o[0], d[0]
+        f = lambda t: np.sum(((R.T @ (o + t * d - ph["centre"][0])) / a) ** 2) - 1
+        ts = np.linspace(0.5, 2.5, 801)
+        fs = np.array([f(t) for t in ts])
+        k = np.argmin(fs)
+        if fs[k] >= 0:
+            assert img[y, x] == 0.0
+            continue
+        t0 = brentq(f, 0.5, ts[k], xtol=1e-14)
+        t1 = brentq(f, ts[k], 2.5, xtol=1e-14)
+        assert img[y, x] == pytest.approx(t1 - t0, rel=1e-9, abs=1e-12)
+        checked += 1
+    assert checked >= 25
+
+
+def test_phantom_volume_membership():
+    ph = si.phantom(6, 3)
+    grid = si.grid(20)
+    vol = oracle.phantom_volume(ph, grid)
+    rng = np.random.default_rng(1)
+    for _ in range(50):
+        ix, iy, iz = rng.integers(0, 20, size=3)
+        x = np.array(grid["origin"]) + (np.array([ix, iy, iz]) + 0.5) * np.array(grid["spacing"])
+        acc = 0.0
+        for e in range(6):
+            q = ph["quat"][e]
+            R = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()
+            y = (R.T @ (x - ph["centre"][e])) / ph["semi"][e]
+            if y @ y <= 1.0:
+                acc += ph["amp"][e]
+        assert vol[iz, iy, ix] == pytest.approx(acc, abs=1e-12)
+
+
+# --------------------------------------------------------------- binning reference
+
+def test_binning_hand_cases():
+    """Hand-computed tile rectangles for 16x16 tiles on a 64x48 detector."""
+    uv = np.array([[16.0, 16.0], [0.2, 0.2], [63.9, 47.9], [-10.0, 5.0], [30.0, 20.0]], np.float32)
+    r = np.array([[0.4, 0.4], [0.1, 0.1], [20.0, 1.0], [3.0, 3.0], [2.5, 13.0]], np.float32)
+    b = oracle.bin_tiles(uv, r, 64, 48)
+    # pixel centres 15.5 .. 16.4 -> column 15 only -> tile 0
+    assert list(b["rect"][0]) == [0, 0, 0, 0]
+    # centre 0.2, half 0.1: floor(0.1 - 0.5) = -1 .. floor(0.3 - 0.5) = -1 -> clipped lo 0, hi -1 -> empty
+    assert b["count"][1] == 0
+    # x: floor(43.4)=43 -> tile 2 .. floor(83.4)=83 -> tile 5, clipped to 3; y: floor(46.4)=46 -> tile 2 .. floor(48.4)=48 -> tile 3, clipped to 2
+    assert list(b["rect"][2]) == [2, 2, 3, 2]
+    assert b["count"][3] == 0
+    # x: floor(27.0)=27 .. floor(32.0)=32 -> tiles 1..2; y: floor(6.5)=6 .. floor(32.5)=32 -> tiles 0..2
+    assert list(b["rect"][4]) == [1, 0, 2, 2]
+    assert b["count"].tolist() == [1, 0, 2, 0, 6]
+    assert b["offset"].tolist() == [0, 1, 1, 3, 3, 9]
+    # keys emitted row-major inside each rect, tiles_x = 4
+    assert b["keys"].tolist() == [0, 10, 11, 1, 2, 5, 6, 9, 10]
+    assert b["sorted_keys"].tolist() == sorted(b["keys"].tolist())
+    # stable: the two records on tile 10 keep record order (2 before 4)
+    assert b["sorted_keys"].tolist() == [0, 1, 2, 5, 6, 9, 10, 10, 11]
+    assert b["sorted_vals"].tolist() == [0, 4, 4, 4, 4, 4, 2, 4, 2]
+    assert b["tile_start"].tolist() == [0, 1, 2, 3, 3, 3, 4, 5, 5, 5, 6, 8, 9]
+
+
+def test_binning_covers_every_support_pixel():
+    """Every FP64 support pair with d^2 <= 9 - 1e-4 lies in a tile the
+    FP32 binning lists for its record."""
+    gs = si.gaussians(400, 31)
+    geom = si.geometry(64)
+    ang = si.angles(2)
+    rec = oracle.splat_records(gs, geom, ang)
+    uv32 = rec["uv"].astype(np.float32)
+    r32 = (np.float32(3.0) * np.sqrt(rec["shat"][:, [0, 2]].astype(np.float32))).astype(np.float32)
+    b = oracle.bin_tiles(uv32, r32, 64, 64, cull=rec["culled"], n_views=2)
+    n = 400
+    ys, xs = np.mgrid[0:64, 0:64]
+    for r in range(2 * n):
+        if rec["culled"][r]:
+            continue
+        du = xs + 0.5 - rec["uv"][r, 0]
+        dv = ys + 0.5 - rec["uv"][r, 1]
+        c0, c1, c2 = rec["conic"][r]
+        d2 = c0 * du * du + 2 * c1 * du * dv + c2 * dv * dv
+        inside = d2 <= 9 - 1e-4
+        if not inside.any():
+            continue
+        tx0, ty0, tx1, ty1 = b["rect"][r]
+        tx = xs[inside] // 16
+        ty = ys[inside] // 16
+        assert b["count"][r] > 0
+        assert tx.min() >= tx0 and tx.max() <= tx1 and ty.min() >= ty0 and ty.max() <= ty1
+
+
+def test_binning_sort_is_stable_and_ranges_partition():
+    gs = si.gaussians(300, 32)
+    geom = si.geometry(64)
+    ang = si.angles(3)
+    rec = oracle.splat_records(gs, geom, ang)
+    uv32 = rec["uv"].astype(np.float32)
+    r32 = (np.float32(3.0) * np.sqrt(rec["shat"][:, [0, 2]].astype(np.float32))).astype(np.float32)
+    b = oracle.bin_tiles(uv32, r32, 64, 64, cull=rec["culled"], n_views=3)
+    start = b["tile_start"]
+    assert start[0] == 0 and start[-1] == b["sorted_keys"].size
+    for t in range(start.size - 1):
+        seg_k = b["sorted_keys"][start[t]:start[t + 1]]
+        seg_v = b["sorted_vals"][start[t]:start[t + 1]]
+        assert np.all(seg_k == t)
+        assert np.all(np.diff(seg_v) > 0)  # ascending record index within a tile
+
+
+# --------------------------------------------------------------- losses / metrics
+
+def test_l1_psnr_adam_hand_values():
+    img = np.array([[[1.0, 2.0], [3.0, 4.0]]])
+    gt = np.array([[[1.5, 2.0], [2.0, 6.0]]])
+    loss, g = oracle.l1_loss_grad(img, gt)
+    assert loss == pytest.approx((0.5 + 0.0 + 1.0 + 2.0) / 4)
+    assert g.tolist() == [[[-0.25, 0.0], [0.25, -0.25]]]
+    vol = np.array([1.0, 2.0, 3.0, 4.0])
+    ref = np.array([1.0, 2.0, 3.0, 2.0])
+    assert oracle.psnr(vol, ref) == pytest.approx(10 * math.log10(9 / 1.0))
+    p, m, v = oracle.adam_step(np.array([1.0]), np.array([0.5]), np.zeros(1), np.zeros(1), 1, 0.1,
+                               eps=0.0)
+    # first step of Adam moves by lr * sign(g)
+    assert p[0] == pytest.approx(0.9)
+    assert m[0] == pytest.approx(0.05) and v[0] == pytest.approx(0.00025)
