@@ -1,0 +1,276 @@
+/*
+ * factgs.h -- C ABI of the MI355X (gfx950) Gaussian X-ray rasterizer and
+ * voxelizer library (libfactgs.so).
+ *
+ * The library implements the two differentiable renderers of the FaCT-GS
+ * CT-reconstruction method (arXiv 2604.01844):
+ *
+ *   - project_views: the X-ray rasterizer. Each 3D Gaussian (Eq. 1:
+ *     density rho, mean p, covariance Sigma) is projected, per cone-beam (or
+ *     parallel-beam) view, to a 2D Gaussian on the flat detector carrying the
+ *     ray-integral density factor mu (Eq. 4, Sec. 3.2); every detector pixel
+ *     is the order-free sum of the splats whose 3-sigma support contains it
+ *     (Sec. 3.2 cutoff, Sec. 3.5 "no depth ordering").
+ *   - voxelize: the density field sigma(x) = sum_i G_i(x) (Eq. 2) sampled at
+ *     the centres of a regular grid, each Gaussian limited to its 3-sigma
+ *     ellipsoid (Sec. 3.3).
+ *
+ * and, for each, the backward pass: the gradient of a scalar loss with
+ * respect to the 11 parameters per Gaussian (Sec. 5: position 3, scale 3,
+ * quaternion 4, density 1), given the loss gradient with respect to the
+ * image or volume. Gradients are those of the function with its support
+ * held fixed (the hard cutoff contributes no derivative).
+ *
+ * Conventions
+ *   Gaussians: structure of arrays in device memory, float32:
+ *     mean[3][n] (x, y, z rows), log_scale[3][n] (natural log of the
+ *     standard deviation along each principal axis), quat[4][n] (w, x, y, z,
+ *     any non-zero norm; normalised inside), density[n] (linear rho).
+ *     Sigma = R(q/|q|) diag(exp(2 log_scale)) R^T.
+ *   World: the reconstruction cube is [-1/2, 1/2]^3, rotation axis +z.
+ *   View at angle th: source at sod (cos th, sin th, 0); camera rows
+ *     e0 = (-sin th, cos th, 0), e1 = (0, 0, -1), e2 = (-cos th, -sin th, 0);
+ *     the flat detector is at distance sdd from the source along e2.
+ *     Detector pixel (j, i) (column j, row i) is sampled at continuous
+ *     pixel coordinates (j + 1/2, i + 1/2); the principal ray hits
+ *     (det_w/2 + off_u, det_h/2 + off_v). Images are [view][det_h][det_w].
+ *   Support: a (pixel, Gaussian) pair contributes iff its Mahalanobis
+ *     distance in the 2D splat satisfies d^2 <= kappa^2 (kappa = 3).
+ *   Grids: voxel (ix, iy, iz) has its centre at origin + (index + 1/2) *
+ *     spacing; volumes are [nz][ny][nx], x fastest.
+ *
+ * Ownership and asynchrony
+ *   Every pointer argument named as device memory must be a device pointer
+ *   on the current HIP device, 16-byte aligned. The caller owns all device
+ *   memory: outputs and the workspace. The library never allocates device
+ *   memory and keeps no state between calls except a thread-local error
+ *   message. All work is enqueued on `stream` (a hipStream_t passed as
+ *   void*; NULL = the default stream). Calls return without waiting for
+ *   the GPU, except where a call must learn the number of (tile, Gaussian)
+ *   pairs to size its workspace use: it then waits on `stream` for one
+ *   4-byte device-to-host copy (documented per call).
+ *
+ * Errors
+ *   Every entry point returns an fgs_status. No C++ exception crosses the
+ *   ABI. On an error nothing is written to the outputs unless stated, and
+ *   fgs_last_error() returns a thread-local description.
+ */
+#ifndef FACTGS_H
+#define FACTGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FGS_OK = 0,
+  FGS_E_INVALID = -1,     /* null pointer, non-positive size, kappa <= 0, view range out of bounds */
+  FGS_E_CAPACITY = -2,    /* workspace too small: ws->needed holds the required bytes; retry */
+  FGS_E_HIP = -3,         /* HIP launch or runtime error; see fgs_last_error() */
+  FGS_E_UNSUPPORTED = -4  /* a size beyond what the kernels index (e.g. 2^32 pairs per call) */
+} fgs_status;
+
+enum { FGS_CONE = 0, FGS_PARALLEL = 1 };
+
+/* Gaussian parameters (Eq. 1 and the 11-value parameterisation of Sec. 5). */
+typedef struct {
+  int64_t n;               /* number of Gaussians, >= 1 */
+  const float *mean;       /* device [3][n] */
+  const float *log_scale;  /* device [3][n] */
+  const float *quat;       /* device [4][n], (w, x, y, z) */
+  const float *density;    /* device [n] */
+} fgs_gaussians;
+
+/* Gradient outputs, same shapes as fgs_gaussians; overwritten, never accumulated. */
+typedef struct {
+  float *mean;       /* device [3][n] */
+  float *log_scale;  /* device [3][n] */
+  float *quat;       /* device [4][n] */
+  float *density;    /* device [n] */
+} fgs_gaussian_grads;
+
+/* Scanner geometry (Sec. 3.2: cone-beam pinhole model or parallel beam). */
+typedef struct {
+  int32_t mode;          /* FGS_CONE or FGS_PARALLEL */
+  int32_t n_views;       /* number of entries in angles */
+  const float *angles;   /* device [n_views], radians */
+  float sod;             /* source-to-rotation-axis distance (cone) */
+  float sdd;             /* source-to-detector distance (cone) */
+  int32_t det_w, det_h;  /* detector pixels */
+  float pitch_u, pitch_v;/* detector pixel pitch (world units at the detector) */
+  float off_u, off_v;    /* principal-point offset in pixels */
+} fgs_geom;
+
+/* Regular voxel grid (any sub-box of space, e.g. a 32^3 crop). */
+typedef struct {
+  float origin[3];       /* outer corner of voxel (0, 0, 0) */
+  float spacing[3];      /* voxel size per axis, > 0 */
+  int32_t dims[3];       /* nx, ny, nz, >= 1 */
+} fgs_grid;
+
+typedef struct {
+  float kappa;           /* support radius in standard deviations (3) */
+  float near_plane;      /* cone beam: Gaussians with camera depth <= near are culled (1e-2) */
+  int32_t recompute;     /* backward only: 1 = rebuild the per-tile lists; 0 = reuse those that
+                            the forward call left in the same workspace (same inputs) */
+  int32_t reserved;
+  void *events;          /* optional hipEvent_t[2] (NULL = none): recorded on the stream right
+                            before and right after the call's pixel or voxel kernel (splat
+                            forward/backward, voxel forward/backward), for timing that kernel */
+} fgs_opts;
+
+/* Caller-owned device workspace. The "out" fields describe what the last
+ * forward call left in it; a backward call with opts.recompute = 0 reads
+ * them, so pass the same struct back unchanged. */
+typedef struct {
+  void *ptr;             /* device memory, 256-byte aligned */
+  uint64_t bytes;        /* size of ptr */
+  uint64_t needed;       /* out: bytes this call needs (on FGS_OK and FGS_E_CAPACITY) */
+  uint64_t n_pairs;      /* out: (tile, Gaussian) pairs of the last binning */
+  uint64_t n_records;    /* out: records of the last binning */
+  uint64_t n_tiles;      /* out: tiles of the last binning */
+  int32_t kind;          /* out: 0 none, 1 rasterizer lists, 2 voxelizer lists */
+  int32_t reserved;
+} fgs_workspace;
+
+/* Additive ellipsoid phantom: sum_e amp_e * [x inside ellipsoid e]. Used to
+ * make synthetic ground truth (stands in for the paper's datasets). */
+typedef struct {
+  int64_t n;             /* ellipsoids */
+  const double *centre;  /* device [n][3] */
+  const double *semi;    /* device [n][3] semi-axes */
+  const double *quat;    /* device [n][4] (w, x, y, z), any non-zero norm */
+  const double *amp;     /* device [n] */
+} fgs_phantom;
+
+/* ---------------------------------------------------------------------
+ * X-ray rasterizer (Eq. 3-4, Sec. 3.2, Sec. 3.5).
+ * Renders views [view_begin, view_begin + view_count) into
+ * img[view_count][det_h][det_w] (device, overwritten).
+ * Pipeline: per-(view, Gaussian) splat records; tile counts, exclusive scan
+ * and key emission (keys = view * tiles_per_view + tile, row-major inside
+ * each record's axis-aligned tile rectangle); stable LSD radix sort; per-tile
+ * ranges; per-tile splat. Per pixel the sum runs over its tile's list in
+ * ascending Gaussian index (deterministic, bit-reproducible).
+ * Synchronisation: waits on `stream` once to read the pair count.
+ * Workspace: if ws->bytes < ws->needed the call returns FGS_E_CAPACITY with
+ * ws->needed set and no output written; grow and retry. The workspace then
+ * holds the lists the backward can reuse (opts.recompute = 0).
+ * ------------------------------------------------------------------- */
+int fgs_project_views_fwd(const fgs_gaussians *g, const fgs_geom *geom, int32_t view_begin,
+                          int32_t view_count, const fgs_opts *opts, float *img,
+                          fgs_workspace *ws, void *stream);
+
+/* Backward of fgs_project_views_fwd: given grad_img[view_count][det_h][det_w]
+ * (device) = dL/dimg, writes dL/d(mean, log_scale, quat, density) summed
+ * over the views (overwritten). Per (tile, Gaussian) pair the pixel sums
+ * are formed by one lane (no atomics), then reduced per (view, Gaussian) in
+ * list order and per Gaussian in view order: deterministic.
+ * opts.recompute = 1 rebuilds the lists (and may return FGS_E_CAPACITY like
+ * the forward); 0 requires the workspace the forward call filled. */
+int fgs_project_views_bwd(const fgs_gaussians *g, const fgs_geom *geom, int32_t view_begin,
+                          int32_t view_count, const fgs_opts *opts, const float *grad_img,
+                          fgs_gaussian_grads *out, fgs_workspace *ws, void *stream);
+
+/* ---------------------------------------------------------------------
+ * Voxelizer (Eq. 2, Sec. 3.3). vol[nz][ny][nx] (device, overwritten) =
+ * sum_i rho_i exp(-1/2 d_i^2) [d_i^2 <= kappa^2] at each voxel centre.
+ * Gaussians are binned into 8x8x8-voxel tiles with the same scan / sort /
+ * range machinery as the rasterizer. Same workspace protocol and single
+ * synchronisation as fgs_project_views_fwd.
+ * ------------------------------------------------------------------- */
+int fgs_voxelize_fwd(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *opts, float *vol,
+                     fgs_workspace *ws, void *stream);
+
+/* Backward of fgs_voxelize_fwd given grad_vol[nz][ny][nx] (device). */
+int fgs_voxelize_bwd(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *opts,
+                     const float *grad_vol, fgs_gaussian_grads *out, fgs_workspace *ws,
+                     void *stream);
+
+/* ---------------------------------------------------------------------
+ * Work counters (measurement). The algorithmic work of the rasterizer is
+ * the number of (pixel, Gaussian) pairs inside the support (d^2 <= kappa^2,
+ * pixels inside the detector); of the voxelizer, the (voxel, Gaussian)
+ * pairs. These calls build the same lists as the forward calls and write
+ * that count to out[0] (device uint64, overwritten). Same workspace
+ * protocol and synchronisation as the forward calls.
+ * ------------------------------------------------------------------- */
+int fgs_project_views_support(const fgs_gaussians *g, const fgs_geom *geom, int32_t view_begin,
+                              int32_t view_count, const fgs_opts *opts, uint64_t *out,
+                              fgs_workspace *ws, void *stream);
+int fgs_voxelize_support(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *opts,
+                         uint64_t *out, fgs_workspace *ws, void *stream);
+
+/* ---------------------------------------------------------------------
+ * Losses and optimiser (Eq. 5 L1 term; Adam).
+ * ------------------------------------------------------------------- */
+
+/* L1 term of Eq. 5 over n_views images of n_per_view values:
+ * loss[0] = sum_v mean_pixels |img - gt| (device scalar, overwritten) and
+ * grad = sign(img - gt) / n_per_view (device, overwritten; sign(0) = 0).
+ * grad may be NULL. Deterministic two-level reduction; scratch from ws
+ * (needs 16 KiB). */
+int fgs_l1_loss_grad(const float *img, const float *gt, int64_t n_per_view, int32_t n_views,
+                     float *loss, float *grad, fgs_workspace *ws, void *stream);
+
+/* One Adam step (Kingma and Ba, with bias correction, step >= 1) on n
+ * float32 values, in place. The gradient is grad + grad2 (grad2 may be
+ * NULL): the sum of two loss terms' gradients is fused into the update.
+ * m, v are the moment buffers (device). If clamp_min_zero != 0 the updated
+ * parameter is clamped at 0 (used for densities). */
+int fgs_adam_step(float *param, const float *grad, const float *grad2, float *m, float *v, int64_t n,
+                  int32_t step, float lr, float beta1, float beta2, float eps, int32_t clamp_min_zero,
+                  void *stream);
+
+/* PSNR = 10 log10(peak^2 / mean((vol - ref)^2)) over n values, written to
+ * out[0] (device float). peak > 0 is given by the caller (max of the
+ * reference). Scratch from ws (16 KiB). */
+int fgs_psnr(const float *vol, const float *ref, int64_t n, float peak, float *out,
+             fgs_workspace *ws, void *stream);
+
+/* ---------------------------------------------------------------------
+ * Synthetic ground truth (additive ellipsoid phantom, computed in FP64).
+ * ------------------------------------------------------------------- */
+
+/* Exact chord projections: img[view_count][det_h][det_w] = sum_e amp_e *
+ * chord length of the ray through each pixel centre. */
+int fgs_phantom_project(const fgs_phantom *ph, const fgs_geom *geom, int32_t view_begin,
+                        int32_t view_count, float *img, void *stream);
+
+/* Indicator sum at voxel centres: vol[nz][ny][nx]. */
+int fgs_phantom_voxelize(const fgs_phantom *ph, const fgs_grid *grid, float *vol, void *stream);
+
+/* ---------------------------------------------------------------------
+ * Introspection (tests): where the last binning of a workspace lives.
+ * Pure host arithmetic on the workspace's out fields. After
+ * fgs_project_views_fwd / fgs_voxelize_fwd the workspace holds, at the byte
+ * offsets written to off[]:
+ *   off[0] records' FP32 centres (float2 per record; voxelizer: float4
+ *          x, y, z in voxel units and rho),
+ *   off[1] FP32 support half-extents (float2 per record, pixels; voxelizer:
+ *          float4, voxels),
+ *   off[2] tile rectangles (4 x uint16 per record: x0, y0, x1, y1;
+ *          voxelizer: 8 x uint16: x0, y0, z0, x1, y1, z1, 0, 0),
+ *   off[3] exclusive offsets (uint32, records + 1),
+ *   off[4] emitted keys (uint32, pairs), off[5] emitted values (uint32),
+ *   off[6] sorted keys, off[7] sorted values, off[8] tile starts (uint32,
+ *   tiles + 1).
+ * counts[0] = records, counts[1] = pairs, counts[2] = tiles.
+ * Records are r = local_view * n + i (voxelizer: r = i).
+ * ------------------------------------------------------------------- */
+int fgs_binning_layout(const fgs_workspace *ws, uint64_t off[9], uint64_t counts[3]);
+
+/* Thread-local message describing the last error (never NULL). */
+const char *fgs_last_error(void);
+
+/* Library version string. */
+const char *fgs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FACTGS_H */

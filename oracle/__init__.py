@@ -220,33 +220,64 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def project_bwd(gs: dict, geom: dict, angles, grad_img, kappa: float = KAPPA, sel=None) -> dict:
+def _split11(a):
+    return dict(mean=a[0:3], log_scale=a[3:6], quat=a[6:10], density=a[10])
+
+
+def project_bwd(gs: dict, geom: dict, angles, grad_img, kappa: float = KAPPA, sel=None,
+                band: float = 0.0) -> dict:
     """Gradient of sum(grad_img * M) w.r.t. mean, log_scale, quat, density of
-    the Gaussians in ``sel`` (default all), support held fixed."""
+    the Gaussians in ``sel`` (default all), support held fixed.
+
+    With band > 0, (pixel, Gaussian) pairs with |d^2 - kappa^2| <= band are
+    left out and ``result["band_abs"]`` holds, per parameter, the sum of the
+    absolute per-pair gradients over them: the boundary pairs whose inclusion
+    no finite-precision evaluation decides uniquely."""
     lib = _load()
     n, keep, p = _gauss_args(gs)
     ang, pa = _d(angles)
     gi, pgi = _d(grad_img)
     sel = np.arange(n, dtype=np.int64) if sel is None else np.ascontiguousarray(sel, dtype=np.int64)
     dm, dl, dq, dr = _bwd_out(sel.shape[0])
+    babs = np.zeros((11, sel.shape[0]))
     g, pg = _d(_geom_vec(geom))
     lib.orc_project_bwd(pg, ctypes.c_double(kappa), ctypes.c_int(ang.shape[0]), pa, ctypes.c_long(n), *p,
                         pgi, ctypes.c_long(sel.shape[0]), sel.ctypes.data_as(ctypes.POINTER(ctypes.c_long)),
-                        _ptr(dm), _ptr(dl), _ptr(dq), _ptr(dr))
-    return dict(mean=dm, log_scale=dl, quat=dq, density=dr)
+                        _ptr(dm), _ptr(dl), _ptr(dq), _ptr(dr), ctypes.c_double(band), _ptr(babs))
+    out = dict(mean=dm, log_scale=dl, quat=dq, density=dr)
+    if band > 0:
+        out["band_abs"] = _split11(babs)
+    return out
 
 
-def voxelize_bwd(gs: dict, grid: dict, grad_vol, kappa: float = KAPPA, sel=None) -> dict:
+def voxelize_bwd(gs: dict, grid: dict, grad_vol, kappa: float = KAPPA, sel=None, band: float = 0.0) -> dict:
+    """Gradient of sum(grad_vol * V); ``band`` as in project_bwd."""
     lib = _load()
     n, keep, p = _gauss_args(gs)
     gv, pgv = _d(grad_vol)
     gr, pgr = _d(_grid_vec(grid))
     sel = np.arange(n, dtype=np.int64) if sel is None else np.ascontiguousarray(sel, dtype=np.int64)
     dm, dl, dq, dr = _bwd_out(sel.shape[0])
+    babs = np.zeros((11, sel.shape[0]))
     lib.orc_voxelize_bwd(ctypes.c_double(kappa), pgr, ctypes.c_long(n), *p, pgv, ctypes.c_long(sel.shape[0]),
                          sel.ctypes.data_as(ctypes.POINTER(ctypes.c_long)),
-                         _ptr(dm), _ptr(dl), _ptr(dq), _ptr(dr))
-    return dict(mean=dm, log_scale=dl, quat=dq, density=dr)
+                         _ptr(dm), _ptr(dl), _ptr(dq), _ptr(dr), ctypes.c_double(band), _ptr(babs))
+    out = dict(mean=dm, log_scale=dl, quat=dq, density=dr)
+    if band > 0:
+        out["band_abs"] = _split11(babs)
+    return out
+
+
+def banded_grad_error(got: dict, ref: dict) -> dict:
+    """Per parameter group: relative L2 of the part of |got - ref| that the
+    boundary band (ref["band_abs"]) cannot explain."""
+    out = {}
+    for k in ("mean", "log_scale", "quat", "density"):
+        g = np.asarray(got[k], dtype=np.float64)
+        r = ref[k]
+        excess = np.maximum(np.abs(g - r) - ref["band_abs"][k], 0.0)
+        out[k] = float(np.linalg.norm(excess.ravel()) / np.linalg.norm(r.ravel()))
+    return out
 
 
 # ---------------------------------------------------------------- phantom

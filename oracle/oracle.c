@@ -667,10 +667,33 @@ static void splat_backward(const view_t *V, const gauss3 *G, const splat_t *S, d
  * the Gaussians listed in sel[n_sel] (every Gaussian's gradient depends on
  * its own support only). Outputs are [3][n_sel], [3][n_sel], [4][n_sel],
  * [n_sel]. grad_img is [n_views][det_h][det_w]. */
+/* Pairs whose d^2 lies within `band` of kappa^2 sit on the support boundary,
+ * where the hard cutoff makes the gradient discontinuous and an evaluation in
+ * any finite precision may include or exclude them. With band > 0 they are
+ * left out of the gradient and the sum over them of |per-pair gradient| is
+ * written to band_abs[11][n_sel] (mean 3, log_scale 3, quat 4, density 1):
+ * any implementation's gradient lies within band_abs of the returned one,
+ * up to its own rounding. band = 0 gives the plain gradient. */
+static void pair_grad_abs(const view_t *V, const gauss3 *G, const splat_t *S, double gg, double du,
+                          double dv, double d2, double *acc11) {
+  double e = exp(-0.5 * d2);
+  double sw = gg * e;
+  double cdu = S->C[0] * du + S->C[1] * dv, cdv = S->C[2] * du + S->C[3] * dv;
+  double sp[2] = {gg * S->w * e * cdu, gg * S->w * e * cdv};
+  double sC[4] = {-0.5 * gg * S->w * e * du * du, -0.5 * gg * S->w * e * du * dv,
+                  -0.5 * gg * S->w * e * dv * du, -0.5 * gg * S->w * e * dv * dv};
+  double m3[3] = {0, 0, 0}, l3[3] = {0, 0, 0}, q4[4] = {0, 0, 0, 0}, r1 = 0.0;
+  splat_backward(V, G, S, sw, sp, sC, m3, l3, q4, &r1);
+  for (int a = 0; a < 3; ++a) { acc11[a] += fabs(m3[a]); acc11[3 + a] += fabs(l3[a]); }
+  for (int c = 0; c < 4; ++c) acc11[6 + c] += fabs(q4[c]);
+  acc11[10] += fabs(r1);
+}
+
 void orc_project_bwd(const double *g, double kappa, int n_views, const double *angles, long n,
                      const double *mean, const double *ls, const double *quat,
                      const double *dens, const double *grad_img, long n_sel, const long *sel,
-                     double *dmean, double *dls, double *dq, double *drho) {
+                     double *dmean, double *dls, double *dq, double *drho, double band,
+                     double *band_abs) {
   int W = (int)g[3], H = (int)g[4];
   view_t *Vs = (view_t *)malloc(sizeof(view_t) * (size_t)n_views);
   for (int v = 0; v < n_views; ++v) make_view(g, angles[v], &Vs[v]);
@@ -680,12 +703,14 @@ void orc_project_bwd(const double *g, double kappa, int n_views, const double *a
     gauss3 G;
     load_gauss(n, i, mean, ls, quat, dens, &G);
     double m3[3] = {0, 0, 0}, l3[3] = {0, 0, 0}, q4[4] = {0, 0, 0, 0}, r1 = 0.0;
+    double babs[11] = {0};
+    double k2 = kappa * kappa;
     for (int v = 0; v < n_views; ++v) {
       splat_t S;
       project_gauss(&Vs[v], &G, &S);
       if (S.culled) continue;
       double box[4];
-      splat_box(&S, kappa, box);
+      splat_box(&S, sqrt(k2 + band), box);
       int x0 = (int)floor(box[0] - 0.5), x1 = (int)ceil(box[1] - 0.5);
       int y0 = (int)floor(box[2] - 0.5), y1 = (int)ceil(box[3] - 0.5);
       if (x0 < 0) x0 = 0;
@@ -698,8 +723,12 @@ void orc_project_bwd(const double *g, double kappa, int n_views, const double *a
         for (int x = x0; x <= x1; ++x) {
           double du = x + 0.5 - S.uv[0], dv = y + 0.5 - S.uv[1];
           double d2 = splat_d2(&S, x + 0.5, y + 0.5);
-          if (d2 > kappa * kappa) continue;
+          if (d2 > k2 + band) continue;
           double gg = gi[(size_t)y * W + x];
+          if (band > 0.0 && fabs(d2 - k2) <= band) {
+            pair_grad_abs(&Vs[v], &G, &S, gg, du, dv, d2, babs);
+            continue;
+          }
           double e = exp(-0.5 * d2);
           sw += gg * e;
           /* d(d2)/d(uv) = -2 C (x - uv): d e / d uv = e C (x - uv) */
@@ -716,14 +745,30 @@ void orc_project_bwd(const double *g, double kappa, int n_views, const double *a
     for (int a = 0; a < 3; ++a) { dmean[a * n_sel + k] = m3[a]; dls[a * n_sel + k] = l3[a]; }
     for (int c = 0; c < 4; ++c) dq[c * n_sel + k] = q4[c];
     drho[k] = r1;
+    if (band_abs)
+      for (int c = 0; c < 11; ++c) band_abs[c * n_sel + k] = babs[c];
   }
   free(Vs);
 }
 
 /* Gradient of L = sum_voxels grad_vol * V for the Gaussians in sel. */
+/* Same band convention as orc_project_bwd. */
+static void voxel_chain(const gauss3 *G, const double A[9], double sr, const double sp[3],
+                        const double sA[9], double m3[3], double l3[3], double q4[4], double *r1) {
+  /* A = Sigma^-1: dSigma = -A dA A */
+  double tmp[9], dSig[9];
+  mat3_mul(A, sA, tmp);
+  mat3_mul(tmp, A, dSig);
+  for (int a = 0; a < 9; ++a) dSig[a] = -dSig[a];
+  sigma_to_params(G, dSig, l3, q4);
+  for (int a = 0; a < 3; ++a) m3[a] = sp[a];
+  *r1 = sr;
+}
+
 void orc_voxelize_bwd(double kappa, const double *gr, long n, const double *mean, const double *ls,
                       const double *quat, const double *dens, const double *grad_vol, long n_sel,
-                      const long *sel, double *dmean, double *dls, double *dq, double *drho) {
+                      const long *sel, double *dmean, double *dls, double *dq, double *drho,
+                      double band, double *band_abs) {
   long nx = (long)gr[6], ny = (long)gr[7];
 #pragma omp parallel for schedule(dynamic, 16)
   for (long k = 0; k < n_sel; ++k) {
@@ -733,8 +778,10 @@ void orc_voxelize_bwd(double kappa, const double *gr, long n, const double *mean
     long lo[3], hi[3];
     load_gauss(n, i, mean, ls, quat, dens, &G);
     mat3_inv(G.Sig, A);
-    vox_box(gr, &G, kappa, lo, hi);
+    double k2 = kappa * kappa;
+    vox_box(gr, &G, sqrt(k2 + band), lo, hi);
     double sr = 0.0, sp[3] = {0, 0, 0}, sA[9] = {0};
+    double babs[11] = {0};
     for (long iz = lo[2]; iz <= hi[2]; ++iz)
       for (long iy = lo[1]; iy <= hi[1]; ++iy)
         for (long ix = lo[0]; ix <= hi[0]; ++ix) {
@@ -744,24 +791,32 @@ void orc_voxelize_bwd(double kappa, const double *gr, long n, const double *mean
           double Ad[3];
           for (int a = 0; a < 3; ++a) Ad[a] = A[3 * a] * dd[0] + A[3 * a + 1] * dd[1] + A[3 * a + 2] * dd[2];
           double d2 = dd[0] * Ad[0] + dd[1] * Ad[1] + dd[2] * Ad[2];
-          if (d2 > kappa * kappa) continue;
+          if (d2 > k2 + band) continue;
           double gg = grad_vol[(iz * ny + iy) * nx + ix];
           double e = exp(-0.5 * d2);
+          if (band > 0.0 && fabs(d2 - k2) <= band) {
+            double psp[3], psA[9], m3[3], l3[3], q4[4], r1;
+            for (int a = 0; a < 3; ++a) psp[a] = gg * G.rho * e * Ad[a];
+            for (int a = 0; a < 3; ++a)
+              for (int b = 0; b < 3; ++b) psA[3 * a + b] = -0.5 * gg * G.rho * e * dd[a] * dd[b];
+            voxel_chain(&G, A, gg * e, psp, psA, m3, l3, q4, &r1);
+            for (int a = 0; a < 3; ++a) { babs[a] += fabs(m3[a]); babs[3 + a] += fabs(l3[a]); }
+            for (int c = 0; c < 4; ++c) babs[6 + c] += fabs(q4[c]);
+            babs[10] += fabs(r1);
+            continue;
+          }
           sr += gg * e;
           for (int a = 0; a < 3; ++a) sp[a] += gg * G.rho * e * Ad[a];
           for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b) sA[3 * a + b] += -0.5 * gg * G.rho * e * dd[a] * dd[b];
         }
-    /* A = Sigma^-1: dSigma = -A dA A */
-    double tmp[9], dSig[9];
-    mat3_mul(A, sA, tmp);
-    mat3_mul(tmp, A, dSig);
-    for (int a = 0; a < 9; ++a) dSig[a] = -dSig[a];
-    double l3[3], q4[4];
-    sigma_to_params(&G, dSig, l3, q4);
-    for (int a = 0; a < 3; ++a) { dmean[a * n_sel + k] = sp[a]; dls[a * n_sel + k] = l3[a]; }
+    double m3[3], l3[3], q4[4], r1;
+    voxel_chain(&G, A, sr, sp, sA, m3, l3, q4, &r1);
+    for (int a = 0; a < 3; ++a) { dmean[a * n_sel + k] = m3[a]; dls[a * n_sel + k] = l3[a]; }
     for (int c = 0; c < 4; ++c) dq[c * n_sel + k] = q4[c];
-    drho[k] = sr;
+    drho[k] = r1;
+    if (band_abs)
+      for (int c = 0; c < 11; ++c) band_abs[c * n_sel + k] = babs[c];
   }
 }
 

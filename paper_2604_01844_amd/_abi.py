@@ -1,0 +1,129 @@
+"""ctypes binding of libfactgs.so (include/factgs.h): argument marshalling only.
+
+Every computation runs in the HIP library. PyTorch supplies device memory
+and the current HIP stream. There is no CPU fallback: if the library is not
+built, or a tensor is not on the GPU, the call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfactgs.so")
+
+FGS_OK = 0
+FGS_E_INVALID = -1
+FGS_E_CAPACITY = -2
+FGS_E_HIP = -3
+FGS_E_UNSUPPORTED = -4
+FGS_CONE = 0
+FGS_PARALLEL = 1
+
+_vp = ctypes.c_void_p
+
+
+class fgs_gaussians(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("mean", _vp), ("log_scale", _vp), ("quat", _vp),
+                ("density", _vp)]
+
+
+class fgs_gaussian_grads(ctypes.Structure):
+    _fields_ = [("mean", _vp), ("log_scale", _vp), ("quat", _vp), ("density", _vp)]
+
+
+class fgs_geom(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("n_views", ctypes.c_int32), ("angles", _vp),
+                ("sod", ctypes.c_float), ("sdd", ctypes.c_float), ("det_w", ctypes.c_int32),
+                ("det_h", ctypes.c_int32), ("pitch_u", ctypes.c_float), ("pitch_v", ctypes.c_float),
+                ("off_u", ctypes.c_float), ("off_v", ctypes.c_float)]
+
+
+class fgs_grid(ctypes.Structure):
+    _fields_ = [("origin", ctypes.c_float * 3), ("spacing", ctypes.c_float * 3),
+                ("dims", ctypes.c_int32 * 3)]
+
+
+class fgs_opts(ctypes.Structure):
+    _fields_ = [("kappa", ctypes.c_float), ("near_plane", ctypes.c_float),
+                ("recompute", ctypes.c_int32), ("reserved", ctypes.c_int32), ("events", _vp)]
+
+
+class fgs_workspace(ctypes.Structure):
+    _fields_ = [("ptr", _vp), ("bytes", ctypes.c_uint64), ("needed", ctypes.c_uint64),
+                ("n_pairs", ctypes.c_uint64), ("n_records", ctypes.c_uint64),
+                ("n_tiles", ctypes.c_uint64), ("kind", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class fgs_phantom(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("centre", _vp), ("semi", _vp), ("quat", _vp), ("amp", _vp)]
+
+
+P = ctypes.POINTER
+# (name, argtypes) of every symbol declared in include/factgs.h
+SIGNATURES = {
+    "fgs_project_views_fwd": [P(fgs_gaussians), P(fgs_geom), ctypes.c_int32, ctypes.c_int32,
+                              P(fgs_opts), _vp, P(fgs_workspace), _vp],
+    "fgs_project_views_bwd": [P(fgs_gaussians), P(fgs_geom), ctypes.c_int32, ctypes.c_int32,
+                              P(fgs_opts), _vp, P(fgs_gaussian_grads), P(fgs_workspace), _vp],
+    "fgs_voxelize_fwd": [P(fgs_gaussians), P(fgs_grid), P(fgs_opts), _vp, P(fgs_workspace), _vp],
+    "fgs_voxelize_bwd": [P(fgs_gaussians), P(fgs_grid), P(fgs_opts), _vp, P(fgs_gaussian_grads),
+                         P(fgs_workspace), _vp],
+    "fgs_l1_loss_grad": [_vp, _vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp, P(fgs_workspace), _vp],
+    "fgs_adam_step": [_vp, _vp, _vp, _vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_float,
+                      ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_int32, _vp],
+    "fgs_project_views_support": [P(fgs_gaussians), P(fgs_geom), ctypes.c_int32, ctypes.c_int32,
+                                  P(fgs_opts), _vp, P(fgs_workspace), _vp],
+    "fgs_voxelize_support": [P(fgs_gaussians), P(fgs_grid), P(fgs_opts), _vp, P(fgs_workspace), _vp],
+    "fgs_psnr": [_vp, _vp, ctypes.c_int64, ctypes.c_float, _vp, P(fgs_workspace), _vp],
+    "fgs_phantom_project": [P(fgs_phantom), P(fgs_geom), ctypes.c_int32, ctypes.c_int32, _vp, _vp],
+    "fgs_phantom_voxelize": [P(fgs_phantom), P(fgs_grid), _vp, _vp],
+    "fgs_binning_layout": [P(fgs_workspace), P(ctypes.c_uint64), P(ctypes.c_uint64)],
+    "fgs_last_error": [],
+    "fgs_version": [],
+}
+
+_lib = None
+
+
+class FgsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libfactgs error {code}: {msg}")
+        self.code = code
+
+
+def lib():
+    """Load libfactgs.so (built in-tree by paper_2604_01844_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run paper_2604_01844_amd/build.py "
+                               "(or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_char_p if name in ("fgs_last_error", "fgs_version") else ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def check(code: int):
+    if code != FGS_OK:
+        raise FgsError(code, lib().fgs_last_error().decode())
+
+
+def ptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("libfactgs takes GPU tensors only")
+    if not t.is_contiguous():
+        raise ValueError("libfactgs takes contiguous tensors only")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def stream_ptr(device=None):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)

@@ -1,0 +1,154 @@
+// Internal declarations of libfactgs: error reporting, workspace carving,
+// launch helpers and the per-Gaussian device math shared by the rasterizer
+// and voxelizer kernels. Not part of the public ABI (include/factgs.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "factgs.h"
+
+namespace fgs {
+
+// ------------------------------------------------------------------ errors
+
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+
+#define FGS_HIP(call)                                     \
+  do {                                                    \
+    hipError_t e_ = (call);                               \
+    if (e_ != hipSuccess) return ::fgs::hip_fail(e_, #call); \
+  } while (0)
+
+#define FGS_LAUNCH_CHECK(what)                            \
+  do {                                                    \
+    hipError_t e_ = hipGetLastError();                    \
+    if (e_ != hipSuccess) return ::fgs::hip_fail(e_, what); \
+  } while (0)
+
+// ------------------------------------------------------------- workspace
+
+constexpr uint64_t kAlign = 256;
+
+inline uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Sequential carving of a caller-owned buffer. Offsets only; `base` may be
+// null when the carver is used just to measure the total.
+struct Carver {
+  char *base;
+  uint64_t used = 0;
+  explicit Carver(void *b) : base(static_cast<char *>(b)) {}
+  template <typename T>
+  T *take(uint64_t count, uint64_t *offset_out = nullptr) {
+    uint64_t off = used;
+    used = align_up(used + count * sizeof(T));
+    if (offset_out) *offset_out = off;
+    return base ? reinterpret_cast<T *>(base + off) : nullptr;
+  }
+};
+
+// ----------------------------------------------------------- scan / sort
+
+// Exclusive prefix sum of n uint32 values, in place: data[n] receives the
+// total. data must hold n + 1 entries. Scratch from scan_scratch_words(n).
+uint64_t scan_scratch_words(uint64_t n);
+int exclusive_scan_u32(uint32_t *data, uint64_t n, uint32_t *scratch, hipStream_t s);
+
+// Stable LSD radix sort of (key, value) uint32 pairs on the low `bits` bits
+// of the key. Input in keys/vals; the sorted result ends in the buffers
+// returned through out_keys/out_vals (either the inputs or the alternates).
+uint64_t sort_scratch_words(uint64_t n);
+int radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
+                     uint64_t n, int bits, uint32_t *scratch, uint32_t **out_keys,
+                     uint32_t **out_vals, hipStream_t s);
+
+inline int bits_for(uint64_t n_values) {  // bits needed to hold 0 .. n_values - 1
+  int b = 0;
+  while ((uint64_t(1) << b) < n_values) ++b;
+  return b;
+}
+
+inline unsigned grid_for(uint64_t n, unsigned block) {
+  return static_cast<unsigned>((n + block - 1) / block);
+}
+
+// ------------------------------------------------------------ device math
+
+// log2(e): exp(x) = exp2(x * log2(e)). Kernels pre-scale quadratic forms by
+// -log2(e)/2 so that the Gaussian factor is a single v_exp_f32.
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kTwoPi = 6.283185307179586f;
+
+struct Mat3 {
+  float m[9];
+};
+
+// Rotation of the normalised quaternion q = (w, x, y, z), Hamilton convention.
+__device__ __forceinline__ void quat_to_rot(float w, float x, float y, float z, float R[9]) {
+  R[0] = 1.f - 2.f * (y * y + z * z);
+  R[1] = 2.f * (x * y - w * z);
+  R[2] = 2.f * (x * z + w * y);
+  R[3] = 2.f * (x * y + w * z);
+  R[4] = 1.f - 2.f * (x * x + z * z);
+  R[5] = 2.f * (y * z - w * x);
+  R[6] = 2.f * (x * z - w * y);
+  R[7] = 2.f * (y * z + w * x);
+  R[8] = 1.f - 2.f * (x * x + y * y);
+}
+
+// Chain rule through quat_to_rot and the normalisation q_hat = q / |q|:
+// dq = (I - q_hat q_hat^T) dq_hat / |q|, dq_hat from dR.
+__device__ __forceinline__ void rot_grad_to_quat(const float qh[4], float qnorm, const float dR[9],
+                                                 float dq[4]) {
+  const float w = qh[0], x = qh[1], y = qh[2], z = qh[3];
+  float gw = 2.f * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+  float gx = 2.f * (y * dR[1] + z * dR[2] + y * dR[3] - 2.f * x * dR[4] - w * dR[5] + z * dR[6] +
+                    w * dR[7] - 2.f * x * dR[8]);
+  float gy = 2.f * (-2.f * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] +
+                    z * dR[7] - 2.f * y * dR[8]);
+  float gz = 2.f * (-2.f * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.f * z * dR[4] +
+                    y * dR[5] + x * dR[6] + y * dR[7]);
+  float dot = gw * w + gx * x + gy * y + gz * z;
+  float inv = 1.f / qnorm;
+  dq[0] = (gw - w * dot) * inv;
+  dq[1] = (gx - x * dot) * inv;
+  dq[2] = (gy - y * dot) * inv;
+  dq[3] = (gz - z * dot) * inv;
+}
+
+// One Gaussian's parameters as loaded from the SoA inputs.
+struct GaussParams {
+  float p[3];
+  float s[3];    // standard deviations exp(log_scale)
+  float qh[4];   // normalised quaternion
+  float qnorm;
+  float R[9];    // rotation (columns are principal axes)
+  float rho;
+};
+
+__device__ __forceinline__ void load_gauss(const fgs_gaussians &g, int64_t i, GaussParams &G) {
+  const int64_t n = g.n;
+  G.p[0] = g.mean[i];
+  G.p[1] = g.mean[n + i];
+  G.p[2] = g.mean[2 * n + i];
+  G.s[0] = expf(g.log_scale[i]);
+  G.s[1] = expf(g.log_scale[n + i]);
+  G.s[2] = expf(g.log_scale[2 * n + i]);
+  float w = g.quat[i], x = g.quat[n + i], y = g.quat[2 * n + i], z = g.quat[3 * n + i];
+  float nn = sqrtf(w * w + x * x + y * y + z * z);
+  G.qnorm = nn;
+  float inv = 1.f / nn;
+  G.qh[0] = w * inv;
+  G.qh[1] = x * inv;
+  G.qh[2] = y * inv;
+  G.qh[3] = z * inv;
+  quat_to_rot(G.qh[0], G.qh[1], G.qh[2], G.qh[3], G.R);
+  G.rho = g.density[i];
+}
+
+}  // namespace fgs

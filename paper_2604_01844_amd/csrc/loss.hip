@@ -1,0 +1,149 @@
+// Loss, metric and optimiser kernels of the reconstruction loop:
+// the L1 term of Eq. 5 with its gradient, PSNR, and Adam.
+// Reductions are two-level with a fixed block count, so results do not
+// depend on timing (no atomics).
+#include <cmath>
+
+#include "fgs_internal.h"
+
+namespace fgs {
+namespace {
+
+constexpr int kRedThreads = 256;
+constexpr int kRedBlocks = 1024;
+
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < kRedThreads / 64; ++w) t += sh[w];
+  return t;
+}
+
+// partial[b] = sum over this block's grid-stride share of |img - gt|; grad
+// written alongside.
+__global__ __launch_bounds__(kRedThreads) void l1_kernel(const float *__restrict__ img,
+                                                         const float *__restrict__ gt, uint64_t n,
+                                                         float inv_p, float *__restrict__ grad,
+                                                         double *__restrict__ partial) {
+  __shared__ double sh[kRedThreads / 64];
+  double acc = 0.0;
+  for (uint64_t i = uint64_t(blockIdx.x) * kRedThreads + threadIdx.x; i < n;
+       i += uint64_t(gridDim.x) * kRedThreads) {
+    const float d = img[i] - gt[i];
+    acc += fabs(double(d));
+    if (grad) grad[i] = (d > 0.f) ? inv_p : ((d < 0.f) ? -inv_p : 0.f);
+  }
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kRedThreads) void sq_err_kernel(const float *__restrict__ a,
+                                                             const float *__restrict__ b, uint64_t n,
+                                                             double *__restrict__ partial) {
+  __shared__ double sh[kRedThreads / 64];
+  double acc = 0.0;
+  for (uint64_t i = uint64_t(blockIdx.x) * kRedThreads + threadIdx.x; i < n;
+       i += uint64_t(gridDim.x) * kRedThreads) {
+    const double d = double(a[i]) - double(b[i]);
+    acc += d * d;
+  }
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// mode 0: out = scale * sum; mode 1: out = 10 log10(peak^2 / (sum / n))
+__global__ __launch_bounds__(kRedThreads) void finish_kernel(const double *__restrict__ partial, int nb,
+                                                             int mode, double scale, double peak,
+                                                             double n, float *__restrict__ out) {
+  __shared__ double sh[kRedThreads / 64];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nb; i += kRedThreads) acc += partial[i];
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) {
+    if (mode == 0)
+      out[0] = float(t * scale);
+    else
+      out[0] = float(10.0 * log10(peak * peak / (t / n)));
+  }
+}
+
+__global__ __launch_bounds__(256) void adam_kernel(float *__restrict__ p, const float *__restrict__ g,
+                                                   const float *__restrict__ g2,
+                                                   float *__restrict__ m, float *__restrict__ v,
+                                                   uint64_t n, float lr, float b1, float b2, float eps,
+                                                   float c1, float c2, int clamp0) {
+  const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g2 ? g[i] + g2[i] : g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float mh = mi / c1;
+  const float vh = vi / c2;
+  float x = p[i] - lr * mh / (sqrtf(vh) + eps);
+  if (clamp0) x = fmaxf(x, 0.f);
+  p[i] = x;
+}
+
+int reduce_blocks(uint64_t n) {
+  uint64_t b = (n + kRedThreads - 1) / kRedThreads;
+  return int(b < kRedBlocks ? (b ? b : 1) : kRedBlocks);
+}
+
+}  // namespace
+}  // namespace fgs
+
+using namespace fgs;
+
+extern "C" int fgs_l1_loss_grad(const float *img, const float *gt, int64_t n_per_view, int32_t n_views,
+                                float *loss, float *grad, fgs_workspace *ws, void *stream) {
+  if (!img || !gt || !loss || !ws || !ws->ptr) return fail(FGS_E_INVALID, "null argument");
+  if (n_per_view <= 0 || n_views <= 0) return fail(FGS_E_INVALID, "sizes");
+  ws->needed = kRedBlocks * sizeof(double);
+  if (ws->bytes < ws->needed) return fail(FGS_E_CAPACITY, "workspace too small");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const uint64_t n = uint64_t(n_per_view) * uint64_t(n_views);
+  const int nb = reduce_blocks(n);
+  double *partial = static_cast<double *>(ws->ptr);
+  const float inv_p = 1.f / float(n_per_view);
+  l1_kernel<<<nb, kRedThreads, 0, s>>>(img, gt, n, inv_p, grad, partial);
+  FGS_LAUNCH_CHECK("l1_kernel");
+  finish_kernel<<<1, kRedThreads, 0, s>>>(partial, nb, 0, 1.0 / double(n_per_view), 0.0, 0.0, loss);
+  FGS_LAUNCH_CHECK("finish_kernel");
+  return FGS_OK;
+}
+
+extern "C" int fgs_psnr(const float *vol, const float *ref, int64_t n, float peak, float *out,
+                        fgs_workspace *ws, void *stream) {
+  if (!vol || !ref || !out || !ws || !ws->ptr) return fail(FGS_E_INVALID, "null argument");
+  if (n <= 0 || !(peak > 0.f)) return fail(FGS_E_INVALID, "sizes or peak");
+  ws->needed = kRedBlocks * sizeof(double);
+  if (ws->bytes < ws->needed) return fail(FGS_E_CAPACITY, "workspace too small");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int nb = reduce_blocks(uint64_t(n));
+  double *partial = static_cast<double *>(ws->ptr);
+  sq_err_kernel<<<nb, kRedThreads, 0, s>>>(vol, ref, uint64_t(n), partial);
+  FGS_LAUNCH_CHECK("sq_err_kernel");
+  finish_kernel<<<1, kRedThreads, 0, s>>>(partial, nb, 1, 0.0, double(peak), double(n), out);
+  FGS_LAUNCH_CHECK("finish_kernel");
+  return FGS_OK;
+}
+
+extern "C" int fgs_adam_step(float *param, const float *grad, const float *grad2, float *m, float *v,
+                             int64_t n, int32_t step, float lr, float beta1, float beta2, float eps,
+                             int32_t clamp_min_zero, void *stream) {
+  if (!param || !grad || !m || !v) return fail(FGS_E_INVALID, "null argument");
+  if (n <= 0 || step < 1) return fail(FGS_E_INVALID, "sizes or step");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const float c1 = float(1.0 - std::pow(double(beta1), double(step)));
+  const float c2 = float(1.0 - std::pow(double(beta2), double(step)));
+  adam_kernel<<<grid_for(uint64_t(n), 256), 256, 0, s>>>(param, grad, grad2, m, v, uint64_t(n), lr, beta1, beta2, eps,
+                                                         c1, c2, clamp_min_zero);
+  FGS_LAUNCH_CHECK("adam_kernel");
+  return FGS_OK;
+}

@@ -1,0 +1,269 @@
+// Device-wide exclusive scan and stable LSD radix sort of uint32 (key, value)
+// pairs, written for 64-wide wavefronts.
+//
+// The rasterizer and voxelizer bin Gaussians into tiles without any depth
+// ordering (the X-ray sum is order-free, Sec. 3.5): the sort key is only the
+// (view, tile) index. Keys are emitted in record order, so a stable sort
+// leaves each tile's list in ascending Gaussian index, which fixes the
+// summation order and makes every result bit-reproducible.
+//
+// Scan: reduce-then-scan over tiles of 4096 values (256 threads x 16).
+// Sort: per pass of up to 9 key bits, (1) a per-tile digit histogram in LDS,
+// (2) an exclusive scan of the digit-major histogram table, (3) a scatter in
+// which every wave ranks its keys with ballot-based digit matching (64-bit
+// lane masks), so the local order of equal digits is the input order.
+#include "fgs_internal.h"
+
+namespace fgs {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kItems = 16;
+constexpr int kTile = kThreads * kItems;  // 4096
+constexpr int kWaves = kThreads / 64;
+constexpr int kMaxBits = 9;
+constexpr int kBins = 1 << kMaxBits;
+
+// Exclusive scan of one value per thread across the 256-thread block.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *wsum,
+                                                         uint32_t &total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) wsum[wid] = x;
+  __syncthreads();
+  uint32_t base = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    uint32_t s = wsum[w];
+    base += (w < wid) ? s : 0u;
+    tot += s;
+  }
+  total = tot;
+  __syncthreads();
+  return base + x - v;
+}
+
+__global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const uint32_t *__restrict__ data,
+                                                               uint64_t n,
+                                                               uint32_t *__restrict__ partial) {
+  __shared__ uint32_t wsum[kWaves];
+  const uint64_t base = uint64_t(blockIdx.x) * kTile;
+  uint32_t s = 0;
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    uint64_t idx = base + uint64_t(j) * kThreads + threadIdx.x;
+    s += (idx < n) ? data[idx] : 0u;
+  }
+  uint32_t total;
+  block_exclusive_scan(s, wsum, total);
+  if (threadIdx.x == 0) partial[blockIdx.x] = total;
+}
+
+// Scans one tile in LDS; adds the scanned tile offset (partial, may be null
+// for a single tile). The last tile writes the grand total to data[n].
+__global__ __launch_bounds__(kThreads) void scan_apply_kernel(uint32_t *__restrict__ data,
+                                                              uint64_t n,
+                                                              const uint32_t *__restrict__ partial,
+                                                              uint32_t n_tiles) {
+  __shared__ uint32_t tile[kTile + kTile / 32];
+  __shared__ uint32_t wsum[kWaves];
+  const uint64_t base = uint64_t(blockIdx.x) * kTile;
+  // padded index: one spare word every 32 to spread the strided reads over banks
+  auto pad = [](int i) { return i + (i >> 5); };
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    int li = j * kThreads + threadIdx.x;
+    uint64_t idx = base + li;
+    tile[pad(li)] = (idx < n) ? data[idx] : 0u;
+  }
+  __syncthreads();
+  uint32_t v[kItems];
+  uint32_t s = 0;
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    v[j] = tile[pad(threadIdx.x * kItems + j)];
+    s += v[j];
+  }
+  uint32_t total;
+  uint32_t run = block_exclusive_scan(s, wsum, total);
+  const uint32_t off = partial ? partial[blockIdx.x] : 0u;
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    tile[pad(threadIdx.x * kItems + j)] = run + off;
+    run += v[j];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    int li = j * kThreads + threadIdx.x;
+    uint64_t idx = base + li;
+    if (idx < n) data[idx] = tile[pad(li)];
+  }
+  if (blockIdx.x == n_tiles - 1 && threadIdx.x == 0) data[n] = off + total;
+}
+
+// ------------------------------------------------------------- radix sort
+
+__global__ __launch_bounds__(kThreads) void rs_hist_kernel(const uint32_t *__restrict__ keys,
+                                                           uint64_t n, int shift, uint32_t mask,
+                                                           uint32_t *__restrict__ hist,
+                                                           uint32_t n_tiles) {
+  __shared__ uint32_t h[kBins];
+  for (int i = threadIdx.x; i < kBins; i += kThreads) h[i] = 0;
+  __syncthreads();
+  const uint64_t base = uint64_t(blockIdx.x) * kTile;
+#pragma unroll 4
+  for (int j = 0; j < kItems; ++j) {
+    uint64_t idx = base + uint64_t(j) * kThreads + threadIdx.x;
+    if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & mask], 1u);
+  }
+  __syncthreads();
+  for (uint32_t d = threadIdx.x; d <= mask; d += kThreads) hist[uint64_t(d) * n_tiles + blockIdx.x] = h[d];
+}
+
+// Stable scatter of one pass. Tile t covers input [t*4096, t*4096 + 4096);
+// wave w of the tile owns the contiguous quarter [w*1024, w*1024 + 1024),
+// processed 64 keys at a time, so (wave, round, lane) order is input order.
+__global__ __launch_bounds__(kThreads) void rs_scatter_kernel(
+    const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in, uint64_t n,
+    int shift, int nbits, const uint32_t *__restrict__ hist_scanned, uint32_t n_tiles,
+    uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out) {
+  __shared__ uint32_t cnt[kWaves][kBins];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const uint32_t mask = (1u << nbits) - 1u;
+  for (int i = threadIdx.x; i < kWaves * kBins; i += kThreads) (&cnt[0][0])[i] = 0;
+  __syncthreads();
+
+  const uint64_t wbase = uint64_t(blockIdx.x) * kTile + uint64_t(wid) * (kItems * 64);
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  uint32_t k[kItems], v[kItems], rank[kItems];
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const uint64_t idx = wbase + uint64_t(j) * 64 + lane;
+    const bool valid = idx < n;
+    const uint32_t key = valid ? keys_in[idx] : 0u;
+    const uint32_t d = (key >> shift) & mask;
+    uint64_t peers = __ballot(valid);
+    for (int b = 0; b < nbits; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t m = __ballot(bit);
+      peers &= bit ? m : ~m;
+    }
+    const uint32_t before = __popcll(peers & lt_mask);
+    uint32_t c = 0;
+    if (valid) c = cnt[wid][d];
+    // the lowest lane of each digit group advances the wave's running count
+    if (valid && before == 0) cnt[wid][d] = c + __popcll(peers);
+    rank[j] = c + before;
+    k[j] = key;
+    v[j] = valid ? vals_in[idx] : 0u;
+  }
+  __syncthreads();
+  // per digit: offset of this wave inside the tile's run of that digit,
+  // plus the tile's global offset for the digit
+  for (uint32_t d = threadIdx.x; d <= mask; d += kThreads) {
+    uint32_t run = hist_scanned[uint64_t(d) * n_tiles + blockIdx.x];
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+      uint32_t c = cnt[w][d];
+      cnt[w][d] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const uint64_t idx = wbase + uint64_t(j) * 64 + lane;
+    if (idx < n) {
+      const uint32_t d = (k[j] >> shift) & mask;
+      const uint32_t pos = cnt[wid][d] + rank[j];
+      keys_out[pos] = k[j];
+      vals_out[pos] = v[j];
+    }
+  }
+}
+
+__global__ void set_zero_kernel(uint32_t *p) { *p = 0u; }
+
+}  // namespace
+
+uint64_t scan_scratch_words(uint64_t n) {
+  uint64_t words = 0;
+  uint64_t m = n;
+  while (m > uint64_t(kTile)) {
+    uint64_t tiles = (m + kTile - 1) / kTile;
+    words += align_up((tiles + 1) * sizeof(uint32_t)) / sizeof(uint32_t);
+    m = tiles;
+  }
+  return words + 64;
+}
+
+int exclusive_scan_u32(uint32_t *data, uint64_t n, uint32_t *scratch, hipStream_t s) {
+  if (n == 0) {
+    // total of an empty array (a kernel, not a memset node, so the call can be captured)
+    set_zero_kernel<<<1, 1, 0, s>>>(data);
+    FGS_LAUNCH_CHECK("set_zero_kernel");
+    return FGS_OK;
+  }
+  const uint64_t tiles = (n + kTile - 1) / kTile;
+  if (tiles == 1) {
+    scan_apply_kernel<<<1, kThreads, 0, s>>>(data, n, nullptr, 1);
+    FGS_LAUNCH_CHECK("scan_apply_kernel");
+    return FGS_OK;
+  }
+  if (tiles > 0xffffffffull) return fail(FGS_E_UNSUPPORTED, "scan: too many elements");
+  uint32_t *partial = scratch;
+  uint32_t *rest = scratch + align_up((tiles + 1) * sizeof(uint32_t)) / sizeof(uint32_t);
+  scan_reduce_kernel<<<unsigned(tiles), kThreads, 0, s>>>(data, n, partial);
+  FGS_LAUNCH_CHECK("scan_reduce_kernel");
+  int st = exclusive_scan_u32(partial, tiles, rest, s);
+  if (st != FGS_OK) return st;
+  scan_apply_kernel<<<unsigned(tiles), kThreads, 0, s>>>(data, n, partial, unsigned(tiles));
+  FGS_LAUNCH_CHECK("scan_apply_kernel");
+  return FGS_OK;
+}
+
+uint64_t sort_scratch_words(uint64_t n) {
+  const uint64_t tiles = (n + kTile - 1) / kTile;
+  const uint64_t table = uint64_t(kBins) * tiles;
+  return align_up((table + 1) * sizeof(uint32_t)) / sizeof(uint32_t) + scan_scratch_words(table);
+}
+
+int radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
+                     uint64_t n, int bits, uint32_t *scratch, uint32_t **out_keys,
+                     uint32_t **out_vals, hipStream_t s) {
+  *out_keys = keys;
+  *out_vals = vals;
+  if (n <= 1 || bits <= 0) return FGS_OK;
+  if (n > 0xffffffffull) return fail(FGS_E_UNSUPPORTED, "sort: more than 2^32 pairs");
+  const uint64_t tiles = (n + kTile - 1) / kTile;
+  const int passes = (bits + kMaxBits - 1) / kMaxBits;
+  const int per = (bits + passes - 1) / passes;
+  uint32_t *table = scratch;
+  uint32_t *scan_tmp = scratch + align_up((uint64_t(kBins) * tiles + 1) * sizeof(uint32_t)) / sizeof(uint32_t);
+  uint32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
+  for (int p = 0, shift = 0; p < passes; ++p, shift += per) {
+    const int nb = (bits - shift < per) ? (bits - shift) : per;
+    const uint32_t mask = (1u << nb) - 1u;
+    rs_hist_kernel<<<unsigned(tiles), kThreads, 0, s>>>(ki, n, shift, mask, table, unsigned(tiles));
+    FGS_LAUNCH_CHECK("rs_hist_kernel");
+    int st = exclusive_scan_u32(table, uint64_t(mask + 1) * tiles, scan_tmp, s);
+    if (st != FGS_OK) return st;
+    rs_scatter_kernel<<<unsigned(tiles), kThreads, 0, s>>>(ki, vi, n, shift, nb, table,
+                                                           unsigned(tiles), ko, vo);
+    FGS_LAUNCH_CHECK("rs_scatter_kernel");
+    uint32_t *t;
+    t = ki; ki = ko; ko = t;
+    t = vi; vi = vo; vo = t;
+  }
+  *out_keys = ki;
+  *out_vals = vi;
+  return FGS_OK;
+}
+
+}  // namespace fgs

@@ -1,0 +1,600 @@
+// Voxelizer (Eq. 2, Sec. 3.3) for gfx950: the density field sampled at the
+// voxel centres of a regular grid, each Gaussian limited to its kappa-sigma
+// ellipsoid, and its backward.
+//
+// Same structure as the rasterizer, one dimension up:
+//   record kernel   per Gaussian: centre in voxel-index coordinates and rho
+//                   (float4, the position+radius packing of Sec. 3.5), the
+//                   voxel-unit inverse covariance pre-scaled by -log2(e)/2,
+//                   half-extents in voxels, the 3D rectangle of 8^3-voxel
+//                   tiles it touches and its tile count;
+//   scan / emit / stable radix sort / ranges as in the rasterizer;
+//   forward         one wave per 8^3 tile; each lane owns one x-row of 8
+//                   voxels; records staged in LDS in batches of 64;
+//   backward        one wave per tile; each lane owns one (tile, Gaussian)
+//                   pair and sums the ten moments sum g e {1, d, d d^T} over
+//                   the tile's 512 voxels; per Gaussian, its contiguous
+//                   partials are reduced in order and the chain rule applied.
+#include "fgs_internal.h"
+
+namespace fgs {
+namespace {
+
+constexpr int kVT = 8;     // voxel tile side
+constexpr int kWave = 64;
+
+struct __align__(16) Rect3 {
+  unsigned short v[8];     // x0, y0, z0, x1, y1, z1, 0, 0
+};
+
+struct GridDev {
+  float origin[3];
+  float h[3];
+  int dims[3];
+  int nt[3];               // tiles per axis
+  float kappa;
+};
+
+// Voxel-unit quantities of one Gaussian: W = diag(1/h) R diag(1/s) is such
+// that A_vox = W W^T is the inverse covariance in voxel-index units.
+struct VoxGauss {
+  float pv[3];             // centre in voxel-index coordinates
+  float W[3][3];
+  float A[3][3];
+  float r[3];              // kappa-sigma half-extents in voxels
+};
+
+__device__ __forceinline__ void vox_gauss(const GaussParams &P, const GridDev &G, VoxGauss &V) {
+  for (int a = 0; a < 3; ++a) {
+    V.pv[a] = (P.p[a] - G.origin[a]) / G.h[a] - 0.5f;
+    float var = 0.f;
+    for (int j = 0; j < 3; ++j) {
+      V.W[a][j] = G.h[a] * P.R[3 * a + j] / P.s[j];
+      const float rs = P.R[3 * a + j] * P.s[j];
+      var += rs * rs;
+    }
+    V.r[a] = G.kappa * sqrtf(var) / G.h[a];
+  }
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      V.A[a][b] = V.W[a][0] * V.W[b][0] + V.W[a][1] * V.W[b][1] + V.W[a][2] * V.W[b][2];
+}
+
+__device__ __forceinline__ void vox_span(float c, float r, int n_tiles, int &t0, int &t1) {
+#pragma clang fp contract(off)
+  const float lim = 16777216.f;
+  float lo = fminf(fmaxf(c - r, -lim), lim);
+  float hi = fminf(fmaxf(c + r, -lim), lim);
+  t0 = max(static_cast<int>(floorf(lo)) >> 3, 0);
+  t1 = min(static_cast<int>(floorf(hi)) >> 3, n_tiles - 1);
+}
+
+__global__ void zero_u64_kernel(unsigned long long *p) { *p = 0ull; }
+
+__global__ __launch_bounds__(256) void vox_record_kernel(fgs_gaussians g, GridDev G,
+                                                         float4 *__restrict__ prho,
+                                                         float4 *__restrict__ a0,
+                                                         float4 *__restrict__ a1,
+                                                         float4 *__restrict__ radii,
+                                                         Rect3 *__restrict__ rect,
+                                                         uint32_t *__restrict__ count,
+                                                         unsigned long long *__restrict__ total64) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  uint32_t cnt = 0;
+  if (i < g.n) {
+    GaussParams P;
+    load_gauss(g, i, P);
+    VoxGauss V;
+    vox_gauss(P, G, V);
+    const float k = -0.5f * kLog2e;
+    prho[i] = make_float4(V.pv[0], V.pv[1], V.pv[2], P.rho);
+    a0[i] = make_float4(k * V.A[0][0], 2.f * k * V.A[0][1], 2.f * k * V.A[0][2], k * V.A[1][1]);
+    a1[i] = make_float4(2.f * k * V.A[1][2], k * V.A[2][2], 0.f, 0.f);
+    radii[i] = make_float4(V.r[0], V.r[1], V.r[2], 0.f);
+    int t0[3], t1[3];
+    bool empty = false;
+    for (int a = 0; a < 3; ++a) {
+      vox_span(V.pv[a], V.r[a], G.nt[a], t0[a], t1[a]);
+      empty |= t0[a] > t1[a];
+    }
+    Rect3 rc;
+    if (empty || !isfinite(V.pv[0] + V.pv[1] + V.pv[2])) {
+      for (int a = 0; a < 8; ++a) rc.v[a] = 0;
+      rc.v[0] = rc.v[1] = rc.v[2] = 1;
+    } else {
+      for (int a = 0; a < 3; ++a) {
+        rc.v[a] = static_cast<unsigned short>(t0[a]);
+        rc.v[3 + a] = static_cast<unsigned short>(t1[a]);
+      }
+      rc.v[6] = rc.v[7] = 0;
+      cnt = uint32_t(t1[0] - t0[0] + 1) * uint32_t(t1[1] - t0[1] + 1) * uint32_t(t1[2] - t0[2] + 1);
+    }
+    rect[i] = rc;
+    count[i] = cnt;
+  }
+  unsigned long long w = cnt;
+  for (int d = 32; d > 0; d >>= 1) w += __shfl_xor(w, d, 64);
+  if ((threadIdx.x & 63) == 0 && w) atomicAdd(total64, w);
+}
+
+__global__ __launch_bounds__(256) void vox_emit_kernel(int64_t n, int ntx, int nty,
+                                                       const Rect3 *__restrict__ rect,
+                                                       const uint32_t *__restrict__ offset,
+                                                       uint32_t *__restrict__ keys,
+                                                       uint32_t *__restrict__ vals) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t o = offset[i];
+  if (o == offset[i + 1]) return;
+  const Rect3 rc = rect[i];
+  for (int tz = rc.v[2]; tz <= rc.v[5]; ++tz)
+    for (int ty = rc.v[1]; ty <= rc.v[4]; ++ty)
+      for (int tx = rc.v[0]; tx <= rc.v[3]; ++tx) {
+        keys[o] = uint32_t((tz * nty + ty) * ntx + tx);
+        vals[o] = uint32_t(i);
+        ++o;
+      }
+}
+
+__global__ __launch_bounds__(256) void vox_ranges_kernel(const uint32_t *__restrict__ skeys, uint64_t K,
+                                                         uint32_t T, uint32_t *__restrict__ start) {
+  const uint64_t k = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k > K) return;
+  const int64_t prev = (k == 0) ? -1 : int64_t(skeys[k - 1]);
+  const int64_t cur = (k == K) ? int64_t(T) : int64_t(skeys[k]);
+  for (int64_t t = prev + 1; t <= cur; ++t) start[t] = uint32_t(k);
+}
+
+// kCount = true: count the (voxel, Gaussian) pairs in the support whose voxel
+// lies in the grid (the algorithmic work) instead of writing the volume.
+template <bool kCount>
+__global__ __launch_bounds__(kWave) void vox_fwd_kernel(const uint32_t *__restrict__ start,
+                                                        const uint32_t *__restrict__ svals,
+                                                        const float4 *__restrict__ prho,
+                                                        const float4 *__restrict__ a0,
+                                                        const float4 *__restrict__ a1, GridDev G,
+                                                        float thr, float *__restrict__ vol,
+                                                        unsigned long long *__restrict__ counter) {
+  __shared__ float4 s_p[kWave], s_a0[kWave], s_a1[kWave];
+  const uint32_t tile = blockIdx.x;
+  const int tx = int(tile % uint32_t(G.nt[0]));
+  const int tyz = int(tile / uint32_t(G.nt[0]));
+  const int ty = tyz % G.nt[1];
+  const int tz = tyz / G.nt[1];
+  const int lane = threadIdx.x;
+  const int y = ty * kVT + (lane & 7);
+  const int z = tz * kVT + (lane >> 3);
+  const float fx0 = float(tx * kVT), fy = float(y), fz = float(z);
+  float acc[kVT];
+#pragma unroll
+  for (int k = 0; k < kVT; ++k) acc[k] = 0.f;
+  const uint32_t b0 = start[tile], e = start[tile + 1];
+  for (uint32_t b = b0; b < e; b += kWave) {
+    const uint32_t m = min(uint32_t(kWave), e - b);
+    if (uint32_t(lane) < m) {
+      const uint32_t r = svals[b + lane];
+      s_p[lane] = prho[r];
+      s_a0[lane] = a0[r];
+      s_a1[lane] = a1[r];
+    }
+    __syncthreads();
+    for (uint32_t j = 0; j < m; ++j) {
+      const float4 p = s_p[j];
+      const float4 c0 = s_a0[j];
+      const float4 c1 = s_a1[j];
+      const float dy = fy - p.y, dz = fz - p.z;
+      const float B = fmaf(c0.y, dy, c0.z * dz);
+      const float Cc = fmaf(dy, fmaf(c0.w, dy, c1.x * dz), c1.y * dz * dz);
+      const float dx0 = fx0 - p.x;
+#pragma unroll
+      for (int k = 0; k < kVT; ++k) {
+        const float dx = dx0 + float(k);
+        const float arg = fmaf(dx, fmaf(c0.x, dx, B), Cc);
+        if (kCount) {
+          acc[k] += (arg >= thr) ? 1.f : 0.f;
+        } else {
+          const float ex = __builtin_amdgcn_exp2f(arg);
+          acc[k] += (arg >= thr) ? p.w * ex : 0.f;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (kCount) {
+    unsigned long long n = 0;
+    if (y < G.dims[1] && z < G.dims[2]) {
+#pragma unroll
+      for (int k = 0; k < kVT; ++k)
+        if (tx * kVT + k < G.dims[0]) n += static_cast<unsigned long long>(acc[k]);
+    }
+    for (int d = 32; d > 0; d >>= 1) n += __shfl_xor(n, d, 64);
+    if (lane == 0 && n) atomicAdd(counter, n);
+    return;
+  }
+  if (y < G.dims[1] && z < G.dims[2]) {
+    float *row = vol + (uint64_t(z) * G.dims[1] + y) * uint64_t(G.dims[0]);
+#pragma unroll
+    for (int k = 0; k < kVT; ++k) {
+      const int x = tx * kVT + k;
+      if (x < G.dims[0]) row[x] = acc[k];
+    }
+  }
+}
+
+__global__ __launch_bounds__(kWave) void vox_bwd_kernel(const uint32_t *__restrict__ start,
+                                                        const uint32_t *__restrict__ svals,
+                                                        const float4 *__restrict__ prho,
+                                                        const float4 *__restrict__ a0,
+                                                        const float4 *__restrict__ a1,
+                                                        const Rect3 *__restrict__ rect,
+                                                        const uint32_t *__restrict__ offset,
+                                                        GridDev G, float thr,
+                                                        const float *__restrict__ gvol,
+                                                        float2 *__restrict__ partials) {
+  __shared__ float s_g[kVT * kVT * kVT];
+  const uint32_t tile = blockIdx.x;
+  const int tx = int(tile % uint32_t(G.nt[0]));
+  const int tyz = int(tile / uint32_t(G.nt[0]));
+  const int ty = tyz % G.nt[1];
+  const int tz = tyz / G.nt[1];
+  const int lane = threadIdx.x;
+  for (int q = lane; q < kVT * kVT * kVT; q += kWave) {
+    const int x = tx * kVT + (q & 7), y = ty * kVT + ((q >> 3) & 7), z = tz * kVT + (q >> 6);
+    s_g[q] = (x < G.dims[0] && y < G.dims[1] && z < G.dims[2])
+                 ? gvol[(uint64_t(z) * G.dims[1] + y) * uint64_t(G.dims[0]) + x]
+                 : 0.f;
+  }
+  __syncthreads();
+  const uint32_t b0 = start[tile], e = start[tile + 1];
+  const float ox = float(tx * kVT), oy = float(ty * kVT), oz = float(tz * kVT);
+  for (uint32_t b = b0; b < e; b += kWave) {
+    const uint32_t k = b + lane;
+    const bool active = k < e;
+    float4 p = make_float4(0.f, 0.f, 0.f, 0.f), c0 = p, c1 = p;
+    uint32_t r = 0;
+    if (active) {
+      r = svals[k];
+      p = prho[r];
+      c0 = a0[r];
+      c1 = a1[r];
+    }
+    const float qx = p.x - ox, qy = p.y - oy, qz = p.z - oz;
+    float S0 = 0.f, Sx = 0.f, Sy = 0.f, Sz = 0.f;
+    float Sxx = 0.f, Sxy = 0.f, Sxz = 0.f, Syy = 0.f, Syz = 0.f, Szz = 0.f;
+    for (int zz = 0; zz < kVT; ++zz) {
+      const float dz = float(zz) - qz;
+      for (int yy = 0; yy < kVT; ++yy) {
+        const float dy = float(yy) - qy;
+        const float B = fmaf(c0.y, dy, c0.z * dz);
+        const float Cc = fmaf(dy, fmaf(c0.w, dy, c1.x * dz), c1.y * dz * dz);
+        const float *gr = s_g + (zz * kVT + yy) * kVT;
+        float R0 = 0.f, RX = 0.f, RXX = 0.f;
+#pragma unroll
+        for (int xx = 0; xx < kVT; ++xx) {
+          const float dx = float(xx) - qx;
+          const float arg = fmaf(dx, fmaf(c0.x, dx, B), Cc);
+          const float ex = __builtin_amdgcn_exp2f(arg);
+          const float ge = (arg >= thr) ? gr[xx] * ex : 0.f;
+          R0 += ge;
+          const float gx = ge * dx;
+          RX += gx;
+          RXX = fmaf(gx, dx, RXX);
+        }
+        S0 += R0;
+        Sx += RX;
+        Sy = fmaf(R0, dy, Sy);
+        Sz = fmaf(R0, dz, Sz);
+        Sxx += RXX;
+        Sxy = fmaf(RX, dy, Sxy);
+        Sxz = fmaf(RX, dz, Sxz);
+        const float Rdy = R0 * dy;
+        Syy = fmaf(Rdy, dy, Syy);
+        Syz = fmaf(Rdy, dz, Syz);
+        Szz = fmaf(R0 * dz, dz, Szz);
+      }
+    }
+    if (active) {
+      const Rect3 rc = rect[r];
+      const uint32_t nx = uint32_t(rc.v[3] - rc.v[0] + 1), ny = uint32_t(rc.v[4] - rc.v[1] + 1);
+      const uint32_t j = (uint32_t(tz - rc.v[2]) * ny + uint32_t(ty - rc.v[1])) * nx + uint32_t(tx - rc.v[0]);
+      const uint64_t q = uint64_t(offset[r]) + j;
+      partials[5 * q + 0] = make_float2(S0, Sx);
+      partials[5 * q + 1] = make_float2(Sy, Sz);
+      partials[5 * q + 2] = make_float2(Sxx, Sxy);
+      partials[5 * q + 3] = make_float2(Sxz, Syy);
+      partials[5 * q + 4] = make_float2(Syz, Szz);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void vox_grad_kernel(fgs_gaussians g, GridDev G,
+                                                       const uint32_t *__restrict__ offset,
+                                                       const float2 *__restrict__ partials,
+                                                       fgs_gaussian_grads out) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= g.n) return;
+  const int64_t n = g.n;
+  const uint32_t o = offset[i], end = offset[i + 1];
+  float s[10];
+#pragma unroll
+  for (int c = 0; c < 10; ++c) s[c] = 0.f;
+  for (uint32_t q = o; q < end; ++q) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      const float2 v = partials[5 * uint64_t(q) + c];
+      s[2 * c] += v.x;
+      s[2 * c + 1] += v.y;
+    }
+  }
+  float res[11];
+#pragma unroll
+  for (int c = 0; c < 11; ++c) res[c] = 0.f;
+  if (o != end) {
+    GaussParams P;
+    load_gauss(g, i, P);
+    VoxGauss V;
+    vox_gauss(P, G, V);
+    // s: S0, Sx, Sy, Sz, Sxx, Sxy, Sxz, Syy, Syz, Szz with d = voxel - centre
+    const float rho = P.rho;
+    const float Sd[3] = {s[1], s[2], s[3]};
+    for (int a = 0; a < 3; ++a) {
+      const float dpv = rho * (V.A[a][0] * Sd[0] + V.A[a][1] * Sd[1] + V.A[a][2] * Sd[2]);
+      res[a] = dpv / G.h[a];
+    }
+    // dA_vox = -rho/2 M, M the symmetric second-moment matrix
+    const float M[3][3] = {{s[4], s[5], s[6]}, {s[5], s[7], s[8]}, {s[6], s[8], s[9]}};
+    // A_vox = W W^T: dW = 2 dA W
+    float dR[9];
+    for (int j = 0; j < 3; ++j) {
+      float dls = 0.f;
+      for (int a = 0; a < 3; ++a) {
+        const float dW = -rho * (M[a][0] * V.W[0][j] + M[a][1] * V.W[1][j] + M[a][2] * V.W[2][j]);
+        // W[a][j] = h_a R[a][j] / s_j
+        dR[3 * a + j] = dW * G.h[a] / P.s[j];
+        dls -= dW * V.W[a][j];
+      }
+      res[3 + j] = dls;
+    }
+    float dq[4];
+    rot_grad_to_quat(P.qh, P.qnorm, dR, dq);
+    res[6] = dq[0]; res[7] = dq[1]; res[8] = dq[2]; res[9] = dq[3];
+    res[10] = s[0];
+  }
+  out.mean[i] = res[0]; out.mean[n + i] = res[1]; out.mean[2 * n + i] = res[2];
+  out.log_scale[i] = res[3]; out.log_scale[n + i] = res[4]; out.log_scale[2 * n + i] = res[5];
+  out.quat[i] = res[6]; out.quat[n + i] = res[7]; out.quat[2 * n + i] = res[8]; out.quat[3 * n + i] = res[9];
+  out.density[i] = res[10];
+}
+
+// ------------------------------------------------------------------ host
+
+struct VoxLayout {
+  uint64_t N, T, K;
+  uint64_t total64, prho, radii, rect, offset, a0, a1, scan_scratch, start;
+  uint64_t fixed_end;
+  uint64_t keys, vals, keys_alt, vals_alt, sort_scratch, partials;
+  uint64_t total;
+  bool sorted_in_alt;
+};
+
+VoxLayout vox_layout(uint64_t N, uint64_t T, uint64_t K) {
+  VoxLayout L{};
+  L.N = N;
+  L.T = T;
+  L.K = K;
+  Carver c(nullptr);
+  c.take<unsigned long long>(1, &L.total64);
+  c.take<float4>(N, &L.prho);
+  c.take<float4>(N, &L.radii);
+  c.take<Rect3>(N, &L.rect);
+  c.take<uint32_t>(N + 1, &L.offset);
+  c.take<float4>(N, &L.a0);
+  c.take<float4>(N, &L.a1);
+  c.take<uint32_t>(scan_scratch_words(N), &L.scan_scratch);
+  c.take<uint32_t>(T + 1, &L.start);
+  L.fixed_end = c.used;
+  c.take<uint32_t>(K, &L.keys);
+  c.take<uint32_t>(K, &L.vals);
+  c.take<uint32_t>(K, &L.keys_alt);
+  c.take<uint32_t>(K, &L.vals_alt);
+  c.take<uint32_t>(sort_scratch_words(K), &L.sort_scratch);
+  c.take<float>(10 * K, &L.partials);
+  L.total = c.used;
+  const int bits = bits_for(T);
+  const int passes = (K > 1 && bits > 0) ? (bits + 8) / 9 : 0;
+  L.sorted_in_alt = (passes & 1) != 0;
+  return L;
+}
+
+template <typename T>
+T *at(void *base, uint64_t off) {
+  return reinterpret_cast<T *>(static_cast<char *>(base) + off);
+}
+
+int validate(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *o, fgs_workspace *ws) {
+  if (!g || !grid || !o || !ws) return fail(FGS_E_INVALID, "null argument");
+  if (g->n <= 0 || !g->mean || !g->log_scale || !g->quat || !g->density)
+    return fail(FGS_E_INVALID, "invalid Gaussians");
+  if (g->n > 0x7fffffff) return fail(FGS_E_UNSUPPORTED, "more than 2^31 Gaussians");
+  for (int a = 0; a < 3; ++a) {
+    if (grid->dims[a] <= 0 || grid->dims[a] > 65535 * kVT) return fail(FGS_E_INVALID, "grid dims");
+    if (!(grid->spacing[a] > 0.f)) return fail(FGS_E_INVALID, "grid spacing");
+  }
+  if (!(o->kappa > 0.f)) return fail(FGS_E_INVALID, "kappa must be > 0");
+  return FGS_OK;
+}
+
+GridDev make_grid_dev(const fgs_grid *grid, const fgs_opts *o) {
+  GridDev G{};
+  for (int a = 0; a < 3; ++a) {
+    G.origin[a] = grid->origin[a];
+    G.h[a] = grid->spacing[a];
+    G.dims[a] = grid->dims[a];
+    G.nt[a] = (grid->dims[a] + kVT - 1) / kVT;
+  }
+  G.kappa = o->kappa;
+  return G;
+}
+
+int vox_build(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *o, fgs_workspace *ws,
+              hipStream_t s, VoxLayout *Lout, GridDev *Gout) {
+  const GridDev G = make_grid_dev(grid, o);
+  const uint64_t T = uint64_t(G.nt[0]) * G.nt[1] * G.nt[2];
+  if (T >= 0xffffffffull) return fail(FGS_E_UNSUPPORTED, "too many voxel tiles");
+  const uint64_t N = uint64_t(g->n);
+  VoxLayout L = vox_layout(N, T, 0);
+  ws->kind = 0;
+  if (!ws->ptr || ws->bytes < L.fixed_end + (uint64_t(1) << 20)) {
+    ws->needed = L.fixed_end + (uint64_t(64) << 20);
+    return fail(FGS_E_CAPACITY, "workspace too small for the per-Gaussian arrays");
+  }
+  void *b = ws->ptr;
+  unsigned long long *total64 = at<unsigned long long>(b, L.total64);
+  zero_u64_kernel<<<1, 1, 0, s>>>(total64);
+  FGS_LAUNCH_CHECK("zero_u64_kernel");
+  vox_record_kernel<<<grid_for(N, 256), 256, 0, s>>>(*g, G, at<float4>(b, L.prho), at<float4>(b, L.a0),
+                                                      at<float4>(b, L.a1), at<float4>(b, L.radii),
+                                                      at<Rect3>(b, L.rect), at<uint32_t>(b, L.offset),
+                                                      total64);
+  FGS_LAUNCH_CHECK("vox_record_kernel");
+  int st = exclusive_scan_u32(at<uint32_t>(b, L.offset), N, at<uint32_t>(b, L.scan_scratch), s);
+  if (st != FGS_OK) return st;
+  unsigned long long K64 = 0;
+  FGS_HIP(hipMemcpyAsync(&K64, total64, sizeof(K64), hipMemcpyDeviceToHost, s));
+  FGS_HIP(hipStreamSynchronize(s));
+  if (K64 >= 0xffffffffull)
+    return fail(FGS_E_UNSUPPORTED, "more than 2^32 (tile, Gaussian) pairs; split the grid into slabs");
+  const uint64_t K = K64;
+  L = vox_layout(N, T, K);
+  ws->needed = L.total;
+  ws->n_pairs = K;
+  ws->n_records = N;
+  ws->n_tiles = T;
+  if (ws->bytes < L.total) return fail(FGS_E_CAPACITY, "workspace too small for the tile lists");
+  if (K > 0) {
+    vox_emit_kernel<<<grid_for(N, 256), 256, 0, s>>>(g->n, G.nt[0], G.nt[1], at<Rect3>(b, L.rect),
+                                                      at<uint32_t>(b, L.offset), at<uint32_t>(b, L.keys),
+                                                      at<uint32_t>(b, L.vals));
+    FGS_LAUNCH_CHECK("vox_emit_kernel");
+  }
+  uint32_t *sk, *sv;
+  st = radix_sort_pairs(at<uint32_t>(b, L.keys), at<uint32_t>(b, L.vals), at<uint32_t>(b, L.keys_alt),
+                        at<uint32_t>(b, L.vals_alt), K, bits_for(T), at<uint32_t>(b, L.sort_scratch),
+                        &sk, &sv, s);
+  if (st != FGS_OK) return st;
+  vox_ranges_kernel<<<grid_for(K + 1, 256), 256, 0, s>>>(sk, K, uint32_t(T), at<uint32_t>(b, L.start));
+  FGS_LAUNCH_CHECK("vox_ranges_kernel");
+  ws->kind = 2;
+  *Lout = L;
+  *Gout = G;
+  return FGS_OK;
+}
+
+}  // namespace
+
+int vox_binning_layout(const fgs_workspace *ws, uint64_t off[9], uint64_t counts[3]) {
+  VoxLayout L = vox_layout(ws->n_records, ws->n_tiles, ws->n_pairs);
+  off[0] = L.prho;
+  off[1] = L.radii;
+  off[2] = L.rect;
+  off[3] = L.offset;
+  off[4] = L.sorted_in_alt ? L.keys : L.keys_alt;
+  off[5] = L.sorted_in_alt ? L.vals : L.vals_alt;
+  off[6] = L.sorted_in_alt ? L.keys_alt : L.keys;
+  off[7] = L.sorted_in_alt ? L.vals_alt : L.vals;
+  off[8] = L.start;
+  counts[0] = L.N;
+  counts[1] = L.K;
+  counts[2] = L.T;
+  return FGS_OK;
+}
+
+}  // namespace fgs
+
+using namespace fgs;
+
+extern "C" int fgs_voxelize_fwd(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *opts,
+                                float *vol, fgs_workspace *ws, void *stream) {
+  int st = validate(g, grid, opts, ws);
+  if (st != FGS_OK) return st;
+  if (!vol) return fail(FGS_E_INVALID, "null volume");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  VoxLayout L;
+  GridDev G;
+  st = vox_build(g, grid, opts, ws, s, &L, &G);
+  if (st != FGS_OK) return st;
+  void *b = ws->ptr;
+  const uint32_t *sv = at<uint32_t>(b, L.sorted_in_alt ? L.vals_alt : L.vals);
+  const float thr = -0.5f * kLog2e * opts->kappa * opts->kappa;
+  hipEvent_t *ev = static_cast<hipEvent_t *>(opts->events);
+  if (ev) FGS_HIP(hipEventRecord(ev[0], s));
+  vox_fwd_kernel<false><<<unsigned(L.T), kWave, 0, s>>>(at<uint32_t>(b, L.start), sv, at<float4>(b, L.prho),
+                                                        at<float4>(b, L.a0), at<float4>(b, L.a1), G, thr, vol,
+                                                        nullptr);
+  FGS_LAUNCH_CHECK("vox_fwd_kernel");
+  if (ev) FGS_HIP(hipEventRecord(ev[1], s));
+  return FGS_OK;
+}
+
+extern "C" int fgs_voxelize_support(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *opts,
+                                    uint64_t *out, fgs_workspace *ws, void *stream) {
+  int st = validate(g, grid, opts, ws);
+  if (st != FGS_OK) return st;
+  if (!out) return fail(FGS_E_INVALID, "null output");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  VoxLayout L;
+  GridDev G;
+  st = vox_build(g, grid, opts, ws, s, &L, &G);
+  if (st != FGS_OK) return st;
+  void *b = ws->ptr;
+  unsigned long long *cnt = reinterpret_cast<unsigned long long *>(out);
+  zero_u64_kernel<<<1, 1, 0, s>>>(cnt);
+  FGS_LAUNCH_CHECK("zero_u64_kernel");
+  const uint32_t *sv = at<uint32_t>(b, L.sorted_in_alt ? L.vals_alt : L.vals);
+  const float thr = -0.5f * kLog2e * opts->kappa * opts->kappa;
+  vox_fwd_kernel<true><<<unsigned(L.T), kWave, 0, s>>>(at<uint32_t>(b, L.start), sv, at<float4>(b, L.prho),
+                                                       at<float4>(b, L.a0), at<float4>(b, L.a1), G, thr,
+                                                       nullptr, cnt);
+  FGS_LAUNCH_CHECK("vox_fwd_kernel<count>");
+  return FGS_OK;
+}
+
+extern "C" int fgs_voxelize_bwd(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *opts,
+                                const float *grad_vol, fgs_gaussian_grads *out, fgs_workspace *ws,
+                                void *stream) {
+  int st = validate(g, grid, opts, ws);
+  if (st != FGS_OK) return st;
+  if (!grad_vol || !out || !out->mean || !out->log_scale || !out->quat || !out->density)
+    return fail(FGS_E_INVALID, "null gradient buffer");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  VoxLayout L;
+  GridDev G;
+  if (opts->recompute) {
+    st = vox_build(g, grid, opts, ws, s, &L, &G);
+    if (st != FGS_OK) return st;
+  } else {
+    G = make_grid_dev(grid, opts);
+    const uint64_t T = uint64_t(G.nt[0]) * G.nt[1] * G.nt[2];
+    if (ws->kind != 2 || ws->n_records != uint64_t(g->n) || ws->n_tiles != T || !ws->ptr)
+      return fail(FGS_E_INVALID, "workspace does not hold this call's voxelizer lists");
+    L = vox_layout(uint64_t(g->n), T, ws->n_pairs);
+    if (ws->bytes < L.total) return fail(FGS_E_INVALID, "workspace lists do not match this call");
+  }
+  void *b = ws->ptr;
+  const uint32_t *sv = at<uint32_t>(b, L.sorted_in_alt ? L.vals_alt : L.vals);
+  const float thr = -0.5f * kLog2e * opts->kappa * opts->kappa;
+  hipEvent_t *ev = static_cast<hipEvent_t *>(opts->events);
+  if (ev) FGS_HIP(hipEventRecord(ev[0], s));
+  if (L.K > 0) {
+    vox_bwd_kernel<<<unsigned(L.T), kWave, 0, s>>>(at<uint32_t>(b, L.start), sv, at<float4>(b, L.prho),
+                                                   at<float4>(b, L.a0), at<float4>(b, L.a1),
+                                                   at<Rect3>(b, L.rect), at<uint32_t>(b, L.offset), G, thr,
+                                                   grad_vol, at<float2>(b, L.partials));
+    FGS_LAUNCH_CHECK("vox_bwd_kernel");
+  }
+  if (ev) FGS_HIP(hipEventRecord(ev[1], s));
+  vox_grad_kernel<<<grid_for(uint64_t(g->n), 256), 256, 0, s>>>(*g, G, at<uint32_t>(b, L.offset),
+                                                                at<float2>(b, L.partials), *out);
+  FGS_LAUNCH_CHECK("vox_grad_kernel");
+  return FGS_OK;
+}

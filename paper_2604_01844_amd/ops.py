@@ -1,0 +1,374 @@
+"""Python entry points over libfactgs: the rasterizer (``project_views``), the
+voxelizer (``voxelize``), their backward calls, losses, Adam, PSNR and the
+phantom generator, plus ``torch.autograd.Function`` wrappers whose backward
+is the library's hand-written backward.
+
+Argument marshalling only: tensors must already be contiguous float32 on the
+GPU; every step runs in the HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+
+import torch
+
+from . import _abi as A
+
+KAPPA = 3.0
+NEAR = 1e-2
+
+
+# ------------------------------------------------------------------ descriptors
+
+@dataclass
+class Geometry:
+    """Circular-orbit flat-detector geometry (cone or parallel beam).
+    ``angles`` is a float32 GPU tensor of view angles in radians."""
+    angles: torch.Tensor
+    det_w: int
+    det_h: int
+    pitch_u: float
+    pitch_v: float
+    sod: float = 1.5
+    sdd: float = 2.0
+    mode: str = "cone"
+    off_u: float = 0.0
+    off_v: float = 0.0
+
+    @classmethod
+    def from_dict(cls, d: dict, angles, device="cuda") -> "Geometry":
+        ang = torch.as_tensor(angles, dtype=torch.float32).to(device).contiguous()
+        return cls(angles=ang, det_w=d["det_w"], det_h=d["det_h"], pitch_u=d["pitch_u"],
+                   pitch_v=d["pitch_v"], sod=d["sod"], sdd=d["sdd"], mode=d["mode"],
+                   off_u=d.get("off_u", 0.0), off_v=d.get("off_v", 0.0))
+
+    @property
+    def n_views(self) -> int:
+        return int(self.angles.numel())
+
+    def struct(self) -> A.fgs_geom:
+        return A.fgs_geom(A.FGS_PARALLEL if self.mode == "parallel" else A.FGS_CONE, self.n_views,
+                          A.ptr(self.angles), self.sod, self.sdd, self.det_w, self.det_h,
+                          self.pitch_u, self.pitch_v, self.off_u, self.off_v)
+
+
+@dataclass
+class Grid:
+    """Voxel grid: voxel (ix, iy, iz) centre = origin + (index + 1/2) * spacing;
+    volumes are [nz][ny][nx]."""
+    origin: tuple
+    spacing: tuple
+    dims: tuple
+
+    @classmethod
+    def from_dict(cls, d: dict) -> "Grid":
+        return cls(tuple(d["origin"]), tuple(d["spacing"]), tuple(int(x) for x in d["dims"]))
+
+    @property
+    def shape(self):
+        nx, ny, nz = self.dims
+        return (nz, ny, nx)
+
+    def struct(self) -> A.fgs_grid:
+        return A.fgs_grid((ctypes.c_float * 3)(*self.origin), (ctypes.c_float * 3)(*self.spacing),
+                          (ctypes.c_int32 * 3)(*self.dims))
+
+
+class Workspace:
+    """Caller-owned device workspace that grows on FGS_E_CAPACITY."""
+
+    def __init__(self, device="cuda", nbytes: int = 0):
+        self.device = torch.device(device)
+        self.buf = None
+        self.s = A.fgs_workspace()
+        if nbytes:
+            self.ensure(nbytes)
+
+    def ensure(self, nbytes: int):
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = None
+            self.buf = torch.empty(int(nbytes * 1.25) + (1 << 20), dtype=torch.uint8, device=self.device)
+            self.s.kind = 0
+        self.s.ptr = self.buf.data_ptr()
+        self.s.bytes = self.buf.numel()
+
+    def call(self, fn, *args):
+        """Call fn(*args, &ws, stream), growing the workspace on FGS_E_CAPACITY."""
+        for _ in range(6):
+            if self.buf is None:
+                self.ensure(64 << 20)
+            code = fn(*args, ctypes.byref(self.s), A.stream_ptr(self.device))
+            if code != A.FGS_E_CAPACITY:
+                A.check(code)
+                return
+            self.ensure(int(self.s.needed))
+        raise A.FgsError(A.FGS_E_CAPACITY, "workspace did not converge")
+
+    @property
+    def n_pairs(self) -> int:
+        return int(self.s.n_pairs)
+
+
+def _gauss(mean, log_scale, quat, density) -> A.fgs_gaussians:
+    n = density.numel()
+    for t, rows in ((mean, 3), (log_scale, 3), (quat, 4)):
+        if t.dtype != torch.float32 or t.shape != (rows, n):
+            raise ValueError(f"expected float32 [{rows}][{n}], got {t.dtype} {tuple(t.shape)}")
+    if density.dtype != torch.float32:
+        raise ValueError("density must be float32")
+    return A.fgs_gaussians(n, A.ptr(mean), A.ptr(log_scale), A.ptr(quat), A.ptr(density))
+
+
+def _grads_like(mean, log_scale, quat, density):
+    return (torch.empty_like(mean), torch.empty_like(log_scale), torch.empty_like(quat),
+            torch.empty_like(density))
+
+
+def _opts(kappa, near, recompute=1, events=None) -> A.fgs_opts:
+    """events: optional pair of started torch.cuda.Event objects to record
+    around the call's pixel/voxel kernel."""
+    o = A.fgs_opts(float(kappa), float(near), int(recompute), 0, None)
+    if events is not None:
+        arr = (ctypes.c_void_p * 2)(events[0].cuda_event, events[1].cuda_event)
+        o._events_keepalive = arr
+        o.events = ctypes.cast(arr, ctypes.c_void_p)
+    return o
+
+
+def timing_events():
+    """A (start, stop) pair of timing events, created on the current stream so
+    the library can record them."""
+    ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    for e in ev:
+        e.record()
+    return ev
+
+
+# ------------------------------------------------------------------ rasterizer
+
+def project_views(mean, log_scale, quat, density, geom: Geometry, view_begin: int = 0,
+                  view_count: int | None = None, *, kappa: float = KAPPA, near: float = NEAR,
+                  ws: Workspace | None = None, out: torch.Tensor | None = None, events=None) -> torch.Tensor:
+    """Rasterize views [view_begin, view_begin + view_count): [V][H][W] float32."""
+    L = A.lib()
+    vc = geom.n_views - view_begin if view_count is None else view_count
+    ws = ws or Workspace(mean.device)
+    if out is None:
+        out = torch.empty((vc, geom.det_h, geom.det_w), dtype=torch.float32, device=mean.device)
+    g = _gauss(mean, log_scale, quat, density)
+    gm = geom.struct()
+    o = _opts(kappa, near, events=events)
+    ws.call(L.fgs_project_views_fwd, ctypes.byref(g), ctypes.byref(gm), view_begin, vc, ctypes.byref(o),
+            A.ptr(out))
+    return out
+
+
+def project_views_backward(mean, log_scale, quat, density, geom: Geometry, grad_img, view_begin: int = 0,
+                           view_count: int | None = None, *, kappa: float = KAPPA, near: float = NEAR,
+                           recompute: bool = True, ws: Workspace | None = None, out=None, events=None):
+    """dL/d(mean, log_scale, quat, density) given dL/dimg."""
+    L = A.lib()
+    vc = geom.n_views - view_begin if view_count is None else view_count
+    ws = ws or Workspace(mean.device)
+    grads = out if out is not None else _grads_like(mean, log_scale, quat, density)
+    g = _gauss(mean, log_scale, quat, density)
+    gr = A.fgs_gaussian_grads(*(A.ptr(t) for t in grads))
+    gm = geom.struct()
+    o = _opts(kappa, near, 1 if recompute else 0, events)
+    ws.call(L.fgs_project_views_bwd, ctypes.byref(g), ctypes.byref(gm), view_begin, vc, ctypes.byref(o),
+            A.ptr(grad_img.contiguous()), ctypes.byref(gr))
+    return grads
+
+
+# ------------------------------------------------------------------ voxelizer
+
+def voxelize(mean, log_scale, quat, density, grid: Grid, *, kappa: float = KAPPA,
+             ws: Workspace | None = None, out: torch.Tensor | None = None, events=None) -> torch.Tensor:
+    L = A.lib()
+    ws = ws or Workspace(mean.device)
+    if out is None:
+        out = torch.empty(grid.shape, dtype=torch.float32, device=mean.device)
+    g = _gauss(mean, log_scale, quat, density)
+    gd = grid.struct()
+    o = _opts(kappa, NEAR, events=events)
+    ws.call(L.fgs_voxelize_fwd, ctypes.byref(g), ctypes.byref(gd), ctypes.byref(o), A.ptr(out))
+    return out
+
+
+def voxelize_backward(mean, log_scale, quat, density, grid: Grid, grad_vol, *, kappa: float = KAPPA,
+                      recompute: bool = True, ws: Workspace | None = None, out=None, events=None):
+    L = A.lib()
+    ws = ws or Workspace(mean.device)
+    grads = out if out is not None else _grads_like(mean, log_scale, quat, density)
+    g = _gauss(mean, log_scale, quat, density)
+    gr = A.fgs_gaussian_grads(*(A.ptr(t) for t in grads))
+    gd = grid.struct()
+    o = _opts(kappa, NEAR, 1 if recompute else 0, events)
+    ws.call(L.fgs_voxelize_bwd, ctypes.byref(g), ctypes.byref(gd), ctypes.byref(o),
+            A.ptr(grad_vol.contiguous()), ctypes.byref(gr))
+    return grads
+
+
+def project_views_support(mean, log_scale, quat, density, geom: Geometry, view_begin: int = 0,
+                          view_count: int | None = None, *, kappa: float = KAPPA, near: float = NEAR,
+                          ws: Workspace | None = None) -> int:
+    """Number of (pixel, Gaussian) pairs in the support (the rasterizer's work)."""
+    L = A.lib()
+    vc = geom.n_views - view_begin if view_count is None else view_count
+    ws = ws or Workspace(mean.device)
+    out = torch.zeros(1, dtype=torch.int64, device=mean.device)
+    g = _gauss(mean, log_scale, quat, density)
+    gm = geom.struct()
+    o = _opts(kappa, near)
+    ws.call(L.fgs_project_views_support, ctypes.byref(g), ctypes.byref(gm), view_begin, vc, ctypes.byref(o),
+            A.ptr(out))
+    return int(out.item())
+
+
+def voxelize_support(mean, log_scale, quat, density, grid: Grid, *, kappa: float = KAPPA,
+                     ws: Workspace | None = None) -> int:
+    """Number of (voxel, Gaussian) pairs in the support (the voxelizer's work)."""
+    L = A.lib()
+    ws = ws or Workspace(mean.device)
+    out = torch.zeros(1, dtype=torch.int64, device=mean.device)
+    g = _gauss(mean, log_scale, quat, density)
+    gd = grid.struct()
+    o = _opts(kappa, NEAR)
+    ws.call(L.fgs_voxelize_support, ctypes.byref(g), ctypes.byref(gd), ctypes.byref(o), A.ptr(out))
+    return int(out.item())
+
+
+# ------------------------------------------------------------------ loss / optimiser
+
+def l1_loss_grad(img, gt, *, n_views: int | None = None, ws: Workspace | None = None, want_grad=True):
+    """Eq. 5 L1 term: (sum over views of mean |img - gt|, sign(img - gt)/P)."""
+    L = A.lib()
+    ws = ws or Workspace(img.device, 1 << 16)
+    nv = img.shape[0] if n_views is None else n_views
+    per = img.numel() // nv
+    loss = torch.empty(1, dtype=torch.float32, device=img.device)
+    grad = torch.empty_like(img) if want_grad else None
+    ws.call(L.fgs_l1_loss_grad, A.ptr(img), A.ptr(gt), per, nv, A.ptr(loss), A.ptr(grad))
+    return loss, grad
+
+
+def psnr(vol, ref, peak: float, ws: Workspace | None = None):
+    L = A.lib()
+    ws = ws or Workspace(vol.device, 1 << 16)
+    out = torch.empty(1, dtype=torch.float32, device=vol.device)
+    ws.call(L.fgs_psnr, A.ptr(vol), A.ptr(ref), vol.numel(), float(peak), A.ptr(out))
+    return out
+
+
+def adam_step(param, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-15,
+              clamp_min_zero=False, grad2=None):
+    """Adam on param with gradient grad (+ grad2 when given), in place."""
+    L = A.lib()
+    A.check(L.fgs_adam_step(A.ptr(param), A.ptr(grad), A.ptr(grad2), A.ptr(m), A.ptr(v), param.numel(), int(step),
+                            float(lr), float(beta1), float(beta2), float(eps), int(clamp_min_zero),
+                            A.stream_ptr(param.device)))
+
+
+# ------------------------------------------------------------------ phantom
+
+def _phantom(ph: dict) -> tuple:
+    keep = [ph[k].contiguous() for k in ("centre", "semi", "quat", "amp")]
+    for t in keep:
+        if t.dtype != torch.float64:
+            raise ValueError("phantom parameters are float64")
+    return keep, A.fgs_phantom(keep[3].numel(), *(A.ptr(t) for t in keep))
+
+
+def phantom_project(ph: dict, geom: Geometry, view_begin=0, view_count=None, out=None):
+    L = A.lib()
+    vc = geom.n_views - view_begin if view_count is None else view_count
+    keep, s = _phantom(ph)
+    dev = keep[0].device
+    if out is None:
+        out = torch.empty((vc, geom.det_h, geom.det_w), dtype=torch.float32, device=dev)
+    gm = geom.struct()
+    A.check(L.fgs_phantom_project(ctypes.byref(s), ctypes.byref(gm), view_begin, vc, A.ptr(out),
+                                  A.stream_ptr(dev)))
+    return out
+
+
+def phantom_voxelize(ph: dict, grid: Grid, out=None):
+    L = A.lib()
+    keep, s = _phantom(ph)
+    dev = keep[0].device
+    if out is None:
+        out = torch.empty(grid.shape, dtype=torch.float32, device=dev)
+    gd = grid.struct()
+    A.check(L.fgs_phantom_voxelize(ctypes.byref(s), ctypes.byref(gd), A.ptr(out), A.stream_ptr(dev)))
+    return out
+
+
+# ------------------------------------------------------------------ introspection
+
+def binning_dump(ws: Workspace) -> dict:
+    """Views of the binning arrays the last forward call left in ``ws``."""
+    L = A.lib()
+    off = (ctypes.c_uint64 * 9)()
+    cnt = (ctypes.c_uint64 * 3)()
+    A.check(L.fgs_binning_layout(ctypes.byref(ws.s), off, cnt))
+    R, K, T = (int(c) for c in cnt)
+    buf = ws.buf
+    vox = ws.s.kind == 2
+
+    def view(i, dtype, count, width=1):
+        nbytes = torch.tensor([], dtype=dtype).element_size() * count * width
+        t = buf[int(off[i]):int(off[i]) + nbytes].view(dtype)
+        return t.view(count, width) if width > 1 else t
+
+    return dict(
+        centre=view(0, torch.float32, R, 4 if vox else 2),
+        radii=view(1, torch.float32, R, 4 if vox else 2),
+        rect=view(2, torch.int16, R, 8 if vox else 4),
+        offset=view(3, torch.int32, R + 1),
+        sorted_keys=view(6, torch.int32, K),
+        sorted_vals=view(7, torch.int32, K),
+        tile_start=view(8, torch.int32, T + 1),
+        n_records=R, n_pairs=K, n_tiles=T)
+
+
+# ------------------------------------------------------------------ autograd
+
+class ProjectViews(torch.autograd.Function):
+    """Differentiable rasterizer; the backward is libfactgs' hand-written one."""
+
+    @staticmethod
+    def forward(ctx, mean, log_scale, quat, density, geom: Geometry, view_begin: int, view_count: int,
+                kappa: float = KAPPA, ws: Workspace | None = None, recompute: bool = True):
+        ws = ws or Workspace(mean.device)
+        img = project_views(mean, log_scale, quat, density, geom, view_begin, view_count, kappa=kappa, ws=ws)
+        ctx.save_for_backward(mean, log_scale, quat, density)
+        ctx.geom, ctx.vb, ctx.vc, ctx.kappa, ctx.ws, ctx.recompute = geom, view_begin, view_count, kappa, ws, recompute
+        return img
+
+    @staticmethod
+    def backward(ctx, grad_img):
+        mean, log_scale, quat, density = ctx.saved_tensors
+        g = project_views_backward(mean, log_scale, quat, density, ctx.geom, grad_img.contiguous(), ctx.vb,
+                                   ctx.vc, kappa=ctx.kappa, recompute=ctx.recompute, ws=ctx.ws)
+        return (*g, None, None, None, None, None, None)
+
+
+class Voxelize(torch.autograd.Function):
+    """Differentiable voxelizer; the backward is libfactgs' hand-written one."""
+
+    @staticmethod
+    def forward(ctx, mean, log_scale, quat, density, grid: Grid, kappa: float = KAPPA,
+                ws: Workspace | None = None, recompute: bool = True):
+        ws = ws or Workspace(mean.device)
+        vol = voxelize(mean, log_scale, quat, density, grid, kappa=kappa, ws=ws)
+        ctx.save_for_backward(mean, log_scale, quat, density)
+        ctx.grid, ctx.kappa, ctx.ws, ctx.recompute = grid, kappa, ws, recompute
+        return vol
+
+    @staticmethod
+    def backward(ctx, grad_vol):
+        mean, log_scale, quat, density = ctx.saved_tensors
+        g = voxelize_backward(mean, log_scale, quat, density, ctx.grid, grad_vol.contiguous(), kappa=ctx.kappa,
+                              recompute=ctx.recompute, ws=ctx.ws)
+        return (*g, None, None, None, None)

@@ -1,0 +1,87 @@
+"""The C-ABI library loads and exports every symbol include/factgs.h declares;
+host-side argument validation (no GPU work) behaves as documented."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "factgs.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fgs_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    syms = declared_symbols()
+    for s in ("fgs_project_views_fwd", "fgs_project_views_bwd", "fgs_voxelize_fwd", "fgs_voxelize_bwd"):
+        assert s in syms
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2604_01844_amd import _abi
+    lib = _abi.lib()
+    for s in declared_symbols():
+        assert hasattr(lib, s), s
+        assert s in _abi.SIGNATURES, s
+    assert set(_abi.SIGNATURES) == set(declared_symbols())
+
+
+def test_version_and_error_strings():
+    from paper_2604_01844_amd import _abi
+    lib = _abi.lib()
+    assert lib.fgs_version().decode().startswith("factgs")
+    assert isinstance(lib.fgs_last_error().decode(), str)
+
+
+def test_validation_rejects_bad_arguments_without_gpu_work():
+    from paper_2604_01844_amd import _abi as A
+    lib = A.lib()
+    ws = A.fgs_workspace()
+    o = A.fgs_opts(3.0, 1e-2, 1, 0, None)
+    # null Gaussians
+    assert lib.fgs_project_views_fwd(None, None, 0, 1, ctypes.byref(o), None, ctypes.byref(ws), None) == A.FGS_E_INVALID
+    g = A.fgs_gaussians(10, 16, 16, 16, 16)  # fake non-null pointers, never dereferenced on invalid input
+    gm = A.fgs_geom(A.FGS_CONE, 4, 16, 1.5, 2.0, 64, 64, 0.04, 0.04, 0.0, 0.0)
+    # view range out of bounds
+    assert lib.fgs_project_views_fwd(ctypes.byref(g), ctypes.byref(gm), 3, 2, ctypes.byref(o), 16,
+                                     ctypes.byref(ws), None) == A.FGS_E_INVALID
+    assert "view range" in lib.fgs_last_error().decode()
+    # kappa <= 0
+    bad = A.fgs_opts(0.0, 1e-2, 1, 0, None)
+    assert lib.fgs_project_views_fwd(ctypes.byref(g), ctypes.byref(gm), 0, 1, ctypes.byref(bad), 16,
+                                     ctypes.byref(ws), None) == A.FGS_E_INVALID
+    # zero Gaussians
+    g0 = A.fgs_gaussians(0, 16, 16, 16, 16)
+    gr = A.fgs_grid((ctypes.c_float * 3)(-0.5, -0.5, -0.5), (ctypes.c_float * 3)(0.1, 0.1, 0.1),
+                    (ctypes.c_int32 * 3)(10, 10, 10))
+    assert lib.fgs_voxelize_fwd(ctypes.byref(g0), ctypes.byref(gr), ctypes.byref(o), 16, ctypes.byref(ws),
+                                None) == A.FGS_E_INVALID
+    # non-positive grid
+    gr2 = A.fgs_grid((ctypes.c_float * 3)(0, 0, 0), (ctypes.c_float * 3)(0.1, 0.0, 0.1),
+                     (ctypes.c_int32 * 3)(10, 10, 10))
+    assert lib.fgs_voxelize_fwd(ctypes.byref(g), ctypes.byref(gr2), ctypes.byref(o), 16, ctypes.byref(ws),
+                                None) == A.FGS_E_INVALID
+    # a workspace that holds no lists
+    off = (ctypes.c_uint64 * 9)()
+    cnt = (ctypes.c_uint64 * 3)()
+    assert lib.fgs_binning_layout(ctypes.byref(ws), off, cnt) == A.FGS_E_INVALID
+    # backward without recompute needs the forward's lists
+    o0 = A.fgs_opts(3.0, 1e-2, 0, 0, None)
+    gg = A.fgs_gaussian_grads(16, 16, 16, 16)
+    assert lib.fgs_project_views_bwd(ctypes.byref(g), ctypes.byref(gm), 0, 1, ctypes.byref(o0), 16,
+                                     ctypes.byref(gg), ctypes.byref(ws), None) == A.FGS_E_INVALID
+
+
+def test_product_path_does_not_import_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2604_01844_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, f
+                assert "liboracle" not in txt, f

@@ -457,3 +457,31 @@ def test_l1_psnr_adam_hand_values():
     # first step of Adam moves by lr * sign(g)
     assert p[0] == pytest.approx(0.9)
     assert m[0] == pytest.approx(0.05) and v[0] == pytest.approx(0.00025)
+
+
+def test_gradient_band_brackets_cutoff_perturbations():
+    """Moving the hard cutoff anywhere inside the boundary band changes the
+    gradient by at most the band's absolute contribution mass; with a
+    vanishing band the banded gradient is the plain one."""
+    gs = si.gaussians(300, 41)
+    gd = si.geometry(48)
+    ang = si.angles(3)
+    c = si.normals((3, 48, 48), 42).astype(np.float64)
+    core = oracle.project_bwd(gs, gd, ang, c, band=1e-3)
+    assert sum(float(np.abs(v).sum()) for v in core["band_abs"].values()) > 0
+    for kap in (3.0 * (1 - 1e-5), 3.0, 3.0 * (1 + 1e-5)):
+        plain = oracle.project_bwd(gs, gd, ang, c, kappa=kap)
+        for k, e in oracle.banded_grad_error(plain, core).items():
+            assert e < 1e-12, (kap, k, e)
+    tiny = oracle.project_bwd(gs, gd, ang, c, band=1e-300)
+    plain = oracle.project_bwd(gs, gd, ang, c)
+    for k in ("mean", "log_scale", "quat", "density"):
+        np.testing.assert_array_equal(tiny[k], plain[k])
+    # voxelizer
+    gr = si.grid(24)
+    cv = si.normals((24, 24, 24), 43).astype(np.float64)
+    vcore = oracle.voxelize_bwd(gs, gr, cv, band=1e-3)
+    for kap in (3.0 * (1 - 1e-5), 3.0 * (1 + 1e-5)):
+        plain = oracle.voxelize_bwd(gs, gr, cv, kappa=kap)
+        for k, e in oracle.banded_grad_error(plain, vcore).items():
+            assert e < 1e-12, (kap, k, e)
