@@ -88,6 +88,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="after timing, copy a MIB-MiB float32 buffer device-to-device 3 times "
+                         "(a plain copy kernel of known size, to scale HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -183,6 +186,13 @@ def main():
                voxels_per_s=NV ** 3 / (ms_step * 1e-3),
                s_per_step=ms_step * 1e-3,
                kernels=kernels, roofline=roof)
+    if args.calibrate_copy:
+        src = torch.ones(args.calibrate_copy << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = src.numel() * 4
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a bounded sample (cpu_baseline)")
         out["cpu_baseline"] = cpu_baseline(gs, gd, ang, grid_d)

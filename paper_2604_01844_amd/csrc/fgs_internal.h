@@ -79,6 +79,16 @@ inline unsigned grid_for(uint64_t n, unsigned block) {
 
 // ------------------------------------------------------------ device math
 
+// Orders one wavefront's LDS accesses: writes issued before are visible to
+// reads issued after, by any lane of the same wave (LDS operations of a wave
+// complete in order). Used where each wave of a workgroup owns its own tile
+// and its own LDS slice, so no workgroup barrier is needed.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // log2(e): exp(x) = exp2(x * log2(e)). Kernels pre-scale quadratic forms by
 // -log2(e)/2 so that the Gaussian factor is a single v_exp_f32.
 constexpr float kLog2e = 1.4426950408889634f;

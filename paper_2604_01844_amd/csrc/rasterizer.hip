@@ -31,7 +31,12 @@ namespace {
 
 constexpr int kTS = 16;          // tile side in pixels
 constexpr int kWave = 64;        // lanes per wave (gfx9 wave64)
+constexpr int kTilesPerBlock = 16;  // independent tiles per workgroup, one per wave
+constexpr int kBlock = kWave * kTilesPerBlock;
 constexpr int kRows = 4;         // pixels per lane in the forward (a column of 4)
+// The quadrant culling test keeps pairs whose exponent reaches thr * kCullSlack
+// (a Mahalanobis radius 0.05% beyond the support), a superset of the per-pixel test.
+constexpr float kCullSlack = 1.001f;
 
 // Tile span of [c - r, c + r] for pixel centres at j + 1/2. Plain float32
 // subtractions and floor: the same decision the integer reference takes.
@@ -48,7 +53,11 @@ __device__ __forceinline__ void tile_span(float c, float r, int n_tiles, int &t0
   t1 = min(jhi >> 4, n_tiles - 1);
 }
 
-__global__ void zero_u64_kernel(unsigned long long *p) { *p = 0ull; }
+constexpr int kTotalSlots = 64;
+
+__global__ void zero_u64_kernel(unsigned long long *p, int n) {
+  if (int(threadIdx.x) < n) p[threadIdx.x] = 0ull;
+}
 
 // Record r = v_local * n + i of one (view, Gaussian) pair. Returns its tile count.
 __device__ __forceinline__ uint32_t record_one(const fgs_gaussians &g, const GeomDev &G, int64_t i,
@@ -100,10 +109,12 @@ __global__ __launch_bounds__(256) void record_kernel(fgs_gaussians g, GeomDev G,
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   uint32_t cnt = 0;
   if (i < g.n) cnt = record_one(g, G, i, int(blockIdx.y), xy, conic_w, radii, rect, count);
-  // 64-bit pair total (detects a 32-bit scan overflow): one atomic per wave
+  // 64-bit pair total (detects a 32-bit scan overflow): one atomic per wave,
+  // spread over kTotalSlots addresses to keep contention low
   unsigned long long w = cnt;
   for (int d = 32; d > 0; d >>= 1) w += __shfl_xor(w, d, 64);
-  if ((threadIdx.x & 63) == 0 && w) atomicAdd(total64, w);
+  if ((threadIdx.x & 63) == 0 && w)
+    atomicAdd(total64 + ((blockIdx.x * 4 + (threadIdx.x >> 6) + blockIdx.y * 7) & (kTotalSlots - 1)), w);
 }
 
 __global__ __launch_bounds__(256) void emit_kernel(uint64_t R, int64_t n, int tiles_x, int tpv,
@@ -136,60 +147,151 @@ __global__ __launch_bounds__(256) void ranges_kernel(const uint32_t *__restrict_
   for (int64_t t = prev + 1; t <= cur; ++t) start[t] = uint32_t(k);
 }
 
+// ---------------------------------------------------------------- quadrants
+//
+// Both pixel kernels split a 16x16 tile into four 8x8 quadrants. For every
+// (tile, Gaussian) pair of a batch the lane that loads the record tests the
+// Gaussian's support ellipse against each quadrant exactly (the smallest
+// Mahalanobis distance over the quadrant's pixel centres, below), and the
+// wave builds one list of batch slots per quadrant. 16-lane group g then
+// works only on quadrant g's list, so pixels outside a Gaussian's support
+// ellipse are skipped at 8x8 granularity instead of 16x16.
+
+// Largest value of the pre-scaled form q = c.x dx^2 + c.y dx dy + c.z dy^2
+// (q = -log2(e)/2 d^2) over the rectangle [x0, x1] x [y0, y1], relative to
+// the centre (u, v): the convex form's minimum of d^2 over a rectangle lies
+// on the edge nearest the centre in x or in y, each a clamped 1D minimum.
+__device__ __forceinline__ float rect_qmax(const float4 &c, float rx, float ry, float u, float v, float x0,
+                                           float x1, float y0, float y1) {
+  const float X = fminf(fmaxf(u, x0), x1);
+  const float dxa = X - u;
+  const float dya = fminf(fmaxf(fmaf(-rx, dxa, v), y0), y1) - v;
+  const float qa = fmaf(dxa, fmaf(c.x, dxa, c.y * dya), c.z * dya * dya);
+  const float Y = fminf(fmaxf(v, y0), y1);
+  const float dyb = Y - v;
+  const float dxb = fminf(fmaxf(fmaf(-ry, dyb, u), x0), x1) - u;
+  const float qb = fmaf(dxb, fmaf(c.x, dxb, c.y * dyb), c.z * dyb * dyb);
+  return fmaxf(qa, qb);
+}
+
+// Bit Q set if the support ellipse reaches a pixel centre of quadrant Q of
+// the tile whose first pixel centre is (tx0, ty0). thr_cull is a hair below
+// the support threshold so the test is a superset of the per-pixel test.
+__device__ __forceinline__ uint32_t quad_mask(const float4 &c, float u, float v, float tx0, float ty0,
+                                              float thr_cull) {
+  const float rx = 0.5f * c.y / c.z;
+  const float ry = 0.5f * c.y / c.x;
+  uint32_t m = 0;
+#pragma unroll
+  for (int Q = 0; Q < 4; ++Q) {
+    const float x0 = tx0 + float((Q & 1) * 8), y0 = ty0 + float((Q >> 1) * 8);
+    if (rect_qmax(c, rx, ry, u, v, x0, x0 + 7.f, y0, y0 + 7.f) >= thr_cull) m |= 1u << Q;
+  }
+  return m;
+}
+
+// Per-quadrant lists of batch slots (slot = lane that loaded the record),
+// in slot order. Returns the four list lengths; lane's own positions in the
+// lists it belongs to go to pos[Q].
+__device__ __forceinline__ void build_quad_lists(uint32_t mask, int lane, uint8_t (*s_list)[kWave],
+                                                 int nq[4], int pos[4]) {
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+  for (int Q = 0; Q < 4; ++Q) {
+    const bool bit = (mask >> Q) & 1u;
+    const uint64_t bal = __ballot(bit);
+    pos[Q] = __popcll(bal & lt);
+    if (bit) s_list[Q][pos[Q]] = uint8_t(lane);
+    nq[Q] = __popcll(bal);
+  }
+}
+
+// Slot kWave of the LDS record arrays holds a record that contributes nothing
+// anywhere (zero weight, support far outside every tile).
+__device__ __forceinline__ void set_null_record(float4 *s_cw, float2 *s_xy) {
+  s_cw[kWave] = make_float4(-1.f, 0.f, -1.f, 0.f);
+  s_xy[kWave] = make_float2(-1.0e4f, -1.0e4f);
+}
+
 // kCount = true: instead of the image, count the (pixel, Gaussian) pairs in
 // the support whose pixel lies on the detector (the algorithmic work).
 template <bool kCount>
-__global__ __launch_bounds__(kWave) void splat_fwd_kernel(const uint32_t *__restrict__ start,
-                                                          const uint32_t *__restrict__ svals,
-                                                          const float2 *__restrict__ xy,
-                                                          const float4 *__restrict__ conic_w,
-                                                          int tiles_x, int tpv, int W, int H,
-                                                          float thr, float *__restrict__ img,
-                                                          unsigned long long *__restrict__ counter) {
-  __shared__ float4 s_cw[kWave];
-  __shared__ float2 s_xy[kWave];
-  const uint32_t tile = blockIdx.x;
+__global__ __launch_bounds__(kBlock) void splat_fwd_kernel(const uint32_t *__restrict__ start,
+                                                           const uint32_t *__restrict__ svals,
+                                                           const float2 *__restrict__ xy,
+                                                           const float4 *__restrict__ conic_w,
+                                                           int tiles_x, int tpv, int W, int H,
+                                                           uint32_t n_tiles, float thr, float thr_cull,
+                                                           float *__restrict__ img,
+                                                           unsigned long long *__restrict__ counter) {
+  __shared__ float4 s_cw_all[kTilesPerBlock][kWave + 1];
+  __shared__ float2 s_xy_all[kTilesPerBlock][kWave + 1];
+  __shared__ uint8_t s_list_all[kTilesPerBlock][4][kWave];
+  const int wid = threadIdx.x / kWave;
+  float4 *s_cw = s_cw_all[wid];
+  float2 *s_xy = s_xy_all[wid];
+  uint8_t(*s_list)[kWave] = s_list_all[wid];
+  const uint32_t tile = blockIdx.x * kTilesPerBlock + wid;
+  if (tile >= n_tiles) return;
   const uint32_t v_local = tile / uint32_t(tpv);
   const uint32_t t = tile - v_local * uint32_t(tpv);
   const int ty = int(t) / tiles_x;
   const int tx = int(t) - ty * tiles_x;
-  const int lane = threadIdx.x;
-  const int col = lane & (kTS - 1);
-  const int row0 = (lane >> 4) * kRows;
+  const int lane = threadIdx.x & (kWave - 1);
+  // 16-lane group grp owns quadrant grp; each lane a column of 4 pixels in it
+  const int grp = lane >> 4;
+  const int sub = lane & 15;
+  const int col = (grp & 1) * 8 + (sub & 7);
+  const int row0 = (grp >> 1) * 8 + (sub >> 3) * kRows;
   const float px = float(tx * kTS + col) + 0.5f;
   const float py = float(ty * kTS + row0) + 0.5f;
+  const float tx0 = float(tx * kTS) + 0.5f, ty0 = float(ty * kTS) + 0.5f;
+  if (lane == 0) set_null_record(s_cw, s_xy);
   float acc[kRows];
 #pragma unroll
   for (int k = 0; k < kRows; ++k) acc[k] = 0.f;
   const uint32_t b0 = start[tile], e = start[tile + 1];
   for (uint32_t b = b0; b < e; b += kWave) {
     const uint32_t m = min(uint32_t(kWave), e - b);
+    uint32_t mask = 0;
     if (uint32_t(lane) < m) {
       const uint32_t r = svals[b + lane];
-      s_cw[lane] = conic_w[r];
-      s_xy[lane] = xy[r];
+      const float4 c = conic_w[r];
+      const float2 q = xy[r];
+      s_cw[lane] = c;
+      s_xy[lane] = q;
+      mask = quad_mask(c, q.x, q.y, tx0, ty0, thr_cull);
     }
-    __syncthreads();
-    for (uint32_t j = 0; j < m; ++j) {
+    int nq[4], pos[4];
+    build_quad_lists(mask, lane, s_list, nq, pos);
+    const int n_me = (grp == 0) ? nq[0] : (grp == 1) ? nq[1] : (grp == 2) ? nq[2] : nq[3];
+    const int n_max = max(max(nq[0], nq[1]), max(nq[2], nq[3]));
+    wave_lds_sync();
+    for (int i = 0; i < n_max; ++i) {
+      const int j = (i < n_me) ? int(s_list[grp][i]) : kWave;
       const float4 c = s_cw[j];
       const float2 q = s_xy[j];
       const float dx = px - q.x;
       const float dy = py - q.y;
       const float A = c.x * dx * dx;
       const float B = c.y * dx;
+      // exponent down the lane's column, expanded about its first pixel:
+      // arg(dy + k) = arg0 + k (2 c.z dy + B) + c.z k^2
+      const float arg0 = fmaf(dy, fmaf(c.z, dy, B), A);
+      const float E = fmaf(2.f * c.z, dy, B);
 #pragma unroll
       for (int k = 0; k < kRows; ++k) {
-        const float d = dy + float(k);
-        const float arg = fmaf(d, fmaf(c.z, d, B), A);
+        const float fk = float(k);
+        const float arg = (k == 0) ? arg0 : fmaf(fk, fmaf(c.z, fk, E), arg0);
         if (kCount) {
           acc[k] += (arg >= thr) ? 1.f : 0.f;
         } else {
           const float ex = __builtin_amdgcn_exp2f(arg);
-          acc[k] += (arg >= thr) ? c.w * ex : 0.f;
+          acc[k] = fmaf(c.w, (arg >= thr) ? ex : 0.f, acc[k]);
         }
       }
     }
-    __syncthreads();
+    wave_lds_sync();
   }
   const int x = tx * kTS + col;
   if (kCount) {
@@ -211,72 +313,147 @@ __global__ __launch_bounds__(kWave) void splat_fwd_kernel(const uint32_t *__rest
   }
 }
 
-__global__ __launch_bounds__(kWave) void splat_bwd_kernel(
+__device__ __forceinline__ float bperm(int src_lane, float v) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(src_lane << 2, __float_as_int(v)));
+}
+
+// Backward over one tile (per-Gaussian formulation). Each round, 16-lane
+// group grp takes the next 16 entries of quadrant grp's list; a lane owns one
+// (quadrant, Gaussian) pair and sums over the quadrant's 64 pixels (dL/dI
+// read from LDS) the six moments sum g e {1, dx, dy, dx^2, dx dy, dy^2},
+// (dx, dy) = pixel - centre. Pixel coordinates are taken relative to the
+// quadrant centre, (cc, rr) in {-3.5, ..., 3.5}: per row the exponent is a
+// quadratic in cc with lane coefficients and the moments are accumulated
+// against the constants cc, cc^2 (branch-free body), then moved to the
+// Gaussian's centre. The lane that loaded a record then gathers its up to
+// four quadrant partials with wavefront permutes, in quadrant order, and
+// writes the pair's six sums to the pair's emission slot: no atomics, and
+// the summation order is fixed.
+__global__ __launch_bounds__(kBlock) void splat_bwd_kernel(
     const uint32_t *__restrict__ start, const uint32_t *__restrict__ svals,
     const float2 *__restrict__ xy, const float4 *__restrict__ conic_w,
     const ushort4 *__restrict__ rect, const uint32_t *__restrict__ offset, int tiles_x, int tpv,
-    int W, int H, float thr, const float *__restrict__ gimg, float2 *__restrict__ partials) {
-  __shared__ float s_g[kTS * kTS];
-  const uint32_t tile = blockIdx.x;
+    int W, int H, uint32_t n_tiles, float thr, float thr_cull, const float *__restrict__ gimg,
+    float2 *__restrict__ partials) {
+  __shared__ float4 s_g4_all[kTilesPerBlock][kTS * kTS / 4];
+  __shared__ float4 s_cw_all[kTilesPerBlock][kWave + 1];
+  __shared__ float2 s_xy_all[kTilesPerBlock][kWave + 1];
+  __shared__ uint8_t s_list_all[kTilesPerBlock][4][kWave];
+  const int wid = threadIdx.x / kWave;
+  float4 *s_g4 = s_g4_all[wid];
+  float *s_g = reinterpret_cast<float *>(s_g4);
+  float4 *s_cw = s_cw_all[wid];
+  float2 *s_xy = s_xy_all[wid];
+  uint8_t(*s_list)[kWave] = s_list_all[wid];
+  const uint32_t tile = blockIdx.x * kTilesPerBlock + wid;
+  if (tile >= n_tiles) return;
   const uint32_t v_local = tile / uint32_t(tpv);
   const uint32_t t = tile - v_local * uint32_t(tpv);
   const int ty = int(t) / tiles_x;
   const int tx = int(t) - ty * tiles_x;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int grp = lane >> 4;
+  const int sub = lane & 15;
   const float *gv = gimg + uint64_t(v_local) * uint64_t(W) * uint64_t(H);
   for (int p = lane; p < kTS * kTS; p += kWave) {
     const int x = tx * kTS + (p & (kTS - 1));
     const int y = ty * kTS + (p >> 4);
     s_g[p] = (x < W && y < H) ? gv[uint64_t(y) * W + x] : 0.f;
   }
-  __syncthreads();
+  if (lane == 0) set_null_record(s_cw, s_xy);
+  wave_lds_sync();
+  const float tx0 = float(tx * kTS) + 0.5f, ty0 = float(ty * kTS) + 0.5f;
+  // centre of this lane group's quadrant, and its first float4 of dL/dI
+  const float ox = float(tx * kTS + (grp & 1) * 8) + 4.f;
+  const float oy = float(ty * kTS + (grp >> 1) * 8) + 4.f;
+  const float4 *g4q = s_g4 + (grp >> 1) * 8 * (kTS / 4) + (grp & 1) * 2;
   const uint32_t b0 = start[tile], e = start[tile + 1];
-  const float ox = float(tx * kTS) + 0.5f, oy = float(ty * kTS) + 0.5f;
   for (uint32_t b = b0; b < e; b += kWave) {
-    const uint32_t k = b + lane;
-    const bool active = k < e;
-    float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
-    float2 q = make_float2(0.f, 0.f);
-    uint32_t r = 0;
-    if (active) {
-      r = svals[k];
-      c = conic_w[r];
-      q = xy[r];
+    const uint32_t m = min(uint32_t(kWave), e - b);
+    uint32_t mask = 0, r = 0;
+    if (uint32_t(lane) < m) {
+      r = svals[b + lane];
+      const float4 c = conic_w[r];
+      const float2 q = xy[r];
+      s_cw[lane] = c;
+      s_xy[lane] = q;
+      mask = quad_mask(c, q.x, q.y, tx0, ty0, thr_cull);
     }
-    // pixel (col, row) of the tile sits at (col - qx, row - qy) from the centre
-    const float qx = q.x - ox, qy = q.y - oy;
-    float S0 = 0.f, Sx = 0.f, Sy = 0.f, Sxx = 0.f, Sxy = 0.f, Syy = 0.f;
-    for (int row = 0; row < kTS; ++row) {
-      const float dy = float(row) - qy;
-      const float B = c.y * dy;
-      const float Cc = c.z * dy * dy;
-      float R0 = 0.f, RX = 0.f, RXX = 0.f;
+    int nq[4], pos[4];
+    build_quad_lists(mask, lane, s_list, nq, pos);
+    const int n_me = (grp == 0) ? nq[0] : (grp == 1) ? nq[1] : (grp == 2) ? nq[2] : nq[3];
+    const int n_max = max(max(nq[0], nq[1]), max(nq[2], nq[3]));
+    wave_lds_sync();
+    float tot[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int round = 0; round * 16 < n_max; ++round) {
+      const int i = round * 16 + sub;
+      const int j = (i < n_me) ? int(s_list[grp][i]) : kWave;
+      const float4 c = s_cw[j];
+      const float2 q = s_xy[j];
+      // Gaussian centre relative to the quadrant centre; arg = c.x dx^2 + c.y dx dy + c.z dy^2
+      const float qx = q.x - ox, qy = q.y - oy;
+      const float m2aqx = -2.f * c.x * qx;
+      const float aqx2 = c.x * qx * qx;
+      const float mbqx = -c.y * qx;
+      float S0 = 0.f, Sc = 0.f, Scc = 0.f, Sr = 0.f, Scr = 0.f, Srr = 0.f;
+#pragma unroll 2
+      for (int row = 0; row < 8; ++row) {
+        const float rr = float(row) - 3.5f;
+        const float dy = rr - qy;
+        const float brow = fmaf(c.y, dy, m2aqx);
+        const float drow = fmaf(dy, fmaf(c.z, dy, mbqx), aqx2);
+        float R0 = 0.f, R1 = 0.f, R2 = 0.f;
 #pragma unroll
-      for (int col = 0; col < kTS; ++col) {
-        const float dx = float(col) - qx;
-        const float arg = fmaf(dx, fmaf(c.x, dx, B), Cc);
-        const float ex = __builtin_amdgcn_exp2f(arg);
-        const float ge = (arg >= thr) ? s_g[row * kTS + col] * ex : 0.f;
-        R0 += ge;
-        const float gx = ge * dx;
-        RX += gx;
-        RXX = fmaf(gx, dx, RXX);
+        for (int qd = 0; qd < 2; ++qd) {
+          const float4 gq = g4q[row * (kTS / 4) + qd];
+          const float gcol[4] = {gq.x, gq.y, gq.z, gq.w};
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const float cc = float(qd * 4 + u) - 3.5f;
+            const float arg = fmaf(cc, fmaf(c.x, cc, brow), drow);
+            const float ex = __builtin_amdgcn_exp2f(arg);
+            const float ge = ((arg >= thr) ? gcol[u] : 0.f) * ex;
+            R0 += ge;
+            R1 = fmaf(ge, cc, R1);
+            R2 = fmaf(ge, cc * cc, R2);
+          }
+        }
+        S0 += R0;
+        Sc += R1;
+        Scc += R2;
+        Sr = fmaf(R0, rr, Sr);
+        Scr = fmaf(R1, rr, Scr);
+        Srr = fmaf(R0, rr * rr, Srr);
       }
-      S0 += R0;
-      Sx += RX;
-      Sy = fmaf(R0, dy, Sy);
-      Sxx += RXX;
-      Sxy = fmaf(RX, dy, Sxy);
-      Syy = fmaf(R0 * dy, dy, Syy);
+      // moments about the Gaussian centre: dx = cc - qx, dy = rr - qy
+      float M[6];
+      M[0] = S0;
+      M[1] = fmaf(-qx, S0, Sc);
+      M[2] = fmaf(-qy, S0, Sr);
+      M[3] = fmaf(qx * qx, S0, fmaf(-2.f * qx, Sc, Scc));
+      M[4] = fmaf(qx * qy, S0, fmaf(-qy, Sc, fmaf(-qx, Sr, Scr)));
+      M[5] = fmaf(qy * qy, S0, fmaf(-2.f * qy, Sr, Srr));
+      // the loading lane of each record collects its quadrants' partials
+#pragma unroll
+      for (int Q = 0; Q < 4; ++Q) {
+        const bool mine = ((mask >> Q) & 1u) && (pos[Q] >> 4) == round;
+        const int src = Q * 16 + (pos[Q] & 15);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          const float v = bperm(src, M[k]);
+          tot[k] += mine ? v : 0.f;
+        }
+      }
     }
-    if (active) {
+    if (uint32_t(lane) < m) {
       const ushort4 rc = rect[r];
-      const uint32_t j = uint32_t(ty - rc.y) * uint32_t(rc.z - rc.x + 1) + uint32_t(tx - rc.x);
-      const uint64_t p = uint64_t(offset[r]) + j;
-      partials[3 * p + 0] = make_float2(S0, Sx);
-      partials[3 * p + 1] = make_float2(Sy, Sxx);
-      partials[3 * p + 2] = make_float2(Sxy, Syy);
+      const uint32_t jr = uint32_t(ty - rc.y) * uint32_t(rc.z - rc.x + 1) + uint32_t(tx - rc.x);
+      const uint64_t p = uint64_t(offset[r]) + jr;
+      partials[3 * p + 0] = make_float2(tot[0], tot[1]);
+      partials[3 * p + 1] = make_float2(tot[2], tot[3]);
+      partials[3 * p + 2] = make_float2(tot[4], tot[5]);
     }
+    wave_lds_sync();
   }
 }
 
@@ -359,7 +536,7 @@ RastLayout rast_layout(uint64_t R, uint64_t T, uint64_t K) {
   L.T = T;
   L.K = K;
   Carver c(nullptr);
-  c.take<unsigned long long>(1, &L.total64);
+  c.take<unsigned long long>(kTotalSlots, &L.total64);
   c.take<float2>(R, &L.xy);
   c.take<float2>(R, &L.radii);
   c.take<ushort4>(R, &L.rect);
@@ -459,7 +636,7 @@ int build_lists(const fgs_gaussians *g, const fgs_geom *geom, int32_t view_begin
   GeomDev G = make_geom_dev(geom, o, view_begin, tg);
   void *b = ws->ptr;
   unsigned long long *total64 = at<unsigned long long>(b, L.total64);
-  zero_u64_kernel<<<1, 1, 0, s>>>(total64);
+  zero_u64_kernel<<<1, kTotalSlots, 0, s>>>(total64, kTotalSlots);
   FGS_LAUNCH_CHECK("zero_u64_kernel");
   dim3 rgrid(grid_for(uint64_t(g->n), 256), unsigned(view_count));
   record_kernel<<<rgrid, 256, 0, s>>>(*g, G, at<float2>(b, L.xy), at<float4>(b, L.conic),
@@ -468,9 +645,11 @@ int build_lists(const fgs_gaussians *g, const fgs_geom *geom, int32_t view_begin
   FGS_LAUNCH_CHECK("record_kernel");
   int st = exclusive_scan_u32(at<uint32_t>(b, L.offset), R, at<uint32_t>(b, L.scan_scratch), s);
   if (st != FGS_OK) return st;
-  unsigned long long K64 = 0;
-  FGS_HIP(hipMemcpyAsync(&K64, total64, sizeof(K64), hipMemcpyDeviceToHost, s));
+  unsigned long long slots[kTotalSlots];
+  FGS_HIP(hipMemcpyAsync(slots, total64, sizeof(slots), hipMemcpyDeviceToHost, s));
   FGS_HIP(hipStreamSynchronize(s));
+  unsigned long long K64 = 0;
+  for (int i = 0; i < kTotalSlots; ++i) K64 += slots[i];
   if (K64 >= 0xffffffffull)
     return fail(FGS_E_UNSUPPORTED, "more than 2^32 (tile, Gaussian) pairs in one call; split the views");
   const uint64_t K = K64;
@@ -522,9 +701,9 @@ extern "C" int fgs_project_views_fwd(const fgs_gaussians *g, const fgs_geom *geo
   const TileGrid tg = tile_grid(geom->det_w, geom->det_h);
   hipEvent_t *ev = static_cast<hipEvent_t *>(opts->events);
   if (ev) FGS_HIP(hipEventRecord(ev[0], s));
-  splat_fwd_kernel<false><<<unsigned(L.T), kWave, 0, s>>>(at<uint32_t>(b, L.start), sv, at<float2>(b, L.xy),
-                                                          at<float4>(b, L.conic), tg.tiles_x, tg.tpv,
-                                                          geom->det_w, geom->det_h, thr, img, nullptr);
+  splat_fwd_kernel<false><<<grid_for(L.T, kTilesPerBlock), kBlock, 0, s>>>(
+      at<uint32_t>(b, L.start), sv, at<float2>(b, L.xy), at<float4>(b, L.conic), tg.tiles_x, tg.tpv,
+      geom->det_w, geom->det_h, uint32_t(L.T), thr, thr * kCullSlack, img, nullptr);
   FGS_LAUNCH_CHECK("splat_fwd_kernel");
   if (ev) FGS_HIP(hipEventRecord(ev[1], s));
   return FGS_OK;
@@ -542,14 +721,14 @@ extern "C" int fgs_project_views_support(const fgs_gaussians *g, const fgs_geom 
   if (st != FGS_OK) return st;
   void *b = ws->ptr;
   unsigned long long *cnt = reinterpret_cast<unsigned long long *>(out);
-  zero_u64_kernel<<<1, 1, 0, s>>>(cnt);
+  zero_u64_kernel<<<1, 1, 0, s>>>(cnt, 1);
   FGS_LAUNCH_CHECK("zero_u64_kernel");
   const uint32_t *sv = at<uint32_t>(b, L.sorted_in_alt ? L.vals_alt : L.vals);
   const float thr = -0.5f * kLog2e * opts->kappa * opts->kappa;
   const TileGrid tg = tile_grid(geom->det_w, geom->det_h);
-  splat_fwd_kernel<true><<<unsigned(L.T), kWave, 0, s>>>(at<uint32_t>(b, L.start), sv, at<float2>(b, L.xy),
-                                                         at<float4>(b, L.conic), tg.tiles_x, tg.tpv,
-                                                         geom->det_w, geom->det_h, thr, nullptr, cnt);
+  splat_fwd_kernel<true><<<grid_for(L.T, kTilesPerBlock), kBlock, 0, s>>>(
+      at<uint32_t>(b, L.start), sv, at<float2>(b, L.xy), at<float4>(b, L.conic), tg.tiles_x, tg.tpv,
+      geom->det_w, geom->det_h, uint32_t(L.T), thr, thr * kCullSlack, nullptr, cnt);
   FGS_LAUNCH_CHECK("splat_fwd_kernel<count>");
   return FGS_OK;
 }
@@ -583,10 +762,10 @@ extern "C" int fgs_project_views_bwd(const fgs_gaussians *g, const fgs_geom *geo
   hipEvent_t *ev = static_cast<hipEvent_t *>(opts->events);
   if (ev) FGS_HIP(hipEventRecord(ev[0], s));
   if (L.K > 0) {
-    splat_bwd_kernel<<<unsigned(L.T), kWave, 0, s>>>(
+    splat_bwd_kernel<<<grid_for(L.T, kTilesPerBlock), kBlock, 0, s>>>(
         at<uint32_t>(b, L.start), sv, at<float2>(b, L.xy), at<float4>(b, L.conic),
         at<ushort4>(b, L.rect), at<uint32_t>(b, L.offset), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
-        thr, grad_img, at<float2>(b, L.partials));
+        uint32_t(L.T), thr, thr * kCullSlack, grad_img, at<float2>(b, L.partials));
     FGS_LAUNCH_CHECK("splat_bwd_kernel");
   }
   if (ev) FGS_HIP(hipEventRecord(ev[1], s));

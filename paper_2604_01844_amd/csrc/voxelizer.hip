@@ -22,6 +22,8 @@ namespace {
 
 constexpr int kVT = 8;     // voxel tile side
 constexpr int kWave = 64;
+constexpr int kTilesPerBlock = 16;  // independent tiles per workgroup, one per wave
+constexpr int kBlock = kWave * kTilesPerBlock;
 
 struct __align__(16) Rect3 {
   unsigned short v[8];     // x0, y0, z0, x1, y1, z1, 0, 0
@@ -69,7 +71,11 @@ __device__ __forceinline__ void vox_span(float c, float r, int n_tiles, int &t0,
   t1 = min(static_cast<int>(floorf(hi)) >> 3, n_tiles - 1);
 }
 
-__global__ void zero_u64_kernel(unsigned long long *p) { *p = 0ull; }
+constexpr int kTotalSlots = 64;
+
+__global__ void zero_u64_kernel(unsigned long long *p, int n) {
+  if (int(threadIdx.x) < n) p[threadIdx.x] = 0ull;
+}
 
 __global__ __launch_bounds__(256) void vox_record_kernel(fgs_gaussians g, GridDev G,
                                                          float4 *__restrict__ prho,
@@ -114,7 +120,8 @@ __global__ __launch_bounds__(256) void vox_record_kernel(fgs_gaussians g, GridDe
   }
   unsigned long long w = cnt;
   for (int d = 32; d > 0; d >>= 1) w += __shfl_xor(w, d, 64);
-  if ((threadIdx.x & 63) == 0 && w) atomicAdd(total64, w);
+  if ((threadIdx.x & 63) == 0 && w)
+    atomicAdd(total64 + ((blockIdx.x * 4 + (threadIdx.x >> 6)) & (kTotalSlots - 1)), w);
 }
 
 __global__ __launch_bounds__(256) void vox_emit_kernel(int64_t n, int ntx, int nty,
@@ -148,20 +155,24 @@ __global__ __launch_bounds__(256) void vox_ranges_kernel(const uint32_t *__restr
 // kCount = true: count the (voxel, Gaussian) pairs in the support whose voxel
 // lies in the grid (the algorithmic work) instead of writing the volume.
 template <bool kCount>
-__global__ __launch_bounds__(kWave) void vox_fwd_kernel(const uint32_t *__restrict__ start,
-                                                        const uint32_t *__restrict__ svals,
-                                                        const float4 *__restrict__ prho,
-                                                        const float4 *__restrict__ a0,
-                                                        const float4 *__restrict__ a1, GridDev G,
-                                                        float thr, float *__restrict__ vol,
-                                                        unsigned long long *__restrict__ counter) {
-  __shared__ float4 s_p[kWave], s_a0[kWave], s_a1[kWave];
-  const uint32_t tile = blockIdx.x;
+__global__ __launch_bounds__(kBlock) void vox_fwd_kernel(const uint32_t *__restrict__ start,
+                                                         const uint32_t *__restrict__ svals,
+                                                         const float4 *__restrict__ prho,
+                                                         const float4 *__restrict__ a0,
+                                                         const float4 *__restrict__ a1, GridDev G,
+                                                         uint32_t n_tiles, float thr,
+                                                         float *__restrict__ vol,
+                                                         unsigned long long *__restrict__ counter) {
+  __shared__ float4 s_all[kTilesPerBlock][3][kWave];
+  const int wid = threadIdx.x / kWave;
+  float4 *s_p = s_all[wid][0], *s_a0 = s_all[wid][1], *s_a1 = s_all[wid][2];
+  const uint32_t tile = blockIdx.x * kTilesPerBlock + wid;
+  if (tile >= n_tiles) return;
   const int tx = int(tile % uint32_t(G.nt[0]));
   const int tyz = int(tile / uint32_t(G.nt[0]));
   const int ty = tyz % G.nt[1];
   const int tz = tyz / G.nt[1];
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
   const int y = ty * kVT + (lane & 7);
   const int z = tz * kVT + (lane >> 3);
   const float fx0 = float(tx * kVT), fy = float(y), fz = float(z);
@@ -177,7 +188,7 @@ __global__ __launch_bounds__(kWave) void vox_fwd_kernel(const uint32_t *__restri
       s_a0[lane] = a0[r];
       s_a1[lane] = a1[r];
     }
-    __syncthreads();
+    wave_lds_sync();
     for (uint32_t j = 0; j < m; ++j) {
       const float4 p = s_p[j];
       const float4 c0 = s_a0[j];
@@ -186,19 +197,23 @@ __global__ __launch_bounds__(kWave) void vox_fwd_kernel(const uint32_t *__restri
       const float B = fmaf(c0.y, dy, c0.z * dz);
       const float Cc = fmaf(dy, fmaf(c0.w, dy, c1.x * dz), c1.y * dz * dz);
       const float dx0 = fx0 - p.x;
+      // exponent along the row, expanded about the first voxel:
+      // arg(dx0 + k) = arg0 + k (2 a dx0 + B) + a k^2
+      const float arg0 = fmaf(dx0, fmaf(c0.x, dx0, B), Cc);
+      const float E = fmaf(2.f * c0.x, dx0, B);
 #pragma unroll
       for (int k = 0; k < kVT; ++k) {
-        const float dx = dx0 + float(k);
-        const float arg = fmaf(dx, fmaf(c0.x, dx, B), Cc);
+        const float fk = float(k);
+        const float arg = (k == 0) ? arg0 : fmaf(fk, fmaf(c0.x, fk, E), arg0);
         if (kCount) {
           acc[k] += (arg >= thr) ? 1.f : 0.f;
         } else {
           const float ex = __builtin_amdgcn_exp2f(arg);
-          acc[k] += (arg >= thr) ? p.w * ex : 0.f;
+          acc[k] = fmaf(p.w, (arg >= thr) ? ex : 0.f, acc[k]);
         }
       }
     }
-    __syncthreads();
+    wave_lds_sync();
   }
   if (kCount) {
     unsigned long long n = 0;
@@ -221,36 +236,47 @@ __global__ __launch_bounds__(kWave) void vox_fwd_kernel(const uint32_t *__restri
   }
 }
 
-__global__ __launch_bounds__(kWave) void vox_bwd_kernel(const uint32_t *__restrict__ start,
-                                                        const uint32_t *__restrict__ svals,
-                                                        const float4 *__restrict__ prho,
-                                                        const float4 *__restrict__ a0,
-                                                        const float4 *__restrict__ a1,
-                                                        const Rect3 *__restrict__ rect,
-                                                        const uint32_t *__restrict__ offset,
-                                                        GridDev G, float thr,
-                                                        const float *__restrict__ gvol,
-                                                        float2 *__restrict__ partials) {
-  __shared__ float s_g[kVT * kVT * kVT];
-  const uint32_t tile = blockIdx.x;
+// Backward over one 8^3 tile: lane j owns pair (tile, list[j]) and sums the
+// ten moments over the 512 voxels. Coordinates are relative to the tile
+// centre, (cx, cy, cz) in {-3.5, ..., 3.5}; along each x-row the exponent is
+// a quadratic in cx with lane coefficients, and the moments are accumulated
+// against the constants cx, cx^2, then moved to the Gaussian's centre once
+// per pair. Branch-free loop body.
+__global__ __launch_bounds__(kBlock) void vox_bwd_kernel(const uint32_t *__restrict__ start,
+                                                         const uint32_t *__restrict__ svals,
+                                                         const float4 *__restrict__ prho,
+                                                         const float4 *__restrict__ a0,
+                                                         const float4 *__restrict__ a1,
+                                                         const Rect3 *__restrict__ rect,
+                                                         const uint32_t *__restrict__ offset,
+                                                         GridDev G, uint32_t n_tiles, float thr,
+                                                         const float *__restrict__ gvol,
+                                                         float2 *__restrict__ partials) {
+  __shared__ float4 s_g4_all[kTilesPerBlock][kVT * kVT * kVT / 4];
+  const int wid = threadIdx.x / kWave;
+  float4 *s_g4 = s_g4_all[wid];
+  float *s_g = reinterpret_cast<float *>(s_g4);
+  const uint32_t tile = blockIdx.x * kTilesPerBlock + wid;
+  if (tile >= n_tiles) return;
   const int tx = int(tile % uint32_t(G.nt[0]));
   const int tyz = int(tile / uint32_t(G.nt[0]));
   const int ty = tyz % G.nt[1];
   const int tz = tyz / G.nt[1];
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
   for (int q = lane; q < kVT * kVT * kVT; q += kWave) {
     const int x = tx * kVT + (q & 7), y = ty * kVT + ((q >> 3) & 7), z = tz * kVT + (q >> 6);
     s_g[q] = (x < G.dims[0] && y < G.dims[1] && z < G.dims[2])
                  ? gvol[(uint64_t(z) * G.dims[1] + y) * uint64_t(G.dims[0]) + x]
                  : 0.f;
   }
-  __syncthreads();
+  wave_lds_sync();
   const uint32_t b0 = start[tile], e = start[tile + 1];
-  const float ox = float(tx * kVT), oy = float(ty * kVT), oz = float(tz * kVT);
+  const float h = 0.5f * (kVT - 1);
+  const float ox = float(tx * kVT) + h, oy = float(ty * kVT) + h, oz = float(tz * kVT) + h;
   for (uint32_t b = b0; b < e; b += kWave) {
     const uint32_t k = b + lane;
     const bool active = k < e;
-    float4 p = make_float4(0.f, 0.f, 0.f, 0.f), c0 = p, c1 = p;
+    float4 p = make_float4(ox, oy, oz, 0.f), c0 = make_float4(0.f, 0.f, 0.f, 0.f), c1 = c0;
     uint32_t r = 0;
     if (active) {
       r = svals[k];
@@ -259,50 +285,71 @@ __global__ __launch_bounds__(kWave) void vox_bwd_kernel(const uint32_t *__restri
       c1 = a1[r];
     }
     const float qx = p.x - ox, qy = p.y - oy, qz = p.z - oz;
-    float S0 = 0.f, Sx = 0.f, Sy = 0.f, Sz = 0.f;
-    float Sxx = 0.f, Sxy = 0.f, Sxz = 0.f, Syy = 0.f, Syz = 0.f, Szz = 0.f;
+    const float m2aqx = -2.f * c0.x * qx;
+    const float aqx2 = c0.x * qx * qx;
+    float S0 = 0.f, Sc = 0.f, Scc = 0.f, Sy = 0.f, Sz = 0.f;
+    float Sxy = 0.f, Sxz = 0.f, Syy = 0.f, Syz = 0.f, Szz = 0.f;
     for (int zz = 0; zz < kVT; ++zz) {
-      const float dz = float(zz) - qz;
+      const float cz = float(zz) - h;
+      const float dz = cz - qz;
+#pragma unroll 2
       for (int yy = 0; yy < kVT; ++yy) {
-        const float dy = float(yy) - qy;
-        const float B = fmaf(c0.y, dy, c0.z * dz);
+        const float cy = float(yy) - h;
+        const float dy = cy - qy;
+        const float lin = fmaf(c0.y, dy, c0.z * dz);
         const float Cc = fmaf(dy, fmaf(c0.w, dy, c1.x * dz), c1.y * dz * dz);
-        const float *gr = s_g + (zz * kVT + yy) * kVT;
-        float R0 = 0.f, RX = 0.f, RXX = 0.f;
+        const float brow = lin + m2aqx;
+        const float drow = fmaf(-lin, qx, aqx2 + Cc);
+        const float4 *g4 = s_g4 + (zz * kVT + yy) * (kVT / 4);
+        float R0 = 0.f, R1 = 0.f, R2 = 0.f;
 #pragma unroll
-        for (int xx = 0; xx < kVT; ++xx) {
-          const float dx = float(xx) - qx;
-          const float arg = fmaf(dx, fmaf(c0.x, dx, B), Cc);
-          const float ex = __builtin_amdgcn_exp2f(arg);
-          const float ge = (arg >= thr) ? gr[xx] * ex : 0.f;
-          R0 += ge;
-          const float gx = ge * dx;
-          RX += gx;
-          RXX = fmaf(gx, dx, RXX);
+        for (int qd = 0; qd < kVT / 4; ++qd) {
+          const float4 gq = g4[qd];
+          const float gcol[4] = {gq.x, gq.y, gq.z, gq.w};
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const float cx = float(qd * 4 + u) - h;
+            const float arg = fmaf(cx, fmaf(c0.x, cx, brow), drow);
+            const float ex = __builtin_amdgcn_exp2f(arg);
+            const float ge = ((arg >= thr) ? gcol[u] : 0.f) * ex;
+            R0 += ge;
+            R1 = fmaf(ge, cx, R1);
+            R2 = fmaf(ge, cx * cx, R2);
+          }
         }
         S0 += R0;
-        Sx += RX;
-        Sy = fmaf(R0, dy, Sy);
-        Sz = fmaf(R0, dz, Sz);
-        Sxx += RXX;
-        Sxy = fmaf(RX, dy, Sxy);
-        Sxz = fmaf(RX, dz, Sxz);
-        const float Rdy = R0 * dy;
-        Syy = fmaf(Rdy, dy, Syy);
-        Syz = fmaf(Rdy, dz, Syz);
-        Szz = fmaf(R0 * dz, dz, Szz);
+        Sc += R1;
+        Scc += R2;
+        Sy = fmaf(R0, cy, Sy);
+        Sz = fmaf(R0, cz, Sz);
+        Sxy = fmaf(R1, cy, Sxy);
+        Sxz = fmaf(R1, cz, Sxz);
+        const float R0y = R0 * cy;
+        Syy = fmaf(R0y, cy, Syy);
+        Syz = fmaf(R0y, cz, Syz);
+        Szz = fmaf(R0 * cz, cz, Szz);
       }
     }
     if (active) {
+      // moments about the Gaussian centre: d = c - q
+      const float Mx = fmaf(-qx, S0, Sc);
+      const float My = fmaf(-qy, S0, Sy);
+      const float Mz = fmaf(-qz, S0, Sz);
+      const float Mxx = fmaf(qx * qx, S0, fmaf(-2.f * qx, Sc, Scc));
+      const float Myy = fmaf(qy * qy, S0, fmaf(-2.f * qy, Sy, Syy));
+      const float Mzz = fmaf(qz * qz, S0, fmaf(-2.f * qz, Sz, Szz));
+      const float Mxy = fmaf(qx * qy, S0, fmaf(-qy, Sc, fmaf(-qx, Sy, Sxy)));
+      const float Mxz = fmaf(qx * qz, S0, fmaf(-qz, Sc, fmaf(-qx, Sz, Sxz)));
+      const float Myz = fmaf(qy * qz, S0, fmaf(-qz, Sy, fmaf(-qy, Sz, Syz)));
       const Rect3 rc = rect[r];
       const uint32_t nx = uint32_t(rc.v[3] - rc.v[0] + 1), ny = uint32_t(rc.v[4] - rc.v[1] + 1);
       const uint32_t j = (uint32_t(tz - rc.v[2]) * ny + uint32_t(ty - rc.v[1])) * nx + uint32_t(tx - rc.v[0]);
       const uint64_t q = uint64_t(offset[r]) + j;
-      partials[5 * q + 0] = make_float2(S0, Sx);
-      partials[5 * q + 1] = make_float2(Sy, Sz);
-      partials[5 * q + 2] = make_float2(Sxx, Sxy);
-      partials[5 * q + 3] = make_float2(Sxz, Syy);
-      partials[5 * q + 4] = make_float2(Syz, Szz);
+      partials[5 * q + 0] = make_float2(S0, Mx);
+      partials[5 * q + 1] = make_float2(My, Mz);
+      partials[5 * q + 2] = make_float2(Mxx, Mxy);
+      partials[5 * q + 3] = make_float2(Mxz, Myy);
+      partials[5 * q + 4] = make_float2(Myz, Mzz);
     }
   }
 }
@@ -383,7 +430,7 @@ VoxLayout vox_layout(uint64_t N, uint64_t T, uint64_t K) {
   L.T = T;
   L.K = K;
   Carver c(nullptr);
-  c.take<unsigned long long>(1, &L.total64);
+  c.take<unsigned long long>(kTotalSlots, &L.total64);
   c.take<float4>(N, &L.prho);
   c.take<float4>(N, &L.radii);
   c.take<Rect3>(N, &L.rect);
@@ -450,7 +497,7 @@ int vox_build(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *o, f
   }
   void *b = ws->ptr;
   unsigned long long *total64 = at<unsigned long long>(b, L.total64);
-  zero_u64_kernel<<<1, 1, 0, s>>>(total64);
+  zero_u64_kernel<<<1, kTotalSlots, 0, s>>>(total64, kTotalSlots);
   FGS_LAUNCH_CHECK("zero_u64_kernel");
   vox_record_kernel<<<grid_for(N, 256), 256, 0, s>>>(*g, G, at<float4>(b, L.prho), at<float4>(b, L.a0),
                                                       at<float4>(b, L.a1), at<float4>(b, L.radii),
@@ -459,9 +506,11 @@ int vox_build(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *o, f
   FGS_LAUNCH_CHECK("vox_record_kernel");
   int st = exclusive_scan_u32(at<uint32_t>(b, L.offset), N, at<uint32_t>(b, L.scan_scratch), s);
   if (st != FGS_OK) return st;
-  unsigned long long K64 = 0;
-  FGS_HIP(hipMemcpyAsync(&K64, total64, sizeof(K64), hipMemcpyDeviceToHost, s));
+  unsigned long long slots[kTotalSlots];
+  FGS_HIP(hipMemcpyAsync(slots, total64, sizeof(slots), hipMemcpyDeviceToHost, s));
   FGS_HIP(hipStreamSynchronize(s));
+  unsigned long long K64 = 0;
+  for (int i = 0; i < kTotalSlots; ++i) K64 += slots[i];
   if (K64 >= 0xffffffffull)
     return fail(FGS_E_UNSUPPORTED, "more than 2^32 (tile, Gaussian) pairs; split the grid into slabs");
   const uint64_t K = K64;
@@ -528,9 +577,9 @@ extern "C" int fgs_voxelize_fwd(const fgs_gaussians *g, const fgs_grid *grid, co
   const float thr = -0.5f * kLog2e * opts->kappa * opts->kappa;
   hipEvent_t *ev = static_cast<hipEvent_t *>(opts->events);
   if (ev) FGS_HIP(hipEventRecord(ev[0], s));
-  vox_fwd_kernel<false><<<unsigned(L.T), kWave, 0, s>>>(at<uint32_t>(b, L.start), sv, at<float4>(b, L.prho),
-                                                        at<float4>(b, L.a0), at<float4>(b, L.a1), G, thr, vol,
-                                                        nullptr);
+  vox_fwd_kernel<false><<<grid_for(L.T, kTilesPerBlock), kBlock, 0, s>>>(
+      at<uint32_t>(b, L.start), sv, at<float4>(b, L.prho), at<float4>(b, L.a0), at<float4>(b, L.a1), G,
+      uint32_t(L.T), thr, vol, nullptr);
   FGS_LAUNCH_CHECK("vox_fwd_kernel");
   if (ev) FGS_HIP(hipEventRecord(ev[1], s));
   return FGS_OK;
@@ -548,13 +597,13 @@ extern "C" int fgs_voxelize_support(const fgs_gaussians *g, const fgs_grid *grid
   if (st != FGS_OK) return st;
   void *b = ws->ptr;
   unsigned long long *cnt = reinterpret_cast<unsigned long long *>(out);
-  zero_u64_kernel<<<1, 1, 0, s>>>(cnt);
+  zero_u64_kernel<<<1, 1, 0, s>>>(cnt, 1);
   FGS_LAUNCH_CHECK("zero_u64_kernel");
   const uint32_t *sv = at<uint32_t>(b, L.sorted_in_alt ? L.vals_alt : L.vals);
   const float thr = -0.5f * kLog2e * opts->kappa * opts->kappa;
-  vox_fwd_kernel<true><<<unsigned(L.T), kWave, 0, s>>>(at<uint32_t>(b, L.start), sv, at<float4>(b, L.prho),
-                                                       at<float4>(b, L.a0), at<float4>(b, L.a1), G, thr,
-                                                       nullptr, cnt);
+  vox_fwd_kernel<true><<<grid_for(L.T, kTilesPerBlock), kBlock, 0, s>>>(
+      at<uint32_t>(b, L.start), sv, at<float4>(b, L.prho), at<float4>(b, L.a0), at<float4>(b, L.a1), G,
+      uint32_t(L.T), thr, nullptr, cnt);
   FGS_LAUNCH_CHECK("vox_fwd_kernel<count>");
   return FGS_OK;
 }
@@ -586,10 +635,10 @@ extern "C" int fgs_voxelize_bwd(const fgs_gaussians *g, const fgs_grid *grid, co
   hipEvent_t *ev = static_cast<hipEvent_t *>(opts->events);
   if (ev) FGS_HIP(hipEventRecord(ev[0], s));
   if (L.K > 0) {
-    vox_bwd_kernel<<<unsigned(L.T), kWave, 0, s>>>(at<uint32_t>(b, L.start), sv, at<float4>(b, L.prho),
-                                                   at<float4>(b, L.a0), at<float4>(b, L.a1),
-                                                   at<Rect3>(b, L.rect), at<uint32_t>(b, L.offset), G, thr,
-                                                   grad_vol, at<float2>(b, L.partials));
+    vox_bwd_kernel<<<grid_for(L.T, kTilesPerBlock), kBlock, 0, s>>>(
+        at<uint32_t>(b, L.start), sv, at<float4>(b, L.prho), at<float4>(b, L.a0), at<float4>(b, L.a1),
+        at<Rect3>(b, L.rect), at<uint32_t>(b, L.offset), G, uint32_t(L.T), thr, grad_vol,
+        at<float2>(b, L.partials));
     FGS_LAUNCH_CHECK("vox_bwd_kernel");
   }
   if (ev) FGS_HIP(hipEventRecord(ev[1], s));
