@@ -329,7 +329,7 @@ __device__ __forceinline__ float bperm(int src_lane, float v) {
 // four quadrant partials with wavefront permutes, in quadrant order, and
 // writes the pair's six sums to the pair's emission slot: no atomics, and
 // the summation order is fixed.
-__global__ __launch_bounds__(kBlock) void splat_bwd_kernel(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void splat_bwd_kernel(
     const uint32_t *__restrict__ start, const uint32_t *__restrict__ svals,
     const float2 *__restrict__ xy, const float4 *__restrict__ conic_w,
     const ushort4 *__restrict__ rect, const uint32_t *__restrict__ offset, int tiles_x, int tpv,
@@ -383,6 +383,9 @@ __global__ __launch_bounds__(kBlock) void splat_bwd_kernel(
     build_quad_lists(mask, lane, s_list, nq, pos);
     const int n_me = (grp == 0) ? nq[0] : (grp == 1) ? nq[1] : (grp == 2) ? nq[2] : nq[3];
     const int n_max = max(max(nq[0], nq[1]), max(nq[2], nq[3]));
+    // this lane's record: its list positions (6 bits each) and quadrant mask, packed
+    const uint32_t posm = uint32_t(pos[0]) | (uint32_t(pos[1]) << 6) | (uint32_t(pos[2]) << 12) |
+                          (uint32_t(pos[3]) << 18) | (mask << 24);
     wave_lds_sync();
     float tot[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     for (int round = 0; round * 16 < n_max; ++round) {
@@ -396,7 +399,7 @@ __global__ __launch_bounds__(kBlock) void splat_bwd_kernel(
       const float aqx2 = c.x * qx * qx;
       const float mbqx = -c.y * qx;
       float S0 = 0.f, Sc = 0.f, Scc = 0.f, Sr = 0.f, Scr = 0.f, Srr = 0.f;
-#pragma unroll 2
+#pragma unroll 1
       for (int row = 0; row < 8; ++row) {
         const float rr = float(row) - 3.5f;
         const float dy = rr - qy;
@@ -436,8 +439,9 @@ __global__ __launch_bounds__(kBlock) void splat_bwd_kernel(
       // the loading lane of each record collects its quadrants' partials
 #pragma unroll
       for (int Q = 0; Q < 4; ++Q) {
-        const bool mine = ((mask >> Q) & 1u) && (pos[Q] >> 4) == round;
-        const int src = Q * 16 + (pos[Q] & 15);
+        const int pq = int((posm >> (6 * Q)) & 63u);
+        const bool mine = ((posm >> (24 + Q)) & 1u) && (pq >> 4) == round;
+        const int src = Q * 16 + (pq & 15);
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
           const float v = bperm(src, M[k]);
