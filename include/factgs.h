@@ -92,6 +92,9 @@ typedef struct {
   float *density;    /* device [n] */
 } fgs_gaussian_grads;
 
+/* Gaussian parameters written by an initialiser: same layout as fgs_gaussians. */
+typedef fgs_gaussian_grads fgs_gaussians_out;
+
 /* Scanner geometry (Sec. 3.2: cone-beam pinhole model or parallel beam). */
 typedef struct {
   int32_t mode;          /* FGS_CONE or FGS_PARALLEL */
@@ -242,6 +245,39 @@ int fgs_phantom_project(const fgs_phantom *ph, const fgs_geom *geom, int32_t vie
 
 /* Indicator sum at voxel centres: vol[nz][ny][nx]. */
 int fgs_phantom_voxelize(const fgs_phantom *ph, const fgs_grid *grid, float *vol, void *stream);
+
+/* ---------------------------------------------------------------------
+ * Initialisation (Sec. 3.1).
+ * ------------------------------------------------------------------- */
+
+/* FDK reconstruction of a full circular cone-beam scan: projections
+ * img[view_count][det_h][det_w] (device) of views [view_begin, view_begin +
+ * view_count), which must cover 360 degrees uniformly, into vol[nz][ny][nx]
+ * (device, overwritten) on `grid`. Discretisation: cosine pre-weight, a
+ * Ram-Lak ramp filter along detector rows by direct convolution on the
+ * detector rescaled to the rotation axis, and distance-weighted
+ * backprojection with bilinear interpolation and a factor 1/2 for the
+ * doubly measured rays. Cone beam only (FGS_E_UNSUPPORTED otherwise);
+ * at most 1024 views and 8192 pixels per row. Workspace: view_count *
+ * det_h * det_w floats (FGS_E_CAPACITY protocol). No synchronisation. */
+int fgs_fdk(const float *img, const fgs_geom *geom, int32_t view_begin, int32_t view_count,
+            const fgs_grid *grid, float *vol, fgs_workspace *ws, void *stream);
+
+/* FDK-gradient sampling initialisation of n Gaussians from vol[nz][ny][nx]
+ * (device) on `grid` (Sec. 3.1): voxels below background_fraction * max(vol)
+ * are zeroed; the gradient magnitude (central differences, zero outside the
+ * grid) is quantised to 24 bits of its maximum, and draw i takes the voxel
+ * whose cumulative-weight interval holds floor(u0[i] * total weight); the
+ * mean is that voxel's corner + (u1, u2, u3)[i] * spacing. uniforms is
+ * device double [4][n] of U[0, 1) variates (u0: voxel, u1..u3: position in
+ * the voxel). density = density_scale * vol trilinearly interpolated at the
+ * mean (zero outside), quaternion = (1, 0, 0, 0), every log-scale = log of
+ * the distance to the nearest other mean, floored at min_scale. Writes all
+ * four arrays of `out` (device). Waits on the stream once (to check that
+ * the volume has a gradient; FGS_E_INVALID if it has none). */
+int fgs_gradient_init(const float *vol, const fgs_grid *grid, float background_fraction,
+                      float density_scale, float min_scale, int64_t n, const double *uniforms,
+                      fgs_gaussians_out *out, fgs_workspace *ws, void *stream);
 
 /* ---------------------------------------------------------------------
  * Introspection (tests): where the last binning of a workspace lives.

@@ -27,6 +27,11 @@ Parity status of each function (what pins it in ``tests/test_oracle_pins.py``):
   by quadrature of the indicator.
 * ``bin_tiles``: pinned by the superset property against FP64 support pairs.
 * ``l1_loss_grad``, ``adam_step``, ``psnr``: pinned by hand-computed values.
+* ``initialisation.fdk`` (FDK, Sec. 3.1): pinned by the reconstruction of
+  uniform spheres and ellipsoids from their exact projections.
+* ``initialisation.gradient_init``: pinned by hand-computed draws, sampling
+  frequencies against the exact multinomial law, trilinear exactness on
+  linear fields and brute-force nearest neighbours.
 """
 from __future__ import annotations
 
@@ -393,6 +398,9 @@ def psnr(vol, gt):
     gt = np.asarray(gt, dtype=np.float64)
     mse = np.mean((vol - gt) ** 2)
     return 10.0 * np.log10(gt.max() ** 2 / mse)
+
+
+from .initialisation import fdk, gradient_init, sampling_weights, trilinear  # noqa: E402,F401
 
 
 def rel_l2(a, b) -> float:

@@ -81,6 +81,9 @@ SIGNATURES = {
     "fgs_phantom_project": [P(fgs_phantom), P(fgs_geom), ctypes.c_int32, ctypes.c_int32, _vp, _vp],
     "fgs_phantom_voxelize": [P(fgs_phantom), P(fgs_grid), _vp, _vp],
     "fgs_binning_layout": [P(fgs_workspace), P(ctypes.c_uint64), P(ctypes.c_uint64)],
+    "fgs_fdk": [_vp, P(fgs_geom), ctypes.c_int32, ctypes.c_int32, P(fgs_grid), _vp, P(fgs_workspace), _vp],
+    "fgs_gradient_init": [_vp, P(fgs_grid), ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_int64, _vp,
+                          P(fgs_gaussian_grads), P(fgs_workspace), _vp],
     "fgs_last_error": [],
     "fgs_version": [],
 }

@@ -56,8 +56,10 @@ struct Carver {
 
 // Exclusive prefix sum of n uint32 values, in place: data[n] receives the
 // total. data must hold n + 1 entries. Scratch from scan_scratch_words(n).
+// Scratch is counted in 32-bit words (8-byte aligned inside the workspace).
 uint64_t scan_scratch_words(uint64_t n);
 int exclusive_scan_u32(uint32_t *data, uint64_t n, uint32_t *scratch, hipStream_t s);
+int exclusive_scan_u64(uint64_t *data, uint64_t n, uint32_t *scratch, hipStream_t s);
 
 // Stable LSD radix sort of (key, value) uint32 pairs on the low `bits` bits
 // of the key. Input in keys/vals; the sorted result ends in the buffers

@@ -25,22 +25,22 @@ constexpr int kMaxBits = 9;
 constexpr int kBins = 1 << kMaxBits;
 
 // Exclusive scan of one value per thread across the 256-thread block.
-__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *wsum,
-                                                         uint32_t &total) {
+template <typename T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T *wsum, T &total) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  uint32_t x = v;
+  T x = v;
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
-    uint32_t y = __shfl_up(x, d, 64);
+    T y = __shfl_up(x, d, 64);
     if (lane >= d) x += y;
   }
   if (lane == 63) wsum[wid] = x;
   __syncthreads();
-  uint32_t base = 0, tot = 0;
+  T base = 0, tot = 0;
 #pragma unroll
   for (int w = 0; w < kWaves; ++w) {
-    uint32_t s = wsum[w];
-    base += (w < wid) ? s : 0u;
+    T s = wsum[w];
+    base += (w < wid) ? s : T(0);
     tot += s;
   }
   total = tot;
@@ -48,30 +48,30 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *w
   return base + x - v;
 }
 
-__global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const uint32_t *__restrict__ data,
-                                                               uint64_t n,
-                                                               uint32_t *__restrict__ partial) {
-  __shared__ uint32_t wsum[kWaves];
+template <typename T>
+__global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const T *__restrict__ data, uint64_t n,
+                                                               T *__restrict__ partial) {
+  __shared__ T wsum[kWaves];
   const uint64_t base = uint64_t(blockIdx.x) * kTile;
-  uint32_t s = 0;
+  T s = 0;
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
     uint64_t idx = base + uint64_t(j) * kThreads + threadIdx.x;
-    s += (idx < n) ? data[idx] : 0u;
+    s += (idx < n) ? data[idx] : T(0);
   }
-  uint32_t total;
+  T total;
   block_exclusive_scan(s, wsum, total);
   if (threadIdx.x == 0) partial[blockIdx.x] = total;
 }
 
 // Scans one tile in LDS; adds the scanned tile offset (partial, may be null
 // for a single tile). The last tile writes the grand total to data[n].
-__global__ __launch_bounds__(kThreads) void scan_apply_kernel(uint32_t *__restrict__ data,
-                                                              uint64_t n,
-                                                              const uint32_t *__restrict__ partial,
+template <typename T>
+__global__ __launch_bounds__(kThreads) void scan_apply_kernel(T *__restrict__ data, uint64_t n,
+                                                              const T *__restrict__ partial,
                                                               uint32_t n_tiles) {
-  __shared__ uint32_t tile[kTile + kTile / 32];
-  __shared__ uint32_t wsum[kWaves];
+  __shared__ T tile[kTile + kTile / 32];
+  __shared__ T wsum[kWaves];
   const uint64_t base = uint64_t(blockIdx.x) * kTile;
   // padded index: one spare word every 32 to spread the strided reads over banks
   auto pad = [](int i) { return i + (i >> 5); };
@@ -79,19 +79,19 @@ __global__ __launch_bounds__(kThreads) void scan_apply_kernel(uint32_t *__restri
   for (int j = 0; j < kItems; ++j) {
     int li = j * kThreads + threadIdx.x;
     uint64_t idx = base + li;
-    tile[pad(li)] = (idx < n) ? data[idx] : 0u;
+    tile[pad(li)] = (idx < n) ? data[idx] : T(0);
   }
   __syncthreads();
-  uint32_t v[kItems];
-  uint32_t s = 0;
+  T v[kItems];
+  T s = 0;
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
     v[j] = tile[pad(threadIdx.x * kItems + j)];
     s += v[j];
   }
-  uint32_t total;
-  uint32_t run = block_exclusive_scan(s, wsum, total);
-  const uint32_t off = partial ? partial[blockIdx.x] : 0u;
+  T total;
+  T run = block_exclusive_scan(s, wsum, total);
+  const T off = partial ? partial[blockIdx.x] : T(0);
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
     tile[pad(threadIdx.x * kItems + j)] = run + off;
@@ -188,44 +188,55 @@ __global__ __launch_bounds__(kThreads) void rs_scatter_kernel(
   }
 }
 
-__global__ void set_zero_kernel(uint32_t *p) { *p = 0u; }
+template <typename T>
+__global__ void set_zero_kernel(T *p) { *p = T(0); }
 
 }  // namespace
 
 uint64_t scan_scratch_words(uint64_t n) {
+  // in units of 64-bit words, enough for both element widths
   uint64_t words = 0;
   uint64_t m = n;
   while (m > uint64_t(kTile)) {
     uint64_t tiles = (m + kTile - 1) / kTile;
-    words += align_up((tiles + 1) * sizeof(uint32_t)) / sizeof(uint32_t);
+    words += align_up((tiles + 1) * sizeof(uint64_t)) / sizeof(uint32_t);
     m = tiles;
   }
   return words + 64;
 }
 
-int exclusive_scan_u32(uint32_t *data, uint64_t n, uint32_t *scratch, hipStream_t s) {
+template <typename T>
+static int exclusive_scan(T *data, uint64_t n, T *scratch, hipStream_t s) {
   if (n == 0) {
     // total of an empty array (a kernel, not a memset node, so the call can be captured)
-    set_zero_kernel<<<1, 1, 0, s>>>(data);
+    set_zero_kernel<T><<<1, 1, 0, s>>>(data);
     FGS_LAUNCH_CHECK("set_zero_kernel");
     return FGS_OK;
   }
   const uint64_t tiles = (n + kTile - 1) / kTile;
   if (tiles == 1) {
-    scan_apply_kernel<<<1, kThreads, 0, s>>>(data, n, nullptr, 1);
+    scan_apply_kernel<T><<<1, kThreads, 0, s>>>(data, n, nullptr, 1);
     FGS_LAUNCH_CHECK("scan_apply_kernel");
     return FGS_OK;
   }
   if (tiles > 0xffffffffull) return fail(FGS_E_UNSUPPORTED, "scan: too many elements");
-  uint32_t *partial = scratch;
-  uint32_t *rest = scratch + align_up((tiles + 1) * sizeof(uint32_t)) / sizeof(uint32_t);
-  scan_reduce_kernel<<<unsigned(tiles), kThreads, 0, s>>>(data, n, partial);
+  T *partial = scratch;
+  T *rest = scratch + align_up((tiles + 1) * sizeof(T)) / sizeof(T);
+  scan_reduce_kernel<T><<<unsigned(tiles), kThreads, 0, s>>>(data, n, partial);
   FGS_LAUNCH_CHECK("scan_reduce_kernel");
-  int st = exclusive_scan_u32(partial, tiles, rest, s);
+  int st = exclusive_scan<T>(partial, tiles, rest, s);
   if (st != FGS_OK) return st;
-  scan_apply_kernel<<<unsigned(tiles), kThreads, 0, s>>>(data, n, partial, unsigned(tiles));
+  scan_apply_kernel<T><<<unsigned(tiles), kThreads, 0, s>>>(data, n, partial, unsigned(tiles));
   FGS_LAUNCH_CHECK("scan_apply_kernel");
   return FGS_OK;
+}
+
+int exclusive_scan_u32(uint32_t *data, uint64_t n, uint32_t *scratch, hipStream_t s) {
+  return exclusive_scan<uint32_t>(data, n, scratch, s);
+}
+
+int exclusive_scan_u64(uint64_t *data, uint64_t n, uint32_t *scratch, hipStream_t s) {
+  return exclusive_scan<uint64_t>(data, n, reinterpret_cast<uint64_t *>(scratch), s);
 }
 
 uint64_t sort_scratch_words(uint64_t n) {

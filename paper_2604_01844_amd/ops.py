@@ -304,6 +304,42 @@ def phantom_voxelize(ph: dict, grid: Grid, out=None):
     return out
 
 
+# ------------------------------------------------------------------ initialisation (Sec. 3.1)
+
+def fdk(img, geom: Geometry, grid: Grid, view_begin: int = 0, view_count: int | None = None,
+        ws: Workspace | None = None, out=None):
+    """FDK reconstruction of cone-beam projections img[V][H][W] on `grid`."""
+    L = A.lib()
+    vc = geom.n_views - view_begin if view_count is None else view_count
+    ws = ws or Workspace(img.device)
+    if out is None:
+        out = torch.empty(grid.shape, dtype=torch.float32, device=img.device)
+    gm = geom.struct()
+    gd = grid.struct()
+    ws.call(L.fgs_fdk, A.ptr(img.contiguous()), ctypes.byref(gm), view_begin, vc, ctypes.byref(gd), A.ptr(out))
+    return out
+
+
+def gradient_init(vol, grid: Grid, uniforms, *, background_fraction: float = 0.05, density_scale: float = 0.15,
+                  min_scale: float = 1e-4, ws: Workspace | None = None):
+    """FDK-gradient sampling initialisation: returns (mean, log_scale, quat,
+    density) of n = uniforms.shape[1] Gaussians; uniforms is a float64 GPU
+    tensor [4][n] of U[0, 1) variates."""
+    L = A.lib()
+    if uniforms.dtype != torch.float64 or uniforms.dim() != 2 or uniforms.shape[0] != 4:
+        raise ValueError("uniforms must be float64 [4][n]")
+    n = uniforms.shape[1]
+    dev = vol.device
+    outs = (torch.empty((3, n), device=dev), torch.empty((3, n), device=dev), torch.empty((4, n), device=dev),
+            torch.empty(n, device=dev))
+    o = A.fgs_gaussian_grads(*(A.ptr(t) for t in outs))
+    ws = ws or Workspace(dev)
+    gd = grid.struct()
+    ws.call(L.fgs_gradient_init, A.ptr(vol.contiguous()), ctypes.byref(gd), float(background_fraction),
+            float(density_scale), float(min_scale), n, A.ptr(uniforms.contiguous()), ctypes.byref(o))
+    return outs
+
+
 # ------------------------------------------------------------------ introspection
 
 def binning_dump(ws: Workspace) -> dict:

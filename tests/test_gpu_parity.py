@@ -408,3 +408,42 @@ def test_full_size_voxelize_gradients_sampled(fgs, scan_case):
     ref = oracle.voxelize_bwd(gs, gr, c, sel=sel, band=BAND)
     errs = grads_rel(g, ref, sel)
     assert max(errs.values()) < TOL, errs
+
+
+# ------------------------------------------------------------------ initialisation (Sec. 3.1)
+
+def test_fdk_matches_oracle(fgs):
+    ph = si.phantom(10, 100)
+    gd = si.geometry(96)
+    ang = si.angles(24)
+    img = oracle.phantom_project(ph, gd, ang).astype(np.float32)
+    gr = dict(origin=(-0.5, -0.45, -0.4), spacing=(1 / 40, 0.9 / 36, 0.8 / 33), dims=(40, 36, 33))
+    vol = fgs.fdk(torch.from_numpy(img).to(DEV), fgs.Geometry.from_dict(gd, ang), fgs.Grid.from_dict(gr))
+    ref = oracle.fdk(img, gd, ang, gr)
+    assert rel(vol.cpu().numpy(), ref) < TOL
+
+
+def test_gradient_init_matches_oracle(fgs):
+    """Same FP32 volume and the same uniforms: identical voxel choices (the
+    integer decision), means, densities and nearest-neighbour scales."""
+    ph = si.phantom(12, 105)
+    gr = si.grid(40)
+    vol = oracle.phantom_volume(ph, gr).astype(np.float32)
+    vol += 0.02 * si.normals(vol.shape, 106)  # FDK-like noise
+    n = 3000
+    u = np.random.Generator(np.random.PCG64(107)).random((4, n))
+    ref = oracle.gradient_init(vol, gr, u)
+    out = fgs.gradient_init(torch.from_numpy(vol).to(DEV), fgs.Grid.from_dict(gr), torch.from_numpy(u).to(DEV))
+    mean, ls, quat, dens = (t.cpu().numpy().astype(np.float64) for t in out)
+    h = np.array(gr["spacing"])
+    o = np.array(gr["origin"])
+    vox = np.floor((mean.T - o) / h).astype(np.int64)
+    nx, ny, nz = gr["dims"]
+    k = vox[:, 0] + nx * (vox[:, 1] + ny * vox[:, 2])
+    # the voxel follows from the mean unless the in-voxel offset is within FP32 rounding of an edge
+    clear = np.all((u[1:] > 1e-5) & (u[1:] < 1 - 1e-5), axis=0)
+    np.testing.assert_array_equal(k[clear], ref["voxel"][clear])
+    np.testing.assert_allclose(mean, ref["mean"], rtol=0, atol=1e-6)
+    assert rel(dens, ref["density"]) < TOL
+    assert rel(ls, ref["log_scale"]) < TOL
+    np.testing.assert_array_equal(quat, ref["quat"])

@@ -485,3 +485,81 @@ def test_gradient_band_brackets_cutoff_perturbations():
         plain = oracle.voxelize_bwd(gs, gr, cv, kappa=kap)
         for k, e in oracle.banded_grad_error(plain, vcore).items():
             assert e < 1e-12, (kap, k, e)
+
+
+# --------------------------------------------------------------- initialisation (Sec. 3.1)
+
+def test_fdk_reconstructs_uniform_sphere_and_ellipsoid():
+    """FDK of the exact projections of a uniform body returns its density in
+    the interior (within the discretisation error of 75 views of 128^2)."""
+    for semi, quat, amp in (((0.2, 0.2, 0.2), (1.0, 0, 0, 0), 1.0), ((0.22, 0.15, 0.18), (0.8, 0.3, -0.2, 0.4), 0.6)):
+        ph = dict(centre=np.array([[0.05, -0.03, 0.02]]), semi=np.array([semi]), quat=np.array([quat]),
+                  amp=np.array([amp]))
+        gd = si.geometry(128)
+        ang = si.angles(75)
+        img = oracle.phantom_project(ph, gd, ang)
+        gr = dict(origin=(-0.07, -0.15, -0.10), spacing=(0.01, 0.01, 0.01), dims=(24, 24, 24))
+        vol = oracle.fdk(img.astype(np.float32), gd, ang, gr).reshape(-1)
+        x = oracle.initialisation._centres(gr)
+        q = np.array(quat) / np.linalg.norm(quat)
+        R = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()
+        y = (x - ph["centre"][0]) @ R / np.array(semi)
+        inner = np.sum(y * y, axis=1) < 0.55 ** 2
+        assert inner.sum() > 200
+        assert np.all(np.abs(vol[inner] / amp - 1.0) < 0.03)
+        assert abs(vol[inner].mean() / amp - 1.0) < 0.01
+
+
+def test_gradient_sampling_hand_case():
+    """A 4-voxel row [0, 1, 1, 0]: central differences 0.5, 0.5, -0.5, -0.5,
+    equal weights 2^24 each; draws land in quarter intervals of u."""
+    vol = np.zeros((1, 1, 4), dtype=np.float32)
+    vol[0, 0, 1:3] = 1.0
+    w = oracle.sampling_weights(vol)
+    assert w.reshape(-1).tolist() == [1 << 24] * 4
+    grid = dict(origin=(0.0, 0.0, 0.0), spacing=(1.0, 1.0, 1.0), dims=(4, 1, 1))
+    u = np.array([[0.0, 0.24, 0.26, 0.99], [0.5] * 4, [0.5] * 4, [0.5] * 4])
+    out = oracle.gradient_init(vol, grid, u)
+    assert out["voxel"].tolist() == [0, 0, 1, 3]
+    np.testing.assert_allclose(out["mean"][0], [0.5, 0.5, 1.5, 3.5])
+    # density = 0.15 * value at the voxel centre (jitter 1/2 puts the mean there)
+    np.testing.assert_allclose(out["density"], 0.15 * np.array([0.0, 0.0, 1.0, 0.0]))
+    assert np.all(out["quat"][0] == 1) and np.all(out["quat"][1:] == 0)
+
+
+def test_gradient_sampling_background_threshold_and_frequencies():
+    """Voxels below 5% of the maximum do not contribute; draws follow the
+    integer weights (chi-square test against the exact multinomial law)."""
+    rng = np.random.default_rng(3)
+    vol = rng.uniform(0.0, 1.0, size=(6, 7, 8)).astype(np.float32)
+    vol[vol < 0.2] = 0.01  # below 5% of the max after thresholding -> zero
+    w = oracle.sampling_weights(vol).reshape(-1).astype(np.float64)
+    p = w / w.sum()
+    n = 200000
+    u = rng.random((4, n))
+    grid = dict(origin=(0.0, 0.0, 0.0), spacing=(1.0, 1.0, 1.0), dims=(8, 7, 6))
+    k = oracle.gradient_init(vol, grid, u)["voxel"]
+    counts = np.bincount(k, minlength=w.size)
+    assert np.all(counts[w == 0] == 0)
+    nz = p > 0
+    chi2 = np.sum((counts[nz] - n * p[nz]) ** 2 / (n * p[nz]))
+    dof = nz.sum() - 1
+    assert chi2 < dof + 6 * math.sqrt(2 * dof)
+
+
+def test_trilinear_is_exact_on_linear_fields_and_nn_scale_is_brute_force():
+    nz, ny, nx = 5, 6, 7
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    vol = 0.3 + 0.1 * x - 0.05 * y + 0.02 * z
+    c = np.random.default_rng(0).uniform(0, 4, size=(100, 3))
+    np.testing.assert_allclose(oracle.trilinear(vol, c), 0.3 + 0.1 * c[:, 0] - 0.05 * c[:, 1] + 0.02 * c[:, 2],
+                               rtol=1e-12)
+    vol32 = np.ones((6, 6, 6), dtype=np.float32)
+    vol32[2:4, 2:4, 2:4] = 2.0
+    grid = dict(origin=(-0.3, -0.3, -0.3), spacing=(0.1, 0.1, 0.1), dims=(6, 6, 6))
+    u = np.random.default_rng(1).random((4, 300))
+    out = oracle.gradient_init(vol32, grid, u)
+    m = out["mean"].T
+    d = np.sqrt(((m[:, None, :] - m[None, :, :]) ** 2).sum(-1))
+    np.fill_diagonal(d, np.inf)
+    np.testing.assert_allclose(out["log_scale"][0], np.log(np.maximum(d.min(1), 1e-4)), rtol=1e-12)
