@@ -280,6 +280,76 @@ int fgs_gradient_init(const float *vol, const fgs_grid *grid, float background_f
                       fgs_gaussians_out *out, fgs_workspace *ws, void *stream);
 
 /* ---------------------------------------------------------------------
+ * Learned initializer: an MLP (544 -> 128 -> 128 -> 32, 8 outputs used)
+ * mapping an FDK patch and position to a Gaussian's density, log-scales and
+ * rotation, in BF16 with FP32 accumulation on the matrix cores. BF16 values
+ * are stored as uint16_t bit patterns (round to nearest even). Matrices are
+ * row-major; "t" buffers hold the transpose (batch index contiguous), which
+ * the weight-gradient products read. `rows` is the batch padded to a
+ * multiple of 32; padded rows must carry zero features (the gather writes
+ * them) and get zero gradient (the heads write it).
+ * ------------------------------------------------------------------- */
+typedef struct {
+  int32_t k_in, hidden, n_out;          /* must be 544, 128, 32 */
+  const uint16_t *w1, *w1t;             /* bf16 [128][544] and [544][128] */
+  const uint16_t *w2, *w2t;             /* bf16 [128][128] and transpose */
+  const uint16_t *w3, *w3t;             /* bf16 [32][128] and [128][32] */
+  const float *b1, *b2, *b3;            /* [128], [128], [32] */
+} fgs_mlp;
+
+typedef struct {
+  float *z1, *z2, *z3;                  /* pre-activations [rows][128], [rows][128], [rows][32] */
+  uint16_t *h1, *h1t, *h2, *h2t;        /* bf16 ReLU activations [rows][128] and transposes
+                                           (transposes may be NULL when no backward follows) */
+} fgs_mlp_acts;
+
+typedef struct {
+  float *dw1, *db1, *dw2, *db2, *dw3, *db3;  /* same shapes as the FP32 weights; overwritten */
+} fgs_mlp_grads;
+
+/* Features of n Gaussians for the MLP: an 8^3 patch of vol[nz][ny][nx] on
+ * `grid`, trilinear samples one voxel apart centred on the mean (zero
+ * outside), times inv_norm; then 2 * mean (x, y, z); zeros to 544. Writes
+ * x[rows][544] and, if xt != NULL, xt[544][rows] (bf16). mean is [3][n]. */
+int fgs_gather_patches(const float *vol, const fgs_grid *grid, float inv_norm, const float *mean, int64_t n,
+                       int32_t rows, uint16_t *x, uint16_t *xt, void *stream);
+
+/* bf16 copies w_b[n_out][k_in] and (if w_bt != NULL) w_bt[k_in][n_out] of
+ * FP32 weights w[n_out][k_in]. */
+int fgs_mlp_pack(const float *w, int32_t n_out, int32_t k_in, uint16_t *w_b, uint16_t *w_bt, void *stream);
+
+/* Forward of the three layers for x[rows][544]: z = x w^T + b, ReLU on the
+ * two hidden layers, activations rounded to bf16 between layers. */
+int fgs_mlp_fwd(const fgs_mlp *net, const uint16_t *x, int32_t rows, fgs_mlp_acts *acts, void *stream);
+
+/* Prediction heads and loss on z3 (the first n of `rows` rows):
+ * density = softplus(z0), log-scales z1..z3, rotation (z4..z7)/|.|.
+ * If params_out != NULL it receives [8][n] (density, 3 log-scales, 4
+ * quaternion). If target != NULL ([n][8]: density, log-scales sorted in
+ * descending order, unit quaternion with w >= 0) the mean over n of
+ * (rho - rho_t)^2 + |s - s_t|^2 + (1 - (q . q_t)^2) goes to loss[0] and its
+ * gradient with respect to z3 to dz3[rows][32] and dz3t[32][rows] (bf16,
+ * zero on padded rows and unused columns). Workspace: ceil(rows/256)
+ * doubles. */
+int fgs_mlp_heads(const float *z3, int32_t rows, int64_t n, const float *target, float *params_out,
+                  uint16_t *dz3, uint16_t *dz3t, float *loss, fgs_workspace *ws, void *stream);
+
+/* Backward of fgs_mlp_fwd: weight and bias gradients (FP32) from the bf16
+ * output gradient dz3 (and its transpose), the transposed input xt and the
+ * forward's activations. Workspace: 4 * rows * 128 bf16. */
+int fgs_mlp_bwd(const fgs_mlp *net, const uint16_t *xt, int32_t rows, const fgs_mlp_acts *acts,
+                const uint16_t *dz3, const uint16_t *dz3t, fgs_mlp_grads *grads, fgs_workspace *ws,
+                void *stream);
+
+/* Training targets [n][8] (device, overwritten) from fitted Gaussians:
+ * density, log-scales in descending order, and the unit quaternion (w >= 0)
+ * of the rotation whose columns are permuted to that order (the third
+ * negated if needed to keep it proper). (s, R) and (P s, R P^T) describe the
+ * same covariance and q, -q the same rotation, so this is the canonical
+ * representative the loss compares with. */
+int fgs_canonical_targets(const fgs_gaussians *g, float *out, void *stream);
+
+/* ---------------------------------------------------------------------
  * Introspection (tests): where the last binning of a workspace lives.
  * Pure host arithmetic on the workspace's out fields. After
  * fgs_project_views_fwd / fgs_voxelize_fwd the workspace holds, at the byte

@@ -32,6 +32,10 @@ Parity status of each function (what pins it in ``tests/test_oracle_pins.py``):
 * ``initialisation.gradient_init``: pinned by hand-computed draws, sampling
   frequencies against the exact multinomial law, trilinear exactness on
   linear fields and brute-force nearest neighbours.
+* ``mlp`` (learned initializer): BF16 rounding pinned against torch's
+  bfloat16 conversion, the backward against finite differences of the
+  unrounded network, the canonical targets against their defining
+  invariances.
 """
 from __future__ import annotations
 
@@ -401,6 +405,7 @@ def psnr(vol, gt):
 
 
 from .initialisation import fdk, gradient_init, sampling_weights, trilinear  # noqa: E402,F401
+from . import mlp  # noqa: E402,F401
 
 
 def rel_l2(a, b) -> float:

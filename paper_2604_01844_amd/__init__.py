@@ -9,3 +9,5 @@ from .ops import (  # noqa: F401
     binning_dump, project_views_support, voxelize_support, timing_events, fdk, gradient_init, KAPPA, NEAR,
 )
 from ._abi import lib, LIB_PATH, FgsError  # noqa: F401
+from .mlp import InitMLP, canonical_targets  # noqa: F401,E402
+from . import recon  # noqa: F401,E402

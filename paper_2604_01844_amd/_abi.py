@@ -61,6 +61,20 @@ class fgs_phantom(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("centre", _vp), ("semi", _vp), ("quat", _vp), ("amp", _vp)]
 
 
+class fgs_mlp(ctypes.Structure):
+    _fields_ = [("k_in", ctypes.c_int32), ("hidden", ctypes.c_int32), ("n_out", ctypes.c_int32),
+                ("w1", _vp), ("w1t", _vp), ("w2", _vp), ("w2t", _vp), ("w3", _vp), ("w3t", _vp),
+                ("b1", _vp), ("b2", _vp), ("b3", _vp)]
+
+
+class fgs_mlp_acts(ctypes.Structure):
+    _fields_ = [("z1", _vp), ("z2", _vp), ("z3", _vp), ("h1", _vp), ("h1t", _vp), ("h2", _vp), ("h2t", _vp)]
+
+
+class fgs_mlp_grads(ctypes.Structure):
+    _fields_ = [("dw1", _vp), ("db1", _vp), ("dw2", _vp), ("db2", _vp), ("dw3", _vp), ("db3", _vp)]
+
+
 P = ctypes.POINTER
 # (name, argtypes) of every symbol declared in include/factgs.h
 SIGNATURES = {
@@ -84,6 +98,13 @@ SIGNATURES = {
     "fgs_fdk": [_vp, P(fgs_geom), ctypes.c_int32, ctypes.c_int32, P(fgs_grid), _vp, P(fgs_workspace), _vp],
     "fgs_gradient_init": [_vp, P(fgs_grid), ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_int64, _vp,
                           P(fgs_gaussian_grads), P(fgs_workspace), _vp],
+    "fgs_gather_patches": [_vp, P(fgs_grid), ctypes.c_float, _vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp, _vp],
+    "fgs_mlp_pack": [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp],
+    "fgs_mlp_fwd": [P(fgs_mlp), _vp, ctypes.c_int32, P(fgs_mlp_acts), _vp],
+    "fgs_mlp_heads": [_vp, ctypes.c_int32, ctypes.c_int64, _vp, _vp, _vp, _vp, _vp, P(fgs_workspace), _vp],
+    "fgs_mlp_bwd": [P(fgs_mlp), _vp, ctypes.c_int32, P(fgs_mlp_acts), _vp, _vp, P(fgs_mlp_grads),
+                    P(fgs_workspace), _vp],
+    "fgs_canonical_targets": [P(fgs_gaussians), _vp, _vp],
     "fgs_last_error": [],
     "fgs_version": [],
 }

@@ -563,3 +563,151 @@ def test_trilinear_is_exact_on_linear_fields_and_nn_scale_is_brute_force():
     d = np.sqrt(((m[:, None, :] - m[None, :, :]) ** 2).sum(-1))
     np.fill_diagonal(d, np.inf)
     np.testing.assert_allclose(out["log_scale"][0], np.log(np.maximum(d.min(1), 1e-4)), rtol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Learned initializer (MLP oracle)
+
+def test_bf16_rounding_matches_torch():
+    import torch
+    rng = np.random.default_rng(7)
+    x = np.concatenate([rng.normal(0, 1, 4000), rng.normal(0, 1e-30, 100), rng.normal(0, 1e30, 100),
+                        np.array([0.0, -0.0, 1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, 1.0 + 2 ** -9,
+                                  1.0 + 3 * 2 ** -9, -1.0 - 2 ** -9, 65504.0])])
+    x = x.astype(np.float32)
+    ref = torch.from_numpy(x).to(torch.bfloat16).float().numpy().astype(np.float64)
+    np.testing.assert_array_equal(oracle.mlp.bf16_round(x), ref)
+    # ties go to even: 1 + 2^-8 is halfway between 1 and 1 + 2^-7
+    assert oracle.mlp.bf16_round(np.float32(1.0 + 2 ** -8)) == 1.0
+    assert oracle.mlp.bf16_round(np.float32(1.0 + 3 * 2 ** -8)) == 1.0 + 2 ** -6
+
+
+def _mlp_case(rng, n, k=544, h=128, o=32):
+    w = dict(w1=rng.normal(0, 0.06, (h, k)), b1=rng.normal(0, 0.1, h), w2=rng.normal(0, 0.12, (h, h)),
+             b2=rng.normal(0, 0.1, h), w3=rng.normal(0, 0.12, (o, h)), b3=rng.normal(0, 0.5, o))
+    x = rng.normal(0, 1, (n, k))
+    ls = rng.normal(-3, 0.5, (3, n))
+    q = rng.normal(0, 1, (4, n))
+    t = oracle.mlp.canonical_target(rng.uniform(0.1, 1, n), ls, q)
+    return w, x, t
+
+
+def _mlp_loss(x, w, t):
+    a = oracle.mlp.forward(x, w["w1"], w["b1"], w["w2"], w["b2"], w["w3"], w["b3"], round_between=False)
+    return oracle.mlp.heads(a["z3"], t)[1]
+
+
+def test_mlp_backward_matches_finite_differences():
+    rng = np.random.default_rng(11)
+    w, x, t = _mlp_case(rng, 24, k=40, h=16, o=32)
+    a = oracle.mlp.forward(x, w["w1"], w["b1"], w["w2"], w["b2"], w["w3"], w["b3"], round_between=False)
+    _, _, dz3 = oracle.mlp.heads(a["z3"], t)
+    g = oracle.mlp.backward(x, a, w["w2"], w["w3"], dz3, round_between=False)
+    eps = 1e-6
+    for name in ("w1", "b1", "w2", "b2", "w3", "b3"):
+        flat = w[name].reshape(-1)
+        for idx in rng.choice(flat.size, 6, replace=False):
+            old = flat[idx]
+            flat[idx] = old + eps
+            lp = _mlp_loss(x, w, t)
+            flat[idx] = old - eps
+            lm = _mlp_loss(x, w, t)
+            flat[idx] = old
+            fd = (lp - lm) / (2 * eps)
+            an = g["d" + name].reshape(-1)[idx]
+            assert abs(fd - an) <= 1e-6 * max(1.0, abs(fd)), (name, idx, fd, an)
+
+
+def test_mlp_heads_gradient_and_quaternion_sign_invariance():
+    rng = np.random.default_rng(12)
+    n = 30
+    z3 = rng.normal(0, 1, (n, 32))
+    _, _, t = _mlp_case(rng, n)
+    p, loss, g = oracle.mlp.heads(z3, t)
+    assert np.all(g[:, 8:] == 0)
+    eps = 1e-6
+    for i, j in [(0, 0), (1, 1), (2, 3), (3, 4), (4, 5), (5, 6), (6, 7), (7, 2)]:
+        zp = z3.copy(); zp[i, j] += eps
+        zm = z3.copy(); zm[i, j] -= eps
+        fd = (oracle.mlp.heads(zp, t)[1] - oracle.mlp.heads(zm, t)[1]) / (2 * eps)
+        assert abs(fd - g[i, j]) <= 1e-7, (i, j, fd, g[i, j])
+    # q and -q describe one rotation: predictions and targets of either sign give one loss
+    zf = z3.copy(); zf[:, 4:8] *= -1
+    tf = t.copy(); tf[:, 4:8] *= -1
+    assert oracle.mlp.heads(zf, t)[1] == pytest.approx(loss, abs=1e-14)
+    assert oracle.mlp.heads(z3, tf)[1] == pytest.approx(loss, abs=1e-14)
+    # the scale of the raw quaternion does not matter; softplus closed form
+    zs = z3.copy(); zs[:, 4:8] *= 3.7
+    assert oracle.mlp.heads(zs, t)[1] == pytest.approx(loss, abs=1e-13)
+    np.testing.assert_allclose(p[0], np.log1p(np.exp(z3[:, 0])), rtol=1e-14)
+    # a perfect prediction has zero loss and zero gradient
+    perfect = np.zeros((n, 32))
+    perfect[:, 0] = np.log(np.expm1(t[:, 0]))
+    perfect[:, 1:8] = t[:, 1:8] * np.r_[1, 1, 1, 2.5, 2.5, 2.5, 2.5]
+    _, l0, g0 = oracle.mlp.heads(perfect, t)
+    assert l0 == pytest.approx(0.0, abs=1e-14)
+    assert np.abs(g0).max() < 1e-14
+
+
+def test_canonical_target_defines_the_same_gaussian():
+    rng = np.random.default_rng(13)
+    n = 200
+    ls = rng.normal(-3, 0.5, (3, n))
+    ls[:, :5] = ls[0, :5]                     # fully tied scales
+    ls[1, 5:10] = ls[0, 5:10]                 # partly tied
+    q = rng.normal(0, 1, (4, n))
+    rho = rng.uniform(0.1, 1, n)
+    t = oracle.mlp.canonical_target(rho, ls, q)
+    np.testing.assert_array_equal(t[:, 0], rho)
+    assert np.all(np.diff(t[:, 1:4], axis=1) <= 0)
+    assert np.all(t[:, 4] >= 0)
+    np.testing.assert_allclose(np.linalg.norm(t[:, 4:8], axis=1), 1.0, atol=1e-13)
+    for i in range(n):
+        R0 = Rotation.from_quat(np.r_[q[1:, i], q[0, i]]).as_matrix()
+        S0 = R0 @ np.diag(np.exp(2 * ls[:, i])) @ R0.T
+        R1 = Rotation.from_quat(np.r_[t[i, 5:8], t[i, 4]]).as_matrix()
+        S1 = R1 @ np.diag(np.exp(2 * t[i, 1:4])) @ R1.T
+        np.testing.assert_allclose(S1, S0, rtol=1e-12, atol=1e-16)
+    # sorted input with w >= 0 is returned unchanged
+    ls_s = -np.sort(-ls, axis=0)
+    qn = q / np.linalg.norm(q, axis=0)
+    qn *= np.where(qn[0] < 0, -1.0, 1.0)
+    t2 = oracle.mlp.canonical_target(rho, ls_s, qn)
+    np.testing.assert_allclose(t2[:, 4:8], qn.T, atol=1e-12)
+    # a permutation (with a sign flip to stay proper) of distinct axes maps back to the same target
+    P = np.array([[0, 1, 0], [1, 0, 0], [0, 0, -1.0]])
+    for i in range(10, 30):
+        R0 = Rotation.from_quat(np.r_[qn[1:, i], qn[0, i]]).as_matrix()
+        Rp = R0 @ P.T
+        qp = Rotation.from_matrix(Rp).as_quat()
+        lp = (np.abs(P) @ ls_s[:, i])
+        t3 = oracle.mlp.canonical_target(rho[i:i + 1], lp[:, None], np.r_[qp[3], qp[:3]][:, None])
+        np.testing.assert_allclose(t3[0], t2[i], atol=1e-12)
+
+
+def test_patch_features_sample_a_linear_field_at_the_stated_offsets():
+    n = 32
+    g = si.grid(n)
+    o = np.asarray(g["origin"], dtype=np.float64)
+    h = np.asarray(g["spacing"], dtype=np.float64)
+    idx = np.stack(np.meshgrid(*(np.arange(n),) * 3, indexing="ij"), -1)  # [z][y][x] -> (z, y, x)
+    cz, cy, cx = (o[::-1] + (idx + 0.5) * h[::-1]).transpose(3, 0, 1, 2)
+    a = np.array([0.3, -1.1, 2.0])
+    vol = (a[0] * cx + a[1] * cy + a[2] * cz + 0.25).astype(np.float32)
+    rng = np.random.default_rng(14)
+    mean = rng.uniform(-0.5 + 5 * h[0], 0.5 - 5 * h[0], (3, 16))
+    f = oracle.mlp.patches(vol, g, mean, 2.0)
+    offs = np.stack(np.meshgrid(np.arange(8), np.arange(8), np.arange(8), indexing="ij"), -1).reshape(-1, 3)
+    for m in range(16):
+        for fi in rng.choice(512, 40, replace=False):
+            iz, iy, ix = offs[fi]
+            p = mean[:, m] + h * (np.array([ix, iy, iz]) - 3.5)
+            vol_lin = a @ p + 0.25
+            assert f[m, fi] == pytest.approx(2.0 * vol_lin, abs=2e-6)
+    np.testing.assert_allclose(f[:, 512:515], 2 * mean.T)
+    assert np.all(f[:, 515:] == 0)
+    # a patch that leaves the grid reads zeros outside it
+    corner = np.full((3, 1), -0.5 + 0.5 * h[0])
+    fc = oracle.mlp.patches(np.ones_like(vol), g, corner, 1.0)
+    np.testing.assert_allclose(fc[0, 0], 0.0)
+    np.testing.assert_allclose(fc[0, 511], 1.0)
