@@ -309,10 +309,15 @@ typedef struct {
 
 /* Features of n Gaussians for the MLP: an 8^3 patch of vol[nz][ny][nx] on
  * `grid`, trilinear samples one voxel apart centred on the mean (zero
- * outside), times inv_norm; then 2 * mean (x, y, z); zeros to 544. Writes
- * x[rows][544] and, if xt != NULL, xt[544][rows] (bf16). mean is [3][n]. */
-int fgs_gather_patches(const float *vol, const fgs_grid *grid, float inv_norm, const float *mean, int64_t n,
-                       int32_t rows, uint16_t *x, uint16_t *xt, void *stream);
+ * outside), times inv_norm (divided by norm_max[0] when norm_max, a device
+ * scalar such as fgs_reduce_max's output, is not NULL); then 2 * mean
+ * (x, y, z); then n_extra (0..29) per-sample values extra[n_extra][n]
+ * (device); zeros to 544. Writes x[rows][544] and, if xt != NULL,
+ * xt[544][rows] (bf16); rows >= n, a multiple of 32, rows past n are zero.
+ * mean is [3][n]. */
+int fgs_gather_patches(const float *vol, const fgs_grid *grid, float inv_norm, const float *norm_max,
+                       const float *mean, const float *extra, int32_t n_extra, int64_t n, int32_t rows,
+                       uint16_t *x, uint16_t *xt, void *stream);
 
 /* bf16 copies w_b[n_out][k_in] and (if w_bt != NULL) w_bt[k_in][n_out] of
  * FP32 weights w[n_out][k_in]. */
@@ -323,16 +328,20 @@ int fgs_mlp_pack(const float *w, int32_t n_out, int32_t k_in, uint16_t *w_b, uin
 int fgs_mlp_fwd(const fgs_mlp *net, const uint16_t *x, int32_t rows, fgs_mlp_acts *acts, void *stream);
 
 /* Prediction heads and loss on z3 (the first n of `rows` rows):
- * density = softplus(z0), log-scales z1..z3, rotation (z4..z7)/|.|.
- * If params_out != NULL it receives [8][n] (density, 3 log-scales, 4
- * quaternion). If target != NULL ([n][8]: density, log-scales sorted in
- * descending order, unit quaternion with w >= 0) the mean over n of
- * (rho - rho_t)^2 + |s - s_t|^2 + (1 - (q . q_t)^2) goes to loss[0] and its
- * gradient with respect to z3 to dz3[rows][32] and dz3t[32][rows] (bf16,
- * zero on padded rows and unused columns). Workspace: ceil(rows/256)
- * doubles. */
-int fgs_mlp_heads(const float *z3, int32_t rows, int64_t n, const float *target, float *params_out,
-                  uint16_t *dz3, uint16_t *dz3t, float *loss, fgs_workspace *ws, void *stream);
+ * density = softplus(z0), log-scales b + z1..z3 with b = base_log_scale[m]
+ * (device [n], or 0 when NULL: the network then predicts an offset from a
+ * per-sample base such as the nearest-neighbour scale), rotation
+ * (z4..z7)/|.|. If params_out != NULL it receives [8][n] (density, 3
+ * log-scales, 4 quaternion). If target != NULL ([n][8]: density, log-scales
+ * sorted in descending order, unit quaternion with w >= 0) the mean over n
+ * of (rho - rho_t)^2 + live * (|s - s_t|^2 + (1 - (q . q_t)^2)), with
+ * live = [rho_t > 1e-3] (a fitted Gaussian of no density has no meaningful
+ * shape), goes to loss[0] and its gradient with respect to z3 to
+ * dz3[rows][32] and dz3t[32][rows] (bf16, zero on padded rows and unused
+ * columns). Workspace: ceil(rows/256) doubles. */
+int fgs_mlp_heads(const float *z3, int32_t rows, int64_t n, const float *base_log_scale, const float *target,
+                  float *params_out, uint16_t *dz3, uint16_t *dz3t, float *loss, fgs_workspace *ws,
+                  void *stream);
 
 /* Backward of fgs_mlp_fwd: weight and bias gradients (FP32) from the bf16
  * output gradient dz3 (and its transpose), the transposed input xt and the
@@ -348,6 +357,11 @@ int fgs_mlp_bwd(const fgs_mlp *net, const uint16_t *xt, int32_t rows, const fgs_
  * same covariance and q, -q the same rotation, so this is the canonical
  * representative the loss compares with. */
 int fgs_canonical_targets(const fgs_gaussians *g, float *out, void *stream);
+
+/* out[0] (device) = max of x[0..n) (FP32; the normaliser of the MLP's
+ * patch features, Sec. 3.1 init from an FDK volume). Needs 4 KiB of
+ * workspace. */
+int fgs_reduce_max(const float *x, int64_t n, float *out, fgs_workspace *ws, void *stream);
 
 /* ---------------------------------------------------------------------
  * Introspection (tests): where the last binning of a workspace lives.

@@ -1,11 +1,14 @@
 """FP64 oracle of the learned initializer's MLP. TEST INFRASTRUCTURE ONLY.
 
 The network is 544 -> 128 (ReLU) -> 128 (ReLU) -> 32, of which 8 outputs are
-used: softplus density, three log-scales, and a quaternion normalised to unit
-length. Operands are BF16 (round to nearest even from FP32); products and
-sums are taken in FP64 here; activations and the output gradient are rounded
-to BF16 between layers, as the kernels store them. The loss per sample is
-(rho - rho_t)^2 + |s - s_t|^2 + (1 - (q . q_t)^2), averaged over samples.
+used: softplus density, three log-scales (optionally offsets from a given
+per-sample base), and a quaternion normalised to unit length. Operands are
+BF16 (round to nearest even from FP32); products and sums are taken in FP64
+here; activations and the output gradient are rounded to BF16 between
+layers, as the kernels store them. The loss per sample is
+(rho - rho_t)^2 + live * (|s - s_t|^2 + (1 - (q . q_t)^2)), live =
+[rho_t > 1e-3] (a fitted Gaussian without density has no meaningful shape),
+averaged over samples.
 """
 from __future__ import annotations
 
@@ -31,27 +34,33 @@ def forward(x, w1, b1, w2, b2, w3, b3, round_between=True):
     return dict(z1=z1, h1=h1, z2=z2, h2=h2, z3=z3)
 
 
-def heads(z3, target=None):
+LIVE_DENSITY = 1e-3
+
+
+def heads(z3, target=None, base_log_scale=None):
     """Predicted parameters [8][n] and, with a target [n][8], the mean loss and
     its gradient with respect to z3 (columns beyond 8 get zero)."""
     y = np.asarray(z3, dtype=np.float64)
     n = y.shape[0]
     rho = np.logaddexp(0.0, y[:, 0])
+    base = np.zeros(n) if base_log_scale is None else np.asarray(base_log_scale, dtype=np.float64)
+    ls = base[:, None] + y[:, 1:4]
     q = y[:, 4:8]
     qn = np.maximum(np.linalg.norm(q, axis=1), 1e-12)
     qh = q / qn[:, None]
-    params = np.concatenate([rho[None], y[:, 1:4].T, qh.T], axis=0)
+    params = np.concatenate([rho[None], ls.T, qh.T], axis=0)
     if target is None:
         return params, None, None
     t = np.asarray(target, dtype=np.float64)
+    live = (t[:, 0] > LIVE_DENSITY).astype(np.float64)
     dot = np.sum(qh * t[:, 4:8], axis=1)
-    loss = np.mean((rho - t[:, 0]) ** 2 + np.sum((y[:, 1:4] - t[:, 1:4]) ** 2, axis=1) + (1.0 - dot ** 2))
+    loss = np.mean((rho - t[:, 0]) ** 2 + live * (np.sum((ls - t[:, 1:4]) ** 2, axis=1) + (1.0 - dot ** 2)))
     g = np.zeros_like(y)
     g[:, 0] = 2.0 * (rho - t[:, 0]) / (1.0 + np.exp(-y[:, 0])) / n
-    g[:, 1:4] = 2.0 * (y[:, 1:4] - t[:, 1:4]) / n
+    g[:, 1:4] = live[:, None] * 2.0 * (ls - t[:, 1:4]) / n
     gh = -2.0 * dot[:, None] * t[:, 4:8]
     proj = np.sum(gh * qh, axis=1)
-    g[:, 4:8] = (gh - qh * proj[:, None]) / qn[:, None] / n
+    g[:, 4:8] = live[:, None] * (gh - qh * proj[:, None]) / qn[:, None] / n
     return params, loss, g
 
 
@@ -70,9 +79,10 @@ def backward(x, acts, w2, w3, dz3, round_between=True):
     return dict(dw1=dw1, db1=db1, dw2=dw2, db2=db2, dw3=dw3, db3=db3)
 
 
-def patches(vol32, grid: dict, mean, inv_norm: float) -> np.ndarray:
+def patches(vol32, grid: dict, mean, inv_norm: float, extra=None) -> np.ndarray:
     """Features [n][544]: 8^3 trilinear samples one voxel apart centred on each
-    mean (zero outside), times inv_norm; then 2 * mean; zeros. FP64."""
+    mean (zero outside), times inv_norm; then 2 * mean; then the rows of
+    extra [k][n]; zeros. FP64."""
     from .initialisation import trilinear
     mean = np.asarray(mean, dtype=np.float64)
     n = mean.shape[1]
@@ -85,6 +95,9 @@ def patches(vol32, grid: dict, mean, inv_norm: float) -> np.ndarray:
     pts = (c[:, None, :] + offs[None, :, :]).reshape(-1, 3)
     feats[:, :512] = inv_norm * trilinear(vol32, pts).reshape(n, 512)
     feats[:, 512:515] = 2.0 * mean.T
+    if extra is not None:
+        e = np.asarray(extra, dtype=np.float64)
+        feats[:, 515:515 + e.shape[0]] = e.T
     return feats
 
 

@@ -98,10 +98,12 @@ SIGNATURES = {
     "fgs_fdk": [_vp, P(fgs_geom), ctypes.c_int32, ctypes.c_int32, P(fgs_grid), _vp, P(fgs_workspace), _vp],
     "fgs_gradient_init": [_vp, P(fgs_grid), ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_int64, _vp,
                           P(fgs_gaussian_grads), P(fgs_workspace), _vp],
-    "fgs_gather_patches": [_vp, P(fgs_grid), ctypes.c_float, _vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp, _vp],
+    "fgs_gather_patches": [_vp, P(fgs_grid), ctypes.c_float, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_int64,
+                           ctypes.c_int32, _vp, _vp, _vp],
+    "fgs_reduce_max": [_vp, ctypes.c_int64, _vp, P(fgs_workspace), _vp],
     "fgs_mlp_pack": [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp],
     "fgs_mlp_fwd": [P(fgs_mlp), _vp, ctypes.c_int32, P(fgs_mlp_acts), _vp],
-    "fgs_mlp_heads": [_vp, ctypes.c_int32, ctypes.c_int64, _vp, _vp, _vp, _vp, _vp, P(fgs_workspace), _vp],
+    "fgs_mlp_heads": [_vp, ctypes.c_int32, ctypes.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, P(fgs_workspace), _vp],
     "fgs_mlp_bwd": [P(fgs_mlp), _vp, ctypes.c_int32, P(fgs_mlp_acts), _vp, _vp, P(fgs_mlp_grads),
                     P(fgs_workspace), _vp],
     "fgs_canonical_targets": [P(fgs_gaussians), _vp, _vp],

@@ -382,3 +382,17 @@ extern "C" int fgs_gradient_init(const float *vol, const fgs_grid *grid, float b
   FGS_LAUNCH_CHECK("nn_scale_kernel");
   return FGS_OK;
 }
+
+extern "C" int fgs_reduce_max(const float *x, int64_t n, float *out, fgs_workspace *ws, void *stream) {
+  if (!x || !out || !ws || n <= 0) return fail(FGS_E_INVALID, "invalid argument");
+  ws->needed = uint64_t(kRedBlocks) * sizeof(float);
+  if (!ws->ptr || ws->bytes < ws->needed) return fail(FGS_E_CAPACITY, "workspace too small");
+  ws->kind = 0;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  float *part = static_cast<float *>(ws->ptr);
+  const int nb = int(std::min<uint64_t>(kRedBlocks, (uint64_t(n) + kRedThreads - 1) / kRedThreads));
+  max_partial_kernel<<<nb, kRedThreads, 0, s>>>(x, uint64_t(n), part);
+  max_final_kernel<<<1, kRedThreads, 0, s>>>(part, nb, out);
+  FGS_LAUNCH_CHECK("max_final_kernel");
+  return FGS_OK;
+}

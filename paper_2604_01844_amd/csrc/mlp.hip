@@ -214,10 +214,14 @@ __device__ __forceinline__ float trilinear_at(const float *__restrict__ vol, con
 }
 
 __global__ __launch_bounds__(256) void gather_kernel(const float *__restrict__ vol, PatchGrid G, float inv_norm,
-                                                     const float *__restrict__ mean, int64_t n, int rows,
-                                                     uint16_t *__restrict__ X, uint16_t *__restrict__ Xt) {
+                                                     const float *__restrict__ norm_max,
+                                                     const float *__restrict__ mean,
+                                                     const float *__restrict__ extra, int n_extra, int64_t n,
+                                                     int rows, uint16_t *__restrict__ X,
+                                                     uint16_t *__restrict__ Xt) {
   const int m = blockIdx.x;
   const bool valid = m < n;
+  if (norm_max) inv_norm = inv_norm / norm_max[0];
   float c[3] = {0.f, 0.f, 0.f}, p[3] = {0.f, 0.f, 0.f};
   if (valid)
     for (int a = 0; a < 3; ++a) {
@@ -233,6 +237,8 @@ __global__ __launch_bounds__(256) void gather_kernel(const float *__restrict__ v
                                     c[2] + float(iz) - 3.5f);
       } else if (f < kPatch * kPatch * kPatch + 3) {
         v = 2.f * p[f - kPatch * kPatch * kPatch];
+      } else if (f < kPatch * kPatch * kPatch + 3 + n_extra) {
+        v = extra[int64_t(f - kPatch * kPatch * kPatch - 3) * n + m];
       }
     }
     const uint16_t h = to_bf16(v);
@@ -241,10 +247,17 @@ __global__ __launch_bounds__(256) void gather_kernel(const float *__restrict__ v
   }
 }
 
+// A fitted Gaussian whose density is at most this carries no shape
+// information: its scale and rotation terms are left out of the loss.
+constexpr float kLiveDensity = 1e-3f;
+
 // Prediction heads and loss. y = Z3 row (8 used of ld): density = softplus(y0),
-// log-scales y1..y3, rotation = (y4..y7) / |.|. Training loss per sample
-// (rho - rho_t)^2 + |s - s_t|^2 + (1 - (q . q_t)^2), averaged over n.
+// log-scales base + y1..y3 (base = per-sample offset, or 0), rotation =
+// (y4..y7) / |.|. Training loss per sample (rho - rho_t)^2 + live *
+// (|s - s_t|^2 + (1 - (q . q_t)^2)), live = [rho_t > kLiveDensity],
+// averaged over n.
 __global__ __launch_bounds__(256) void heads_kernel(const float *__restrict__ Z3, int ld, int64_t n, int rows,
+                                                    const float *__restrict__ base_ls,
                                                     const float *__restrict__ target, float *__restrict__ out,
                                                     uint16_t *__restrict__ D, uint16_t *__restrict__ Dt,
                                                     double *__restrict__ partial) {
@@ -261,9 +274,12 @@ __global__ __launch_bounds__(256) void heads_kernel(const float *__restrict__ Z3
     const float qn = fmaxf(sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]), 1e-12f);
     float qh[4];
     for (int j = 0; j < 4; ++j) qh[j] = q[j] / qn;
+    const float base = base_ls ? base_ls[m] : 0.f;
+    float ls[3];
+    for (int j = 0; j < 3; ++j) ls[j] = base + y[1 + j];
     if (out) {
       out[m] = rho;
-      for (int j = 0; j < 3; ++j) out[(1 + j) * n + m] = y[1 + j];
+      for (int j = 0; j < 3; ++j) out[(1 + j) * n + m] = ls[j];
       for (int j = 0; j < 4; ++j) out[(4 + j) * n + m] = qh[j];
     }
     if (target) {
@@ -272,20 +288,22 @@ __global__ __launch_bounds__(256) void heads_kernel(const float *__restrict__ Z3
       const float dr = rho - t[0];
       float l = dr * dr;
       g[0] = 2.f * dr * sig * inv_n;
-      for (int j = 0; j < 3; ++j) {
-        const float ds = y[1 + j] - t[1 + j];
-        l += ds * ds;
-        g[1 + j] = 2.f * ds * inv_n;
+      if (t[0] > kLiveDensity) {
+        for (int j = 0; j < 3; ++j) {
+          const float ds = ls[j] - t[1 + j];
+          l += ds * ds;
+          g[1 + j] = 2.f * ds * inv_n;
+        }
+        const float dot = qh[0] * t[4] + qh[1] * t[5] + qh[2] * t[6] + qh[3] * t[7];
+        l += 1.f - dot * dot;
+        // d/dqh of -(qh . t)^2 = -2 dot t, projected through the normalisation
+        float gh[4], proj = 0.f;
+        for (int j = 0; j < 4; ++j) {
+          gh[j] = -2.f * dot * t[4 + j];
+          proj += gh[j] * qh[j];
+        }
+        for (int j = 0; j < 4; ++j) g[4 + j] = (gh[j] - qh[j] * proj) / qn * inv_n;
       }
-      const float dot = qh[0] * t[4] + qh[1] * t[5] + qh[2] * t[6] + qh[3] * t[7];
-      l += 1.f - dot * dot;
-      // d/dqh of -(qh . t)^2 = -2 dot t, projected through the normalisation
-      float gh[4], proj = 0.f;
-      for (int j = 0; j < 4; ++j) {
-        gh[j] = -2.f * dot * t[4 + j];
-        proj += gh[j] * qh[j];
-      }
-      for (int j = 0; j < 4; ++j) g[4 + j] = (gh[j] - qh[j] * proj) / qn * inv_n;
       lm = double(l);
     }
   }
@@ -329,9 +347,12 @@ int check_net(const fgs_mlp *net) {
 
 using namespace fgs;
 
-extern "C" int fgs_gather_patches(const float *vol, const fgs_grid *grid, float inv_norm, const float *mean,
-                                  int64_t n, int32_t rows, uint16_t *x, uint16_t *xt, void *stream) {
+extern "C" int fgs_gather_patches(const float *vol, const fgs_grid *grid, float inv_norm, const float *norm_max,
+                                  const float *mean, const float *extra, int32_t n_extra, int64_t n, int32_t rows,
+                                  uint16_t *x, uint16_t *xt, void *stream) {
   if (!vol || !grid || !mean || !x) return fail(FGS_E_INVALID, "null argument");
+  if (n_extra < 0 || n_extra > kFeat - kPatch * kPatch * kPatch - 3 || (n_extra > 0 && !extra))
+    return fail(FGS_E_INVALID, "extra features: 0..29 rows of n values");
   if (n <= 0 || rows < n || rows % 32) return fail(FGS_E_INVALID, "rows must be >= n and a multiple of 32");
   PatchGrid G{};
   for (int a = 0; a < 3; ++a) {
@@ -341,7 +362,8 @@ extern "C" int fgs_gather_patches(const float *vol, const fgs_grid *grid, float 
     G.dims[a] = grid->dims[a];
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
-  gather_kernel<<<unsigned(rows), 256, 0, s>>>(vol, G, inv_norm, mean, n, rows, x, xt);
+  gather_kernel<<<unsigned(rows), 256, 0, s>>>(vol, G, inv_norm, norm_max, mean, extra, n_extra, n, rows, x,
+                                                  xt);
   FGS_LAUNCH_CHECK("gather_kernel");
   return FGS_OK;
 }
@@ -373,7 +395,8 @@ extern "C" int fgs_mlp_fwd(const fgs_mlp *net, const uint16_t *x, int32_t rows, 
   return gemm_nt<kEpiFwd>(acts->h2, net->w3, rows, net->n_out, net->hidden, e, s);
 }
 
-extern "C" int fgs_mlp_heads(const float *z3, int32_t rows, int64_t n, const float *target, float *params_out,
+extern "C" int fgs_mlp_heads(const float *z3, int32_t rows, int64_t n, const float *base_log_scale,
+                             const float *target, float *params_out,
                              uint16_t *dz3, uint16_t *dz3t, float *loss, fgs_workspace *ws, void *stream) {
   if (!z3 || n <= 0 || rows < n || rows % 32) return fail(FGS_E_INVALID, "invalid sizes");
   if (target && (!dz3 || !dz3t || !loss || !ws || !ws->ptr)) return fail(FGS_E_INVALID, "training needs gradient, loss and workspace");
@@ -385,7 +408,8 @@ extern "C" int fgs_mlp_heads(const float *z3, int32_t rows, int64_t n, const flo
     if (ws->bytes < ws->needed) return fail(FGS_E_CAPACITY, "workspace too small");
     partial = static_cast<double *>(ws->ptr);
   }
-  heads_kernel<<<nb, 256, 0, s>>>(z3, 32, n, rows, target, params_out, target ? dz3 : nullptr, dz3t, partial);
+  heads_kernel<<<nb, 256, 0, s>>>(z3, 32, n, rows, base_log_scale, target, params_out, target ? dz3 : nullptr,
+                                  dz3t, partial);
   FGS_LAUNCH_CHECK("heads_kernel");
   if (target) {
     loss_final_kernel<<<1, 256, 0, s>>>(partial, nb, 1.0 / double(n), loss);

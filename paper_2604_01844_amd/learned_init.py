@@ -1,0 +1,286 @@
+"""Learned initializer: FDK-gradient sampling (Sec. 3.1) places the
+Gaussians; a small MLP maps the FDK patch around each position to its
+density, scales and rotation, in place of the fixed rules of Sec. 3.1
+(density 0.15 x FDK value, nearest-neighbour isotropic scale, identity
+rotation).
+
+* Training pairs: a random ellipsoid phantom -> its exact cone-beam
+  projections -> FDK on a 128^3 grid; Gaussians placed and sized by the
+  FDK-gradient rule of Sec. 3.1 on that volume, exactly as at inference,
+  then fitted to the phantom volume on the same grid by the voxelizer loop
+  of Sec. 3.6.
+* Training: one pair per step. Inputs, taken where each Gaussian was
+  placed: the FDK patch (normalised by the volume's maximum), the position,
+  and the nearest-neighbour log-scale of the placement rule, from which the
+  network predicts log-scale offsets. Targets: the canonical form of the
+  fitted density, scales and rotation. Adam on the FP32 master weights.
+* Inference: the same gradient sampling of the scan's FDK volume gives the
+  positions and nearest-neighbour scales, the network the rest.
+* Comparison: both initialisations from the same positions reconstruct the
+  same scan; seconds and epochs to a fixed PSNR, the PSNR before the first
+  step, and the iteration ratio of Eq. 7 (the fraction of the cold run's
+  epochs the warm run needs to reach the cold run's best PSNR).
+
+Every numerical step runs in libfactgs; this module orders the calls.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+import synth_inputs as si
+
+from . import ops, recon
+from .mlp import InitMLP, canonical_targets
+
+
+# PSNR levels (dB) at which both arms' seconds and epochs are also reported.
+LEVELS = (30.0, 35.0, 38.0)
+
+
+@dataclass
+class ScanConfig:
+    views: int = 75
+    det: int = 512
+    init_vol: int = 128     # FDK grid of the initialisation (and of the pairs)
+    eval_vol: int = 256     # grid of the reconstruction's PSNR
+    n_gauss: int = 50000
+    fit_iters: int = 200
+
+
+@dataclass
+class Pair:
+    seed: int
+    fdk: torch.Tensor
+    fdk_max: torch.Tensor   # device scalar
+    mean: torch.Tensor      # [3][n] placement (network input)
+    base: torch.Tensor      # [n] nearest-neighbour log-scale of the placement
+    target: torch.Tensor    # [n][8] canonical targets of the fitted Gaussians
+    fit_psnr: float
+
+
+class Scanner:
+    """Geometry, grids and workspaces of one scan configuration on a device."""
+
+    def __init__(self, cfg: ScanConfig, device="cuda"):
+        self.cfg = cfg
+        self.device = torch.device(device)
+        self.geom = ops.Geometry.from_dict(si.geometry(cfg.det), si.angles(cfg.views), self.device)
+        self.grid = ops.Grid.from_dict(si.grid(cfg.init_vol))
+        self.eval_grid = ops.Grid.from_dict(si.grid(cfg.eval_vol))
+        self.ws = ops.Workspace(self.device)
+        self.ws_small = ops.Workspace(self.device, 1 << 16)
+
+    def phantom(self, seed: int) -> dict:
+        return {k: torch.from_numpy(np.ascontiguousarray(v)).to(self.device)
+                for k, v in si.random_phantom(seed).items()}
+
+    def project(self, ph: dict):
+        return ops.phantom_project(ph, self.geom)
+
+    def fdk(self, proj):
+        vol = ops.fdk(proj, self.geom, self.grid, ws=self.ws)
+        return vol, ops.reduce_max(vol, ws=self.ws_small)
+
+    def uniforms(self, seed: int):
+        n = self.cfg.n_gauss
+        u = si.uniforms(4 * n, seed + 5_000_000).reshape(4, n)
+        return torch.from_numpy(u).to(self.device)
+
+
+def make_pair(sc: Scanner, seed: int, fit_adam: recon.AdamConfig = recon.FIT_ADAM) -> Pair:
+    """One training pair (FDK volume, fitted Gaussians) from phantom `seed`."""
+    ph = sc.phantom(seed)
+    vfdk, vmax = sc.fdk(sc.project(ph))
+    vgt = ops.phantom_voxelize(ph, sc.grid)
+    model = fdk_gradient_model(sc, vfdk, sc.uniforms(seed))
+    mean0, base = model.params[0].clone(), model.params[1][0].clone()
+    hist = recon.fit_volume(model, vgt, sc.grid, iters=sc.cfg.fit_iters, adam=fit_adam,
+                            eval_every=sc.cfg.fit_iters)
+    return Pair(seed, vfdk, vmax, mean0, base, canonical_targets(*model.params), hist.psnr[-1])
+
+
+def train(pairs: list, *, epochs: int, lr: float = 1e-3, seed: int = 0, net: InitMLP | None = None,
+          device="cuda", log=None):
+    """Train the MLP over `pairs` (one pair per step, a fresh pair order per
+    epoch). Returns (net, mean loss per epoch)."""
+    grid = ops.Grid.from_dict(si.grid(pairs[0].fdk.shape[-1]))
+    net = net or InitMLP(InitMLP.init_weights(seed), device)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    losses = []
+    for ep in range(epochs):
+        acc = torch.zeros(1, device=net.device)
+        for k in rng.permutation(len(pairs)):
+            p = pairs[k]
+            acc += net.train_step(p.fdk, grid, 1.0, p.mean, p.target, lr, norm_max=p.fdk_max, base_log_scale=p.base)
+        losses.append(float(acc.item()) / len(pairs))
+        if log:
+            log(f"epoch {ep + 1}: loss {losses[-1]:.4f}")
+    return net, losses
+
+
+def fdk_gradient_model(sc: Scanner, vfdk, uniforms) -> recon.GaussianModel:
+    """Sec. 3.1's initialisation from the FDK volume."""
+    return recon.init_from_volume(vfdk, sc.grid, sc.cfg.n_gauss, uniforms)
+
+
+def learned_model(sc: Scanner, net: InitMLP, vfdk, vmax, uniforms) -> recon.GaussianModel:
+    """Positions by the same gradient sampling; density, scales and rotation
+    from the network."""
+    mean, ls0, _, _ = ops.gradient_init(vfdk, sc.grid, uniforms, min_scale=0.25 * min(sc.grid.spacing), ws=sc.ws)
+    d, ls, q = net.predict(vfdk, sc.grid, 1.0, mean, norm_max=vmax, base_log_scale=ls0[0].contiguous())
+    return recon.GaussianModel(mean, ls, q, d)
+
+
+@dataclass
+class ArmResult:
+    init_s: float
+    history: recon.History
+    psnr0: float = field(init=False)
+
+    def __post_init__(self):
+        self.psnr0 = self.history.psnr[0]
+
+    def seconds_to(self, target: float):
+        return self.history.seconds_to(target)
+
+    def epochs_to(self, target: float):
+        for e, p in zip(self.history.epochs, self.history.psnr):
+            if p >= target:
+                return e
+        return None
+
+
+def run_arm(sc: Scanner, arm: str, seed: int, *, epochs: int, adam: recon.AdamConfig, net: InitMLP | None = None,
+            target_psnr: float | None = None, proj=None, vol_gt=None) -> ArmResult:
+    """Reconstruct phantom `seed` from its projections with one
+    initialisation; the clock covers FDK, the initialisation and the
+    optimisation (evaluation excluded)."""
+    if proj is None or vol_gt is None:
+        ph = sc.phantom(seed)
+        proj = sc.project(ph)
+        vol_gt = ops.phantom_voxelize(ph, sc.eval_grid)
+    u = sc.uniforms(seed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    vfdk, vmax = sc.fdk(proj)
+    model = fdk_gradient_model(sc, vfdk, u) if arm == "fdk_gradient" else learned_model(sc, net, vfdk, vmax, u)
+    torch.cuda.synchronize()
+    t_init = time.perf_counter() - t0
+    hist = recon.reconstruct(model, proj, sc.geom, epochs=epochs, adam=adam, vol_gt=vol_gt, eval_grid=sc.eval_grid,
+                             eval_every=1, target_psnr=target_psnr, seed=seed, t_offset=t_init, eval_at_start=True)
+    return ArmResult(t_init, hist)
+
+
+def calibrate_target(sc: Scanner, *, seeds=(1997, 1998, 1999), epochs: int = 100,
+                     adam: recon.AdamConfig) -> float:
+    """Fixed PSNR target: the lowest PSNR the FDK-gradient baseline reaches
+    after `epochs` on the calibration phantoms, rounded down to 0.1 dB (the
+    phantoms differ by a few dB, so one phantom's level is not reached by
+    others)."""
+    finals = [run_arm(sc, "fdk_gradient", s, epochs=epochs, adam=adam).history.psnr[-1] for s in seeds]
+    return math.floor(10.0 * min(finals)) / 10.0
+
+
+def iteration_ratio(cold: ArmResult, warm: ArmResult, n_iter: int):
+    """Eq. 7: epochs the warm run needs to reach the cold run's best PSNR,
+    as a fraction of the cold run's epochs (None if never reached)."""
+    best = max(cold.history.psnr)
+    e = warm.epochs_to(best)
+    return None if e is None else e / n_iter
+
+
+def compare(sc: Scanner, net: InitMLP, seeds, *, target_psnr: float, epochs: int, adam: recon.AdamConfig,
+            log=None) -> list:
+    """Both arms on each held-out phantom, run for `epochs` epochs."""
+    out = []
+    for seed in seeds:
+        ph = sc.phantom(seed)
+        proj = sc.project(ph)
+        vol_gt = ops.phantom_voxelize(ph, sc.eval_grid)
+        cold = run_arm(sc, "fdk_gradient", seed, epochs=epochs, adam=adam, proj=proj, vol_gt=vol_gt)
+        warm = run_arm(sc, "learned", seed, epochs=epochs, adam=adam, net=net, proj=proj, vol_gt=vol_gt)
+        row = dict(seed=seed)
+        for name, r in (("fdk_gradient", cold), ("learned", warm)):
+            row[name] = dict(init_s=r.init_s, psnr0=r.psnr0, psnr_final=r.history.psnr[-1],
+                             s_to_target=r.seconds_to(target_psnr), epochs_to_target=r.epochs_to(target_psnr))
+        row["tau_iter"] = iteration_ratio(cold, warm, epochs)
+        row["levels"] = {f"{lv:g}": {name: dict(s=r.seconds_to(lv), epochs=r.epochs_to(lv))
+                                     for name, r in (("fdk_gradient", cold), ("learned", warm))}
+                         for lv in LEVELS}
+        out.append(row)
+        if log:
+            log(f"phantom {seed}: {row}")
+    return out
+
+
+def initialise(sc: Scanner, vfdk, vmax, uniforms, net: InitMLP | None = None) -> recon.GaussianModel:
+    """The learned initialisation when a trained network is given, else the
+    FDK-gradient rule it falls back to."""
+    return fdk_gradient_model(sc, vfdk, uniforms) if net is None else learned_model(sc, net, vfdk, vmax, uniforms)
+
+
+def main(argv=None):
+    """Whole experiment: pairs, training, calibration, comparison. Progress
+    on stderr, one JSON summary on stdout."""
+    import argparse
+    import json
+    import sys
+
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--pairs", type=int, default=200)
+    ap.add_argument("--train-epochs", type=int, default=40)
+    ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--held-out", type=int, default=10)
+    ap.add_argument("--epochs", type=int, default=150)
+    ap.add_argument("--calibration-epochs", type=int, default=100)
+    a = ap.parse_args(argv)
+    log = lambda m: print(f"[learned-init] {m}", file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    sc = Scanner(ScanConfig(), dev)
+    adam = recon.AdamConfig(lr_density=2e-3)
+    t0 = time.perf_counter()
+    pairs = []
+    for k, seed in enumerate(range(1000, 1000 + a.pairs)):
+        pairs.append(make_pair(sc, seed))
+        if (k + 1) % 25 == 0:
+            log(f"{k + 1} pairs ({time.perf_counter() - t0:.1f} s)")
+    torch.cuda.synchronize()
+    t_pairs = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    net, losses = train(pairs, epochs=a.train_epochs, lr=a.lr, seed=0, device=dev, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    target = calibrate_target(sc, epochs=a.calibration_epochs, adam=adam)
+    log(f"target PSNR {target} dB")
+    rows = compare(sc, net, range(2000, 2000 + a.held_out), target_psnr=target, epochs=a.epochs, adam=adam, log=log)
+
+    def stat(arm, key):
+        v = [r[arm][key] for r in rows if r[arm][key] is not None]
+        return dict(mean=float(np.mean(v)) if v else None, std=float(np.std(v)) if v else None,
+                    reached=len(v), of=len(rows))
+
+    taus = [r["tau_iter"] for r in rows if r["tau_iter"] is not None]
+
+    def level_stat(lv, arm, key):
+        v = [r["levels"][f"{lv:g}"][arm][key] for r in rows if r["levels"][f"{lv:g}"][arm][key] is not None]
+        return dict(mean=float(np.mean(v)) if v else None, reached=len(v), of=len(rows))
+    summary = dict(
+        pairs=a.pairs, pair_seconds=t_pairs, fit_psnr_mean=float(np.mean([p.fit_psnr for p in pairs])),
+        train_epochs=a.train_epochs, train_steps=a.train_epochs * a.pairs, train_seconds=t_train,
+        train_loss_first=losses[0], train_loss_last=losses[-1], target_psnr=target, epochs=a.epochs,
+        arms={arm: {k: stat(arm, k) for k in ("s_to_target", "epochs_to_target", "psnr0", "psnr_final")}
+              for arm in ("fdk_gradient", "learned")},
+        tau_iter=dict(mean=float(np.mean(taus)) if taus else None, reached=len(taus), of=len(rows)),
+        levels={f"{lv:g}": {arm: {k: level_stat(lv, arm, k) for k in ("s", "epochs")}
+                            for arm in ("fdk_gradient", "learned")} for lv in LEVELS},
+        per_phantom=rows)
+    print(json.dumps(summary), flush=True)
+
+
+if __name__ == "__main__":
+    main()

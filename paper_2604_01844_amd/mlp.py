@@ -64,15 +64,21 @@ class InitMLP:
                          A.ptr(self.wbt[1]), A.ptr(self.wb[2]), A.ptr(self.wbt[2]), A.ptr(self.b[0]),
                          A.ptr(self.b[1]), A.ptr(self.b[2]))
 
-    def features(self, vol, grid: ops.Grid, inv_norm: float, mean, transposed: bool = False):
-        """bf16 features [rows][544] (and [544][rows]) of the Gaussians at mean [3][n]."""
+    def features(self, vol, grid: ops.Grid, inv_norm: float, mean, transposed: bool = False, norm_max=None,
+                 extra=None):
+        """bf16 features [rows][544] (and [544][rows]) of the Gaussians at
+        mean [3][n]; samples scaled by inv_norm / norm_max[0] (norm_max a
+        device scalar, optional); extra [k][n] per-sample inputs (optional)."""
         n = mean.shape[1]
         rows = pad_rows(n)
         x = _i16((rows, K_IN), self.device)
         xt = _i16((K_IN, rows), self.device) if transposed else None
         gd = grid.struct()
-        A.check(A.lib().fgs_gather_patches(A.ptr(vol), ctypes.byref(gd), float(inv_norm), A.ptr(mean.contiguous()),
-                                           n, rows, A.ptr(x), A.ptr(xt), A.stream_ptr(self.device)))
+        n_extra = 0 if extra is None else extra.shape[0]
+        A.check(A.lib().fgs_gather_patches(A.ptr(vol), ctypes.byref(gd), float(inv_norm), A.ptr(norm_max),
+                                           A.ptr(mean.contiguous()),
+                                           A.ptr(None if extra is None else extra.contiguous()), n_extra, n,
+                                           rows, A.ptr(x), A.ptr(xt), A.stream_ptr(self.device)))
         return x, xt, rows
 
     def forward(self, x, rows: int, keep_transposes: bool = False) -> dict:
@@ -86,19 +92,21 @@ class InitMLP:
         A.check(A.lib().fgs_mlp_fwd(ctypes.byref(net), A.ptr(x), rows, ctypes.byref(s), A.stream_ptr(self.device)))
         return acts
 
-    def heads(self, acts: dict, n: int, target=None):
-        """Predicted [8][n]; with target [n][8] also (loss, dz3, dz3t)."""
+    def heads(self, acts: dict, n: int, target=None, base_log_scale=None):
+        """Predicted [8][n]; with target [n][8] also (loss, dz3, dz3t).
+        Log-scales are base_log_scale [n] (optional) plus the network's."""
         rows = acts["z3"].shape[0]
         out = torch.empty((8, n), device=self.device)
+        base = A.ptr(None if base_log_scale is None else base_log_scale.contiguous())
         if target is None:
-            A.check(A.lib().fgs_mlp_heads(A.ptr(acts["z3"]), rows, n, None, A.ptr(out), None, None, None,
+            A.check(A.lib().fgs_mlp_heads(A.ptr(acts["z3"]), rows, n, base, None, A.ptr(out), None, None, None,
                                           None, A.stream_ptr(self.device)))
             return out, None, None, None
         loss = torch.empty(1, device=self.device)
         dz3 = _i16((rows, N_OUT), self.device)
         dz3t = _i16((N_OUT, rows), self.device)
-        self.ws.call(A.lib().fgs_mlp_heads, A.ptr(acts["z3"]), rows, n, A.ptr(target.contiguous()), A.ptr(out),
-                     A.ptr(dz3), A.ptr(dz3t), A.ptr(loss))
+        self.ws.call(A.lib().fgs_mlp_heads, A.ptr(acts["z3"]), rows, n, base, A.ptr(target.contiguous()),
+                     A.ptr(out), A.ptr(dz3), A.ptr(dz3t), A.ptr(loss))
         return out, loss, dz3, dz3t
 
     def backward(self, xt, rows: int, acts: dict, dz3, dz3t):
@@ -117,21 +125,27 @@ class InitMLP:
             ops.adam_step(p, g, m, v, self.step, lr, eps=1e-8)
         self.pack()
 
-    def train_step(self, vol, grid, inv_norm, mean, target, lr: float) -> float:
+    def train_step(self, vol, grid, inv_norm, mean, target, lr: float, norm_max=None, base_log_scale=None):
+        """One Adam step on the batch of Gaussians at mean [3][n] with
+        targets [n][8]; returns the batch loss (device scalar). With
+        base_log_scale [n] the network sees it as an input and predicts
+        log-scales relative to it."""
         n = mean.shape[1]
-        x, xt, rows = self.features(vol, grid, inv_norm, mean, transposed=True)
+        extra = None if base_log_scale is None else base_log_scale.reshape(1, n)
+        x, xt, rows = self.features(vol, grid, inv_norm, mean, transposed=True, norm_max=norm_max, extra=extra)
         acts = self.forward(x, rows, keep_transposes=True)
-        _, loss, dz3, dz3t = self.heads(acts, n, target)
+        _, loss, dz3, dz3t = self.heads(acts, n, target, base_log_scale)
         self.backward(xt, rows, acts, dz3, dz3t)
         self.adam(lr)
         return loss
 
-    def predict(self, vol, grid, inv_norm, mean):
+    def predict(self, vol, grid, inv_norm, mean, norm_max=None, base_log_scale=None):
         """(density [n], log_scale [3][n], quat [4][n]) for Gaussians at mean."""
         n = mean.shape[1]
-        x, _, rows = self.features(vol, grid, inv_norm, mean)
+        extra = None if base_log_scale is None else base_log_scale.reshape(1, n)
+        x, _, rows = self.features(vol, grid, inv_norm, mean, norm_max=norm_max, extra=extra)
         acts = self.forward(x, rows)
-        out, *_ = self.heads(acts, n)
+        out, *_ = self.heads(acts, n, None, base_log_scale)
         return out[0].contiguous(), out[1:4].contiguous(), out[4:8].contiguous()
 
 

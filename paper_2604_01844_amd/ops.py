@@ -340,6 +340,14 @@ def gradient_init(vol, grid: Grid, uniforms, *, background_fraction: float = 0.0
     return outs
 
 
+def reduce_max(x, ws: Workspace | None = None, out=None):
+    """Device scalar max(x) (FP32), computed by the library."""
+    ws = ws or Workspace(x.device, 1 << 16)
+    out = torch.empty(1, device=x.device) if out is None else out
+    ws.call(A.lib().fgs_reduce_max, A.ptr(x.contiguous()), x.numel(), A.ptr(out))
+    return out
+
+
 # ------------------------------------------------------------------ introspection
 
 def binning_dump(ws: Workspace) -> dict:

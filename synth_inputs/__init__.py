@@ -31,6 +31,7 @@ __all__ = [
     "CONFIGS",
     "gaussians",
     "phantom",
+    "random_phantom",
     "angles",
     "geometry",
     "grid",
@@ -102,6 +103,14 @@ def phantom(n_ell: int, seed: int) -> dict:
         semi[e] = rng.uniform(0.02, 0.12, size=3)
         amp[e] = rng.uniform(0.1, 0.5)
     return dict(centre=centre, semi=semi, quat=quat, amp=amp)
+
+
+def random_phantom(seed: int, lo: int = 20, hi: int = 60) -> dict:
+    """Phantom with a seeded ellipsoid count U{lo..hi} (the training-pair
+    scenes of the learned initializer; seeds 1000+ for training, 2000+ held
+    out, 1999 for calibrating the PSNR target)."""
+    n_ell = int(np.random.Generator(np.random.PCG64(seed + 7_000_000)).integers(lo, hi + 1))
+    return phantom(n_ell, seed)
 
 
 def angles(n_views: int) -> np.ndarray:

@@ -108,15 +108,23 @@ def test_gather_patches(fgs, n):
     vol = np.abs(si.normals((nv, nv, nv), 5))
     mean = si.uniforms((3, n), 6) * 1.1 - 0.55  # some patches leave the grid, some means lie outside it
     mean = mean.astype(np.float32)
+    extra = si.normals((3, n), 16)
     net = InitMLP(weights(1), DEV)
-    x, xt, rows = net.features(torch.from_numpy(vol).to(DEV), fgs.Grid.from_dict(g), 1.7,
-                               torch.from_numpy(mean).to(DEV), transposed=True)
+    vd = torch.from_numpy(vol).to(DEV)
+    x, xt, rows = net.features(vd, fgs.Grid.from_dict(g), 1.7, torch.from_numpy(mean).to(DEV), transposed=True,
+                               extra=torch.from_numpy(extra).to(DEV))
     torch.cuda.synchronize()
     got = from_bits(x)
-    ref = oracle.mlp.patches(vol, g, mean.astype(np.float64), np.float64(np.float32(1.7)))
+    ref = oracle.mlp.patches(vol, g, mean.astype(np.float64), np.float64(np.float32(1.7)), extra=extra)
     assert within_bf16(got[:n], ref, 1e-6) <= 0
     assert np.all(got[n:] == 0)
     np.testing.assert_array_equal(xt.cpu().numpy(), x.cpu().numpy().T)
+    # normalised by a device-side maximum (the library's own reduction)
+    vmax = fgs.reduce_max(vd)
+    assert float(vmax.item()) == float(vol.max())
+    x2, _, _ = net.features(vd, fgs.Grid.from_dict(g), 1.0, torch.from_numpy(mean).to(DEV), norm_max=vmax)
+    ref2 = oracle.mlp.patches(vol, g, mean.astype(np.float64), 1.0 / float(vol.max()))
+    assert within_bf16(from_bits(x2)[:n], ref2, 1e-6) <= 0
 
 
 @pytest.mark.parametrize("n", [1, 3001])
@@ -146,13 +154,16 @@ def test_heads_and_loss(fgs, n):
     z3 = np.zeros((rows, 32), dtype=np.float32)
     z3[:n] = si.normals((n, 32), 9)
     t = targets(n, 10)
+    t[::7, 0] = 0.0  # dead targets
+    base = (si.normals(n, 18) * 0.5 - 4).astype(np.float32)
     net = InitMLP(weights(2), DEV)
     acts = {"z3": torch.from_numpy(z3).to(DEV)}
-    p_inf, *_ = net.heads(acts, n)
-    p, loss, dz3, dz3t = net.heads(acts, n, torch.from_numpy(t.astype(np.float32)).to(DEV))
+    bd = torch.from_numpy(base).to(DEV)
+    p_inf, *_ = net.heads(acts, n, base_log_scale=bd)
+    p, loss, dz3, dz3t = net.heads(acts, n, torch.from_numpy(t.astype(np.float32)).to(DEV), base_log_scale=bd)
     torch.cuda.synchronize()
     t32 = t.astype(np.float32).astype(np.float64)
-    rp, rloss, rg = oracle.mlp.heads(z3[:n].astype(np.float64), t32)
+    rp, rloss, rg = oracle.mlp.heads(z3[:n].astype(np.float64), t32, base.astype(np.float64))
     assert oracle.rel_l2(p.cpu().numpy(), rp) <= 1e-6
     np.testing.assert_array_equal(p.cpu().numpy(), p_inf.cpu().numpy())
     assert abs(float(loss.item()) - rloss) <= 1e-6 * abs(rloss)

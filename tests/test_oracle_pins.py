@@ -623,14 +623,23 @@ def test_mlp_heads_gradient_and_quaternion_sign_invariance():
     n = 30
     z3 = rng.normal(0, 1, (n, 32))
     _, _, t = _mlp_case(rng, n)
+    base = rng.normal(-4, 0.5, n)
+    t[[3, 9], 0] = 0.0  # two dead targets: only their density term counts
+    for b in (None, base):
+        p, loss, g = oracle.mlp.heads(z3, t, b)
+        assert np.all(g[:, 8:] == 0)
+        assert np.all(g[[3, 9], 1:8] == 0)
+        eps = 1e-6
+        for i, j in [(0, 0), (1, 1), (2, 3), (3, 4), (4, 5), (5, 6), (6, 7), (7, 2), (9, 0), (9, 1)]:
+            zp = z3.copy(); zp[i, j] += eps
+            zm = z3.copy(); zm[i, j] -= eps
+            fd = (oracle.mlp.heads(zp, t, b)[1] - oracle.mlp.heads(zm, t, b)[1]) / (2 * eps)
+            assert abs(fd - g[i, j]) <= 1e-7, (i, j, fd, g[i, j])
+    np.testing.assert_allclose(p[1:4], base[None, :] + z3[:, 1:4].T, rtol=1e-15)
+    # a dead target's shape terms do not count: changing its predicted shape leaves the loss
+    zd = z3.copy(); zd[3, 1:8] += 0.7
+    assert oracle.mlp.heads(zd, t, base)[1] == pytest.approx(loss, abs=1e-15)
     p, loss, g = oracle.mlp.heads(z3, t)
-    assert np.all(g[:, 8:] == 0)
-    eps = 1e-6
-    for i, j in [(0, 0), (1, 1), (2, 3), (3, 4), (4, 5), (5, 6), (6, 7), (7, 2)]:
-        zp = z3.copy(); zp[i, j] += eps
-        zm = z3.copy(); zm[i, j] -= eps
-        fd = (oracle.mlp.heads(zp, t)[1] - oracle.mlp.heads(zm, t)[1]) / (2 * eps)
-        assert abs(fd - g[i, j]) <= 1e-7, (i, j, fd, g[i, j])
     # q and -q describe one rotation: predictions and targets of either sign give one loss
     zf = z3.copy(); zf[:, 4:8] *= -1
     tf = t.copy(); tf[:, 4:8] *= -1
@@ -706,6 +715,11 @@ def test_patch_features_sample_a_linear_field_at_the_stated_offsets():
             assert f[m, fi] == pytest.approx(2.0 * vol_lin, abs=2e-6)
     np.testing.assert_allclose(f[:, 512:515], 2 * mean.T)
     assert np.all(f[:, 515:] == 0)
+    ex = rng.normal(0, 1, (2, 16))
+    fe = oracle.mlp.patches(vol, g, mean, 2.0, extra=ex)
+    np.testing.assert_array_equal(fe[:, :515], f[:, :515])
+    np.testing.assert_array_equal(fe[:, 515:517], ex.T)
+    assert np.all(fe[:, 517:] == 0)
     # a patch that leaves the grid reads zeros outside it
     corner = np.full((3, 1), -0.5 + 0.5 * h[0])
     fc = oracle.mlp.patches(np.ones_like(vol), g, corner, 1.0)
