@@ -119,7 +119,8 @@ typedef struct {
   float near_plane;      /* cone beam: Gaussians with camera depth <= near are culled (1e-2) */
   int32_t recompute;     /* backward only: 1 = rebuild the per-tile lists; 0 = reuse those that
                             the forward call left in the same workspace (same inputs) */
-  int32_t reserved;
+  int32_t accumulate;    /* backward only: 1 = add the gradients to what `out` holds (summing
+                            over view chunks or voxel slabs); 0 = overwrite */
   void *events;          /* optional hipEvent_t[2] (NULL = none): recorded on the stream right
                             before and right after the call's pixel or voxel kernel (splat
                             forward/backward, voxel forward/backward), for timing that kernel */

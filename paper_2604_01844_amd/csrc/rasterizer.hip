@@ -504,7 +504,7 @@ __global__ __launch_bounds__(256) void record_grad_kernel(fgs_gaussians g, GeomD
 
 __global__ __launch_bounds__(256) void view_sum_kernel(int64_t n, int views,
                                                        const float *__restrict__ grad_rec,
-                                                       fgs_gaussian_grads out) {
+                                                       fgs_gaussian_grads out, int accumulate) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const uint64_t R = uint64_t(views) * uint64_t(n);
@@ -515,6 +515,12 @@ __global__ __launch_bounds__(256) void view_sum_kernel(int64_t n, int views,
     const uint64_t r = uint64_t(v) * uint64_t(n) + uint64_t(i);
 #pragma unroll
     for (int c = 0; c < 11; ++c) acc[c] += grad_rec[uint64_t(c) * R + r];
+  }
+  if (accumulate) {
+    acc[0] += out.mean[i]; acc[1] += out.mean[n + i]; acc[2] += out.mean[2 * n + i];
+    acc[3] += out.log_scale[i]; acc[4] += out.log_scale[n + i]; acc[5] += out.log_scale[2 * n + i];
+    acc[6] += out.quat[i]; acc[7] += out.quat[n + i]; acc[8] += out.quat[2 * n + i]; acc[9] += out.quat[3 * n + i];
+    acc[10] += out.density[i];
   }
   out.mean[i] = acc[0]; out.mean[n + i] = acc[1]; out.mean[2 * n + i] = acc[2];
   out.log_scale[i] = acc[3]; out.log_scale[n + i] = acc[4]; out.log_scale[2 * n + i] = acc[5];
@@ -778,7 +784,7 @@ extern "C" int fgs_project_views_bwd(const fgs_gaussians *g, const fgs_geom *geo
                                            at<float>(b, L.grad_rec));
   FGS_LAUNCH_CHECK("record_grad_kernel");
   view_sum_kernel<<<grid_for(uint64_t(g->n), 256), 256, 0, s>>>(g->n, view_count, at<float>(b, L.grad_rec),
-                                                                *out);
+                                                                *out, opts->accumulate);
   FGS_LAUNCH_CHECK("view_sum_kernel");
   return FGS_OK;
 }

@@ -357,7 +357,7 @@ __global__ __launch_bounds__(kBlock) void vox_bwd_kernel(const uint32_t *__restr
 __global__ __launch_bounds__(256) void vox_grad_kernel(fgs_gaussians g, GridDev G,
                                                        const uint32_t *__restrict__ offset,
                                                        const float2 *__restrict__ partials,
-                                                       fgs_gaussian_grads out) {
+                                                       fgs_gaussian_grads out, int accumulate) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= g.n) return;
   const int64_t n = g.n;
@@ -406,6 +406,12 @@ __global__ __launch_bounds__(256) void vox_grad_kernel(fgs_gaussians g, GridDev 
     rot_grad_to_quat(P.qh, P.qnorm, dR, dq);
     res[6] = dq[0]; res[7] = dq[1]; res[8] = dq[2]; res[9] = dq[3];
     res[10] = s[0];
+  }
+  if (accumulate) {
+    res[0] += out.mean[i]; res[1] += out.mean[n + i]; res[2] += out.mean[2 * n + i];
+    res[3] += out.log_scale[i]; res[4] += out.log_scale[n + i]; res[5] += out.log_scale[2 * n + i];
+    res[6] += out.quat[i]; res[7] += out.quat[n + i]; res[8] += out.quat[2 * n + i]; res[9] += out.quat[3 * n + i];
+    res[10] += out.density[i];
   }
   out.mean[i] = res[0]; out.mean[n + i] = res[1]; out.mean[2 * n + i] = res[2];
   out.log_scale[i] = res[3]; out.log_scale[n + i] = res[4]; out.log_scale[2 * n + i] = res[5];
@@ -643,7 +649,8 @@ extern "C" int fgs_voxelize_bwd(const fgs_gaussians *g, const fgs_grid *grid, co
   }
   if (ev) FGS_HIP(hipEventRecord(ev[1], s));
   vox_grad_kernel<<<grid_for(uint64_t(g->n), 256), 256, 0, s>>>(*g, G, at<uint32_t>(b, L.offset),
-                                                                at<float2>(b, L.partials), *out);
+                                                                at<float2>(b, L.partials), *out,
+                                                                opts->accumulate);
   FGS_LAUNCH_CHECK("vox_grad_kernel");
   return FGS_OK;
 }

@@ -125,10 +125,10 @@ def _grads_like(mean, log_scale, quat, density):
             torch.empty_like(density))
 
 
-def _opts(kappa, near, recompute=1, events=None) -> A.fgs_opts:
+def _opts(kappa, near, recompute=1, events=None, accumulate=0) -> A.fgs_opts:
     """events: optional pair of started torch.cuda.Event objects to record
     around the call's pixel/voxel kernel."""
-    o = A.fgs_opts(float(kappa), float(near), int(recompute), 0, None)
+    o = A.fgs_opts(float(kappa), float(near), int(recompute), int(accumulate), None)
     if events is not None:
         arr = (ctypes.c_void_p * 2)(events[0].cuda_event, events[1].cuda_event)
         o._events_keepalive = arr
@@ -146,10 +146,33 @@ def timing_events():
 
 
 # ------------------------------------------------------------------ rasterizer
+#
+# One library call bins all its views together; a call whose (tile, Gaussian)
+# pairs would exceed 2^32 is refused with FGS_E_UNSUPPORTED. The wrappers then
+# split the view range into chunks (halving until the library accepts them)
+# and remember the chunk size in the workspace object. The backward of a
+# chunked range rebuilds each chunk's lists and accumulates the gradients in
+# the library (opts.accumulate).
+
+def _over_views(ws: Workspace, vc: int, views_per_call: int | None, run):
+    """run(begin_offset, count, first) for each chunk of the range."""
+    per = views_per_call or getattr(ws, "views_per_call", None) or vc
+    while True:
+        try:
+            for b in range(0, vc, per):
+                run(b, min(per, vc - b), b == 0, per < vc)
+            return
+        except A.FgsError as e:
+            if e.code != A.FGS_E_UNSUPPORTED or per == 1 or views_per_call:
+                raise
+            per = (per + 1) // 2
+            ws.views_per_call = per
+
 
 def project_views(mean, log_scale, quat, density, geom: Geometry, view_begin: int = 0,
                   view_count: int | None = None, *, kappa: float = KAPPA, near: float = NEAR,
-                  ws: Workspace | None = None, out: torch.Tensor | None = None, events=None) -> torch.Tensor:
+                  ws: Workspace | None = None, out: torch.Tensor | None = None, events=None,
+                  views_per_call: int | None = None) -> torch.Tensor:
     """Rasterize views [view_begin, view_begin + view_count): [V][H][W] float32."""
     L = A.lib()
     vc = geom.n_views - view_begin if view_count is None else view_count
@@ -159,15 +182,20 @@ def project_views(mean, log_scale, quat, density, geom: Geometry, view_begin: in
     g = _gauss(mean, log_scale, quat, density)
     gm = geom.struct()
     o = _opts(kappa, near, events=events)
-    ws.call(L.fgs_project_views_fwd, ctypes.byref(g), ctypes.byref(gm), view_begin, vc, ctypes.byref(o),
-            A.ptr(out))
+
+    def run(b, c, first, chunked):
+        ws.call(L.fgs_project_views_fwd, ctypes.byref(g), ctypes.byref(gm), view_begin + b, c, ctypes.byref(o),
+                A.ptr(out[b]))
+    _over_views(ws, vc, views_per_call, run)
     return out
 
 
 def project_views_backward(mean, log_scale, quat, density, geom: Geometry, grad_img, view_begin: int = 0,
                            view_count: int | None = None, *, kappa: float = KAPPA, near: float = NEAR,
-                           recompute: bool = True, ws: Workspace | None = None, out=None, events=None):
-    """dL/d(mean, log_scale, quat, density) given dL/dimg."""
+                           recompute: bool = True, ws: Workspace | None = None, out=None, events=None,
+                           views_per_call: int | None = None):
+    """dL/d(mean, log_scale, quat, density) given dL/dimg. Lists left by the
+    forward are reused only when the range ran as one call."""
     L = A.lib()
     vc = geom.n_views - view_begin if view_count is None else view_count
     ws = ws or Workspace(mean.device)
@@ -175,9 +203,13 @@ def project_views_backward(mean, log_scale, quat, density, geom: Geometry, grad_
     g = _gauss(mean, log_scale, quat, density)
     gr = A.fgs_gaussian_grads(*(A.ptr(t) for t in grads))
     gm = geom.struct()
-    o = _opts(kappa, near, 1 if recompute else 0, events)
-    ws.call(L.fgs_project_views_bwd, ctypes.byref(g), ctypes.byref(gm), view_begin, vc, ctypes.byref(o),
-            A.ptr(grad_img.contiguous()), ctypes.byref(gr))
+    gi = grad_img.contiguous()
+
+    def run(b, c, first, chunked):
+        o = _opts(kappa, near, 1 if (recompute or chunked) else 0, events, accumulate=0 if first else 1)
+        ws.call(L.fgs_project_views_bwd, ctypes.byref(g), ctypes.byref(gm), view_begin + b, c, ctypes.byref(o),
+                A.ptr(gi[b]), ctypes.byref(gr))
+    _over_views(ws, vc, views_per_call, run)
     return grads
 
 
@@ -221,9 +253,16 @@ def project_views_support(mean, log_scale, quat, density, geom: Geometry, view_b
     g = _gauss(mean, log_scale, quat, density)
     gm = geom.struct()
     o = _opts(kappa, near)
-    ws.call(L.fgs_project_views_support, ctypes.byref(g), ctypes.byref(gm), view_begin, vc, ctypes.byref(o),
-            A.ptr(out))
-    return int(out.item())
+    total = [0]
+
+    def run(b, c, first, chunked):
+        if first:
+            total[0] = 0
+        ws.call(L.fgs_project_views_support, ctypes.byref(g), ctypes.byref(gm), view_begin + b, c,
+                ctypes.byref(o), A.ptr(out))
+        total[0] += int(out.item())
+    _over_views(ws, vc, None, run)
+    return total[0]
 
 
 def voxelize_support(mean, log_scale, quat, density, grid: Grid, *, kappa: float = KAPPA,

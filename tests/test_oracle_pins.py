@@ -275,6 +275,21 @@ def test_projection_gradient_matches_finite_differences():
         _fd_check(fwd, gs, ana, 1e-4, 1e-7)
 
 
+def test_projection_gradient_matches_finite_differences_at_2048_detector():
+    """The scaling workload's geometry (2048^2 detector, F ~ 1450 px): three
+    of its Gaussians, two views, kappa = 8, Richardson central differences
+    with h = 1e-3."""
+    full = si.gaussians(500000, 2)
+    idx = np.array([11, 250000, 499999])
+    gs = {k: np.ascontiguousarray(v[..., idx], dtype=np.float64) for k, v in full.items()}
+    geom = si.geometry(2048)
+    ang = [0.0, 2.2]
+    c = np.random.default_rng(9).normal(size=(2, 2048, 2048))
+    fwd = lambda g: float(np.sum(c * oracle.project(g, geom, ang, kappa=8.0)))
+    ana = oracle.project_bwd(gs, geom, ang, c, kappa=8.0)
+    _fd_check(fwd, gs, ana, 1e-3, 1e-6)
+
+
 def test_voxelizer_gradient_matches_finite_differences():
     gs = _random_scene(4, 22, sigma=0.06)
     grid = si.grid(24)
