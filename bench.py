@@ -1,24 +1,32 @@
 """Benchmark of the FaCT-GS hot path on one MI355X.
 
-One step = one pass of the whole hot path over the standard-scan workload
-(the paper's 75-view 512^2 setting, Sec. 4.1, with 50,000 Gaussians and a
-256^3 voxel grid):
-  rasterizer forward over all 75 views -> L1 loss and gradient against the
-  phantom's exact projections -> rasterizer backward (lists reused) ->
-  voxelizer forward at 256^3 -> L1 against the phantom volume -> voxelizer
-  backward -> one Adam step on all 11 N parameters (both gradients fused).
+One step = one pass of the whole hot path over one workload:
+  rasterizer forward over all views -> L1 loss and gradient against the
+  phantom's exact projections -> rasterizer backward -> voxelizer forward
+  over the whole grid -> L1 against the phantom volume -> voxelizer backward
+  -> one Adam step on all 11 N parameters (both gradients fused).
 
-Prints ONE JSON line. `value` is view-pixels processed per second of whole
-steps (75 * 512^2 per step); `voxels_per_s` the same for the 256^3 grid.
-`roofline` is for the step's dominant kernel, timed with HIP events that the
-library records around it on the stream it runs on; its work is the exact
-number of (pixel|voxel, Gaussian) support pairs, counted on the GPU.
-`cpu_baseline` times the FP64 oracle on a bounded sample of the same step
-on the host cores.
+Workloads (synthetic, seeded; they stand in for the paper's datasets):
+  scan  (default) 50,000 Gaussians, 75 cone-beam views of 512^2, 256^3 voxels;
+        all views in one library call, the backward reuses the forward's lists.
+  scale 500,000 Gaussians, 50 views of 2048^2, 512^3 voxels; 10 views per
+        library call, lists rebuilt in the backward.
+
+Prints ONE JSON line. `value` is view-pixels per second of whole steps;
+`voxels_per_s` the same for the voxel grid. For the scan workload the
+one-view optimisation step of the reconstruction loop (Sec. 3.4: forward,
+L1, backward, Adam for one view) is also timed over one epoch of 75 steps
+(`s_per_view_step`, `s_per_epoch`). `roofline` is for the step's dominant
+kernel, timed with HIP events that the library records around it on the
+stream it runs on; its work is the exact number of (pixel|voxel, Gaussian)
+support pairs, counted on the GPU. `cpu_baseline` times the FP64 oracle on a
+bounded sample of the same step on the host cores.
 """
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -39,46 +47,94 @@ METRIC = "fwd+bwd view-pixels/s and voxels/s; s/iter and s-to-PSNR at 75×512² 
 #   voxelizer backward : offset 3, quadratic form 14, exp 1, g*e 1, ten moments 19  = 38
 FLOPS_PER_PAIR = {"splat_fwd": 12, "splat_bwd": 22, "vox_fwd": 20, "vox_bwd": 38}
 PEAK_FP32_TFLOPS = 157.3  # MI355X published FP32 vector peak
+NAMES = ("splat_fwd", "splat_bwd", "vox_fwd", "vox_bwd")
+WORKLOADS = {
+    "scan": dict(config="scan", views_per_call=None, recompute=False,
+                 label="standard scan: {N} Gaussians, {V} cone-beam views {D}x{D} (SOD 1.5, SDD 2.0), voxelizer "
+                       "{NV}^3; rasterizer and voxelizer fwd+bwd, L1 losses and Adam per step"),
+    "scale": dict(config="scale", views_per_call=10, recompute=True,
+                  label="scaling: {N} Gaussians, {V} cone-beam views {D}x{D} (10 views per call, lists rebuilt "
+                        "in the backward), voxelizer {NV}^3; fwd+bwd, L1 losses and Adam per step"),
+}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(gs, gd, ang, grid_d, budget_views=4, budget_slices=16, budget_gauss=2000):
+def source_digest() -> str:
+    """SHA-256 over the library's kernel sources: HBM traffic measured on an
+    older build of the kernels is not reported."""
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2604_01844_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    if it was taken on the current kernel sources (else None)."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    digest = source_digest()
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            f = line.split()
+            if len(f) == 5 and f[0] == workload and f[1] == kernel and f[2] == digest:
+                return dict(fetch_bytes=float(f[3]), write_bytes=float(f[4]))
+    return None
+
+
+def cpu_baseline(gs, gd, ang, grid_d, budget_s=12.0):
     """Time the FP64 oracle on a bounded sample of one step and scale it to the
-    whole step: `budget_views` of the 75 views (forward + backward over all
-    Gaussians), `budget_slices` z-slices of the 256^3 voxelizer forward and
-    the voxelizer backward of `budget_gauss` Gaussians."""
+    whole step: whole views of the rasterizer forward+backward over all
+    Gaussians (about half the budget), 8-slice slabs of the voxelizer forward
+    from the middle of the grid outwards, and the voxelizer backward of
+    chunks of 1000 Gaussians (a quarter each)."""
     import oracle
     oracle.build(force=False)
     n_views = len(ang)
     nx, ny, nz = grid_d["dims"]
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    c = np.ones((budget_views, gd["det_h"], gd["det_w"])) / (gd["det_h"] * gd["det_w"])
-    t0 = time.perf_counter()
-    oracle.project(gs, gd, ang[:budget_views])
-    t1 = time.perf_counter()
-    oracle.project_bwd(gs, gd, ang[:budget_views], c)
-    t2 = time.perf_counter()
-    slab = dict(origin=grid_d["origin"], spacing=grid_d["spacing"], dims=(nx, ny, budget_slices))
-    oracle.voxelize(gs, slab)
-    t3 = time.perf_counter()
     n = gs["density"].shape[0]
-    sel = np.random.default_rng(0).choice(n, budget_gauss, replace=False)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    c1 = np.ones((1, gd["det_h"], gd["det_w"])) / (gd["det_h"] * gd["det_w"])
+    t_proj, nv = 0.0, 0
+    while nv < n_views and (nv == 0 or t_proj < 0.5 * budget_s):
+        t0 = time.perf_counter()
+        oracle.project(gs, gd, ang[nv:nv + 1])
+        oracle.project_bwd(gs, gd, ang[nv:nv + 1], c1)
+        t_proj += time.perf_counter() - t0
+        nv += 1
+    h = grid_d["spacing"][2]
+    t_vox, slabs = 0.0, 0
+    order = [nz // 2 - 8 * (k // 2 + 1) if k % 2 == 0 else nz // 2 + 8 * (k // 2) for k in range(nz // 8)]
+    while slabs < len(order) and (slabs == 0 or t_vox < 0.25 * budget_s):
+        z0 = order[slabs]
+        slab = dict(origin=(grid_d["origin"][0], grid_d["origin"][1], grid_d["origin"][2] + z0 * h),
+                    spacing=grid_d["spacing"], dims=(nx, ny, 8))
+        t0 = time.perf_counter()
+        oracle.voxelize(gs, slab)
+        t_vox += time.perf_counter() - t0
+        slabs += 1
     gv = np.ones((nz, ny, nx)) / (nx * ny * nz)
-    t4 = time.perf_counter()
-    oracle.voxelize_bwd(gs, grid_d, gv, sel=sel)
-    t5 = time.perf_counter()
-    step_s = ((t1 - t0) + (t2 - t1)) * n_views / budget_views + (t3 - t2) * nz / budget_slices \
-        + (t5 - t4) * n / budget_gauss
-    sampled = (t2 - t0) + (t3 - t2) + (t5 - t4)
+    perm = np.random.default_rng(0).permutation(n)
+    t_vb, done = 0.0, 0
+    while done < n and (done == 0 or t_vb < 0.25 * budget_s):
+        t0 = time.perf_counter()
+        oracle.voxelize_bwd(gs, grid_d, gv, sel=perm[done:done + 1000])
+        t_vb += time.perf_counter() - t0
+        done += min(1000, n - done)
+    step_s = t_proj * n_views / nv + t_vox * nz / (8 * slabs) + t_vb * n / done
+    sampled = t_proj + t_vox + t_vb
     return dict(value=n_views * gd["det_w"] * gd["det_h"] / step_s, unit="view-pixels/s", cores=cores,
                 kind="oracle",
-                sample=(f"FP64 oracle, {budget_views} of {n_views} views rasterized forward+backward over all "
-                        f"{n} Gaussians, {budget_slices} of {nz} z-slices voxelized, voxelizer backward of "
-                        f"{budget_gauss} of {n} Gaussians; {sampled:.1f} s measured, scaled linearly to one "
-                        f"step ({step_s:.1f} s)"),
+                sample=(f"FP64 oracle with {cores} OpenMP threads: {nv} of {n_views} views rasterized "
+                        f"forward+backward over all {n} Gaussians, {8 * slabs} of {nz} z-slices voxelized, "
+                        f"voxelizer backward of {done} of {n} Gaussians; {sampled:.1f} s measured, scaled "
+                        f"linearly to one step ({step_s:.1f} s)"),
                 seconds_per_step=step_s)
 
 
@@ -87,23 +143,26 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="scan")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-view-steps", action="store_true", help="skip the one-view step timing")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after timing, copy a MIB-MiB float32 buffer device-to-device 3 times "
                          "(a plain copy kernel of known size, to scale HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(sharding is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path; run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
     import paper_2604_01844_amd as fgs
     import synth_inputs as si
 
+    wl = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    cfg = si.CONFIGS["scan"]
+    cfg = si.CONFIGS[wl["config"]]
     N, V, D, NV = cfg["n_gauss"], cfg["n_views"], cfg["det"], cfg["vol"]
     gs = si.gaussians(N, cfg["seed"])
     gd = si.geometry(D)
@@ -113,7 +172,7 @@ def main():
     grid = fgs.Grid.from_dict(grid_d)
     ph = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in si.phantom(cfg["n_ell"],
                                                                                        cfg["phantom_seed"]).items()}
-    log(f"workload: {N} Gaussians, {V} views {D}x{D}, {NV}^3 voxels")
+    log(f"workload {args.workload}: {N} Gaussians, {V} views {D}x{D}, {NV}^3 voxels")
     i_gt = fgs.phantom_project(ph, geom)
     v_gt = fgs.phantom_voxelize(ph, grid)
 
@@ -125,15 +184,16 @@ def main():
     img = torch.empty((V, D, D), device=dev)
     vol = torch.empty(grid.shape, device=dev)
     ws_p, ws_v, ws_l = fgs.Workspace(dev), fgs.Workspace(dev), fgs.Workspace(dev, 1 << 16)
-    names = ("splat_fwd", "splat_bwd", "vox_fwd", "vox_bwd")
+    vpc = wl["views_per_call"]
+    chunks = 1 if vpc is None else (V + vpc - 1) // vpc
     state = {"step": 0}
 
     def step(ev=None):
         e = ev or {}
-        fgs.project_views(*params, geom, ws=ws_p, out=img, events=e.get("splat_fwd"))
+        fgs.project_views(*params, geom, ws=ws_p, out=img, events=e.get("splat_fwd"), views_per_call=vpc)
         _, g_img = fgs.l1_loss_grad(img, i_gt, ws=ws_l)
-        fgs.project_views_backward(*params, geom, g_img, recompute=False, ws=ws_p, out=gp,
-                                   events=e.get("splat_bwd"))
+        fgs.project_views_backward(*params, geom, g_img, recompute=wl["recompute"], ws=ws_p, out=gp,
+                                   events=e.get("splat_bwd"), views_per_call=vpc)
         fgs.voxelize(*params, grid, ws=ws_v, out=vol, events=e.get("vox_fwd"))
         _, g_vol = fgs.l1_loss_grad(vol, v_gt, n_views=1, ws=ws_l)
         fgs.voxelize_backward(*params, grid, g_vol, recompute=False, ws=ws_v, out=gv, events=e.get("vox_bwd"))
@@ -142,12 +202,23 @@ def main():
             fgs.adam_step(p, gp[k], moms[k][0], moms[k][1], state["step"], lrs[k], grad2=gv[k],
                           clamp_min_zero=(k == 3))
 
-    pairs0 = {"splat": fgs.project_views_support(*params, geom), "vox": fgs.voxelize_support(*params, grid)}
+    def events():
+        e = {n: fgs.timing_events() for n in ("vox_fwd", "vox_bwd")}
+        for n in ("splat_fwd", "splat_bwd"):
+            e[n] = fgs.timing_events() if chunks == 1 else [fgs.timing_events() for _ in range(chunks)]
+        return e
+
+    def elapsed(pair_or_list):
+        pl = [pair_or_list] if isinstance(pair_or_list, tuple) else pair_or_list
+        return sum(a.elapsed_time(b) for a, b in pl)
+
+    pairs0 = {"splat": fgs.project_views_support(*params, geom, ws=ws_p),
+              "vox": fgs.voxelize_support(*params, grid, ws=ws_v)}
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     log(f"warmup done ({args.warmup} steps); timing {args.steps} steps")
-    evs = [{n: fgs.timing_events() for n in names} for _ in range(args.steps)]
+    evs = [events() for _ in range(args.steps)]
     torch.cuda.synchronize()
     t_start = torch.cuda.Event(enable_timing=True)
     t_stop = torch.cuda.Event(enable_timing=True)
@@ -160,32 +231,56 @@ def main():
     wall = time.perf_counter() - wall0
     ms_total = t_start.elapsed_time(t_stop)
     ms_step = ms_total / args.steps
-    kern_ms = {n: float(np.mean([e[n][0].elapsed_time(e[n][1]) for e in evs])) for n in names}
-    pairs1 = {"splat": fgs.project_views_support(*params, geom), "vox": fgs.voxelize_support(*params, grid)}
+    kern_ms = {n: float(np.mean([elapsed(e[n]) for e in evs])) for n in NAMES}
+    pairs1 = {"splat": fgs.project_views_support(*params, geom, ws=ws_p),
+              "vox": fgs.voxelize_support(*params, grid, ws=ws_v)}
     pairs = {k: 0.5 * (pairs0[k] + pairs1[k]) for k in pairs0}
     log(f"timed: {ms_step:.3f} ms/step (wall {1e3 * wall / args.steps:.3f}); kernels {kern_ms}")
 
     kernels = {}
-    for n in names:
+    for n in NAMES:
         pr = pairs["splat" if n.startswith("splat") else "vox"]
         tf = pr * FLOPS_PER_PAIR[n] / (kern_ms[n] * 1e-3) / 1e12
-        kernels[n] = dict(ms=round(kern_ms[n], 4), support_pairs=int(pr),
-                          pairs_per_s=pr / (kern_ms[n] * 1e-3), tflops=round(tf, 3))
-    dom = max(names, key=lambda n: kern_ms[n])
+        kernels[n] = dict(ms=round(kern_ms[n], 4), launches=chunks if n.startswith("splat") else 1,
+                          support_pairs=int(pr), pairs_per_s=pr / (kern_ms[n] * 1e-3), tflops=round(tf, 3))
+    dom = max(NAMES, key=lambda n: kern_ms[n])
+    launches = kernels[dom]["launches"]
+    tr = measured_traffic(args.workload, dom)
     roof = dict(bound="alu", achieved=round(kernels[dom]["tflops"], 3), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
-                frac=round(kernels[dom]["tflops"] / PEAK_FP32_TFLOPS, 4), traffic=None, kernel=dom,
-                flops_per_pair=FLOPS_PER_PAIR[dom], support_pairs=int(pairs["splat" if dom.startswith("splat")
-                                                                             else "vox"]))
+                frac=round(kernels[dom]["tflops"] / PEAK_FP32_TFLOPS, 4),
+                traffic=None if tr is None else round(tr["fetch_bytes"] + tr["write_bytes"]),
+                kernel=dom, flops_per_pair=FLOPS_PER_PAIR[dom], support_pairs=kernels[dom]["support_pairs"],
+                launches_per_step=launches, avg_launch_ms=round(kern_ms[dom] / launches, 4))
     out = dict(metric=METRIC, value=V * D * D / (ms_step * 1e-3), unit="view-pixels/s", n_gpus=1,
                steps=args.steps, warmup=args.warmup, ms_per_step=round(ms_step, 4), higher_is_better=True,
                scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
-               config=dict(workload=f"standard scan: {N} Gaussians, {V} cone-beam views {D}x{D} "
-                                    f"(SOD 1.5, SDD 2.0), voxelizer {NV}^3; rasterizer and voxelizer "
-                                    f"fwd+bwd, L1 losses and Adam per step",
-                           n_gauss=N, views=V, det=D, vol=NV),
-               voxels_per_s=NV ** 3 / (ms_step * 1e-3),
-               s_per_step=ms_step * 1e-3,
+               config=dict(workload=wl["label"].format(N=N, V=V, D=D, NV=NV), n_gauss=N, views=V, det=D, vol=NV),
+               voxels_per_s=NV ** 3 / (ms_step * 1e-3), s_per_step=ms_step * 1e-3,
                kernels=kernels, roofline=roof)
+
+    if args.workload == "scan" and not args.no_view_steps:
+        # the reconstruction loop's optimizer step: one view fwd, L1, bwd (lists reused), Adam
+        img1 = torch.empty((1, D, D), device=dev)
+        order = np.random.Generator(np.random.PCG64(0)).permutation(V)
+
+        def view_step(v):
+            fgs.project_views(*params, geom, int(v), 1, ws=ws_p, out=img1)
+            _, g1 = fgs.l1_loss_grad(img1, i_gt[v:v + 1], ws=ws_l)
+            fgs.project_views_backward(*params, geom, g1, int(v), 1, recompute=False, ws=ws_p, out=gp)
+            state["step"] += 1
+            for k, p in enumerate(params):
+                fgs.adam_step(p, gp[k], moms[k][0], moms[k][1], state["step"], lrs[k], clamp_min_zero=(k == 3))
+        for v in order[:5]:
+            view_step(v)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        for v in order:
+            view_step(v)
+        torch.cuda.synchronize()
+        epoch_s = time.perf_counter() - w0
+        out["s_per_view_step"] = epoch_s / V
+        out["s_per_epoch"] = epoch_s
+        log(f"one-view steps: {1e3 * epoch_s / V:.3f} ms/step, {epoch_s:.3f} s/epoch")
     if args.calibrate_copy:
         src = torch.ones(args.calibrate_copy << 18, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)

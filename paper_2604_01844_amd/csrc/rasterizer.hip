@@ -2,25 +2,32 @@
 //
 // Forward, per call over a batch of views:
 //   1. record kernel      one thread per (view, Gaussian): splat centre,
-//                         pre-scaled conic and w = rho mu (float4), support
+//                         pre-scaled conic and w = rho mu packed in one
+//                         32-byte line with the pair-slot addressing, support
 //                         half-extents, axis-aligned tile rectangle, count.
 //   2. exclusive scan     counts -> key offsets (one readback of the total).
 //   3. emit kernel        keys (view * tiles_per_view + tile) and values
-//                         (record index), row-major inside each rectangle.
+//                         (record index), row-major inside each rectangle;
+//                         completes the record's slot base.
 //   4. radix sort         stable; no depth key (the sum is order-free).
 //   5. ranges kernel      per-tile [start, end) by boundary detection.
-//   6. splat kernel       one 64-lane wave per 16x16 tile; batches of 64
-//                         records staged in LDS; each lane owns a column of
-//                         4 pixels; the Gaussian factor is one v_exp_f32 of a
-//                         pre-scaled quadratic form; support test d^2 <= k^2.
+//   6. splat kernel       one 64-lane wave per 16x16 tile, 16 tiles per
+//                         workgroup; batches of 64 records staged in LDS;
+//                         each record is tested against the tile's four 8x8
+//                         quadrants and a 16-lane group walks one quadrant's
+//                         list, each lane a column of 4 pixels; the Gaussian
+//                         factor is one v_exp_f32 of a pre-scaled quadratic
+//                         form; support test d^2 <= k^2.
 // Backward (per-Gaussian formulation, Sec. 3.5):
-//   7. splat-grad kernel  one wave per tile; each lane owns one
-//                         (tile, Gaussian) pair of the tile's list and sums
-//                         over the 256 pixels, reading dL/dI from LDS, the
-//                         six moments sum g e {1, dx, dy, dx^2, dx dy, dy^2}.
-//                         No atomics and no cross-lane traffic: the pair's
-//                         sums go to the pair's emission slot, so a record's
-//                         partial sums are contiguous.
+//   7. splat-grad kernel  same tiling and quadrant lists; one lane per
+//                         (quadrant, Gaussian) pair sums over the quadrant's
+//                         64 pixels (dL/dI from LDS) the six moments
+//                         sum g e {1, dx, dy, dx^2, dx dy, dy^2}; the lane
+//                         that loaded the record gathers its quadrants'
+//                         partials by wavefront permutes, in quadrant order,
+//                         and writes the pair's sums to its emission slot (32
+//                         bytes), so a record's partial sums are contiguous.
+//                         No atomics.
 //   8. record-grad kernel per record: reduce its contiguous partials in order
 //                         and apply the chain rule to the 11 parameters.
 //   9. view-sum kernel    per Gaussian: sum its records over views in order.
@@ -55,6 +62,15 @@ __device__ __forceinline__ void tile_span(float c, float r, int n_tiles, int &t0
 
 constexpr int kTotalSlots = 64;
 
+// What the pixel kernels read per (tile, Gaussian) pair, packed in one
+// 32-byte line: a = (u, v, pre-scaled conic c00, c01), b = (c11, w, base,
+// width), where the pair's emission slot for tile (tx, ty) of the record's
+// rectangle is base + ty * width + tx (32-bit wrap-around; base is written
+// once the key offsets are known).
+struct SplatRec {
+  float4 a, b;
+};
+
 __global__ void zero_u64_kernel(unsigned long long *p, int n) {
   if (int(threadIdx.x) < n) p[threadIdx.x] = 0ull;
 }
@@ -62,7 +78,7 @@ __global__ void zero_u64_kernel(unsigned long long *p, int n) {
 // Record r = v_local * n + i of one (view, Gaussian) pair. Returns its tile count.
 __device__ __forceinline__ uint32_t record_one(const fgs_gaussians &g, const GeomDev &G, int64_t i,
                                                int v_local, float2 *__restrict__ xy,
-                                               float4 *__restrict__ conic_w, float2 *__restrict__ radii,
+                                               SplatRec *__restrict__ rec, float2 *__restrict__ radii,
                                                ushort4 *__restrict__ rect, uint32_t *__restrict__ count) {
   const int64_t r = int64_t(v_local) * g.n + i;
   GaussParams P;
@@ -73,7 +89,8 @@ __device__ __forceinline__ uint32_t record_one(const fgs_gaussians &g, const Geo
   splat_forward(P, F, G, S);
   if (!S.ok) {
     xy[r] = make_float2(0.f, 0.f);
-    conic_w[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+    rec[r].a = make_float4(0.f, 0.f, 0.f, 0.f);
+    rec[r].b = make_float4(0.f, 0.f, 0.f, 0.f);
     radii[r] = make_float2(0.f, 0.f);
     rect[r] = make_ushort4(1, 1, 0, 0);
     count[r] = 0;
@@ -87,7 +104,8 @@ __device__ __forceinline__ uint32_t record_one(const fgs_gaussians &g, const Geo
   const bool empty = (x0 > x1) || (y0 > y1);
   const float k = -0.5f * kLog2e;
   xy[r] = make_float2(S.u, S.v);
-  conic_w[r] = make_float4(k * S.C00, 2.f * k * S.C01, k * S.C11, S.w);
+  rec[r].a = make_float4(S.u, S.v, k * S.C00, 2.f * k * S.C01);
+  rec[r].b = make_float4(k * S.C11, S.w, 0.f, __uint_as_float(empty ? 0u : uint32_t(x1 - x0 + 1)));
   radii[r] = make_float2(ru, rv);
   if (empty) {
     rect[r] = make_ushort4(1, 1, 0, 0);
@@ -101,14 +119,14 @@ __device__ __forceinline__ uint32_t record_one(const fgs_gaussians &g, const Geo
 }
 
 __global__ __launch_bounds__(256) void record_kernel(fgs_gaussians g, GeomDev G, float2 *__restrict__ xy,
-                                                     float4 *__restrict__ conic_w,
+                                                     SplatRec *__restrict__ rec,
                                                      float2 *__restrict__ radii,
                                                      ushort4 *__restrict__ rect,
                                                      uint32_t *__restrict__ count,
                                                      unsigned long long *__restrict__ total64) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   uint32_t cnt = 0;
-  if (i < g.n) cnt = record_one(g, G, i, int(blockIdx.y), xy, conic_w, radii, rect, count);
+  if (i < g.n) cnt = record_one(g, G, i, int(blockIdx.y), xy, rec, radii, rect, count);
   // 64-bit pair total (detects a 32-bit scan overflow): one atomic per wave,
   // spread over kTotalSlots addresses to keep contention low
   unsigned long long w = cnt;
@@ -121,13 +139,15 @@ __global__ __launch_bounds__(256) void emit_kernel(uint64_t R, int64_t n, int ti
                                                    const ushort4 *__restrict__ rect,
                                                    const uint32_t *__restrict__ offset,
                                                    uint32_t *__restrict__ keys,
-                                                   uint32_t *__restrict__ vals) {
+                                                   uint32_t *__restrict__ vals, SplatRec *__restrict__ rec) {
   const uint64_t r = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (r >= R) return;
   uint32_t o = offset[r];
   const uint32_t end = offset[r + 1];
   if (o == end) return;
   const ushort4 rc = rect[r];
+  const uint32_t wdt = uint32_t(rc.z) - rc.x + 1u;
+  rec[r].b.z = __uint_as_float(o - uint32_t(rc.y) * wdt - uint32_t(rc.x));
   const uint32_t base = uint32_t(r / uint64_t(n)) * uint32_t(tpv);
   for (int ty = rc.y; ty <= rc.w; ++ty)
     for (int tx = rc.x; tx <= rc.z; ++tx) {
@@ -218,8 +238,7 @@ __device__ __forceinline__ void set_null_record(float4 *s_cw, float2 *s_xy) {
 template <bool kCount>
 __global__ __launch_bounds__(kBlock) void splat_fwd_kernel(const uint32_t *__restrict__ start,
                                                            const uint32_t *__restrict__ svals,
-                                                           const float2 *__restrict__ xy,
-                                                           const float4 *__restrict__ conic_w,
+                                                           const SplatRec *__restrict__ rec,
                                                            int tiles_x, int tpv, int W, int H,
                                                            uint32_t n_tiles, float thr, float thr_cull,
                                                            float *__restrict__ img,
@@ -256,8 +275,10 @@ __global__ __launch_bounds__(kBlock) void splat_fwd_kernel(const uint32_t *__res
     uint32_t mask = 0;
     if (uint32_t(lane) < m) {
       const uint32_t r = svals[b + lane];
-      const float4 c = conic_w[r];
-      const float2 q = xy[r];
+      const float4 ra = rec[r].a;
+      const float2 rb = *reinterpret_cast<const float2 *>(&rec[r].b);
+      const float4 c = make_float4(ra.z, ra.w, rb.x, rb.y);
+      const float2 q = make_float2(ra.x, ra.y);
       s_cw[lane] = c;
       s_xy[lane] = q;
       mask = quad_mask(c, q.x, q.y, tx0, ty0, thr_cull);
@@ -331,10 +352,8 @@ __device__ __forceinline__ float bperm(int src_lane, float v) {
 // the summation order is fixed.
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void splat_bwd_kernel(
     const uint32_t *__restrict__ start, const uint32_t *__restrict__ svals,
-    const float2 *__restrict__ xy, const float4 *__restrict__ conic_w,
-    const ushort4 *__restrict__ rect, const uint32_t *__restrict__ offset, int tiles_x, int tpv,
-    int W, int H, uint32_t n_tiles, float thr, float thr_cull, const float *__restrict__ gimg,
-    float2 *__restrict__ partials) {
+    const SplatRec *__restrict__ rec, int tiles_x, int tpv, int W, int H, uint32_t n_tiles, float thr,
+    float thr_cull, const float *__restrict__ gimg, float4 *__restrict__ partials) {
   __shared__ float4 s_g4_all[kTilesPerBlock][kTS * kTS / 4];
   __shared__ float4 s_cw_all[kTilesPerBlock][kWave + 1];
   __shared__ float2 s_xy_all[kTilesPerBlock][kWave + 1];
@@ -370,11 +389,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
   const uint32_t b0 = start[tile], e = start[tile + 1];
   for (uint32_t b = b0; b < e; b += kWave) {
     const uint32_t m = min(uint32_t(kWave), e - b);
-    uint32_t mask = 0, r = 0;
+    uint32_t mask = 0, slot = 0;
     if (uint32_t(lane) < m) {
-      r = svals[b + lane];
-      const float4 c = conic_w[r];
-      const float2 q = xy[r];
+      const uint32_t r = svals[b + lane];
+      const float4 ra = rec[r].a, rb = rec[r].b;
+      const float4 c = make_float4(ra.z, ra.w, rb.x, rb.y);
+      const float2 q = make_float2(ra.x, ra.y);
+      slot = __float_as_uint(rb.z) + uint32_t(ty) * __float_as_uint(rb.w) + uint32_t(tx);
       s_cw[lane] = c;
       s_xy[lane] = q;
       mask = quad_mask(c, q.x, q.y, tx0, ty0, thr_cull);
@@ -450,12 +471,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
       }
     }
     if (uint32_t(lane) < m) {
-      const ushort4 rc = rect[r];
-      const uint32_t jr = uint32_t(ty - rc.y) * uint32_t(rc.z - rc.x + 1) + uint32_t(tx - rc.x);
-      const uint64_t p = uint64_t(offset[r]) + jr;
-      partials[3 * p + 0] = make_float2(tot[0], tot[1]);
-      partials[3 * p + 1] = make_float2(tot[2], tot[3]);
-      partials[3 * p + 2] = make_float2(tot[4], tot[5]);
+      partials[2 * uint64_t(slot) + 0] = make_float4(tot[0], tot[1], tot[2], tot[3]);
+      partials[2 * uint64_t(slot) + 1] = make_float4(tot[4], tot[5], 0.f, 0.f);
     }
     wave_lds_sync();
   }
@@ -463,7 +480,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
 
 __global__ __launch_bounds__(256) void record_grad_kernel(fgs_gaussians g, GeomDev G,
                                                           const uint32_t *__restrict__ offset,
-                                                          const float2 *__restrict__ partials,
+                                                          const float4 *__restrict__ partials,
                                                           uint64_t R, float *__restrict__ grad_rec) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= g.n) return;
@@ -478,11 +495,10 @@ __global__ __launch_bounds__(256) void record_grad_kernel(fgs_gaussians g, GeomD
   }
   float sums[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   for (uint32_t p = o; p < end; ++p) {
-    const float2 a = partials[3 * uint64_t(p) + 0];
-    const float2 b = partials[3 * uint64_t(p) + 1];
-    const float2 c = partials[3 * uint64_t(p) + 2];
-    sums[0] += a.x; sums[1] += a.y; sums[2] += b.x;
-    sums[3] += b.y; sums[4] += c.x; sums[5] += c.y;
+    const float4 a = partials[2 * uint64_t(p) + 0];
+    const float2 b = *reinterpret_cast<const float2 *>(&partials[2 * uint64_t(p) + 1]);
+    sums[0] += a.x; sums[1] += a.y; sums[2] += a.z;
+    sums[3] += a.w; sums[4] += b.x; sums[5] += b.y;
   }
   GaussParams P;
   load_gauss(g, i, P);
@@ -533,7 +549,7 @@ __global__ __launch_bounds__(256) void view_sum_kernel(int64_t n, int views,
 struct RastLayout {
   uint64_t R, T, K;
   // byte offsets
-  uint64_t total64, xy, radii, rect, offset, conic, scan_scratch, start, grad_rec;
+  uint64_t total64, xy, radii, rect, offset, rec, scan_scratch, start, grad_rec;
   uint64_t fixed_end;
   uint64_t keys, vals, keys_alt, vals_alt, sort_scratch, partials;
   uint64_t total;
@@ -551,7 +567,7 @@ RastLayout rast_layout(uint64_t R, uint64_t T, uint64_t K) {
   c.take<float2>(R, &L.radii);
   c.take<ushort4>(R, &L.rect);
   c.take<uint32_t>(R + 1, &L.offset);
-  c.take<float4>(R, &L.conic);
+  c.take<SplatRec>(R, &L.rec);
   c.take<uint32_t>(scan_scratch_words(R), &L.scan_scratch);
   c.take<uint32_t>(T + 1, &L.start);
   c.take<float>(11 * R, &L.grad_rec);
@@ -561,7 +577,7 @@ RastLayout rast_layout(uint64_t R, uint64_t T, uint64_t K) {
   c.take<uint32_t>(K, &L.keys_alt);
   c.take<uint32_t>(K, &L.vals_alt);
   c.take<uint32_t>(sort_scratch_words(K), &L.sort_scratch);
-  c.take<float>(6 * K, &L.partials);
+  c.take<float4>(2 * K, &L.partials);
   L.total = c.used;
   const int bits = bits_for(T);
   const int passes = (K > 1 && bits > 0) ? (bits + 8) / 9 : 0;
@@ -649,7 +665,7 @@ int build_lists(const fgs_gaussians *g, const fgs_geom *geom, int32_t view_begin
   zero_u64_kernel<<<1, kTotalSlots, 0, s>>>(total64, kTotalSlots);
   FGS_LAUNCH_CHECK("zero_u64_kernel");
   dim3 rgrid(grid_for(uint64_t(g->n), 256), unsigned(view_count));
-  record_kernel<<<rgrid, 256, 0, s>>>(*g, G, at<float2>(b, L.xy), at<float4>(b, L.conic),
+  record_kernel<<<rgrid, 256, 0, s>>>(*g, G, at<float2>(b, L.xy), at<SplatRec>(b, L.rec),
                                       at<float2>(b, L.radii), at<ushort4>(b, L.rect),
                                       at<uint32_t>(b, L.offset), total64);
   FGS_LAUNCH_CHECK("record_kernel");
@@ -672,7 +688,7 @@ int build_lists(const fgs_gaussians *g, const fgs_geom *geom, int32_t view_begin
   if (K > 0) {
     emit_kernel<<<grid_for(R, 256), 256, 0, s>>>(R, g->n, tg.tiles_x, tg.tpv, at<ushort4>(b, L.rect),
                                                   at<uint32_t>(b, L.offset), at<uint32_t>(b, L.keys),
-                                                  at<uint32_t>(b, L.vals));
+                                                  at<uint32_t>(b, L.vals), at<SplatRec>(b, L.rec));
     FGS_LAUNCH_CHECK("emit_kernel");
   }
   uint32_t *sk, *sv;
@@ -712,7 +728,7 @@ extern "C" int fgs_project_views_fwd(const fgs_gaussians *g, const fgs_geom *geo
   hipEvent_t *ev = static_cast<hipEvent_t *>(opts->events);
   if (ev) FGS_HIP(hipEventRecord(ev[0], s));
   splat_fwd_kernel<false><<<grid_for(L.T, kTilesPerBlock), kBlock, 0, s>>>(
-      at<uint32_t>(b, L.start), sv, at<float2>(b, L.xy), at<float4>(b, L.conic), tg.tiles_x, tg.tpv,
+      at<uint32_t>(b, L.start), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv,
       geom->det_w, geom->det_h, uint32_t(L.T), thr, thr * kCullSlack, img, nullptr);
   FGS_LAUNCH_CHECK("splat_fwd_kernel");
   if (ev) FGS_HIP(hipEventRecord(ev[1], s));
@@ -737,7 +753,7 @@ extern "C" int fgs_project_views_support(const fgs_gaussians *g, const fgs_geom 
   const float thr = -0.5f * kLog2e * opts->kappa * opts->kappa;
   const TileGrid tg = tile_grid(geom->det_w, geom->det_h);
   splat_fwd_kernel<true><<<grid_for(L.T, kTilesPerBlock), kBlock, 0, s>>>(
-      at<uint32_t>(b, L.start), sv, at<float2>(b, L.xy), at<float4>(b, L.conic), tg.tiles_x, tg.tpv,
+      at<uint32_t>(b, L.start), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv,
       geom->det_w, geom->det_h, uint32_t(L.T), thr, thr * kCullSlack, nullptr, cnt);
   FGS_LAUNCH_CHECK("splat_fwd_kernel<count>");
   return FGS_OK;
@@ -773,14 +789,13 @@ extern "C" int fgs_project_views_bwd(const fgs_gaussians *g, const fgs_geom *geo
   if (ev) FGS_HIP(hipEventRecord(ev[0], s));
   if (L.K > 0) {
     splat_bwd_kernel<<<grid_for(L.T, kTilesPerBlock), kBlock, 0, s>>>(
-        at<uint32_t>(b, L.start), sv, at<float2>(b, L.xy), at<float4>(b, L.conic),
-        at<ushort4>(b, L.rect), at<uint32_t>(b, L.offset), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
-        uint32_t(L.T), thr, thr * kCullSlack, grad_img, at<float2>(b, L.partials));
+        at<uint32_t>(b, L.start), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
+        uint32_t(L.T), thr, thr * kCullSlack, grad_img, at<float4>(b, L.partials));
     FGS_LAUNCH_CHECK("splat_bwd_kernel");
   }
   if (ev) FGS_HIP(hipEventRecord(ev[1], s));
   dim3 rgrid(grid_for(uint64_t(g->n), 256), unsigned(view_count));
-  record_grad_kernel<<<rgrid, 256, 0, s>>>(*g, G, at<uint32_t>(b, L.offset), at<float2>(b, L.partials), R,
+  record_grad_kernel<<<rgrid, 256, 0, s>>>(*g, G, at<uint32_t>(b, L.offset), at<float4>(b, L.partials), R,
                                            at<float>(b, L.grad_rec));
   FGS_LAUNCH_CHECK("record_grad_kernel");
   view_sum_kernel<<<grid_for(uint64_t(g->n), 256), 256, 0, s>>>(g->n, view_count, at<float>(b, L.grad_rec),

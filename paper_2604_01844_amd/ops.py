@@ -154,13 +154,21 @@ def timing_events():
 # chunked range rebuilds each chunk's lists and accumulates the gradients in
 # the library (opts.accumulate).
 
+def _chunk_events(events, k):
+    """events: None, one (start, stop) pair, or a list of pairs (one per chunk)."""
+    if events is None or isinstance(events, tuple):
+        return events
+    return events[k]
+
+
 def _over_views(ws: Workspace, vc: int, views_per_call: int | None, run):
-    """run(begin_offset, count, first) for each chunk of the range."""
+    """run(begin_offset, count, first, chunked, chunk_index) for each chunk of
+    the range."""
     per = views_per_call or getattr(ws, "views_per_call", None) or vc
     while True:
         try:
-            for b in range(0, vc, per):
-                run(b, min(per, vc - b), b == 0, per < vc)
+            for k, b in enumerate(range(0, vc, per)):
+                run(b, min(per, vc - b), b == 0, per < vc, k)
             return
         except A.FgsError as e:
             if e.code != A.FGS_E_UNSUPPORTED or per == 1 or views_per_call:
@@ -181,9 +189,9 @@ def project_views(mean, log_scale, quat, density, geom: Geometry, view_begin: in
         out = torch.empty((vc, geom.det_h, geom.det_w), dtype=torch.float32, device=mean.device)
     g = _gauss(mean, log_scale, quat, density)
     gm = geom.struct()
-    o = _opts(kappa, near, events=events)
 
-    def run(b, c, first, chunked):
+    def run(b, c, first, chunked, k):
+        o = _opts(kappa, near, events=_chunk_events(events, k))
         ws.call(L.fgs_project_views_fwd, ctypes.byref(g), ctypes.byref(gm), view_begin + b, c, ctypes.byref(o),
                 A.ptr(out[b]))
     _over_views(ws, vc, views_per_call, run)
@@ -205,8 +213,9 @@ def project_views_backward(mean, log_scale, quat, density, geom: Geometry, grad_
     gm = geom.struct()
     gi = grad_img.contiguous()
 
-    def run(b, c, first, chunked):
-        o = _opts(kappa, near, 1 if (recompute or chunked) else 0, events, accumulate=0 if first else 1)
+    def run(b, c, first, chunked, k):
+        o = _opts(kappa, near, 1 if (recompute or chunked) else 0, _chunk_events(events, k),
+                  accumulate=0 if first else 1)
         ws.call(L.fgs_project_views_bwd, ctypes.byref(g), ctypes.byref(gm), view_begin + b, c, ctypes.byref(o),
                 A.ptr(gi[b]), ctypes.byref(gr))
     _over_views(ws, vc, views_per_call, run)
@@ -255,7 +264,7 @@ def project_views_support(mean, log_scale, quat, density, geom: Geometry, view_b
     o = _opts(kappa, near)
     total = [0]
 
-    def run(b, c, first, chunked):
+    def run(b, c, first, chunked, k):
         if first:
             total[0] = 0
         ws.call(L.fgs_project_views_support, ctypes.byref(g), ctypes.byref(gm), view_begin + b, c,
