@@ -235,6 +235,11 @@ int fgs_adam_step(float *param, const float *grad, const float *grad2, float *m,
 int fgs_psnr(const float *vol, const float *ref, int64_t n, float peak, float *out,
              fgs_workspace *ws, void *stream);
 
+/* dst[0..n) = src[0..n) (device, FP32, 16-byte aligned, n a multiple of 4):
+ * a plain streaming copy that reads and writes exactly 4 n bytes, the
+ * reference for scaling HBM traffic counters of the other kernels. */
+int fgs_copy(const float *src, float *dst, int64_t n, void *stream);
+
 /* ---------------------------------------------------------------------
  * Synthetic ground truth (additive ellipsoid phantom, computed in FP64).
  * ------------------------------------------------------------------- */

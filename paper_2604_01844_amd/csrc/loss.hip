@@ -4,6 +4,8 @@
 // depend on timing (no atomics).
 #include <cmath>
 
+#include <algorithm>
+
 #include "fgs_internal.h"
 
 namespace fgs {
@@ -145,5 +147,32 @@ extern "C" int fgs_adam_step(float *param, const float *grad, const float *grad2
   adam_kernel<<<grid_for(uint64_t(n), 256), 256, 0, s>>>(param, grad, grad2, m, v, uint64_t(n), lr, beta1, beta2, eps,
                                                          c1, c2, clamp_min_zero);
   FGS_LAUNCH_CHECK("adam_kernel");
+  return FGS_OK;
+}
+
+namespace fgs {
+namespace {
+
+// Plain streaming copy, 16 bytes per thread per step (the reference kernel for
+// HBM traffic counters: it reads and writes exactly 4 n bytes).
+__global__ __launch_bounds__(256) void copy_kernel(const float4 *__restrict__ src, float4 *__restrict__ dst,
+                                                   uint64_t n4) {
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n4; i += uint64_t(gridDim.x) * blockDim.x)
+    dst[i] = src[i];
+}
+
+}  // namespace
+}  // namespace fgs
+
+extern "C" int fgs_copy(const float *src, float *dst, int64_t n, void *stream) {
+  if (!src || !dst || n < 0 || (n & 3) || (reinterpret_cast<uintptr_t>(src) & 15) ||
+      (reinterpret_cast<uintptr_t>(dst) & 15))
+    return fail(FGS_E_INVALID, "copy: 16-byte aligned buffers, n a multiple of 4");
+  if (n == 0) return FGS_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const uint64_t n4 = uint64_t(n) / 4;
+  const unsigned blocks = unsigned(std::min<uint64_t>((n4 + 255) / 256, 256u * 64u));
+  copy_kernel<<<blocks, 256, 0, s>>>(reinterpret_cast<const float4 *>(src), reinterpret_cast<float4 *>(dst), n4);
+  FGS_LAUNCH_CHECK("copy_kernel");
   return FGS_OK;
 }

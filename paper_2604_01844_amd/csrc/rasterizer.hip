@@ -338,18 +338,19 @@ __device__ __forceinline__ float bperm(int src_lane, float v) {
   return __int_as_float(__builtin_amdgcn_ds_bpermute(src_lane << 2, __float_as_int(v)));
 }
 
-// Backward over one tile (per-Gaussian formulation). Each round, 16-lane
-// group grp takes the next 16 entries of quadrant grp's list; a lane owns one
-// (quadrant, Gaussian) pair and sums over the quadrant's 64 pixels (dL/dI
-// read from LDS) the six moments sum g e {1, dx, dy, dx^2, dx dy, dy^2},
-// (dx, dy) = pixel - centre. Pixel coordinates are taken relative to the
-// quadrant centre, (cc, rr) in {-3.5, ..., 3.5}: per row the exponent is a
-// quadratic in cc with lane coefficients and the moments are accumulated
+// Backward over one tile (per-Gaussian formulation). The (quadrant, Gaussian)
+// pairs of a batch form one list, quadrant by quadrant; each round the 64
+// lanes take the next 64 pairs, so rounds are full whatever the split over
+// quadrants. A lane owns one pair and sums over the quadrant's 64 pixels
+// (dL/dI read from LDS) the six moments sum g e {1, dx, dy, dx^2, dx dy,
+// dy^2}, (dx, dy) = pixel - centre. Pixel coordinates are taken relative to
+// the quadrant centre, (cc, rr) in {-3.5, ..., 3.5}: per row the exponent is
+// a quadratic in cc with lane coefficients and the moments are accumulated
 // against the constants cc, cc^2 (branch-free body), then moved to the
-// Gaussian's centre. The lane that loaded a record then gathers its up to
-// four quadrant partials with wavefront permutes, in quadrant order, and
-// writes the pair's six sums to the pair's emission slot: no atomics, and
-// the summation order is fixed.
+// Gaussian's centre. The lane that loaded a record gathers its up to four
+// quadrant partials with wavefront permutes, in quadrant order, and writes
+// the pair's six sums to the pair's emission slot: no atomics, and the
+// summation order is fixed.
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void splat_bwd_kernel(
     const uint32_t *__restrict__ start, const uint32_t *__restrict__ svals,
     const SplatRec *__restrict__ rec, int tiles_x, int tpv, int W, int H, uint32_t n_tiles, float thr,
@@ -357,13 +358,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
   __shared__ float4 s_g4_all[kTilesPerBlock][kTS * kTS / 4];
   __shared__ float4 s_cw_all[kTilesPerBlock][kWave + 1];
   __shared__ float2 s_xy_all[kTilesPerBlock][kWave + 1];
-  __shared__ uint8_t s_list_all[kTilesPerBlock][4][kWave];
+  __shared__ uint8_t s_cat_all[kTilesPerBlock][4 * kWave];
   const int wid = threadIdx.x / kWave;
   float4 *s_g4 = s_g4_all[wid];
   float *s_g = reinterpret_cast<float *>(s_g4);
   float4 *s_cw = s_cw_all[wid];
   float2 *s_xy = s_xy_all[wid];
-  uint8_t(*s_list)[kWave] = s_list_all[wid];
+  uint8_t *s_cat = s_cat_all[wid];
   const uint32_t tile = blockIdx.x * kTilesPerBlock + wid;
   if (tile >= n_tiles) return;
   const uint32_t v_local = tile / uint32_t(tpv);
@@ -371,8 +372,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
   const int ty = int(t) / tiles_x;
   const int tx = int(t) - ty * tiles_x;
   const int lane = threadIdx.x & (kWave - 1);
-  const int grp = lane >> 4;
-  const int sub = lane & 15;
   const float *gv = gimg + uint64_t(v_local) * uint64_t(W) * uint64_t(H);
   for (int p = lane; p < kTS * kTS; p += kWave) {
     const int x = tx * kTS + (p & (kTS - 1));
@@ -382,10 +381,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
   if (lane == 0) set_null_record(s_cw, s_xy);
   wave_lds_sync();
   const float tx0 = float(tx * kTS) + 0.5f, ty0 = float(ty * kTS) + 0.5f;
-  // centre of this lane group's quadrant, and its first float4 of dL/dI
-  const float ox = float(tx * kTS + (grp & 1) * 8) + 4.f;
-  const float oy = float(ty * kTS + (grp >> 1) * 8) + 4.f;
-  const float4 *g4q = s_g4 + (grp >> 1) * 8 * (kTS / 4) + (grp & 1) * 2;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const uint32_t b0 = start[tile], e = start[tile + 1];
   for (uint32_t b = b0; b < e; b += kWave) {
     const uint32_t m = min(uint32_t(kWave), e - b);
@@ -400,18 +396,33 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
       s_xy[lane] = q;
       mask = quad_mask(c, q.x, q.y, tx0, ty0, thr_cull);
     }
-    int nq[4], pos[4];
-    build_quad_lists(mask, lane, s_list, nq, pos);
-    const int n_me = (grp == 0) ? nq[0] : (grp == 1) ? nq[1] : (grp == 2) ? nq[2] : nq[3];
-    const int n_max = max(max(nq[0], nq[1]), max(nq[2], nq[3]));
-    // this lane's record: its list positions (6 bits each) and quadrant mask, packed
-    const uint32_t posm = uint32_t(pos[0]) | (uint32_t(pos[1]) << 6) | (uint32_t(pos[2]) << 12) |
-                          (uint32_t(pos[3]) << 18) | (mask << 24);
+    // one list of (quadrant << 6 | batch slot) entries, quadrant-major; gpk
+    // holds this lane's record's position in it for each quadrant (8 bits each)
+    int n_pairs = 0;
+    uint32_t gpk = 0;
+#pragma unroll
+    for (int Q = 0; Q < 4; ++Q) {
+      const bool bit = (mask >> Q) & 1u;
+      const uint64_t bal = __ballot(bit);
+      const int gp = n_pairs + __popcll(bal & lt);
+      if (bit) s_cat[gp] = uint8_t((Q << 6) | lane);
+      gpk |= uint32_t(gp & 255) << (8 * Q);
+      n_pairs += __popcll(bal);
+    }
     wave_lds_sync();
     float tot[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    for (int round = 0; round * 16 < n_max; ++round) {
-      const int i = round * 16 + sub;
-      const int j = (i < n_me) ? int(s_list[grp][i]) : kWave;
+    for (int base = 0; base < n_pairs; base += kWave) {
+      const int idx = base + lane;
+      int Q = 0, j = kWave;
+      if (idx < n_pairs) {
+        const int ent = s_cat[idx];
+        Q = ent >> 6;
+        j = ent & 63;
+      }
+      // centre of the pair's quadrant and its first float4 of dL/dI
+      const float ox = float(tx * kTS + (Q & 1) * 8) + 4.f;
+      const float oy = float(ty * kTS + (Q >> 1) * 8) + 4.f;
+      const float4 *g4q = s_g4 + (Q >> 1) * 8 * (kTS / 4) + (Q & 1) * 2;
       const float4 c = s_cw[j];
       const float2 q = s_xy[j];
       // Gaussian centre relative to the quadrant centre; arg = c.x dx^2 + c.y dx dy + c.z dy^2
@@ -457,12 +468,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
       M[3] = fmaf(qx * qx, S0, fmaf(-2.f * qx, Sc, Scc));
       M[4] = fmaf(qx * qy, S0, fmaf(-qy, Sc, fmaf(-qx, Sr, Scr)));
       M[5] = fmaf(qy * qy, S0, fmaf(-2.f * qy, Sr, Srr));
-      // the loading lane of each record collects its quadrants' partials
+      // the loading lane of each record collects its quadrants' partials from
+      // this round's lanes (quadrants with no pair in the round are skipped)
 #pragma unroll
-      for (int Q = 0; Q < 4; ++Q) {
-        const int pq = int((posm >> (6 * Q)) & 63u);
-        const bool mine = ((posm >> (24 + Q)) & 1u) && (pq >> 4) == round;
-        const int src = Q * 16 + (pq & 15);
+      for (int QQ = 0; QQ < 4; ++QQ) {
+        const int rel = int((gpk >> (8 * QQ)) & 255u) - base;
+        const bool mine = ((mask >> QQ) & 1u) && rel >= 0 && rel < kWave;
+        if (__ballot(mine) == 0ull) continue;
+        const int src = mine ? rel : 0;
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
           const float v = bperm(src, M[k]);
