@@ -238,6 +238,9 @@ def main():
     ms_total = t_start.elapsed_time(t_stop)
     ms_step = ms_total / args.steps
     kern_ms = {n: float(np.mean([elapsed(e[n]) for e in evs])) for n in NAMES}
+    # (tile, Gaussian) keys of the last binning of each workspace (for a
+    # view-chunked workload: of the last chunk)
+    keys = {"splat": ws_p.n_pairs, "vox": ws_v.n_pairs}
     pairs1 = {"splat": fgs.project_views_support(*params, geom, ws=ws_p),
               "vox": fgs.voxelize_support(*params, grid, ws=ws_v)}
     pairs = {k: 0.5 * (pairs0[k] + pairs1[k]) for k in pairs0}
@@ -248,7 +251,8 @@ def main():
         pr = pairs["splat" if n.startswith("splat") else "vox"]
         tf = pr * FLOPS_PER_PAIR[n] / (kern_ms[n] * 1e-3) / 1e12
         kernels[n] = dict(ms=round(kern_ms[n], 4), launches=chunks if n.startswith("splat") else 1,
-                          support_pairs=int(pr), pairs_per_s=pr / (kern_ms[n] * 1e-3), tflops=round(tf, 3))
+                          support_pairs=int(pr), keys_per_launch=int(keys["splat" if n.startswith("splat") else "vox"]),
+                          pairs_per_s=pr / (kern_ms[n] * 1e-3), tflops=round(tf, 3))
     dom = max(NAMES, key=lambda n: kern_ms[n])
     launches = kernels[dom]["launches"]
     tr = measured_traffic(args.workload, dom)
