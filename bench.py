@@ -15,8 +15,9 @@ Workloads (synthetic, seeded; they stand in for the paper's datasets):
 Prints ONE JSON line. `value` is view-pixels per second of whole steps;
 `voxels_per_s` the same for the voxel grid. For the scan workload the
 one-view optimisation step of the reconstruction loop (Sec. 3.4: forward,
-L1, backward, Adam for one view) is also timed over one epoch of 75 steps
-(`s_per_view_step`, `s_per_epoch`). `roofline` is for the step's dominant
+L1, backward for one view, plus a randomly placed 32^3 crop voxelized with
+the gradient of its total variation, then Adam) is also timed over one epoch
+of 75 steps (`s_per_view_step`, `s_per_epoch`). `roofline` is for the step's dominant
 kernel, timed with HIP events that the library records around it on the
 stream it runs on; its work is the exact number of (pixel|voxel, Gaussian)
 support pairs, counted on the GPU. `cpu_baseline` times the FP64 oracle on a
@@ -61,6 +62,7 @@ WORKLOADS = {
                         "in the backward), voxelizer {NV}^3; fwd+bwd, L1 losses and Adam per step"),
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+TV_WEIGHT = 0.05  # weight of the crop TV term in the one-view step (the paper prints none)
 
 
 def log(msg):
@@ -273,13 +275,17 @@ def main():
 
     if args.workload == "scan" and not args.no_view_steps:
         # the reconstruction loop's optimizer step: one view fwd, L1, bwd (lists reused), Adam
+        from paper_2604_01844_amd.recon import CropTV
         img1 = torch.empty((1, D, D), device=dev)
-        order = np.random.Generator(np.random.PCG64(0)).permutation(V)
+        rng = np.random.Generator(np.random.PCG64(0))
+        order = rng.permutation(V)
+        tv = CropTV(grid, TV_WEIGHT, 32, dev)
 
         def view_step(v):
             fgs.project_views(*params, geom, int(v), 1, ws=ws_p, out=img1)
             _, g1 = fgs.l1_loss_grad(img1, i_gt[v:v + 1], ws=ws_l)
             fgs.project_views_backward(*params, geom, g1, int(v), 1, recompute=False, ws=ws_p, out=gp)
+            tv.add_grad(params, gp, rng)
             state["step"] += 1
             for k, p in enumerate(params):
                 fgs.adam_step(p, gp[k], moms[k][0], moms[k][1], state["step"], lrs[k], clamp_min_zero=(k == 3))

@@ -235,6 +235,15 @@ int fgs_adam_step(float *param, const float *grad, const float *grad2, float *m,
 int fgs_psnr(const float *vol, const float *ref, int64_t n, float peak, float *out,
              fgs_workspace *ws, void *stream);
 
+/* 3D total variation of vol[nz][ny][nx] (the TV term of Eq. 5, on the
+ * sampled sub-volume): loss[0] = scale * (1/n) sum over voxels and axes of
+ * |V(i + e_a) - V(i)| (forward differences inside the grid, n = voxel
+ * count), and, if grad != NULL, grad = its gradient (sign(0) = 0), both
+ * device buffers, overwritten. dims = {nx, ny, nz} (host). Workspace: at
+ * most 8 KiB. */
+int fgs_tv_loss_grad(const float *vol, const int32_t dims[3], float scale, float *loss, float *grad,
+                     fgs_workspace *ws, void *stream);
+
 /* dst[0..n) = src[0..n) (device, FP32, 16-byte aligned, n a multiple of 4):
  * a plain streaming copy that reads and writes exactly 4 n bytes, the
  * reference for scaling HBM traffic counters of the other kernels. */

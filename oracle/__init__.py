@@ -32,6 +32,8 @@ Parity status of each function (what pins it in ``tests/test_oracle_pins.py``):
 * ``initialisation.gradient_init``: pinned by hand-computed draws, sampling
   frequencies against the exact multinomial law, trilinear exactness on
   linear fields and brute-force nearest neighbours.
+* ``tv_loss_grad``: pinned by a hand-computed volume, finite differences
+  and the invariances of a total variation.
 * ``mlp`` (learned initializer): BF16 rounding pinned against torch's
   bfloat16 conversion, the backward against finite differences of the
   unrounded network, the canonical targets against their defining
@@ -394,6 +396,28 @@ def adam_step(param, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, e
     mh = m / (1 - beta1 ** step)
     vh = v / (1 - beta2 ** step)
     return param - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def tv_loss_grad(vol32, scale: float = 1.0):
+    """3D total variation (the TV term of Eq. 5): scale/n times the sum over
+    voxels and axes of |V(i + e_a) - V(i)| (forward differences inside the
+    grid, n = voxel count), and its gradient. The differences and their signs
+    are taken in FP32 (the input's precision), the sums in FP64."""
+    v = np.asarray(vol32, dtype=np.float32)
+    n = v.size
+    loss = 0.0
+    grad = np.zeros(v.shape)
+    for axis in range(3):
+        d = np.diff(v, axis=axis)             # FP32 forward differences
+        loss += np.abs(d.astype(np.float64)).sum()
+        sg = np.sign(d).astype(np.float64)
+        lo = [slice(None)] * 3
+        hi = [slice(None)] * 3
+        lo[axis] = slice(0, -1)
+        hi[axis] = slice(1, None)
+        grad[tuple(lo)] -= sg                 # V(i) enters d(i) with sign -1
+        grad[tuple(hi)] += sg                 # V(i + e_a) enters d(i) with sign +1
+    return scale * loss / n, grad * (scale / n)
 
 
 def psnr(vol, gt):

@@ -1,5 +1,6 @@
 // Loss, metric and optimiser kernels of the reconstruction loop:
-// the L1 term of Eq. 5 with its gradient, PSNR, and Adam.
+// the L1 and 3D total-variation terms of Eq. 5 with their gradients, PSNR,
+// and Adam.
 // Reductions are two-level with a fixed block count, so results do not
 // depend on timing (no atomics).
 #include <cmath>
@@ -92,6 +93,37 @@ __global__ __launch_bounds__(256) void adam_kernel(float *__restrict__ p, const 
   p[i] = x;
 }
 
+// 3D total variation (the homogeneity prior of Eq. 5 on a sampled
+// sub-volume): TV = (1/n) sum over voxels and axes of |V(i + e_a) - V(i)|
+// (forward differences inside the grid), and its gradient
+// dTV/dV(i) = (1/n) sum_a [sign(V(i) - V(i - e_a)) - sign(V(i + e_a) - V(i))],
+// sign(0) = 0. Both scaled by `scale` (the loss weight). One thread per voxel.
+__device__ __forceinline__ float sgn(float d) { return (d > 0.f) ? 1.f : ((d < 0.f) ? -1.f : 0.f); }
+
+__global__ __launch_bounds__(kRedThreads) void tv_kernel(const float *__restrict__ vol, int nx, int ny, int nz,
+                                                         float scale_n, float *__restrict__ grad,
+                                                         double *__restrict__ partial) {
+  __shared__ double sh[kRedThreads / 64];
+  const uint64_t n = uint64_t(nx) * ny * nz;
+  const uint64_t sy = uint64_t(nx), sz = uint64_t(nx) * ny;
+  double acc = 0.0;
+  for (uint64_t i = uint64_t(blockIdx.x) * kRedThreads + threadIdx.x; i < n;
+       i += uint64_t(gridDim.x) * kRedThreads) {
+    const int x = int(i % sy), y = int((i / sy) % ny), z = int(i / sz);
+    const float v = vol[i];
+    float g = 0.f;
+    if (x + 1 < nx) { const float d = vol[i + 1] - v; acc += fabs(double(d)); g -= sgn(d); }
+    if (y + 1 < ny) { const float d = vol[i + sy] - v; acc += fabs(double(d)); g -= sgn(d); }
+    if (z + 1 < nz) { const float d = vol[i + sz] - v; acc += fabs(double(d)); g -= sgn(d); }
+    if (x > 0) g += sgn(v - vol[i - 1]);
+    if (y > 0) g += sgn(v - vol[i - sy]);
+    if (z > 0) g += sgn(v - vol[i - sz]);
+    if (grad) grad[i] = g * scale_n;
+  }
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
 int reduce_blocks(uint64_t n) {
   uint64_t b = (n + kRedThreads - 1) / kRedThreads;
   return int(b < kRedBlocks ? (b ? b : 1) : kRedBlocks);
@@ -174,5 +206,24 @@ extern "C" int fgs_copy(const float *src, float *dst, int64_t n, void *stream) {
   const unsigned blocks = unsigned(std::min<uint64_t>((n4 + 255) / 256, 256u * 64u));
   copy_kernel<<<blocks, 256, 0, s>>>(reinterpret_cast<const float4 *>(src), reinterpret_cast<float4 *>(dst), n4);
   FGS_LAUNCH_CHECK("copy_kernel");
+  return FGS_OK;
+}
+
+extern "C" int fgs_tv_loss_grad(const float *vol, const int32_t dims[3], float scale, float *loss, float *grad,
+                                fgs_workspace *ws, void *stream) {
+  if (!vol || !dims || !loss || !ws) return fail(FGS_E_INVALID, "null argument");
+  if (dims[0] <= 0 || dims[1] <= 0 || dims[2] <= 0) return fail(FGS_E_INVALID, "dims must be >= 1");
+  const uint64_t n = uint64_t(dims[0]) * dims[1] * dims[2];
+  const int nb = reduce_blocks(n);
+  ws->needed = uint64_t(nb) * sizeof(double);
+  if (!ws->ptr || ws->bytes < ws->needed) return fail(FGS_E_CAPACITY, "workspace too small");
+  ws->kind = 0;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double *partial = static_cast<double *>(ws->ptr);
+  tv_kernel<<<nb, kRedThreads, 0, s>>>(vol, dims[0], dims[1], dims[2], float(double(scale) / double(n)), grad,
+                                       partial);
+  FGS_LAUNCH_CHECK("tv_kernel");
+  finish_kernel<<<1, kRedThreads, 0, s>>>(partial, nb, 0, double(scale) / double(n), 0.0, 0.0, loss);
+  FGS_LAUNCH_CHECK("finish_kernel");
   return FGS_OK;
 }

@@ -238,14 +238,17 @@ def voxelize(mean, log_scale, quat, density, grid: Grid, *, kappa: float = KAPPA
 
 
 def voxelize_backward(mean, log_scale, quat, density, grid: Grid, grad_vol, *, kappa: float = KAPPA,
-                      recompute: bool = True, ws: Workspace | None = None, out=None, events=None):
+                      recompute: bool = True, ws: Workspace | None = None, out=None, events=None,
+                      accumulate: bool = False):
+    """dL/d(mean, log_scale, quat, density) given dL/dvol; with accumulate the
+    gradients are added to `out` instead of overwriting it."""
     L = A.lib()
     ws = ws or Workspace(mean.device)
     grads = out if out is not None else _grads_like(mean, log_scale, quat, density)
     g = _gauss(mean, log_scale, quat, density)
     gr = A.fgs_gaussian_grads(*(A.ptr(t) for t in grads))
     gd = grid.struct()
-    o = _opts(kappa, NEAR, 1 if recompute else 0, events)
+    o = _opts(kappa, NEAR, 1 if recompute else 0, events, accumulate=1 if accumulate else 0)
     ws.call(L.fgs_voxelize_bwd, ctypes.byref(g), ctypes.byref(gd), ctypes.byref(o),
             A.ptr(grad_vol.contiguous()), ctypes.byref(gr))
     return grads
@@ -299,6 +302,20 @@ def l1_loss_grad(img, gt, *, n_views: int | None = None, ws: Workspace | None = 
     grad = torch.empty_like(img) if want_grad else None
     ws.call(L.fgs_l1_loss_grad, A.ptr(img), A.ptr(gt), per, nv, A.ptr(loss), A.ptr(grad))
     return loss, grad
+
+
+def tv_loss_grad(vol, *, scale: float = 1.0, ws: Workspace | None = None, want_grad=True, grad=None):
+    """3D total variation of vol [nz][ny][nx] (TV term of Eq. 5) times scale:
+    (loss device scalar, gradient or None)."""
+    ws = ws or Workspace(vol.device, 1 << 16)
+    nz, ny, nx = vol.shape
+    dims = (ctypes.c_int32 * 3)(nx, ny, nz)
+    loss = torch.empty(1, device=vol.device)
+    if want_grad and grad is None:
+        grad = torch.empty_like(vol)
+    ws.call(A.lib().fgs_tv_loss_grad, A.ptr(vol.contiguous()), dims, float(scale), A.ptr(loss),
+            A.ptr(grad if want_grad else None))
+    return loss, (grad if want_grad else None)
 
 
 def psnr(vol, ref, peak: float, ws: Workspace | None = None):

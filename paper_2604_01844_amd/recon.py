@@ -10,13 +10,14 @@ Both are thin drivers. Every numerical step runs in libfactgs:
 
 Python only orders the calls, draws the view order and keeps the clock.
 
-Reconstruction follows the paper's loop with the L1 term of Eq. 5:
+Reconstruction follows the paper's loop with the L1 and TV terms of Eq. 5:
 - one view per optimizer step, views in a fresh random order each epoch;
+- with tv_weight > 0, each step also voxelizes a randomly placed 32^3 crop of
+  the reconstruction grid and adds the gradient of tv_weight * TV(crop);
 - a paper "iteration" is one pass over all views (its Table 1 times grow
   linearly with the number of views at a fixed iteration count).
 
-The SSIM and TV terms (and the 32^3 crop they need) are not part of this
-build.
+The SSIM term is not part of this build.
 
 Fitting follows Sec. 3.6 with the L1 term of Eq. 6:
 - initialise by gradient sampling on the target volume;
@@ -123,10 +124,37 @@ def init_from_volume(vol, grid: ops.Grid, n: int, uniforms, *, background_fracti
     return GaussianModel(mean, ls, q, d)
 
 
+class CropTV:
+    """The per-step TV prior of Eq. 5: a crop of `size`^3 voxels of `grid`,
+    placed uniformly at random, voxelized, and weight * TV(crop) added to the
+    step's gradient through the voxelizer backward."""
+
+    def __init__(self, grid: ops.Grid, weight: float, size: int = 32, device="cuda"):
+        self.grid, self.weight, self.size = grid, float(weight), size
+        self.ws = ops.Workspace(device)
+        self.ws_l = ops.Workspace(device, 1 << 16)
+        self.vol = torch.empty((size, size, size), device=device)
+        self.grad = torch.empty_like(self.vol)
+
+    def crop(self, rng) -> ops.Grid:
+        off = [int(rng.integers(0, d - self.size + 1)) for d in self.grid.dims]
+        origin = tuple(float(np.float32(o + k * h)) for o, k, h in zip(self.grid.origin, off, self.grid.spacing))
+        return ops.Grid(origin, self.grid.spacing, (self.size,) * 3)
+
+    def add_grad(self, params, grads, rng):
+        """Add the gradient of weight * TV(random crop) to `grads` (the four
+        parameter gradient tensors); returns the TV term (device scalar)."""
+        g = self.crop(rng)
+        ops.voxelize(*params, g, ws=self.ws, out=self.vol)
+        loss, _ = ops.tv_loss_grad(self.vol, scale=self.weight, ws=self.ws_l, grad=self.grad)
+        ops.voxelize_backward(*params, g, self.grad, recompute=False, ws=self.ws, out=grads, accumulate=True)
+        return loss
+
+
 def reconstruct(model: GaussianModel, proj_gt, geom: ops.Geometry, *, epochs: int, adam: AdamConfig,
                 vol_gt=None, eval_grid: ops.Grid | None = None, eval_every: int = 1,
                 target_psnr: float | None = None, seed: int = 0, clock_start: float | None = None,
-                t_offset: float = 0.0, eval_at_start: bool = False) -> History:
+                t_offset: float = 0.0, eval_at_start: bool = False, tv: CropTV | None = None) -> History:
     """Optimise `model` against projections proj_gt[V][H][W] (GPU), one view
     per step. If vol_gt/eval_grid are given, PSNR is evaluated every
     `eval_every` epochs (and before the first step with eval_at_start),
@@ -159,6 +187,8 @@ def reconstruct(model: GaussianModel, proj_gt, geom: ops.Geometry, *, epochs: in
             loss, g = ops.l1_loss_grad(img, proj_gt[v:v + 1], ws=ws_l)
             ops.project_views_backward(*model.params, geom, g, int(v), 1, recompute=False, ws=ws_p,
                                        out=model.grads)
+            if tv is not None:
+                tv.add_grad(model.params, model.grads, rng)
             model.adam(adam)
         if vol_gt is not None and (ep % eval_every == 0 or ep == epochs):
             torch.cuda.synchronize()

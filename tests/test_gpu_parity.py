@@ -447,3 +447,32 @@ def test_gradient_init_matches_oracle(fgs):
     assert rel(dens, ref["density"]) < TOL
     assert rel(ls, ref["log_scale"]) < TOL
     np.testing.assert_array_equal(quat, ref["quat"])
+
+
+# ------------------------------------------------------------------ TV prior and the crop step
+
+@pytest.mark.parametrize("shape", [(32, 32, 32), (33, 29, 37), (1, 1, 5)])
+def test_tv_loss_grad_matches_oracle(fgs, shape):
+    v = si.normals(shape, 90 + shape[0])
+    loss, g = fgs.tv_loss_grad(torch.from_numpy(v).to(DEV), scale=0.05)
+    rl, rg = oracle.tv_loss_grad(v, scale=0.05)
+    assert abs(float(loss.item()) - rl) <= 1e-6 * abs(rl)
+    np.testing.assert_allclose(g.cpu().numpy(), rg, rtol=1e-6, atol=1e-12)
+
+
+def test_voxelize_backward_accumulates(fgs):
+    """opts.accumulate adds the crop's gradient to the projection gradient."""
+    gs = si.gaussians(3000, 91)
+    d = dev(gs)
+    gr = fgs.Grid(tuple(np.float32(-0.5 + k / 64) for k in (5, 17, 40)), (np.float32(1 / 64),) * 3, (32, 32, 32))
+    c = torch.from_numpy(si.normals((32, 32, 32), 92)).to(DEV)
+    fresh = fgs.voxelize_backward(*args(d), gr, c)
+    base = [torch.from_numpy(si.normals(t.shape, 93 + k)).to(DEV) for k, t in enumerate(fresh)]
+    acc = [b.clone() for b in base]
+    fgs.voxelize_backward(*args(d), gr, c, out=acc, accumulate=True)
+    for a, b, f in zip(acc, base, fresh):
+        np.testing.assert_allclose(a.cpu().numpy(), (b + f).cpu().numpy(), rtol=1e-6, atol=1e-6)
+    ref = oracle.voxelize_bwd(gs, dict(origin=gr.origin, spacing=gr.spacing, dims=gr.dims), c.cpu().numpy(),
+                              band=BAND)
+    errs = grads_rel(fresh, ref)
+    assert max(errs.values()) < TOL, errs

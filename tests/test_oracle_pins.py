@@ -740,3 +740,31 @@ def test_patch_features_sample_a_linear_field_at_the_stated_offsets():
     fc = oracle.mlp.patches(np.ones_like(vol), g, corner, 1.0)
     np.testing.assert_allclose(fc[0, 0], 0.0)
     np.testing.assert_allclose(fc[0, 511], 1.0)
+
+
+# ---------------------------------------------------------------------------
+# 3D total variation (TV term of Eq. 5)
+
+def test_tv_hand_values_invariances_and_finite_differences():
+    # 1 x 2 x 3 volume (nz, ny, nx): x-differences 1, 3 / -2, 0; y-differences 1, -2, -5
+    v = np.array([[[0.0, 1.0, 4.0], [1.0, -1.0, -1.0]]], dtype=np.float32)
+    loss, g = oracle.tv_loss_grad(v, scale=2.0)
+    assert loss == pytest.approx(2.0 * (1 + 3 + 2 + 0 + 1 + 2 + 5) / 6, rel=1e-15)
+    # voxel (0,0,0): x-diff +1 -> -1, y-diff +1 -> -1; voxel (0,1,1): x-diffs -2 (in: -1), 0; y-diff -2 (in: -1)
+    np.testing.assert_allclose(g[0, 0, 0], 2.0 * (-1 - 1) / 6)
+    np.testing.assert_allclose(g[0, 1, 1], 2.0 * (-1 + 0 - 1) / 6)
+    np.testing.assert_allclose(g.sum(), 0.0, atol=1e-15)  # translation invariance of TV
+    assert oracle.tv_loss_grad(np.full((4, 5, 6), 3.5, np.float32))[0] == 0.0
+    rng = np.random.default_rng(31)
+    w = rng.normal(size=(5, 6, 7)).astype(np.float32)
+    l0, g0 = oracle.tv_loss_grad(w)
+    assert oracle.tv_loss_grad(w + np.float32(2.0))[0] == pytest.approx(l0, rel=1e-6)
+    assert oracle.tv_loss_grad(-w)[0] == pytest.approx(l0, rel=1e-15)
+    # TV is piecewise linear: central differences are exact away from ties
+    w64 = w.astype(np.float64)
+    for idx in [(0, 0, 0), (2, 3, 4), (4, 5, 6), (1, 0, 6)]:
+        h = 1e-3
+        wp = w64.copy(); wp[idx] += h
+        wm = w64.copy(); wm[idx] -= h
+        f = lambda a: sum(np.abs(np.diff(a, axis=ax)).sum() for ax in range(3)) / a.size
+        assert (f(wp) - f(wm)) / (2 * h) == pytest.approx(g0[idx], abs=1e-9)
