@@ -8,10 +8,40 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <type_traits>
 
 #include "factgs.h"
 
 namespace fgs {
+
+// Independent tiles (one per wave) per workgroup of the pixel and voxel
+// kernels: 16 when a call has enough tiles to give every CU several
+// workgroups (which is what lets a CU hold enough waves), fewer for small
+// calls (one view, a crop) so that their waves spread over all CUs.
+inline int tiles_per_block(uint64_t n_tiles) { return n_tiles >= 16384 ? 16 : (n_tiles >= 4096 ? 4 : 1); }
+
+// Waves per tile: a call with few tiles (one view, a crop) splits each
+// tile's list over several waves (strided batches), so that the longest
+// list does not set the kernel time; large calls keep one wave per tile.
+inline int chunks_per_tile(uint64_t n_tiles) {
+  if (n_tiles >= 8192) return 1;
+  const uint64_t c = (8192 + n_tiles - 1) / n_tiles;
+  return int(c < 16 ? c : 16);
+}
+
+// out[i] = sum over c = 0..chunks-1 (in order) of part[c * n + i].
+int sum_chunks(const float *part, int chunks, uint64_t n, float *out, hipStream_t s);
+
+// Calls f(std::integral_constant<int, TPB>) with TPB = tiles_per_block(n_tiles).
+template <typename F>
+void with_tiles_per_block(uint64_t n_tiles, F &&f) {
+  switch (tiles_per_block(n_tiles)) {
+    case 16: f(std::integral_constant<int, 16>()); break;
+    case 4: f(std::integral_constant<int, 4>()); break;
+    default: f(std::integral_constant<int, 1>()); break;
+  }
+}
+
 
 // ------------------------------------------------------------------ errors
 

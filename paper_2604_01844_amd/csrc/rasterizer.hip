@@ -11,8 +11,8 @@
 //                         completes the record's slot base.
 //   4. radix sort         stable; no depth key (the sum is order-free).
 //   5. ranges kernel      per-tile [start, end) by boundary detection.
-//   6. splat kernel       one 64-lane wave per 16x16 tile, 16 tiles per
-//                         workgroup; batches of 64 records staged in LDS;
+//   6. splat kernel       one 64-lane wave per 16x16 tile, up to 16 tiles
+//                         per workgroup; batches of 64 records staged in LDS;
 //                         each record is tested against the tile's four 8x8
 //                         quadrants and a 16-lane group walks one quadrant's
 //                         list, each lane a column of 4 pixels; the Gaussian
@@ -38,8 +38,6 @@ namespace {
 
 constexpr int kTS = 16;          // tile side in pixels
 constexpr int kWave = 64;        // lanes per wave (gfx9 wave64)
-constexpr int kTilesPerBlock = 16;  // independent tiles per workgroup, one per wave
-constexpr int kBlock = kWave * kTilesPerBlock;
 constexpr int kRows = 4;         // pixels per lane in the forward (a column of 4)
 // The quadrant culling test keeps pairs whose exponent reaches thr * kCullSlack
 // (a Mahalanobis radius 0.05% beyond the support), a superset of the per-pixel test.
@@ -235,23 +233,27 @@ __device__ __forceinline__ void set_null_record(float4 *s_cw, float2 *s_xy) {
 
 // kCount = true: instead of the image, count the (pixel, Gaussian) pairs in
 // the support whose pixel lies on the detector (the algorithmic work).
-template <bool kCount>
-__global__ __launch_bounds__(kBlock) void splat_fwd_kernel(const uint32_t *__restrict__ start,
+template <bool kCount, int TPB>
+__global__ __launch_bounds__(kWave * TPB) void splat_fwd_kernel(const uint32_t *__restrict__ start,
                                                            const uint32_t *__restrict__ svals,
                                                            const SplatRec *__restrict__ rec,
                                                            int tiles_x, int tpv, int W, int H,
-                                                           uint32_t n_tiles, float thr, float thr_cull,
-                                                           float *__restrict__ img,
+                                                           uint32_t n_tiles, int n_chunks, float thr,
+                                                           float thr_cull, float *__restrict__ img,
                                                            unsigned long long *__restrict__ counter) {
-  __shared__ float4 s_cw_all[kTilesPerBlock][kWave + 1];
-  __shared__ float2 s_xy_all[kTilesPerBlock][kWave + 1];
-  __shared__ uint8_t s_list_all[kTilesPerBlock][4][kWave];
+  __shared__ float4 s_cw_all[TPB][kWave + 1];
+  __shared__ float2 s_xy_all[TPB][kWave + 1];
+  __shared__ uint8_t s_list_all[TPB][4][kWave];
   const int wid = threadIdx.x / kWave;
   float4 *s_cw = s_cw_all[wid];
   float2 *s_xy = s_xy_all[wid];
   uint8_t(*s_list)[kWave] = s_list_all[wid];
-  const uint32_t tile = blockIdx.x * kTilesPerBlock + wid;
-  if (tile >= n_tiles) return;
+  // work unit = (tile, chunk): chunk c takes batches c, c + n_chunks, ... of
+  // the tile's list and writes its own partial image (n_chunks > 1)
+  const uint32_t unit = blockIdx.x * TPB + wid;
+  if (unit >= n_tiles * uint32_t(n_chunks)) return;
+  const uint32_t tile = unit / uint32_t(n_chunks);
+  const uint32_t chunk = unit - tile * uint32_t(n_chunks);
   const uint32_t v_local = tile / uint32_t(tpv);
   const uint32_t t = tile - v_local * uint32_t(tpv);
   const int ty = int(t) / tiles_x;
@@ -270,7 +272,7 @@ __global__ __launch_bounds__(kBlock) void splat_fwd_kernel(const uint32_t *__res
 #pragma unroll
   for (int k = 0; k < kRows; ++k) acc[k] = 0.f;
   const uint32_t b0 = start[tile], e = start[tile + 1];
-  for (uint32_t b = b0; b < e; b += kWave) {
+  for (uint32_t b = b0 + chunk * kWave; b < e; b += kWave * uint32_t(n_chunks)) {
     const uint32_t m = min(uint32_t(kWave), e - b);
     uint32_t mask = 0;
     if (uint32_t(lane) < m) {
@@ -326,7 +328,7 @@ __global__ __launch_bounds__(kBlock) void splat_fwd_kernel(const uint32_t *__res
     if (lane == 0 && n) atomicAdd(counter, n);
     return;
   }
-  float *out = img + uint64_t(v_local) * uint64_t(W) * uint64_t(H);
+  float *out = img + (uint64_t(chunk) * (n_tiles / uint32_t(tpv)) + v_local) * uint64_t(W) * uint64_t(H);
 #pragma unroll
   for (int k = 0; k < kRows; ++k) {
     const int y = ty * kTS + row0 + k;
@@ -351,22 +353,27 @@ __device__ __forceinline__ float bperm(int src_lane, float v) {
 // quadrant partials with wavefront permutes, in quadrant order, and writes
 // the pair's six sums to the pair's emission slot: no atomics, and the
 // summation order is fixed.
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void splat_bwd_kernel(
+template <int TPB>
+__global__ __launch_bounds__(kWave * TPB) __attribute__((amdgpu_waves_per_eu(8, 8))) void splat_bwd_kernel(
     const uint32_t *__restrict__ start, const uint32_t *__restrict__ svals,
-    const SplatRec *__restrict__ rec, int tiles_x, int tpv, int W, int H, uint32_t n_tiles, float thr,
-    float thr_cull, const float *__restrict__ gimg, float4 *__restrict__ partials) {
-  __shared__ float4 s_g4_all[kTilesPerBlock][kTS * kTS / 4];
-  __shared__ float4 s_cw_all[kTilesPerBlock][kWave + 1];
-  __shared__ float2 s_xy_all[kTilesPerBlock][kWave + 1];
-  __shared__ uint8_t s_cat_all[kTilesPerBlock][4 * kWave];
+    const SplatRec *__restrict__ rec, int tiles_x, int tpv, int W, int H, uint32_t n_tiles, int n_chunks,
+    float thr, float thr_cull, const float *__restrict__ gimg, float4 *__restrict__ partials) {
+  __shared__ float4 s_g4_all[TPB][kTS * kTS / 4];
+  __shared__ float4 s_cw_all[TPB][kWave + 1];
+  __shared__ float2 s_xy_all[TPB][kWave + 1];
+  __shared__ uint8_t s_cat_all[TPB][4 * kWave];
   const int wid = threadIdx.x / kWave;
   float4 *s_g4 = s_g4_all[wid];
   float *s_g = reinterpret_cast<float *>(s_g4);
   float4 *s_cw = s_cw_all[wid];
   float2 *s_xy = s_xy_all[wid];
   uint8_t *s_cat = s_cat_all[wid];
-  const uint32_t tile = blockIdx.x * kTilesPerBlock + wid;
-  if (tile >= n_tiles) return;
+  // work unit = (tile, chunk): chunk c takes batches c, c + n_chunks, ...
+  // (each pair's sums go to its own slot, so chunks are independent)
+  const uint32_t unit = blockIdx.x * TPB + wid;
+  if (unit >= n_tiles * uint32_t(n_chunks)) return;
+  const uint32_t tile = unit / uint32_t(n_chunks);
+  const uint32_t chunk = unit - tile * uint32_t(n_chunks);
   const uint32_t v_local = tile / uint32_t(tpv);
   const uint32_t t = tile - v_local * uint32_t(tpv);
   const int ty = int(t) / tiles_x;
@@ -383,7 +390,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
   const float tx0 = float(tx * kTS) + 0.5f, ty0 = float(ty * kTS) + 0.5f;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const uint32_t b0 = start[tile], e = start[tile + 1];
-  for (uint32_t b = b0; b < e; b += kWave) {
+  for (uint32_t b = b0 + chunk * kWave; b < e; b += kWave * uint32_t(n_chunks)) {
     const uint32_t m = min(uint32_t(kWave), e - b);
     uint32_t mask = 0, slot = 0;
     if (uint32_t(lane) < m) {
@@ -660,8 +667,10 @@ GeomDev make_geom_dev(const fgs_geom *geom, const fgs_opts *o, int view_begin, c
 
 // Steps 1-5. On success the workspace holds records, sorted lists and tile
 // starts; *Lout describes them.
+// extra_bytes: room the caller needs after the lists (partial images).
 int build_lists(const fgs_gaussians *g, const fgs_geom *geom, int32_t view_begin, int32_t view_count,
-                const fgs_opts *o, fgs_workspace *ws, hipStream_t s, RastLayout *Lout) {
+                const fgs_opts *o, fgs_workspace *ws, hipStream_t s, RastLayout *Lout,
+                uint64_t extra_bytes = 0) {
   const uint64_t R = uint64_t(view_count) * uint64_t(g->n);
   const TileGrid tg = tile_grid(geom->det_w, geom->det_h);
   const uint64_t T = uint64_t(view_count) * uint64_t(tg.tpv);
@@ -693,11 +702,11 @@ int build_lists(const fgs_gaussians *g, const fgs_geom *geom, int32_t view_begin
     return fail(FGS_E_UNSUPPORTED, "more than 2^32 (tile, Gaussian) pairs in one call; split the views");
   const uint64_t K = K64;
   L = rast_layout(R, T, K);
-  ws->needed = L.total;
+  ws->needed = L.total + extra_bytes;
   ws->n_pairs = K;
   ws->n_records = R;
   ws->n_tiles = T;
-  if (ws->bytes < L.total) return fail(FGS_E_CAPACITY, "workspace too small for the tile lists");
+  if (ws->bytes < L.total + extra_bytes) return fail(FGS_E_CAPACITY, "workspace too small for the tile lists");
   if (K > 0) {
     emit_kernel<<<grid_for(R, 256), 256, 0, s>>>(R, g->n, tg.tiles_x, tg.tpv, at<ushort4>(b, L.rect),
                                                   at<uint32_t>(b, L.offset), at<uint32_t>(b, L.keys),
@@ -731,19 +740,33 @@ extern "C" int fgs_project_views_fwd(const fgs_gaussians *g, const fgs_geom *geo
   if (st != FGS_OK) return st;
   if (!img) return fail(FGS_E_INVALID, "null image");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  const TileGrid tg = tile_grid(geom->det_w, geom->det_h);
+  const uint64_t T = uint64_t(view_count) * uint64_t(tg.tpv);
+  const int chunks = chunks_per_tile(T);
+  const uint64_t n_img = uint64_t(view_count) * uint64_t(geom->det_w) * uint64_t(geom->det_h);
+  // partial images of the chunks, after the lists (only when chunked)
+  const uint64_t part_bytes = chunks > 1 ? uint64_t(chunks) * n_img * sizeof(float) + 256 : 0;
   RastLayout L;
-  st = build_lists(g, geom, view_begin, view_count, opts, ws, s, &L);
+  st = build_lists(g, geom, view_begin, view_count, opts, ws, s, &L, part_bytes);
   if (st != FGS_OK) return st;
   void *b = ws->ptr;
+  float *part = chunks > 1 ? at<float>(b, (L.total + 255) / 256 * 256) : img;
   const uint32_t *sv = at<uint32_t>(b, L.sorted_in_alt ? L.vals_alt : L.vals);
   const float thr = -0.5f * kLog2e * opts->kappa * opts->kappa;
-  const TileGrid tg = tile_grid(geom->det_w, geom->det_h);
   hipEvent_t *ev = static_cast<hipEvent_t *>(opts->events);
   if (ev) FGS_HIP(hipEventRecord(ev[0], s));
-  splat_fwd_kernel<false><<<grid_for(L.T, kTilesPerBlock), kBlock, 0, s>>>(
-      at<uint32_t>(b, L.start), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv,
-      geom->det_w, geom->det_h, uint32_t(L.T), thr, thr * kCullSlack, img, nullptr);
+  const uint64_t units = L.T * uint64_t(chunks);
+  with_tiles_per_block(units, [&](auto tpb) {
+    constexpr int TPB = decltype(tpb)::value;
+    splat_fwd_kernel<false, TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
+        at<uint32_t>(b, L.start), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
+        uint32_t(L.T), chunks, thr, thr * kCullSlack, part, nullptr);
+  });
   FGS_LAUNCH_CHECK("splat_fwd_kernel");
+  if (chunks > 1) {
+    st = sum_chunks(part, chunks, n_img, img, s);
+    if (st != FGS_OK) return st;
+  }
   if (ev) FGS_HIP(hipEventRecord(ev[1], s));
   return FGS_OK;
 }
@@ -765,9 +788,14 @@ extern "C" int fgs_project_views_support(const fgs_gaussians *g, const fgs_geom 
   const uint32_t *sv = at<uint32_t>(b, L.sorted_in_alt ? L.vals_alt : L.vals);
   const float thr = -0.5f * kLog2e * opts->kappa * opts->kappa;
   const TileGrid tg = tile_grid(geom->det_w, geom->det_h);
-  splat_fwd_kernel<true><<<grid_for(L.T, kTilesPerBlock), kBlock, 0, s>>>(
-      at<uint32_t>(b, L.start), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv,
-      geom->det_w, geom->det_h, uint32_t(L.T), thr, thr * kCullSlack, nullptr, cnt);
+  const int chunks = chunks_per_tile(L.T);
+  const uint64_t units = L.T * uint64_t(chunks);
+  with_tiles_per_block(units, [&](auto tpb) {
+    constexpr int TPB = decltype(tpb)::value;
+    splat_fwd_kernel<true, TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
+        at<uint32_t>(b, L.start), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
+        uint32_t(L.T), chunks, thr, thr * kCullSlack, nullptr, cnt);
+  });
   FGS_LAUNCH_CHECK("splat_fwd_kernel<count>");
   return FGS_OK;
 }
@@ -801,9 +829,14 @@ extern "C" int fgs_project_views_bwd(const fgs_gaussians *g, const fgs_geom *geo
   hipEvent_t *ev = static_cast<hipEvent_t *>(opts->events);
   if (ev) FGS_HIP(hipEventRecord(ev[0], s));
   if (L.K > 0) {
-    splat_bwd_kernel<<<grid_for(L.T, kTilesPerBlock), kBlock, 0, s>>>(
-        at<uint32_t>(b, L.start), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
-        uint32_t(L.T), thr, thr * kCullSlack, grad_img, at<float4>(b, L.partials));
+    const int chunks = chunks_per_tile(L.T);
+    const uint64_t units = L.T * uint64_t(chunks);
+    with_tiles_per_block(units, [&](auto tpb) {
+      constexpr int TPB = decltype(tpb)::value;
+      splat_bwd_kernel<TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
+          at<uint32_t>(b, L.start), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
+          uint32_t(L.T), chunks, thr, thr * kCullSlack, grad_img, at<float4>(b, L.partials));
+    });
     FGS_LAUNCH_CHECK("splat_bwd_kernel");
   }
   if (ev) FGS_HIP(hipEventRecord(ev[1], s));

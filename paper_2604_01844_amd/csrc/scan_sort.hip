@@ -278,3 +278,26 @@ int radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_
 }
 
 }  // namespace fgs
+
+namespace fgs {
+namespace {
+
+__global__ __launch_bounds__(256) void sum_chunks_kernel(const float *__restrict__ part, int chunks, uint64_t n,
+                                                         float *__restrict__ out) {
+  const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float acc = part[i];
+  for (int c = 1; c < chunks; ++c) acc += part[uint64_t(c) * n + i];
+  out[i] = acc;
+}
+
+}  // namespace
+
+int sum_chunks(const float *part, int chunks, uint64_t n, float *out, hipStream_t s) {
+  if (n == 0) return FGS_OK;
+  sum_chunks_kernel<<<grid_for(n, 256), 256, 0, s>>>(part, chunks, n, out);
+  FGS_LAUNCH_CHECK("sum_chunks_kernel");
+  return FGS_OK;
+}
+
+}  // namespace fgs

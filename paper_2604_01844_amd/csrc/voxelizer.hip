@@ -22,8 +22,6 @@ namespace {
 
 constexpr int kVT = 8;     // voxel tile side
 constexpr int kWave = 64;
-constexpr int kTilesPerBlock = 16;  // independent tiles per workgroup, one per wave
-constexpr int kBlock = kWave * kTilesPerBlock;
 
 struct __align__(16) Rect3 {
   unsigned short v[8];     // x0, y0, z0, x1, y1, z1, 0, 0
@@ -154,20 +152,24 @@ __global__ __launch_bounds__(256) void vox_ranges_kernel(const uint32_t *__restr
 
 // kCount = true: count the (voxel, Gaussian) pairs in the support whose voxel
 // lies in the grid (the algorithmic work) instead of writing the volume.
-template <bool kCount>
-__global__ __launch_bounds__(kBlock) void vox_fwd_kernel(const uint32_t *__restrict__ start,
+template <bool kCount, int TPB>
+__global__ __launch_bounds__(kWave * TPB) void vox_fwd_kernel(const uint32_t *__restrict__ start,
                                                          const uint32_t *__restrict__ svals,
                                                          const float4 *__restrict__ prho,
                                                          const float4 *__restrict__ a0,
                                                          const float4 *__restrict__ a1, GridDev G,
-                                                         uint32_t n_tiles, float thr,
+                                                         uint32_t n_tiles, int n_chunks, float thr,
                                                          float *__restrict__ vol,
                                                          unsigned long long *__restrict__ counter) {
-  __shared__ float4 s_all[kTilesPerBlock][3][kWave];
+  __shared__ float4 s_all[TPB][3][kWave];
   const int wid = threadIdx.x / kWave;
   float4 *s_p = s_all[wid][0], *s_a0 = s_all[wid][1], *s_a1 = s_all[wid][2];
-  const uint32_t tile = blockIdx.x * kTilesPerBlock + wid;
-  if (tile >= n_tiles) return;
+  // work unit = (tile, chunk): chunk c takes batches c, c + n_chunks, ... of
+  // the tile's list and writes its own partial volume (n_chunks > 1)
+  const uint32_t unit = blockIdx.x * TPB + wid;
+  if (unit >= n_tiles * uint32_t(n_chunks)) return;
+  const uint32_t tile = unit / uint32_t(n_chunks);
+  const uint32_t chunk = unit - tile * uint32_t(n_chunks);
   const int tx = int(tile % uint32_t(G.nt[0]));
   const int tyz = int(tile / uint32_t(G.nt[0]));
   const int ty = tyz % G.nt[1];
@@ -180,7 +182,7 @@ __global__ __launch_bounds__(kBlock) void vox_fwd_kernel(const uint32_t *__restr
 #pragma unroll
   for (int k = 0; k < kVT; ++k) acc[k] = 0.f;
   const uint32_t b0 = start[tile], e = start[tile + 1];
-  for (uint32_t b = b0; b < e; b += kWave) {
+  for (uint32_t b = b0 + chunk * kWave; b < e; b += kWave * uint32_t(n_chunks)) {
     const uint32_t m = min(uint32_t(kWave), e - b);
     if (uint32_t(lane) < m) {
       const uint32_t r = svals[b + lane];
@@ -227,7 +229,8 @@ __global__ __launch_bounds__(kBlock) void vox_fwd_kernel(const uint32_t *__restr
     return;
   }
   if (y < G.dims[1] && z < G.dims[2]) {
-    float *row = vol + (uint64_t(z) * G.dims[1] + y) * uint64_t(G.dims[0]);
+    const uint64_t n_vox = uint64_t(G.dims[0]) * uint64_t(G.dims[1]) * uint64_t(G.dims[2]);
+    float *row = vol + uint64_t(chunk) * n_vox + (uint64_t(z) * G.dims[1] + y) * uint64_t(G.dims[0]);
 #pragma unroll
     for (int k = 0; k < kVT; ++k) {
       const int x = tx * kVT + k;
@@ -242,22 +245,26 @@ __global__ __launch_bounds__(kBlock) void vox_fwd_kernel(const uint32_t *__restr
 // a quadratic in cx with lane coefficients, and the moments are accumulated
 // against the constants cx, cx^2, then moved to the Gaussian's centre once
 // per pair. Branch-free loop body.
-__global__ __launch_bounds__(kBlock) void vox_bwd_kernel(const uint32_t *__restrict__ start,
+template <int TPB>
+__global__ __launch_bounds__(kWave * TPB) void vox_bwd_kernel(const uint32_t *__restrict__ start,
                                                          const uint32_t *__restrict__ svals,
                                                          const float4 *__restrict__ prho,
                                                          const float4 *__restrict__ a0,
                                                          const float4 *__restrict__ a1,
                                                          const Rect3 *__restrict__ rect,
                                                          const uint32_t *__restrict__ offset,
-                                                         GridDev G, uint32_t n_tiles, float thr,
+                                                         GridDev G, uint32_t n_tiles, int n_chunks, float thr,
                                                          const float *__restrict__ gvol,
                                                          float2 *__restrict__ partials) {
-  __shared__ float4 s_g4_all[kTilesPerBlock][kVT * kVT * kVT / 4];
+  __shared__ float4 s_g4_all[TPB][kVT * kVT * kVT / 4];
   const int wid = threadIdx.x / kWave;
   float4 *s_g4 = s_g4_all[wid];
   float *s_g = reinterpret_cast<float *>(s_g4);
-  const uint32_t tile = blockIdx.x * kTilesPerBlock + wid;
-  if (tile >= n_tiles) return;
+  // work unit = (tile, chunk): chunk c takes batches c, c + n_chunks, ...
+  const uint32_t unit = blockIdx.x * TPB + wid;
+  if (unit >= n_tiles * uint32_t(n_chunks)) return;
+  const uint32_t tile = unit / uint32_t(n_chunks);
+  const uint32_t chunk = unit - tile * uint32_t(n_chunks);
   const int tx = int(tile % uint32_t(G.nt[0]));
   const int tyz = int(tile / uint32_t(G.nt[0]));
   const int ty = tyz % G.nt[1];
@@ -273,7 +280,7 @@ __global__ __launch_bounds__(kBlock) void vox_bwd_kernel(const uint32_t *__restr
   const uint32_t b0 = start[tile], e = start[tile + 1];
   const float h = 0.5f * (kVT - 1);
   const float ox = float(tx * kVT) + h, oy = float(ty * kVT) + h, oz = float(tz * kVT) + h;
-  for (uint32_t b = b0; b < e; b += kWave) {
+  for (uint32_t b = b0 + chunk * kWave; b < e; b += kWave * uint32_t(n_chunks)) {
     const uint32_t k = b + lane;
     const bool active = k < e;
     float4 p = make_float4(ox, oy, oz, 0.f), c0 = make_float4(0.f, 0.f, 0.f, 0.f), c1 = c0;
@@ -489,8 +496,9 @@ GridDev make_grid_dev(const fgs_grid *grid, const fgs_opts *o) {
   return G;
 }
 
+// extra_bytes: room the caller needs after the lists (partial volumes).
 int vox_build(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *o, fgs_workspace *ws,
-              hipStream_t s, VoxLayout *Lout, GridDev *Gout) {
+              hipStream_t s, VoxLayout *Lout, GridDev *Gout, uint64_t extra_bytes = 0) {
   const GridDev G = make_grid_dev(grid, o);
   const uint64_t T = uint64_t(G.nt[0]) * G.nt[1] * G.nt[2];
   if (T >= 0xffffffffull) return fail(FGS_E_UNSUPPORTED, "too many voxel tiles");
@@ -521,11 +529,11 @@ int vox_build(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *o, f
     return fail(FGS_E_UNSUPPORTED, "more than 2^32 (tile, Gaussian) pairs; split the grid into slabs");
   const uint64_t K = K64;
   L = vox_layout(N, T, K);
-  ws->needed = L.total;
+  ws->needed = L.total + extra_bytes;
   ws->n_pairs = K;
   ws->n_records = N;
   ws->n_tiles = T;
-  if (ws->bytes < L.total) return fail(FGS_E_CAPACITY, "workspace too small for the tile lists");
+  if (ws->bytes < L.total + extra_bytes) return fail(FGS_E_CAPACITY, "workspace too small for the tile lists");
   if (K > 0) {
     vox_emit_kernel<<<grid_for(N, 256), 256, 0, s>>>(g->n, G.nt[0], G.nt[1], at<Rect3>(b, L.rect),
                                                       at<uint32_t>(b, L.offset), at<uint32_t>(b, L.keys),
@@ -574,19 +582,34 @@ extern "C" int fgs_voxelize_fwd(const fgs_gaussians *g, const fgs_grid *grid, co
   if (st != FGS_OK) return st;
   if (!vol) return fail(FGS_E_INVALID, "null volume");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  const uint64_t n_tiles = uint64_t((grid->dims[0] + kVT - 1) / kVT) * uint64_t((grid->dims[1] + kVT - 1) / kVT) *
+                           uint64_t((grid->dims[2] + kVT - 1) / kVT);
+  const int chunks = chunks_per_tile(n_tiles);
+  const uint64_t n_vox = uint64_t(grid->dims[0]) * uint64_t(grid->dims[1]) * uint64_t(grid->dims[2]);
+  // partial volumes of the chunks, after the lists (only when chunked)
+  const uint64_t part_bytes = chunks > 1 ? uint64_t(chunks) * n_vox * sizeof(float) + 256 : 0;
   VoxLayout L;
   GridDev G;
-  st = vox_build(g, grid, opts, ws, s, &L, &G);
+  st = vox_build(g, grid, opts, ws, s, &L, &G, part_bytes);
   if (st != FGS_OK) return st;
   void *b = ws->ptr;
+  float *part = chunks > 1 ? at<float>(b, (L.total + 255) / 256 * 256) : vol;
   const uint32_t *sv = at<uint32_t>(b, L.sorted_in_alt ? L.vals_alt : L.vals);
   const float thr = -0.5f * kLog2e * opts->kappa * opts->kappa;
   hipEvent_t *ev = static_cast<hipEvent_t *>(opts->events);
   if (ev) FGS_HIP(hipEventRecord(ev[0], s));
-  vox_fwd_kernel<false><<<grid_for(L.T, kTilesPerBlock), kBlock, 0, s>>>(
-      at<uint32_t>(b, L.start), sv, at<float4>(b, L.prho), at<float4>(b, L.a0), at<float4>(b, L.a1), G,
-      uint32_t(L.T), thr, vol, nullptr);
+  const uint64_t units = L.T * uint64_t(chunks);
+  with_tiles_per_block(units, [&](auto tpb) {
+    constexpr int TPB = decltype(tpb)::value;
+    vox_fwd_kernel<false, TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
+        at<uint32_t>(b, L.start), sv, at<float4>(b, L.prho), at<float4>(b, L.a0), at<float4>(b, L.a1), G,
+        uint32_t(L.T), chunks, thr, part, nullptr);
+  });
   FGS_LAUNCH_CHECK("vox_fwd_kernel");
+  if (chunks > 1) {
+    st = sum_chunks(part, chunks, n_vox, vol, s);
+    if (st != FGS_OK) return st;
+  }
   if (ev) FGS_HIP(hipEventRecord(ev[1], s));
   return FGS_OK;
 }
@@ -607,9 +630,14 @@ extern "C" int fgs_voxelize_support(const fgs_gaussians *g, const fgs_grid *grid
   FGS_LAUNCH_CHECK("zero_u64_kernel");
   const uint32_t *sv = at<uint32_t>(b, L.sorted_in_alt ? L.vals_alt : L.vals);
   const float thr = -0.5f * kLog2e * opts->kappa * opts->kappa;
-  vox_fwd_kernel<true><<<grid_for(L.T, kTilesPerBlock), kBlock, 0, s>>>(
-      at<uint32_t>(b, L.start), sv, at<float4>(b, L.prho), at<float4>(b, L.a0), at<float4>(b, L.a1), G,
-      uint32_t(L.T), thr, nullptr, cnt);
+  const int chunks = chunks_per_tile(L.T);
+  const uint64_t units = L.T * uint64_t(chunks);
+  with_tiles_per_block(units, [&](auto tpb) {
+    constexpr int TPB = decltype(tpb)::value;
+    vox_fwd_kernel<true, TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
+        at<uint32_t>(b, L.start), sv, at<float4>(b, L.prho), at<float4>(b, L.a0), at<float4>(b, L.a1), G,
+        uint32_t(L.T), chunks, thr, nullptr, cnt);
+  });
   FGS_LAUNCH_CHECK("vox_fwd_kernel<count>");
   return FGS_OK;
 }
@@ -641,10 +669,15 @@ extern "C" int fgs_voxelize_bwd(const fgs_gaussians *g, const fgs_grid *grid, co
   hipEvent_t *ev = static_cast<hipEvent_t *>(opts->events);
   if (ev) FGS_HIP(hipEventRecord(ev[0], s));
   if (L.K > 0) {
-    vox_bwd_kernel<<<grid_for(L.T, kTilesPerBlock), kBlock, 0, s>>>(
-        at<uint32_t>(b, L.start), sv, at<float4>(b, L.prho), at<float4>(b, L.a0), at<float4>(b, L.a1),
-        at<Rect3>(b, L.rect), at<uint32_t>(b, L.offset), G, uint32_t(L.T), thr, grad_vol,
-        at<float2>(b, L.partials));
+    const int chunks = chunks_per_tile(L.T);
+    const uint64_t units = L.T * uint64_t(chunks);
+    with_tiles_per_block(units, [&](auto tpb) {
+      constexpr int TPB = decltype(tpb)::value;
+      vox_bwd_kernel<TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
+          at<uint32_t>(b, L.start), sv, at<float4>(b, L.prho), at<float4>(b, L.a0), at<float4>(b, L.a1),
+          at<Rect3>(b, L.rect), at<uint32_t>(b, L.offset), G, uint32_t(L.T), chunks, thr, grad_vol,
+          at<float2>(b, L.partials));
+    });
     FGS_LAUNCH_CHECK("vox_bwd_kernel");
   }
   if (ev) FGS_HIP(hipEventRecord(ev[1], s));
