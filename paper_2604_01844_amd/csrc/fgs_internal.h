@@ -29,6 +29,22 @@ inline int chunks_per_tile(uint64_t n_tiles) {
   return int(c < 16 ? c : 16);
 }
 
+// Key emission is block-cooperative: a block of kEmitBlock threads takes
+// kEmitBlock consecutive records and writes their keys (which are contiguous
+// after the scan) in coalesced rounds of kEmitBlock, each thread finding its
+// key's record by binary search over the block's offsets in LDS.
+constexpr int kEmitBlock = 256;
+
+// Largest i in [0, n) with off[i] <= q, for off ascending (off[0] <= q).
+__device__ __forceinline__ int upper_index(const uint32_t *off, int n, uint32_t q) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= q) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
 // out[i] = sum over c = 0..chunks-1 (in order) of part[c * n + i].
 int sum_chunks(const float *part, int chunks, uint64_t n, float *out, hipStream_t s);
 

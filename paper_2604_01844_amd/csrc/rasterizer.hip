@@ -133,26 +133,41 @@ __global__ __launch_bounds__(256) void record_kernel(fgs_gaussians g, GeomDev G,
     atomicAdd(total64 + ((blockIdx.x * 4 + (threadIdx.x >> 6) + blockIdx.y * 7) & (kTotalSlots - 1)), w);
 }
 
-__global__ __launch_bounds__(256) void emit_kernel(uint64_t R, int64_t n, int tiles_x, int tpv,
-                                                   const ushort4 *__restrict__ rect,
-                                                   const uint32_t *__restrict__ offset,
-                                                   uint32_t *__restrict__ keys,
-                                                   uint32_t *__restrict__ vals, SplatRec *__restrict__ rec) {
-  const uint64_t r = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (r >= R) return;
-  uint32_t o = offset[r];
-  const uint32_t end = offset[r + 1];
-  if (o == end) return;
-  const ushort4 rc = rect[r];
-  const uint32_t wdt = uint32_t(rc.z) - rc.x + 1u;
-  rec[r].b.z = __uint_as_float(o - uint32_t(rc.y) * wdt - uint32_t(rc.x));
-  const uint32_t base = uint32_t(r / uint64_t(n)) * uint32_t(tpv);
-  for (int ty = rc.y; ty <= rc.w; ++ty)
-    for (int tx = rc.x; tx <= rc.z; ++tx) {
-      keys[o] = base + uint32_t(ty * tiles_x + tx);
-      vals[o] = uint32_t(r);
-      ++o;
+__global__ __launch_bounds__(kEmitBlock) void emit_kernel(uint64_t R, int64_t n, int tiles_x, int tpv,
+                                                          const ushort4 *__restrict__ rect,
+                                                          const uint32_t *__restrict__ offset,
+                                                          uint32_t *__restrict__ keys,
+                                                          uint32_t *__restrict__ vals, SplatRec *__restrict__ rec) {
+  __shared__ uint32_t s_off[kEmitBlock + 1];
+  __shared__ ushort4 s_rect[kEmitBlock];
+  const uint64_t r0 = uint64_t(blockIdx.x) * kEmitBlock;
+  const int nr = int(min(uint64_t(kEmitBlock), R - r0));
+  const int t = threadIdx.x;
+  if (t < nr) {
+    const uint64_t r = r0 + t;
+    const uint32_t o = offset[r];
+    const ushort4 rc = rect[r];
+    s_off[t] = o;
+    s_rect[t] = rc;
+    if (offset[r + 1] != o) {
+      const uint32_t wdt = uint32_t(rc.z) - rc.x + 1u;
+      rec[r].b.z = __uint_as_float(o - uint32_t(rc.y) * wdt - uint32_t(rc.x));
     }
+  }
+  if (t == 0) s_off[nr] = offset[r0 + nr];
+  __syncthreads();
+  const uint32_t o0 = s_off[0], oe = s_off[nr];
+  for (uint32_t q = o0 + t; q < oe; q += kEmitBlock) {
+    const int i = upper_index(s_off, nr, q);
+    const ushort4 rc = s_rect[i];
+    const uint32_t wdt = uint32_t(rc.z) - rc.x + 1u;
+    const uint32_t j = q - s_off[i];
+    const uint32_t dy = j / wdt;
+    const uint64_t r = r0 + i;
+    const uint32_t base = uint32_t(r / uint64_t(n)) * uint32_t(tpv);
+    keys[q] = base + (uint32_t(rc.y) + dy) * uint32_t(tiles_x) + uint32_t(rc.x) + (j - dy * wdt);
+    vals[q] = uint32_t(r);
+  }
 }
 
 // start[t] = first sorted position whose key is >= t, for t in [0, T].
@@ -708,7 +723,7 @@ int build_lists(const fgs_gaussians *g, const fgs_geom *geom, int32_t view_begin
   ws->n_tiles = T;
   if (ws->bytes < L.total + extra_bytes) return fail(FGS_E_CAPACITY, "workspace too small for the tile lists");
   if (K > 0) {
-    emit_kernel<<<grid_for(R, 256), 256, 0, s>>>(R, g->n, tg.tiles_x, tg.tpv, at<ushort4>(b, L.rect),
+    emit_kernel<<<grid_for(R, kEmitBlock), kEmitBlock, 0, s>>>(R, g->n, tg.tiles_x, tg.tpv, at<ushort4>(b, L.rect),
                                                   at<uint32_t>(b, L.offset), at<uint32_t>(b, L.keys),
                                                   at<uint32_t>(b, L.vals), at<SplatRec>(b, L.rec));
     FGS_LAUNCH_CHECK("emit_kernel");

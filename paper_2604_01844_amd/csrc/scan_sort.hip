@@ -129,11 +129,19 @@ __global__ __launch_bounds__(kThreads) void rs_hist_kernel(const uint32_t *__res
 // Stable scatter of one pass. Tile t covers input [t*4096, t*4096 + 4096);
 // wave w of the tile owns the contiguous quarter [w*1024, w*1024 + 1024),
 // processed 64 keys at a time, so (wave, round, lane) order is input order.
+// Keys are first placed in LDS in the tile's digit-sorted order, then
+// written out linearly: consecutive threads write consecutive positions of
+// each digit's run, so the global writes are coalesced.
 __global__ __launch_bounds__(kThreads) void rs_scatter_kernel(
     const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in, uint64_t n,
     int shift, int nbits, const uint32_t *__restrict__ hist_scanned, uint32_t n_tiles,
     uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out) {
   __shared__ uint32_t cnt[kWaves][kBins];
+  __shared__ uint32_t s_local[kBins];     // tile-local start of each digit's run
+  __shared__ uint32_t s_global[kBins];    // global start of each digit's run for this tile
+  __shared__ uint32_t s_keys[kTile];
+  __shared__ uint32_t s_vals[kTile];
+  __shared__ uint32_t s_wsum[kWaves];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const uint32_t mask = (1u << nbits) - 1u;
   for (int i = threadIdx.x; i < kWaves * kBins; i += kThreads) (&cnt[0][0])[i] = 0;
@@ -164,16 +172,39 @@ __global__ __launch_bounds__(kThreads) void rs_scatter_kernel(
     v[j] = valid ? vals_in[idx] : 0u;
   }
   __syncthreads();
-  // per digit: offset of this wave inside the tile's run of that digit,
-  // plus the tile's global offset for the digit
-  for (uint32_t d = threadIdx.x; d <= mask; d += kThreads) {
-    uint32_t run = hist_scanned[uint64_t(d) * n_tiles + blockIdx.x];
+  // per digit d: the tile's count, the waves' offsets inside the digit's run,
+  // then an exclusive scan of the counts over digits (the tile-local starts)
+  const int bins = int(mask) + 1;
+  const int per_thread = (bins + kThreads - 1) / kThreads;  // <= 2
+  uint32_t tot[2] = {0u, 0u};
+  for (int q = 0; q < per_thread; ++q) {
+    const int d = threadIdx.x * per_thread + q;
+    if (d < bins) {
+      uint32_t run = 0;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) {
-      uint32_t c = cnt[w][d];
-      cnt[w][d] = run;
-      run += c;
+      for (int w = 0; w < kWaves; ++w) {
+        const uint32_t c = cnt[w][d];
+        cnt[w][d] = run;
+        run += c;
+      }
+      tot[q] = run;
+      s_global[d] = hist_scanned[uint64_t(d) * n_tiles + blockIdx.x];
     }
+  }
+  const uint32_t mine = tot[0] + tot[1];
+  uint32_t incl = mine;  // inclusive scan of `mine` over the block
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) s_wsum[wid] = incl;
+  __syncthreads();
+  uint32_t excl = incl - mine;
+  for (int w = 0; w < wid; ++w) excl += s_wsum[w];
+  for (int q = 0; q < per_thread; ++q) {
+    const int d = threadIdx.x * per_thread + q;
+    if (d < bins) s_local[d] = excl;
+    excl += tot[q];
   }
   __syncthreads();
 #pragma unroll
@@ -181,10 +212,20 @@ __global__ __launch_bounds__(kThreads) void rs_scatter_kernel(
     const uint64_t idx = wbase + uint64_t(j) * 64 + lane;
     if (idx < n) {
       const uint32_t d = (k[j] >> shift) & mask;
-      const uint32_t pos = cnt[wid][d] + rank[j];
-      keys_out[pos] = k[j];
-      vals_out[pos] = v[j];
+      const uint32_t lp = s_local[d] + cnt[wid][d] + rank[j];
+      s_keys[lp] = k[j];
+      s_vals[lp] = v[j];
     }
+  }
+  __syncthreads();
+  const uint64_t tbase = uint64_t(blockIdx.x) * kTile;
+  const int nt = int(min(uint64_t(kTile), n - tbase));
+  for (int i = threadIdx.x; i < nt; i += kThreads) {
+    const uint32_t key = s_keys[i];
+    const uint32_t d = (key >> shift) & mask;
+    const uint32_t pos = s_global[d] + (uint32_t(i) - s_local[d]);
+    keys_out[pos] = key;
+    vals_out[pos] = s_vals[i];
   }
 }
 

@@ -122,23 +122,36 @@ __global__ __launch_bounds__(256) void vox_record_kernel(fgs_gaussians g, GridDe
     atomicAdd(total64 + ((blockIdx.x * 4 + (threadIdx.x >> 6)) & (kTotalSlots - 1)), w);
 }
 
-__global__ __launch_bounds__(256) void vox_emit_kernel(int64_t n, int ntx, int nty,
-                                                       const Rect3 *__restrict__ rect,
-                                                       const uint32_t *__restrict__ offset,
-                                                       uint32_t *__restrict__ keys,
-                                                       uint32_t *__restrict__ vals) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  uint32_t o = offset[i];
-  if (o == offset[i + 1]) return;
-  const Rect3 rc = rect[i];
-  for (int tz = rc.v[2]; tz <= rc.v[5]; ++tz)
-    for (int ty = rc.v[1]; ty <= rc.v[4]; ++ty)
-      for (int tx = rc.v[0]; tx <= rc.v[3]; ++tx) {
-        keys[o] = uint32_t((tz * nty + ty) * ntx + tx);
-        vals[o] = uint32_t(i);
-        ++o;
-      }
+__global__ __launch_bounds__(kEmitBlock) void vox_emit_kernel(int64_t n, int ntx, int nty,
+                                                              const Rect3 *__restrict__ rect,
+                                                              const uint32_t *__restrict__ offset,
+                                                              uint32_t *__restrict__ keys,
+                                                              uint32_t *__restrict__ vals) {
+  __shared__ uint32_t s_off[kEmitBlock + 1];
+  __shared__ Rect3 s_rect[kEmitBlock];
+  const int64_t i0 = int64_t(blockIdx.x) * kEmitBlock;
+  const int nr = int(min(int64_t(kEmitBlock), n - i0));
+  const int t = threadIdx.x;
+  if (t < nr) {
+    s_off[t] = offset[i0 + t];
+    s_rect[t] = rect[i0 + t];
+  }
+  if (t == 0) s_off[nr] = offset[i0 + nr];
+  __syncthreads();
+  const uint32_t o0 = s_off[0], oe = s_off[nr];
+  for (uint32_t q = o0 + t; q < oe; q += kEmitBlock) {
+    const int i = upper_index(s_off, nr, q);
+    const Rect3 rc = s_rect[i];
+    const uint32_t nx = uint32_t(rc.v[3]) - rc.v[0] + 1u, ny = uint32_t(rc.v[4]) - rc.v[1] + 1u;
+    const uint32_t j = q - s_off[i];
+    const uint32_t jz = j / (nx * ny);
+    const uint32_t jxy = j - jz * nx * ny;
+    const uint32_t jy = jxy / nx;
+    const uint32_t jx = jxy - jy * nx;
+    const uint32_t tz = rc.v[2] + jz, ty = rc.v[1] + jy, tx = rc.v[0] + jx;
+    keys[q] = (tz * uint32_t(nty) + ty) * uint32_t(ntx) + tx;
+    vals[q] = uint32_t(i0 + i);
+  }
 }
 
 __global__ __launch_bounds__(256) void vox_ranges_kernel(const uint32_t *__restrict__ skeys, uint64_t K,
@@ -535,7 +548,7 @@ int vox_build(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *o, f
   ws->n_tiles = T;
   if (ws->bytes < L.total + extra_bytes) return fail(FGS_E_CAPACITY, "workspace too small for the tile lists");
   if (K > 0) {
-    vox_emit_kernel<<<grid_for(N, 256), 256, 0, s>>>(g->n, G.nt[0], G.nt[1], at<Rect3>(b, L.rect),
+    vox_emit_kernel<<<grid_for(N, kEmitBlock), kEmitBlock, 0, s>>>(g->n, G.nt[0], G.nt[1], at<Rect3>(b, L.rect),
                                                       at<uint32_t>(b, L.offset), at<uint32_t>(b, L.keys),
                                                       at<uint32_t>(b, L.vals));
     FGS_LAUNCH_CHECK("vox_emit_kernel");
