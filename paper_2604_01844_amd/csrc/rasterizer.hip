@@ -513,28 +513,57 @@ __global__ __launch_bounds__(kWave * TPB) __attribute__((amdgpu_waves_per_eu(8, 
   }
 }
 
+// Per record: reduce its contiguous partial slots, then the chain rule to
+// the 11 parameters. A block takes 256 consecutive records of one view. The
+// slots are read by groups of kGradLanes lanes, one record per group at a
+// time, each lane taking every kGradLanes-th slot (consecutive lanes read
+// consecutive 32-byte slots), then summed across the group in a fixed
+// butterfly order; one thread per record then applies the chain rule.
+constexpr int kGradLanes = 8;
+
 __global__ __launch_bounds__(256) void record_grad_kernel(fgs_gaussians g, GeomDev G,
                                                           const uint32_t *__restrict__ offset,
                                                           const float4 *__restrict__ partials,
                                                           uint64_t R, float *__restrict__ grad_rec) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= g.n) return;
+  __shared__ float s_sum[256][7];
+  const int t = threadIdx.x;
+  const int64_t i0 = int64_t(blockIdx.x) * 256;
   const int v_local = blockIdx.y;
-  const uint64_t r = uint64_t(v_local) * uint64_t(g.n) + uint64_t(i);
-  const uint32_t o = offset[r], end = offset[r + 1];
+  const uint64_t rbase = uint64_t(v_local) * uint64_t(g.n);
+  const int li = t % kGradLanes;
+  for (int idx = t / kGradLanes; idx < 256; idx += 256 / kGradLanes) {
+    float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (i0 + idx < g.n) {
+      const uint64_t r = rbase + uint64_t(i0 + idx);
+      const uint32_t o = offset[r], end = offset[r + 1];
+      for (uint32_t p = o + li; p < end; p += kGradLanes) {
+        const float4 a = partials[2 * uint64_t(p) + 0];
+        const float2 b = *reinterpret_cast<const float2 *>(&partials[2 * uint64_t(p) + 1]);
+        acc[0] += a.x; acc[1] += a.y; acc[2] += a.z;
+        acc[3] += a.w; acc[4] += b.x; acc[5] += b.y;
+      }
+    }
+#pragma unroll
+    for (int d = 1; d < kGradLanes; d <<= 1)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) acc[c] += __shfl_xor(acc[c], d, kGradLanes);
+    if (li == 0)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) s_sum[idx][c] = acc[c];
+  }
+  __syncthreads();
+  const int64_t i = i0 + t;
+  if (i >= g.n) return;
+  const uint64_t r = rbase + uint64_t(i);
   float out[11];
-  if (o == end) {
+  if (offset[r] == offset[r + 1]) {
 #pragma unroll
     for (int c = 0; c < 11; ++c) grad_rec[uint64_t(c) * R + r] = 0.f;
     return;
   }
-  float sums[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  for (uint32_t p = o; p < end; ++p) {
-    const float4 a = partials[2 * uint64_t(p) + 0];
-    const float2 b = *reinterpret_cast<const float2 *>(&partials[2 * uint64_t(p) + 1]);
-    sums[0] += a.x; sums[1] += a.y; sums[2] += a.z;
-    sums[3] += a.w; sums[4] += b.x; sums[5] += b.y;
-  }
+  float sums[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) sums[c] = s_sum[t][c];
   GaussParams P;
   load_gauss(g, i, P);
   ViewFrame F;

@@ -122,15 +122,19 @@ __global__ __launch_bounds__(256) void vox_record_kernel(fgs_gaussians g, GridDe
     atomicAdd(total64 + ((blockIdx.x * 4 + (threadIdx.x >> 6)) & (kTotalSlots - 1)), w);
 }
 
+// A Gaussian spans hundreds of voxel tiles, so a block takes only
+// kVoxEmitRecords Gaussians (enough blocks to fill the chip).
+constexpr int kVoxEmitRecords = 32;
+
 __global__ __launch_bounds__(kEmitBlock) void vox_emit_kernel(int64_t n, int ntx, int nty,
                                                               const Rect3 *__restrict__ rect,
                                                               const uint32_t *__restrict__ offset,
                                                               uint32_t *__restrict__ keys,
                                                               uint32_t *__restrict__ vals) {
-  __shared__ uint32_t s_off[kEmitBlock + 1];
-  __shared__ Rect3 s_rect[kEmitBlock];
-  const int64_t i0 = int64_t(blockIdx.x) * kEmitBlock;
-  const int nr = int(min(int64_t(kEmitBlock), n - i0));
+  __shared__ uint32_t s_off[kVoxEmitRecords + 1];
+  __shared__ Rect3 s_rect[kVoxEmitRecords];
+  const int64_t i0 = int64_t(blockIdx.x) * kVoxEmitRecords;
+  const int nr = int(min(int64_t(kVoxEmitRecords), n - i0));
   const int t = threadIdx.x;
   if (t < nr) {
     s_off[t] = offset[i0 + t];
@@ -374,25 +378,54 @@ __global__ __launch_bounds__(kWave * TPB) void vox_bwd_kernel(const uint32_t *__
   }
 }
 
+// Per Gaussian: reduce its contiguous partial slots (ten moments each), then
+// the chain rule. A block takes kGradGauss consecutive Gaussians; their slots
+// are read by groups of kGradLanes lanes (consecutive lanes, consecutive
+// slots) and summed across the group in a fixed butterfly order; one thread
+// per Gaussian then applies the chain rule.
+constexpr int kGradGauss = 64;
+constexpr int kGradLanes = 32;
+
 __global__ __launch_bounds__(256) void vox_grad_kernel(fgs_gaussians g, GridDev G,
                                                        const uint32_t *__restrict__ offset,
                                                        const float2 *__restrict__ partials,
                                                        fgs_gaussian_grads out, int accumulate) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  __shared__ float s_sum[kGradGauss][11];
+  const int t = threadIdx.x;
+  const int64_t i0 = int64_t(blockIdx.x) * kGradGauss;
+  const int li = t % kGradLanes;
+  for (int idx = t / kGradLanes; idx < kGradGauss; idx += 256 / kGradLanes) {
+    float acc[10];
+#pragma unroll
+    for (int c = 0; c < 10; ++c) acc[c] = 0.f;
+    if (i0 + idx < g.n) {
+      const uint32_t o = offset[i0 + idx], end = offset[i0 + idx + 1];
+      for (uint32_t q = o + li; q < end; q += kGradLanes) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+          const float2 v = partials[5 * uint64_t(q) + c];
+          acc[2 * c] += v.x;
+          acc[2 * c + 1] += v.y;
+        }
+      }
+    }
+#pragma unroll
+    for (int d = 1; d < kGradLanes; d <<= 1)
+#pragma unroll
+      for (int c = 0; c < 10; ++c) acc[c] += __shfl_xor(acc[c], d, kGradLanes);
+    if (li == 0)
+#pragma unroll
+      for (int c = 0; c < 10; ++c) s_sum[idx][c] = acc[c];
+  }
+  __syncthreads();
+  if (t >= kGradGauss) return;
+  const int64_t i = i0 + t;
   if (i >= g.n) return;
   const int64_t n = g.n;
   const uint32_t o = offset[i], end = offset[i + 1];
   float s[10];
 #pragma unroll
-  for (int c = 0; c < 10; ++c) s[c] = 0.f;
-  for (uint32_t q = o; q < end; ++q) {
-#pragma unroll
-    for (int c = 0; c < 5; ++c) {
-      const float2 v = partials[5 * uint64_t(q) + c];
-      s[2 * c] += v.x;
-      s[2 * c + 1] += v.y;
-    }
-  }
+  for (int c = 0; c < 10; ++c) s[c] = s_sum[t][c];
   float res[11];
 #pragma unroll
   for (int c = 0; c < 11; ++c) res[c] = 0.f;
@@ -548,7 +581,7 @@ int vox_build(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *o, f
   ws->n_tiles = T;
   if (ws->bytes < L.total + extra_bytes) return fail(FGS_E_CAPACITY, "workspace too small for the tile lists");
   if (K > 0) {
-    vox_emit_kernel<<<grid_for(N, kEmitBlock), kEmitBlock, 0, s>>>(g->n, G.nt[0], G.nt[1], at<Rect3>(b, L.rect),
+    vox_emit_kernel<<<grid_for(N, kVoxEmitRecords), kEmitBlock, 0, s>>>(g->n, G.nt[0], G.nt[1], at<Rect3>(b, L.rect),
                                                       at<uint32_t>(b, L.offset), at<uint32_t>(b, L.keys),
                                                       at<uint32_t>(b, L.vals));
     FGS_LAUNCH_CHECK("vox_emit_kernel");
@@ -694,7 +727,7 @@ extern "C" int fgs_voxelize_bwd(const fgs_gaussians *g, const fgs_grid *grid, co
     FGS_LAUNCH_CHECK("vox_bwd_kernel");
   }
   if (ev) FGS_HIP(hipEventRecord(ev[1], s));
-  vox_grad_kernel<<<grid_for(uint64_t(g->n), 256), 256, 0, s>>>(*g, G, at<uint32_t>(b, L.offset),
+  vox_grad_kernel<<<grid_for(uint64_t(g->n), kGradGauss), 256, 0, s>>>(*g, G, at<uint32_t>(b, L.offset),
                                                                 at<float2>(b, L.partials), *out,
                                                                 opts->accumulate);
   FGS_LAUNCH_CHECK("vox_grad_kernel");
