@@ -70,6 +70,10 @@ __device__ __forceinline__ void vox_span(float c, float r, int n_tiles, int &t0,
 }
 
 constexpr int kTotalSlots = 64;
+// The tile culling test keeps tiles whose best voxel centre reaches thr *
+// kCullSlack (a Mahalanobis radius 0.05% beyond the support): a superset of
+// the per-voxel test.
+constexpr float kCullSlack = 1.001f;
 
 __global__ void zero_u64_kernel(unsigned long long *p, int n) {
   if (int(threadIdx.x) < n) p[threadIdx.x] = 0ull;
@@ -80,11 +84,8 @@ __global__ __launch_bounds__(256) void vox_record_kernel(fgs_gaussians g, GridDe
                                                          float4 *__restrict__ a0,
                                                          float4 *__restrict__ a1,
                                                          float4 *__restrict__ radii,
-                                                         Rect3 *__restrict__ rect,
-                                                         uint32_t *__restrict__ count,
-                                                         unsigned long long *__restrict__ total64) {
+                                                         Rect3 *__restrict__ rect) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  uint32_t cnt = 0;
   if (i < g.n) {
     GaussParams P;
     load_gauss(g, i, P);
@@ -111,50 +112,128 @@ __global__ __launch_bounds__(256) void vox_record_kernel(fgs_gaussians g, GridDe
         rc.v[3 + a] = static_cast<unsigned short>(t1[a]);
       }
       rc.v[6] = rc.v[7] = 0;
-      cnt = uint32_t(t1[0] - t0[0] + 1) * uint32_t(t1[1] - t0[1] + 1) * uint32_t(t1[2] - t0[2] + 1);
     }
     rect[i] = rc;
-    count[i] = cnt;
   }
-  unsigned long long w = cnt;
-  for (int d = 32; d > 0; d >>= 1) w += __shfl_xor(w, d, 64);
-  if ((threadIdx.x & 63) == 0 && w)
-    atomicAdd(total64 + ((blockIdx.x * 4 + (threadIdx.x >> 6)) & (kTotalSlots - 1)), w);
 }
 
-// A Gaussian spans hundreds of voxel tiles, so a block takes only
-// kVoxEmitRecords Gaussians (enough blocks to fill the chip).
-constexpr int kVoxEmitRecords = 32;
-
-__global__ __launch_bounds__(kEmitBlock) void vox_emit_kernel(int64_t n, int ntx, int nty,
-                                                              const Rect3 *__restrict__ rect,
-                                                              const uint32_t *__restrict__ offset,
-                                                              uint32_t *__restrict__ keys,
-                                                              uint32_t *__restrict__ vals) {
-  __shared__ uint32_t s_off[kVoxEmitRecords + 1];
-  __shared__ Rect3 s_rect[kVoxEmitRecords];
-  const int64_t i0 = int64_t(blockIdx.x) * kVoxEmitRecords;
-  const int nr = int(min(int64_t(kVoxEmitRecords), n - i0));
-  const int t = threadIdx.x;
-  if (t < nr) {
-    s_off[t] = offset[i0 + t];
-    s_rect[t] = rect[i0 + t];
+// Largest value of the pre-scaled (negative definite) form
+// arg(d) = c0.x dx^2 + dx (c0.y dy + c0.z dz) + c0.w dy^2 + c1.x dy dz + c1.y dz^2
+// over the box lo <= p + d <= hi. Its maximiser lies on one of the three
+// planes x_a = clamp(p_a); on each, the restricted 2D form is maximised over
+// the face rectangle along its two clamped lines (the same construction as
+// the rasterizer's quadrant test, one dimension up).
+__device__ float box_qmax(const float4 &c0, const float4 &c1, const float p[3], const float lo[3],
+                          const float hi[3]) {
+  const float M[3][3] = {{c0.x, 0.5f * c0.y, 0.5f * c0.z},
+                         {0.5f * c0.y, c0.w, 0.5f * c1.x},
+                         {0.5f * c0.z, 0.5f * c1.x, c1.y}};
+  float best = -INFINITY;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int b = (a + 1) % 3, c = (a + 2) % 3;
+    const float D = fminf(fmaxf(p[a], lo[a]), hi[a]) - p[a];
+    const float lb = lo[b] - p[b], hb = hi[b] - p[b], lc = lo[c] - p[c], hc = hi[c] - p[c];
+    const float mbb = M[b][b], mcc = M[c][c], mbc = M[b][c], mab = M[a][b], mac = M[a][c];
+    const float det = mbb * mcc - mbc * mbc;
+    if (!(det > 0.f)) return 0.f;  // degenerate form: keep the tile
+    const float ybh = -D * (mcc * mab - mbc * mac) / det;
+    const float ych = -D * (mbb * mac - mbc * mab) / det;
+    const float yb1 = fminf(fmaxf(ybh, lb), hb);
+    const float yc1 = fminf(fmaxf(-(mbc * yb1 + D * mac) / mcc, lc), hc);
+    const float yc2 = fminf(fmaxf(ych, lc), hc);
+    const float yb2 = fminf(fmaxf(-(mbc * yc2 + D * mab) / mbb, lb), hb);
+    const float base = M[a][a] * D * D;
+    const float f1 = base + 2.f * D * (mab * yb1 + mac * yc1) + yb1 * (mbb * yb1 + 2.f * mbc * yc1) + mcc * yc1 * yc1;
+    const float f2 = base + 2.f * D * (mab * yb2 + mac * yc2) + yb2 * (mbb * yb2 + 2.f * mbc * yc2) + mcc * yc2 * yc2;
+    best = fmaxf(best, fmaxf(f1, f2));
   }
-  if (t == 0) s_off[nr] = offset[i0 + nr];
-  __syncthreads();
-  const uint32_t o0 = s_off[0], oe = s_off[nr];
-  for (uint32_t q = o0 + t; q < oe; q += kEmitBlock) {
-    const int i = upper_index(s_off, nr, q);
-    const Rect3 rc = s_rect[i];
-    const uint32_t nx = uint32_t(rc.v[3]) - rc.v[0] + 1u, ny = uint32_t(rc.v[4]) - rc.v[1] + 1u;
-    const uint32_t j = q - s_off[i];
-    const uint32_t jz = j / (nx * ny);
-    const uint32_t jxy = j - jz * nx * ny;
-    const uint32_t jy = jxy / nx;
-    const uint32_t jx = jxy - jy * nx;
-    const uint32_t tz = rc.v[2] + jz, ty = rc.v[1] + jy, tx = rc.v[0] + jx;
-    keys[q] = (tz * uint32_t(nty) + ty) * uint32_t(ntx) + tx;
-    vals[q] = uint32_t(i0 + i);
+  return best;
+}
+
+// Tile j (row-major, x fastest) of rectangle rc, and whether the Gaussian's
+// support ellipsoid reaches one of its voxel centres (a superset test: the
+// threshold carries a small slack).
+__device__ __forceinline__ bool tile_hit(const Rect3 &rc, uint32_t j, const float4 &p, const float4 &c0,
+                                         const float4 &c1, float thr_cull, uint32_t &tx, uint32_t &ty,
+                                         uint32_t &tz) {
+  const uint32_t nx = uint32_t(rc.v[3]) - rc.v[0] + 1u, ny = uint32_t(rc.v[4]) - rc.v[1] + 1u;
+  const uint32_t jz = j / (nx * ny);
+  const uint32_t jxy = j - jz * nx * ny;
+  const uint32_t jy = jxy / nx;
+  tx = rc.v[0] + (jxy - jy * nx);
+  ty = rc.v[1] + jy;
+  tz = rc.v[2] + jz;
+  const float pc[3] = {p.x, p.y, p.z};
+  const float lo[3] = {float(tx * kVT), float(ty * kVT), float(tz * kVT)};
+  const float hi[3] = {lo[0] + float(kVT - 1), lo[1] + float(kVT - 1), lo[2] + float(kVT - 1)};
+  return box_qmax(c0, c1, pc, lo, hi) >= thr_cull;
+}
+
+__device__ __forceinline__ uint32_t rect_tiles(const Rect3 &rc) {
+  if (rc.v[0] > rc.v[3] || rc.v[1] > rc.v[4] || rc.v[2] > rc.v[5]) return 0u;
+  return (uint32_t(rc.v[3]) - rc.v[0] + 1u) * (uint32_t(rc.v[4]) - rc.v[1] + 1u) * (uint32_t(rc.v[5]) - rc.v[2] + 1u);
+}
+
+// One wave per Gaussian: the number of tiles of its rectangle that its
+// support reaches (the key count), and the 64-bit total.
+__global__ __launch_bounds__(256) void vox_count_kernel(int64_t n, const float4 *__restrict__ prho,
+                                                        const float4 *__restrict__ a0,
+                                                        const float4 *__restrict__ a1,
+                                                        const Rect3 *__restrict__ rect, float thr_cull,
+                                                        uint32_t *__restrict__ count,
+                                                        unsigned long long *__restrict__ total64) {
+  const int64_t i = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= n) return;
+  const Rect3 rc = rect[i];
+  const uint32_t nt = rect_tiles(rc);
+  const float4 p = prho[i], c0 = a0[i], c1 = a1[i];
+  uint32_t cnt = 0;
+  for (uint32_t j0 = 0; j0 < nt; j0 += 64) {
+    const uint32_t j = j0 + lane;
+    uint32_t tx, ty, tz;
+    const bool hit = j < nt && tile_hit(rc, j, p, c0, c1, thr_cull, tx, ty, tz);
+    cnt += __popcll(__ballot(hit));
+  }
+  if (lane == 0) {
+    count[i] = cnt;
+    if (cnt) atomicAdd(total64 + (uint64_t(i) & (kTotalSlots - 1)), (unsigned long long)cnt);
+  }
+}
+
+// One wave per Gaussian: the keys of the tiles its support reaches, in
+// row-major order, at its offset. The sort's value is the emission slot q
+// (a Gaussian's slots are contiguous, which is where the backward writes its
+// partial sums); gid[q] is the Gaussian.
+__global__ __launch_bounds__(256) void vox_emit_kernel(int64_t n, int ntx, int nty, const float4 *__restrict__ prho,
+                                                       const float4 *__restrict__ a0,
+                                                       const float4 *__restrict__ a1,
+                                                       const Rect3 *__restrict__ rect, float thr_cull,
+                                                       const uint32_t *__restrict__ offset,
+                                                       uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                                                       uint32_t *__restrict__ gid) {
+  const int64_t i = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= n) return;
+  uint32_t o = offset[i];
+  if (o == offset[i + 1]) return;
+  const Rect3 rc = rect[i];
+  const uint32_t nt = rect_tiles(rc);
+  const float4 p = prho[i], c0 = a0[i], c1 = a1[i];
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (uint32_t j0 = 0; j0 < nt; j0 += 64) {
+    const uint32_t j = j0 + lane;
+    uint32_t tx = 0, ty = 0, tz = 0;
+    const bool hit = j < nt && tile_hit(rc, j, p, c0, c1, thr_cull, tx, ty, tz);
+    const uint64_t bal = __ballot(hit);
+    if (hit) {
+      const uint32_t q = o + uint32_t(__popcll(bal & lt));
+      keys[q] = (tz * uint32_t(nty) + ty) * uint32_t(ntx) + tx;
+      vals[q] = q;
+      gid[q] = uint32_t(i);
+    }
+    o += uint32_t(__popcll(bal));
   }
 }
 
@@ -174,7 +253,8 @@ __global__ __launch_bounds__(kWave * TPB) void vox_fwd_kernel(const uint32_t *__
                                                          const uint32_t *__restrict__ svals,
                                                          const float4 *__restrict__ prho,
                                                          const float4 *__restrict__ a0,
-                                                         const float4 *__restrict__ a1, GridDev G,
+                                                         const float4 *__restrict__ a1,
+                                                         const uint32_t *__restrict__ gid, GridDev G,
                                                          uint32_t n_tiles, int n_chunks, float thr,
                                                          float *__restrict__ vol,
                                                          unsigned long long *__restrict__ counter) {
@@ -202,7 +282,7 @@ __global__ __launch_bounds__(kWave * TPB) void vox_fwd_kernel(const uint32_t *__
   for (uint32_t b = b0 + chunk * kWave; b < e; b += kWave * uint32_t(n_chunks)) {
     const uint32_t m = min(uint32_t(kWave), e - b);
     if (uint32_t(lane) < m) {
-      const uint32_t r = svals[b + lane];
+      const uint32_t r = gid[svals[b + lane]];
       s_p[lane] = prho[r];
       s_a0[lane] = a0[r];
       s_a1[lane] = a1[r];
@@ -268,8 +348,7 @@ __global__ __launch_bounds__(kWave * TPB) void vox_bwd_kernel(const uint32_t *__
                                                          const float4 *__restrict__ prho,
                                                          const float4 *__restrict__ a0,
                                                          const float4 *__restrict__ a1,
-                                                         const Rect3 *__restrict__ rect,
-                                                         const uint32_t *__restrict__ offset,
+                                                         const uint32_t *__restrict__ gid,
                                                          GridDev G, uint32_t n_tiles, int n_chunks, float thr,
                                                          const float *__restrict__ gvol,
                                                          float2 *__restrict__ partials) {
@@ -301,9 +380,10 @@ __global__ __launch_bounds__(kWave * TPB) void vox_bwd_kernel(const uint32_t *__
     const uint32_t k = b + lane;
     const bool active = k < e;
     float4 p = make_float4(ox, oy, oz, 0.f), c0 = make_float4(0.f, 0.f, 0.f, 0.f), c1 = c0;
-    uint32_t r = 0;
+    uint32_t q = 0;
     if (active) {
-      r = svals[k];
+      q = svals[k];
+      const uint32_t r = gid[q];
       p = prho[r];
       c0 = a0[r];
       c1 = a1[r];
@@ -365,15 +445,11 @@ __global__ __launch_bounds__(kWave * TPB) void vox_bwd_kernel(const uint32_t *__
       const float Mxy = fmaf(qx * qy, S0, fmaf(-qy, Sc, fmaf(-qx, Sy, Sxy)));
       const float Mxz = fmaf(qx * qz, S0, fmaf(-qz, Sc, fmaf(-qx, Sz, Sxz)));
       const float Myz = fmaf(qy * qz, S0, fmaf(-qz, Sy, fmaf(-qy, Sz, Syz)));
-      const Rect3 rc = rect[r];
-      const uint32_t nx = uint32_t(rc.v[3] - rc.v[0] + 1), ny = uint32_t(rc.v[4] - rc.v[1] + 1);
-      const uint32_t j = (uint32_t(tz - rc.v[2]) * ny + uint32_t(ty - rc.v[1])) * nx + uint32_t(tx - rc.v[0]);
-      const uint64_t q = uint64_t(offset[r]) + j;
-      partials[5 * q + 0] = make_float2(S0, Mx);
-      partials[5 * q + 1] = make_float2(My, Mz);
-      partials[5 * q + 2] = make_float2(Mxx, Mxy);
-      partials[5 * q + 3] = make_float2(Mxz, Myy);
-      partials[5 * q + 4] = make_float2(Myz, Mzz);
+      partials[5 * uint64_t(q) + 0] = make_float2(S0, Mx);
+      partials[5 * uint64_t(q) + 1] = make_float2(My, Mz);
+      partials[5 * uint64_t(q) + 2] = make_float2(Mxx, Mxy);
+      partials[5 * uint64_t(q) + 3] = make_float2(Mxz, Myy);
+      partials[5 * uint64_t(q) + 4] = make_float2(Myz, Mzz);
     }
   }
 }
@@ -478,7 +554,7 @@ struct VoxLayout {
   uint64_t N, T, K;
   uint64_t total64, prho, radii, rect, offset, a0, a1, scan_scratch, start;
   uint64_t fixed_end;
-  uint64_t keys, vals, keys_alt, vals_alt, sort_scratch, partials;
+  uint64_t keys, vals, keys_alt, vals_alt, gid, sort_scratch, partials;
   uint64_t total;
   bool sorted_in_alt;
 };
@@ -503,6 +579,7 @@ VoxLayout vox_layout(uint64_t N, uint64_t T, uint64_t K) {
   c.take<uint32_t>(K, &L.vals);
   c.take<uint32_t>(K, &L.keys_alt);
   c.take<uint32_t>(K, &L.vals_alt);
+  c.take<uint32_t>(K, &L.gid);
   c.take<uint32_t>(sort_scratch_words(K), &L.sort_scratch);
   c.take<float>(10 * K, &L.partials);
   L.total = c.used;
@@ -561,9 +638,13 @@ int vox_build(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *o, f
   FGS_LAUNCH_CHECK("zero_u64_kernel");
   vox_record_kernel<<<grid_for(N, 256), 256, 0, s>>>(*g, G, at<float4>(b, L.prho), at<float4>(b, L.a0),
                                                       at<float4>(b, L.a1), at<float4>(b, L.radii),
-                                                      at<Rect3>(b, L.rect), at<uint32_t>(b, L.offset),
-                                                      total64);
+                                                      at<Rect3>(b, L.rect));
   FGS_LAUNCH_CHECK("vox_record_kernel");
+  const float thr_cull = -0.5f * kLog2e * o->kappa * o->kappa * kCullSlack;
+  vox_count_kernel<<<grid_for(N, 4), 256, 0, s>>>(int64_t(N), at<float4>(b, L.prho), at<float4>(b, L.a0),
+                                                   at<float4>(b, L.a1), at<Rect3>(b, L.rect), thr_cull,
+                                                   at<uint32_t>(b, L.offset), total64);
+  FGS_LAUNCH_CHECK("vox_count_kernel");
   int st = exclusive_scan_u32(at<uint32_t>(b, L.offset), N, at<uint32_t>(b, L.scan_scratch), s);
   if (st != FGS_OK) return st;
   unsigned long long slots[kTotalSlots];
@@ -581,9 +662,10 @@ int vox_build(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *o, f
   ws->n_tiles = T;
   if (ws->bytes < L.total + extra_bytes) return fail(FGS_E_CAPACITY, "workspace too small for the tile lists");
   if (K > 0) {
-    vox_emit_kernel<<<grid_for(N, kVoxEmitRecords), kEmitBlock, 0, s>>>(g->n, G.nt[0], G.nt[1], at<Rect3>(b, L.rect),
-                                                      at<uint32_t>(b, L.offset), at<uint32_t>(b, L.keys),
-                                                      at<uint32_t>(b, L.vals));
+    vox_emit_kernel<<<grid_for(N, 4), 256, 0, s>>>(int64_t(N), G.nt[0], G.nt[1], at<float4>(b, L.prho),
+                                                    at<float4>(b, L.a0), at<float4>(b, L.a1), at<Rect3>(b, L.rect),
+                                                    thr_cull, at<uint32_t>(b, L.offset), at<uint32_t>(b, L.keys),
+                                                    at<uint32_t>(b, L.vals), at<uint32_t>(b, L.gid));
     FGS_LAUNCH_CHECK("vox_emit_kernel");
   }
   uint32_t *sk, *sv;
@@ -648,8 +730,8 @@ extern "C" int fgs_voxelize_fwd(const fgs_gaussians *g, const fgs_grid *grid, co
   with_tiles_per_block(units, [&](auto tpb) {
     constexpr int TPB = decltype(tpb)::value;
     vox_fwd_kernel<false, TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
-        at<uint32_t>(b, L.start), sv, at<float4>(b, L.prho), at<float4>(b, L.a0), at<float4>(b, L.a1), G,
-        uint32_t(L.T), chunks, thr, part, nullptr);
+        at<uint32_t>(b, L.start), sv, at<float4>(b, L.prho), at<float4>(b, L.a0), at<float4>(b, L.a1),
+        at<uint32_t>(b, L.gid), G, uint32_t(L.T), chunks, thr, part, nullptr);
   });
   FGS_LAUNCH_CHECK("vox_fwd_kernel");
   if (chunks > 1) {
@@ -681,8 +763,8 @@ extern "C" int fgs_voxelize_support(const fgs_gaussians *g, const fgs_grid *grid
   with_tiles_per_block(units, [&](auto tpb) {
     constexpr int TPB = decltype(tpb)::value;
     vox_fwd_kernel<true, TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
-        at<uint32_t>(b, L.start), sv, at<float4>(b, L.prho), at<float4>(b, L.a0), at<float4>(b, L.a1), G,
-        uint32_t(L.T), chunks, thr, nullptr, cnt);
+        at<uint32_t>(b, L.start), sv, at<float4>(b, L.prho), at<float4>(b, L.a0), at<float4>(b, L.a1),
+        at<uint32_t>(b, L.gid), G, uint32_t(L.T), chunks, thr, nullptr, cnt);
   });
   FGS_LAUNCH_CHECK("vox_fwd_kernel<count>");
   return FGS_OK;
@@ -721,8 +803,7 @@ extern "C" int fgs_voxelize_bwd(const fgs_gaussians *g, const fgs_grid *grid, co
       constexpr int TPB = decltype(tpb)::value;
       vox_bwd_kernel<TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
           at<uint32_t>(b, L.start), sv, at<float4>(b, L.prho), at<float4>(b, L.a0), at<float4>(b, L.a1),
-          at<Rect3>(b, L.rect), at<uint32_t>(b, L.offset), G, uint32_t(L.T), chunks, thr, grad_vol,
-          at<float2>(b, L.partials));
+          at<uint32_t>(b, L.gid), G, uint32_t(L.T), chunks, thr, grad_vol, at<float2>(b, L.partials));
     });
     FGS_LAUNCH_CHECK("vox_bwd_kernel");
   }
