@@ -6,15 +6,21 @@
 //   record kernel   per Gaussian: centre in voxel-index coordinates and rho
 //                   (float4, the position+radius packing of Sec. 3.5), the
 //                   voxel-unit inverse covariance pre-scaled by -log2(e)/2,
-//                   half-extents in voxels, the 3D rectangle of 8^3-voxel
-//                   tiles it touches and its tile count;
-//   scan / emit / stable radix sort / ranges as in the rasterizer;
+//                   half-extents in voxels and the 3D rectangle of 8^3-voxel
+//                   tiles its box touches;
+//   count kernel    one wave per Gaussian: of the rectangle's tiles, those
+//                   its support ellipsoid actually reaches (exact box test;
+//                   about 57% of the box's tiles for the standard scan);
+//   scan / emit     keys of the reached tiles; the sort's value is the
+//                   emission slot, whose Gaussian is gid[slot];
+//   stable radix sort / ranges as in the rasterizer;
 //   forward         one wave per 8^3 tile; each lane owns one x-row of 8
 //                   voxels; records staged in LDS in batches of 64;
 //   backward        one wave per tile; each lane owns one (tile, Gaussian)
 //                   pair and sums the ten moments sum g e {1, d, d d^T} over
-//                   the tile's 512 voxels; per Gaussian, its contiguous
-//                   partials are reduced in order and the chain rule applied.
+//                   the tile's 512 voxels into the pair's emission slot; per
+//                   Gaussian, its contiguous slots are reduced in a fixed
+//                   order and the chain rule applied.
 #include "fgs_internal.h"
 
 namespace fgs {
