@@ -14,10 +14,11 @@ Workloads (synthetic, seeded; they stand in for the paper's datasets):
 
 Prints ONE JSON line. `value` is view-pixels per second of whole steps;
 `voxels_per_s` the same for the voxel grid. For the scan workload the
-one-view optimisation step of the reconstruction loop (Sec. 3.4: forward,
-L1, backward for one view, plus a randomly placed 32^3 crop voxelized with
-the gradient of its total variation, then Adam) is also timed over one epoch
-of 75 steps (`s_per_view_step`, `s_per_epoch`). `roofline` is for the step's dominant
+one-view optimisation step of the reconstruction loop (Sec. 3.4, the loss
+of Eq. 5: forward for one view, L1 and SSIM with their gradients, backward,
+a randomly placed 32^3 crop voxelized with the gradient of its total
+variation, then Adam) is also timed over one epoch of 75 steps
+(`s_per_view_step`, `s_per_epoch`). `roofline` is for the step's dominant
 kernel, timed with HIP events that the library records around it on the
 stream it runs on; its work is the exact number of (pixel|voxel, Gaussian)
 support pairs, counted on the GPU. `cpu_baseline` times the FP64 oracle on a
@@ -62,7 +63,10 @@ WORKLOADS = {
                         "in the backward), voxelizer {NV}^3; fwd+bwd, L1 losses and Adam per step"),
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
-TV_WEIGHT = 0.05  # weight of the crop TV term in the one-view step (the paper prints none)
+# Weights of the SSIM and crop-TV terms of Eq. 5 in the one-view step (the
+# paper prints none).
+SSIM_WEIGHT = 0.25
+TV_WEIGHT = 0.05
 
 
 def log(msg):
@@ -280,10 +284,12 @@ def main():
         rng = np.random.Generator(np.random.PCG64(0))
         order = rng.permutation(V)
         tv = CropTV(grid, TV_WEIGHT, 32, dev)
+        ws_s = fgs.Workspace(dev)
 
         def view_step(v):
             fgs.project_views(*params, geom, int(v), 1, ws=ws_p, out=img1)
             _, g1 = fgs.l1_loss_grad(img1, i_gt[v:v + 1], ws=ws_l)
+            fgs.ssim_loss_grad(img1, i_gt[v:v + 1], scale=SSIM_WEIGHT, ws=ws_s, grad=g1, accumulate=True)
             fgs.project_views_backward(*params, geom, g1, int(v), 1, recompute=False, ws=ws_p, out=gp)
             tv.add_grad(params, gp, rng)
             state["step"] += 1

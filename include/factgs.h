@@ -235,6 +235,17 @@ int fgs_adam_step(float *param, const float *grad, const float *grad2, float *m,
 int fgs_psnr(const float *vol, const float *ref, int64_t n, float peak, float *out,
              fgs_workspace *ws, void *stream);
 
+/* SSIM term of Eq. 5 over n_views images [n_views][H][W] (device):
+ * loss[0] = scale * (1 - mean SSIM(img, gt)) with the local statistics of
+ * an 11-tap Gaussian window (sigma 1.5, zero outside the image) and the
+ * constants c1, c2 > 0 (0.01^2 and 0.03^2 for unit dynamic range). If grad
+ * != NULL it receives scale * d(1 - mean SSIM)/d img, added to its contents
+ * when accumulate != 0 (e.g. onto the L1 gradient), else overwriting them.
+ * Workspace: 12 bytes per pixel (with grad) plus 8 per 32x32 tile. */
+int fgs_ssim_loss_grad(const float *img, const float *gt, int32_t W, int32_t H, int32_t n_views, float c1,
+                       float c2, float scale, float *loss, float *grad, int32_t accumulate, fgs_workspace *ws,
+                       void *stream);
+
 /* 3D total variation of vol[nz][ny][nx] (the TV term of Eq. 5, on the
  * sampled sub-volume): loss[0] = scale * (1/n) sum over voxels and axes of
  * |V(i + e_a) - V(i)| (forward differences inside the grid, n = voxel

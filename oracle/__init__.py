@@ -34,6 +34,8 @@ Parity status of each function (what pins it in ``tests/test_oracle_pins.py``):
   linear fields and brute-force nearest neighbours.
 * ``tv_loss_grad``: pinned by a hand-computed volume, finite differences
   and the invariances of a total variation.
+* ``ssim_loss_grad``: pinned by SSIM(x, x) = 1, a brute-force windowed sum at
+  every pixel of a small case, and finite differences of the loss.
 * ``mlp`` (learned initializer): BF16 rounding pinned against torch's
   bfloat16 conversion, the backward against finite differences of the
   unrounded network, the canonical targets against their defining
@@ -418,6 +420,44 @@ def tv_loss_grad(vol32, scale: float = 1.0):
         grad[tuple(lo)] -= sg                 # V(i) enters d(i) with sign -1
         grad[tuple(hi)] += sg                 # V(i + e_a) enters d(i) with sign +1
     return scale * loss / n, grad * (scale / n)
+
+
+def ssim_window(size: int = 11, sigma: float = 1.5) -> np.ndarray:
+    """Normalised 1D Gaussian window of the SSIM index (the 2D window is its
+    outer product)."""
+    k = np.arange(size) - (size - 1) / 2
+    w = np.exp(-k * k / (2 * sigma * sigma))
+    return w / w.sum()
+
+
+def ssim_loss_grad(img, gt, scale: float = 1.0, c1: float = 1e-4, c2: float = 9e-4, size: int = 11,
+                   sigma: float = 1.5):
+    """SSIM term of Eq. 5: scale * (1 - mean SSIM(img, gt)) over all views and
+    pixels, SSIM(p) = (2 mx my + c1)(2 sxy + c2) / ((mx^2 + my^2 + c1)(sx^2 +
+    sy^2 + c2)) with local statistics under a Gaussian window (zero outside
+    the image), and its gradient with respect to img. img, gt [V][H][W]."""
+    from scipy.ndimage import correlate
+    x = np.asarray(img, dtype=np.float64)
+    y = np.asarray(gt, dtype=np.float64)
+    w1 = ssim_window(size, sigma)
+    w2 = np.outer(w1, w1)[None]
+    conv = lambda a: correlate(a, w2, mode="constant", cval=0.0)
+    mx, my = conv(x), conv(y)
+    exx, eyy, exy = conv(x * x), conv(y * y), conv(x * y)
+    A = 2 * mx * my + c1
+    B = 2 * (exy - mx * my) + c2
+    C = mx * mx + my * my + c1
+    D = (exx - mx * mx) + (eyy - my * my) + c2
+    S = A * B / (C * D)
+    n = x.size
+    loss = scale * (1.0 - S.mean())
+    # dS/d(mx, exx, exy) with the other local statistics fixed
+    g_mx = (2 * my * B - 2 * my * A) / (C * D) - S * (2 * mx / C - 2 * mx / D)
+    g_exx = -S / D
+    g_exy = 2 * A / (C * D)
+    # the window is symmetric: the adjoint of the correlation is itself
+    grad = -(scale / n) * (conv(g_mx) + 2 * x * conv(g_exx) + y * conv(g_exy))
+    return loss, grad
 
 
 def psnr(vol, gt):

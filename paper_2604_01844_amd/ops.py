@@ -304,6 +304,24 @@ def l1_loss_grad(img, gt, *, n_views: int | None = None, ws: Workspace | None = 
     return loss, grad
 
 
+SSIM_C1, SSIM_C2 = 0.01 ** 2, 0.03 ** 2
+
+
+def ssim_loss_grad(img, gt, *, scale: float = 1.0, c1: float = SSIM_C1, c2: float = SSIM_C2,
+                   ws: Workspace | None = None, grad=None, accumulate: bool = False, want_grad=True):
+    """SSIM term of Eq. 5 over img, gt [V][H][W]: (loss device scalar
+    scale * (1 - mean SSIM), gradient or None). With accumulate the gradient
+    is added to `grad`."""
+    ws = ws or Workspace(img.device)
+    V, H, W = img.shape
+    loss = torch.empty(1, device=img.device)
+    if want_grad and grad is None:
+        grad = torch.empty_like(img)
+    ws.call(A.lib().fgs_ssim_loss_grad, A.ptr(img.contiguous()), A.ptr(gt.contiguous()), W, H, V, float(c1),
+            float(c2), float(scale), A.ptr(loss), A.ptr(grad if want_grad else None), 1 if accumulate else 0)
+    return loss, (grad if want_grad else None)
+
+
 def tv_loss_grad(vol, *, scale: float = 1.0, ws: Workspace | None = None, want_grad=True, grad=None):
     """3D total variation of vol [nz][ny][nx] (TV term of Eq. 5) times scale:
     (loss device scalar, gradient or None)."""

@@ -10,14 +10,16 @@ Both are thin drivers. Every numerical step runs in libfactgs:
 
 Python only orders the calls, draws the view order and keeps the clock.
 
-Reconstruction follows the paper's loop with the L1 and TV terms of Eq. 5:
+Reconstruction follows the paper's loop with the loss of Eq. 5:
 - one view per optimizer step, views in a fresh random order each epoch;
-- with tv_weight > 0, each step also voxelizes a randomly placed 32^3 crop of
+- L1 plus, with ssim_weight > 0, ssim_weight * (1 - SSIM) on the view;
+- with a CropTV, each step also voxelizes a randomly placed 32^3 crop of
   the reconstruction grid and adds the gradient of tv_weight * TV(crop);
 - a paper "iteration" is one pass over all views (its Table 1 times grow
   linearly with the number of views at a fixed iteration count).
 
-The SSIM term is not part of this build.
+The paper prints no weights; the defaults used in this package's
+experiments are stated where they are set.
 
 Fitting follows Sec. 3.6 with the L1 term of Eq. 6:
 - initialise by gradient sampling on the target volume;
@@ -154,7 +156,8 @@ class CropTV:
 def reconstruct(model: GaussianModel, proj_gt, geom: ops.Geometry, *, epochs: int, adam: AdamConfig,
                 vol_gt=None, eval_grid: ops.Grid | None = None, eval_every: int = 1,
                 target_psnr: float | None = None, seed: int = 0, clock_start: float | None = None,
-                t_offset: float = 0.0, eval_at_start: bool = False, tv: CropTV | None = None) -> History:
+                t_offset: float = 0.0, eval_at_start: bool = False, tv: CropTV | None = None,
+                ssim_weight: float = 0.0) -> History:
     """Optimise `model` against projections proj_gt[V][H][W] (GPU), one view
     per step. If vol_gt/eval_grid are given, PSNR is evaluated every
     `eval_every` epochs (and before the first step with eval_at_start),
@@ -163,6 +166,7 @@ def reconstruct(model: GaussianModel, proj_gt, geom: ops.Geometry, *, epochs: in
     dev = proj_gt.device
     V = proj_gt.shape[0]
     ws_p, ws_l, ws_v = ops.Workspace(dev), ops.Workspace(dev, 1 << 16), ops.Workspace(dev)
+    ws_s = ops.Workspace(dev)
     img = torch.empty((1, geom.det_h, geom.det_w), device=dev)
     vol = torch.empty(eval_grid.shape, device=dev) if eval_grid is not None else None
     peak = float(vol_gt.max().item()) if vol_gt is not None else 1.0
@@ -185,6 +189,8 @@ def reconstruct(model: GaussianModel, proj_gt, geom: ops.Geometry, *, epochs: in
         for v in rng.permutation(V):
             ops.project_views(*model.params, geom, int(v), 1, ws=ws_p, out=img)
             loss, g = ops.l1_loss_grad(img, proj_gt[v:v + 1], ws=ws_l)
+            if ssim_weight > 0:
+                ops.ssim_loss_grad(img, proj_gt[v:v + 1], scale=ssim_weight, ws=ws_s, grad=g, accumulate=True)
             ops.project_views_backward(*model.params, geom, g, int(v), 1, recompute=False, ws=ws_p,
                                        out=model.grads)
             if tv is not None:

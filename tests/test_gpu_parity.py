@@ -476,3 +476,18 @@ def test_voxelize_backward_accumulates(fgs):
                               band=BAND)
     errs = grads_rel(fresh, ref)
     assert max(errs.values()) < TOL, errs
+
+
+@pytest.mark.parametrize("shape", [(2, 64, 64), (3, 45, 71), (1, 7, 5)])
+def test_ssim_loss_grad_matches_oracle(fgs, shape):
+    x = np.abs(si.normals(shape, 94)) * 0.5
+    y = np.abs(si.normals(shape, 95)) * 0.5
+    xd, yd = torch.from_numpy(x).to(DEV), torch.from_numpy(y).to(DEV)
+    loss, g = fgs.ssim_loss_grad(xd, yd, scale=0.25)
+    rl, rg = oracle.ssim_loss_grad(x, y, scale=0.25)
+    assert abs(float(loss.item()) - rl) <= 1e-5 * abs(rl)
+    assert rel(g.cpu().numpy(), rg) < TOL
+    base = torch.from_numpy(si.normals(shape, 96)).to(DEV)
+    acc = base.clone()
+    fgs.ssim_loss_grad(xd, yd, scale=0.25, grad=acc, accumulate=True)
+    np.testing.assert_allclose(acc.cpu().numpy(), (base + g).cpu().numpy(), rtol=1e-6, atol=1e-9)

@@ -768,3 +768,47 @@ def test_tv_hand_values_invariances_and_finite_differences():
         wm = w64.copy(); wm[idx] -= h
         f = lambda a: sum(np.abs(np.diff(a, axis=ax)).sum() for ax in range(3)) / a.size
         assert (f(wp) - f(wm)) / (2 * h) == pytest.approx(g0[idx], abs=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# SSIM term of Eq. 5
+
+def test_ssim_window_identity_constants_and_brute_force():
+    rng = np.random.default_rng(41)
+    x = rng.uniform(0, 1, (2, 17, 23))
+    loss, g = oracle.ssim_loss_grad(x, x)
+    assert loss == pytest.approx(0.0, abs=1e-14)
+    assert np.abs(g).max() < 1e-14
+    w = oracle.ssim_window()
+    assert w.sum() == pytest.approx(1.0, abs=1e-15) and np.argmax(w) == 5 and w[0] == pytest.approx(w[10])
+    # brute force at a few pixels (zero padding), from the definition
+    y = rng.uniform(0, 1, (2, 17, 23))
+    c1, c2 = 1e-4, 9e-4
+    W2 = np.outer(w, w)
+    pad = lambda a: np.pad(a, ((0, 0), (5, 5), (5, 5)))
+    xp, yp = pad(x), pad(y)
+    vals = []
+    for v in range(2):
+        for i in range(17):
+            for j in range(23):
+                px, py = xp[v, i:i + 11, j:j + 11], yp[v, i:i + 11, j:j + 11]
+                mx, my = (W2 * px).sum(), (W2 * py).sum()
+                sx = (W2 * px * px).sum() - mx * mx
+                sy = (W2 * py * py).sum() - my * my
+                sxy = (W2 * px * py).sum() - mx * my
+                vals.append((2 * mx * my + c1) * (2 * sxy + c2) / ((mx * mx + my * my + c1) * (sx + sy + c2)))
+    loss, _ = oracle.ssim_loss_grad(x, y, scale=0.7)
+    assert loss == pytest.approx(0.7 * (1 - np.mean(vals)), rel=1e-12)
+
+
+def test_ssim_gradient_matches_finite_differences():
+    rng = np.random.default_rng(42)
+    x = rng.uniform(0, 1, (2, 13, 15))
+    y = rng.uniform(0, 1, (2, 13, 15))
+    _, g = oracle.ssim_loss_grad(x, y, scale=0.5)
+    h = 1e-6
+    for idx in [(0, 0, 0), (0, 6, 7), (1, 12, 14), (1, 3, 10), (0, 12, 0)]:
+        xp = x.copy(); xp[idx] += h
+        xm = x.copy(); xm[idx] -= h
+        fd = (oracle.ssim_loss_grad(xp, y, scale=0.5)[0] - oracle.ssim_loss_grad(xm, y, scale=0.5)[0]) / (2 * h)
+        assert fd == pytest.approx(g[idx], rel=1e-6, abs=1e-11)
