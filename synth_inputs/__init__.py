@@ -32,6 +32,7 @@ __all__ = [
     "gaussians",
     "phantom",
     "random_phantom",
+    "perturbed_phantom",
     "angles",
     "geometry",
     "grid",
@@ -111,6 +112,21 @@ def random_phantom(seed: int, lo: int = 20, hi: int = 60) -> dict:
     out, 1999 for calibrating the PSNR target)."""
     n_ell = int(np.random.Generator(np.random.PCG64(seed + 7_000_000)).integers(lo, hi + 1))
     return phantom(n_ell, seed)
+
+
+def perturbed_phantom(ph: dict, seed: int, shift: float = 0.01, scale: float = 0.1, amp: float = 0.2) -> dict:
+    """A prior scan of the same object: each ellipsoid's centre moved by up to
+    `shift` per axis, semi-axes scaled by U(1 - scale, 1 + scale), amplitudes
+    by U(1 - amp, 1 + amp); the body's amplitude is kept."""
+    rng = np.random.Generator(np.random.PCG64(seed + 9_000_000))
+    n = ph["amp"].shape[0]
+    out = {k: np.array(v, dtype=np.float64, copy=True) for k, v in ph.items()}
+    out["centre"] = out["centre"] + rng.uniform(-shift, shift, size=(n, 3))
+    out["semi"] = out["semi"] * rng.uniform(1 - scale, 1 + scale, size=(n, 3))
+    f = rng.uniform(1 - amp, 1 + amp, size=n)
+    f[0] = 1.0
+    out["amp"] = out["amp"] * f
+    return out
 
 
 def angles(n_views: int) -> np.ndarray:

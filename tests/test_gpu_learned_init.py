@@ -39,3 +39,23 @@ def test_fallback_without_network_is_the_fdk_gradient_rule():
     b = L.fdk_gradient_model(sc, vfdk, u)
     for x, y in zip(a.params, b.params):
         assert torch.equal(x, y)
+
+
+def test_warm_start_from_a_prior_saves_iterations():
+    """Sec. 3.6: Gaussians fitted (50 steps) to a prior scan of the same
+    object start the reconstruction far higher than the FDK-gradient rule and
+    reach the cold run's best PSNR in a fraction of its epochs (Eq. 7)."""
+    from paper_2604_01844_amd import recon, learned_init as L, warm_start as WS
+    sc = L.Scanner(L.ScanConfig(), DEV)
+    adam = recon.AdamConfig(lr_density=2e-3)
+    ph = sc.phantom(2002)
+    proj = sc.project(ph)
+    from paper_2604_01844_amd import ops
+    vol_gt = ops.phantom_voxelize(ph, sc.eval_grid)
+    epochs = 30
+    cold = L.run_arm(sc, "fdk_gradient", 2002, epochs=epochs, adam=adam, proj=proj, vol_gt=vol_gt)
+    warm = WS.run_warm(sc, 2002, epochs=epochs, adam=adam, proj=proj, vol_gt=vol_gt)
+    print(f"psnr0 {cold.psnr0:.2f} -> {warm.psnr0:.2f}; final {cold.history.psnr[-1]:.2f} / {warm.history.psnr[-1]:.2f}")
+    assert warm.psnr0 > cold.psnr0 + 3.0
+    tau = L.iteration_ratio(cold, warm, epochs)
+    assert tau is not None and tau < 0.8, tau
