@@ -246,6 +246,14 @@ int fgs_ssim_loss_grad(const float *img, const float *gt, int32_t W, int32_t H, 
                        float c2, float scale, float *loss, float *grad, int32_t accumulate, fgs_workspace *ws,
                        void *stream);
 
+/* 3D SSIM term of the fitting loss (Eq. 6) over vol, gt [nz][ny][nx]
+ * (device): loss[0] = scale * (1 - mean SSIM) with the separable 11^3
+ * Gaussian window (sigma 1.5, zero outside the grid), constants c1, c2 > 0;
+ * grad (optional) as in fgs_ssim_loss_grad. dims = {nx, ny, nz} (host).
+ * Workspace: 40 bytes per voxel. */
+int fgs_ssim3d_loss_grad(const float *vol, const float *gt, const int32_t dims[3], float c1, float c2, float scale,
+                         float *loss, float *grad, int32_t accumulate, fgs_workspace *ws, void *stream);
+
 /* 3D total variation of vol[nz][ny][nx] (the TV term of Eq. 5, on the
  * sampled sub-volume): loss[0] = scale * (1/n) sum over voxels and axes of
  * |V(i + e_a) - V(i)| (forward differences inside the grid, n = voxel

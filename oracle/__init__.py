@@ -34,8 +34,9 @@ Parity status of each function (what pins it in ``tests/test_oracle_pins.py``):
   linear fields and brute-force nearest neighbours.
 * ``tv_loss_grad``: pinned by a hand-computed volume, finite differences
   and the invariances of a total variation.
-* ``ssim_loss_grad``: pinned by SSIM(x, x) = 1, a brute-force windowed sum at
-  every pixel of a small case, and finite differences of the loss.
+* ``ssim_loss_grad``, ``ssim3d_loss_grad``: pinned by SSIM(x, x) = 1, a
+  brute-force windowed sum at every pixel (voxel) of a small case, and
+  finite differences of the loss.
 * ``mlp`` (learned initializer): BF16 rounding pinned against torch's
   bfloat16 conversion, the backward against finite differences of the
   unrounded network, the canonical targets against their defining
@@ -457,6 +458,31 @@ def ssim_loss_grad(img, gt, scale: float = 1.0, c1: float = 1e-4, c2: float = 9e
     g_exy = 2 * A / (C * D)
     # the window is symmetric: the adjoint of the correlation is itself
     grad = -(scale / n) * (conv(g_mx) + 2 * x * conv(g_exx) + y * conv(g_exy))
+    return loss, grad
+
+
+def ssim3d_loss_grad(vol, gt, scale: float = 1.0, c1: float = 1e-4, c2: float = 9e-4, size: int = 11,
+                     sigma: float = 1.5):
+    """The 3D SSIM term of Eq. 6: scale * (1 - mean SSIM) over the voxels of
+    vol, gt [nz][ny][nx], with local statistics under the separable 3D
+    Gaussian window (zero outside the grid), and its gradient with respect
+    to vol. Same per-voxel formula as ssim_loss_grad."""
+    from scipy.ndimage import correlate
+    x = np.asarray(vol, dtype=np.float64)
+    y = np.asarray(gt, dtype=np.float64)
+    w1 = ssim_window(size, sigma)
+    w3 = w1[:, None, None] * w1[None, :, None] * w1[None, None, :]
+    conv = lambda a: correlate(a, w3, mode="constant", cval=0.0)
+    mx, my = conv(x), conv(y)
+    exx, eyy, exy = conv(x * x), conv(y * y), conv(x * y)
+    A = 2 * mx * my + c1
+    B = 2 * (exy - mx * my) + c2
+    C = mx * mx + my * my + c1
+    D = (exx - mx * mx) + (eyy - my * my) + c2
+    S = A * B / (C * D)
+    loss = scale * (1.0 - S.mean())
+    g_mx = (2 * my * B - 2 * my * A) / (C * D) - S * (2 * mx / C - 2 * mx / D)
+    grad = -(scale / x.size) * (conv(g_mx) + 2 * x * conv(-S / D) + y * conv(2 * A / (C * D)))
     return loss, grad
 
 

@@ -103,6 +103,8 @@ SIGNATURES = {
     "fgs_reduce_max": [_vp, ctypes.c_int64, _vp, P(fgs_workspace), _vp],
     "fgs_copy": [_vp, _vp, ctypes.c_int64, _vp],
     "fgs_tv_loss_grad": [_vp, P(ctypes.c_int32), ctypes.c_float, _vp, _vp, P(fgs_workspace), _vp],
+    "fgs_ssim3d_loss_grad": [_vp, _vp, P(ctypes.c_int32), ctypes.c_float, ctypes.c_float, ctypes.c_float, _vp, _vp,
+                             ctypes.c_int32, P(fgs_workspace), _vp],
     "fgs_ssim_loss_grad": [_vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
                            ctypes.c_float, _vp, _vp, ctypes.c_int32, P(fgs_workspace), _vp],
     "fgs_mlp_pack": [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp],

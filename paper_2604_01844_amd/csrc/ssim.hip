@@ -16,6 +16,8 @@
 //   stats kernel: the five statistics, SSIM (block partial sums, no atomics)
 //                 and the three G maps;
 //   grad kernel:  the windowed sums of the G maps and the gradient.
+// The 3D variant (the fitting loss of Eq. 6) is at the end of the file.
+#include <algorithm>
 #include <cmath>
 
 #include "fgs_internal.h"
@@ -32,6 +34,19 @@ constexpr int kThreads = 256;
 struct Window {
   float w[kWin];
 };
+
+// Normalised 11-tap Gaussian window, sigma 1.5 (computed in double).
+Window gaussian_window() {
+  Window win;
+  double wsum = 0.0, wd[kWin];
+  for (int k = 0; k < kWin; ++k) {
+    const double d = double(k - kR);
+    wd[k] = std::exp(-d * d / (2.0 * 1.5 * 1.5));
+    wsum += wd[k];
+  }
+  for (int k = 0; k < kWin; ++k) win.w[k] = float(wd[k] / wsum);
+  return win;
+}
 
 __device__ __forceinline__ double block_sum(double v, double *sh) {
   for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
@@ -190,14 +205,7 @@ extern "C" int fgs_ssim_loss_grad(const float *img, const float *gt, int32_t W, 
   float *g1 = grad ? reinterpret_cast<float *>(b + o_g) : nullptr;
   float *g2 = grad ? g1 + n : nullptr;
   float *g3 = grad ? g2 + n : nullptr;
-  Window win;
-  double wsum = 0.0, wd[kWin];
-  for (int k = 0; k < kWin; ++k) {
-    const double d = double(k - kR);
-    wd[k] = std::exp(-d * d / (2.0 * 1.5 * 1.5));
-    wsum += wd[k];
-  }
-  for (int k = 0; k < kWin; ++k) win.w[k] = float(wd[k] / wsum);
+  const Window win = gaussian_window();
   hipStream_t s = static_cast<hipStream_t>(stream);
   ssim_stats_kernel<<<grid, kThreads, 0, s>>>(img, gt, W, H, win, c1, c2, g1, g2, g3, partial);
   FGS_LAUNCH_CHECK("ssim_stats_kernel");
@@ -207,6 +215,134 @@ extern "C" int fgs_ssim_loss_grad(const float *img, const float *gt, int32_t W, 
     ssim_grad_kernel<<<grid, kThreads, 0, s>>>(img, gt, W, H, win, g1, g2, g3, float(-double(scale) / double(n)),
                                                accumulate, grad);
     FGS_LAUNCH_CHECK("ssim_grad_kernel");
+  }
+  return FGS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// 3D SSIM (the fitting loss of Eq. 6): the same per-voxel formula with the
+// separable 11^3 window, as three 1D passes (x, then y, then z) over
+// channel-major volumes, one thread per output voxel and all channels; no
+// atomics (block partial sums for the mean).
+
+namespace fgs {
+namespace {
+
+// out[c][i] = sum_k w[k] in_c(i + (k - 5) e_axis), zero outside the grid.
+// first pass (products != 0): the 5 channels are formed from x and y:
+// x, y, x^2, y^2, x y.
+template <int CH, bool PRODUCTS>
+__global__ __launch_bounds__(256) void sep_pass_kernel(const float *__restrict__ in, const float *__restrict__ y_in,
+                                                       int nx, int ny, int nz, int axis, Window win,
+                                                       float *__restrict__ out) {
+  const uint64_t n = uint64_t(nx) * ny * nz;
+  const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int x = int(i % uint64_t(nx));
+  const int yy = int((i / uint64_t(nx)) % uint64_t(ny));
+  const int z = int(i / (uint64_t(nx) * ny));
+  const int pos = axis == 0 ? x : (axis == 1 ? yy : z);
+  const int len = axis == 0 ? nx : (axis == 1 ? ny : nz);
+  const int64_t stride = axis == 0 ? 1 : (axis == 1 ? int64_t(nx) : int64_t(nx) * ny);
+  float acc[CH];
+#pragma unroll
+  for (int c = 0; c < CH; ++c) acc[c] = 0.f;
+#pragma unroll
+  for (int k = 0; k < kWin; ++k) {
+    const int p = pos + k - kR;
+    if (p < 0 || p >= len) continue;
+    const uint64_t j = uint64_t(int64_t(i) + int64_t(k - kR) * stride);
+    const float wk = win.w[k];
+    if (PRODUCTS) {
+      const float xv = in[j], yv = y_in[j];
+      acc[0] = fmaf(wk, xv, acc[0]);
+      acc[1] = fmaf(wk, yv, acc[1]);
+      acc[2] = fmaf(wk * xv, xv, acc[2]);
+      acc[3] = fmaf(wk * yv, yv, acc[3]);
+      acc[4] = fmaf(wk * xv, yv, acc[4]);
+    } else {
+#pragma unroll
+      for (int c = 0; c < CH; ++c) acc[c] = fmaf(wk, in[uint64_t(c) * n + j], acc[c]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < CH; ++c) out[uint64_t(c) * n + i] = acc[c];
+}
+
+// From the windowed statistics m[5][n]: SSIM partial sums and G maps g[3][n].
+__global__ __launch_bounds__(256) void ssim_map_kernel(const float *__restrict__ m, uint64_t n, float c1, float c2,
+                                                       float *__restrict__ g, double *__restrict__ partial) {
+  __shared__ double sh[kThreads / 64];
+  double acc = 0.0;
+  for (uint64_t i = uint64_t(blockIdx.x) * kThreads + threadIdx.x; i < n; i += uint64_t(gridDim.x) * kThreads) {
+    const float mx = m[i], my = m[n + i];
+    const float A = fmaf(2.f * mx, my, c1);
+    const float B = fmaf(2.f, m[4 * n + i] - mx * my, c2);
+    const float C = fmaf(mx, mx, fmaf(my, my, c1));
+    const float D = (m[2 * n + i] - mx * mx) + (m[3 * n + i] - my * my) + c2;
+    const float CD = C * D;
+    const float S = A * B / CD;
+    acc += double(S);
+    if (g) {
+      g[i] = 2.f * my * (B - A) / CD - S * (2.f * mx / C - 2.f * mx / D);
+      g[n + i] = -S / D;
+      g[2 * n + i] = 2.f * A / CD;
+    }
+  }
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(256) void ssim_combine_kernel(const float *__restrict__ vol, const float *__restrict__ gt,
+                                                           const float *__restrict__ cg, uint64_t n, float coef,
+                                                           int accumulate, float *__restrict__ grad) {
+  const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gq = coef * (cg[i] + 2.f * vol[i] * cg[n + i] + gt[i] * cg[2 * n + i]);
+  grad[i] = accumulate ? grad[i] + gq : gq;
+}
+
+}  // namespace
+}  // namespace fgs
+
+extern "C" int fgs_ssim3d_loss_grad(const float *vol, const float *gt, const int32_t dims[3], float c1, float c2,
+                                    float scale, float *loss, float *grad, int32_t accumulate, fgs_workspace *ws,
+                                    void *stream) {
+  if (!vol || !gt || !dims || !loss || !ws) return fail(FGS_E_INVALID, "null argument");
+  if (dims[0] <= 0 || dims[1] <= 0 || dims[2] <= 0) return fail(FGS_E_INVALID, "dims must be >= 1");
+  if (!(c1 > 0.f) || !(c2 > 0.f)) return fail(FGS_E_INVALID, "c1 and c2 must be > 0");
+  const int nx = dims[0], ny = dims[1], nz = dims[2];
+  const uint64_t n = uint64_t(nx) * ny * nz;
+  const int nb = int(std::min<uint64_t>((n + kThreads - 1) / kThreads, 1024));
+  Carver c(nullptr);
+  uint64_t o_a, o_b, o_part;
+  c.take<float>(5 * n, &o_a);
+  c.take<float>(5 * n, &o_b);
+  c.take<double>(uint64_t(nb), &o_part);
+  ws->needed = c.used;
+  if (!ws->ptr || ws->bytes < ws->needed) return fail(FGS_E_CAPACITY, "workspace too small");
+  ws->kind = 0;
+  char *b = static_cast<char *>(ws->ptr);
+  float *ba = reinterpret_cast<float *>(b + o_a), *bb = reinterpret_cast<float *>(b + o_b);
+  double *partial = reinterpret_cast<double *>(b + o_part);
+  const Window win = gaussian_window();
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const unsigned g1 = grid_for(n, 256);
+  sep_pass_kernel<5, true><<<g1, 256, 0, s>>>(vol, gt, nx, ny, nz, 0, win, ba);
+  sep_pass_kernel<5, false><<<g1, 256, 0, s>>>(ba, nullptr, nx, ny, nz, 1, win, bb);
+  sep_pass_kernel<5, false><<<g1, 256, 0, s>>>(bb, nullptr, nx, ny, nz, 2, win, ba);
+  FGS_LAUNCH_CHECK("sep_pass_kernel");
+  ssim_map_kernel<<<nb, kThreads, 0, s>>>(ba, n, c1, c2, grad ? bb : nullptr, partial);
+  FGS_LAUNCH_CHECK("ssim_map_kernel");
+  ssim_finish_kernel<<<1, kThreads, 0, s>>>(partial, nb, double(n), double(scale), loss);
+  FGS_LAUNCH_CHECK("ssim_finish_kernel");
+  if (grad) {
+    sep_pass_kernel<3, false><<<g1, 256, 0, s>>>(bb, nullptr, nx, ny, nz, 0, win, ba);
+    sep_pass_kernel<3, false><<<g1, 256, 0, s>>>(ba, nullptr, nx, ny, nz, 1, win, bb);
+    sep_pass_kernel<3, false><<<g1, 256, 0, s>>>(bb, nullptr, nx, ny, nz, 2, win, ba);
+    FGS_LAUNCH_CHECK("sep_pass_kernel");
+    ssim_combine_kernel<<<g1, 256, 0, s>>>(vol, gt, ba, n, float(-double(scale) / double(n)), accumulate, grad);
+    FGS_LAUNCH_CHECK("ssim_combine_kernel");
   }
   return FGS_OK;
 }

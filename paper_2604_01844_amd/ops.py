@@ -322,6 +322,21 @@ def ssim_loss_grad(img, gt, *, scale: float = 1.0, c1: float = SSIM_C1, c2: floa
     return loss, (grad if want_grad else None)
 
 
+def ssim3d_loss_grad(vol, gt, *, scale: float = 1.0, c1: float = SSIM_C1, c2: float = SSIM_C2,
+                     ws: Workspace | None = None, grad=None, accumulate: bool = False, want_grad=True):
+    """3D SSIM term of Eq. 6 over vol, gt [nz][ny][nx]: (loss device scalar,
+    gradient or None); with accumulate the gradient is added to `grad`."""
+    ws = ws or Workspace(vol.device)
+    nz, ny, nx = vol.shape
+    dims = (ctypes.c_int32 * 3)(nx, ny, nz)
+    loss = torch.empty(1, device=vol.device)
+    if want_grad and grad is None:
+        grad = torch.empty_like(vol)
+    ws.call(A.lib().fgs_ssim3d_loss_grad, A.ptr(vol.contiguous()), A.ptr(gt.contiguous()), dims, float(c1),
+            float(c2), float(scale), A.ptr(loss), A.ptr(grad if want_grad else None), 1 if accumulate else 0)
+    return loss, (grad if want_grad else None)
+
+
 def tv_loss_grad(vol, *, scale: float = 1.0, ws: Workspace | None = None, want_grad=True, grad=None):
     """3D total variation of vol [nz][ny][nx] (TV term of Eq. 5) times scale:
     (loss device scalar, gradient or None)."""

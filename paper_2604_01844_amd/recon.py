@@ -213,11 +213,13 @@ def reconstruct(model: GaussianModel, proj_gt, geom: ops.Geometry, *, epochs: in
 
 
 def fit_volume(model: GaussianModel, vol_gt, grid: ops.Grid, *, iters: int, adam: AdamConfig,
-               eval_every: int = 10) -> History:
-    """Fit `model` to vol_gt on `grid` (Sec. 3.6, L1 term): voxelize, L1,
-    voxelizer backward, Adam, each step over the whole grid."""
+               eval_every: int = 10, ssim_weight: float = 0.0) -> History:
+    """Fit `model` to vol_gt on `grid` (Sec. 3.6, Eq. 6): voxelize, L1 plus
+    (with ssim_weight > 0) ssim_weight * (1 - 3D SSIM), voxelizer backward,
+    Adam, each step over the whole grid."""
     dev = vol_gt.device
     ws_v, ws_l = ops.Workspace(dev), ops.Workspace(dev, 1 << 16)
+    ws_s = ops.Workspace(dev)
     vol = torch.empty(grid.shape, device=dev)
     peak = float(vol_gt.max().item())
     hist = History()
@@ -227,6 +229,8 @@ def fit_volume(model: GaussianModel, vol_gt, grid: ops.Grid, *, iters: int, adam
     for it in range(1, iters + 1):
         ops.voxelize(*model.params, grid, ws=ws_v, out=vol)
         loss, g = ops.l1_loss_grad(vol, vol_gt, n_views=1, ws=ws_l)
+        if ssim_weight > 0:
+            ops.ssim3d_loss_grad(vol, vol_gt, scale=ssim_weight, ws=ws_s, grad=g, accumulate=True)
         ops.voxelize_backward(*model.params, grid, g, recompute=False, ws=ws_v, out=model.grads)
         model.adam(adam)
         if it % eval_every == 0 or it == iters:

@@ -491,3 +491,14 @@ def test_ssim_loss_grad_matches_oracle(fgs, shape):
     acc = base.clone()
     fgs.ssim_loss_grad(xd, yd, scale=0.25, grad=acc, accumulate=True)
     np.testing.assert_allclose(acc.cpu().numpy(), (base + g).cpu().numpy(), rtol=1e-6, atol=1e-9)
+
+
+@pytest.mark.parametrize("shape", [(20, 24, 28), (1, 9, 13)])
+def test_ssim3d_loss_grad_matches_oracle(fgs, shape):
+    x = np.abs(si.normals(shape, 97)) * 0.5
+    y = np.abs(si.normals(shape, 98)) * 0.5
+    xd, yd = torch.from_numpy(x).to(DEV), torch.from_numpy(y).to(DEV)
+    loss, g = fgs.ssim3d_loss_grad(xd, yd, scale=0.2)
+    rl, rg = oracle.ssim3d_loss_grad(x, y, scale=0.2)
+    assert abs(float(loss.item()) - rl) <= 1e-5 * abs(rl)
+    assert rel(g.cpu().numpy(), rg) < TOL

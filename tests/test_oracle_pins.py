@@ -812,3 +812,34 @@ def test_ssim_gradient_matches_finite_differences():
         xm = x.copy(); xm[idx] -= h
         fd = (oracle.ssim_loss_grad(xp, y, scale=0.5)[0] - oracle.ssim_loss_grad(xm, y, scale=0.5)[0]) / (2 * h)
         assert fd == pytest.approx(g[idx], rel=1e-6, abs=1e-11)
+
+
+def test_ssim3d_identity_brute_force_and_finite_differences():
+    rng = np.random.default_rng(43)
+    x = rng.uniform(0, 1, (7, 8, 9))
+    y = rng.uniform(0, 1, (7, 8, 9))
+    l0, g0 = oracle.ssim3d_loss_grad(x, x)
+    assert l0 == pytest.approx(0.0, abs=1e-14) and np.abs(g0).max() < 1e-14
+    w = oracle.ssim_window()
+    W3 = w[:, None, None] * w[None, :, None] * w[None, None, :]
+    pad = lambda a: np.pad(a, 5)
+    xp, yp = pad(x), pad(y)
+    c1, c2 = 1e-4, 9e-4
+    vals = []
+    for i in range(7):
+        for j in range(8):
+            for k in range(9):
+                px, py = xp[i:i + 11, j:j + 11, k:k + 11], yp[i:i + 11, j:j + 11, k:k + 11]
+                mx, my = (W3 * px).sum(), (W3 * py).sum()
+                sx = (W3 * px * px).sum() - mx * mx
+                sy = (W3 * py * py).sum() - my * my
+                sxy = (W3 * px * py).sum() - mx * my
+                vals.append((2 * mx * my + c1) * (2 * sxy + c2) / ((mx * mx + my * my + c1) * (sx + sy + c2)))
+    loss, g = oracle.ssim3d_loss_grad(x, y, scale=0.3)
+    assert loss == pytest.approx(0.3 * (1 - np.mean(vals)), rel=1e-12)
+    h = 1e-4   # the gradient entries are ~1e-5 of a loss ~0.3: a larger step keeps rounding below 1e-8
+    for idx in [(0, 0, 0), (3, 4, 5), (6, 7, 8), (2, 0, 8)]:
+        xp_ = x.copy(); xp_[idx] += h
+        xm_ = x.copy(); xm_[idx] -= h
+        fd = (oracle.ssim3d_loss_grad(xp_, y, scale=0.3)[0] - oracle.ssim3d_loss_grad(xm_, y, scale=0.3)[0]) / (2 * h)
+        assert fd == pytest.approx(g[idx], rel=1e-5, abs=1e-12)
