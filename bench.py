@@ -150,6 +150,38 @@ def cpu_baseline(gs, gd, ang, grid_d, budget_s=12.0):
                 seconds_per_step=step_s)
 
 
+ABLATIONS = (("design", 0), ("square boxes", 1), ("no quadrant culling", 2), ("per-pixel atomic backward", 4),
+             ("all three", 7))
+
+
+def ablation(fgs, params, geom, i_gt, V, D, steps, log):
+    """An MI355X analogue of the paper's Table 3 for the rasterizer: the
+    standard scan's batched forward, L1 and backward (lists reused), with one
+    part of the design switched off at a time. Prints one JSON line."""
+    import torch
+    dev = params[0].device
+    img = torch.empty((V, D, D), device=dev)
+    gp = [torch.empty_like(p) for p in params]
+    ws_p, ws_l = fgs.Workspace(dev), fgs.Workspace(dev, 1 << 16)
+    rows = {}
+    for name, flag in ABLATIONS:
+        def step():
+            fgs.project_views(*params, geom, ws=ws_p, out=img, ablate=flag)
+            _, g = fgs.l1_loss_grad(img, i_gt, ws=ws_l)
+            fgs.project_views_backward(*params, geom, g, recompute=False, ws=ws_p, out=gp, ablate=flag)
+        step()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            step()
+        b.record()
+        torch.cuda.synchronize()
+        rows[name] = dict(ms=a.elapsed_time(b) / steps, keys=ws_p.n_pairs)
+        log(f"ablation {name}: {rows[name]['ms']:.3f} ms per fwd+bwd over {V} views, {ws_p.n_pairs} keys")
+    print(json.dumps(dict(ablation="rasterizer fwd+L1+bwd, standard scan", steps=steps, rows=rows)), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,6 +190,8 @@ def main():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="scan")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-view-steps", action="store_true", help="skip the one-view step timing")
+    ap.add_argument("--ablation", action="store_true",
+                    help="instead of the benchmark, time the rasterizer with parts of its design switched off")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after timing, run the library's plain copy kernel 3 times on a MIB-MiB buffer "
                          "(known read and write bytes, to scale HBM traffic counters)")
@@ -189,6 +223,9 @@ def main():
     v_gt = fgs.phantom_voxelize(ph, grid)
 
     params = [torch.from_numpy(gs[k]).to(dev) for k in ("mean", "log_scale", "quat", "density")]
+    if args.ablation:
+        ablation(fgs, params, geom, i_gt, V, D, max(1, min(args.steps, 5)), log)
+        return
     lrs = [2e-4, 5e-3, 1e-3, 1e-2]
     moms = [(torch.zeros_like(p), torch.zeros_like(p)) for p in params]
     gp = [torch.empty_like(p) for p in params]

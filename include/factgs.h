@@ -121,10 +121,26 @@ typedef struct {
                             the forward call left in the same workspace (same inputs) */
   int32_t accumulate;    /* backward only: 1 = add the gradients to what `out` holds (summing
                             over view chunks or voxel slabs); 0 = overwrite */
+  int32_t ablate;        /* rasterizer only: 0 = the library's design. For measuring what its
+                            parts contribute (an analogue of the paper's Table 3), a bitmask of
+                            FGS_ABLATE_* that switches parts off; results stay correct. Other
+                            bits: FGS_E_INVALID */
+  int32_t reserved;      /* must be 0 (FGS_E_INVALID otherwise) */
   void *events;          /* optional hipEvent_t[2] (NULL = none): recorded on the stream right
                             before and right after the call's pixel or voxel kernel (splat
                             forward/backward, voxel forward/backward), for timing that kernel */
 } fgs_opts;
+
+/* fgs_opts.ablate bits (rasterizer). */
+#define FGS_ABLATE_SQUARE_BOX 1     /* tile rectangles from the square of half-side kappa sqrt(lambda_max)
+                                       (the circle bound of the original splatting) instead of the
+                                       support ellipse's exact box */
+#define FGS_ABLATE_QUADRANT_CULL 2  /* no per-quadrant culling inside a tile: every pixel of every
+                                       listed (tile, Gaussian) pair is evaluated */
+#define FGS_ABLATE_PER_PIXEL_BWD 4  /* pixel-parallel backward: per listed Gaussian, the tile's pixel
+                                       contributions are summed across the wave and added to the
+                                       record with float atomics (not deterministic) instead of the
+                                       per-Gaussian pair slots */
 
 /* Caller-owned device workspace. The "out" fields describe what the last
  * forward call left in it; a backward call with opts.recompute = 0 reads

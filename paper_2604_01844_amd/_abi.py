@@ -48,7 +48,8 @@ class fgs_grid(ctypes.Structure):
 
 class fgs_opts(ctypes.Structure):
     _fields_ = [("kappa", ctypes.c_float), ("near_plane", ctypes.c_float),
-                ("recompute", ctypes.c_int32), ("accumulate", ctypes.c_int32), ("events", _vp)]
+                ("recompute", ctypes.c_int32), ("accumulate", ctypes.c_int32), ("ablate", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("events", _vp)]
 
 
 class fgs_workspace(ctypes.Structure):

@@ -94,8 +94,13 @@ __device__ __forceinline__ uint32_t record_one(const fgs_gaussians &g, const Geo
     count[r] = 0;
     return 0;
   }
-  const float ru = G.kappa * sqrtf(S.a);
-  const float rv = G.kappa * sqrtf(S.c);
+  float ru = G.kappa * sqrtf(S.a);
+  float rv = G.kappa * sqrtf(S.c);
+  if (G.ablate & FGS_ABLATE_SQUARE_BOX) {
+    // square of half-side kappa sqrt(lambda_max): the circle bound
+    const float h = 0.5f * (S.a - S.c);
+    ru = rv = G.kappa * sqrtf(0.5f * (S.a + S.c) + sqrtf(h * h + S.b * S.b));
+  }
   int x0, x1, y0, y1;
   tile_span(S.u, ru, G.tiles_x, x0, x1);
   tile_span(S.v, rv, G.tiles_y, y0, y1);
@@ -254,7 +259,7 @@ __global__ __launch_bounds__(kWave * TPB) void splat_fwd_kernel(const uint32_t *
                                                            const SplatRec *__restrict__ rec,
                                                            int tiles_x, int tpv, int W, int H,
                                                            uint32_t n_tiles, int n_chunks, float thr,
-                                                           float thr_cull, float *__restrict__ img,
+                                                           float thr_cull, int no_cull, float *__restrict__ img,
                                                            unsigned long long *__restrict__ counter) {
   __shared__ float4 s_cw_all[TPB][kWave + 1];
   __shared__ float2 s_xy_all[TPB][kWave + 1];
@@ -298,7 +303,7 @@ __global__ __launch_bounds__(kWave * TPB) void splat_fwd_kernel(const uint32_t *
       const float2 q = make_float2(ra.x, ra.y);
       s_cw[lane] = c;
       s_xy[lane] = q;
-      mask = quad_mask(c, q.x, q.y, tx0, ty0, thr_cull);
+      mask = no_cull ? 0xFu : quad_mask(c, q.x, q.y, tx0, ty0, thr_cull);
     }
     int nq[4], pos[4];
     build_quad_lists(mask, lane, s_list, nq, pos);
@@ -372,7 +377,7 @@ template <int TPB>
 __global__ __launch_bounds__(kWave * TPB) __attribute__((amdgpu_waves_per_eu(8, 8))) void splat_bwd_kernel(
     const uint32_t *__restrict__ start, const uint32_t *__restrict__ svals,
     const SplatRec *__restrict__ rec, int tiles_x, int tpv, int W, int H, uint32_t n_tiles, int n_chunks,
-    float thr, float thr_cull, const float *__restrict__ gimg, float4 *__restrict__ partials) {
+    float thr, float thr_cull, int no_cull, const float *__restrict__ gimg, float4 *__restrict__ partials) {
   __shared__ float4 s_g4_all[TPB][kTS * kTS / 4];
   __shared__ float4 s_cw_all[TPB][kWave + 1];
   __shared__ float2 s_xy_all[TPB][kWave + 1];
@@ -416,7 +421,7 @@ __global__ __launch_bounds__(kWave * TPB) __attribute__((amdgpu_waves_per_eu(8, 
       slot = __float_as_uint(rb.z) + uint32_t(ty) * __float_as_uint(rb.w) + uint32_t(tx);
       s_cw[lane] = c;
       s_xy[lane] = q;
-      mask = quad_mask(c, q.x, q.y, tx0, ty0, thr_cull);
+      mask = no_cull ? 0xFu : quad_mask(c, q.x, q.y, tx0, ty0, thr_cull);
     }
     // one list of (quadrant << 6 | batch slot) entries, quadrant-major; gpk
     // holds this lane's record's position in it for each quadrant (8 bits each)
@@ -513,6 +518,81 @@ __global__ __launch_bounds__(kWave * TPB) __attribute__((amdgpu_waves_per_eu(8, 
   }
 }
 
+// Ablation only (FGS_ABLATE_PER_PIXEL_BWD): the pixel-parallel backward of
+// the original splatting. One wave per tile, each lane a column of 4 pixels;
+// for every listed Gaussian each lane forms its pixels' six moment terms,
+// the wave sums them (butterfly) and one lane adds them to the record's
+// accumulator acc6[r][6] with float atomics. Not deterministic.
+__global__ __launch_bounds__(kWave) void splat_bwd_pixel_kernel(
+    const uint32_t *__restrict__ start, const uint32_t *__restrict__ svals, const SplatRec *__restrict__ rec,
+    int tiles_x, int tpv, int W, int H, uint32_t n_tiles, float thr, const float *__restrict__ gimg,
+    float *__restrict__ acc6) {
+  __shared__ float4 s_cw[kWave];
+  __shared__ float2 s_xy[kWave];
+  __shared__ uint32_t s_r[kWave];
+  const uint32_t tile = blockIdx.x;
+  if (tile >= n_tiles) return;
+  const uint32_t v_local = tile / uint32_t(tpv);
+  const uint32_t t = tile - v_local * uint32_t(tpv);
+  const int ty = int(t) / tiles_x;
+  const int tx = int(t) - ty * tiles_x;
+  const int lane = threadIdx.x;
+  const int col = lane & 15, row0 = (lane >> 4) * kRows;
+  const float px = float(tx * kTS + col) + 0.5f;
+  const float *gv = gimg + uint64_t(v_local) * uint64_t(W) * uint64_t(H);
+  float gpx[kRows];
+#pragma unroll
+  for (int k = 0; k < kRows; ++k) {
+    const int x = tx * kTS + col, y = ty * kTS + row0 + k;
+    gpx[k] = (x < W && y < H) ? gv[uint64_t(y) * W + x] : 0.f;
+  }
+  const uint32_t b0 = start[tile], e = start[tile + 1];
+  for (uint32_t b = b0; b < e; b += kWave) {
+    const uint32_t m = min(uint32_t(kWave), e - b);
+    if (uint32_t(lane) < m) {
+      const uint32_t r = svals[b + lane];
+      const float4 ra = rec[r].a, rb = rec[r].b;
+      s_cw[lane] = make_float4(ra.z, ra.w, rb.x, rb.y);
+      s_xy[lane] = make_float2(ra.x, ra.y);
+      s_r[lane] = r;
+    }
+    wave_lds_sync();
+    for (uint32_t j = 0; j < m; ++j) {
+      const float4 c = s_cw[j];
+      const float2 q = s_xy[j];
+      const float dx = px - q.x;
+      float mo[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int k = 0; k < kRows; ++k) {
+        const float dy = float(ty * kTS + row0 + k) + 0.5f - q.y;
+        const float arg = fmaf(dx, fmaf(c.x, dx, c.y * dy), c.z * dy * dy);
+        const float ge = ((arg >= thr) ? gpx[k] : 0.f) * __builtin_amdgcn_exp2f(arg);
+        mo[0] += ge;
+        mo[1] = fmaf(ge, dx, mo[1]);
+        mo[2] = fmaf(ge, dy, mo[2]);
+        mo[3] = fmaf(ge * dx, dx, mo[3]);
+        mo[4] = fmaf(ge * dx, dy, mo[4]);
+        mo[5] = fmaf(ge * dy, dy, mo[5]);
+      }
+#pragma unroll
+      for (int d = 32; d > 0; d >>= 1)
+#pragma unroll
+        for (int i = 0; i < 6; ++i) mo[i] += __shfl_xor(mo[i], d, 64);
+      if (lane == 0) {
+        float *a = acc6 + 6 * uint64_t(s_r[j]);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) unsafeAtomicAdd(a + i, mo[i]);
+      }
+    }
+    wave_lds_sync();
+  }
+}
+
+__global__ __launch_bounds__(256) void fill_zero_kernel(float *__restrict__ p, uint64_t n) {
+  const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.f;
+}
+
 // Per record: reduce its contiguous partial slots, then the chain rule to
 // the 11 parameters. A block takes 256 consecutive records of one view. The
 // slots are read by groups of kGradLanes lanes, one record per group at a
@@ -524,14 +604,15 @@ constexpr int kGradLanes = 8;
 __global__ __launch_bounds__(256) void record_grad_kernel(fgs_gaussians g, GeomDev G,
                                                           const uint32_t *__restrict__ offset,
                                                           const float4 *__restrict__ partials,
-                                                          uint64_t R, float *__restrict__ grad_rec) {
+                                                          const float *__restrict__ acc6, uint64_t R,
+                                                          float *__restrict__ grad_rec) {
   __shared__ float s_sum[256][7];
   const int t = threadIdx.x;
   const int64_t i0 = int64_t(blockIdx.x) * 256;
   const int v_local = blockIdx.y;
   const uint64_t rbase = uint64_t(v_local) * uint64_t(g.n);
   const int li = t % kGradLanes;
-  for (int idx = t / kGradLanes; idx < 256; idx += 256 / kGradLanes) {
+  for (int idx = t / kGradLanes; idx < 256 && !acc6; idx += 256 / kGradLanes) {
     float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (i0 + idx < g.n) {
       const uint64_t r = rbase + uint64_t(i0 + idx);
@@ -563,7 +644,7 @@ __global__ __launch_bounds__(256) void record_grad_kernel(fgs_gaussians g, GeomD
   }
   float sums[6];
 #pragma unroll
-  for (int c = 0; c < 6; ++c) sums[c] = s_sum[t][c];
+  for (int c = 0; c < 6; ++c) sums[c] = acc6 ? acc6[6 * r + c] : s_sum[t][c];
   GaussParams P;
   load_gauss(g, i, P);
   ViewFrame F;
@@ -682,6 +763,9 @@ int validate(const fgs_gaussians *g, const fgs_geom *geom, int32_t view_begin, i
   if (view_count <= 0 || view_begin < 0 || int64_t(view_begin) + view_count > geom->n_views)
     return fail(FGS_E_INVALID, "view range");
   if (!(o->kappa > 0.f)) return fail(FGS_E_INVALID, "kappa must be > 0");
+  if (o->ablate & ~(FGS_ABLATE_SQUARE_BOX | FGS_ABLATE_QUADRANT_CULL | FGS_ABLATE_PER_PIXEL_BWD))
+    return fail(FGS_E_INVALID, "unknown ablate bits");
+  if (o->reserved != 0) return fail(FGS_E_INVALID, "opts.reserved must be 0");
   return FGS_OK;
 }
 
@@ -705,6 +789,7 @@ GeomDev make_geom_dev(const fgs_geom *geom, const fgs_opts *o, int view_begin, c
   G.cv = 0.5f * float(geom->det_h) + geom->off_v;
   G.near_plane = o->near_plane;
   G.kappa = o->kappa;
+  G.ablate = o->ablate;
   G.angles = geom->angles;
   return G;
 }
@@ -804,7 +889,8 @@ extern "C" int fgs_project_views_fwd(const fgs_gaussians *g, const fgs_geom *geo
     constexpr int TPB = decltype(tpb)::value;
     splat_fwd_kernel<false, TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
         at<uint32_t>(b, L.start), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
-        uint32_t(L.T), chunks, thr, thr * kCullSlack, part, nullptr);
+        uint32_t(L.T), chunks, thr, thr * kCullSlack, (opts->ablate & FGS_ABLATE_QUADRANT_CULL) ? 1 : 0, part,
+        nullptr);
   });
   FGS_LAUNCH_CHECK("splat_fwd_kernel");
   if (chunks > 1) {
@@ -838,7 +924,7 @@ extern "C" int fgs_project_views_support(const fgs_gaussians *g, const fgs_geom 
     constexpr int TPB = decltype(tpb)::value;
     splat_fwd_kernel<true, TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
         at<uint32_t>(b, L.start), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
-        uint32_t(L.T), chunks, thr, thr * kCullSlack, nullptr, cnt);
+        uint32_t(L.T), chunks, thr, thr * kCullSlack, 0, nullptr, cnt);
   });
   FGS_LAUNCH_CHECK("splat_fwd_kernel<count>");
   return FGS_OK;
@@ -872,20 +958,34 @@ extern "C" int fgs_project_views_bwd(const fgs_gaussians *g, const fgs_geom *geo
   const float thr = -0.5f * kLog2e * opts->kappa * opts->kappa;
   hipEvent_t *ev = static_cast<hipEvent_t *>(opts->events);
   if (ev) FGS_HIP(hipEventRecord(ev[0], s));
-  if (L.K > 0) {
+  float *acc6 = nullptr;
+  if (opts->ablate & FGS_ABLATE_PER_PIXEL_BWD) {
+    // the records' accumulators take the place of the pair slots
+    if (8 * L.K < 6 * R) return fail(FGS_E_UNSUPPORTED, "per-pixel backward ablation: too few pairs");
+    acc6 = at<float>(b, L.partials);
+    fill_zero_kernel<<<grid_for(6 * R, 256), 256, 0, s>>>(acc6, 6 * R);
+    FGS_LAUNCH_CHECK("fill_zero_kernel");
+    if (L.K > 0) {
+      splat_bwd_pixel_kernel<<<unsigned(L.T), kWave, 0, s>>>(at<uint32_t>(b, L.start), sv, at<SplatRec>(b, L.rec),
+                                                             tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
+                                                             uint32_t(L.T), thr, grad_img, acc6);
+      FGS_LAUNCH_CHECK("splat_bwd_pixel_kernel");
+    }
+  } else if (L.K > 0) {
     const int chunks = chunks_per_tile(L.T);
     const uint64_t units = L.T * uint64_t(chunks);
     with_tiles_per_block(units, [&](auto tpb) {
       constexpr int TPB = decltype(tpb)::value;
       splat_bwd_kernel<TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
           at<uint32_t>(b, L.start), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
-          uint32_t(L.T), chunks, thr, thr * kCullSlack, grad_img, at<float4>(b, L.partials));
+          uint32_t(L.T), chunks, thr, thr * kCullSlack, (opts->ablate & FGS_ABLATE_QUADRANT_CULL) ? 1 : 0,
+          grad_img, at<float4>(b, L.partials));
     });
     FGS_LAUNCH_CHECK("splat_bwd_kernel");
   }
   if (ev) FGS_HIP(hipEventRecord(ev[1], s));
   dim3 rgrid(grid_for(uint64_t(g->n), 256), unsigned(view_count));
-  record_grad_kernel<<<rgrid, 256, 0, s>>>(*g, G, at<uint32_t>(b, L.offset), at<float4>(b, L.partials), R,
+  record_grad_kernel<<<rgrid, 256, 0, s>>>(*g, G, at<uint32_t>(b, L.offset), at<float4>(b, L.partials), acc6, R,
                                            at<float>(b, L.grad_rec));
   FGS_LAUNCH_CHECK("record_grad_kernel");
   view_sum_kernel<<<grid_for(uint64_t(g->n), 256), 256, 0, s>>>(g->n, view_count, at<float>(b, L.grad_rec),

@@ -125,10 +125,15 @@ def _grads_like(mean, log_scale, quat, density):
             torch.empty_like(density))
 
 
-def _opts(kappa, near, recompute=1, events=None, accumulate=0) -> A.fgs_opts:
+# fgs_opts.ablate bits (include/factgs.h): switch one part of the
+# rasterizer's design off, for measuring what it contributes
+ABLATE_SQUARE_BOX, ABLATE_QUADRANT_CULL, ABLATE_PER_PIXEL_BWD = 1, 2, 4
+
+
+def _opts(kappa, near, recompute=1, events=None, accumulate=0, ablate=0) -> A.fgs_opts:
     """events: optional pair of started torch.cuda.Event objects to record
     around the call's pixel/voxel kernel."""
-    o = A.fgs_opts(float(kappa), float(near), int(recompute), int(accumulate), None)
+    o = A.fgs_opts(float(kappa), float(near), int(recompute), int(accumulate), int(ablate), 0, None)
     if events is not None:
         arr = (ctypes.c_void_p * 2)(events[0].cuda_event, events[1].cuda_event)
         o._events_keepalive = arr
@@ -180,7 +185,7 @@ def _over_views(ws: Workspace, vc: int, views_per_call: int | None, run):
 def project_views(mean, log_scale, quat, density, geom: Geometry, view_begin: int = 0,
                   view_count: int | None = None, *, kappa: float = KAPPA, near: float = NEAR,
                   ws: Workspace | None = None, out: torch.Tensor | None = None, events=None,
-                  views_per_call: int | None = None) -> torch.Tensor:
+                  views_per_call: int | None = None, ablate: int = 0) -> torch.Tensor:
     """Rasterize views [view_begin, view_begin + view_count): [V][H][W] float32."""
     L = A.lib()
     vc = geom.n_views - view_begin if view_count is None else view_count
@@ -191,7 +196,7 @@ def project_views(mean, log_scale, quat, density, geom: Geometry, view_begin: in
     gm = geom.struct()
 
     def run(b, c, first, chunked, k):
-        o = _opts(kappa, near, events=_chunk_events(events, k))
+        o = _opts(kappa, near, events=_chunk_events(events, k), ablate=ablate)
         ws.call(L.fgs_project_views_fwd, ctypes.byref(g), ctypes.byref(gm), view_begin + b, c, ctypes.byref(o),
                 A.ptr(out[b]))
     _over_views(ws, vc, views_per_call, run)
@@ -201,7 +206,7 @@ def project_views(mean, log_scale, quat, density, geom: Geometry, view_begin: in
 def project_views_backward(mean, log_scale, quat, density, geom: Geometry, grad_img, view_begin: int = 0,
                            view_count: int | None = None, *, kappa: float = KAPPA, near: float = NEAR,
                            recompute: bool = True, ws: Workspace | None = None, out=None, events=None,
-                           views_per_call: int | None = None):
+                           views_per_call: int | None = None, ablate: int = 0):
     """dL/d(mean, log_scale, quat, density) given dL/dimg. Lists left by the
     forward are reused only when the range ran as one call."""
     L = A.lib()
@@ -215,7 +220,7 @@ def project_views_backward(mean, log_scale, quat, density, geom: Geometry, grad_
 
     def run(b, c, first, chunked, k):
         o = _opts(kappa, near, 1 if (recompute or chunked) else 0, _chunk_events(events, k),
-                  accumulate=0 if first else 1)
+                  accumulate=0 if first else 1, ablate=ablate)
         ws.call(L.fgs_project_views_bwd, ctypes.byref(g), ctypes.byref(gm), view_begin + b, c, ctypes.byref(o),
                 A.ptr(gi[b]), ctypes.byref(gr))
     _over_views(ws, vc, views_per_call, run)

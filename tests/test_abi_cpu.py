@@ -42,7 +42,7 @@ def test_validation_rejects_bad_arguments_without_gpu_work():
     from paper_2604_01844_amd import _abi as A
     lib = A.lib()
     ws = A.fgs_workspace()
-    o = A.fgs_opts(3.0, 1e-2, 1, 0, None)
+    o = A.fgs_opts(kappa=3.0, near_plane=1e-2, recompute=1)
     # null Gaussians
     assert lib.fgs_project_views_fwd(None, None, 0, 1, ctypes.byref(o), None, ctypes.byref(ws), None) == A.FGS_E_INVALID
     g = A.fgs_gaussians(10, 16, 16, 16, 16)  # fake non-null pointers, never dereferenced on invalid input
@@ -52,9 +52,14 @@ def test_validation_rejects_bad_arguments_without_gpu_work():
                                      ctypes.byref(ws), None) == A.FGS_E_INVALID
     assert "view range" in lib.fgs_last_error().decode()
     # kappa <= 0
-    bad = A.fgs_opts(0.0, 1e-2, 1, 0, None)
+    bad = A.fgs_opts(kappa=0.0, near_plane=1e-2, recompute=1)
     assert lib.fgs_project_views_fwd(ctypes.byref(g), ctypes.byref(gm), 0, 1, ctypes.byref(bad), 16,
                                      ctypes.byref(ws), None) == A.FGS_E_INVALID
+    # unknown ablation bits, non-zero reserved field
+    for bad in (A.fgs_opts(kappa=3.0, near_plane=1e-2, recompute=1, ablate=8),
+                A.fgs_opts(kappa=3.0, near_plane=1e-2, recompute=1, reserved=1)):
+        assert lib.fgs_project_views_fwd(ctypes.byref(g), ctypes.byref(gm), 0, 1, ctypes.byref(bad), 16,
+                                         ctypes.byref(ws), None) == A.FGS_E_INVALID
     # zero Gaussians
     g0 = A.fgs_gaussians(0, 16, 16, 16, 16)
     gr = A.fgs_grid((ctypes.c_float * 3)(-0.5, -0.5, -0.5), (ctypes.c_float * 3)(0.1, 0.1, 0.1),
@@ -71,7 +76,7 @@ def test_validation_rejects_bad_arguments_without_gpu_work():
     cnt = (ctypes.c_uint64 * 3)()
     assert lib.fgs_binning_layout(ctypes.byref(ws), off, cnt) == A.FGS_E_INVALID
     # backward without recompute needs the forward's lists
-    o0 = A.fgs_opts(3.0, 1e-2, 0, 0, None)
+    o0 = A.fgs_opts(kappa=3.0, near_plane=1e-2, recompute=0)
     gg = A.fgs_gaussian_grads(16, 16, 16, 16)
     assert lib.fgs_project_views_bwd(ctypes.byref(g), ctypes.byref(gm), 0, 1, ctypes.byref(o0), 16,
                                      ctypes.byref(gg), ctypes.byref(ws), None) == A.FGS_E_INVALID
