@@ -329,6 +329,16 @@ int fgs_gradient_init(const float *vol, const fgs_grid *grid, float background_f
                       float density_scale, float min_scale, int64_t n, const double *uniforms,
                       fgs_gaussians_out *out, fgs_workspace *ws, void *stream);
 
+/* FDK-intensity sampling initialisation, the baseline the paper compares its
+ * gradient rule against (Sec. 4, initialisation evaluation): as
+ * fgs_gradient_init, with the weight of a voxel its thresholded value itself
+ * (voxels below background_fraction * max(vol), and negative ones, weigh
+ * zero), quantised to 24 bits of the maximum. FGS_E_INVALID if no voxel has
+ * weight. Same arguments, outputs, workspace protocol and single wait. */
+int fgs_intensity_init(const float *vol, const fgs_grid *grid, float background_fraction,
+                       float density_scale, float min_scale, int64_t n, const double *uniforms,
+                       fgs_gaussians_out *out, fgs_workspace *ws, void *stream);
+
 /* ---------------------------------------------------------------------
  * Learned initializer: an MLP (544 -> 128 -> 128 -> 32, 8 outputs used)
  * mapping an FDK patch and position to a Gaussian's density, log-scales and

@@ -29,7 +29,8 @@ Parity status of each function (what pins it in ``tests/test_oracle_pins.py``):
 * ``l1_loss_grad``, ``adam_step``, ``psnr``: pinned by hand-computed values.
 * ``initialisation.fdk`` (FDK, Sec. 3.1): pinned by the reconstruction of
   uniform spheres and ellipsoids from their exact projections.
-* ``initialisation.gradient_init``: pinned by hand-computed draws, sampling
+* ``initialisation.gradient_init`` (both weightings, gradient and the
+  intensity baseline): pinned by hand-computed weights and draws, sampling
   frequencies against the exact multinomial law, trilinear exactness on
   linear fields and brute-force nearest neighbours.
 * ``tv_loss_grad``: pinned by a hand-computed volume, finite differences

@@ -92,12 +92,20 @@ def fdk(img, geom: dict, angles, grid: dict) -> np.ndarray:
     return (0.5 * 2.0 * math.pi / V * acc).reshape(nz, ny, nx)
 
 
-def sampling_weights(vol32, background_fraction: float = 0.05):
-    """Integer sampling weights (float32 gradient magnitude of the
-    background-thresholded volume, quantised to 24 bits of its maximum)."""
+def sampling_weights(vol32, background_fraction: float = 0.05, weighting: str = "gradient"):
+    """Integer sampling weights: the float32 gradient magnitude of the
+    background-thresholded volume (Sec. 3.1), or for the intensity-sampling
+    baseline the thresholded, non-negative value itself, quantised to 24 bits
+    of its maximum."""
     v = np.asarray(vol32, dtype=np.float32)
     thr = np.float32(background_fraction) * np.float32(v.max())
     vt = np.where(v >= thr, v, np.float32(0)).astype(np.float32)
+    if weighting == "intensity":
+        g = np.maximum(vt, np.float32(0))
+        scale = np.float32(16777216.0) / np.float32(g.max())
+        return np.floor(g * scale).astype(np.uint64)
+    if weighting != "gradient":
+        raise ValueError(weighting)
     p = np.pad(vt, 1)
     half = np.float32(0.5)
     gx = half * (p[1:-1, 1:-1, 2:] - p[1:-1, 1:-1, :-2])
@@ -132,14 +140,16 @@ def trilinear(vol, c):
 
 
 def gradient_init(vol32, grid: dict, uniforms, background_fraction: float = 0.05, density_scale: float = 0.15,
-                  min_scale: float = 1e-4) -> dict:
+                  min_scale: float = 1e-4, weighting: str = "gradient") -> dict:
     """FDK-gradient sampling initialisation (Sec. 3.1) of n = uniforms.shape[1]
-    Gaussians; uniforms[4][n]: voxel choice, then position inside the voxel."""
+    Gaussians; uniforms[4][n]: voxel choice, then position inside the voxel.
+    weighting="intensity": the intensity-sampling baseline of the
+    initialisation comparison (Sec. 4), which differs only in the weights."""
     u = np.asarray(uniforms, dtype=np.float64)
     n = u.shape[1]
     vol32 = np.asarray(vol32, dtype=np.float32)
     nz, ny, nx = vol32.shape
-    w = sampling_weights(vol32, background_fraction).reshape(-1)
+    w = sampling_weights(vol32, background_fraction, weighting).reshape(-1)
     cdf = np.zeros(w.size + 1, dtype=np.uint64)
     np.cumsum(w, out=cdf[1:])
     total = int(cdf[-1])

@@ -99,6 +99,8 @@ SIGNATURES = {
     "fgs_fdk": [_vp, P(fgs_geom), ctypes.c_int32, ctypes.c_int32, P(fgs_grid), _vp, P(fgs_workspace), _vp],
     "fgs_gradient_init": [_vp, P(fgs_grid), ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_int64, _vp,
                           P(fgs_gaussian_grads), P(fgs_workspace), _vp],
+    "fgs_intensity_init": [_vp, P(fgs_grid), ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_int64, _vp,
+                           P(fgs_gaussian_grads), P(fgs_workspace), _vp],
     "fgs_gather_patches": [_vp, P(fgs_grid), ctypes.c_float, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_int64,
                            ctypes.c_int32, _vp, _vp, _vp],
     "fgs_reduce_max": [_vp, ctypes.c_int64, _vp, P(fgs_workspace), _vp],

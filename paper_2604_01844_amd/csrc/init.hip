@@ -16,7 +16,8 @@
 // interpolation between pixel centres and zero outside the detector.
 //
 // Sampling is exact in integers: per-voxel weights are the FP32 gradient
-// magnitude quantised to 24 bits of its maximum, their 64-bit prefix sum is
+// magnitude (or, for intensity sampling, the thresholded value) quantised to
+// 24 bits of its maximum, their 64-bit prefix sum is
 // the CDF, and draw i takes the voxel whose CDF interval holds
 // floor(u_i * total) (u_i given, FP64).
 #include <cmath>
@@ -169,6 +170,19 @@ __global__ __launch_bounds__(256) void grad_mag_kernel(const float *__restrict__
   const float gz = 0.5f * (val(ix, iy, iz + 1) - val(ix, iy, iz - 1));
   const float sq = gx * gx + gy * gy;
   gmag[idx] = sqrtf(sq + gz * gz);
+}
+
+// Intensity weighting: the volume itself with voxels below
+// background_fraction * max (and negative values) set to zero.
+__global__ __launch_bounds__(256) void intensity_kernel(const float *__restrict__ vol, uint64_t nv,
+                                                        float background_fraction,
+                                                        const float *__restrict__ vmax,
+                                                        float *__restrict__ wgt) {
+  const uint64_t idx = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= nv) return;
+  const float thr = background_fraction * vmax[0];
+  const float v = vol[idx];
+  wgt[idx] = (v >= thr && v > 0.f) ? v : 0.f;
 }
 
 __global__ __launch_bounds__(256) void quantize_kernel(const float *__restrict__ gmag, uint64_t n,
@@ -327,9 +341,11 @@ extern "C" int fgs_fdk(const float *img, const fgs_geom *geom, int32_t view_begi
   return FGS_OK;
 }
 
-extern "C" int fgs_gradient_init(const float *vol, const fgs_grid *grid, float background_fraction,
-                                 float density_scale, float min_scale, int64_t n, const double *uniforms,
-                                 fgs_gaussians_out *out, fgs_workspace *ws, void *stream) {
+enum class Weighting { kGradient, kIntensity };
+
+static int sampling_init(Weighting mode, const float *vol, const fgs_grid *grid, float background_fraction,
+                         float density_scale, float min_scale, int64_t n, const double *uniforms,
+                         fgs_gaussians_out *out, fgs_workspace *ws, void *stream) {
   if (!vol || !grid || !uniforms || !out || !ws || !out->mean || !out->log_scale || !out->quat || !out->density)
     return fail(FGS_E_INVALID, "null argument");
   if (n <= 0) return fail(FGS_E_INVALID, "n must be positive");
@@ -356,16 +372,23 @@ extern "C" int fgs_gradient_init(const float *vol, const fgs_grid *grid, float b
   max_partial_kernel<<<nb, kRedThreads, 0, s>>>(vol, nv, part);
   max_final_kernel<<<1, kRedThreads, 0, s>>>(part, nb, vmax);
   FGS_LAUNCH_CHECK("max_final_kernel");
-  grad_mag_kernel<<<grid_for(nv, 256), 256, 0, s>>>(vol, grid->dims[0], grid->dims[1], grid->dims[2],
-                                                    background_fraction, vmax, gmag);
-  FGS_LAUNCH_CHECK("grad_mag_kernel");
+  if (mode == Weighting::kGradient) {
+    grad_mag_kernel<<<grid_for(nv, 256), 256, 0, s>>>(vol, grid->dims[0], grid->dims[1], grid->dims[2],
+                                                      background_fraction, vmax, gmag);
+    FGS_LAUNCH_CHECK("grad_mag_kernel");
+  } else {
+    intensity_kernel<<<grid_for(nv, 256), 256, 0, s>>>(vol, nv, background_fraction, vmax, gmag);
+    FGS_LAUNCH_CHECK("intensity_kernel");
+  }
   max_partial_kernel<<<nb, kRedThreads, 0, s>>>(gmag, nv, part);
   max_final_kernel<<<1, kRedThreads, 0, s>>>(part, nb, gmax);
   FGS_LAUNCH_CHECK("max_final_kernel");
   float gm_host = 0.f;
   FGS_HIP(hipMemcpyAsync(&gm_host, gmax, sizeof(float), hipMemcpyDeviceToHost, s));
   FGS_HIP(hipStreamSynchronize(s));
-  if (!(gm_host > 0.f)) return fail(FGS_E_INVALID, "the thresholded volume has no gradient to sample");
+  if (!(gm_host > 0.f))
+    return fail(FGS_E_INVALID, mode == Weighting::kGradient ? "the thresholded volume has no gradient to sample"
+                                                            : "the thresholded volume has no mass to sample");
   quantize_kernel<<<grid_for(nv, 256), 256, 0, s>>>(gmag, nv, gmax, w);
   FGS_LAUNCH_CHECK("quantize_kernel");
   int st = exclusive_scan_u64(w, nv, reinterpret_cast<uint32_t *>(b + o_scan), s);
@@ -381,6 +404,20 @@ extern "C" int fgs_gradient_init(const float *vol, const fgs_grid *grid, float b
   nn_scale_kernel<<<grid_for(uint64_t(n), 256), 256, 0, s>>>(out->mean, n, min_scale, out->log_scale);
   FGS_LAUNCH_CHECK("nn_scale_kernel");
   return FGS_OK;
+}
+
+extern "C" int fgs_gradient_init(const float *vol, const fgs_grid *grid, float background_fraction,
+                                 float density_scale, float min_scale, int64_t n, const double *uniforms,
+                                 fgs_gaussians_out *out, fgs_workspace *ws, void *stream) {
+  return sampling_init(Weighting::kGradient, vol, grid, background_fraction, density_scale, min_scale, n,
+                       uniforms, out, ws, stream);
+}
+
+extern "C" int fgs_intensity_init(const float *vol, const fgs_grid *grid, float background_fraction,
+                                  float density_scale, float min_scale, int64_t n, const double *uniforms,
+                                  fgs_gaussians_out *out, fgs_workspace *ws, void *stream) {
+  return sampling_init(Weighting::kIntensity, vol, grid, background_fraction, density_scale, min_scale, n,
+                       uniforms, out, ws, stream);
 }
 
 extern "C" int fgs_reduce_max(const float *x, int64_t n, float *out, fgs_workspace *ws, void *stream) {

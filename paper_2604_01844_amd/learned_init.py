@@ -123,9 +123,10 @@ def train(pairs: list, *, epochs: int, lr: float = 1e-3, seed: int = 0, net: Ini
     return net, losses
 
 
-def fdk_gradient_model(sc: Scanner, vfdk, uniforms) -> recon.GaussianModel:
-    """Sec. 3.1's initialisation from the FDK volume."""
-    return recon.init_from_volume(vfdk, sc.grid, sc.cfg.n_gauss, uniforms)
+def fdk_gradient_model(sc: Scanner, vfdk, uniforms, weighting: str = "gradient") -> recon.GaussianModel:
+    """Sec. 3.1's initialisation from the FDK volume (weighting="intensity":
+    the intensity-sampling baseline)."""
+    return recon.init_from_volume(vfdk, sc.grid, sc.cfg.n_gauss, uniforms, weighting=weighting)
 
 
 def learned_model(sc: Scanner, net: InitMLP, vfdk, vmax, uniforms) -> recon.GaussianModel:
@@ -168,7 +169,12 @@ def run_arm(sc: Scanner, arm: str, seed: int, *, epochs: int, adam: recon.AdamCo
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     vfdk, vmax = sc.fdk(proj)
-    model = fdk_gradient_model(sc, vfdk, u) if arm == "fdk_gradient" else learned_model(sc, net, vfdk, vmax, u)
+    if arm in ("fdk_gradient", "fdk_intensity"):
+        model = fdk_gradient_model(sc, vfdk, u, weighting=arm[4:])
+    elif arm == "learned":
+        model = learned_model(sc, net, vfdk, vmax, u)
+    else:
+        raise ValueError(arm)
     torch.cuda.synchronize()
     t_init = time.perf_counter() - t0
     hist = recon.reconstruct(model, proj, sc.geom, epochs=epochs, adam=adam, vol_gt=vol_gt, eval_grid=sc.eval_grid,

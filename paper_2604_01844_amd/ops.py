@@ -424,11 +424,15 @@ def fdk(img, geom: Geometry, grid: Grid, view_begin: int = 0, view_count: int | 
 
 
 def gradient_init(vol, grid: Grid, uniforms, *, background_fraction: float = 0.05, density_scale: float = 0.15,
-                  min_scale: float = 1e-4, ws: Workspace | None = None):
+                  min_scale: float = 1e-4, ws: Workspace | None = None, weighting: str = "gradient"):
     """FDK-gradient sampling initialisation: returns (mean, log_scale, quat,
     density) of n = uniforms.shape[1] Gaussians; uniforms is a float64 GPU
-    tensor [4][n] of U[0, 1) variates."""
+    tensor [4][n] of U[0, 1) variates. weighting="intensity" samples by the
+    thresholded value instead of its gradient magnitude (fgs_intensity_init)."""
     L = A.lib()
+    fn = {"gradient": L.fgs_gradient_init, "intensity": L.fgs_intensity_init}.get(weighting)
+    if fn is None:
+        raise ValueError("weighting must be 'gradient' or 'intensity'")
     if uniforms.dtype != torch.float64 or uniforms.dim() != 2 or uniforms.shape[0] != 4:
         raise ValueError("uniforms must be float64 [4][n]")
     n = uniforms.shape[1]
@@ -438,7 +442,7 @@ def gradient_init(vol, grid: Grid, uniforms, *, background_fraction: float = 0.0
     o = A.fgs_gaussian_grads(*(A.ptr(t) for t in outs))
     ws = ws or Workspace(dev)
     gd = grid.struct()
-    ws.call(L.fgs_gradient_init, A.ptr(vol.contiguous()), ctypes.byref(gd), float(background_fraction),
+    ws.call(fn, A.ptr(vol.contiguous()), ctypes.byref(gd), float(background_fraction),
             float(density_scale), float(min_scale), n, A.ptr(uniforms.contiguous()), ctypes.byref(o))
     return outs
 

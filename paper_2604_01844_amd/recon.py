@@ -114,15 +114,17 @@ class History:
 
 
 def init_from_volume(vol, grid: ops.Grid, n: int, uniforms, *, background_fraction=0.05,
-                     density_scale=0.15) -> GaussianModel:
+                     density_scale=0.15, weighting="gradient") -> GaussianModel:
     """Gradient-sampling initialisation (Sec. 3.1) from a volume on the GPU;
-    uniforms is a float64 [4][>= n] array or device tensor of U[0, 1) draws."""
+    uniforms is a float64 [4][>= n] array or device tensor of U[0, 1) draws.
+    weighting="intensity" gives the intensity-sampling baseline."""
     if isinstance(uniforms, torch.Tensor):
         u = uniforms[:, :n].to(vol.device, torch.float64).contiguous()
     else:
         u = torch.from_numpy(np.ascontiguousarray(uniforms[:, :n], dtype=np.float64)).to(vol.device)
     mean, ls, q, d = ops.gradient_init(vol, grid, u, background_fraction=background_fraction,
-                                       density_scale=density_scale, min_scale=0.25 * min(grid.spacing))
+                                       density_scale=density_scale, min_scale=0.25 * min(grid.spacing),
+                                       weighting=weighting)
     return GaussianModel(mean, ls, q, d)
 
 

@@ -54,20 +54,51 @@ def run_warm(sc: Scanner, seed: int, *, epochs: int, adam: recon.AdamConfig, pro
     return ArmResult(t_init, hist)
 
 
+def ssim3d(vol, gt) -> float:
+    """Mean 3D SSIM (Eq. 6's window and constants) of vol against gt."""
+    loss, _ = ops.ssim3d_loss_grad(vol, gt, want_grad=False)
+    return 1.0 - float(loss.item())
+
+
+def init_quality(sc: Scanner, seed: int, *, fit_iters: int = 50) -> dict:
+    """The paper's initialisation comparison (Sec. 4): 3D SSIM against the
+    target volume of what each strategy starts from, on the evaluation grid:
+    FDK-intensity sampling, FDK-gradient sampling (both from the FDK of the
+    scan's projections), the prior volume used directly, and the rapid fit to
+    the prior."""
+    ph = sc.phantom(seed)
+    gt = ops.phantom_voxelize(ph, sc.eval_grid)
+    vfdk, _ = sc.fdk(sc.project(ph))
+    u = sc.uniforms(seed)
+    out = {}
+    for w in ("intensity", "gradient"):
+        m = recon.init_from_volume(vfdk, sc.grid, sc.cfg.n_gauss, u, weighting=w)
+        out[f"fdk_{w}"] = ssim3d(ops.voxelize(*m.params, sc.eval_grid), gt)
+    pph = prior_phantom(sc, seed)
+    out["prior_direct"] = ssim3d(ops.phantom_voxelize(pph, sc.eval_grid), gt)
+    warm = warm_model(sc, ops.phantom_voxelize(pph, sc.grid), u, fit_iters=fit_iters)
+    out["rapid_fit"] = ssim3d(ops.voxelize(*warm.params, sc.eval_grid), gt)
+    return out
+
+
 def compare(sc: Scanner, seeds, *, epochs: int, adam: recon.AdamConfig, fit_iters: int = 50, log=None) -> list:
-    """Cold start (FDK-gradient rule) against warm start from the prior, per
-    held-out phantom: PSNR before the first step, seconds/epochs to fixed
-    levels, and Eq. 7's ratio (the fraction of the cold run's epochs the warm
-    run needs to reach the cold run's best PSNR)."""
+    """Cold starts (FDK-gradient rule, and the FDK-intensity baseline) against
+    warm start from the prior, per held-out phantom: the initialisation's 3D
+    SSIM, PSNR before the first step, seconds/epochs to fixed levels, and
+    Eq. 7's ratio (the fraction of the gradient-rule run's epochs the warm run
+    needs to reach that run's best PSNR)."""
     rows = []
     for seed in seeds:
         ph = sc.phantom(seed)
         proj = sc.project(ph)
         vol_gt = ops.phantom_voxelize(ph, sc.eval_grid)
+        inten = run_arm(sc, "fdk_intensity", seed, epochs=epochs, adam=adam, proj=proj, vol_gt=vol_gt)
         cold = run_arm(sc, "fdk_gradient", seed, epochs=epochs, adam=adam, proj=proj, vol_gt=vol_gt)
         warm = run_warm(sc, seed, epochs=epochs, adam=adam, proj=proj, vol_gt=vol_gt, fit_iters=fit_iters)
-        row = dict(seed=seed, tau_iter=iteration_ratio(cold, warm, epochs))
-        for name, r in (("cold", cold), ("warm", warm)):
+        row = dict(seed=seed, tau_iter=iteration_ratio(cold, warm, epochs),
+                   tau_iter_gradient_vs_intensity=iteration_ratio(inten, cold, epochs),
+                   init_ssim3d=init_quality(sc, seed, fit_iters=fit_iters))
+        for name, r in (("intensity", inten), ("cold", cold), ("warm", warm)):
             row[name] = dict(init_s=r.init_s, psnr0=r.psnr0, psnr_final=r.history.psnr[-1],
                              levels={f"{lv:g}": dict(s=r.seconds_to(lv), epochs=r.epochs_to(lv)) for lv in LEVELS})
         rows.append(row)
@@ -77,7 +108,8 @@ def compare(sc: Scanner, seeds, *, epochs: int, adam: recon.AdamConfig, fit_iter
 
 
 def main(argv=None):
-    """Warm start vs cold start on held-out phantoms; JSON summary on stdout."""
+    """Warm start vs cold starts (gradient and intensity sampling) on held-out
+    phantoms; JSON summary on stdout."""
     import argparse
     import json
     import sys
@@ -91,14 +123,15 @@ def main(argv=None):
     rows = compare(sc, range(2000, 2000 + a.held_out), epochs=a.epochs, adam=recon.AdamConfig(lr_density=2e-3),
                    fit_iters=a.fit_iters, log=log)
     taus = [r["tau_iter"] for r in rows if r["tau_iter"] is not None]
+    taus_gi = [r["tau_iter_gradient_vs_intensity"] for r in rows if r["tau_iter_gradient_vs_intensity"] is not None]
+    arms = ("intensity", "cold", "warm")
+    mean = lambda key: {n: float(np.mean([r[n][key] for r in rows])) for n in arms}
     summary = dict(epochs=a.epochs, fit_iters=a.fit_iters, tau_iter_mean=float(np.mean(taus)) if taus else None,
                    tau_reached=len(taus), of=len(rows),
-                   psnr0=dict(cold=float(np.mean([r["cold"]["psnr0"] for r in rows])),
-                              warm=float(np.mean([r["warm"]["psnr0"] for r in rows]))),
-                   psnr_final=dict(cold=float(np.mean([r["cold"]["psnr_final"] for r in rows])),
-                                   warm=float(np.mean([r["warm"]["psnr_final"] for r in rows]))),
-                   init_s=dict(cold=float(np.mean([r["cold"]["init_s"] for r in rows])),
-                               warm=float(np.mean([r["warm"]["init_s"] for r in rows]))),
+                   tau_iter_gradient_vs_intensity=float(np.mean(taus_gi)) if taus_gi else None,
+                   init_ssim3d={k: float(np.mean([r["init_ssim3d"][k] for r in rows]))
+                                for k in rows[0]["init_ssim3d"]},
+                   psnr0=mean("psnr0"), psnr_final=mean("psnr_final"), init_s=mean("init_s"),
                    per_phantom=rows)
     print(json.dumps(summary), flush=True)
 

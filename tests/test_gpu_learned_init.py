@@ -59,3 +59,17 @@ def test_warm_start_from_a_prior_saves_iterations():
     assert warm.psnr0 > cold.psnr0 + 3.0
     tau = L.iteration_ratio(cold, warm, epochs)
     assert tau is not None and tau < 0.8, tau
+
+
+def test_initialisation_comparison_ranks_as_the_paper():
+    """The paper's initialisation comparison (Sec. 4): against the target
+    volume, gradient sampling starts closer (3D SSIM) than intensity
+    sampling, and the rapid 50-step fit to the prior starts about as close
+    as the prior itself used directly."""
+    from paper_2604_01844_amd import learned_init as L, warm_start as WS
+    sc = L.Scanner(L.ScanConfig(), DEV)
+    q = WS.init_quality(sc, 2003)
+    print(q)
+    assert q["fdk_gradient"] > q["fdk_intensity"] + 0.03, q
+    assert abs(q["rapid_fit"] - q["prior_direct"]) < 0.03, q
+    assert q["rapid_fit"] > q["fdk_gradient"] + 0.05, q

@@ -423,17 +423,20 @@ def test_fdk_matches_oracle(fgs):
     assert rel(vol.cpu().numpy(), ref) < TOL
 
 
-def test_gradient_init_matches_oracle(fgs):
+@pytest.mark.parametrize("weighting", ["gradient", "intensity"])
+def test_gradient_init_matches_oracle(fgs, weighting):
     """Same FP32 volume and the same uniforms: identical voxel choices (the
-    integer decision), means, densities and nearest-neighbour scales."""
+    integer decision), means, densities and nearest-neighbour scales, for the
+    gradient rule and the intensity-sampling baseline."""
     ph = si.phantom(12, 105)
     gr = si.grid(40)
     vol = oracle.phantom_volume(ph, gr).astype(np.float32)
     vol += 0.02 * si.normals(vol.shape, 106)  # FDK-like noise
     n = 3000
     u = np.random.Generator(np.random.PCG64(107)).random((4, n))
-    ref = oracle.gradient_init(vol, gr, u)
-    out = fgs.gradient_init(torch.from_numpy(vol).to(DEV), fgs.Grid.from_dict(gr), torch.from_numpy(u).to(DEV))
+    ref = oracle.gradient_init(vol, gr, u, weighting=weighting)
+    out = fgs.gradient_init(torch.from_numpy(vol).to(DEV), fgs.Grid.from_dict(gr), torch.from_numpy(u).to(DEV),
+                            weighting=weighting)
     mean, ls, quat, dens = (t.cpu().numpy().astype(np.float64) for t in out)
     h = np.array(gr["spacing"])
     o = np.array(gr["origin"])

@@ -562,6 +562,49 @@ def test_gradient_sampling_background_threshold_and_frequencies():
     assert chi2 < dof + 6 * math.sqrt(2 * dof)
 
 
+def test_intensity_sampling_hand_case():
+    """Intensity baseline on the row [0.01, 1, 3, -2] (max 3, threshold
+    0.15): weights floor(v * 2^24 / 3) = [0, 5592405, 2^24, 0]; total
+    22369621, so u0 = 0.2 lands in voxel 1 and u0 = 0.3 in voxel 2 (the
+    interval edge sits at u0 = 5592405 / 22369621 = 0.25000000...)."""
+    vol = np.array([[[0.01, 1.0, 3.0, -2.0]]], dtype=np.float32)
+    w = oracle.sampling_weights(vol, weighting="intensity")
+    assert w.reshape(-1).tolist() == [0, 5592405, 1 << 24, 0]
+    grid = dict(origin=(0.0, 0.0, 0.0), spacing=(1.0, 1.0, 1.0), dims=(4, 1, 1))
+    u = np.array([[0.0, 0.2, 0.24999, 0.25001, 0.3, 0.999999], [0.5] * 6, [0.5] * 6, [0.5] * 6])
+    out = oracle.gradient_init(vol, grid, u, weighting="intensity")
+    assert out["voxel"].tolist() == [1, 1, 1, 2, 2, 2]
+    np.testing.assert_allclose(out["density"], 0.15 * np.array([1.0, 1.0, 1.0, 3.0, 3.0, 3.0]), rtol=1e-7)
+    # the gradient rule on the same (thresholded) row [0, 1, 3, 0]: central
+    # differences 0.5, 1.5, -0.5, -1.5, so it weighs the edges, not the mass
+    g = oracle.sampling_weights(vol).reshape(-1)
+    assert g.tolist() == [5592405, 1 << 24, 5592405, 1 << 24]
+
+
+def test_intensity_sampling_frequencies():
+    """Draws follow the thresholded intensities (chi-square against the exact
+    multinomial law of the integer weights, whose ratios are those of the
+    values to within 2^-24)."""
+    rng = np.random.default_rng(4)
+    vol = rng.uniform(-0.2, 1.0, size=(5, 6, 7)).astype(np.float32)
+    w = oracle.sampling_weights(vol, weighting="intensity").reshape(-1).astype(np.float64)
+    v = vol.reshape(-1).astype(np.float64)
+    keep = v >= np.float32(0.05) * np.float32(vol.max())
+    assert np.all(w[~keep] == 0)
+    np.testing.assert_allclose(w[keep] / w.max(), v[keep] / v.max(), atol=2 ** -23)
+    n = 200000
+    u = rng.random((4, n))
+    grid = dict(origin=(0.0, 0.0, 0.0), spacing=(1.0, 1.0, 1.0), dims=(7, 6, 5))
+    k = oracle.gradient_init(vol, grid, u, weighting="intensity")["voxel"]
+    counts = np.bincount(k, minlength=w.size)
+    p = w / w.sum()
+    assert np.all(counts[w == 0] == 0)
+    nz = p > 0
+    chi2 = np.sum((counts[nz] - n * p[nz]) ** 2 / (n * p[nz]))
+    dof = nz.sum() - 1
+    assert chi2 < dof + 6 * math.sqrt(2 * dof)
+
+
 def test_trilinear_is_exact_on_linear_fields_and_nn_scale_is_brute_force():
     nz, ny, nx = 5, 6, 7
     z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
