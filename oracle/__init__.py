@@ -19,6 +19,13 @@ Parity status of each function (what pins it in ``tests/test_oracle_pins.py``):
   mu identity at the splat centre in cone beam, by the small-Gaussian limit
   M -> E, by the 2D splat-mass closed form and by brute force.
 * ``exact_points`` (Eq. 3): pinned by quadrature.
+* ``exact_project`` / ``exact_points_cut`` (the ray-exact model: Eq. 3 with
+  the kappa support): pinned by the isotropic closed form with its cutoff,
+  quadrature at large kappa, brute force over every pixel, and equality with
+  the splat in parallel beam (where the two models coincide).
+* ``exact_bwd``: pinned by Richardson finite differences at kappa = 8 and,
+  at kappa = 3, by finite differences of the uncut integrals over the
+  unperturbed support.
 * ``voxelize`` (Eq. 2, Sec. 3.3): pinned by the 3D mass closed form and
   brute force.
 * ``project_bwd`` / ``voxelize_bwd``: pinned by Richardson finite
@@ -164,6 +171,57 @@ def exact_points(gs: dict, geom: dict, angle: float, u, v) -> np.ndarray:
     g, pg = _d(_geom_vec(geom))
     lib.orc_exact_points(pg, ctypes.c_double(angle), ctypes.c_long(n), *p, ctypes.c_long(uu.shape[0]),
                          pu, pv, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return out
+
+
+# ---------------------------------------------------------------- ray-exact model (Eq. 3, kappa support)
+
+def exact_project(gs: dict, geom: dict, angles, kappa: float = KAPPA, brute: bool = False) -> np.ndarray:
+    """Ray-exact model for every pixel of every view: each Gaussian adds its
+    exact line integral (Eq. 3) to the rays that pass within Mahalanobis
+    distance kappa of its mean. [V][H][W] float64."""
+    lib = _load()
+    n, keep, p = _gauss_args(gs)
+    ang, pa = _d(angles)
+    V = ang.shape[0]
+    img = np.zeros((V, geom["det_h"], geom["det_w"]))
+    g, pg = _d(_geom_vec(geom))
+    lib.orc_exact_project(pg, ctypes.c_double(kappa), ctypes.c_int(V), pa, ctypes.c_long(n), *p,
+                          ctypes.c_int(1 if brute else 0), _ptr(img))
+    return img
+
+
+def exact_points_cut(gs: dict, geom: dict, angle: float, u, v, kappa: float = KAPPA) -> np.ndarray:
+    """The ray-exact model of one view at arbitrary detector points."""
+    lib = _load()
+    n, keep, p = _gauss_args(gs)
+    uu, pu = _d(u); vv, pv = _d(v)
+    out = np.zeros(uu.shape[0])
+    g, pg = _d(_geom_vec(geom))
+    lib.orc_exact_points_cut(pg, ctypes.c_double(kappa), ctypes.c_double(angle), ctypes.c_long(n), *p,
+                             ctypes.c_long(uu.shape[0]), pu, pv, _ptr(out))
+    return out
+
+
+def exact_bwd(gs: dict, geom: dict, angles, grad_img, kappa: float = KAPPA, sel=None,
+              band: float = 0.0) -> dict:
+    """Gradient of sum(grad_img * E_kappa) (the ray-exact model), support held
+    fixed; ``band`` as in project_bwd, on the ray's squared Mahalanobis
+    distance to the mean."""
+    lib = _load()
+    n, keep, p = _gauss_args(gs)
+    ang, pa = _d(angles)
+    gi, pgi = _d(grad_img)
+    sel = np.arange(n, dtype=np.int64) if sel is None else np.ascontiguousarray(sel, dtype=np.int64)
+    dm, dl, dq, dr = _bwd_out(sel.shape[0])
+    babs = np.zeros((11, sel.shape[0]))
+    g, pg = _d(_geom_vec(geom))
+    lib.orc_exact_bwd(pg, ctypes.c_double(kappa), ctypes.c_int(ang.shape[0]), pa, ctypes.c_long(n), *p,
+                      pgi, ctypes.c_long(sel.shape[0]), sel.ctypes.data_as(ctypes.POINTER(ctypes.c_long)),
+                      _ptr(dm), _ptr(dl), _ptr(dq), _ptr(dr), ctypes.c_double(band), _ptr(babs))
+    out = dict(mean=dm, log_scale=dl, quat=dq, density=dr)
+    if band > 0:
+        out["band_abs"] = _split11(babs)
     return out
 
 

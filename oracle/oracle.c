@@ -15,7 +15,8 @@
  *   - the attenuation field as a plain sum of Gaussians (Eq. 2), evaluated at
  *     voxel centres with the 3-sigma (Mahalanobis) support (Sec. 3.3);
  *   - the exact line integral of each Gaussian along a cone-beam or
- *     parallel-beam ray (Eq. 3);
+ *     parallel-beam ray (Eq. 3), and the ray-exact model: that integral with
+ *     the kappa support, as an image and with its gradient;
  *   - the method's splat model: each Gaussian projected to a 2D Gaussian on
  *     the detector with the integration factor mu (Eq. 4, Sec. 3.2), summed
  *     in any order (Sec. 3.5, no depth ordering);
@@ -455,6 +456,264 @@ void orc_rays(const double *g, double angle, long npts, const double *u, const d
   view_t V;
   make_view(g, angle, &V);
   for (long k = 0; k < npts; ++k) detector_ray(&V, u[k], v[k], o + 3 * k, d + 3 * k);
+}
+
+/* ------------------------------------------------------------------ */
+/* Ray-exact model: Eq. 3 with the kappa support                       */
+/* ------------------------------------------------------------------ */
+
+/* The ray-exact model replaces the splat M by the exact line integral E of
+ * each Gaussian, with the same kind of support: Gaussian i contributes to
+ * the ray through a detector point iff the ray passes within Mahalanobis
+ * distance kappa of its mean, i.e. the smallest value over the line of
+ * (x - p)^T Sigma^-1 (x - p) is <= kappa^2. In cone beam a Gaussian is left
+ * out of a view, as for M, when its camera depth is <= near, and also when
+ * the source lies inside its kappa-ellipsoid (then every ray through the
+ * source passes within kappa and the support is no longer a bounded region
+ * of the detector). */
+static void sigma_to_params(const gauss3 *G, const double dSig[9], double dls[3], double dq[4]);
+
+static int exact_valid(const view_t *V, const gauss3 *G, const double A[9], double kappa) {
+  if (V->parallel) return 1;
+  double x0[3], t2 = 0.0, q = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    x0[a] = V->src[a] - G->p[a];
+    t2 += V->W[6 + a] * (G->p[a] - V->src[a]);
+  }
+  if (!(t2 > V->near_plane)) return 0;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) q += x0[a] * A[3 * a + b] * x0[b];
+  return q > kappa * kappa;
+}
+
+/* Quadratic-in-t pieces of (o + t d - p)^T A (o + t d - p), |d| = 1. */
+typedef struct {
+  double a, b, c, h;   /* d^T A d, d^T A x0, x0^T A x0, c - b^2/a (x0 = o - p) */
+  double x0[3], Ad[3], Ax0[3];
+} ray_form;
+
+static void ray_form_of(const gauss3 *G, const double A[9], const double o[3], const double d[3],
+                        ray_form *F) {
+  for (int a = 0; a < 3; ++a) F->x0[a] = o[a] - G->p[a];
+  for (int a = 0; a < 3; ++a) {
+    F->Ad[a] = A[3 * a] * d[0] + A[3 * a + 1] * d[1] + A[3 * a + 2] * d[2];
+    F->Ax0[a] = A[3 * a] * F->x0[0] + A[3 * a + 1] * F->x0[1] + A[3 * a + 2] * F->x0[2];
+  }
+  F->a = d[0] * F->Ad[0] + d[1] * F->Ad[1] + d[2] * F->Ad[2];
+  F->b = d[0] * F->Ax0[0] + d[1] * F->Ax0[1] + d[2] * F->Ax0[2];
+  F->c = F->x0[0] * F->Ax0[0] + F->x0[1] * F->Ax0[1] + F->x0[2] * F->Ax0[2];
+  F->h = F->c - F->b * F->b / F->a;
+}
+
+/* A superset of the detector pixels whose rays meet Gaussian G's
+ * kappa-ellipsoid: the image of its bounding ball (radius kappa s_max).
+ * Cone beam: a camera point t within r of the centre t_c has
+ * |t0/t2 - t0c/t2c| <= r (t2c + |t0c|) / ((t2c - r) t2c), likewise for t1.
+ * Returns 0 (use the whole detector) when the ball reaches the source plane. */
+static int ball_box(const view_t *V, const gauss3 *G, double kappa, int Wd, int Hd, int box[4]) {
+  double smax = sqrt(fmax(G->s2[0], fmax(G->s2[1], G->s2[2])));
+  double r = kappa * smax, t[3];
+  for (int a = 0; a < 3; ++a) {
+    t[a] = 0.0;
+    for (int b = 0; b < 3; ++b) t[a] += V->W[3 * a + b] * (G->p[b] - (V->parallel ? 0.0 : V->src[b]));
+  }
+  double cu, cv, hu, hv;
+  if (V->parallel) {
+    cu = V->Fu * t[0] + V->cu; cv = V->Fv * t[1] + V->cv;
+    hu = V->Fu * r; hv = V->Fv * r;
+  } else {
+    if (!(t[2] - r > 0.0)) return 0;
+    cu = V->Fu * t[0] / t[2] + V->cu; cv = V->Fv * t[1] / t[2] + V->cv;
+    hu = V->Fu * r * (t[2] + fabs(t[0])) / ((t[2] - r) * t[2]);
+    hv = V->Fv * r * (t[2] + fabs(t[1])) / ((t[2] - r) * t[2]);
+  }
+  box[0] = (int)floor(cu - hu - 1.5); box[1] = (int)ceil(cu + hu + 0.5);
+  box[2] = (int)floor(cv - hv - 1.5); box[3] = (int)ceil(cv + hv + 0.5);
+  if (box[0] < 0) box[0] = 0;
+  if (box[2] < 0) box[2] = 0;
+  if (box[1] > Wd - 1) box[1] = Wd - 1;
+  if (box[3] > Hd - 1) box[3] = Hd - 1;
+  return 1;
+}
+
+/* img[n_views][det_h][det_w] of the ray-exact model. brute != 0: every
+ * pixel against every Gaussian; else pixels inside each Gaussian's ball box. */
+void orc_exact_project(const double *g, double kappa, int n_views, const double *angles, long n,
+                       const double *mean, const double *ls, const double *quat, const double *dens,
+                       int brute, double *img) {
+  int Wd = (int)g[3], Hd = (int)g[4];
+  double k2 = kappa * kappa;
+  gauss3 *Gs = (gauss3 *)malloc(sizeof(gauss3) * (size_t)n);
+  double *As = (double *)malloc(sizeof(double) * 9 * (size_t)n);
+  for (long i = 0; i < n; ++i) {
+    load_gauss(n, i, mean, ls, quat, dens, &Gs[i]);
+    mat3_inv(Gs[i].Sig, As + 9 * i);
+  }
+  for (int v = 0; v < n_views; ++v) {
+    view_t V;
+    make_view(g, angles[v], &V);
+    double *out = img + (size_t)v * Wd * Hd;
+    if (brute) {
+#pragma omp parallel for schedule(static)
+      for (long k = 0; k < (long)Wd * Hd; ++k) {
+        double o[3], d[3], acc = 0.0;
+        detector_ray(&V, (double)(k % Wd) + 0.5, (double)(k / Wd) + 0.5, o, d);
+        for (long i = 0; i < n; ++i) {
+          if (!exact_valid(&V, &Gs[i], As + 9 * i, kappa)) continue;
+          ray_form F;
+          ray_form_of(&Gs[i], As + 9 * i, o, d, &F);
+          if (F.h <= k2) acc += Gs[i].rho * sqrt(TWO_PI / F.a) * exp(-0.5 * F.h);
+        }
+        out[k] = acc;
+      }
+      continue;
+    }
+    int *bx = (int *)malloc(sizeof(int) * 5 * (size_t)n);
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < n; ++i) {
+      int *b = bx + 5 * i;
+      b[4] = exact_valid(&V, &Gs[i], As + 9 * i, kappa);
+      b[0] = 0; b[1] = Wd - 1; b[2] = 0; b[3] = Hd - 1;
+      if (b[4]) ball_box(&V, &Gs[i], kappa, Wd, Hd, b);
+    }
+    /* each thread owns whole rows; Gaussians are visited in index order */
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int y = 0; y < Hd; ++y) {
+      for (int x = 0; x < Wd; ++x) out[(size_t)y * Wd + x] = 0.0;
+      for (long i = 0; i < n; ++i) {
+        const int *box = bx + 5 * i;
+        if (!box[4] || y < box[2] || y > box[3]) continue;
+        for (int x = box[0]; x <= box[1]; ++x) {
+          double o[3], d[3];
+          detector_ray(&V, x + 0.5, y + 0.5, o, d);
+          ray_form F;
+          ray_form_of(&Gs[i], As + 9 * i, o, d, &F);
+          if (F.h <= k2) out[(size_t)y * Wd + x] += Gs[i].rho * sqrt(TWO_PI / F.a) * exp(-0.5 * F.h);
+        }
+      }
+    }
+    free(bx);
+  }
+  free(Gs);
+  free(As);
+}
+
+/* The ray-exact model at arbitrary detector points of one view. */
+void orc_exact_points_cut(const double *g, double kappa, double angle, long n, const double *mean,
+                          const double *ls, const double *quat, const double *dens, long npts,
+                          const double *u, const double *v, double *out) {
+  view_t V;
+  make_view(g, angle, &V);
+  double k2 = kappa * kappa;
+  gauss3 *Gs = (gauss3 *)malloc(sizeof(gauss3) * (size_t)n);
+  double *As = (double *)malloc(sizeof(double) * 9 * (size_t)n);
+  int *ok = (int *)malloc(sizeof(int) * (size_t)n);
+  for (long i = 0; i < n; ++i) {
+    load_gauss(n, i, mean, ls, quat, dens, &Gs[i]);
+    mat3_inv(Gs[i].Sig, As + 9 * i);
+    ok[i] = exact_valid(&V, &Gs[i], As + 9 * i, kappa);
+  }
+#pragma omp parallel for schedule(static)
+  for (long k = 0; k < npts; ++k) {
+    double o[3], d[3], acc = 0.0;
+    detector_ray(&V, u[k], v[k], o, d);
+    for (long i = 0; i < n; ++i) {
+      if (!ok[i]) continue;
+      ray_form F;
+      ray_form_of(&Gs[i], As + 9 * i, o, d, &F);
+      if (F.h <= k2) acc += Gs[i].rho * sqrt(TWO_PI / F.a) * exp(-0.5 * F.h);
+    }
+    out[k] = acc;
+  }
+  free(Gs);
+  free(As);
+  free(ok);
+}
+
+/* Gradient of one (ray, Gaussian) term E = rho sqrt(2 pi / a) exp(-h / 2),
+ * h = c - b^2 / a, times gg, with respect to the mean, A = Sigma^-1 (full
+ * 3x3, symmetrised by the caller's conversion) and rho. */
+static void exact_term_grad(const gauss3 *G, const ray_form *F, const double d[3], double gg,
+                            double dp[3], double dA[9], double *drho) {
+  double e1 = sqrt(TWO_PI / F->a) * exp(-0.5 * F->h);
+  double E = G->rho * e1;
+  *drho += gg * e1;
+  double Ea = -0.5 * E * (1.0 / F->a + F->b * F->b / (F->a * F->a));
+  double Eb = E * F->b / F->a;
+  double Ec = -0.5 * E;
+  /* dE/dA = Ea d d^T + Eb d x0^T + Ec x0 x0^T; x0 = o - p, so dE/dp = -dE/dx0 */
+  for (int i = 0; i < 3; ++i) {
+    for (int j = 0; j < 3; ++j)
+      dA[3 * i + j] += gg * (Ea * d[i] * d[j] + Eb * d[i] * F->x0[j] + Ec * F->x0[i] * F->x0[j]);
+    dp[i] -= gg * (Eb * F->Ad[i] + 2.0 * Ec * F->Ax0[i]);
+  }
+}
+
+/* From dL/dA (A = Sigma^-1, full matrix) to the parameter gradients. */
+static void exact_chain(const gauss3 *G, const double A[9], const double dA[9], double dls[3], double dq[4]) {
+  double sym[9], tmp[9], dSig[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) sym[3 * i + j] = 0.5 * (dA[3 * i + j] + dA[3 * j + i]);
+  /* A = Sigma^-1: dSigma = -A dA A */
+  mat3_mul(A, sym, tmp);
+  mat3_mul(tmp, A, dSig);
+  for (int e = 0; e < 9; ++e) dSig[e] = -dSig[e];
+  sigma_to_params(G, dSig, dls, dq);
+}
+
+/* Gradient of sum(grad_img * E_cut) for the Gaussians in sel, the support
+ * held fixed; band as in orc_project_bwd, on h - kappa^2. */
+void orc_exact_bwd(const double *g, double kappa, int n_views, const double *angles, long n,
+                   const double *mean, const double *ls, const double *quat, const double *dens,
+                   const double *grad_img, long n_sel, const long *sel, double *dmean, double *dls,
+                   double *dq, double *drho, double band, double *band_abs) {
+  int Wd = (int)g[3], Hd = (int)g[4];
+  double k2 = kappa * kappa;
+  view_t *Vs = (view_t *)malloc(sizeof(view_t) * (size_t)n_views);
+  for (int v = 0; v < n_views; ++v) make_view(g, angles[v], &Vs[v]);
+#pragma omp parallel for schedule(dynamic, 4)
+  for (long k = 0; k < n_sel; ++k) {
+    gauss3 G;
+    double A[9];
+    load_gauss(n, sel[k], mean, ls, quat, dens, &G);
+    mat3_inv(G.Sig, A);
+    double dp[3] = {0, 0, 0}, dA[9] = {0}, r1 = 0.0, babs[11] = {0};
+    for (int v = 0; v < n_views; ++v) {
+      const view_t *V = &Vs[v];
+      if (!exact_valid(V, &G, A, kappa)) continue;
+      int box[4] = {0, Wd - 1, 0, Hd - 1};
+      ball_box(V, &G, sqrt(k2 + band), Wd, Hd, box);
+      const double *gi = grad_img + (size_t)v * Wd * Hd;
+      for (int y = box[2]; y <= box[3]; ++y)
+        for (int x = box[0]; x <= box[1]; ++x) {
+          double o[3], d[3];
+          detector_ray(V, x + 0.5, y + 0.5, o, d);
+          ray_form F;
+          ray_form_of(&G, A, o, d, &F);
+          if (F.h > k2 + band) continue;
+          double gg = gi[(size_t)y * Wd + x];
+          if (band > 0.0 && fabs(F.h - k2) <= band) {
+            double p1[3] = {0, 0, 0}, a1[9] = {0}, q1 = 0.0, l3[3], q4[4];
+            exact_term_grad(&G, &F, d, gg, p1, a1, &q1);
+            exact_chain(&G, A, a1, l3, q4);
+            for (int a = 0; a < 3; ++a) { babs[a] += fabs(p1[a]); babs[3 + a] += fabs(l3[a]); }
+            for (int c = 0; c < 4; ++c) babs[6 + c] += fabs(q4[c]);
+            babs[10] += fabs(q1);
+            continue;
+          }
+          if (F.h > k2) continue;
+          exact_term_grad(&G, &F, d, gg, dp, dA, &r1);
+        }
+    }
+    double l3[3], q4[4];
+    exact_chain(&G, A, dA, l3, q4);
+    for (int a = 0; a < 3; ++a) { dmean[a * n_sel + k] = dp[a]; dls[a * n_sel + k] = l3[a]; }
+    for (int c = 0; c < 4; ++c) dq[c * n_sel + k] = q4[c];
+    drho[k] = r1;
+    if (band_abs)
+      for (int c = 0; c < 11; ++c) band_abs[c * n_sel + k] = babs[c];
+  }
+  free(Vs);
 }
 
 /* ------------------------------------------------------------------ */

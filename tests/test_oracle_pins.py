@@ -290,6 +290,125 @@ def test_projection_gradient_matches_finite_differences_at_2048_detector():
     _fd_check(fwd, gs, ana, 1e-3, 1e-6)
 
 
+# --------------------------------------------------------------- ray-exact model (Eq. 3 with the support)
+
+def test_ray_exact_isotropic_closed_form_with_cutoff():
+    """An isotropic Gaussian (any rotation) integrates along a ray at
+    perpendicular distance r from its mean to rho sigma sqrt(2 pi)
+    exp(-r^2 / (2 sigma^2)), and the model keeps it iff r <= kappa sigma.
+    r comes from the cross product with the ray's unit direction."""
+    rng = np.random.default_rng(31)
+    n = 5
+    sig = np.array([0.03, 0.05, 0.02, 0.04, 0.06])
+    gs = dict(mean=rng.uniform(-0.2, 0.2, size=(3, n)), log_scale=np.tile(np.log(sig), (3, 1)),
+              quat=rng.normal(size=(4, n)), density=rng.uniform(0.3, 1.0, size=n))
+    for mode in ("cone", "parallel"):
+        geom = si.geometry(64, mode=mode)
+        ang = 1.3
+        rec = oracle.splat_records(gs, geom, [ang])
+        for i in range(n):
+            g1 = subset(gs, [i])
+            # points around the projected centre, out to beyond the support
+            u = rec["uv"][i, 0] + rng.uniform(-12, 12, size=300)
+            v = rec["uv"][i, 1] + rng.uniform(-12, 12, size=300)
+            o, d = oracle.rays(geom, ang, u, v)
+            r = np.linalg.norm(np.cross(gs["mean"][:, i] - o, d), axis=1)
+            ref = gs["density"][i] * sig[i] * math.sqrt(2 * math.pi) * np.exp(-0.5 * (r / sig[i]) ** 2)
+            ref[r > 3.0 * sig[i]] = 0.0
+            got = oracle.exact_points_cut(g1, geom, ang, u, v, kappa=3.0)
+            far = np.abs(r / sig[i] - 3.0) > 1e-9
+            assert 0 < np.sum(ref > 0) < 300
+            np.testing.assert_allclose(got[far], ref[far], rtol=1e-10, atol=1e-15)
+
+
+def test_ray_exact_large_kappa_matches_quadrature():
+    gs = _random_scene(4, 32)
+    for mode in ("cone", "parallel"):
+        geom = si.geometry(64, mode=mode)
+        ang = 2.1
+        rec = oracle.splat_records(gs, geom, [ang])
+        u = rec["uv"][:, 0] + np.array([0.4, -2.1, 1.0, 0.0])
+        v = rec["uv"][:, 1] + np.array([-0.7, 0.3, 2.0, -1.2])
+        lo, hi = (0.5, 2.5) if mode == "cone" else (1.0, 3.0)
+        q = oracle.quadrature_points(gs, geom, ang, u, v, lo, hi)
+        np.testing.assert_allclose(oracle.exact_points_cut(gs, geom, ang, u, v, kappa=20.0), q,
+                                   rtol=1e-9, atol=1e-14)
+
+
+def test_ray_exact_image_boxed_equals_brute_force_and_points():
+    """The per-Gaussian pixel boxes are a superset of the support (brute
+    force over every pixel gives the same image), and image pixels equal the
+    point evaluation at pixel centres."""
+    gs = _random_scene(30, 33, sigma=0.05)
+    for mode in ("cone", "parallel"):
+        geom = si.geometry(40, 36, mode=mode)
+        geom["off_u"], geom["off_v"] = 2.5, -1.25
+        ang = [0.2, 3.9]
+        a = oracle.exact_project(gs, geom, ang)
+        b = oracle.exact_project(gs, geom, ang, brute=True)
+        np.testing.assert_allclose(a, b, rtol=1e-13, atol=1e-15)
+        ys, xs = np.meshgrid(np.arange(36), np.arange(40), indexing="ij")
+        pts = oracle.exact_points_cut(gs, geom, ang[1], xs.ravel() + 0.5, ys.ravel() + 0.5)
+        np.testing.assert_allclose(a[1].ravel(), pts, rtol=1e-13, atol=1e-15)
+        assert a.max() > 0.1
+
+
+def test_ray_exact_equals_splat_in_parallel_beam():
+    """For parallel rays the projected 3D Gaussian is exactly the 2D splat and
+    the ray's Mahalanobis distance is the splat's, so E_kappa = M_kappa
+    pixel for pixel (away from the support boundary)."""
+    gs = _random_scene(20, 34, sigma=0.05)
+    geom = si.geometry(48, mode="parallel")
+    ang = [0.6, 2.0]
+    e = oracle.exact_project(gs, geom, ang)
+    m = oracle.project(gs, geom, ang)
+    np.testing.assert_allclose(e, m, rtol=1e-9, atol=1e-12 * m.max())
+
+
+def test_ray_exact_differs_from_splat_in_cone_beam():
+    """In cone beam the model gap is real: on the standard scan's geometry the
+    splat's image departs from the ray-exact one by a fraction of a percent."""
+    gs = si.gaussians(300, 35)
+    geom = si.geometry(128)
+    ang = si.angles(3)
+    e = oracle.exact_project(gs, geom, ang)
+    m = oracle.project(gs, geom, ang)
+    gap = oracle.rel_l2(m, e)
+    assert 1e-4 < gap < 5e-2, gap
+
+
+def test_ray_exact_gradient_matches_finite_differences():
+    """Analytic FP64 gradient of <c, E_kappa> (kappa = 8: the cutoff is
+    invisible at the step size) vs Richardson central differences."""
+    gs = _random_scene(4, 36, sigma=0.05)
+    for mode in ("cone", "parallel"):
+        geom = si.geometry(32, mode=mode)
+        ang = [0.45, 2.9]
+        c = np.random.default_rng(5).normal(size=(2, 32, 32))
+        fwd = lambda g: float(np.sum(c * oracle.exact_project(g, geom, ang, kappa=8.0)))
+        ana = oracle.exact_bwd(gs, geom, ang, c, kappa=8.0)
+        _fd_check(fwd, gs, ana, 1e-4, 1e-7)
+
+
+def test_ray_exact_gradient_holds_the_support_fixed():
+    """At kappa = 3 the gradient is that of the uncut integrals summed over
+    the pixels in the support at the unperturbed parameters."""
+    gs = _random_scene(3, 37, sigma=0.1)
+    geom = si.geometry(32)
+    ang = [1.0]
+    c = np.random.default_rng(6).normal(size=(1, 32, 32))
+    ys, xs = np.meshgrid(np.arange(32), np.arange(32), indexing="ij")
+    u, v = xs.ravel() + 0.5, ys.ravel() + 0.5
+    ana = oracle.exact_bwd(gs, geom, ang, c, kappa=3.0)
+    for i in range(3):
+        g1 = subset(gs, [i])
+        inside = oracle.exact_points_cut(g1, geom, ang[0], u, v, kappa=3.0) > 0
+        assert 20 < inside.sum() < 1024
+        cu, uu, vv = c[0].ravel()[inside], u[inside], v[inside]
+        fwd = lambda g: float(np.sum(cu * oracle.exact_points(g, geom, ang[0], uu, vv)))
+        _fd_check(fwd, g1, {k: ana[k][..., i:i + 1] for k in ana}, 1e-4, 1e-7)
+
+
 def test_voxelizer_gradient_matches_finite_differences():
     gs = _random_scene(4, 22, sigma=0.06)
     grid = si.grid(24)
