@@ -150,8 +150,9 @@ def cpu_baseline(gs, gd, ang, grid_d, budget_s=12.0):
                 seconds_per_step=step_s)
 
 
-ABLATIONS = (("design", 0), ("square boxes", 1), ("no quadrant culling", 2), ("per-pixel atomic backward", 4),
-             ("all three", 7))
+ABLATIONS = (("design", 0, "splat"), ("square boxes", 1, "splat"), ("no quadrant culling", 2, "splat"),
+             ("per-pixel atomic backward", 4, "splat"), ("all three", 7, "splat"),
+             ("ray-exact model (E of Eq. 3 instead of M)", 0, "exact"))
 
 
 def ablation(fgs, params, geom, i_gt, V, D, steps, log):
@@ -164,11 +165,13 @@ def ablation(fgs, params, geom, i_gt, V, D, steps, log):
     gp = [torch.empty_like(p) for p in params]
     ws_p, ws_l = fgs.Workspace(dev), fgs.Workspace(dev, 1 << 16)
     rows = {}
-    for name, flag in ABLATIONS:
-        def step():
-            fgs.project_views(*params, geom, ws=ws_p, out=img, ablate=flag)
+    for name, flag, model in ABLATIONS:
+        def step(ev=None):
+            e = ev or {}
+            fgs.project_views(*params, geom, ws=ws_p, out=img, ablate=flag, model=model, events=e.get("fwd"))
             _, g = fgs.l1_loss_grad(img, i_gt, ws=ws_l)
-            fgs.project_views_backward(*params, geom, g, recompute=False, ws=ws_p, out=gp, ablate=flag)
+            fgs.project_views_backward(*params, geom, g, recompute=False, ws=ws_p, out=gp, ablate=flag,
+                                       model=model, events=e.get("bwd"))
         step()
         torch.cuda.synchronize()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -177,8 +180,14 @@ def ablation(fgs, params, geom, i_gt, V, D, steps, log):
             step()
         b.record()
         torch.cuda.synchronize()
-        rows[name] = dict(ms=a.elapsed_time(b) / steps, keys=ws_p.n_pairs)
-        log(f"ablation {name}: {rows[name]['ms']:.3f} ms per fwd+bwd over {V} views, {ws_p.n_pairs} keys")
+        ev = {k: fgs.timing_events() for k in ("fwd", "bwd")}
+        step(ev)
+        torch.cuda.synchronize()
+        pairs = fgs.project_views_support(*params, geom, model=model)
+        rows[name] = dict(ms=a.elapsed_time(b) / steps, keys=ws_p.n_pairs, support_pairs=pairs,
+                          pixel_kernel_ms={k: v[0].elapsed_time(v[1]) for k, v in ev.items()})
+        log(f"ablation {name}: {rows[name]['ms']:.3f} ms per fwd+bwd over {V} views, {ws_p.n_pairs} keys, "
+            f"pixel kernels {rows[name]['pixel_kernel_ms']}, {pairs} support pairs")
     print(json.dumps(dict(ablation="rasterizer fwd+L1+bwd, standard scan", steps=steps, rows=rows)), flush=True)
 
 

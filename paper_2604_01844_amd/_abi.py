@@ -21,6 +21,8 @@ FGS_E_HIP = -3
 FGS_E_UNSUPPORTED = -4
 FGS_CONE = 0
 FGS_PARALLEL = 1
+FGS_MODEL_SPLAT = 0
+FGS_MODEL_RAY_EXACT = 1
 
 _vp = ctypes.c_void_p
 
@@ -49,7 +51,7 @@ class fgs_grid(ctypes.Structure):
 class fgs_opts(ctypes.Structure):
     _fields_ = [("kappa", ctypes.c_float), ("near_plane", ctypes.c_float),
                 ("recompute", ctypes.c_int32), ("accumulate", ctypes.c_int32), ("ablate", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("events", _vp)]
+                ("model", ctypes.c_int32), ("events", _vp)]
 
 
 class fgs_workspace(ctypes.Structure):

@@ -30,7 +30,7 @@ extern "C" const char *fgs_version(void) { return "factgs-gfx950 0.1"; }
 
 extern "C" int fgs_binning_layout(const fgs_workspace *ws, uint64_t off[9], uint64_t counts[3]) {
   if (!ws || !off || !counts) return fgs::fail(FGS_E_INVALID, "null argument");
-  if (ws->kind == 1) return fgs::rast_binning_layout(ws, off, counts);
+  if (ws->kind == 1 || ws->kind == 3) return fgs::rast_binning_layout(ws, off, counts);
   if (ws->kind == 2) return fgs::vox_binning_layout(ws, off, counts);
   return fgs::fail(FGS_E_INVALID, "workspace holds no lists");
 }

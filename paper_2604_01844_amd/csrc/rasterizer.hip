@@ -31,7 +31,7 @@
 //   8. record-grad kernel per record: reduce its contiguous partials in order
 //                         and apply the chain rule to the 11 parameters.
 //   9. view-sum kernel    per Gaussian: sum its records over views in order.
-#include "splat_math.h"
+#include "exact_math.h"
 
 namespace fgs {
 namespace {
@@ -121,15 +121,80 @@ __device__ __forceinline__ uint32_t record_one(const fgs_gaussians &g, const Geo
   return cnt;
 }
 
+// Ray-exact model: one 64-byte record per (view, Gaussian) pair,
+//   a = (u, v, K00, K01), b = (K11, lu, lv, a0), c = (C00, C01, C11, escale),
+//   d = (w, base, width, 0), escale = -t2^2 log2(e) / 2, w = rho sqrt(2 pi),
+// in the notation of exact_math.h; the pair slot is base + ty * width + tx.
+struct ExactRec {
+  float4 a, b, c, d;
+};
+
+// The tile rectangle of the support ellipse is widened by this factor, so
+// FP32 rounding of the box never drops a pixel the per-pixel test keeps.
+constexpr float kExactBoxSlack = 1.0005f;
+constexpr float kLn2 = 0.6931471805599453f;
+
+__device__ __forceinline__ uint32_t record_one_exact(const fgs_gaussians &g, const GeomDev &G, int64_t i,
+                                                     int v_local, float2 *__restrict__ xy,
+                                                     ExactRec *__restrict__ rec, float2 *__restrict__ radii,
+                                                     ushort4 *__restrict__ rect, uint32_t *__restrict__ count) {
+  const int64_t r = int64_t(v_local) * g.n + i;
+  GaussParams P;
+  load_gauss(g, i, P);
+  ViewFrame F;
+  make_frame(G, G.view_begin + v_local, F);
+  ExactSplat X;
+  exact_forward(P, F, G, X);
+  float dcx = 0.f, dcy = 0.f, hx = 0.f, hy = 0.f, cs00, cs01, cs11;
+  const bool ok = X.ok && exact_silhouette(X.K00, X.K01, X.K11, X.lu, X.lv, X.a0, X.C00, X.C01, X.C11,
+                                           X.t[2] * X.t[2], G.kappa * G.kappa, dcx, dcy, hx, hy, cs00, cs01,
+                                           cs11);
+  int x0 = 1, x1 = 0, y0 = 1, y1 = 0;
+  const float cx = X.u + dcx, cy = X.v + dcy;
+  const float ru = hx * kExactBoxSlack, rv = hy * kExactBoxSlack;
+  if (ok) {
+    tile_span(cx, ru, G.tiles_x, x0, x1);
+    tile_span(cy, rv, G.tiles_y, y0, y1);
+  }
+  const bool empty = !ok || (x0 > x1) || (y0 > y1);
+  if (!ok) {
+    xy[r] = make_float2(0.f, 0.f);
+    radii[r] = make_float2(0.f, 0.f);
+    rec[r].a = rec[r].b = rec[r].c = rec[r].d = make_float4(0.f, 0.f, 0.f, 0.f);
+  } else {
+    xy[r] = make_float2(cx, cy);
+    radii[r] = make_float2(ru, rv);
+    rec[r].a = make_float4(X.u, X.v, X.K00, X.K01);
+    rec[r].b = make_float4(X.K11, X.lu, X.lv, X.a0);
+    rec[r].c = make_float4(X.C00, X.C01, X.C11, X.esn * kLog2e);
+    rec[r].d = make_float4(X.w, 0.f, __uint_as_float(empty ? 0u : uint32_t(x1 - x0 + 1)), 0.f);
+  }
+  if (empty) {
+    rect[r] = make_ushort4(1, 1, 0, 0);
+    count[r] = 0;
+    return 0;
+  }
+  rect[r] = make_ushort4(x0, y0, x1, y1);
+  const uint32_t cnt = uint32_t(x1 - x0 + 1) * uint32_t(y1 - y0 + 1);
+  count[r] = cnt;
+  return cnt;
+}
+
+template <bool kExact>
 __global__ __launch_bounds__(256) void record_kernel(fgs_gaussians g, GeomDev G, float2 *__restrict__ xy,
-                                                     SplatRec *__restrict__ rec,
+                                                     void *__restrict__ rec,
                                                      float2 *__restrict__ radii,
                                                      ushort4 *__restrict__ rect,
                                                      uint32_t *__restrict__ count,
                                                      unsigned long long *__restrict__ total64) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   uint32_t cnt = 0;
-  if (i < g.n) cnt = record_one(g, G, i, int(blockIdx.y), xy, rec, radii, rect, count);
+  if (i < g.n) {
+    if (kExact)
+      cnt = record_one_exact(g, G, i, int(blockIdx.y), xy, static_cast<ExactRec *>(rec), radii, rect, count);
+    else
+      cnt = record_one(g, G, i, int(blockIdx.y), xy, static_cast<SplatRec *>(rec), radii, rect, count);
+  }
   // 64-bit pair total (detects a 32-bit scan overflow): one atomic per wave,
   // spread over kTotalSlots addresses to keep contention low
   unsigned long long w = cnt;
@@ -142,7 +207,8 @@ __global__ __launch_bounds__(kEmitBlock) void emit_kernel(uint64_t R, int64_t n,
                                                           const ushort4 *__restrict__ rect,
                                                           const uint32_t *__restrict__ offset,
                                                           uint32_t *__restrict__ keys,
-                                                          uint32_t *__restrict__ vals, SplatRec *__restrict__ rec) {
+                                                          uint32_t *__restrict__ vals, float *__restrict__ base_field,
+                                                          uint32_t base_stride) {
   __shared__ uint32_t s_off[kEmitBlock + 1];
   __shared__ ushort4 s_rect[kEmitBlock];
   const uint64_t r0 = uint64_t(blockIdx.x) * kEmitBlock;
@@ -156,7 +222,7 @@ __global__ __launch_bounds__(kEmitBlock) void emit_kernel(uint64_t R, int64_t n,
     s_rect[t] = rc;
     if (offset[r + 1] != o) {
       const uint32_t wdt = uint32_t(rc.z) - rc.x + 1u;
-      rec[r].b.z = __uint_as_float(o - uint32_t(rc.y) * wdt - uint32_t(rc.x));
+      base_field[r * base_stride] = __uint_as_float(o - uint32_t(rc.y) * wdt - uint32_t(rc.x));
     }
   }
   if (t == 0) s_off[nr] = offset[r0 + nr];
@@ -689,6 +755,391 @@ __global__ __launch_bounds__(256) void view_sum_kernel(int64_t n, int views,
   out.density[i] = acc[10];
 }
 
+// ---------------------------------------------------------------- ray-exact pixel kernels
+//
+// Same tiling, quadrant culling (against the support ellipse of the model)
+// and lists as the splat kernels; per pixel the exact line integral of the
+// record's Gaussian (exact_math.h) replaces the splat:
+//   A = a0 + 2 l.delta + delta^T K delta, C = delta^T C delta,
+//   contribution w A^-1/2 exp2(escale C / A) where escale C / A >= thr,
+// and the pixel's |d| multiplies the sum (forward) or dL/dI (backward).
+
+// Quadrant mask of a ray-exact record (all four quadrants if the support
+// ellipse comes out degenerate in FP32: the per-pixel test then decides).
+__device__ __forceinline__ uint32_t exact_quad_mask(const float4 &ra, const float4 &rb, const float4 &rc, float k2,
+                                                    float tx0, float ty0, float thr_cull) {
+  float dcx, dcy, hx, hy, cs00, cs01, cs11;
+  const float t2sq = -2.f * kLn2 * rc.w;
+  if (!exact_silhouette(ra.z, ra.w, rb.x, rb.y, rb.z, rb.w, rc.x, rc.y, rc.z, t2sq, k2, dcx, dcy, hx, hy, cs00,
+                        cs01, cs11))
+    return 0xFu;
+  const float k = -0.5f * kLog2e;
+  const float4 c = make_float4(k * cs00, 2.f * k * cs01, k * cs11, 0.f);
+  return quad_mask(c, ra.x + dcx, ra.y + dcy, tx0, ty0, thr_cull);
+}
+
+// |d| of the ray through pixel coordinate (x, y): the arc length per unit depth.
+__device__ __forceinline__ float ray_length(float x, float y, float fu, float fv, float cu, float cv) {
+  const float s = (x - cu) / fu, r = (y - cv) / fv;
+  return sqrtf(fmaf(s, s, fmaf(r, r, 1.f)));
+}
+
+// A record that contributes nothing: zero weight, exponent far below thr.
+__device__ __forceinline__ void set_null_exact(float4 *s_a, float4 *s_b, float4 *s_c) {
+  s_a[kWave] = make_float4(-1.0e4f, -1.0e4f, 0.f, 0.f);
+  s_b[kWave] = make_float4(0.f, 0.f, 0.f, 1.f);
+  s_c[kWave] = make_float4(1.f, 0.f, 1.f, -1.f);
+}
+
+struct ExactCam {
+  float fu, fv, cu, cv, k2;
+};
+
+template <bool kCount, int TPB>
+__global__ __launch_bounds__(kWave * TPB) void splat_fwd_exact_kernel(
+    const uint32_t *__restrict__ start, const uint32_t *__restrict__ svals, const ExactRec *__restrict__ rec,
+    int tiles_x, int tpv, int W, int H, uint32_t n_tiles, int n_chunks, float thr, float thr_cull, ExactCam cam,
+    float *__restrict__ img, unsigned long long *__restrict__ counter) {
+  __shared__ float4 s_a_all[TPB][kWave + 1];
+  __shared__ float4 s_b_all[TPB][kWave + 1];
+  __shared__ float4 s_c_all[TPB][kWave + 1];
+  __shared__ float s_w_all[TPB][kWave + 1];
+  __shared__ uint8_t s_list_all[TPB][4][kWave];
+  const int wid = threadIdx.x / kWave;
+  float4 *s_a = s_a_all[wid];
+  float4 *s_b = s_b_all[wid];
+  float4 *s_c = s_c_all[wid];
+  float *s_w = s_w_all[wid];
+  uint8_t(*s_list)[kWave] = s_list_all[wid];
+  const uint32_t unit = blockIdx.x * TPB + wid;
+  if (unit >= n_tiles * uint32_t(n_chunks)) return;
+  const uint32_t tile = unit / uint32_t(n_chunks);
+  const uint32_t chunk = unit - tile * uint32_t(n_chunks);
+  const uint32_t v_local = tile / uint32_t(tpv);
+  const uint32_t t = tile - v_local * uint32_t(tpv);
+  const int ty = int(t) / tiles_x;
+  const int tx = int(t) - ty * tiles_x;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int grp = lane >> 4;
+  const int sub = lane & 15;
+  const int col = (grp & 1) * 8 + (sub & 7);
+  const int row0 = (grp >> 1) * 8 + (sub >> 3) * kRows;
+  const float px = float(tx * kTS + col) + 0.5f;
+  const float py = float(ty * kTS + row0) + 0.5f;
+  const float tx0 = float(tx * kTS) + 0.5f, ty0 = float(ty * kTS) + 0.5f;
+  if (lane == 0) {
+    set_null_exact(s_a, s_b, s_c);
+    s_w[kWave] = 0.f;
+  }
+  float acc[kRows];
+#pragma unroll
+  for (int k = 0; k < kRows; ++k) acc[k] = 0.f;
+  const uint32_t b0 = start[tile], e = start[tile + 1];
+  for (uint32_t b = b0 + chunk * kWave; b < e; b += kWave * uint32_t(n_chunks)) {
+    const uint32_t m = min(uint32_t(kWave), e - b);
+    uint32_t mask = 0;
+    if (uint32_t(lane) < m) {
+      const uint32_t r = svals[b + lane];
+      const float4 ra = rec[r].a, rb = rec[r].b, rc = rec[r].c;
+      s_a[lane] = ra;
+      s_b[lane] = rb;
+      s_c[lane] = rc;
+      s_w[lane] = rec[r].d.x;
+      mask = exact_quad_mask(ra, rb, rc, cam.k2, tx0, ty0, thr_cull);
+    }
+    int nq[4], pos[4];
+    build_quad_lists(mask, lane, s_list, nq, pos);
+    const int n_me = (grp == 0) ? nq[0] : (grp == 1) ? nq[1] : (grp == 2) ? nq[2] : nq[3];
+    const int n_max = max(max(nq[0], nq[1]), max(nq[2], nq[3]));
+    wave_lds_sync();
+    for (int i = 0; i < n_max; ++i) {
+      const int j = (i < n_me) ? int(s_list[grp][i]) : kWave;
+      const float4 ra = s_a[j], rb = s_b[j], rc = s_c[j];
+      const float w = s_w[j];
+      const float dx = px - ra.x;
+      const float dy0 = py - ra.y;
+      const float Kx = ra.z * dx * dx, K1 = 2.f * ra.w * dx;
+      const float Cx = rc.x * dx * dx, C1 = 2.f * rc.y * dx;
+      const float Lx = rb.y * dx;
+#pragma unroll
+      for (int k = 0; k < kRows; ++k) {
+        const float dy = dy0 + float(k);
+        const float K = fmaf(dy, fmaf(rb.x, dy, K1), Kx);
+        const float C = fmaf(dy, fmaf(rc.z, dy, C1), Cx);
+        const float L = fmaf(rb.z, dy, Lx);
+        const float A = fmaf(2.f, L, rb.w + K);
+        const float ri = __builtin_amdgcn_rsqf(A);
+        const float arg = rc.w * C * (ri * ri);
+        if (kCount) {
+          acc[k] += (arg >= thr) ? 1.f : 0.f;
+        } else {
+          const float ex = __builtin_amdgcn_exp2f(arg);
+          acc[k] = fmaf(w * ri, (arg >= thr) ? ex : 0.f, acc[k]);
+        }
+      }
+    }
+    wave_lds_sync();
+  }
+  const int x = tx * kTS + col;
+  if (kCount) {
+    unsigned long long n = 0;
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+      const int y = ty * kTS + row0 + k;
+      if (x < W && y < H) n += static_cast<unsigned long long>(acc[k]);
+    }
+    for (int d = 32; d > 0; d >>= 1) n += __shfl_xor(n, d, 64);
+    if (lane == 0 && n) atomicAdd(counter, n);
+    return;
+  }
+  float *out = img + (uint64_t(chunk) * (n_tiles / uint32_t(tpv)) + v_local) * uint64_t(W) * uint64_t(H);
+#pragma unroll
+  for (int k = 0; k < kRows; ++k) {
+    const int y = ty * kTS + row0 + k;
+    if (x < W && y < H) out[uint64_t(y) * W + x] = acc[k] * ray_length(px, py + float(k), cam.fu, cam.fv, cam.cu, cam.cv);
+  }
+}
+
+// Number of per-pair sums of the ray-exact backward (exact_backward's s[]);
+// a pair's slot holds them in 16 floats (64 bytes).
+constexpr int kExactSums = 13;
+
+// Backward of the ray-exact model over one tile, organised as the splat
+// backward: one lane per (quadrant, Gaussian) pair sums over the quadrant's
+// 64 pixels, coordinates relative to the quadrant centre; per row the sums
+// against the column constants cc, cc^2 are folded with the row constants,
+// then moved to the Gaussian's centre. With p = g |d| A^-1/2 exp(phi) the
+// sums are those exact_backward takes: sum p, sum p C / A, and the moments
+// of alpha = -(p / A)(1/2 + phi) and beta = p / A.
+template <int TPB>
+__global__ __launch_bounds__(kWave * TPB) void splat_bwd_exact_kernel(
+    const uint32_t *__restrict__ start, const uint32_t *__restrict__ svals, const ExactRec *__restrict__ rec,
+    int tiles_x, int tpv, int W, int H, uint32_t n_tiles, int n_chunks, float thr, float thr_cull, ExactCam cam,
+    const float *__restrict__ gimg, float4 *__restrict__ partials) {
+  __shared__ float4 s_g4_all[TPB][kTS * kTS / 4];
+  __shared__ float4 s_a_all[TPB][kWave + 1];
+  __shared__ float4 s_b_all[TPB][kWave + 1];
+  __shared__ float4 s_c_all[TPB][kWave + 1];
+  __shared__ uint8_t s_cat_all[TPB][4 * kWave];
+  const int wid = threadIdx.x / kWave;
+  float4 *s_g4 = s_g4_all[wid];
+  float *s_g = reinterpret_cast<float *>(s_g4);
+  float4 *s_a = s_a_all[wid];
+  float4 *s_b = s_b_all[wid];
+  float4 *s_c = s_c_all[wid];
+  uint8_t *s_cat = s_cat_all[wid];
+  const uint32_t unit = blockIdx.x * TPB + wid;
+  if (unit >= n_tiles * uint32_t(n_chunks)) return;
+  const uint32_t tile = unit / uint32_t(n_chunks);
+  const uint32_t chunk = unit - tile * uint32_t(n_chunks);
+  const uint32_t v_local = tile / uint32_t(tpv);
+  const uint32_t t = tile - v_local * uint32_t(tpv);
+  const int ty = int(t) / tiles_x;
+  const int tx = int(t) - ty * tiles_x;
+  const int lane = threadIdx.x & (kWave - 1);
+  const float *gv = gimg + uint64_t(v_local) * uint64_t(W) * uint64_t(H);
+  for (int p = lane; p < kTS * kTS; p += kWave) {
+    const int x = tx * kTS + (p & (kTS - 1));
+    const int y = ty * kTS + (p >> 4);
+    s_g[p] = (x < W && y < H)
+                 ? gv[uint64_t(y) * W + x] * ray_length(float(x) + 0.5f, float(y) + 0.5f, cam.fu, cam.fv, cam.cu, cam.cv)
+                 : 0.f;
+  }
+  if (lane == 0) set_null_exact(s_a, s_b, s_c);
+  wave_lds_sync();
+  const float tx0 = float(tx * kTS) + 0.5f, ty0 = float(ty * kTS) + 0.5f;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const uint32_t b0 = start[tile], e = start[tile + 1];
+  for (uint32_t b = b0 + chunk * kWave; b < e; b += kWave * uint32_t(n_chunks)) {
+    const uint32_t m = min(uint32_t(kWave), e - b);
+    uint32_t mask = 0, slot = 0;
+    if (uint32_t(lane) < m) {
+      const uint32_t r = svals[b + lane];
+      const float4 ra = rec[r].a, rb = rec[r].b, rc = rec[r].c, rd = rec[r].d;
+      slot = __float_as_uint(rd.y) + uint32_t(ty) * __float_as_uint(rd.z) + uint32_t(tx);
+      s_a[lane] = ra;
+      s_b[lane] = rb;
+      s_c[lane] = rc;
+      mask = exact_quad_mask(ra, rb, rc, cam.k2, tx0, ty0, thr_cull);
+    }
+    int n_pairs = 0;
+    uint32_t gpk = 0;
+#pragma unroll
+    for (int Q = 0; Q < 4; ++Q) {
+      const bool bit = (mask >> Q) & 1u;
+      const uint64_t bal = __ballot(bit);
+      const int gp = n_pairs + __popcll(bal & lt);
+      if (bit) s_cat[gp] = uint8_t((Q << 6) | lane);
+      gpk |= uint32_t(gp & 255) << (8 * Q);
+      n_pairs += __popcll(bal);
+    }
+    wave_lds_sync();
+    float tot[kExactSums];
+#pragma unroll
+    for (int k = 0; k < kExactSums; ++k) tot[k] = 0.f;
+    for (int base = 0; base < n_pairs; base += kWave) {
+      const int idx = base + lane;
+      int Q = 0, j = kWave;
+      if (idx < n_pairs) {
+        const int ent = s_cat[idx];
+        Q = ent >> 6;
+        j = ent & 63;
+      }
+      const float ox = float(tx * kTS + (Q & 1) * 8) + 4.f;
+      const float oy = float(ty * kTS + (Q >> 1) * 8) + 4.f;
+      const float4 *g4q = s_g4 + (Q >> 1) * 8 * (kTS / 4) + (Q & 1) * 2;
+      const float4 ra = s_a[j], rb = s_b[j], rc = s_c[j];
+      const float qx = ra.x - ox, qy = ra.y - oy;
+      float Sw = 0.f, Se = 0.f;
+      float a0 = 0.f, ac = 0.f, acc2 = 0.f, ar = 0.f, acr = 0.f, arr = 0.f;
+      float b0s = 0.f, bc = 0.f, bcc = 0.f, br = 0.f, bcr = 0.f, brr = 0.f;
+#pragma unroll 1
+      for (int row = 0; row < 8; ++row) {
+        const float rr = float(row) - 3.5f;
+        const float dy = rr - qy;
+        const float Krow1 = 2.f * ra.w * dy, Krow0 = rb.x * dy * dy;
+        const float Crow1 = 2.f * rc.y * dy, Crow0 = rc.z * dy * dy;
+        const float Lrow = rb.z * dy;
+        float Ra0 = 0.f, Ra1 = 0.f, Ra2 = 0.f, Rb0 = 0.f, Rb1 = 0.f, Rb2 = 0.f;
+#pragma unroll
+        for (int qd = 0; qd < 2; ++qd) {
+          const float4 gq = g4q[row * (kTS / 4) + qd];
+          const float gcol[4] = {gq.x, gq.y, gq.z, gq.w};
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const float cc = float(qd * 4 + u) - 3.5f;
+            const float dx = cc - qx;
+            const float K = fmaf(dx, fmaf(ra.z, dx, Krow1), Krow0);
+            const float C = fmaf(dx, fmaf(rc.x, dx, Crow1), Crow0);
+            const float L = fmaf(rb.y, dx, Lrow);
+            const float A = fmaf(2.f, L, rb.w + K);
+            const float ri = __builtin_amdgcn_rsqf(A);
+            const float ia = ri * ri;
+            const float arg = rc.w * C * ia;
+            const float ex = __builtin_amdgcn_exp2f(arg);
+            const float p = ((arg >= thr) ? gcol[u] : 0.f) * ri * ex;
+            const float be = p * ia;
+            const float al = -be * fmaf(arg, kLn2, 0.5f);
+            Sw += p;
+            Se = fmaf(be, C, Se);
+            Ra0 += al;
+            Ra1 = fmaf(al, cc, Ra1);
+            Ra2 = fmaf(al, cc * cc, Ra2);
+            Rb0 += be;
+            Rb1 = fmaf(be, cc, Rb1);
+            Rb2 = fmaf(be, cc * cc, Rb2);
+          }
+        }
+        a0 += Ra0; ac += Ra1; acc2 += Ra2;
+        ar = fmaf(Ra0, rr, ar); acr = fmaf(Ra1, rr, acr); arr = fmaf(Ra0, rr * rr, arr);
+        b0s += Rb0; bc += Rb1; bcc += Rb2;
+        br = fmaf(Rb0, rr, br); bcr = fmaf(Rb1, rr, bcr); brr = fmaf(Rb0, rr * rr, brr);
+      }
+      // moments about the Gaussian's centre: dx = cc - qx, dy = rr - qy
+      float M[kExactSums];
+      M[0] = Sw;
+      M[1] = Se;
+      M[2] = a0;
+      M[3] = fmaf(-qx, a0, ac);
+      M[4] = fmaf(-qy, a0, ar);
+      M[5] = fmaf(qx * qx, a0, fmaf(-2.f * qx, ac, acc2));
+      M[6] = fmaf(qx * qy, a0, fmaf(-qy, ac, fmaf(-qx, ar, acr)));
+      M[7] = fmaf(qy * qy, a0, fmaf(-2.f * qy, ar, arr));
+      M[8] = fmaf(-qx, b0s, bc);
+      M[9] = fmaf(-qy, b0s, br);
+      M[10] = fmaf(qx * qx, b0s, fmaf(-2.f * qx, bc, bcc));
+      M[11] = fmaf(qx * qy, b0s, fmaf(-qy, bc, fmaf(-qx, br, bcr)));
+      M[12] = fmaf(qy * qy, b0s, fmaf(-2.f * qy, br, brr));
+#pragma unroll
+      for (int QQ = 0; QQ < 4; ++QQ) {
+        const int rel = int((gpk >> (8 * QQ)) & 255u) - base;
+        const bool mine = ((mask >> QQ) & 1u) && rel >= 0 && rel < kWave;
+        if (__ballot(mine) == 0ull) continue;
+        const int src = mine ? rel : 0;
+#pragma unroll
+        for (int k = 0; k < kExactSums; ++k) {
+          const float v = bperm(src, M[k]);
+          tot[k] += mine ? v : 0.f;
+        }
+      }
+    }
+    if (uint32_t(lane) < m) {
+      float4 *o = partials + 4 * uint64_t(slot);
+      o[0] = make_float4(tot[0], tot[1], tot[2], tot[3]);
+      o[1] = make_float4(tot[4], tot[5], tot[6], tot[7]);
+      o[2] = make_float4(tot[8], tot[9], tot[10], tot[11]);
+      o[3] = make_float4(tot[12], 0.f, 0.f, 0.f);
+    }
+    wave_lds_sync();
+  }
+}
+
+// Ray-exact counterpart of record_grad_kernel: each record's 64-byte slots
+// are reduced in order (groups of kGradLanes lanes, fixed butterfly), then
+// exact_backward applies the chain rule.
+__global__ __launch_bounds__(256) void record_grad_exact_kernel(fgs_gaussians g, GeomDev G,
+                                                                const uint32_t *__restrict__ offset,
+                                                                const float4 *__restrict__ partials, uint64_t R,
+                                                                float *__restrict__ grad_rec) {
+  __shared__ float s_sum[256][kExactSums + 1];
+  const int t = threadIdx.x;
+  const int64_t i0 = int64_t(blockIdx.x) * 256;
+  const int v_local = blockIdx.y;
+  const uint64_t rbase = uint64_t(v_local) * uint64_t(g.n);
+  const int li = t % kGradLanes;
+  for (int idx = t / kGradLanes; idx < 256; idx += 256 / kGradLanes) {
+    float acc[kExactSums];
+#pragma unroll
+    for (int c = 0; c < kExactSums; ++c) acc[c] = 0.f;
+    if (i0 + idx < g.n) {
+      const uint64_t r = rbase + uint64_t(i0 + idx);
+      const uint32_t o = offset[r], end = offset[r + 1];
+      for (uint32_t p = o + li; p < end; p += kGradLanes) {
+        const float4 *q = partials + 4 * uint64_t(p);
+        const float4 x0 = q[0], x1 = q[1], x2 = q[2];
+        const float x3 = q[3].x;
+        acc[0] += x0.x; acc[1] += x0.y; acc[2] += x0.z; acc[3] += x0.w;
+        acc[4] += x1.x; acc[5] += x1.y; acc[6] += x1.z; acc[7] += x1.w;
+        acc[8] += x2.x; acc[9] += x2.y; acc[10] += x2.z; acc[11] += x2.w;
+        acc[12] += x3;
+      }
+    }
+#pragma unroll
+    for (int d = 1; d < kGradLanes; d <<= 1)
+#pragma unroll
+      for (int c = 0; c < kExactSums; ++c) acc[c] += __shfl_xor(acc[c], d, kGradLanes);
+    if (li == 0)
+#pragma unroll
+      for (int c = 0; c < kExactSums; ++c) s_sum[idx][c] = acc[c];
+  }
+  __syncthreads();
+  const int64_t i = i0 + t;
+  if (i >= g.n) return;
+  const uint64_t r = rbase + uint64_t(i);
+  float out[11];
+  bool zero = offset[r] == offset[r + 1];
+  ExactSplat X;
+  GaussParams P;
+  ViewFrame F;
+  if (!zero) {
+    load_gauss(g, i, P);
+    make_frame(G, G.view_begin + v_local, F);
+    exact_forward(P, F, G, X);
+    zero = !X.ok;
+  }
+  if (zero) {
+#pragma unroll
+    for (int c = 0; c < 11; ++c) grad_rec[uint64_t(c) * R + r] = 0.f;
+    return;
+  }
+  float sums[kExactSums];
+#pragma unroll
+  for (int c = 0; c < kExactSums; ++c) sums[c] = s_sum[t][c];
+  exact_backward(P, F, G, X, sums, out);
+#pragma unroll
+  for (int c = 0; c < 11; ++c) grad_rec[uint64_t(c) * R + r] = out[c];
+}
+
 // ------------------------------------------------------------------ host
 
 struct RastLayout {
@@ -701,7 +1152,8 @@ struct RastLayout {
   bool sorted_in_alt;
 };
 
-RastLayout rast_layout(uint64_t R, uint64_t T, uint64_t K) {
+// exact: the ray-exact model's 64-byte records and pair slots (else 32).
+RastLayout rast_layout(uint64_t R, uint64_t T, uint64_t K, bool exact) {
   RastLayout L{};
   L.R = R;
   L.T = T;
@@ -712,7 +1164,10 @@ RastLayout rast_layout(uint64_t R, uint64_t T, uint64_t K) {
   c.take<float2>(R, &L.radii);
   c.take<ushort4>(R, &L.rect);
   c.take<uint32_t>(R + 1, &L.offset);
-  c.take<SplatRec>(R, &L.rec);
+  if (exact)
+    c.take<ExactRec>(R, &L.rec);
+  else
+    c.take<SplatRec>(R, &L.rec);
   c.take<uint32_t>(scan_scratch_words(R), &L.scan_scratch);
   c.take<uint32_t>(T + 1, &L.start);
   c.take<float>(11 * R, &L.grad_rec);
@@ -722,7 +1177,7 @@ RastLayout rast_layout(uint64_t R, uint64_t T, uint64_t K) {
   c.take<uint32_t>(K, &L.keys_alt);
   c.take<uint32_t>(K, &L.vals_alt);
   c.take<uint32_t>(sort_scratch_words(K), &L.sort_scratch);
-  c.take<float4>(2 * K, &L.partials);
+  c.take<float4>((exact ? 4 : 2) * K, &L.partials);
   L.total = c.used;
   const int bits = bits_for(T);
   const int passes = (K > 1 && bits > 0) ? (bits + 8) / 9 : 0;
@@ -765,8 +1220,20 @@ int validate(const fgs_gaussians *g, const fgs_geom *geom, int32_t view_begin, i
   if (!(o->kappa > 0.f)) return fail(FGS_E_INVALID, "kappa must be > 0");
   if (o->ablate & ~(FGS_ABLATE_SQUARE_BOX | FGS_ABLATE_QUADRANT_CULL | FGS_ABLATE_PER_PIXEL_BWD))
     return fail(FGS_E_INVALID, "unknown ablate bits");
-  if (o->reserved != 0) return fail(FGS_E_INVALID, "opts.reserved must be 0");
+  if (o->model != FGS_MODEL_SPLAT && o->model != FGS_MODEL_RAY_EXACT) return fail(FGS_E_INVALID, "opts.model");
+  if (o->model == FGS_MODEL_RAY_EXACT && o->ablate)
+    return fail(FGS_E_UNSUPPORTED, "the ablation switches apply to the splat model only");
   return FGS_OK;
+}
+
+// The ray-exact kernels run for the ray-exact model in cone beam; in
+// parallel beam the two models are the same function and the splat kernels run.
+bool use_exact(const fgs_geom *geom, const fgs_opts *o) {
+  return o->model == FGS_MODEL_RAY_EXACT && geom->mode == FGS_CONE;
+}
+
+ExactCam exact_cam(const GeomDev &G) {
+  return ExactCam{G.fu, G.fv, G.cu, G.cv, G.kappa * G.kappa};
 }
 
 GeomDev make_geom_dev(const fgs_geom *geom, const fgs_opts *o, int view_begin, const TileGrid &L) {
@@ -804,7 +1271,8 @@ int build_lists(const fgs_gaussians *g, const fgs_geom *geom, int32_t view_begin
   const TileGrid tg = tile_grid(geom->det_w, geom->det_h);
   const uint64_t T = uint64_t(view_count) * uint64_t(tg.tpv);
   if (T >= 0xffffffffull || R >= 0xffffffffull) return fail(FGS_E_UNSUPPORTED, "too many tiles or records in one call");
-  RastLayout L = rast_layout(R, T, 0);
+  const bool exact = use_exact(geom, o);
+  RastLayout L = rast_layout(R, T, 0, exact);
   ws->kind = 0;
   if (!ws->ptr || ws->bytes < L.fixed_end + (uint64_t(1) << 20)) {
     ws->needed = L.fixed_end + (uint64_t(64) << 20);
@@ -816,9 +1284,14 @@ int build_lists(const fgs_gaussians *g, const fgs_geom *geom, int32_t view_begin
   zero_u64_kernel<<<1, kTotalSlots, 0, s>>>(total64, kTotalSlots);
   FGS_LAUNCH_CHECK("zero_u64_kernel");
   dim3 rgrid(grid_for(uint64_t(g->n), 256), unsigned(view_count));
-  record_kernel<<<rgrid, 256, 0, s>>>(*g, G, at<float2>(b, L.xy), at<SplatRec>(b, L.rec),
-                                      at<float2>(b, L.radii), at<ushort4>(b, L.rect),
-                                      at<uint32_t>(b, L.offset), total64);
+  if (exact)
+    record_kernel<true><<<rgrid, 256, 0, s>>>(*g, G, at<float2>(b, L.xy), at<void>(b, L.rec),
+                                              at<float2>(b, L.radii), at<ushort4>(b, L.rect),
+                                              at<uint32_t>(b, L.offset), total64);
+  else
+    record_kernel<false><<<rgrid, 256, 0, s>>>(*g, G, at<float2>(b, L.xy), at<void>(b, L.rec),
+                                               at<float2>(b, L.radii), at<ushort4>(b, L.rect),
+                                               at<uint32_t>(b, L.offset), total64);
   FGS_LAUNCH_CHECK("record_kernel");
   int st = exclusive_scan_u32(at<uint32_t>(b, L.offset), R, at<uint32_t>(b, L.scan_scratch), s);
   if (st != FGS_OK) return st;
@@ -830,7 +1303,7 @@ int build_lists(const fgs_gaussians *g, const fgs_geom *geom, int32_t view_begin
   if (K64 >= 0xffffffffull)
     return fail(FGS_E_UNSUPPORTED, "more than 2^32 (tile, Gaussian) pairs in one call; split the views");
   const uint64_t K = K64;
-  L = rast_layout(R, T, K);
+  L = rast_layout(R, T, K, exact);
   ws->needed = L.total + extra_bytes;
   ws->n_pairs = K;
   ws->n_records = R;
@@ -839,7 +1312,9 @@ int build_lists(const fgs_gaussians *g, const fgs_geom *geom, int32_t view_begin
   if (K > 0) {
     emit_kernel<<<grid_for(R, kEmitBlock), kEmitBlock, 0, s>>>(R, g->n, tg.tiles_x, tg.tpv, at<ushort4>(b, L.rect),
                                                   at<uint32_t>(b, L.offset), at<uint32_t>(b, L.keys),
-                                                  at<uint32_t>(b, L.vals), at<SplatRec>(b, L.rec));
+                                                  at<uint32_t>(b, L.vals),
+                                                  exact ? &at<ExactRec>(b, L.rec)->d.y : &at<SplatRec>(b, L.rec)->b.z,
+                                                  exact ? 16u : 8u);
     FGS_LAUNCH_CHECK("emit_kernel");
   }
   uint32_t *sk, *sv;
@@ -849,7 +1324,7 @@ int build_lists(const fgs_gaussians *g, const fgs_geom *geom, int32_t view_begin
   if (st != FGS_OK) return st;
   ranges_kernel<<<grid_for(K + 1, 256), 256, 0, s>>>(sk, K, uint32_t(T), at<uint32_t>(b, L.start));
   FGS_LAUNCH_CHECK("ranges_kernel");
-  ws->kind = 1;
+  ws->kind = exact ? 3 : 1;
   *Lout = L;
   return FGS_OK;
 }
@@ -885,14 +1360,25 @@ extern "C" int fgs_project_views_fwd(const fgs_gaussians *g, const fgs_geom *geo
   hipEvent_t *ev = static_cast<hipEvent_t *>(opts->events);
   if (ev) FGS_HIP(hipEventRecord(ev[0], s));
   const uint64_t units = L.T * uint64_t(chunks);
-  with_tiles_per_block(units, [&](auto tpb) {
-    constexpr int TPB = decltype(tpb)::value;
-    splat_fwd_kernel<false, TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
-        at<uint32_t>(b, L.start), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
-        uint32_t(L.T), chunks, thr, thr * kCullSlack, (opts->ablate & FGS_ABLATE_QUADRANT_CULL) ? 1 : 0, part,
-        nullptr);
-  });
-  FGS_LAUNCH_CHECK("splat_fwd_kernel");
+  if (use_exact(geom, opts)) {
+    const ExactCam cam = exact_cam(make_geom_dev(geom, opts, view_begin, tg));
+    with_tiles_per_block(units, [&](auto tpb) {
+      constexpr int TPB = decltype(tpb)::value;
+      splat_fwd_exact_kernel<false, TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
+          at<uint32_t>(b, L.start), sv, at<ExactRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
+          uint32_t(L.T), chunks, thr, thr * kCullSlack, cam, part, nullptr);
+    });
+    FGS_LAUNCH_CHECK("splat_fwd_exact_kernel");
+  } else {
+    with_tiles_per_block(units, [&](auto tpb) {
+      constexpr int TPB = decltype(tpb)::value;
+      splat_fwd_kernel<false, TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
+          at<uint32_t>(b, L.start), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
+          uint32_t(L.T), chunks, thr, thr * kCullSlack, (opts->ablate & FGS_ABLATE_QUADRANT_CULL) ? 1 : 0, part,
+          nullptr);
+    });
+    FGS_LAUNCH_CHECK("splat_fwd_kernel");
+  }
   if (chunks > 1) {
     st = sum_chunks(part, chunks, n_img, img, s);
     if (st != FGS_OK) return st;
@@ -920,6 +1406,17 @@ extern "C" int fgs_project_views_support(const fgs_gaussians *g, const fgs_geom 
   const TileGrid tg = tile_grid(geom->det_w, geom->det_h);
   const int chunks = chunks_per_tile(L.T);
   const uint64_t units = L.T * uint64_t(chunks);
+  if (use_exact(geom, opts)) {
+    const ExactCam cam = exact_cam(make_geom_dev(geom, opts, view_begin, tg));
+    with_tiles_per_block(units, [&](auto tpb) {
+      constexpr int TPB = decltype(tpb)::value;
+      splat_fwd_exact_kernel<true, TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
+          at<uint32_t>(b, L.start), sv, at<ExactRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
+          uint32_t(L.T), chunks, thr, thr * kCullSlack, cam, nullptr, cnt);
+    });
+    FGS_LAUNCH_CHECK("splat_fwd_exact_kernel<count>");
+    return FGS_OK;
+  }
   with_tiles_per_block(units, [&](auto tpb) {
     constexpr int TPB = decltype(tpb)::value;
     splat_fwd_kernel<true, TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
@@ -944,10 +1441,10 @@ extern "C" int fgs_project_views_bwd(const fgs_gaussians *g, const fgs_geom *geo
     st = build_lists(g, geom, view_begin, view_count, opts, ws, s, &L);
     if (st != FGS_OK) return st;
   } else {
-    if (ws->kind != 1 || ws->n_records != R || !ws->ptr)
+    if (ws->kind != (use_exact(geom, opts) ? 3 : 1) || ws->n_records != R || !ws->ptr)
       return fail(FGS_E_INVALID, "workspace does not hold this call's rasterizer lists");
     const uint64_t T = uint64_t(view_count) * uint64_t(tile_grid(geom->det_w, geom->det_h).tpv);
-    L = rast_layout(R, T, ws->n_pairs);
+    L = rast_layout(R, T, ws->n_pairs, use_exact(geom, opts));
     if (T != ws->n_tiles || ws->bytes < L.total)
       return fail(FGS_E_INVALID, "workspace lists do not match this call");
   }
@@ -958,6 +1455,29 @@ extern "C" int fgs_project_views_bwd(const fgs_gaussians *g, const fgs_geom *geo
   const float thr = -0.5f * kLog2e * opts->kappa * opts->kappa;
   hipEvent_t *ev = static_cast<hipEvent_t *>(opts->events);
   if (ev) FGS_HIP(hipEventRecord(ev[0], s));
+  if (use_exact(geom, opts)) {
+    if (L.K > 0) {
+      const int chunks = chunks_per_tile(L.T);
+      const uint64_t units = L.T * uint64_t(chunks);
+      const ExactCam cam = exact_cam(G);
+      with_tiles_per_block(units, [&](auto tpb) {
+        constexpr int TPB = decltype(tpb)::value;
+        splat_bwd_exact_kernel<TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
+            at<uint32_t>(b, L.start), sv, at<ExactRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
+            uint32_t(L.T), chunks, thr, thr * kCullSlack, cam, grad_img, at<float4>(b, L.partials));
+      });
+      FGS_LAUNCH_CHECK("splat_bwd_exact_kernel");
+    }
+    if (ev) FGS_HIP(hipEventRecord(ev[1], s));
+    dim3 rgrid(grid_for(uint64_t(g->n), 256), unsigned(view_count));
+    record_grad_exact_kernel<<<rgrid, 256, 0, s>>>(*g, G, at<uint32_t>(b, L.offset), at<float4>(b, L.partials), R,
+                                                   at<float>(b, L.grad_rec));
+    FGS_LAUNCH_CHECK("record_grad_exact_kernel");
+    view_sum_kernel<<<grid_for(uint64_t(g->n), 256), 256, 0, s>>>(g->n, view_count, at<float>(b, L.grad_rec),
+                                                                  *out, opts->accumulate);
+    FGS_LAUNCH_CHECK("view_sum_kernel");
+    return FGS_OK;
+  }
   float *acc6 = nullptr;
   if (opts->ablate & FGS_ABLATE_PER_PIXEL_BWD) {
     // the records' accumulators take the place of the pair slots
@@ -996,7 +1516,7 @@ extern "C" int fgs_project_views_bwd(const fgs_gaussians *g, const fgs_geom *geo
 
 namespace fgs {
 int rast_binning_layout(const fgs_workspace *ws, uint64_t off[9], uint64_t counts[3]) {
-  RastLayout L = rast_layout(ws->n_records, ws->n_tiles, ws->n_pairs);
+  RastLayout L = rast_layout(ws->n_records, ws->n_tiles, ws->n_pairs, ws->kind == 3);
   off[0] = L.xy;
   off[1] = L.radii;
   off[2] = L.rect;

@@ -610,7 +610,7 @@ int validate(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *o, fg
     if (!(grid->spacing[a] > 0.f)) return fail(FGS_E_INVALID, "grid spacing");
   }
   if (!(o->kappa > 0.f)) return fail(FGS_E_INVALID, "kappa must be > 0");
-  if (o->reserved != 0) return fail(FGS_E_INVALID, "opts.reserved must be 0");
+  if (o->model != 0) return fail(FGS_E_INVALID, "opts.model must be 0 for the voxelizer");
   return FGS_OK;
 }
 

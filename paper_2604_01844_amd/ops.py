@@ -130,10 +130,20 @@ def _grads_like(mean, log_scale, quat, density):
 ABLATE_SQUARE_BOX, ABLATE_QUADRANT_CULL, ABLATE_PER_PIXEL_BWD = 1, 2, 4
 
 
-def _opts(kappa, near, recompute=1, events=None, accumulate=0, ablate=0) -> A.fgs_opts:
+# fgs_opts.model: the splat M of Eq. 4 (the method) or the ray-exact E of Eq. 3
+MODELS = {"splat": A.FGS_MODEL_SPLAT, "exact": A.FGS_MODEL_RAY_EXACT}
+
+
+def _model(model: str) -> int:
+    if model not in MODELS:
+        raise ValueError(f"model must be one of {sorted(MODELS)}")
+    return MODELS[model]
+
+
+def _opts(kappa, near, recompute=1, events=None, accumulate=0, ablate=0, model="splat") -> A.fgs_opts:
     """events: optional pair of started torch.cuda.Event objects to record
     around the call's pixel/voxel kernel."""
-    o = A.fgs_opts(float(kappa), float(near), int(recompute), int(accumulate), int(ablate), 0, None)
+    o = A.fgs_opts(float(kappa), float(near), int(recompute), int(accumulate), int(ablate), _model(model), None)
     if events is not None:
         arr = (ctypes.c_void_p * 2)(events[0].cuda_event, events[1].cuda_event)
         o._events_keepalive = arr
@@ -185,8 +195,9 @@ def _over_views(ws: Workspace, vc: int, views_per_call: int | None, run):
 def project_views(mean, log_scale, quat, density, geom: Geometry, view_begin: int = 0,
                   view_count: int | None = None, *, kappa: float = KAPPA, near: float = NEAR,
                   ws: Workspace | None = None, out: torch.Tensor | None = None, events=None,
-                  views_per_call: int | None = None, ablate: int = 0) -> torch.Tensor:
-    """Rasterize views [view_begin, view_begin + view_count): [V][H][W] float32."""
+                  views_per_call: int | None = None, ablate: int = 0, model: str = "splat") -> torch.Tensor:
+    """Rasterize views [view_begin, view_begin + view_count): [V][H][W] float32.
+    model="exact": the ray-exact line integrals instead of the splat."""
     L = A.lib()
     vc = geom.n_views - view_begin if view_count is None else view_count
     ws = ws or Workspace(mean.device)
@@ -196,7 +207,7 @@ def project_views(mean, log_scale, quat, density, geom: Geometry, view_begin: in
     gm = geom.struct()
 
     def run(b, c, first, chunked, k):
-        o = _opts(kappa, near, events=_chunk_events(events, k), ablate=ablate)
+        o = _opts(kappa, near, events=_chunk_events(events, k), ablate=ablate, model=model)
         ws.call(L.fgs_project_views_fwd, ctypes.byref(g), ctypes.byref(gm), view_begin + b, c, ctypes.byref(o),
                 A.ptr(out[b]))
     _over_views(ws, vc, views_per_call, run)
@@ -206,9 +217,10 @@ def project_views(mean, log_scale, quat, density, geom: Geometry, view_begin: in
 def project_views_backward(mean, log_scale, quat, density, geom: Geometry, grad_img, view_begin: int = 0,
                            view_count: int | None = None, *, kappa: float = KAPPA, near: float = NEAR,
                            recompute: bool = True, ws: Workspace | None = None, out=None, events=None,
-                           views_per_call: int | None = None, ablate: int = 0):
+                           views_per_call: int | None = None, ablate: int = 0, model: str = "splat"):
     """dL/d(mean, log_scale, quat, density) given dL/dimg. Lists left by the
-    forward are reused only when the range ran as one call."""
+    forward are reused only when the range ran as one call (with the same
+    model)."""
     L = A.lib()
     vc = geom.n_views - view_begin if view_count is None else view_count
     ws = ws or Workspace(mean.device)
@@ -220,7 +232,7 @@ def project_views_backward(mean, log_scale, quat, density, geom: Geometry, grad_
 
     def run(b, c, first, chunked, k):
         o = _opts(kappa, near, 1 if (recompute or chunked) else 0, _chunk_events(events, k),
-                  accumulate=0 if first else 1, ablate=ablate)
+                  accumulate=0 if first else 1, ablate=ablate, model=model)
         ws.call(L.fgs_project_views_bwd, ctypes.byref(g), ctypes.byref(gm), view_begin + b, c, ctypes.byref(o),
                 A.ptr(gi[b]), ctypes.byref(gr))
     _over_views(ws, vc, views_per_call, run)
@@ -261,7 +273,7 @@ def voxelize_backward(mean, log_scale, quat, density, grid: Grid, grad_vol, *, k
 
 def project_views_support(mean, log_scale, quat, density, geom: Geometry, view_begin: int = 0,
                           view_count: int | None = None, *, kappa: float = KAPPA, near: float = NEAR,
-                          ws: Workspace | None = None) -> int:
+                          ws: Workspace | None = None, model: str = "splat") -> int:
     """Number of (pixel, Gaussian) pairs in the support (the rasterizer's work)."""
     L = A.lib()
     vc = geom.n_views - view_begin if view_count is None else view_count
@@ -269,7 +281,7 @@ def project_views_support(mean, log_scale, quat, density, geom: Geometry, view_b
     out = torch.zeros(1, dtype=torch.int64, device=mean.device)
     g = _gauss(mean, log_scale, quat, density)
     gm = geom.struct()
-    o = _opts(kappa, near)
+    o = _opts(kappa, near, model=model)
     total = [0]
 
     def run(b, c, first, chunked, k):
@@ -490,19 +502,21 @@ class ProjectViews(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, mean, log_scale, quat, density, geom: Geometry, view_begin: int, view_count: int,
-                kappa: float = KAPPA, ws: Workspace | None = None, recompute: bool = True):
+                kappa: float = KAPPA, ws: Workspace | None = None, recompute: bool = True, model: str = "splat"):
         ws = ws or Workspace(mean.device)
-        img = project_views(mean, log_scale, quat, density, geom, view_begin, view_count, kappa=kappa, ws=ws)
+        img = project_views(mean, log_scale, quat, density, geom, view_begin, view_count, kappa=kappa, ws=ws,
+                            model=model)
         ctx.save_for_backward(mean, log_scale, quat, density)
         ctx.geom, ctx.vb, ctx.vc, ctx.kappa, ctx.ws, ctx.recompute = geom, view_begin, view_count, kappa, ws, recompute
+        ctx.model = model
         return img
 
     @staticmethod
     def backward(ctx, grad_img):
         mean, log_scale, quat, density = ctx.saved_tensors
         g = project_views_backward(mean, log_scale, quat, density, ctx.geom, grad_img.contiguous(), ctx.vb,
-                                   ctx.vc, kappa=ctx.kappa, recompute=ctx.recompute, ws=ctx.ws)
-        return (*g, None, None, None, None, None, None)
+                                   ctx.vc, kappa=ctx.kappa, recompute=ctx.recompute, ws=ctx.ws, model=ctx.model)
+        return (*g, None, None, None, None, None, None, None)
 
 
 class Voxelize(torch.autograd.Function):

@@ -55,11 +55,20 @@ def test_validation_rejects_bad_arguments_without_gpu_work():
     bad = A.fgs_opts(kappa=0.0, near_plane=1e-2, recompute=1)
     assert lib.fgs_project_views_fwd(ctypes.byref(g), ctypes.byref(gm), 0, 1, ctypes.byref(bad), 16,
                                      ctypes.byref(ws), None) == A.FGS_E_INVALID
-    # unknown ablation bits, non-zero reserved field
+    # unknown ablation bits, unknown model, ablation of the ray-exact model
     for bad in (A.fgs_opts(kappa=3.0, near_plane=1e-2, recompute=1, ablate=8),
-                A.fgs_opts(kappa=3.0, near_plane=1e-2, recompute=1, reserved=1)):
+                A.fgs_opts(kappa=3.0, near_plane=1e-2, recompute=1, model=2)):
         assert lib.fgs_project_views_fwd(ctypes.byref(g), ctypes.byref(gm), 0, 1, ctypes.byref(bad), 16,
                                          ctypes.byref(ws), None) == A.FGS_E_INVALID
+    abl = A.fgs_opts(kappa=3.0, near_plane=1e-2, recompute=1, ablate=1, model=A.FGS_MODEL_RAY_EXACT)
+    assert lib.fgs_project_views_fwd(ctypes.byref(g), ctypes.byref(gm), 0, 1, ctypes.byref(abl), 16,
+                                     ctypes.byref(ws), None) == A.FGS_E_UNSUPPORTED
+    # the voxelizer has one model
+    gr1 = A.fgs_grid((ctypes.c_float * 3)(-0.5, -0.5, -0.5), (ctypes.c_float * 3)(0.1, 0.1, 0.1),
+                     (ctypes.c_int32 * 3)(10, 10, 10))
+    vm = A.fgs_opts(kappa=3.0, near_plane=1e-2, recompute=1, model=1)
+    assert lib.fgs_voxelize_fwd(ctypes.byref(g), ctypes.byref(gr1), ctypes.byref(vm), 16, ctypes.byref(ws),
+                                None) == A.FGS_E_INVALID
     # zero Gaussians
     g0 = A.fgs_gaussians(0, 16, 16, 16, 16)
     gr = A.fgs_grid((ctypes.c_float * 3)(-0.5, -0.5, -0.5), (ctypes.c_float * 3)(0.1, 0.1, 0.1),
