@@ -213,6 +213,52 @@ int fgs_project_views_bwd(const fgs_gaussians *g, const fgs_geom *geom, int32_t 
                           fgs_gaussian_grads *out, fgs_workspace *ws, void *stream);
 
 /* ---------------------------------------------------------------------
+ * Adaptive density control (Sec. 3.4: the loss gradient prunes, clones or
+ * splits Gaussians; Suppl. C: the count is capped 10% above the initial one).
+ * ------------------------------------------------------------------- */
+
+/* Per optimiser step: stat[0][i] += |grad_mean_i| (Euclidean norm of
+ * grad_mean[3][n]), stat[1][i] += 1 if that norm is > 0 (device, FP32).
+ * The caller zeroes stat after each densification. Asynchronous. */
+int fgs_adc_accumulate(const float *grad_mean, int64_t n, float *stat, void *stream);
+
+typedef struct {
+  float grad_threshold;  /* densify Gaussians whose mean accumulated |dL/dmean| (stat[0] /
+                            max(stat[1], 1)) is > this */
+  float split_scale;     /* candidates whose largest standard deviation is > this are split,
+                            the others cloned (> 0) */
+  float prune_density;   /* Gaussians with density < this are removed */
+  float prune_scale;     /* and those whose largest standard deviation is > this (> 0) */
+  float split_shrink;    /* children's standard deviations = parent's / split_shrink (> 0) */
+  int32_t reserved;
+  int64_t n_max;         /* cap on the output count */
+} fgs_adc_params;
+
+/* One densification step over n = g->n Gaussians with Adam moments m, v
+ * (same layout) and statistics stat[2][n] (all device).
+ * Each Gaussian is pruned (density < prune_density, or largest standard
+ * deviation > prune_scale, or a NaN in either), kept, or, if not pruned and
+ * its score exceeds grad_threshold, densified: cloned (two copies at half
+ * the density; the copy gets zero moments) or, if its largest standard
+ * deviation exceeds split_scale, split into two children at mean + R diag(s) z
+ * with z from normals[6][n] (device, standard normal variates: rows 0-2 for
+ * the first child, 3-5 for the second), log-scales reduced by
+ * log(split_shrink), density times split_shrink^3 / 2 (the pair keeps the
+ * parent's mass), zero moments. Clone and split both keep the total mass.
+ * If the candidates exceed n_max minus the survivors, those with the largest
+ * score are densified (ties: lower index) and the rest kept.
+ * Output (device, caller-owned, room for n_max Gaussians): the survivors in
+ * input order, each densified one followed by its copy (clone) or with its
+ * two children in its place (split), in [3][n_out] / [4][n_out] / [n_out]
+ * layout with n_out = *n_out (host) the new count. FGS_E_INVALID if the
+ * survivors alone exceed n_max (nothing is written). Waits on the stream once.
+ * Workspace: about 25 bytes per Gaussian (FGS_E_CAPACITY protocol). */
+int fgs_adc_densify(const fgs_gaussians *g, const fgs_gaussian_grads *m, const fgs_gaussian_grads *v,
+                    const float *stat, const float *normals, const fgs_adc_params *p,
+                    fgs_gaussians_out *g_out, fgs_gaussian_grads *m_out, fgs_gaussian_grads *v_out,
+                    int64_t *n_out, fgs_workspace *ws, void *stream);
+
+/* ---------------------------------------------------------------------
  * Voxelizer (Eq. 2, Sec. 3.3). vol[nz][ny][nx] (device, overwritten) =
  * sum_i rho_i exp(-1/2 d_i^2) [d_i^2 <= kappa^2] at each voxel centre.
  * Gaussians are binned into 8x8x8-voxel tiles with the same scan / sort /

@@ -60,6 +60,12 @@ class fgs_workspace(ctypes.Structure):
                 ("n_tiles", ctypes.c_uint64), ("kind", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class fgs_adc_params(ctypes.Structure):
+    _fields_ = [("grad_threshold", ctypes.c_float), ("split_scale", ctypes.c_float),
+                ("prune_density", ctypes.c_float), ("prune_scale", ctypes.c_float),
+                ("split_shrink", ctypes.c_float), ("reserved", ctypes.c_int32), ("n_max", ctypes.c_int64)]
+
+
 class fgs_phantom(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("centre", _vp), ("semi", _vp), ("quat", _vp), ("amp", _vp)]
 
@@ -106,6 +112,10 @@ SIGNATURES = {
     "fgs_gather_patches": [_vp, P(fgs_grid), ctypes.c_float, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_int64,
                            ctypes.c_int32, _vp, _vp, _vp],
     "fgs_reduce_max": [_vp, ctypes.c_int64, _vp, P(fgs_workspace), _vp],
+    "fgs_adc_accumulate": [_vp, ctypes.c_int64, _vp, _vp],
+    "fgs_adc_densify": [P(fgs_gaussians), P(fgs_gaussian_grads), P(fgs_gaussian_grads), _vp, _vp, P(fgs_adc_params),
+                        P(fgs_gaussian_grads), P(fgs_gaussian_grads), P(fgs_gaussian_grads), P(ctypes.c_int64),
+                        P(fgs_workspace), _vp],
     "fgs_copy": [_vp, _vp, ctypes.c_int64, _vp],
     "fgs_tv_loss_grad": [_vp, P(ctypes.c_int32), ctypes.c_float, _vp, _vp, P(fgs_workspace), _vp],
     "fgs_ssim3d_loss_grad": [_vp, _vp, P(ctypes.c_int32), ctypes.c_float, ctypes.c_float, ctypes.c_float, _vp, _vp,

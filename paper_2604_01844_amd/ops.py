@@ -467,6 +467,47 @@ def reduce_max(x, ws: Workspace | None = None, out=None):
     return out
 
 
+# ------------------------------------------------------------------ adaptive density control
+
+def adc_accumulate(grad_mean, stat):
+    """stat[2][n] += (|dL/dmean|, [|dL/dmean| > 0]) per Gaussian (in place)."""
+    n = stat.shape[1]
+    if stat.shape != (2, n) or grad_mean.shape != (3, n) or stat.dtype != torch.float32:
+        raise ValueError("expected grad_mean [3][n] and stat float32 [2][n]")
+    A.check(A.lib().fgs_adc_accumulate(A.ptr(grad_mean.contiguous()), n, A.ptr(stat),
+                                       A.stream_ptr(stat.device)))
+
+
+def adc_densify(params, m, v, stat, normals, *, grad_threshold: float, split_scale: float,
+                prune_density: float, prune_scale: float, split_shrink: float = 1.6, n_max: int,
+                ws: Workspace | None = None):
+    """One densification step (fgs_adc_densify). params, m, v: lists of the
+    four SoA tensors; stat [2][n]; normals float32 [6][n] standard normal
+    variates. Returns (params, m, v) at the new count."""
+    n = params[3].numel()
+    dev = params[3].device
+    if normals.shape != (6, n) or normals.dtype != torch.float32:
+        raise ValueError("normals must be float32 [6][n]")
+    rows = (3, 3, 4, 1)
+    bufs = [[torch.empty(r * n_max, device=dev) for r in rows] for _ in range(3)]
+    outs = [A.fgs_gaussian_grads(*(A.ptr(t) for t in b)) for b in bufs]
+    g = _gauss(*params)
+    gm = A.fgs_gaussian_grads(*(A.ptr(t) for t in m))
+    gv = A.fgs_gaussian_grads(*(A.ptr(t) for t in v))
+    prm = A.fgs_adc_params(float(grad_threshold), float(split_scale), float(prune_density), float(prune_scale),
+                           float(split_shrink), 0, int(n_max))
+    n_out = ctypes.c_int64(0)
+    ws = ws or Workspace(dev)
+    ws.call(A.lib().fgs_adc_densify, ctypes.byref(g), ctypes.byref(gm), ctypes.byref(gv), A.ptr(stat.contiguous()),
+            A.ptr(normals.contiguous()), ctypes.byref(prm), ctypes.byref(outs[0]), ctypes.byref(outs[1]),
+            ctypes.byref(outs[2]), ctypes.byref(n_out))
+    k = int(n_out.value)
+
+    def shaped(b):
+        return [b[0][:3 * k].view(3, k), b[1][:3 * k].view(3, k), b[2][:4 * k].view(4, k), b[3][:k]]
+    return shaped(bufs[0]), shaped(bufs[1]), shaped(bufs[2])
+
+
 # ------------------------------------------------------------------ introspection
 
 def binning_dump(ws: Workspace) -> dict:

@@ -1,0 +1,106 @@
+"""GPU parity of adaptive density control (fgs_adc_accumulate,
+fgs_adc_densify) against the NumPy oracle: the decisions, the capped
+selection and the output order bit-exact (integer work taken on FP32 values
+in FP32 on both sides), the new parameters within FP32 rounding, the carried
+Adam moments exact."""
+import numpy as np
+import pytest
+import torch
+
+import synth_inputs as si
+from oracle import adc as oadc
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+KEYS = ("mean", "log_scale", "quat", "density")
+TH = dict(grad_threshold=0.6, split_scale=0.045, prune_density=0.2, prune_scale=0.07)
+
+
+@pytest.fixture(scope="module")
+def ops():
+    import paper_2604_01844_amd as m
+    m.lib()
+    from paper_2604_01844_amd import ops as o
+    return o
+
+
+def _case(n, seed):
+    gs = si.gaussians(n, seed)
+    stat = np.abs(si.normals((2, n), seed + 1)).astype(np.float32)
+    stat[1] = np.floor(stat[1] * 3.0)                                # visible-step counts 0..
+    m = {k: si.normals(v.shape, seed + 2 + j).astype(np.float32) for j, (k, v) in enumerate(gs.items())}
+    v = {k: np.abs(si.normals(v.shape, seed + 10 + j)).astype(np.float32) for j, (k, v) in enumerate(gs.items())}
+    z = si.normals((6, n), seed + 20).astype(np.float32)
+    return gs, stat, m, v, z
+
+
+def _dev(d):
+    return [torch.from_numpy(np.ascontiguousarray(d[k], dtype=np.float32)).to(DEV) for k in KEYS]
+
+
+def _check(got, ref):
+    for t, k in zip(got, KEYS):
+        a = t.cpu().numpy().astype(np.float64)
+        assert a.shape == ref[k].shape, (k, a.shape, ref[k].shape)
+        np.testing.assert_allclose(a, ref[k], rtol=2e-6, atol=1e-7, err_msg=k)
+
+
+@pytest.mark.parametrize("n_max_factor", [2.0, 1.1, 0.97])
+def test_densify_matches_oracle(ops, n_max_factor):
+    """Room for every candidate, the paper's 10% cap, and a cap below the
+    input count (pruning makes room)."""
+    n = 20000
+    gs, stat, m, v, z = _case(n, 41)
+    n_max = int(n_max_factor * n)
+    rg, rm, rv, code = oadc.densify(gs, m, v, stat, z, **TH, split_shrink=1.6, n_max=n_max)
+    assert np.sum(code == oadc.CLONE) > 100 and np.sum(code == oadc.SPLIT) > 100 and np.sum(code == oadc.PRUNE) > 100
+    params, mo, vo = ops.adc_densify(_dev(gs), _dev(m), _dev(v), torch.from_numpy(stat).to(DEV),
+                                     torch.from_numpy(z).to(DEV), **TH, split_shrink=1.6, n_max=n_max)
+    assert params[3].numel() == rg["density"].shape[0]
+    _check(params, rg)
+    for got, ref in ((mo, rm), (vo, rv)):
+        for t, k in zip(got, KEYS):
+            np.testing.assert_array_equal(t.cpu().numpy().astype(np.float64), ref[k])
+
+
+def test_accumulate_matches_oracle(ops):
+    """Statistics accumulated on the GPU over three steps (some Gaussians
+    unseen in some steps)."""
+    n = 5000
+    stat = torch.zeros((2, n), device=DEV)
+    ref = np.zeros((2, n))
+    for k in range(3):
+        g = si.normals((3, n), 50 + k).astype(np.float32)
+        g[:, k::7] = 0.0
+        ops.adc_accumulate(torch.from_numpy(g).to(DEV), stat)
+        ref = oadc.accumulate(g, ref)
+    np.testing.assert_allclose(stat.cpu().numpy(), ref, rtol=2e-6)
+
+
+def test_densify_twice_in_a_row(ops):
+    """Two densifications in a row, each side on its own previous output
+    (the second with a tighter cap)."""
+    n = 5000
+    gs, stat, m, v, z = _case(n, 42)
+    rg, rm, rv, _ = oadc.densify(gs, m, v, stat, z, **TH, n_max=int(1.1 * n))
+    p1, m1, v1 = ops.adc_densify(_dev(gs), _dev(m), _dev(v), torch.from_numpy(stat).to(DEV),
+                                 torch.from_numpy(z).to(DEV), **TH, n_max=int(1.1 * n))
+    _check(p1, rg)
+    n1 = rg["density"].shape[0]
+    stat2 = np.abs(si.normals((2, n1), 60)).astype(np.float32)
+    z2 = si.normals((6, n1), 61).astype(np.float32)
+    rg2, _, _, _ = oadc.densify(rg, rm, rv, stat2, z2, **TH, n_max=n1 + 50)
+    p2, _, _ = ops.adc_densify(p1, m1, v1, torch.from_numpy(stat2).to(DEV), torch.from_numpy(z2).to(DEV), **TH,
+                               n_max=n1 + 50)
+    assert p2[3].numel() == rg2["density"].shape[0] == n1 + 50
+    _check(p2, rg2)
+
+
+def test_densify_refuses_a_cap_below_the_survivors(ops):
+    from paper_2604_01844_amd import FgsError
+    n = 1000
+    gs, stat, m, v, z = _case(n, 43)
+    with pytest.raises(FgsError):
+        ops.adc_densify(_dev(gs), _dev(m), _dev(v), torch.from_numpy(stat).to(DEV), torch.from_numpy(z).to(DEV),
+                        **TH, n_max=10)
