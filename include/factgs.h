@@ -239,12 +239,13 @@ typedef struct {
  * Each Gaussian is pruned (density < prune_density, or largest standard
  * deviation > prune_scale, or a NaN in either), kept, or, if not pruned and
  * its score exceeds grad_threshold, densified: cloned (two copies at half
- * the density; the copy gets zero moments) or, if its largest standard
- * deviation exceeds split_scale, split into two children at mean + R diag(s) z
- * with z from normals[6][n] (device, standard normal variates: rows 0-2 for
- * the first child, 3-5 for the second), log-scales reduced by
- * log(split_shrink), density times split_shrink^3 / 2 (the pair keeps the
- * parent's mass), zero moments. Clone and split both keep the total mass.
+ * the density) or, if its largest standard deviation exceeds split_scale,
+ * split into two children at mean + R diag(s) z with z from normals[6][n]
+ * (device, standard normal variates: rows 0-2 for the first child, 3-5 for
+ * the second), log-scales reduced by log(split_shrink), density times
+ * split_shrink^3 / 2 (the pair keeps the parent's mass). Clone and split
+ * both keep the total mass; every output Gaussian carries its source's
+ * Adam moments.
  * If the candidates exceed n_max minus the survivors, those with the largest
  * score are densified (ties: lower index) and the rest kept.
  * Output (device, caller-owned, room for n_max Gaussians): the survivors in

@@ -22,8 +22,10 @@ gives no criteria or thresholds; the readings written out here:
 * when the candidates do not fit under the cap, the largest scores are
   densified (ties: lower index), the rest kept;
 * output order: survivors in input order, a clone's copy right after it, a
-  split parent replaced by its two children; Adam moments carried over for
-  kept Gaussians and a clone's original, zero for new ones.
+  split parent replaced by its two children; every output Gaussian carries
+  its source's Adam moments (fresh zero moments late in a run make Adam's
+  first updates of the new Gaussians several times the learning rate, since
+  the bias correction follows the global step count).
 
 Decisions are comparisons of FP32 values in FP32 (the score by correctly
 rounded FP32 division, sizes in the log domain), as the GPU takes them.
@@ -101,8 +103,8 @@ def densify(gs: dict, m: dict, v: dict, stat, normals, *, grad_threshold, split_
         for k, val in zip(keys, (mean, ls, q, rho)):
             cols[k].append(val)
         for k in keys:
-            mcols[k].append(Mi[k][..., mom_of] if mom_of is not None else np.zeros_like(Mi[k][..., 0]))
-            vcols[k].append(Vi[k][..., mom_of] if mom_of is not None else np.zeros_like(Vi[k][..., 0]))
+            mcols[k].append(Mi[k][..., mom_of])
+            vcols[k].append(Vi[k][..., mom_of])
 
     for i in range(n):
         c = code[i]
@@ -113,12 +115,12 @@ def densify(gs: dict, m: dict, v: dict, stat, normals, *, grad_threshold, split_
             put(mean, ls, q, rho, i)
         elif c == CLONE:
             put(mean, ls, q, 0.5 * rho, i)
-            put(mean, ls, q, 0.5 * rho, None)
+            put(mean, ls, q, 0.5 * rho, i)
         else:
             s = np.exp(ls)
             for child in range(2):
                 put(mean + R[:, :, i] @ (s * z[3 * child:3 * child + 3, i]), ls - math.log(split_shrink), q,
-                    rho * split_shrink ** 3 / 2.0, None)
+                    rho * split_shrink ** 3 / 2.0, i)
 
     def pack(c):
         out = {}

@@ -110,28 +110,30 @@ __device__ __forceinline__ void adc_put(const AdcOut &o, int64_t q, const float 
   o.g.density[q] = rho;
 }
 
-__device__ __forceinline__ void adc_moments(const AdcOut &o, int64_t q, const fgs_gaussian_grads *m,
-                                            const fgs_gaussian_grads *v, int64_t n_in, int64_t i) {
+__device__ __forceinline__ void adc_moments(const AdcOut &o, int64_t q, const fgs_gaussian_grads &m,
+                                            const fgs_gaussian_grads &v, int64_t n_in, int64_t i) {
   const int64_t n = o.n;
   for (int a = 0; a < 3; ++a) {
-    o.m.mean[a * n + q] = m ? m->mean[a * n_in + i] : 0.f;
-    o.v.mean[a * n + q] = v ? v->mean[a * n_in + i] : 0.f;
-    o.m.log_scale[a * n + q] = m ? m->log_scale[a * n_in + i] : 0.f;
-    o.v.log_scale[a * n + q] = v ? v->log_scale[a * n_in + i] : 0.f;
+    o.m.mean[a * n + q] = m.mean[a * n_in + i];
+    o.v.mean[a * n + q] = v.mean[a * n_in + i];
+    o.m.log_scale[a * n + q] = m.log_scale[a * n_in + i];
+    o.v.log_scale[a * n + q] = v.log_scale[a * n_in + i];
   }
   for (int a = 0; a < 4; ++a) {
-    o.m.quat[a * n + q] = m ? m->quat[a * n_in + i] : 0.f;
-    o.v.quat[a * n + q] = v ? v->quat[a * n_in + i] : 0.f;
+    o.m.quat[a * n + q] = m.quat[a * n_in + i];
+    o.v.quat[a * n + q] = v.quat[a * n_in + i];
   }
-  o.m.density[q] = m ? m->density[i] : 0.f;
-  o.v.density[q] = v ? v->density[i] : 0.f;
+  o.m.density[q] = m.density[i];
+  o.v.density[q] = v.density[i];
 }
 
-// Kept: copied with its moments. Clone: the original (with its moments) and
-// a copy (zero moments), both at half density. Split: two children at
-// mean + R diag(s) z (z the given standard normals), standard deviations
-// divided by the shrink factor, density scaled so the pair carries the
-// parent's mass, zero moments.
+// Kept: copied with its moments. Clone: the original and a copy, both at
+// half density. Split: two children at mean + R diag(s) z (z the given
+// standard normals), standard deviations divided by the shrink factor,
+// density scaled so the pair carries the parent's mass. New Gaussians take
+// their parent's Adam moments: with fresh (zero) moments late in a run, the
+// step-count bias correction no longer compensates and their first few
+// hundred updates would be several times the learning rate.
 __global__ __launch_bounds__(256) void adc_emit_kernel(fgs_gaussians g, fgs_gaussian_grads m, fgs_gaussian_grads v,
                                                        const uint32_t *__restrict__ code,
                                                        const uint32_t *__restrict__ pos,
@@ -152,14 +154,14 @@ __global__ __launch_bounds__(256) void adc_emit_kernel(fgs_gaussians g, fgs_gaus
   const float rho = g.density[i];
   if (c == kKeep) {
     adc_put(o, q, mean, ls, qt, rho);
-    adc_moments(o, q, &m, &v, n, i);
+    adc_moments(o, q, m, v, n, i);
     return;
   }
   if (c == kClone) {
     adc_put(o, q, mean, ls, qt, 0.5f * rho);
-    adc_moments(o, q, &m, &v, n, i);
+    adc_moments(o, q, m, v, n, i);
     adc_put(o, q + 1, mean, ls, qt, 0.5f * rho);
-    adc_moments(o, q + 1, nullptr, nullptr, n, i);
+    adc_moments(o, q + 1, m, v, n, i);
     return;
   }
   GaussParams P;
@@ -171,7 +173,7 @@ __global__ __launch_bounds__(256) void adc_emit_kernel(fgs_gaussians g, fgs_gaus
     for (int j = 0; j < 3; ++j) z[j] = normals[(3 * child + j) * n + i] * P.s[j];
     for (int a = 0; a < 3; ++a) cm[a] = mean[a] + P.R[3 * a] * z[0] + P.R[3 * a + 1] * z[1] + P.R[3 * a + 2] * z[2];
     adc_put(o, q + child, cm, cls, qt, split_rho * rho);
-    adc_moments(o, q + child, nullptr, nullptr, n, i);
+    adc_moments(o, q + child, m, v, n, i);
   }
 }
 

@@ -58,6 +58,23 @@ class AdamConfig:
 FIT_ADAM = AdamConfig(lr_mean=1e-3, lr_log_scale=2e-2, lr_quat=5e-3, lr_density=2e-2)
 
 
+@dataclass
+class ADCConfig:
+    """Adaptive density control during reconstruction (Sec. 3.4; the count is
+    capped at `cap` times the initial one, Suppl. C). The paper gives no
+    schedule or thresholds; these are this library's choices."""
+    every: int = 75              # optimiser steps between densifications
+    start: int = 150             # no densification before this step
+    stop: int = 3750             # nor after this one
+    grad_threshold: float = 2e-4 # mean |dL/dmean| over the steps a Gaussian was seen
+    split_scale: float = 0.02    # largest standard deviation above which candidates split
+    prune_density: float = 1e-3
+    prune_scale: float = 0.25
+    split_shrink: float = 1.6
+    cap: float = 1.1
+    seed: int = 0
+
+
 class GaussianModel:
     """Gaussian parameters (float32 SoA on the GPU) with their Adam state."""
 
@@ -72,6 +89,13 @@ class GaussianModel:
     @property
     def n(self) -> int:
         return self.params[3].numel()
+
+    def replace(self, params, m, v):
+        """Take new parameters and moments (e.g. after densification); the
+        step count is kept, gradient buffers follow the new size."""
+        self.params, self.m, self.v = list(params), list(m), list(v)
+        self.grads = [torch.empty_like(p) for p in self.params]
+        self.grads2 = [torch.empty_like(p) for p in self.params]
 
     def adam(self, cfg: AdamConfig, second: bool = False):
         """One Adam step with the gradient in `grads` (+ `grads2`)."""
@@ -159,7 +183,7 @@ def reconstruct(model: GaussianModel, proj_gt, geom: ops.Geometry, *, epochs: in
                 vol_gt=None, eval_grid: ops.Grid | None = None, eval_every: int = 1,
                 target_psnr: float | None = None, seed: int = 0, clock_start: float | None = None,
                 t_offset: float = 0.0, eval_at_start: bool = False, tv: CropTV | None = None,
-                ssim_weight: float = 0.0) -> History:
+                ssim_weight: float = 0.0, adc: ADCConfig | None = None) -> History:
     """Optimise `model` against projections proj_gt[V][H][W] (GPU), one view
     per step. If vol_gt/eval_grid are given, PSNR is evaluated every
     `eval_every` epochs (and before the first step with eval_at_start),
@@ -186,6 +210,7 @@ def reconstruct(model: GaussianModel, proj_gt, geom: ops.Geometry, *, epochs: in
             return hist
         torch.cuda.synchronize()
     t0 = time.perf_counter() if clock_start is None else clock_start
+    dens = _Densifier(model, adc, dev) if adc is not None else None
     for ep in range(1, epochs + 1):
         loss_sum = 0.0
         for v in rng.permutation(V):
@@ -197,7 +222,11 @@ def reconstruct(model: GaussianModel, proj_gt, geom: ops.Geometry, *, epochs: in
                                        out=model.grads)
             if tv is not None:
                 tv.add_grad(model.params, model.grads, rng)
+            if dens is not None:
+                dens.observe()
             model.adam(adam)
+            if dens is not None:
+                dens.maybe_densify()
         if vol_gt is not None and (ep % eval_every == 0 or ep == epochs):
             torch.cuda.synchronize()
             t_run += time.perf_counter() - t0
@@ -212,6 +241,37 @@ def reconstruct(model: GaussianModel, proj_gt, geom: ops.Geometry, *, epochs: in
             torch.cuda.synchronize()
             t0 = time.perf_counter()
     return hist
+
+
+class _Densifier:
+    """Gradient statistics and the densification schedule of ADCConfig."""
+
+    def __init__(self, model: GaussianModel, cfg: ADCConfig, dev):
+        self.model, self.cfg, self.dev = model, cfg, dev
+        self.n_max = int(cfg.cap * model.n)
+        self.stat = torch.zeros((2, model.n), device=dev)
+        self.rng = np.random.Generator(np.random.PCG64(cfg.seed))
+        self.ws = ops.Workspace(dev)
+        self.steps = 0
+        self.counts = []
+
+    def observe(self):
+        ops.adc_accumulate(self.model.grads[0], self.stat)
+
+    def maybe_densify(self):
+        self.steps += 1
+        c = self.cfg
+        if self.steps < c.start or self.steps > c.stop or self.steps % c.every:
+            return
+        m = self.model
+        z = torch.from_numpy(self.rng.standard_normal((6, m.n), dtype=np.float32)).to(self.dev)
+        p, mo, vo = ops.adc_densify(m.params, m.m, m.v, self.stat, z, grad_threshold=c.grad_threshold,
+                                    split_scale=c.split_scale, prune_density=c.prune_density,
+                                    prune_scale=c.prune_scale, split_shrink=c.split_shrink, n_max=self.n_max,
+                                    ws=self.ws)
+        m.replace(p, mo, vo)
+        self.stat = torch.zeros((2, m.n), device=self.dev)
+        self.counts.append(m.n)
 
 
 def fit_volume(model: GaussianModel, vol_gt, grid: ops.Grid, *, iters: int, adam: AdamConfig,

@@ -104,3 +104,41 @@ def test_densify_refuses_a_cap_below_the_survivors(ops):
     with pytest.raises(FgsError):
         ops.adc_densify(_dev(gs), _dev(m), _dev(v), torch.from_numpy(stat).to(DEV), torch.from_numpy(z).to(DEV),
                         **TH, n_max=10)
+
+
+def test_clone_leaves_the_field_unchanged_and_split_keeps_the_mass(ops):
+    """Cloning halves two copies of the same Gaussian: the voxelized field
+    must not change. Splitting moves mass but keeps its total."""
+    n = 3000
+    gs, stat, m, v, z = _case(n, 44)
+    grid = ops.Grid.from_dict(si.grid(64))
+    before = ops.voxelize(*_dev(gs), grid)
+    th = dict(TH, split_scale=10.0, prune_density=0.0, prune_scale=10.0)
+    p, _, _ = ops.adc_densify(_dev(gs), _dev(m), _dev(v), torch.from_numpy(stat).to(DEV),
+                              torch.from_numpy(z).to(DEV), **th, n_max=2 * n)
+    assert p[3].numel() > n + 100
+    after = ops.voxelize(*p, grid)
+    rel = float((after - before).norm() / before.norm())
+    assert rel < 1e-6, rel
+    th = dict(TH, split_scale=1e-6, prune_density=0.0, prune_scale=10.0)
+    p, _, _ = ops.adc_densify(_dev(gs), _dev(m), _dev(v), torch.from_numpy(stat).to(DEV),
+                              torch.from_numpy(z).to(DEV), **th, n_max=2 * n)
+    got = {k: t.cpu().numpy() for k, t in zip(KEYS, p)}
+    assert abs(oadc.mass(got) / oadc.mass(gs) - 1.0) < 1e-5
+
+
+def test_reconstruction_with_density_control(ops):
+    """The reconstruction loop with densification every epoch: the count
+    grows to the 10% cap and never beyond, and the PSNR still rises."""
+    from paper_2604_01844_amd import recon, learned_init as L
+    sc = L.Scanner(L.ScanConfig(n_gauss=20000), torch.device(DEV))
+    ph = sc.phantom(2004)
+    proj = sc.project(ph)
+    vol_gt = ops.phantom_voxelize(ph, sc.eval_grid)
+    vfdk, _ = sc.fdk(proj)
+    model = L.fdk_gradient_model(sc, vfdk, sc.uniforms(2004))
+    adc = recon.ADCConfig(every=75, start=75, grad_threshold=1e-6, prune_density=0.0)
+    hist = recon.reconstruct(model, proj, sc.geom, epochs=6, adam=recon.AdamConfig(lr_density=2e-3), vol_gt=vol_gt,
+                             eval_grid=sc.eval_grid, eval_every=6, eval_at_start=True, adc=adc)
+    assert model.n == 22000
+    assert hist.psnr[-1] > hist.psnr[0] + 5.0, hist.psnr

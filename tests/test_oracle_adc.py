@@ -39,9 +39,9 @@ def test_hand_case_decisions_order_and_values():
     np.testing.assert_allclose(out["mean"][:, 4], gs["mean"][:, 3] - [0.10, 0, 0], atol=1e-15)
     np.testing.assert_allclose(np.exp(out["log_scale"][:, 3]), [0.05, 0.02, 0.02])
     np.testing.assert_allclose(out["mean"][:, [0, 1, 2, 5]], gs["mean"][:, [0, 2, 2, 5]])
-    # moments: kept and the clone's original carry theirs, new ones start at zero
-    assert mo["density"].tolist() == [100.3, 100.4, 0.0, 0.0, 0.0, 100.2]
-    assert vo["density"].tolist() == [200.3, 200.4, 0.0, 0.0, 0.0, 200.2]
+    # moments: every output Gaussian carries its source's
+    assert mo["density"].tolist() == [100.3, 100.4, 100.4, 100.8, 100.8, 100.2]
+    assert vo["density"].tolist() == [200.3, 200.4, 200.4, 200.8, 200.8, 200.2]
 
 
 def test_cap_keeps_the_largest_scores_ties_by_index():
