@@ -237,6 +237,26 @@ def test_projection_backward_matches_oracle(fgs, mode):
     assert max(errs.values()) < TOL, errs
 
 
+def test_large_gaussians_take_the_interior_path(fgs):
+    """Gaussians spanning many tiles (here over 48 tiles per record, where
+    the pixel kernels skip the cutoff test for all-interior quadrants):
+    every pixel, and the gradients, against the oracle."""
+    gs = si.gaussians(300, 21, log_scale_mean=math.log(0.15))
+    gd = si.geometry(256)
+    ang = si.angles(3)
+    geom = fgs.Geometry.from_dict(gd, ang)
+    t = dev(gs)
+    ws = fgs.Workspace(DEV)
+    img = fgs.project_views(*args(t), geom, ws=ws).cpu().numpy()
+    assert ws.n_pairs >= 48 * 3 * 300, ws.n_pairs
+    assert rel(img, oracle.project(gs, gd, ang)) < TOL
+    c = si.normals((3, 256, 256), 22)
+    g = fgs.project_views_backward(*args(t), geom, torch.from_numpy(c).to(DEV))
+    ref = oracle.project_bwd(gs, gd, ang, c.astype(np.float64), band=BAND)
+    errs = grads_rel(g, ref)
+    assert max(errs.values()) < TOL, errs
+
+
 def test_backward_stored_lists_equal_recomputed(fgs):
     a, _ = _proj_grad_case(fgs, 1500, 12, 64, 4, recompute=True)
     b, _ = _proj_grad_case(fgs, 1500, 12, 64, 4, recompute=False)
