@@ -367,6 +367,37 @@ __device__ __forceinline__ void build_quad_lists_split(uint32_t mask, uint32_t i
   }
 }
 
+// Software pipelining of a tile's record batches: while a batch is being
+// evaluated, the next batch's records and the record indices of the one
+// after are already in flight, so the two dependent loads (index, then
+// record) of a batch overlap the previous batch's arithmetic instead of
+// stalling the wave. Lane l holds entry l of its batches. The forward uses
+// it (3% faster on 512^2 views); in the backward the eight extra registers
+// spill under its 64-register budget and it got slower.
+template <typename Rec>
+struct BatchPrefetch {
+  Rec cur, nxt;
+  uint32_t idx;  // record index of this lane's entry two batches ahead
+  __device__ __forceinline__ static uint32_t count(uint32_t b, uint32_t e) {
+    return b < e ? min(uint32_t(kWave), e - b) : 0u;
+  }
+  // before the loop: records of batch b, indices of batch b + stride
+  __device__ __forceinline__ void start(const uint32_t *__restrict__ svals, const Rec *__restrict__ rec, uint32_t b,
+                                        uint32_t stride, uint32_t e, int lane) {
+    if (uint32_t(lane) < count(b, e)) nxt = rec[svals[b + lane]];
+    if (uint32_t(lane) < count(b + stride, e)) idx = svals[b + stride + lane];
+  }
+  // at the top of the iteration for batch b: cur = batch b's record; issue
+  // the loads of batch b + stride (records) and b + 2 stride (indices)
+  __device__ __forceinline__ void advance(const uint32_t *__restrict__ svals, const Rec *__restrict__ rec,
+                                          uint32_t b, uint32_t stride, uint32_t e, int lane) {
+    cur = nxt;
+    const uint32_t b1 = b + stride, b2 = b1 + stride;
+    if (uint32_t(lane) < count(b1, e)) nxt = rec[idx];
+    if (b1 < e && uint32_t(lane) < count(b2, e)) idx = svals[b2 + lane];
+  }
+};
+
 // Slot kWave of the LDS record arrays holds a record that contributes nothing
 // anywhere (zero weight, support far outside every tile).
 __device__ __forceinline__ void set_null_record(float4 *s_cw, float2 *s_xy) {
@@ -416,13 +447,16 @@ __global__ __launch_bounds__(kWave * TPB) void splat_fwd_kernel(const uint32_t *
 #pragma unroll
   for (int k = 0; k < kRows; ++k) acc[k] = 0.f;
   const uint32_t b0 = start[tile], e = start[tile + 1];
-  for (uint32_t b = b0 + chunk * kWave; b < e; b += kWave * uint32_t(n_chunks)) {
+  const uint32_t stride = kWave * uint32_t(n_chunks);
+  BatchPrefetch<SplatRec> pf;
+  pf.start(svals, rec, b0 + chunk * kWave, stride, e, lane);
+  for (uint32_t b = b0 + chunk * kWave; b < e; b += stride) {
     const uint32_t m = min(uint32_t(kWave), e - b);
+    pf.advance(svals, rec, b, stride, e, lane);
     uint32_t mask = 0, imask = 0;
     if (uint32_t(lane) < m) {
-      const uint32_t r = svals[b + lane];
-      const float4 ra = rec[r].a;
-      const float2 rb = *reinterpret_cast<const float2 *>(&rec[r].b);
+      const float4 ra = pf.cur.a;
+      const float2 rb = make_float2(pf.cur.b.x, pf.cur.b.y);
       const float4 c = make_float4(ra.z, ra.w, rb.x, rb.y);
       const float2 q = make_float2(ra.x, ra.y);
       s_cw[lane] = c;
