@@ -169,7 +169,7 @@ typedef struct {
   uint64_t n_tiles;      /* out: tiles of the last binning */
   int32_t kind;          /* out: 0 none, 1 rasterizer lists (splat model), 2 voxelizer lists,
                             3 rasterizer lists (ray-exact model) */
-  int32_t reserved;
+  int32_t tile_bits;     /* out: rasterizer: width of the tile field of its keys */
 } fgs_workspace;
 
 /* Additive ellipsoid phantom: sum_e amp_e * [x inside ellipsoid e]. Used to
@@ -500,10 +500,14 @@ int fgs_reduce_max(const float *x, int64_t n, float *out, fgs_workspace *ws, voi
  *          voxelizer: 8 x uint16: x0, y0, z0, x1, y1, z1, 0, 0),
  *   off[3] exclusive offsets (uint32, records + 1),
  *   off[4] emitted keys (uint32, pairs), off[5] emitted values (uint32),
- *   off[6] sorted keys, off[7] sorted values, off[8] tile starts (uint32,
- *   tiles + 1).
+ *   off[6] sorted keys, off[7] sorted values, off[8] rasterizer: per tile
+ *   (local_view * tiles_per_view + tile) its [begin, end) in the sorted
+ *   arrays (2 x uint32, tiles); voxelizer: tile starts (uint32, tiles + 1).
  * counts[0] = records, counts[1] = pairs, counts[2] = tiles.
- * Records are r = local_view * n + i (voxelizer: r = i).
+ * Records are r = local_view * n + i (voxelizer: r = i). Rasterizer keys are
+ * local_view << ws->tile_bits | tile, sorted by tile and then view (each
+ * key's pairs contiguous, in ascending record order); voxelizer keys are the
+ * tile index, sorted ascending.
  * ------------------------------------------------------------------- */
 int fgs_binning_layout(const fgs_workspace *ws, uint64_t off[9], uint64_t counts[3]);
 

@@ -57,7 +57,7 @@ class fgs_opts(ctypes.Structure):
 class fgs_workspace(ctypes.Structure):
     _fields_ = [("ptr", _vp), ("bytes", ctypes.c_uint64), ("needed", ctypes.c_uint64),
                 ("n_pairs", ctypes.c_uint64), ("n_records", ctypes.c_uint64),
-                ("n_tiles", ctypes.c_uint64), ("kind", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("n_tiles", ctypes.c_uint64), ("kind", ctypes.c_int32), ("tile_bits", ctypes.c_int32)]
 
 
 class fgs_adc_params(ctypes.Structure):

@@ -107,6 +107,15 @@ uint64_t scan_scratch_words(uint64_t n);
 int exclusive_scan_u32(uint32_t *data, uint64_t n, uint32_t *scratch, hipStream_t s);
 int exclusive_scan_u64(uint64_t *data, uint64_t n, uint32_t *scratch, hipStream_t s);
 
+// Widest digit of one radix-sort pass (1024 bins).
+constexpr int kSortMaxBits = 10;
+
+// Passes radix_sort_pairs makes over n pairs sorted on `bits` bits; the
+// result ends in the alternate buffers when this is odd.
+inline int sort_passes(uint64_t n, int bits) {
+  return (n > 1 && bits > 0) ? (bits + kSortMaxBits - 1) / kSortMaxBits : 0;
+}
+
 // Stable LSD radix sort of (key, value) uint32 pairs on the low `bits` bits
 // of the key. Input in keys/vals; the sorted result ends in the buffers
 // returned through out_keys/out_vals (either the inputs or the alternates).

@@ -6,11 +6,17 @@
 //                         32-byte line with the pair-slot addressing, support
 //                         half-extents, axis-aligned tile rectangle, count.
 //   2. exclusive scan     counts -> key offsets (one readback of the total).
-//   3. emit kernel        keys (view * tiles_per_view + tile) and values
+//   3. emit kernel        keys (view << tile_bits | tile) and values
 //                         (record index), row-major inside each rectangle;
-//                         completes the record's slot base.
-//   4. radix sort         stable; no depth key (the sum is order-free).
-//   5. ranges kernel      per-tile [start, end) by boundary detection.
+//                         completes the record's slot base. Records are
+//                         view-major, so the emitted keys already ascend in
+//                         the view field.
+//   4. radix sort         stable, over the tile field only (one pass for up
+//                         to 1024 tiles per view): with the input already in
+//                         view order this orders the pairs by (tile, view),
+//                         each tile's list in ascending Gaussian index; no
+//                         depth key (the sum is order-free).
+//   5. ranges kernel      per-(view, tile) [start, end) by boundary detection.
 //   6. splat kernel       one 64-lane wave per 16x16 tile, up to 16 tiles
 //                         per workgroup; batches of 64 records staged in LDS;
 //                         each record is tested against the tile's four 8x8
@@ -205,7 +211,7 @@ __global__ __launch_bounds__(256) void record_kernel(fgs_gaussians g, GeomDev G,
     atomicAdd(total64 + ((blockIdx.x * 4 + (threadIdx.x >> 6) + blockIdx.y * 7) & (kTotalSlots - 1)), w);
 }
 
-__global__ __launch_bounds__(kEmitBlock) void emit_kernel(uint64_t R, int64_t n, int tiles_x, int tpv,
+__global__ __launch_bounds__(kEmitBlock) void emit_kernel(uint64_t R, int64_t n, int tiles_x, int tile_bits,
                                                           const ushort4 *__restrict__ rect,
                                                           const uint32_t *__restrict__ offset,
                                                           uint32_t *__restrict__ keys,
@@ -237,20 +243,28 @@ __global__ __launch_bounds__(kEmitBlock) void emit_kernel(uint64_t R, int64_t n,
     const uint32_t j = q - s_off[i];
     const uint32_t dy = j / wdt;
     const uint64_t r = r0 + i;
-    const uint32_t base = uint32_t(r / uint64_t(n)) * uint32_t(tpv);
-    keys[q] = base + (uint32_t(rc.y) + dy) * uint32_t(tiles_x) + uint32_t(rc.x) + (j - dy * wdt);
+    const uint32_t base = uint32_t(r / uint64_t(n)) << tile_bits;
+    keys[q] = base | ((uint32_t(rc.y) + dy) * uint32_t(tiles_x) + uint32_t(rc.x) + (j - dy * wdt));
     vals[q] = uint32_t(r);
   }
 }
 
-// start[t] = first sorted position whose key is >= t, for t in [0, T].
-__global__ __launch_bounds__(256) void ranges_kernel(const uint32_t *__restrict__ skeys, uint64_t K,
-                                                     uint32_t T, uint32_t *__restrict__ start) {
+__global__ __launch_bounds__(256) void zero_ranges_kernel(uint2 *__restrict__ rng, uint64_t T) {
+  const uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t < T) rng[t] = make_uint2(0u, 0u);
+}
+
+// rng[v * tpv + t] = [first, last + 1) of key (v << tile_bits | t) in the
+// sorted keys; each key's pairs are contiguous there (tiles without pairs
+// keep the empty range the zero kernel wrote).
+__global__ __launch_bounds__(256) void ranges_kernel(const uint32_t *__restrict__ skeys, uint64_t K, int tile_bits,
+                                                     uint32_t tpv, uint2 *__restrict__ rng) {
   const uint64_t k = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (k > K) return;
-  const int64_t prev = (k == 0) ? -1 : int64_t(skeys[k - 1]);
-  const int64_t cur = (k == K) ? int64_t(T) : int64_t(skeys[k]);
-  for (int64_t t = prev + 1; t <= cur; ++t) start[t] = uint32_t(k);
+  if (k >= K) return;
+  const uint32_t key = skeys[k];
+  const uint32_t tile = (key >> tile_bits) * tpv + (key & ((1u << tile_bits) - 1u));
+  if (k == 0 || skeys[k - 1] != key) rng[tile].x = uint32_t(k);
+  if (k + 1 == K || skeys[k + 1] != key) rng[tile].y = uint32_t(k + 1);
 }
 
 // ---------------------------------------------------------------- quadrants
@@ -408,7 +422,7 @@ __device__ __forceinline__ void set_null_record(float4 *s_cw, float2 *s_xy) {
 // kCount = true: instead of the image, count the (pixel, Gaussian) pairs in
 // the support whose pixel lies on the detector (the algorithmic work).
 template <bool kCount, bool kInterior, int TPB>
-__global__ __launch_bounds__(kWave * TPB) void splat_fwd_kernel(const uint32_t *__restrict__ start,
+__global__ __launch_bounds__(kWave * TPB) void splat_fwd_kernel(const uint2 *__restrict__ rng,
                                                            const uint32_t *__restrict__ svals,
                                                            const SplatRec *__restrict__ rec,
                                                            int tiles_x, int tpv, int W, int H,
@@ -446,7 +460,7 @@ __global__ __launch_bounds__(kWave * TPB) void splat_fwd_kernel(const uint32_t *
   float acc[kRows];
 #pragma unroll
   for (int k = 0; k < kRows; ++k) acc[k] = 0.f;
-  const uint32_t b0 = start[tile], e = start[tile + 1];
+  const uint32_t b0 = rng[tile].x, e = rng[tile].y;
   const uint32_t stride = kWave * uint32_t(n_chunks);
   BatchPrefetch<SplatRec> pf;
   pf.start(svals, rec, b0 + chunk * kWave, stride, e, lane);
@@ -558,7 +572,7 @@ __device__ __forceinline__ float bperm(int src_lane, float v) {
 // summation order is fixed.
 template <int TPB>
 __global__ __launch_bounds__(kWave * TPB) __attribute__((amdgpu_waves_per_eu(8, 8))) void splat_bwd_kernel(
-    const uint32_t *__restrict__ start, const uint32_t *__restrict__ svals,
+    const uint2 *__restrict__ rng, const uint32_t *__restrict__ svals,
     const SplatRec *__restrict__ rec, int tiles_x, int tpv, int W, int H, uint32_t n_tiles, int n_chunks,
     float thr, float thr_cull, int no_cull, const float *__restrict__ gimg, float4 *__restrict__ partials) {
   __shared__ float4 s_g4_all[TPB][kTS * kTS / 4];
@@ -592,7 +606,7 @@ __global__ __launch_bounds__(kWave * TPB) __attribute__((amdgpu_waves_per_eu(8, 
   wave_lds_sync();
   const float tx0 = float(tx * kTS) + 0.5f, ty0 = float(ty * kTS) + 0.5f;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const uint32_t b0 = start[tile], e = start[tile + 1];
+  const uint32_t b0 = rng[tile].x, e = rng[tile].y;
   for (uint32_t b = b0 + chunk * kWave; b < e; b += kWave * uint32_t(n_chunks)) {
     const uint32_t m = min(uint32_t(kWave), e - b);
     uint32_t mask = 0, slot = 0;
@@ -707,7 +721,7 @@ __global__ __launch_bounds__(kWave * TPB) __attribute__((amdgpu_waves_per_eu(8, 
 // the wave sums them (butterfly) and one lane adds them to the record's
 // accumulator acc6[r][6] with float atomics. Not deterministic.
 __global__ __launch_bounds__(kWave) void splat_bwd_pixel_kernel(
-    const uint32_t *__restrict__ start, const uint32_t *__restrict__ svals, const SplatRec *__restrict__ rec,
+    const uint2 *__restrict__ rng, const uint32_t *__restrict__ svals, const SplatRec *__restrict__ rec,
     int tiles_x, int tpv, int W, int H, uint32_t n_tiles, float thr, const float *__restrict__ gimg,
     float *__restrict__ acc6) {
   __shared__ float4 s_cw[kWave];
@@ -729,7 +743,7 @@ __global__ __launch_bounds__(kWave) void splat_bwd_pixel_kernel(
     const int x = tx * kTS + col, y = ty * kTS + row0 + k;
     gpx[k] = (x < W && y < H) ? gv[uint64_t(y) * W + x] : 0.f;
   }
-  const uint32_t b0 = start[tile], e = start[tile + 1];
+  const uint32_t b0 = rng[tile].x, e = rng[tile].y;
   for (uint32_t b = b0; b < e; b += kWave) {
     const uint32_t m = min(uint32_t(kWave), e - b);
     if (uint32_t(lane) < m) {
@@ -914,7 +928,7 @@ struct ExactCam {
 
 template <bool kCount, int TPB>
 __global__ __launch_bounds__(kWave * TPB) void splat_fwd_exact_kernel(
-    const uint32_t *__restrict__ start, const uint32_t *__restrict__ svals, const ExactRec *__restrict__ rec,
+    const uint2 *__restrict__ rng, const uint32_t *__restrict__ svals, const ExactRec *__restrict__ rec,
     int tiles_x, int tpv, int W, int H, uint32_t n_tiles, int n_chunks, float thr, float thr_cull, ExactCam cam,
     float *__restrict__ img, unsigned long long *__restrict__ counter) {
   __shared__ float4 s_a_all[TPB][kWave + 1];
@@ -951,7 +965,7 @@ __global__ __launch_bounds__(kWave * TPB) void splat_fwd_exact_kernel(
   float acc[kRows];
 #pragma unroll
   for (int k = 0; k < kRows; ++k) acc[k] = 0.f;
-  const uint32_t b0 = start[tile], e = start[tile + 1];
+  const uint32_t b0 = rng[tile].x, e = rng[tile].y;
   for (uint32_t b = b0 + chunk * kWave; b < e; b += kWave * uint32_t(n_chunks)) {
     const uint32_t m = min(uint32_t(kWave), e - b);
     uint32_t mask = 0;
@@ -1030,7 +1044,7 @@ constexpr int kExactSums = 13;
 // of alpha = -(p / A)(1/2 + phi) and beta = p / A.
 template <int TPB>
 __global__ __launch_bounds__(kWave * TPB) void splat_bwd_exact_kernel(
-    const uint32_t *__restrict__ start, const uint32_t *__restrict__ svals, const ExactRec *__restrict__ rec,
+    const uint2 *__restrict__ rng, const uint32_t *__restrict__ svals, const ExactRec *__restrict__ rec,
     int tiles_x, int tpv, int W, int H, uint32_t n_tiles, int n_chunks, float thr, float thr_cull, ExactCam cam,
     const float *__restrict__ gimg, float4 *__restrict__ partials) {
   __shared__ float4 s_g4_all[TPB][kTS * kTS / 4];
@@ -1066,7 +1080,7 @@ __global__ __launch_bounds__(kWave * TPB) void splat_bwd_exact_kernel(
   wave_lds_sync();
   const float tx0 = float(tx * kTS) + 0.5f, ty0 = float(ty * kTS) + 0.5f;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const uint32_t b0 = start[tile], e = start[tile + 1];
+  const uint32_t b0 = rng[tile].x, e = rng[tile].y;
   for (uint32_t b = b0 + chunk * kWave; b < e; b += kWave * uint32_t(n_chunks)) {
     const uint32_t m = min(uint32_t(kWave), e - b);
     uint32_t mask = 0, slot = 0;
@@ -1262,7 +1276,7 @@ __global__ __launch_bounds__(256) void record_grad_exact_kernel(fgs_gaussians g,
 struct RastLayout {
   uint64_t R, T, K;
   // byte offsets
-  uint64_t total64, xy, radii, rect, offset, rec, scan_scratch, start, grad_rec;
+  uint64_t total64, xy, radii, rect, offset, rec, scan_scratch, rng, grad_rec;
   uint64_t fixed_end;
   uint64_t keys, vals, keys_alt, vals_alt, sort_scratch, partials;
   uint64_t total;
@@ -1270,7 +1284,7 @@ struct RastLayout {
 };
 
 // exact: the ray-exact model's 64-byte records and pair slots (else 32).
-RastLayout rast_layout(uint64_t R, uint64_t T, uint64_t K, bool exact) {
+RastLayout rast_layout(uint64_t R, uint64_t T, uint64_t K, bool exact, int tile_bits) {
   RastLayout L{};
   L.R = R;
   L.T = T;
@@ -1286,7 +1300,7 @@ RastLayout rast_layout(uint64_t R, uint64_t T, uint64_t K, bool exact) {
   else
     c.take<SplatRec>(R, &L.rec);
   c.take<uint32_t>(scan_scratch_words(R), &L.scan_scratch);
-  c.take<uint32_t>(T + 1, &L.start);
+  c.take<uint2>(T, &L.rng);
   c.take<float>(11 * R, &L.grad_rec);
   L.fixed_end = c.used;
   c.take<uint32_t>(K, &L.keys);
@@ -1296,8 +1310,8 @@ RastLayout rast_layout(uint64_t R, uint64_t T, uint64_t K, bool exact) {
   c.take<uint32_t>(sort_scratch_words(K), &L.sort_scratch);
   c.take<float4>((exact ? 4 : 2) * K, &L.partials);
   L.total = c.used;
-  const int bits = bits_for(T);
-  const int passes = (K > 1 && bits > 0) ? (bits + 8) / 9 : 0;
+  const int bits = tile_bits;
+  const int passes = sort_passes(K, bits);
   L.sorted_in_alt = (passes & 1) != 0;
   return L;
 }
@@ -1389,7 +1403,8 @@ int build_lists(const fgs_gaussians *g, const fgs_geom *geom, int32_t view_begin
   const uint64_t T = uint64_t(view_count) * uint64_t(tg.tpv);
   if (T >= 0xffffffffull || R >= 0xffffffffull) return fail(FGS_E_UNSUPPORTED, "too many tiles or records in one call");
   const bool exact = use_exact(geom, o);
-  RastLayout L = rast_layout(R, T, 0, exact);
+  const int tile_bits = bits_for(uint64_t(tg.tpv));
+  RastLayout L = rast_layout(R, T, 0, exact, tile_bits);
   ws->kind = 0;
   if (!ws->ptr || ws->bytes < L.fixed_end + (uint64_t(1) << 20)) {
     ws->needed = L.fixed_end + (uint64_t(64) << 20);
@@ -1420,14 +1435,15 @@ int build_lists(const fgs_gaussians *g, const fgs_geom *geom, int32_t view_begin
   if (K64 >= 0xffffffffull)
     return fail(FGS_E_UNSUPPORTED, "more than 2^32 (tile, Gaussian) pairs in one call; split the views");
   const uint64_t K = K64;
-  L = rast_layout(R, T, K, exact);
+  L = rast_layout(R, T, K, exact, tile_bits);
   ws->needed = L.total + extra_bytes;
   ws->n_pairs = K;
   ws->n_records = R;
   ws->n_tiles = T;
+  ws->tile_bits = tile_bits;
   if (ws->bytes < L.total + extra_bytes) return fail(FGS_E_CAPACITY, "workspace too small for the tile lists");
   if (K > 0) {
-    emit_kernel<<<grid_for(R, kEmitBlock), kEmitBlock, 0, s>>>(R, g->n, tg.tiles_x, tg.tpv, at<ushort4>(b, L.rect),
+    emit_kernel<<<grid_for(R, kEmitBlock), kEmitBlock, 0, s>>>(R, g->n, tg.tiles_x, tile_bits, at<ushort4>(b, L.rect),
                                                   at<uint32_t>(b, L.offset), at<uint32_t>(b, L.keys),
                                                   at<uint32_t>(b, L.vals),
                                                   exact ? &at<ExactRec>(b, L.rec)->d.y : &at<SplatRec>(b, L.rec)->b.z,
@@ -1436,11 +1452,15 @@ int build_lists(const fgs_gaussians *g, const fgs_geom *geom, int32_t view_begin
   }
   uint32_t *sk, *sv;
   st = radix_sort_pairs(at<uint32_t>(b, L.keys), at<uint32_t>(b, L.vals), at<uint32_t>(b, L.keys_alt),
-                        at<uint32_t>(b, L.vals_alt), K, bits_for(T), at<uint32_t>(b, L.sort_scratch),
+                        at<uint32_t>(b, L.vals_alt), K, tile_bits, at<uint32_t>(b, L.sort_scratch),
                         &sk, &sv, s);
   if (st != FGS_OK) return st;
-  ranges_kernel<<<grid_for(K + 1, 256), 256, 0, s>>>(sk, K, uint32_t(T), at<uint32_t>(b, L.start));
-  FGS_LAUNCH_CHECK("ranges_kernel");
+  zero_ranges_kernel<<<grid_for(T, 256), 256, 0, s>>>(at<uint2>(b, L.rng), T);
+  FGS_LAUNCH_CHECK("zero_ranges_kernel");
+  if (K > 0) {
+    ranges_kernel<<<grid_for(K, 256), 256, 0, s>>>(sk, K, tile_bits, uint32_t(tg.tpv), at<uint2>(b, L.rng));
+    FGS_LAUNCH_CHECK("ranges_kernel");
+  }
   ws->kind = exact ? 3 : 1;
   *Lout = L;
   return FGS_OK;
@@ -1482,7 +1502,7 @@ extern "C" int fgs_project_views_fwd(const fgs_gaussians *g, const fgs_geom *geo
     with_tiles_per_block(units, [&](auto tpb) {
       constexpr int TPB = decltype(tpb)::value;
       splat_fwd_exact_kernel<false, TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
-          at<uint32_t>(b, L.start), sv, at<ExactRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
+          at<uint2>(b, L.rng), sv, at<ExactRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
           uint32_t(L.T), chunks, thr, thr * kCullSlack, cam, part, nullptr);
     });
     FGS_LAUNCH_CHECK("splat_fwd_exact_kernel");
@@ -1493,11 +1513,11 @@ extern "C" int fgs_project_views_fwd(const fgs_gaussians *g, const fgs_geom *geo
       constexpr int TPB = decltype(tpb)::value;
       if (interior)
         splat_fwd_kernel<false, true, TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
-            at<uint32_t>(b, L.start), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
+            at<uint2>(b, L.rng), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
             uint32_t(L.T), chunks, thr, thr * kCullSlack, thr * kInteriorSlack, no_cull, part, nullptr);
       else
         splat_fwd_kernel<false, false, TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
-            at<uint32_t>(b, L.start), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
+            at<uint2>(b, L.rng), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
             uint32_t(L.T), chunks, thr, thr * kCullSlack, thr * kInteriorSlack, no_cull, part, nullptr);
     });
     FGS_LAUNCH_CHECK("splat_fwd_kernel");
@@ -1534,7 +1554,7 @@ extern "C" int fgs_project_views_support(const fgs_gaussians *g, const fgs_geom 
     with_tiles_per_block(units, [&](auto tpb) {
       constexpr int TPB = decltype(tpb)::value;
       splat_fwd_exact_kernel<true, TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
-          at<uint32_t>(b, L.start), sv, at<ExactRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
+          at<uint2>(b, L.rng), sv, at<ExactRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
           uint32_t(L.T), chunks, thr, thr * kCullSlack, cam, nullptr, cnt);
     });
     FGS_LAUNCH_CHECK("splat_fwd_exact_kernel<count>");
@@ -1543,7 +1563,7 @@ extern "C" int fgs_project_views_support(const fgs_gaussians *g, const fgs_geom 
   with_tiles_per_block(units, [&](auto tpb) {
     constexpr int TPB = decltype(tpb)::value;
     splat_fwd_kernel<true, false, TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
-        at<uint32_t>(b, L.start), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
+        at<uint2>(b, L.rng), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
         uint32_t(L.T), chunks, thr, thr * kCullSlack, thr * kInteriorSlack, 0, nullptr, cnt);
   });
   FGS_LAUNCH_CHECK("splat_fwd_kernel<count>");
@@ -1567,7 +1587,7 @@ extern "C" int fgs_project_views_bwd(const fgs_gaussians *g, const fgs_geom *geo
     if (ws->kind != (use_exact(geom, opts) ? 3 : 1) || ws->n_records != R || !ws->ptr)
       return fail(FGS_E_INVALID, "workspace does not hold this call's rasterizer lists");
     const uint64_t T = uint64_t(view_count) * uint64_t(tile_grid(geom->det_w, geom->det_h).tpv);
-    L = rast_layout(R, T, ws->n_pairs, use_exact(geom, opts));
+    L = rast_layout(R, T, ws->n_pairs, use_exact(geom, opts), ws->tile_bits);
     if (T != ws->n_tiles || ws->bytes < L.total)
       return fail(FGS_E_INVALID, "workspace lists do not match this call");
   }
@@ -1586,7 +1606,7 @@ extern "C" int fgs_project_views_bwd(const fgs_gaussians *g, const fgs_geom *geo
       with_tiles_per_block(units, [&](auto tpb) {
         constexpr int TPB = decltype(tpb)::value;
         splat_bwd_exact_kernel<TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
-            at<uint32_t>(b, L.start), sv, at<ExactRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
+            at<uint2>(b, L.rng), sv, at<ExactRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
             uint32_t(L.T), chunks, thr, thr * kCullSlack, cam, grad_img, at<float4>(b, L.partials));
       });
       FGS_LAUNCH_CHECK("splat_bwd_exact_kernel");
@@ -1609,7 +1629,7 @@ extern "C" int fgs_project_views_bwd(const fgs_gaussians *g, const fgs_geom *geo
     fill_zero_kernel<<<grid_for(6 * R, 256), 256, 0, s>>>(acc6, 6 * R);
     FGS_LAUNCH_CHECK("fill_zero_kernel");
     if (L.K > 0) {
-      splat_bwd_pixel_kernel<<<unsigned(L.T), kWave, 0, s>>>(at<uint32_t>(b, L.start), sv, at<SplatRec>(b, L.rec),
+      splat_bwd_pixel_kernel<<<unsigned(L.T), kWave, 0, s>>>(at<uint2>(b, L.rng), sv, at<SplatRec>(b, L.rec),
                                                              tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
                                                              uint32_t(L.T), thr, grad_img, acc6);
       FGS_LAUNCH_CHECK("splat_bwd_pixel_kernel");
@@ -1620,7 +1640,7 @@ extern "C" int fgs_project_views_bwd(const fgs_gaussians *g, const fgs_geom *geo
     with_tiles_per_block(units, [&](auto tpb) {
       constexpr int TPB = decltype(tpb)::value;
       splat_bwd_kernel<TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
-          at<uint32_t>(b, L.start), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
+          at<uint2>(b, L.rng), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
           uint32_t(L.T), chunks, thr, thr * kCullSlack, (opts->ablate & FGS_ABLATE_QUADRANT_CULL) ? 1 : 0,
           grad_img, at<float4>(b, L.partials));
     });
@@ -1639,7 +1659,7 @@ extern "C" int fgs_project_views_bwd(const fgs_gaussians *g, const fgs_geom *geo
 
 namespace fgs {
 int rast_binning_layout(const fgs_workspace *ws, uint64_t off[9], uint64_t counts[3]) {
-  RastLayout L = rast_layout(ws->n_records, ws->n_tiles, ws->n_pairs, ws->kind == 3);
+  RastLayout L = rast_layout(ws->n_records, ws->n_tiles, ws->n_pairs, ws->kind == 3, ws->tile_bits);
   off[0] = L.xy;
   off[1] = L.radii;
   off[2] = L.rect;
@@ -1648,7 +1668,7 @@ int rast_binning_layout(const fgs_workspace *ws, uint64_t off[9], uint64_t count
   off[5] = L.sorted_in_alt ? L.vals : L.vals_alt;
   off[6] = L.sorted_in_alt ? L.keys_alt : L.keys;
   off[7] = L.sorted_in_alt ? L.vals_alt : L.vals;
-  off[8] = L.start;
+  off[8] = L.rng;
   counts[0] = L.R;
   counts[1] = L.K;
   counts[2] = L.T;

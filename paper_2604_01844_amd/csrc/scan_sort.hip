@@ -21,8 +21,7 @@ constexpr int kThreads = 256;
 constexpr int kItems = 16;
 constexpr int kTile = kThreads * kItems;  // 4096
 constexpr int kWaves = kThreads / 64;
-constexpr int kMaxBits = 9;
-constexpr int kBins = 1 << kMaxBits;
+constexpr int kMaxBins = 1 << kSortMaxBits;
 
 // Exclusive scan of one value per thread across the 256-thread block.
 template <typename T>
@@ -109,10 +108,15 @@ __global__ __launch_bounds__(kThreads) void scan_apply_kernel(T *__restrict__ da
 
 // ------------------------------------------------------------- radix sort
 
+// NB: the widest digit the kernel is built for (its LDS tables hold 2^NB
+// bins). Passes of up to 9 bits use the NB = 9 build, which needs less LDS;
+// only a pass that the 10-bit build saves runs with it.
+template <int NB>
 __global__ __launch_bounds__(kThreads) void rs_hist_kernel(const uint32_t *__restrict__ keys,
                                                            uint64_t n, int shift, uint32_t mask,
                                                            uint32_t *__restrict__ hist,
                                                            uint32_t n_tiles) {
+  constexpr int kBins = 1 << NB;
   __shared__ uint32_t h[kBins];
   for (int i = threadIdx.x; i < kBins; i += kThreads) h[i] = 0;
   __syncthreads();
@@ -132,10 +136,12 @@ __global__ __launch_bounds__(kThreads) void rs_hist_kernel(const uint32_t *__res
 // Keys are first placed in LDS in the tile's digit-sorted order, then
 // written out linearly: consecutive threads write consecutive positions of
 // each digit's run, so the global writes are coalesced.
+template <int NB>
 __global__ __launch_bounds__(kThreads) void rs_scatter_kernel(
     const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in, uint64_t n,
     int shift, int nbits, const uint32_t *__restrict__ hist_scanned, uint32_t n_tiles,
     uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out) {
+  constexpr int kBins = 1 << NB;
   __shared__ uint32_t cnt[kWaves][kBins];
   __shared__ uint32_t s_local[kBins];     // tile-local start of each digit's run
   __shared__ uint32_t s_global[kBins];    // global start of each digit's run for this tile
@@ -175,8 +181,9 @@ __global__ __launch_bounds__(kThreads) void rs_scatter_kernel(
   // per digit d: the tile's count, the waves' offsets inside the digit's run,
   // then an exclusive scan of the counts over digits (the tile-local starts)
   const int bins = int(mask) + 1;
-  const int per_thread = (bins + kThreads - 1) / kThreads;  // <= 2
-  uint32_t tot[2] = {0u, 0u};
+  constexpr int kPer = (kBins + kThreads - 1) / kThreads;
+  const int per_thread = (bins + kThreads - 1) / kThreads;  // <= kPer
+  uint32_t tot[kPer] = {};
   for (int q = 0; q < per_thread; ++q) {
     const int d = threadIdx.x * per_thread + q;
     if (d < bins) {
@@ -191,7 +198,9 @@ __global__ __launch_bounds__(kThreads) void rs_scatter_kernel(
       s_global[d] = hist_scanned[uint64_t(d) * n_tiles + blockIdx.x];
     }
   }
-  const uint32_t mine = tot[0] + tot[1];
+  uint32_t mine = 0;
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) mine += tot[q];
   uint32_t incl = mine;  // inclusive scan of `mine` over the block
   for (int o = 1; o < 64; o <<= 1) {
     const uint32_t y = __shfl_up(incl, o, 64);
@@ -282,7 +291,7 @@ int exclusive_scan_u64(uint64_t *data, uint64_t n, uint32_t *scratch, hipStream_
 
 uint64_t sort_scratch_words(uint64_t n) {
   const uint64_t tiles = (n + kTile - 1) / kTile;
-  const uint64_t table = uint64_t(kBins) * tiles;
+  const uint64_t table = uint64_t(kMaxBins) * tiles;
   return align_up((table + 1) * sizeof(uint32_t)) / sizeof(uint32_t) + scan_scratch_words(table);
 }
 
@@ -294,20 +303,25 @@ int radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_
   if (n <= 1 || bits <= 0) return FGS_OK;
   if (n > 0xffffffffull) return fail(FGS_E_UNSUPPORTED, "sort: more than 2^32 pairs");
   const uint64_t tiles = (n + kTile - 1) / kTile;
-  const int passes = (bits + kMaxBits - 1) / kMaxBits;
+  const int passes = sort_passes(n, bits);
   const int per = (bits + passes - 1) / passes;
   uint32_t *table = scratch;
-  uint32_t *scan_tmp = scratch + align_up((uint64_t(kBins) * tiles + 1) * sizeof(uint32_t)) / sizeof(uint32_t);
+  uint32_t *scan_tmp = scratch + align_up((uint64_t(kMaxBins) * tiles + 1) * sizeof(uint32_t)) / sizeof(uint32_t);
   uint32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
   for (int p = 0, shift = 0; p < passes; ++p, shift += per) {
     const int nb = (bits - shift < per) ? (bits - shift) : per;
     const uint32_t mask = (1u << nb) - 1u;
-    rs_hist_kernel<<<unsigned(tiles), kThreads, 0, s>>>(ki, n, shift, mask, table, unsigned(tiles));
+    if (nb > 9)
+      rs_hist_kernel<10><<<unsigned(tiles), kThreads, 0, s>>>(ki, n, shift, mask, table, unsigned(tiles));
+    else
+      rs_hist_kernel<9><<<unsigned(tiles), kThreads, 0, s>>>(ki, n, shift, mask, table, unsigned(tiles));
     FGS_LAUNCH_CHECK("rs_hist_kernel");
     int st = exclusive_scan_u32(table, uint64_t(mask + 1) * tiles, scan_tmp, s);
     if (st != FGS_OK) return st;
-    rs_scatter_kernel<<<unsigned(tiles), kThreads, 0, s>>>(ki, vi, n, shift, nb, table,
-                                                           unsigned(tiles), ko, vo);
+    if (nb > 9)
+      rs_scatter_kernel<10><<<unsigned(tiles), kThreads, 0, s>>>(ki, vi, n, shift, nb, table, unsigned(tiles), ko, vo);
+    else
+      rs_scatter_kernel<9><<<unsigned(tiles), kThreads, 0, s>>>(ki, vi, n, shift, nb, table, unsigned(tiles), ko, vo);
     FGS_LAUNCH_CHECK("rs_scatter_kernel");
     uint32_t *t;
     t = ki; ki = ko; ko = t;

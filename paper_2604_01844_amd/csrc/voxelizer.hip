@@ -590,7 +590,7 @@ VoxLayout vox_layout(uint64_t N, uint64_t T, uint64_t K) {
   c.take<float>(10 * K, &L.partials);
   L.total = c.used;
   const int bits = bits_for(T);
-  const int passes = (K > 1 && bits > 0) ? (bits + 8) / 9 : 0;
+  const int passes = sort_passes(K, bits);
   L.sorted_in_alt = (passes & 1) != 0;
   return L;
 }

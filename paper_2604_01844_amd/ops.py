@@ -511,7 +511,8 @@ def adc_densify(params, m, v, stat, normals, *, grad_threshold: float, split_sca
 # ------------------------------------------------------------------ introspection
 
 def binning_dump(ws: Workspace) -> dict:
-    """Views of the binning arrays the last forward call left in ``ws``."""
+    """Views of the binning arrays the last forward call left in ``ws``
+    (rasterizer: per-tile [begin, end) ranges; voxelizer: tile starts)."""
     L = A.lib()
     off = (ctypes.c_uint64 * 9)()
     cnt = (ctypes.c_uint64 * 3)()
@@ -532,7 +533,8 @@ def binning_dump(ws: Workspace) -> dict:
         offset=view(3, torch.int32, R + 1),
         sorted_keys=view(6, torch.int32, K),
         sorted_vals=view(7, torch.int32, K),
-        tile_start=view(8, torch.int32, T + 1),
+        **({"tile_start": view(8, torch.int32, T + 1)} if vox else
+           {"tile_ranges": view(8, torch.int32, T, 2), "tile_bits": int(ws.s.tile_bits)}),
         n_records=R, n_pairs=K, n_tiles=T)
 
 
