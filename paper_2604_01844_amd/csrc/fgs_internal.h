@@ -48,6 +48,17 @@ __device__ __forceinline__ int upper_index(const uint32_t *off, int n, uint32_t 
 // out[i] = sum over c = 0..chunks-1 (in order) of part[c * n + i].
 int sum_chunks(const float *part, int chunks, uint64_t n, float *out, hipStream_t s);
 
+// XCD-aware block order. MI355X has 8 XCDs, each with its own L2, and hands
+// out consecutive workgroups round-robin over them. Renumbering so that XCD x
+// takes the x-th contiguous eighth of the blocks keeps neighbouring tiles,
+// which read the same records, in one L2. A bijection of [0, n).
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t n) {
+  const uint32_t x = b % kXcds, q = b / kXcds;
+  const uint32_t base = n / kXcds, rem = n % kXcds;
+  return x * base + (x < rem ? x : rem) + q;
+}
+
 // Calls f(std::integral_constant<int, TPB>) with TPB = tiles_per_block(n_tiles).
 template <typename F>
 void with_tiles_per_block(uint64_t n_tiles, F &&f) {

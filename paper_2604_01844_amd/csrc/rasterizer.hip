@@ -439,7 +439,7 @@ __global__ __launch_bounds__(kWave * TPB) void splat_fwd_kernel(const uint2 *__r
   uint8_t(*s_list)[kWave] = s_list_all[wid];
   // work unit = (tile, chunk): chunk c takes batches c, c + n_chunks, ... of
   // the tile's list and writes its own partial image (n_chunks > 1)
-  const uint32_t unit = blockIdx.x * TPB + wid;
+  const uint32_t unit = xcd_block(blockIdx.x, gridDim.x) * TPB + wid;
   if (unit >= n_tiles * uint32_t(n_chunks)) return;
   const uint32_t tile = unit / uint32_t(n_chunks);
   const uint32_t chunk = unit - tile * uint32_t(n_chunks);
@@ -587,7 +587,7 @@ __global__ __launch_bounds__(kWave * TPB) __attribute__((amdgpu_waves_per_eu(8, 
   uint8_t *s_cat = s_cat_all[wid];
   // work unit = (tile, chunk): chunk c takes batches c, c + n_chunks, ...
   // (each pair's sums go to its own slot, so chunks are independent)
-  const uint32_t unit = blockIdx.x * TPB + wid;
+  const uint32_t unit = xcd_block(blockIdx.x, gridDim.x) * TPB + wid;
   if (unit >= n_tiles * uint32_t(n_chunks)) return;
   const uint32_t tile = unit / uint32_t(n_chunks);
   const uint32_t chunk = unit - tile * uint32_t(n_chunks);
@@ -942,7 +942,7 @@ __global__ __launch_bounds__(kWave * TPB) void splat_fwd_exact_kernel(
   float4 *s_c = s_c_all[wid];
   float *s_w = s_w_all[wid];
   uint8_t(*s_list)[kWave] = s_list_all[wid];
-  const uint32_t unit = blockIdx.x * TPB + wid;
+  const uint32_t unit = xcd_block(blockIdx.x, gridDim.x) * TPB + wid;
   if (unit >= n_tiles * uint32_t(n_chunks)) return;
   const uint32_t tile = unit / uint32_t(n_chunks);
   const uint32_t chunk = unit - tile * uint32_t(n_chunks);
@@ -1059,7 +1059,7 @@ __global__ __launch_bounds__(kWave * TPB) void splat_bwd_exact_kernel(
   float4 *s_b = s_b_all[wid];
   float4 *s_c = s_c_all[wid];
   uint8_t *s_cat = s_cat_all[wid];
-  const uint32_t unit = blockIdx.x * TPB + wid;
+  const uint32_t unit = xcd_block(blockIdx.x, gridDim.x) * TPB + wid;
   if (unit >= n_tiles * uint32_t(n_chunks)) return;
   const uint32_t tile = unit / uint32_t(n_chunks);
   const uint32_t chunk = unit - tile * uint32_t(n_chunks);
