@@ -269,7 +269,7 @@ __global__ __launch_bounds__(kWave * TPB) void vox_fwd_kernel(const uint32_t *__
   float4 *s_p = s_all[wid][0], *s_a0 = s_all[wid][1], *s_a1 = s_all[wid][2];
   // work unit = (tile, chunk): chunk c takes batches c, c + n_chunks, ... of
   // the tile's list and writes its own partial volume (n_chunks > 1)
-  const uint32_t unit = blockIdx.x * TPB + wid;
+  const uint32_t unit = xcd_block(blockIdx.x, gridDim.x) * TPB + wid;
   if (unit >= n_tiles * uint32_t(n_chunks)) return;
   const uint32_t tile = unit / uint32_t(n_chunks);
   const uint32_t chunk = unit - tile * uint32_t(n_chunks);
@@ -363,6 +363,7 @@ __global__ __launch_bounds__(kWave * TPB) void vox_bwd_kernel(const uint32_t *__
   float4 *s_g4 = s_g4_all[wid];
   float *s_g = reinterpret_cast<float *>(s_g4);
   // work unit = (tile, chunk): chunk c takes batches c, c + n_chunks, ...
+  // (the natural block order: the XCD-aware one measured 4% slower here)
   const uint32_t unit = blockIdx.x * TPB + wid;
   if (unit >= n_tiles * uint32_t(n_chunks)) return;
   const uint32_t tile = unit / uint32_t(n_chunks);
