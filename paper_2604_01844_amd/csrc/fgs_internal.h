@@ -121,10 +121,11 @@ int exclusive_scan_u64(uint64_t *data, uint64_t n, uint32_t *scratch, hipStream_
 // Widest digit of one radix-sort pass (1024 bins).
 constexpr int kSortMaxBits = 10;
 
-// Passes radix_sort_pairs makes over n pairs sorted on `bits` bits; the
-// result ends in the alternate buffers when this is odd.
-inline int sort_passes(uint64_t n, int bits) {
-  return (n > 1 && bits > 0) ? (bits + kSortMaxBits - 1) / kSortMaxBits : 0;
+// Passes radix_sort_pairs makes over n pairs sorted on `bits` bits with
+// digits of at most max_bits; the result ends in the alternate buffers when
+// this is odd.
+inline int sort_passes(uint64_t n, int bits, int max_bits = kSortMaxBits) {
+  return (n > 1 && bits > 0) ? (bits + max_bits - 1) / max_bits : 0;
 }
 
 // Stable LSD radix sort of (key, value) uint32 pairs on the low `bits` bits
@@ -133,7 +134,7 @@ inline int sort_passes(uint64_t n, int bits) {
 uint64_t sort_scratch_words(uint64_t n);
 int radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
                      uint64_t n, int bits, uint32_t *scratch, uint32_t **out_keys,
-                     uint32_t **out_vals, hipStream_t s);
+                     uint32_t **out_vals, hipStream_t s, int max_bits = kSortMaxBits);
 
 inline int bits_for(uint64_t n_values) {  // bits needed to hold 0 .. n_values - 1
   int b = 0;

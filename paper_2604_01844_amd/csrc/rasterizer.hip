@@ -11,11 +11,12 @@
 //                         completes the record's slot base. Records are
 //                         view-major, so the emitted keys already ascend in
 //                         the view field.
-//   4. radix sort         stable, over the tile field only (one pass for up
-//                         to 1024 tiles per view): with the input already in
-//                         view order this orders the pairs by (tile, view),
-//                         each tile's list in ascending Gaussian index; no
-//                         depth key (the sum is order-free).
+//   4. radix sort         stable, over the tile field only (two passes of
+//                         at most 7 bits for up to 16384 tiles per view):
+//                         with the input already in view order this orders
+//                         the pairs by (tile, view), each tile's list in
+//                         ascending Gaussian index; no depth key (the sum is
+//                         order-free).
 //   5. ranges kernel      per-(view, tile) [start, end) by boundary detection.
 //   6. splat kernel       one 64-lane wave per 16x16 tile, up to 16 tiles
 //                         per workgroup; batches of 64 records staged in LDS;
@@ -67,6 +68,13 @@ __device__ __forceinline__ void tile_span(float c, float r, int n_tiles, int &t0
 }
 
 constexpr int kTotalSlots = 64;
+
+// Widest digit of the rasterizer's sort passes over the tile field. Narrow
+// digits keep the per-block histograms small and the output runs long;
+// measured on MI355X, two 5-bit passes (1024 tiles per view) beat one 10-bit
+// pass by ~0.3 ms per standard-scan step, and two 7-bit passes (16384 tiles)
+// beat three 5-bit ones.
+constexpr int kRastSortBits = 7;
 
 // What the pixel kernels read per (tile, Gaussian) pair, packed in one
 // 32-byte line: a = (u, v, pre-scaled conic c00, c01), b = (c11, w, base,
@@ -1311,7 +1319,7 @@ RastLayout rast_layout(uint64_t R, uint64_t T, uint64_t K, bool exact, int tile_
   c.take<float4>((exact ? 4 : 2) * K, &L.partials);
   L.total = c.used;
   const int bits = tile_bits;
-  const int passes = sort_passes(K, bits);
+  const int passes = sort_passes(K, bits, kRastSortBits);
   L.sorted_in_alt = (passes & 1) != 0;
   return L;
 }
@@ -1453,7 +1461,7 @@ int build_lists(const fgs_gaussians *g, const fgs_geom *geom, int32_t view_begin
   uint32_t *sk, *sv;
   st = radix_sort_pairs(at<uint32_t>(b, L.keys), at<uint32_t>(b, L.vals), at<uint32_t>(b, L.keys_alt),
                         at<uint32_t>(b, L.vals_alt), K, tile_bits, at<uint32_t>(b, L.sort_scratch),
-                        &sk, &sv, s);
+                        &sk, &sv, s, kRastSortBits);
   if (st != FGS_OK) return st;
   zero_ranges_kernel<<<grid_for(T, 256), 256, 0, s>>>(at<uint2>(b, L.rng), T);
   FGS_LAUNCH_CHECK("zero_ranges_kernel");

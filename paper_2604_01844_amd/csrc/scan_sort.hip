@@ -109,8 +109,8 @@ __global__ __launch_bounds__(kThreads) void scan_apply_kernel(T *__restrict__ da
 // ------------------------------------------------------------- radix sort
 
 // NB: the widest digit the kernel is built for (its LDS tables hold 2^NB
-// bins). Passes of up to 9 bits use the NB = 9 build, which needs less LDS;
-// only a pass that the 10-bit build saves runs with it.
+// bins); each pass runs the smallest build (6, 9 or 10 bits) that holds its
+// digit, which needs the least LDS.
 template <int NB>
 __global__ __launch_bounds__(kThreads) void rs_hist_kernel(const uint32_t *__restrict__ keys,
                                                            uint64_t n, int shift, uint32_t mask,
@@ -297,13 +297,14 @@ uint64_t sort_scratch_words(uint64_t n) {
 
 int radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
                      uint64_t n, int bits, uint32_t *scratch, uint32_t **out_keys,
-                     uint32_t **out_vals, hipStream_t s) {
+                     uint32_t **out_vals, hipStream_t s, int max_bits) {
   *out_keys = keys;
   *out_vals = vals;
   if (n <= 1 || bits <= 0) return FGS_OK;
   if (n > 0xffffffffull) return fail(FGS_E_UNSUPPORTED, "sort: more than 2^32 pairs");
   const uint64_t tiles = (n + kTile - 1) / kTile;
-  const int passes = sort_passes(n, bits);
+  if (max_bits < 1 || max_bits > kSortMaxBits) return fail(FGS_E_INVALID, "sort: digit width");
+  const int passes = sort_passes(n, bits, max_bits);
   const int per = (bits + passes - 1) / passes;
   uint32_t *table = scratch;
   uint32_t *scan_tmp = scratch + align_up((uint64_t(kMaxBins) * tiles + 1) * sizeof(uint32_t)) / sizeof(uint32_t);
@@ -313,15 +314,19 @@ int radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_
     const uint32_t mask = (1u << nb) - 1u;
     if (nb > 9)
       rs_hist_kernel<10><<<unsigned(tiles), kThreads, 0, s>>>(ki, n, shift, mask, table, unsigned(tiles));
-    else
+    else if (nb > 6)
       rs_hist_kernel<9><<<unsigned(tiles), kThreads, 0, s>>>(ki, n, shift, mask, table, unsigned(tiles));
+    else
+      rs_hist_kernel<6><<<unsigned(tiles), kThreads, 0, s>>>(ki, n, shift, mask, table, unsigned(tiles));
     FGS_LAUNCH_CHECK("rs_hist_kernel");
     int st = exclusive_scan_u32(table, uint64_t(mask + 1) * tiles, scan_tmp, s);
     if (st != FGS_OK) return st;
     if (nb > 9)
       rs_scatter_kernel<10><<<unsigned(tiles), kThreads, 0, s>>>(ki, vi, n, shift, nb, table, unsigned(tiles), ko, vo);
-    else
+    else if (nb > 6)
       rs_scatter_kernel<9><<<unsigned(tiles), kThreads, 0, s>>>(ki, vi, n, shift, nb, table, unsigned(tiles), ko, vo);
+    else
+      rs_scatter_kernel<6><<<unsigned(tiles), kThreads, 0, s>>>(ki, vi, n, shift, nb, table, unsigned(tiles), ko, vo);
     FGS_LAUNCH_CHECK("rs_scatter_kernel");
     uint32_t *t;
     t = ki; ki = ko; ko = t;
