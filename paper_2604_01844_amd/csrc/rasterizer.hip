@@ -265,14 +265,20 @@ __global__ __launch_bounds__(256) void zero_ranges_kernel(uint2 *__restrict__ rn
 // rng[v * tpv + t] = [first, last + 1) of key (v << tile_bits | t) in the
 // sorted keys; each key's pairs are contiguous there (tiles without pairs
 // keep the empty range the zero kernel wrote).
+// Each key is loaded once; its neighbours come from the adjacent lanes (the
+// wave's first and last lanes load theirs).
 __global__ __launch_bounds__(256) void ranges_kernel(const uint32_t *__restrict__ skeys, uint64_t K, int tile_bits,
                                                      uint32_t tpv, uint2 *__restrict__ rng) {
   const uint64_t k = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  const uint32_t key = k < K ? skeys[k] : 0u;
+  uint32_t prev = __shfl_up(key, 1, kWave), next = __shfl_down(key, 1, kWave);
   if (k >= K) return;
-  const uint32_t key = skeys[k];
+  if (lane == 0) prev = k > 0 ? skeys[k - 1] : ~key;
+  if (lane == kWave - 1 || k + 1 == K) next = k + 1 < K ? skeys[k + 1] : ~key;
   const uint32_t tile = (key >> tile_bits) * tpv + (key & ((1u << tile_bits) - 1u));
-  if (k == 0 || skeys[k - 1] != key) rng[tile].x = uint32_t(k);
-  if (k + 1 == K || skeys[k + 1] != key) rng[tile].y = uint32_t(k + 1);
+  if (prev != key) rng[tile].x = uint32_t(k);
+  if (next != key) rng[tile].y = uint32_t(k + 1);
 }
 
 // ---------------------------------------------------------------- quadrants
