@@ -121,10 +121,17 @@ __global__ __launch_bounds__(kThreads) void rs_hist_kernel(const uint32_t *__res
   for (int i = threadIdx.x; i < kBins; i += kThreads) h[i] = 0;
   __syncthreads();
   const uint64_t base = uint64_t(blockIdx.x) * kTile;
-#pragma unroll 4
+  // all of the thread's loads first, so their latencies overlap
+  uint32_t kk[kItems];
+#pragma unroll
   for (int j = 0; j < kItems; ++j) {
-    uint64_t idx = base + uint64_t(j) * kThreads + threadIdx.x;
-    if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & mask], 1u);
+    const uint64_t idx = base + uint64_t(j) * kThreads + threadIdx.x;
+    kk[j] = idx < n ? keys[idx] : 0u;
+  }
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const uint64_t idx = base + uint64_t(j) * kThreads + threadIdx.x;
+    if (idx < n) atomicAdd(&h[(kk[j] >> shift) & mask], 1u);
   }
   __syncthreads();
   for (uint32_t d = threadIdx.x; d <= mask; d += kThreads) hist[uint64_t(d) * n_tiles + blockIdx.x] = h[d];
@@ -156,11 +163,18 @@ __global__ __launch_bounds__(kThreads) void rs_scatter_kernel(
   const uint64_t wbase = uint64_t(blockIdx.x) * kTile + uint64_t(wid) * (kItems * 64);
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   uint32_t k[kItems], v[kItems], rank[kItems];
+  // all of the wave's loads first, so their latencies overlap
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const uint64_t idx = wbase + uint64_t(j) * 64 + lane;
+    k[j] = idx < n ? keys_in[idx] : 0u;
+    v[j] = idx < n ? vals_in[idx] : 0u;
+  }
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
     const uint64_t idx = wbase + uint64_t(j) * 64 + lane;
     const bool valid = idx < n;
-    const uint32_t key = valid ? keys_in[idx] : 0u;
+    const uint32_t key = k[j];
     const uint32_t d = (key >> shift) & mask;
     uint64_t peers = __ballot(valid);
     for (int b = 0; b < nbits; ++b) {
@@ -174,8 +188,6 @@ __global__ __launch_bounds__(kThreads) void rs_scatter_kernel(
     // the lowest lane of each digit group advances the wave's running count
     if (valid && before == 0) cnt[wid][d] = c + __popcll(peers);
     rank[j] = c + before;
-    k[j] = key;
-    v[j] = valid ? vals_in[idx] : 0u;
   }
   __syncthreads();
   // per digit d: the tile's count, the waves' offsets inside the digit's run,
@@ -183,10 +195,16 @@ __global__ __launch_bounds__(kThreads) void rs_scatter_kernel(
   const int bins = int(mask) + 1;
   constexpr int kPer = (kBins + kThreads - 1) / kThreads;
   const int per_thread = (bins + kThreads - 1) / kThreads;  // <= kPer
-  uint32_t tot[kPer] = {};
-  for (int q = 0; q < per_thread; ++q) {
+  uint32_t tot[kPer] = {}, gstart[kPer] = {};
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {  // the table loads first, so they overlap
     const int d = threadIdx.x * per_thread + q;
-    if (d < bins) {
+    if (q < per_thread && d < bins) gstart[q] = hist_scanned[uint64_t(d) * n_tiles + blockIdx.x];
+  }
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int d = threadIdx.x * per_thread + q;
+    if (q < per_thread && d < bins) {
       uint32_t run = 0;
 #pragma unroll
       for (int w = 0; w < kWaves; ++w) {
@@ -195,7 +213,7 @@ __global__ __launch_bounds__(kThreads) void rs_scatter_kernel(
         run += c;
       }
       tot[q] = run;
-      s_global[d] = hist_scanned[uint64_t(d) * n_tiles + blockIdx.x];
+      s_global[d] = gstart[q];
     }
   }
   uint32_t mine = 0;
