@@ -811,6 +811,7 @@ __global__ __launch_bounds__(256) void fill_zero_kernel(float *__restrict__ p, u
 // consecutive 32-byte slots), then summed across the group in a fixed
 // butterfly order; one thread per record then applies the chain rule.
 constexpr int kGradLanes = 8;
+constexpr int kGradUnroll = 4;
 
 __global__ __launch_bounds__(256) void record_grad_kernel(fgs_gaussians g, GeomDev G,
                                                           const uint32_t *__restrict__ offset,
@@ -828,11 +829,22 @@ __global__ __launch_bounds__(256) void record_grad_kernel(fgs_gaussians g, GeomD
     if (i0 + idx < g.n) {
       const uint64_t r = rbase + uint64_t(i0 + idx);
       const uint32_t o = offset[r], end = offset[r + 1];
-      for (uint32_t p = o + li; p < end; p += kGradLanes) {
-        const float4 a = partials[2 * uint64_t(p) + 0];
-        const float2 b = *reinterpret_cast<const float2 *>(&partials[2 * uint64_t(p) + 1]);
-        acc[0] += a.x; acc[1] += a.y; acc[2] += a.z;
-        acc[3] += a.w; acc[4] += b.x; acc[5] += b.y;
+      // kGradUnroll slots' loads in flight at a time; summed in slot order
+      for (uint32_t p = o + li; p < end; p += kGradUnroll * kGradLanes) {
+        float4 a[kGradUnroll];
+        float2 b[kGradUnroll];
+#pragma unroll
+        for (int u = 0; u < kGradUnroll; ++u) {
+          const uint32_t pp = p + uint32_t(u * kGradLanes);
+          a[u] = pp < end ? partials[2 * uint64_t(pp) + 0] : make_float4(0.f, 0.f, 0.f, 0.f);
+          b[u] = pp < end ? *reinterpret_cast<const float2 *>(&partials[2 * uint64_t(pp) + 1]) : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < kGradUnroll; ++u) {
+          if (p + uint32_t(u * kGradLanes) >= end) break;
+          acc[0] += a[u].x; acc[1] += a[u].y; acc[2] += a[u].z;
+          acc[3] += a[u].w; acc[4] += b[u].x; acc[5] += b[u].y;
+        }
       }
     }
 #pragma unroll
