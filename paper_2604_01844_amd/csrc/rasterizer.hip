@@ -649,8 +649,17 @@ __global__ __launch_bounds__(kWave * TPB) __attribute__((amdgpu_waves_per_eu(8, 
     }
     wave_lds_sync();
     float tot[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    for (int base = 0; base < n_pairs; base += kWave) {
-      const int idx = base + lane;
+    for (int base = 0; base < n_pairs;) {
+      // a round with at most 32 pairs left spreads each pair's 8 rows over
+      // 2, 4 or 8 lanes (lane = part * P + pair); the parts are summed in a
+      // fixed tree below, so the result stays deterministic
+      const int rem = n_pairs - base;
+      const int lg = rem > 32 ? 0 : rem > 16 ? 1 : rem > 8 ? 2 : 3;
+      const int P = kWave >> lg;
+      const int nrows = 8 >> lg;
+      const int row0 = (lane >> (6 - lg)) * nrows;
+      const float rr0 = float(row0) - 3.5f;
+      const int idx = base + (lane & (P - 1));
       int Q = 0, j = kWave;
       if (idx < n_pairs) {
         const int ent = s_cat[idx];
@@ -660,7 +669,7 @@ __global__ __launch_bounds__(kWave * TPB) __attribute__((amdgpu_waves_per_eu(8, 
       // centre of the pair's quadrant and its first float4 of dL/dI
       const float ox = float(tx * kTS + (Q & 1) * 8) + 4.f;
       const float oy = float(ty * kTS + (Q >> 1) * 8) + 4.f;
-      const float4 *g4q = s_g4 + (Q >> 1) * 8 * (kTS / 4) + (Q & 1) * 2;
+      const float4 *g4q = s_g4 + ((Q >> 1) * 8 + row0) * (kTS / 4) + (Q & 1) * 2;
       const float4 c = s_cw[j];
       const float2 q = s_xy[j];
       // Gaussian centre relative to the quadrant centre; arg = c.x dx^2 + c.y dx dy + c.z dy^2
@@ -670,8 +679,8 @@ __global__ __launch_bounds__(kWave * TPB) __attribute__((amdgpu_waves_per_eu(8, 
       const float mbqx = -c.y * qx;
       float S0 = 0.f, Sc = 0.f, Scc = 0.f, Sr = 0.f, Scr = 0.f, Srr = 0.f;
 #pragma unroll 1
-      for (int row = 0; row < 8; ++row) {
-        const float rr = float(row) - 3.5f;
+      for (int row = 0; row < nrows; ++row) {
+        const float rr = rr0 + float(row);
         const float dy = rr - qy;
         const float brow = fmaf(c.y, dy, m2aqx);
         const float drow = fmaf(dy, fmaf(c.z, dy, mbqx), aqx2);
@@ -706,12 +715,18 @@ __global__ __launch_bounds__(kWave * TPB) __attribute__((amdgpu_waves_per_eu(8, 
       M[3] = fmaf(qx * qx, S0, fmaf(-2.f * qx, Sc, Scc));
       M[4] = fmaf(qx * qy, S0, fmaf(-qy, Sc, fmaf(-qx, Sr, Scr)));
       M[5] = fmaf(qy * qy, S0, fmaf(-2.f * qy, Sr, Srr));
+      // parts summed pairwise (halves, then quarters, ...) into lanes < P
+      for (int off = kWave / 2; off >= P; off >>= 1) {
+        const int src = (lane + off) & (kWave - 1);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) M[k] += bperm(src, M[k]);
+      }
       // the loading lane of each record collects its quadrants' partials from
       // this round's lanes (quadrants with no pair in the round are skipped)
 #pragma unroll
       for (int QQ = 0; QQ < 4; ++QQ) {
         const int rel = int((gpk >> (8 * QQ)) & 255u) - base;
-        const bool mine = ((mask >> QQ) & 1u) && rel >= 0 && rel < kWave;
+        const bool mine = ((mask >> QQ) & 1u) && rel >= 0 && rel < P;
         if (__ballot(mine) == 0ull) continue;
         const int src = mine ? rel : 0;
 #pragma unroll
@@ -720,6 +735,7 @@ __global__ __launch_bounds__(kWave * TPB) __attribute__((amdgpu_waves_per_eu(8, 
           tot[k] += mine ? v : 0.f;
         }
       }
+      base += P;
     }
     if (uint32_t(lane) < m) {
       partials[2 * uint64_t(slot) + 0] = make_float4(tot[0], tot[1], tot[2], tot[3]);
