@@ -589,12 +589,14 @@ __global__ __launch_bounds__(kWave * TPB) __attribute__((amdgpu_waves_per_eu(8, 
     const uint2 *__restrict__ rng, const uint32_t *__restrict__ svals,
     const SplatRec *__restrict__ rec, int tiles_x, int tpv, int W, int H, uint32_t n_tiles, int n_chunks,
     float thr, float thr_cull, int no_cull, const float *__restrict__ gimg, float4 *__restrict__ partials) {
-  __shared__ float4 s_g4_all[TPB][kTS * kTS / 4];
+  // per pixel: g = dL/dI and g cc (cc: column relative to the quadrant
+  // centre), so the row loop accumulates with three FMAs per pixel
+  __shared__ float4 s_g4_all[TPB][2][kTS * kTS / 4];
   __shared__ float4 s_cw_all[TPB][kWave + 1];
   __shared__ float2 s_xy_all[TPB][kWave + 1];
   __shared__ uint8_t s_cat_all[TPB][4 * kWave];
   const int wid = threadIdx.x / kWave;
-  float4 *s_g4 = s_g4_all[wid];
+  float4 *s_g4 = s_g4_all[wid][0];
   float *s_g = reinterpret_cast<float *>(s_g4);
   float4 *s_cw = s_cw_all[wid];
   float2 *s_xy = s_xy_all[wid];
@@ -614,7 +616,10 @@ __global__ __launch_bounds__(kWave * TPB) __attribute__((amdgpu_waves_per_eu(8, 
   for (int p = lane; p < kTS * kTS; p += kWave) {
     const int x = tx * kTS + (p & (kTS - 1));
     const int y = ty * kTS + (p >> 4);
-    s_g[p] = (x < W && y < H) ? gv[uint64_t(y) * W + x] : 0.f;
+    const float g = (x < W && y < H) ? gv[uint64_t(y) * W + x] : 0.f;
+    const float cc = float(p & 7) - 3.5f;
+    s_g[p] = g;
+    s_g[kTS * kTS + p] = g * cc;
   }
   if (lane == 0) set_null_record(s_cw, s_xy);
   wave_lds_sync();
@@ -677,35 +682,44 @@ __global__ __launch_bounds__(kWave * TPB) __attribute__((amdgpu_waves_per_eu(8, 
       const float m2aqx = -2.f * c.x * qx;
       const float aqx2 = c.x * qx * qx;
       const float mbqx = -c.y * qx;
-      float S0 = 0.f, Sc = 0.f, Scc = 0.f, Sr = 0.f, Scr = 0.f, Srr = 0.f;
+      // per column: A = sum over rows of g e; per row: sum over columns of
+      // g e and of g e cc, folded into the row moments
+      float A[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      float Sr = 0.f, Scr = 0.f, Srr = 0.f;
 #pragma unroll 1
       for (int row = 0; row < nrows; ++row) {
         const float rr = rr0 + float(row);
         const float dy = rr - qy;
         const float brow = fmaf(c.y, dy, m2aqx);
         const float drow = fmaf(dy, fmaf(c.z, dy, mbqx), aqx2);
-        float R0 = 0.f, R1 = 0.f, R2 = 0.f;
+        float R0 = 0.f, R1 = 0.f;
 #pragma unroll
         for (int qd = 0; qd < 2; ++qd) {
-          const float4 gq = g4q[row * (kTS / 4) + qd];
-          const float gcol[4] = {gq.x, gq.y, gq.z, gq.w};
+          const float4 g0 = g4q[row * (kTS / 4) + qd];
+          const float4 g1 = g4q[kTS * kTS / 4 + row * (kTS / 4) + qd];
+          const float G0[4] = {g0.x, g0.y, g0.z, g0.w};
+          const float G1[4] = {g1.x, g1.y, g1.z, g1.w};
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const float cc = float(qd * 4 + u) - 3.5f;
             const float arg = fmaf(cc, fmaf(c.x, cc, brow), drow);
-            const float ex = __builtin_amdgcn_exp2f(arg);
-            const float ge = ((arg >= thr) ? gcol[u] : 0.f) * ex;
-            R0 += ge;
-            R1 = fmaf(ge, cc, R1);
-            R2 = fmaf(ge, cc * cc, R2);
+            const float ex = (arg >= thr) ? __builtin_amdgcn_exp2f(arg) : 0.f;
+            A[qd * 4 + u] = fmaf(G0[u], ex, A[qd * 4 + u]);
+            R0 = fmaf(G0[u], ex, R0);
+            R1 = fmaf(G1[u], ex, R1);
           }
         }
-        S0 += R0;
-        Sc += R1;
-        Scc += R2;
         Sr = fmaf(R0, rr, Sr);
         Scr = fmaf(R1, rr, Scr);
         Srr = fmaf(R0, rr * rr, Srr);
+      }
+      float S0 = 0.f, Sc = 0.f, Scc = 0.f;
+#pragma unroll
+      for (int col = 0; col < 8; ++col) {
+        const float cc = float(col) - 3.5f;
+        S0 += A[col];
+        Sc = fmaf(A[col], cc, Sc);
+        Scc = fmaf(A[col], cc * cc, Scc);
       }
       // moments about the Gaussian centre: dx = cc - qx, dy = rr - qy
       float M[6];
