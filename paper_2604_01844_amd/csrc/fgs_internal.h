@@ -18,7 +18,14 @@ namespace fgs {
 // kernels: 16 when a call has enough tiles to give every CU several
 // workgroups (which is what lets a CU hold enough waves), fewer for small
 // calls (one view, a crop) so that their waves spread over all CUs.
-inline int tiles_per_block(uint64_t n_tiles) { return n_tiles >= 16384 ? 16 : (n_tiles >= 4096 ? 4 : 1); }
+// A workgroup's LDS is released only when all its waves are done, so a wave
+// that finishes its tile early leaves its slot idle until the workgroup's
+// longest tile ends. small_blocks = true caps large calls at 4 tiles per
+// workgroup: this pays where tile lists are long and uneven, and costs a
+// little (more workgroups to dispatch) where they are short.
+inline int tiles_per_block(uint64_t n_tiles, bool small_blocks = false) {
+  return n_tiles >= 16384 ? (small_blocks ? 4 : 16) : (n_tiles >= 4096 ? 4 : 1);
+}
 
 // Waves per tile: a call with few tiles (one view, a crop) splits each
 // tile's list over several waves (strided batches), so that the longest
@@ -59,10 +66,10 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t n) {
   return x * base + (x < rem ? x : rem) + q;
 }
 
-// Calls f(std::integral_constant<int, TPB>) with TPB = tiles_per_block(n_tiles).
+// Calls f(std::integral_constant<int, TPB>) with TPB = tiles_per_block(n_tiles, small_blocks).
 template <typename F>
-void with_tiles_per_block(uint64_t n_tiles, F &&f) {
-  switch (tiles_per_block(n_tiles)) {
+void with_tiles_per_block(uint64_t n_tiles, F &&f, bool small_blocks = false) {
+  switch (tiles_per_block(n_tiles, small_blocks)) {
     case 16: f(std::integral_constant<int, 16>()); break;
     case 4: f(std::integral_constant<int, 4>()); break;
     default: f(std::integral_constant<int, 1>()); break;

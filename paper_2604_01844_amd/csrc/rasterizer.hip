@@ -357,6 +357,14 @@ __device__ __forceinline__ void build_quad_lists(uint32_t mask, int lane, uint8_
 // the iterations are all-interior and the kernel gets ~8% slower; at about
 // 180 (500k Gaussians, 2048^2 views) 77% are, and it gets 7% faster.
 constexpr float kInteriorSlack = 0.999f;
+
+// Workgroup size of the splat kernels in large calls. The backward takes 4
+// tiles per workgroup always; the forward does when a call averages at least
+// kSmallBlockKeysPerTile keys per tile. Measured on MI355X: the backward is
+// 2% faster with 4 at about 720 keys per tile (75 views of 512^2, 50k
+// Gaussians) and 11% at about 5,700 (10 views of 2048^2, 500k Gaussians);
+// the forward is 3% slower with 4 at 720 and 13% faster at 5,700.
+constexpr uint64_t kSmallBlockKeysPerTile = 2048;
 constexpr uint64_t kInteriorKeysPerRecord = 48;
 
 __device__ __forceinline__ uint32_t quad_interior(const float4 &c, float u, float v, float tx0, float ty0,
@@ -1575,7 +1583,7 @@ extern "C" int fgs_project_views_fwd(const fgs_gaussians *g, const fgs_geom *geo
         splat_fwd_kernel<false, false, TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
             at<uint2>(b, L.rng), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
             uint32_t(L.T), chunks, thr, thr * kCullSlack, thr * kInteriorSlack, no_cull, part, nullptr);
-    });
+    }, L.K >= kSmallBlockKeysPerTile * L.T);
     FGS_LAUNCH_CHECK("splat_fwd_kernel");
   }
   if (chunks > 1) {
@@ -1621,7 +1629,7 @@ extern "C" int fgs_project_views_support(const fgs_gaussians *g, const fgs_geom 
     splat_fwd_kernel<true, false, TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
         at<uint2>(b, L.rng), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
         uint32_t(L.T), chunks, thr, thr * kCullSlack, thr * kInteriorSlack, 0, nullptr, cnt);
-  });
+  }, L.K >= kSmallBlockKeysPerTile * L.T);
   FGS_LAUNCH_CHECK("splat_fwd_kernel<count>");
   return FGS_OK;
 }
@@ -1699,7 +1707,7 @@ extern "C" int fgs_project_views_bwd(const fgs_gaussians *g, const fgs_geom *geo
           at<uint2>(b, L.rng), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
           uint32_t(L.T), chunks, thr, thr * kCullSlack, (opts->ablate & FGS_ABLATE_QUADRANT_CULL) ? 1 : 0,
           grad_img, at<float4>(b, L.partials));
-    });
+    }, true);
     FGS_LAUNCH_CHECK("splat_bwd_kernel");
   }
   if (ev) FGS_HIP(hipEventRecord(ev[1], s));
