@@ -1172,8 +1172,16 @@ __global__ __launch_bounds__(kWave * TPB) void splat_bwd_exact_kernel(
     float tot[kExactSums];
 #pragma unroll
     for (int k = 0; k < kExactSums; ++k) tot[k] = 0.f;
-    for (int base = 0; base < n_pairs; base += kWave) {
-      const int idx = base + lane;
+    for (int base = 0; base < n_pairs;) {
+      // the last partial round spreads each pair's rows over 2, 4 or 8 lanes,
+      // as in the splat backward
+      const int rem = n_pairs - base;
+      const int lg = rem > 32 ? 0 : rem > 16 ? 1 : rem > 8 ? 2 : 3;
+      const int P = kWave >> lg;
+      const int nrows = 8 >> lg;
+      const int row0 = (lane >> (6 - lg)) * nrows;
+      const float rr0 = float(row0) - 3.5f;
+      const int idx = base + (lane & (P - 1));
       int Q = 0, j = kWave;
       if (idx < n_pairs) {
         const int ent = s_cat[idx];
@@ -1182,15 +1190,15 @@ __global__ __launch_bounds__(kWave * TPB) void splat_bwd_exact_kernel(
       }
       const float ox = float(tx * kTS + (Q & 1) * 8) + 4.f;
       const float oy = float(ty * kTS + (Q >> 1) * 8) + 4.f;
-      const float4 *g4q = s_g4 + (Q >> 1) * 8 * (kTS / 4) + (Q & 1) * 2;
+      const float4 *g4q = s_g4 + ((Q >> 1) * 8 + row0) * (kTS / 4) + (Q & 1) * 2;
       const float4 ra = s_a[j], rb = s_b[j], rc = s_c[j];
       const float qx = ra.x - ox, qy = ra.y - oy;
       float Sw = 0.f, Se = 0.f;
       float a0 = 0.f, ac = 0.f, acc2 = 0.f, ar = 0.f, acr = 0.f, arr = 0.f;
       float b0s = 0.f, bc = 0.f, bcc = 0.f, br = 0.f, bcr = 0.f, brr = 0.f;
 #pragma unroll 1
-      for (int row = 0; row < 8; ++row) {
-        const float rr = float(row) - 3.5f;
+      for (int row = 0; row < nrows; ++row) {
+        const float rr = rr0 + float(row);
         const float dy = rr - qy;
         const float Krow1 = 2.f * ra.w * dy, Krow0 = rb.x * dy * dy;
         const float Crow1 = 2.f * rc.y * dy, Crow0 = rc.z * dy * dy;
@@ -1245,10 +1253,15 @@ __global__ __launch_bounds__(kWave * TPB) void splat_bwd_exact_kernel(
       M[10] = fmaf(qx * qx, b0s, fmaf(-2.f * qx, bc, bcc));
       M[11] = fmaf(qx * qy, b0s, fmaf(-qy, bc, fmaf(-qx, br, bcr)));
       M[12] = fmaf(qy * qy, b0s, fmaf(-2.f * qy, br, brr));
+      for (int off = kWave / 2; off >= P; off >>= 1) {
+        const int src = (lane + off) & (kWave - 1);
+#pragma unroll
+        for (int k = 0; k < kExactSums; ++k) M[k] += bperm(src, M[k]);
+      }
 #pragma unroll
       for (int QQ = 0; QQ < 4; ++QQ) {
         const int rel = int((gpk >> (8 * QQ)) & 255u) - base;
-        const bool mine = ((mask >> QQ) & 1u) && rel >= 0 && rel < kWave;
+        const bool mine = ((mask >> QQ) & 1u) && rel >= 0 && rel < P;
         if (__ballot(mine) == 0ull) continue;
         const int src = mine ? rel : 0;
 #pragma unroll
@@ -1257,6 +1270,7 @@ __global__ __launch_bounds__(kWave * TPB) void splat_bwd_exact_kernel(
           tot[k] += mine ? v : 0.f;
         }
       }
+      base += P;
     }
     if (uint32_t(lane) < m) {
       float4 *o = partials + 4 * uint64_t(slot);
@@ -1672,7 +1686,7 @@ extern "C" int fgs_project_views_bwd(const fgs_gaussians *g, const fgs_geom *geo
         splat_bwd_exact_kernel<TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
             at<uint2>(b, L.rng), sv, at<ExactRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
             uint32_t(L.T), chunks, thr, thr * kCullSlack, cam, grad_img, at<float4>(b, L.partials));
-      });
+      }, true);
       FGS_LAUNCH_CHECK("splat_bwd_exact_kernel");
     }
     if (ev) FGS_HIP(hipEventRecord(ev[1], s));
