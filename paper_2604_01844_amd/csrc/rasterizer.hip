@@ -434,6 +434,23 @@ struct BatchPrefetch {
   }
 };
 
+// Work order of a view's tiles in the backward kernels: strips of four tile
+// rows, taken column by column, so consecutive work units (a workgroup's
+// tiles) cover 4x4 blocks of tiles instead of pieces of one row.
+// Neighbouring tiles have similar list lengths (the waves of a workgroup
+// finish closer together) and share records. A bijection of
+// [0, tiles_x * tiles_y) for any detector size; the last strip may be lower
+// than four rows. Measured on MI355X (standard scan, 75 views of 512^2): the
+// splat backward 6% faster; the splat forward 19% slower with the same order,
+// so the forward kernels keep row-major order.
+__device__ __forceinline__ void tile_of(uint32_t k, int tiles_x, int tiles_y, int &tx, int &ty) {
+  const int s = int(k) / (4 * tiles_x);
+  const int h = min(4, tiles_y - 4 * s);
+  const int r = int(k) - s * 4 * tiles_x;
+  tx = r / h;
+  ty = 4 * s + (r - tx * h);
+}
+
 // Slot kWave of the LDS record arrays holds a record that contributes nothing
 // anywhere (zero weight, support far outside every tile).
 __device__ __forceinline__ void set_null_record(float4 *s_cw, float2 *s_xy) {
@@ -469,6 +486,7 @@ __global__ __launch_bounds__(kWave * TPB) void splat_fwd_kernel(const uint2 *__r
   const uint32_t t = tile - v_local * uint32_t(tpv);
   const int ty = int(t) / tiles_x;
   const int tx = int(t) - ty * tiles_x;
+  const uint32_t rt = tile;
   const int lane = threadIdx.x & (kWave - 1);
   // 16-lane group grp owns quadrant grp; each lane a column of 4 pixels in it
   const int grp = lane >> 4;
@@ -482,7 +500,7 @@ __global__ __launch_bounds__(kWave * TPB) void splat_fwd_kernel(const uint2 *__r
   float acc[kRows];
 #pragma unroll
   for (int k = 0; k < kRows; ++k) acc[k] = 0.f;
-  const uint32_t b0 = rng[tile].x, e = rng[tile].y;
+  const uint32_t b0 = rng[rt].x, e = rng[rt].y;
   const uint32_t stride = kWave * uint32_t(n_chunks);
   BatchPrefetch<SplatRec> pf;
   pf.start(svals, rec, b0 + chunk * kWave, stride, e, lane);
@@ -617,8 +635,9 @@ __global__ __launch_bounds__(kWave * TPB) __attribute__((amdgpu_waves_per_eu(8, 
   const uint32_t chunk = unit - tile * uint32_t(n_chunks);
   const uint32_t v_local = tile / uint32_t(tpv);
   const uint32_t t = tile - v_local * uint32_t(tpv);
-  const int ty = int(t) / tiles_x;
-  const int tx = int(t) - ty * tiles_x;
+  int tx, ty;
+  tile_of(t, tiles_x, tpv / tiles_x, tx, ty);
+  const uint32_t rt = v_local * uint32_t(tpv) + uint32_t(ty * tiles_x + tx);
   const int lane = threadIdx.x & (kWave - 1);
   const float *gv = gimg + uint64_t(v_local) * uint64_t(W) * uint64_t(H);
   for (int p = lane; p < kTS * kTS; p += kWave) {
@@ -633,7 +652,7 @@ __global__ __launch_bounds__(kWave * TPB) __attribute__((amdgpu_waves_per_eu(8, 
   wave_lds_sync();
   const float tx0 = float(tx * kTS) + 0.5f, ty0 = float(ty * kTS) + 0.5f;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const uint32_t b0 = rng[tile].x, e = rng[tile].y;
+  const uint32_t b0 = rng[rt].x, e = rng[rt].y;
   for (uint32_t b = b0 + chunk * kWave; b < e; b += kWave * uint32_t(n_chunks)) {
     const uint32_t m = min(uint32_t(kWave), e - b);
     uint32_t mask = 0, slot = 0;
@@ -1014,6 +1033,7 @@ __global__ __launch_bounds__(kWave * TPB) void splat_fwd_exact_kernel(
   const uint32_t t = tile - v_local * uint32_t(tpv);
   const int ty = int(t) / tiles_x;
   const int tx = int(t) - ty * tiles_x;
+  const uint32_t rt = tile;
   const int lane = threadIdx.x & (kWave - 1);
   const int grp = lane >> 4;
   const int sub = lane & 15;
@@ -1029,7 +1049,7 @@ __global__ __launch_bounds__(kWave * TPB) void splat_fwd_exact_kernel(
   float acc[kRows];
 #pragma unroll
   for (int k = 0; k < kRows; ++k) acc[k] = 0.f;
-  const uint32_t b0 = rng[tile].x, e = rng[tile].y;
+  const uint32_t b0 = rng[rt].x, e = rng[rt].y;
   for (uint32_t b = b0 + chunk * kWave; b < e; b += kWave * uint32_t(n_chunks)) {
     const uint32_t m = min(uint32_t(kWave), e - b);
     uint32_t mask = 0;
@@ -1129,8 +1149,9 @@ __global__ __launch_bounds__(kWave * TPB) void splat_bwd_exact_kernel(
   const uint32_t chunk = unit - tile * uint32_t(n_chunks);
   const uint32_t v_local = tile / uint32_t(tpv);
   const uint32_t t = tile - v_local * uint32_t(tpv);
-  const int ty = int(t) / tiles_x;
-  const int tx = int(t) - ty * tiles_x;
+  int tx, ty;
+  tile_of(t, tiles_x, tpv / tiles_x, tx, ty);
+  const uint32_t rt = v_local * uint32_t(tpv) + uint32_t(ty * tiles_x + tx);
   const int lane = threadIdx.x & (kWave - 1);
   const float *gv = gimg + uint64_t(v_local) * uint64_t(W) * uint64_t(H);
   for (int p = lane; p < kTS * kTS; p += kWave) {
@@ -1144,7 +1165,7 @@ __global__ __launch_bounds__(kWave * TPB) void splat_bwd_exact_kernel(
   wave_lds_sync();
   const float tx0 = float(tx * kTS) + 0.5f, ty0 = float(ty * kTS) + 0.5f;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const uint32_t b0 = rng[tile].x, e = rng[tile].y;
+  const uint32_t b0 = rng[rt].x, e = rng[rt].y;
   for (uint32_t b = b0 + chunk * kWave; b < e; b += kWave * uint32_t(n_chunks)) {
     const uint32_t m = min(uint32_t(kWave), e - b);
     uint32_t mask = 0, slot = 0;
