@@ -469,12 +469,13 @@ __global__ __launch_bounds__(kWave * TPB) void splat_fwd_kernel(const uint2 *__r
                                                            float thr_cull, float thr_int, int no_cull,
                                                            float *__restrict__ img,
                                                            unsigned long long *__restrict__ counter) {
-  __shared__ float4 s_cw_all[TPB][kWave + 1];
-  __shared__ float2 s_xy_all[TPB][kWave + 1];
+  // per batch slot: the conic and weight, and (centre, 2 c11): one address,
+  // the second array at a fixed offset from the first
+  __shared__ float4 s_rec_all[TPB][2][kWave + 1];
   __shared__ uint8_t s_list_all[TPB][4][kWave];
   const int wid = threadIdx.x / kWave;
-  float4 *s_cw = s_cw_all[wid];
-  float2 *s_xy = s_xy_all[wid];
+  float4 *s_cw = s_rec_all[wid][0];
+  float4 *s_xy = s_rec_all[wid][1];
   uint8_t(*s_list)[kWave] = s_list_all[wid];
   // work unit = (tile, chunk): chunk c takes batches c, c + n_chunks, ... of
   // the tile's list and writes its own partial image (n_chunks > 1)
@@ -496,7 +497,10 @@ __global__ __launch_bounds__(kWave * TPB) void splat_fwd_kernel(const uint2 *__r
   const float px = float(tx * kTS + col) + 0.5f;
   const float py = float(ty * kTS + row0) + 0.5f;
   const float tx0 = float(tx * kTS) + 0.5f, ty0 = float(ty * kTS) + 0.5f;
-  if (lane == 0) set_null_record(s_cw, s_xy);
+  if (lane == 0) {
+    s_cw[kWave] = make_float4(-1.f, 0.f, -1.f, 0.f);
+    s_xy[kWave] = make_float4(-1.0e4f, -1.0e4f, -2.f, 0.f);
+  }
   float acc[kRows];
 #pragma unroll
   for (int k = 0; k < kRows; ++k) acc[k] = 0.f;
@@ -514,7 +518,7 @@ __global__ __launch_bounds__(kWave * TPB) void splat_fwd_kernel(const uint2 *__r
       const float4 c = make_float4(ra.z, ra.w, rb.x, rb.y);
       const float2 q = make_float2(ra.x, ra.y);
       s_cw[lane] = c;
-      s_xy[lane] = q;
+      s_xy[lane] = make_float4(q.x, q.y, 2.f * c.z, 0.f);
       mask = no_cull ? 0xFu : quad_mask(c, q.x, q.y, tx0, ty0, thr_cull);
       if (kInterior && !kCount) imask = quad_interior(c, q.x, q.y, tx0, ty0, thr_int) & mask;
     }
@@ -525,21 +529,24 @@ __global__ __launch_bounds__(kWave * TPB) void splat_fwd_kernel(const uint2 *__r
       int pos[4];
       build_quad_lists(mask, lane, s_list, nq, pos);
     }
-    const int n_me = (grp == 0) ? nq[0] : (grp == 1) ? nq[1] : (grp == 2) ? nq[2] : nq[3];
     const int n_max = max(max(nq[0], nq[1]), max(nq[2], nq[3]));
+    // the shorter lists are padded to n_max with the null slot
+#pragma unroll
+    for (int Q = 0; Q < 4; ++Q)
+      if (lane >= nq[Q] && lane < n_max) s_list[Q][lane] = uint8_t(kWave);
     // iterations in which every group's pair is interior skip the cutoff test
     const int n_fast = (kInterior && !kCount) ? min(min(ni[0], ni[1]), min(ni[2], ni[3])) : 0;
     wave_lds_sync();
     for (int i = 0; i < n_fast; ++i) {
       const int j = int(s_list[grp][i]);
       const float4 c = s_cw[j];
-      const float2 q = s_xy[j];
+      const float4 q = s_xy[j];
       const float dx = px - q.x;
       const float dy = py - q.y;
       const float A = c.x * dx * dx;
       const float B = c.y * dx;
       const float arg0 = fmaf(dy, fmaf(c.z, dy, B), A);
-      const float E = fmaf(2.f * c.z, dy, B);
+      const float E = fmaf(q.z, dy, B);
 #pragma unroll
       for (int k = 0; k < kRows; ++k) {
         const float fk = float(k);
@@ -548,9 +555,9 @@ __global__ __launch_bounds__(kWave * TPB) void splat_fwd_kernel(const uint2 *__r
       }
     }
     for (int i = n_fast; i < n_max; ++i) {
-      const int j = (i < n_me) ? int(s_list[grp][i]) : kWave;
+      const int j = int(s_list[grp][i]);
       const float4 c = s_cw[j];
-      const float2 q = s_xy[j];
+      const float4 q = s_xy[j];
       const float dx = px - q.x;
       const float dy = py - q.y;
       const float A = c.x * dx * dx;
@@ -558,7 +565,7 @@ __global__ __launch_bounds__(kWave * TPB) void splat_fwd_kernel(const uint2 *__r
       // exponent down the lane's column, expanded about its first pixel:
       // arg(dy + k) = arg0 + k (2 c.z dy + B) + c.z k^2
       const float arg0 = fmaf(dy, fmaf(c.z, dy, B), A);
-      const float E = fmaf(2.f * c.z, dy, B);
+      const float E = fmaf(q.z, dy, B);
 #pragma unroll
       for (int k = 0; k < kRows; ++k) {
         const float fk = float(k);
