@@ -1071,11 +1071,13 @@ __global__ __launch_bounds__(kWave * TPB) void splat_fwd_exact_kernel(
     }
     int nq[4], pos[4];
     build_quad_lists(mask, lane, s_list, nq, pos);
-    const int n_me = (grp == 0) ? nq[0] : (grp == 1) ? nq[1] : (grp == 2) ? nq[2] : nq[3];
     const int n_max = max(max(nq[0], nq[1]), max(nq[2], nq[3]));
+#pragma unroll
+    for (int Q = 0; Q < 4; ++Q)
+      if (lane >= nq[Q] && lane < n_max) s_list[Q][lane] = uint8_t(kWave);
     wave_lds_sync();
     for (int i = 0; i < n_max; ++i) {
-      const int j = (i < n_me) ? int(s_list[grp][i]) : kWave;
+      const int j = int(s_list[grp][i]);
       const float4 ra = s_a[j], rb = s_b[j], rc = s_c[j];
       const float w = s_w[j];
       const float dx = px - ra.x;
