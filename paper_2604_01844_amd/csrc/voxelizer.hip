@@ -345,9 +345,11 @@ __global__ __launch_bounds__(kWave * TPB) void vox_fwd_kernel(const uint32_t *__
 // Backward over one 8^3 tile: lane j owns pair (tile, list[j]) and sums the
 // ten moments over the 512 voxels. Coordinates are relative to the tile
 // centre, (cx, cy, cz) in {-3.5, ..., 3.5}; along each x-row the exponent is
-// a quadratic in cx with lane coefficients, and the moments are accumulated
-// against the constants cx, cx^2, then moved to the Gaussian's centre once
-// per pair. Branch-free loop body.
+// a quadratic in cx with lane coefficients. The tile's g and g cx are staged
+// in LDS, and each voxel adds g e into its column's sum (over y and z) and
+// into the row's sums of g e and g e cx (three FMAs); the x-moments follow
+// from the column sums, the others from the row sums, and all are moved to
+// the Gaussian's centre once per pair. Branch-free loop body.
 template <int TPB>
 __global__ __launch_bounds__(kWave * TPB) void vox_bwd_kernel(const uint32_t *__restrict__ start,
                                                          const uint32_t *__restrict__ svals,
@@ -358,10 +360,11 @@ __global__ __launch_bounds__(kWave * TPB) void vox_bwd_kernel(const uint32_t *__
                                                          GridDev G, uint32_t n_tiles, int n_chunks, float thr,
                                                          const float *__restrict__ gvol,
                                                          float2 *__restrict__ partials) {
-  __shared__ float4 s_g4_all[TPB][kVT * kVT * kVT / 4];
+  __shared__ float4 s_g4_all[TPB][2][kVT * kVT * kVT / 4];
   const int wid = threadIdx.x / kWave;
-  float4 *s_g4 = s_g4_all[wid];
+  float4 *s_g4 = s_g4_all[wid][0];
   float *s_g = reinterpret_cast<float *>(s_g4);
+  const float h = 0.5f * (kVT - 1);
   // work unit = (tile, chunk): chunk c takes batches c, c + n_chunks, ...
   // (the natural block order: the XCD-aware one measured 4% slower here)
   const uint32_t unit = blockIdx.x * TPB + wid;
@@ -375,13 +378,14 @@ __global__ __launch_bounds__(kWave * TPB) void vox_bwd_kernel(const uint32_t *__
   const int lane = threadIdx.x & (kWave - 1);
   for (int q = lane; q < kVT * kVT * kVT; q += kWave) {
     const int x = tx * kVT + (q & 7), y = ty * kVT + ((q >> 3) & 7), z = tz * kVT + (q >> 6);
-    s_g[q] = (x < G.dims[0] && y < G.dims[1] && z < G.dims[2])
-                 ? gvol[(uint64_t(z) * G.dims[1] + y) * uint64_t(G.dims[0]) + x]
-                 : 0.f;
+    const float g = (x < G.dims[0] && y < G.dims[1] && z < G.dims[2])
+                        ? gvol[(uint64_t(z) * G.dims[1] + y) * uint64_t(G.dims[0]) + x]
+                        : 0.f;
+    s_g[q] = g;
+    s_g[kVT * kVT * kVT + q] = g * (float(q & 7) - h);
   }
   wave_lds_sync();
   const uint32_t b0 = start[tile], e = start[tile + 1];
-  const float h = 0.5f * (kVT - 1);
   const float ox = float(tx * kVT) + h, oy = float(ty * kVT) + h, oz = float(tz * kVT) + h;
   for (uint32_t b = b0 + chunk * kWave; b < e; b += kWave * uint32_t(n_chunks)) {
     const uint32_t k = b + lane;
@@ -398,8 +402,10 @@ __global__ __launch_bounds__(kWave * TPB) void vox_bwd_kernel(const uint32_t *__
     const float qx = p.x - ox, qy = p.y - oy, qz = p.z - oz;
     const float m2aqx = -2.f * c0.x * qx;
     const float aqx2 = c0.x * qx * qx;
-    float S0 = 0.f, Sc = 0.f, Scc = 0.f, Sy = 0.f, Sz = 0.f;
-    float Sxy = 0.f, Sxz = 0.f, Syy = 0.f, Syz = 0.f, Szz = 0.f;
+    float A[kVT];
+#pragma unroll
+    for (int u = 0; u < kVT; ++u) A[u] = 0.f;
+    float Sy = 0.f, Sz = 0.f, Sxy = 0.f, Sxz = 0.f, Syy = 0.f, Syz = 0.f, Szz = 0.f;
     for (int zz = 0; zz < kVT; ++zz) {
       const float cz = float(zz) - h;
       const float dz = cz - qz;
@@ -412,25 +418,23 @@ __global__ __launch_bounds__(kWave * TPB) void vox_bwd_kernel(const uint32_t *__
         const float brow = lin + m2aqx;
         const float drow = fmaf(-lin, qx, aqx2 + Cc);
         const float4 *g4 = s_g4 + (zz * kVT + yy) * (kVT / 4);
-        float R0 = 0.f, R1 = 0.f, R2 = 0.f;
+        float R0 = 0.f, R1 = 0.f;
 #pragma unroll
         for (int qd = 0; qd < kVT / 4; ++qd) {
-          const float4 gq = g4[qd];
-          const float gcol[4] = {gq.x, gq.y, gq.z, gq.w};
+          const float4 g0 = g4[qd];
+          const float4 g1 = g4[kVT * kVT * kVT / 4 + qd];
+          const float G0[4] = {g0.x, g0.y, g0.z, g0.w};
+          const float G1[4] = {g1.x, g1.y, g1.z, g1.w};
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const float cx = float(qd * 4 + u) - h;
             const float arg = fmaf(cx, fmaf(c0.x, cx, brow), drow);
-            const float ex = __builtin_amdgcn_exp2f(arg);
-            const float ge = ((arg >= thr) ? gcol[u] : 0.f) * ex;
-            R0 += ge;
-            R1 = fmaf(ge, cx, R1);
-            R2 = fmaf(ge, cx * cx, R2);
+            const float ex = (arg >= thr) ? __builtin_amdgcn_exp2f(arg) : 0.f;
+            A[qd * 4 + u] = fmaf(G0[u], ex, A[qd * 4 + u]);
+            R0 = fmaf(G0[u], ex, R0);
+            R1 = fmaf(G1[u], ex, R1);
           }
         }
-        S0 += R0;
-        Sc += R1;
-        Scc += R2;
         Sy = fmaf(R0, cy, Sy);
         Sz = fmaf(R0, cz, Sz);
         Sxy = fmaf(R1, cy, Sxy);
@@ -440,6 +444,14 @@ __global__ __launch_bounds__(kWave * TPB) void vox_bwd_kernel(const uint32_t *__
         Syz = fmaf(R0y, cz, Syz);
         Szz = fmaf(R0 * cz, cz, Szz);
       }
+    }
+    float S0 = 0.f, Sc = 0.f, Scc = 0.f;
+#pragma unroll
+    for (int u = 0; u < kVT; ++u) {
+      const float cx = float(u) - h;
+      S0 += A[u];
+      Sc = fmaf(A[u], cx, Sc);
+      Scc = fmaf(A[u], cx * cx, Scc);
     }
     if (active) {
       // moments about the Gaussian centre: d = c - q
