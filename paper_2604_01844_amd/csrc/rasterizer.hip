@@ -265,20 +265,43 @@ __global__ __launch_bounds__(256) void zero_ranges_kernel(uint2 *__restrict__ rn
 // rng[v * tpv + t] = [first, last + 1) of key (v << tile_bits | t) in the
 // sorted keys; each key's pairs are contiguous there (tiles without pairs
 // keep the empty range the zero kernel wrote).
-// Each key is loaded once; its neighbours come from the adjacent lanes (the
-// wave's first and last lanes load theirs).
+// A wave takes kRangeItems * 64 consecutive keys, all loads issued first, and
+// finds each key's neighbours in the adjacent lanes (across rounds through
+// lanes 0 and 63); only the keys just outside its span are loaded twice.
+constexpr int kRangeItems = 16;
+
 __global__ __launch_bounds__(256) void ranges_kernel(const uint32_t *__restrict__ skeys, uint64_t K, int tile_bits,
                                                      uint32_t tpv, uint2 *__restrict__ rng) {
-  const uint64_t k = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & (kWave - 1);
-  const uint32_t key = k < K ? skeys[k] : 0u;
-  uint32_t prev = __shfl_up(key, 1, kWave), next = __shfl_down(key, 1, kWave);
-  if (k >= K) return;
-  if (lane == 0) prev = k > 0 ? skeys[k - 1] : ~key;
-  if (lane == kWave - 1 || k + 1 == K) next = k + 1 < K ? skeys[k + 1] : ~key;
-  const uint32_t tile = (key >> tile_bits) * tpv + (key & ((1u << tile_bits) - 1u));
-  if (prev != key) rng[tile].x = uint32_t(k);
-  if (next != key) rng[tile].y = uint32_t(k + 1);
+  const uint64_t base = ((uint64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6) * uint64_t(kWave * kRangeItems);
+  if (base >= K) return;  // uniform over the wave
+  uint32_t key[kRangeItems];
+#pragma unroll
+  for (int j = 0; j < kRangeItems; ++j) {
+    const uint64_t k = base + uint64_t(j) * kWave + lane;
+    key[j] = k < K ? skeys[k] : 0u;
+  }
+  const uint64_t after = base + uint64_t(kWave * kRangeItems);
+  const uint32_t edge_prev = (lane == 0 && base > 0) ? skeys[base - 1] : 0u;
+  const uint32_t edge_next = (lane == kWave - 1 && after < K) ? skeys[after] : 0u;
+  const uint32_t tmask = (1u << tile_bits) - 1u;
+#pragma unroll
+  for (int j = 0; j < kRangeItems; ++j) {
+    const uint64_t k = base + uint64_t(j) * kWave + lane;
+    const uint32_t kv = key[j];
+    uint32_t prev = __shfl_up(kv, 1, kWave), next = __shfl_down(kv, 1, kWave);
+    const uint32_t prev_round = j > 0 ? uint32_t(__builtin_amdgcn_readlane(int(key[j > 0 ? j - 1 : 0]), kWave - 1)) : 0u;
+    const uint32_t next_round =
+        j + 1 < kRangeItems ? uint32_t(__builtin_amdgcn_readlane(int(key[j + 1 < kRangeItems ? j + 1 : j]), 0)) : 0u;
+    if (lane == 0) prev = j > 0 ? prev_round : (base > 0 ? edge_prev : ~kv);
+    if (lane == kWave - 1) next = j + 1 < kRangeItems ? next_round : edge_next;
+    if (k < K) {
+      if (k + 1 == K) next = ~kv;
+      const uint32_t tile = (kv >> tile_bits) * tpv + (kv & tmask);
+      if (prev != kv) rng[tile].x = uint32_t(k);
+      if (next != kv) rng[tile].y = uint32_t(k + 1);
+    }
+  }
 }
 
 // ---------------------------------------------------------------- quadrants
@@ -1566,7 +1589,9 @@ int build_lists(const fgs_gaussians *g, const fgs_geom *geom, int32_t view_begin
   zero_ranges_kernel<<<grid_for(T, 256), 256, 0, s>>>(at<uint2>(b, L.rng), T);
   FGS_LAUNCH_CHECK("zero_ranges_kernel");
   if (K > 0) {
-    ranges_kernel<<<grid_for(K, 256), 256, 0, s>>>(sk, K, tile_bits, uint32_t(tg.tpv), at<uint2>(b, L.rng));
+    const uint64_t waves = (K + uint64_t(kWave * kRangeItems) - 1) / uint64_t(kWave * kRangeItems);
+    ranges_kernel<<<grid_for(waves * kWave, 256), 256, 0, s>>>(sk, K, tile_bits, uint32_t(tg.tpv),
+                                                               at<uint2>(b, L.rng));
     FGS_LAUNCH_CHECK("ranges_kernel");
   }
   ws->kind = exact ? 3 : 1;
