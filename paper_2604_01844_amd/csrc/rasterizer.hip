@@ -244,8 +244,20 @@ __global__ __launch_bounds__(kEmitBlock) void emit_kernel(uint64_t R, int64_t n,
   if (t == 0) s_off[nr] = offset[r0 + nr];
   __syncthreads();
   const uint32_t o0 = s_off[0], oe = s_off[nr];
-  for (uint32_t q = o0 + t; q < oe; q += kEmitBlock) {
-    const int i = upper_index(s_off, nr, q);
+  // each wave writes a contiguous quarter of the block's keys, 64 at a time;
+  // a lane finds its first key's record by binary search, then walks forward
+  // (its keys ascend, and so do their records)
+  constexpr int kEmitWaves = kEmitBlock / 64;
+  const int wid = t >> 6, lane = t & 63;
+  const uint32_t span = oe - o0, per_wave = (span + kEmitWaves - 1) / kEmitWaves;
+  const uint32_t qa = o0 + min(span, uint32_t(wid) * per_wave);
+  const uint32_t qb = o0 + min(span, uint32_t(wid + 1) * per_wave);
+  int i = -1;
+  for (uint32_t q = qa + uint32_t(lane); q < qb; q += 64) {
+    if (i < 0)
+      i = upper_index(s_off, nr, q);
+    else
+      while (s_off[i + 1] <= q) ++i;  // s_off[nr] = oe > q ends the walk
     const ushort4 rc = s_rect[i];
     const uint32_t wdt = uint32_t(rc.z) - rc.x + 1u;
     const uint32_t j = q - s_off[i];
