@@ -444,7 +444,7 @@ __device__ __forceinline__ void build_quad_lists_split(uint32_t mask, uint32_t i
 // record) of a batch overlap the previous batch's arithmetic instead of
 // stalling the wave. Lane l holds entry l of its batches. The forward uses
 // it (3% faster on 512^2 views); in the backward the eight extra registers
-// spill under its 64-register budget and it got slower.
+// spilled and it got slower.
 template <typename Rec>
 struct BatchPrefetch {
   Rec cur, nxt;
@@ -651,9 +651,10 @@ __device__ __forceinline__ float bperm(int src_lane, float v) {
 // Gaussian's centre. The lane that loaded a record gathers its up to four
 // quadrant partials with wavefront permutes, in quadrant order, and writes
 // the pair's six sums to the pair's emission slot: no atomics, and the
-// summation order is fixed.
+// summation order is fixed. 72 registers (7 waves per SIMD): at 64 the
+// round loop spilled, and 72 measured 2% faster on 512^2 views.
 template <int TPB>
-__global__ __launch_bounds__(kWave * TPB) __attribute__((amdgpu_waves_per_eu(8, 8))) void splat_bwd_kernel(
+__global__ __launch_bounds__(kWave * TPB) __attribute__((amdgpu_waves_per_eu(7, 7))) void splat_bwd_kernel(
     const uint2 *__restrict__ rng, const uint32_t *__restrict__ svals,
     const SplatRec *__restrict__ rec, int tiles_x, int tpv, int W, int H, uint32_t n_tiles, int n_chunks,
     float thr, float thr_cull, int no_cull, const float *__restrict__ gimg, float4 *__restrict__ partials) {
