@@ -195,6 +195,47 @@ def test_binning_matches_integer_reference(fgs):
     assert covered == d["n_pairs"]
 
 
+@pytest.mark.parametrize("n, w, h, views, seed", [(1, 32, 32, 1, 21), (3, 48, 40, 2, 22), (40, 64, 64, 3, 23),
+                                                   (5000, 176, 144, 4, 24)])
+def test_binning_ranges_across_sizes(fgs, n, w, h, views, seed):
+    """Tile ranges, sorted keys and per-tile lists at sizes from a handful of
+    keys (one partial wave of the ranges and emit kernels) to many waves with
+    a ragged end, against the integer reference."""
+    gs = si.gaussians(n, seed)
+    gd = si.geometry(w, h)
+    ang = si.angles(views)
+    geom = fgs.Geometry.from_dict(gd, ang)
+    ws = fgs.Workspace(DEV)
+    fgs.project_views(*args(dev(gs)), geom, ws=ws)
+    torch.cuda.synchronize()
+    d = {k: (v.cpu().numpy() if torch.is_tensor(v) else v) for k, v in fgs.binning_dump(ws).items()}
+    rec = oracle.splat_records(gs, gd, ang)
+    r64 = 3.0 * np.sqrt(rec["shat"][:, [0, 2]])
+    b = oracle.bin_tiles(rec["uv"].astype(np.float32), r64.astype(np.float32), w, h, cull=rec["culled"],
+                         n_views=views)
+    amb = (_ambiguous(rec["uv"][:, 0], r64[:, 0]) | _ambiguous(rec["uv"][:, 1], r64[:, 1]))
+    amb_ids = set(np.nonzero(amb)[0].tolist())
+    tpv = -(-w // 16) * -(-h // 16)
+    tb = d["tile_bits"]
+    assert d["n_tiles"] == views * tpv
+    rng = d["tile_ranges"].astype(np.int64)
+    skeys = d["sorted_keys"].astype(np.int64)
+    covered = 0
+    for t in range(d["n_tiles"]):
+        v, tt = divmod(t, tpv)
+        lo, hi = rng[t]
+        assert 0 <= lo <= hi <= d["n_pairs"]
+        covered += hi - lo
+        assert np.all(skeys[lo:hi] == (v << tb) | tt)
+        gl = d["sorted_vals"][lo:hi].astype(np.int64)
+        assert np.all(np.diff(gl) > 0)
+        ol = b["sorted_vals"][b["tile_start"][t]:b["tile_start"][t + 1]]
+        assert [x for x in gl.tolist() if x not in amb_ids] == [x for x in ol.tolist() if x not in amb_ids], t
+    assert covered == d["n_pairs"]
+    if n == 5000:
+        assert d["n_pairs"] > 4 * 1024   # several waves of the ranges kernel
+
+
 def test_binning_covers_support(fgs):
     """Every FP64 support pair with d^2 <= 9 - 1e-3 is in a tile the GPU lists."""
     gs = si.gaussians(400, 10)
