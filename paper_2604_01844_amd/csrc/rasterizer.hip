@@ -47,7 +47,8 @@ namespace {
 
 constexpr int kTS = 16;          // tile side in pixels
 constexpr int kWave = 64;        // lanes per wave (gfx9 wave64)
-constexpr int kRows = 4;         // pixels per lane in the forward (a column of 4)
+constexpr int kRows = 4;         // pixels per lane (a column of 4): ray-exact forward, per-pixel ablation
+constexpr int kFwdRows = 8;      // pixels per lane in the splat forward (a quadrant column)
 // The quadrant culling test keeps pairs whose exponent reaches thr * kCullSlack
 // (a Mahalanobis radius 0.05% beyond the support), a superset of the per-pixel test.
 constexpr float kCullSlack = 1.001f;
@@ -524,11 +525,14 @@ __global__ __launch_bounds__(kWave * TPB) void splat_fwd_kernel(const uint2 *__r
   const int tx = int(t) - ty * tiles_x;
   const uint32_t rt = tile;
   const int lane = threadIdx.x & (kWave - 1);
-  // 16-lane group grp owns quadrant grp; each lane a column of 4 pixels in it
+  // 16-lane group grp owns quadrant grp. Its two 8-lane halves take two pairs
+  // of the quadrant's list at a time (entries i and i + 1), each lane a
+  // whole column of the quadrant (8 pixels); the halves' sums of the same
+  // pixels are added once at the end.
   const int grp = lane >> 4;
-  const int sub = lane & 15;
-  const int col = (grp & 1) * 8 + (sub & 7);
-  const int row0 = (grp >> 1) * 8 + (sub >> 3) * kRows;
+  const int half = (lane >> 3) & 1;
+  const int col = (grp & 1) * 8 + (lane & 7);
+  const int row0 = (grp >> 1) * 8;
   const float px = float(tx * kTS + col) + 0.5f;
   const float py = float(ty * kTS + row0) + 0.5f;
   const float tx0 = float(tx * kTS) + 0.5f, ty0 = float(ty * kTS) + 0.5f;
@@ -536,9 +540,9 @@ __global__ __launch_bounds__(kWave * TPB) void splat_fwd_kernel(const uint2 *__r
     s_cw[kWave] = make_float4(-1.f, 0.f, -1.f, 0.f);
     s_xy[kWave] = make_float4(-1.0e4f, -1.0e4f, -2.f, 0.f);
   }
-  float acc[kRows];
+  float acc[kFwdRows];
 #pragma unroll
-  for (int k = 0; k < kRows; ++k) acc[k] = 0.f;
+  for (int k = 0; k < kFwdRows; ++k) acc[k] = 0.f;
   const uint32_t b0 = rng[rt].x, e = rng[rt].y;
   const uint32_t stride = kWave * uint32_t(n_chunks);
   BatchPrefetch<SplatRec> pf;
@@ -565,15 +569,16 @@ __global__ __launch_bounds__(kWave * TPB) void splat_fwd_kernel(const uint2 *__r
       build_quad_lists(mask, lane, s_list, nq, pos);
     }
     const int n_max = max(max(nq[0], nq[1]), max(nq[2], nq[3]));
-    // the shorter lists are padded to n_max with the null slot
+    // the lists are padded with the null slot to n_max rounded up to even
+    const int n_pad = (n_max + 1) & ~1;
 #pragma unroll
     for (int Q = 0; Q < 4; ++Q)
-      if (lane >= nq[Q] && lane < n_max) s_list[Q][lane] = uint8_t(kWave);
-    // iterations in which every group's pair is interior skip the cutoff test
-    const int n_fast = (kInterior && !kCount) ? min(min(ni[0], ni[1]), min(ni[2], ni[3])) : 0;
+      if (lane >= nq[Q] && lane < n_pad) s_list[Q][lane] = uint8_t(kWave);
+    // iterations in which every group's two pairs are interior skip the cutoff test
+    const int n_fast = (kInterior && !kCount) ? (min(min(ni[0], ni[1]), min(ni[2], ni[3])) & ~1) : 0;
     wave_lds_sync();
-    for (int i = 0; i < n_fast; ++i) {
-      const int j = int(s_list[grp][i]);
+    for (int i = 0; i < n_fast; i += 2) {
+      const int j = int(s_list[grp][i + half]);
       const float4 c = s_cw[j];
       const float4 q = s_xy[j];
       const float dx = px - q.x;
@@ -583,14 +588,14 @@ __global__ __launch_bounds__(kWave * TPB) void splat_fwd_kernel(const uint2 *__r
       const float arg0 = fmaf(dy, fmaf(c.z, dy, B), A);
       const float E = fmaf(q.z, dy, B);
 #pragma unroll
-      for (int k = 0; k < kRows; ++k) {
+      for (int k = 0; k < kFwdRows; ++k) {
         const float fk = float(k);
         const float arg = (k == 0) ? arg0 : fmaf(fk, fmaf(c.z, fk, E), arg0);
         acc[k] = fmaf(c.w, __builtin_amdgcn_exp2f(arg), acc[k]);
       }
     }
-    for (int i = n_fast; i < n_max; ++i) {
-      const int j = int(s_list[grp][i]);
+    for (int i = n_fast; i < n_max; i += 2) {
+      const int j = int(s_list[grp][i + half]);
       const float4 c = s_cw[j];
       const float4 q = s_xy[j];
       const float dx = px - q.x;
@@ -602,7 +607,7 @@ __global__ __launch_bounds__(kWave * TPB) void splat_fwd_kernel(const uint2 *__r
       const float arg0 = fmaf(dy, fmaf(c.z, dy, B), A);
       const float E = fmaf(q.z, dy, B);
 #pragma unroll
-      for (int k = 0; k < kRows; ++k) {
+      for (int k = 0; k < kFwdRows; ++k) {
         const float fk = float(k);
         const float arg = (k == 0) ? arg0 : fmaf(fk, fmaf(c.z, fk, E), arg0);
         if (kCount) {
@@ -617,9 +622,10 @@ __global__ __launch_bounds__(kWave * TPB) void splat_fwd_kernel(const uint2 *__r
   }
   const int x = tx * kTS + col;
   if (kCount) {
+    // both halves count their own pairs; the wave total is the tile's
     unsigned long long n = 0;
 #pragma unroll
-    for (int k = 0; k < kRows; ++k) {
+    for (int k = 0; k < kFwdRows; ++k) {
       const int y = ty * kTS + row0 + k;
       if (x < W && y < H) n += static_cast<unsigned long long>(acc[k]);
     }
@@ -627,9 +633,13 @@ __global__ __launch_bounds__(kWave * TPB) void splat_fwd_kernel(const uint2 *__r
     if (lane == 0 && n) atomicAdd(counter, n);
     return;
   }
+  // half 0 adds half 1's sums of the same pixels (lane + 8) and writes
+#pragma unroll
+  for (int k = 0; k < kFwdRows; ++k) acc[k] += __shfl_down(acc[k], 8, kWave);
+  if (half) return;
   float *out = img + (uint64_t(chunk) * (n_tiles / uint32_t(tpv)) + v_local) * uint64_t(W) * uint64_t(H);
 #pragma unroll
-  for (int k = 0; k < kRows; ++k) {
+  for (int k = 0; k < kFwdRows; ++k) {
     const int y = ty * kTS + row0 + k;
     if (x < W && y < H) out[uint64_t(y) * W + x] = acc[k];
   }
