@@ -285,6 +285,25 @@ def test_projection_backward_matches_oracle(fgs, mode):
     assert max(errs.values()) < TOL, errs
 
 
+@pytest.mark.parametrize("w, h", [(80, 40), (96, 72), (48, 112)])
+def test_projection_backward_ragged_tile_rows(fgs, w, h):
+    """Detectors whose tile-row count is not a multiple of four (3, 5 and 7
+    rows): the backward takes tiles in strips of four rows, the last one
+    lower. Images and gradients against the oracle."""
+    gs = si.gaussians(1500, 31)
+    gd = si.geometry(w, h)
+    ang = si.angles(3)
+    geom = fgs.Geometry.from_dict(gd, ang)
+    t = dev(gs)
+    img = fgs.project_views(*args(t), geom).cpu().numpy()
+    assert rel(img, oracle.project(gs, gd, ang)) < TOL
+    c = si.normals((3, h, w), 32)
+    g = fgs.project_views_backward(*args(t), geom, torch.from_numpy(c).to(DEV))
+    ref = oracle.project_bwd(gs, gd, ang, c.astype(np.float64), band=BAND)
+    errs = grads_rel(g, ref)
+    assert max(errs.values()) < TOL, errs
+
+
 def test_large_gaussians_take_the_interior_path(fgs):
     """Gaussians spanning many tiles (here over 48 tiles per record, where
     the pixel kernels skip the cutoff test for all-interior quadrants):
