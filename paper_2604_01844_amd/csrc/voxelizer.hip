@@ -160,9 +160,8 @@ __device__ float box_qmax(const float4 &c0, const float4 &c1, const float p[3], 
 // Tile j (row-major, x fastest) of rectangle rc, and whether the Gaussian's
 // support ellipsoid reaches one of its voxel centres (a superset test: the
 // threshold carries a small slack).
-__device__ __forceinline__ bool tile_hit(const Rect3 &rc, uint32_t j, const float4 &p, const float4 &c0,
-                                         const float4 &c1, float thr_cull, uint32_t &tx, uint32_t &ty,
-                                         uint32_t &tz) {
+// Tile j of the rectangle, row-major (x fastest).
+__device__ __forceinline__ void tile_coords(const Rect3 &rc, uint32_t j, uint32_t &tx, uint32_t &ty, uint32_t &tz) {
   const uint32_t nx = uint32_t(rc.v[3]) - rc.v[0] + 1u, ny = uint32_t(rc.v[4]) - rc.v[1] + 1u;
   const uint32_t jz = j / (nx * ny);
   const uint32_t jxy = j - jz * nx * ny;
@@ -170,6 +169,12 @@ __device__ __forceinline__ bool tile_hit(const Rect3 &rc, uint32_t j, const floa
   tx = rc.v[0] + (jxy - jy * nx);
   ty = rc.v[1] + jy;
   tz = rc.v[2] + jz;
+}
+
+__device__ __forceinline__ bool tile_hit(const Rect3 &rc, uint32_t j, const float4 &p, const float4 &c0,
+                                         const float4 &c1, float thr_cull, uint32_t &tx, uint32_t &ty,
+                                         uint32_t &tz) {
+  tile_coords(rc, j, tx, ty, tz);
   const float pc[3] = {p.x, p.y, p.z};
   const float lo[3] = {float(tx * kVT), float(ty * kVT), float(tz * kVT)};
   const float hi[3] = {lo[0] + float(kVT - 1), lo[1] + float(kVT - 1), lo[2] + float(kVT - 1)};
@@ -182,13 +187,18 @@ __device__ __forceinline__ uint32_t rect_tiles(const Rect3 &rc) {
 }
 
 // One wave per Gaussian: the number of tiles of its rectangle that its
-// support reaches (the key count), and the 64-bit total.
+// support reaches (the key count), and the 64-bit total. The hit ballots of
+// the first kHitWords rounds are kept, so the emission reads them instead of
+// repeating the test (rectangles of at most 64 kHitWords tiles).
+constexpr int kHitWords = 8;
+
 __global__ __launch_bounds__(256) void vox_count_kernel(int64_t n, const float4 *__restrict__ prho,
                                                         const float4 *__restrict__ a0,
                                                         const float4 *__restrict__ a1,
                                                         const Rect3 *__restrict__ rect, float thr_cull,
                                                         uint32_t *__restrict__ count,
-                                                        unsigned long long *__restrict__ total64) {
+                                                        unsigned long long *__restrict__ total64,
+                                                        unsigned long long *__restrict__ hits) {
   const int64_t i = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (i >= n) return;
@@ -200,7 +210,9 @@ __global__ __launch_bounds__(256) void vox_count_kernel(int64_t n, const float4 
     const uint32_t j = j0 + lane;
     uint32_t tx, ty, tz;
     const bool hit = j < nt && tile_hit(rc, j, p, c0, c1, thr_cull, tx, ty, tz);
-    cnt += __popcll(__ballot(hit));
+    const uint64_t bal = __ballot(hit);
+    cnt += __popcll(bal);
+    if (lane == 0 && nt <= 64u * kHitWords) hits[uint64_t(i) * kHitWords + j0 / 64] = bal;
   }
   if (lane == 0) {
     count[i] = cnt;
@@ -217,6 +229,7 @@ __global__ __launch_bounds__(256) void vox_emit_kernel(int64_t n, int ntx, int n
                                                        const float4 *__restrict__ a1,
                                                        const Rect3 *__restrict__ rect, float thr_cull,
                                                        const uint32_t *__restrict__ offset,
+                                                       const unsigned long long *__restrict__ hits,
                                                        uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
                                                        uint32_t *__restrict__ gid) {
   const int64_t i = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
@@ -228,10 +241,17 @@ __global__ __launch_bounds__(256) void vox_emit_kernel(int64_t n, int ntx, int n
   const uint32_t nt = rect_tiles(rc);
   const float4 p = prho[i], c0 = a0[i], c1 = a1[i];
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const bool stored = nt <= 64u * kHitWords;  // the count kept this rectangle's ballots
   for (uint32_t j0 = 0; j0 < nt; j0 += 64) {
     const uint32_t j = j0 + lane;
     uint32_t tx = 0, ty = 0, tz = 0;
-    const bool hit = j < nt && tile_hit(rc, j, p, c0, c1, thr_cull, tx, ty, tz);
+    bool hit;
+    if (stored) {
+      hit = j < nt && ((hits[uint64_t(i) * kHitWords + j0 / 64] >> lane) & 1ull);
+      if (hit) tile_coords(rc, j, tx, ty, tz);
+    } else {
+      hit = j < nt && tile_hit(rc, j, p, c0, c1, thr_cull, tx, ty, tz);
+    }
     const uint64_t bal = __ballot(hit);
     if (hit) {
       const uint32_t q = o + uint32_t(__popcll(bal & lt));
@@ -571,7 +591,7 @@ __global__ __launch_bounds__(256) void vox_grad_kernel(fgs_gaussians g, GridDev 
 
 struct VoxLayout {
   uint64_t N, T, K;
-  uint64_t total64, prho, radii, rect, offset, a0, a1, scan_scratch, start;
+  uint64_t total64, prho, radii, rect, offset, a0, a1, scan_scratch, start, hits;
   uint64_t fixed_end;
   uint64_t keys, vals, keys_alt, vals_alt, gid, sort_scratch, partials;
   uint64_t total;
@@ -593,6 +613,7 @@ VoxLayout vox_layout(uint64_t N, uint64_t T, uint64_t K) {
   c.take<float4>(N, &L.a1);
   c.take<uint32_t>(scan_scratch_words(N), &L.scan_scratch);
   c.take<uint32_t>(T + 1, &L.start);
+  c.take<unsigned long long>(N * kHitWords, &L.hits);
   L.fixed_end = c.used;
   c.take<uint32_t>(K, &L.keys);
   c.take<uint32_t>(K, &L.vals);
@@ -663,7 +684,8 @@ int vox_build(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *o, f
   const float thr_cull = -0.5f * kLog2e * o->kappa * o->kappa * kCullSlack;
   vox_count_kernel<<<grid_for(N, 4), 256, 0, s>>>(int64_t(N), at<float4>(b, L.prho), at<float4>(b, L.a0),
                                                    at<float4>(b, L.a1), at<Rect3>(b, L.rect), thr_cull,
-                                                   at<uint32_t>(b, L.offset), total64);
+                                                   at<uint32_t>(b, L.offset), total64,
+                                                   at<unsigned long long>(b, L.hits));
   FGS_LAUNCH_CHECK("vox_count_kernel");
   int st = exclusive_scan_u32(at<uint32_t>(b, L.offset), N, at<uint32_t>(b, L.scan_scratch), s);
   if (st != FGS_OK) return st;
@@ -684,7 +706,8 @@ int vox_build(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *o, f
   if (K > 0) {
     vox_emit_kernel<<<grid_for(N, 4), 256, 0, s>>>(int64_t(N), G.nt[0], G.nt[1], at<float4>(b, L.prho),
                                                     at<float4>(b, L.a0), at<float4>(b, L.a1), at<Rect3>(b, L.rect),
-                                                    thr_cull, at<uint32_t>(b, L.offset), at<uint32_t>(b, L.keys),
+                                                    thr_cull, at<uint32_t>(b, L.offset),
+                                                    at<unsigned long long>(b, L.hits), at<uint32_t>(b, L.keys),
                                                     at<uint32_t>(b, L.vals), at<uint32_t>(b, L.gid));
     FGS_LAUNCH_CHECK("vox_emit_kernel");
   }
