@@ -366,6 +366,26 @@ def test_voxelize_ragged_crop(fgs):
     assert rel(vol, ref) < TOL
 
 
+def test_voxelize_small_and_large_boxes(fgs):
+    """Small Gaussians (tile boxes of a few tiles, whose hit ballots the count
+    pass keeps for the emission) mixed with large ones (boxes of over 512
+    tiles, whose emission repeats the exact test): volume and gradients
+    against the oracle."""
+    small = si.gaussians(400, 41)
+    large = si.gaussians(60, 42, log_scale_mean=math.log(0.15))
+    gs = {k: np.concatenate([small[k], large[k]], axis=-1) for k in small}
+    gr = si.grid(96)
+    t = dev(gs)
+    grid = fgs.Grid.from_dict(gr)
+    vol = fgs.voxelize(*args(t), grid).cpu().numpy()
+    assert rel(vol, oracle.voxelize(gs, gr)) < TOL
+    c = si.normals((96, 96, 96), 43)
+    g = fgs.voxelize_backward(*args(t), grid, torch.from_numpy(c).to(DEV))
+    ref = oracle.voxelize_bwd(gs, gr, c.astype(np.float64), band=BAND)
+    errs = grads_rel(g, ref)
+    assert max(errs.values()) < TOL, errs
+
+
 def test_voxelize_deterministic(fgs):
     gs = si.gaussians(3000, 16)
     g = fgs.Grid.from_dict(si.grid(48))
