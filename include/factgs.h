@@ -295,8 +295,8 @@ int fgs_voxelize_support(const fgs_gaussians *g, const fgs_grid *grid, const fgs
 /* L1 term of Eq. 5 over n_views images of n_per_view values:
  * loss[0] = sum_v mean_pixels |img - gt| (device scalar, overwritten) and
  * grad = sign(img - gt) / n_per_view (device, overwritten; sign(0) = 0).
- * grad may be NULL. Deterministic two-level reduction; scratch from ws
- * (needs 16 KiB). */
+ * grad may be NULL. Deterministic two-level FP32 reduction (compensated
+ * per-thread sums, then pairwise trees); scratch from ws (needs 4 KiB). */
 int fgs_l1_loss_grad(const float *img, const float *gt, int64_t n_per_view, int32_t n_views,
                      float *loss, float *grad, fgs_workspace *ws, void *stream);
 
@@ -311,7 +311,8 @@ int fgs_adam_step(float *param, const float *grad, const float *grad2, float *m,
 
 /* PSNR = 10 log10(peak^2 / mean((vol - ref)^2)) over n values, written to
  * out[0] (device float). peak > 0 is given by the caller (max of the
- * reference). Scratch from ws (16 KiB). */
+ * reference). FP32 reduction as in fgs_l1_loss_grad; scratch from ws
+ * (4 KiB). */
 int fgs_psnr(const float *vol, const float *ref, int64_t n, float peak, float *out,
              fgs_workspace *ws, void *stream);
 
@@ -321,7 +322,7 @@ int fgs_psnr(const float *vol, const float *ref, int64_t n, float peak, float *o
  * constants c1, c2 > 0 (0.01^2 and 0.03^2 for unit dynamic range). If grad
  * != NULL it receives scale * d(1 - mean SSIM)/d img, added to its contents
  * when accumulate != 0 (e.g. onto the L1 gradient), else overwriting them.
- * Workspace: 12 bytes per pixel (with grad) plus 8 per 32x32 tile. */
+ * Workspace: 12 bytes per pixel (with grad) plus 4 per 32x32 tile. */
 int fgs_ssim_loss_grad(const float *img, const float *gt, int32_t W, int32_t H, int32_t n_views, float c1,
                        float c2, float scale, float *loss, float *grad, int32_t accumulate, fgs_workspace *ws,
                        void *stream);
@@ -462,7 +463,7 @@ int fgs_mlp_fwd(const fgs_mlp *net, const uint16_t *x, int32_t rows, fgs_mlp_act
  * live = [rho_t > 1e-3] (a fitted Gaussian of no density has no meaningful
  * shape), goes to loss[0] and its gradient with respect to z3 to
  * dz3[rows][32] and dz3t[32][rows] (bf16, zero on padded rows and unused
- * columns). Workspace: ceil(rows/256) doubles. */
+ * columns). Workspace: ceil(rows/256) floats. */
 int fgs_mlp_heads(const float *z3, int32_t rows, int64_t n, const float *base_log_scale, const float *target,
                   float *params_out, uint16_t *dz3, uint16_t *dz3t, float *loss, fgs_workspace *ws,
                   void *stream);

@@ -165,6 +165,46 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Compensated FP32 accumulation (Neumaier's form of Kahan summation): the
+// running error term keeps a long sequential sum within a few ulps of its
+// exact value. Scalar reductions (losses, metrics) accumulate each thread's
+// strided share with it; lanes, waves and blocks are then combined by
+// pairwise trees, so every result is FP32 and independent of timing.
+struct CompSum {
+  float s = 0.f, c = 0.f;
+  __device__ __forceinline__ void add(float x) {
+    const float t = s + x;
+    c += (fabsf(s) >= fabsf(x)) ? ((s - t) + x) : ((x - t) + s);
+    s = t;
+  }
+  __device__ __forceinline__ float value() const { return s + c; }
+};
+
+// Sum of v over a workgroup of NT threads (NT a multiple of 64): an xor
+// butterfly inside each wave, then the wave totals pairwise. The result is
+// valid in thread 0 only. sh holds NT / 64 floats. Contains a barrier: every
+// thread of the workgroup must call it.
+template <int NT>
+__device__ __forceinline__ float block_sum_f32(float v, float *sh) {
+  static_assert(NT % 64 == 0 && NT <= 1024, "workgroup of whole waves");
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  float t = 0.f;
+  if (threadIdx.x == 0) {
+    float w[NT / 64];
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) w[i] = sh[i];
+#pragma unroll
+    for (int step = 1; step < NT / 64; step *= 2)
+#pragma unroll
+      for (int i = 0; i + step < NT / 64; i += 2 * step) w[i] += w[i + step];
+    t = w[0];
+  }
+  return t;
+}
+
 // log2(e): exp(x) = exp2(x * log2(e)). Kernels pre-scale quadratic forms by
 // -log2(e)/2 so that the Gaussian factor is a single v_exp_f32.
 constexpr float kLog2e = 1.4426950408889634f;

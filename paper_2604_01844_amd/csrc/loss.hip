@@ -15,63 +15,48 @@ namespace {
 constexpr int kRedThreads = 256;
 constexpr int kRedBlocks = 1024;
 
-__device__ __forceinline__ double block_sum(double v, double *sh) {
-  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0) sh[wid] = v;
-  __syncthreads();
-  double t = 0.0;
-  if (threadIdx.x == 0)
-    for (int w = 0; w < kRedThreads / 64; ++w) t += sh[w];
-  return t;
-}
-
 // partial[b] = sum over this block's grid-stride share of |img - gt|; grad
 // written alongside.
 __global__ __launch_bounds__(kRedThreads) void l1_kernel(const float *__restrict__ img,
                                                          const float *__restrict__ gt, uint64_t n,
                                                          float inv_p, float *__restrict__ grad,
-                                                         double *__restrict__ partial) {
-  __shared__ double sh[kRedThreads / 64];
-  double acc = 0.0;
+                                                         float *__restrict__ partial) {
+  __shared__ float sh[kRedThreads / 64];
+  CompSum acc;
   for (uint64_t i = uint64_t(blockIdx.x) * kRedThreads + threadIdx.x; i < n;
        i += uint64_t(gridDim.x) * kRedThreads) {
     const float d = img[i] - gt[i];
-    acc += fabs(double(d));
+    acc.add(fabsf(d));
     if (grad) grad[i] = (d > 0.f) ? inv_p : ((d < 0.f) ? -inv_p : 0.f);
   }
-  const double t = block_sum(acc, sh);
+  const float t = block_sum_f32<kRedThreads>(acc.value(), sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
 __global__ __launch_bounds__(kRedThreads) void sq_err_kernel(const float *__restrict__ a,
                                                              const float *__restrict__ b, uint64_t n,
-                                                             double *__restrict__ partial) {
-  __shared__ double sh[kRedThreads / 64];
-  double acc = 0.0;
+                                                             float *__restrict__ partial) {
+  __shared__ float sh[kRedThreads / 64];
+  CompSum acc;
   for (uint64_t i = uint64_t(blockIdx.x) * kRedThreads + threadIdx.x; i < n;
        i += uint64_t(gridDim.x) * kRedThreads) {
-    const double d = double(a[i]) - double(b[i]);
-    acc += d * d;
+    const float d = a[i] - b[i];
+    acc.add(d * d);
   }
-  const double t = block_sum(acc, sh);
+  const float t = block_sum_f32<kRedThreads>(acc.value(), sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-// mode 0: out = scale * sum; mode 1: out = 10 log10(peak^2 / (sum / n))
-__global__ __launch_bounds__(kRedThreads) void finish_kernel(const double *__restrict__ partial, int nb,
-                                                             int mode, double scale, double peak,
-                                                             double n, float *__restrict__ out) {
-  __shared__ double sh[kRedThreads / 64];
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < nb; i += kRedThreads) acc += partial[i];
-  const double t = block_sum(acc, sh);
-  if (threadIdx.x == 0) {
-    if (mode == 0)
-      out[0] = float(t * scale);
-    else
-      out[0] = float(10.0 * log10(peak * peak / (t / n)));
-  }
+// mode 0: out = scale * sum; mode 1: out = 10 log10(peak^2 / (sum / n)),
+// with peak2_n = peak^2 * n formed on the host.
+__global__ __launch_bounds__(kRedThreads) void finish_kernel(const float *__restrict__ partial, int nb,
+                                                             int mode, float scale, float peak2_n,
+                                                             float *__restrict__ out) {
+  __shared__ float sh[kRedThreads / 64];
+  CompSum acc;
+  for (int i = threadIdx.x; i < nb; i += kRedThreads) acc.add(partial[i]);
+  const float t = block_sum_f32<kRedThreads>(acc.value(), sh);
+  if (threadIdx.x == 0) out[0] = (mode == 0) ? t * scale : 10.f * log10f(peak2_n / t);
 }
 
 __global__ __launch_bounds__(256) void adam_kernel(float *__restrict__ p, const float *__restrict__ g,
@@ -102,31 +87,45 @@ __device__ __forceinline__ float sgn(float d) { return (d > 0.f) ? 1.f : ((d < 0
 
 __global__ __launch_bounds__(kRedThreads) void tv_kernel(const float *__restrict__ vol, int nx, int ny, int nz,
                                                          float scale_n, float *__restrict__ grad,
-                                                         double *__restrict__ partial) {
-  __shared__ double sh[kRedThreads / 64];
+                                                         float *__restrict__ partial) {
+  __shared__ float sh[kRedThreads / 64];
   const uint64_t n = uint64_t(nx) * ny * nz;
   const uint64_t sy = uint64_t(nx), sz = uint64_t(nx) * ny;
-  double acc = 0.0;
+  CompSum acc;
   for (uint64_t i = uint64_t(blockIdx.x) * kRedThreads + threadIdx.x; i < n;
        i += uint64_t(gridDim.x) * kRedThreads) {
     const int x = int(i % sy), y = int((i / sy) % ny), z = int(i / sz);
     const float v = vol[i];
     float g = 0.f;
-    if (x + 1 < nx) { const float d = vol[i + 1] - v; acc += fabs(double(d)); g -= sgn(d); }
-    if (y + 1 < ny) { const float d = vol[i + sy] - v; acc += fabs(double(d)); g -= sgn(d); }
-    if (z + 1 < nz) { const float d = vol[i + sz] - v; acc += fabs(double(d)); g -= sgn(d); }
+    if (x + 1 < nx) { const float d = vol[i + 1] - v; acc.add(fabsf(d)); g -= sgn(d); }
+    if (y + 1 < ny) { const float d = vol[i + sy] - v; acc.add(fabsf(d)); g -= sgn(d); }
+    if (z + 1 < nz) { const float d = vol[i + sz] - v; acc.add(fabsf(d)); g -= sgn(d); }
     if (x > 0) g += sgn(v - vol[i - 1]);
     if (y > 0) g += sgn(v - vol[i - sy]);
     if (z > 0) g += sgn(v - vol[i - sz]);
     if (grad) grad[i] = g * scale_n;
   }
-  const double t = block_sum(acc, sh);
+  const float t = block_sum_f32<kRedThreads>(acc.value(), sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
 int reduce_blocks(uint64_t n) {
   uint64_t b = (n + kRedThreads - 1) / kRedThreads;
   return int(b < kRedBlocks ? (b ? b : 1) : kRedBlocks);
+}
+
+// The L1 term's two launches, with `partial` (at least reduce_blocks(n)
+// floats of device memory) holding the per-block sums between them.
+int launch_l1(const float *img, const float *gt, int64_t n_per_view, int32_t n_views, float *loss, float *grad,
+              float *partial, hipStream_t s) {
+  const uint64_t n = uint64_t(n_per_view) * uint64_t(n_views);
+  const int nb = reduce_blocks(n);
+  const float inv_p = 1.f / float(n_per_view);
+  l1_kernel<<<nb, kRedThreads, 0, s>>>(img, gt, n, inv_p, grad, partial);
+  FGS_LAUNCH_CHECK("l1_kernel");
+  finish_kernel<<<1, kRedThreads, 0, s>>>(partial, nb, 0, float(1.0 / double(n_per_view)), 0.f, loss);
+  FGS_LAUNCH_CHECK("finish_kernel");
+  return FGS_OK;
 }
 
 }  // namespace
@@ -138,32 +137,25 @@ extern "C" int fgs_l1_loss_grad(const float *img, const float *gt, int64_t n_per
                                 float *loss, float *grad, fgs_workspace *ws, void *stream) {
   if (!img || !gt || !loss || !ws || !ws->ptr) return fail(FGS_E_INVALID, "null argument");
   if (n_per_view <= 0 || n_views <= 0) return fail(FGS_E_INVALID, "sizes");
-  ws->needed = kRedBlocks * sizeof(double);
+  ws->needed = kRedBlocks * sizeof(float);
   if (ws->bytes < ws->needed) return fail(FGS_E_CAPACITY, "workspace too small");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const uint64_t n = uint64_t(n_per_view) * uint64_t(n_views);
-  const int nb = reduce_blocks(n);
-  double *partial = static_cast<double *>(ws->ptr);
-  const float inv_p = 1.f / float(n_per_view);
-  l1_kernel<<<nb, kRedThreads, 0, s>>>(img, gt, n, inv_p, grad, partial);
-  FGS_LAUNCH_CHECK("l1_kernel");
-  finish_kernel<<<1, kRedThreads, 0, s>>>(partial, nb, 0, 1.0 / double(n_per_view), 0.0, 0.0, loss);
-  FGS_LAUNCH_CHECK("finish_kernel");
-  return FGS_OK;
+  return launch_l1(img, gt, n_per_view, n_views, loss, grad, static_cast<float *>(ws->ptr),
+                   static_cast<hipStream_t>(stream));
 }
 
 extern "C" int fgs_psnr(const float *vol, const float *ref, int64_t n, float peak, float *out,
                         fgs_workspace *ws, void *stream) {
   if (!vol || !ref || !out || !ws || !ws->ptr) return fail(FGS_E_INVALID, "null argument");
   if (n <= 0 || !(peak > 0.f)) return fail(FGS_E_INVALID, "sizes or peak");
-  ws->needed = kRedBlocks * sizeof(double);
+  ws->needed = kRedBlocks * sizeof(float);
   if (ws->bytes < ws->needed) return fail(FGS_E_CAPACITY, "workspace too small");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int nb = reduce_blocks(uint64_t(n));
-  double *partial = static_cast<double *>(ws->ptr);
+  float *partial = static_cast<float *>(ws->ptr);
   sq_err_kernel<<<nb, kRedThreads, 0, s>>>(vol, ref, uint64_t(n), partial);
   FGS_LAUNCH_CHECK("sq_err_kernel");
-  finish_kernel<<<1, kRedThreads, 0, s>>>(partial, nb, 1, 0.0, double(peak), double(n), out);
+  finish_kernel<<<1, kRedThreads, 0, s>>>(partial, nb, 1, 0.f, float(double(peak) * double(peak) * double(n)),
+                                          out);
   FGS_LAUNCH_CHECK("finish_kernel");
   return FGS_OK;
 }
@@ -215,15 +207,15 @@ extern "C" int fgs_tv_loss_grad(const float *vol, const int32_t dims[3], float s
   if (dims[0] <= 0 || dims[1] <= 0 || dims[2] <= 0) return fail(FGS_E_INVALID, "dims must be >= 1");
   const uint64_t n = uint64_t(dims[0]) * dims[1] * dims[2];
   const int nb = reduce_blocks(n);
-  ws->needed = uint64_t(nb) * sizeof(double);
+  ws->needed = uint64_t(nb) * sizeof(float);
   if (!ws->ptr || ws->bytes < ws->needed) return fail(FGS_E_CAPACITY, "workspace too small");
   ws->kind = 0;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  double *partial = static_cast<double *>(ws->ptr);
+  float *partial = static_cast<float *>(ws->ptr);
   tv_kernel<<<nb, kRedThreads, 0, s>>>(vol, dims[0], dims[1], dims[2], float(double(scale) / double(n)), grad,
                                        partial);
   FGS_LAUNCH_CHECK("tv_kernel");
-  finish_kernel<<<1, kRedThreads, 0, s>>>(partial, nb, 0, double(scale) / double(n), 0.0, 0.0, loss);
+  finish_kernel<<<1, kRedThreads, 0, s>>>(partial, nb, 0, float(double(scale) / double(n)), 0.f, loss);
   FGS_LAUNCH_CHECK("finish_kernel");
   return FGS_OK;
 }

@@ -260,10 +260,10 @@ __global__ __launch_bounds__(256) void heads_kernel(const float *__restrict__ Z3
                                                     const float *__restrict__ base_ls,
                                                     const float *__restrict__ target, float *__restrict__ out,
                                                     uint16_t *__restrict__ D, uint16_t *__restrict__ Dt,
-                                                    double *__restrict__ partial) {
-  __shared__ double sh[4];
+                                                    float *__restrict__ partial) {
+  __shared__ float sh[4];
   const int64_t m = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  double lm = 0.0;
+  float lm = 0.f;
   float g[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   if (m < n) {
     const float *y = Z3 + m * ld;
@@ -304,7 +304,7 @@ __global__ __launch_bounds__(256) void heads_kernel(const float *__restrict__ Z3
         }
         for (int j = 0; j < 4; ++j) g[4 + j] = (gh[j] - qh[j] * proj) / qn * inv_n;
       }
-      lm = double(l);
+      lm = l;
     }
   }
   if (D && m < rows) {
@@ -315,22 +315,18 @@ __global__ __launch_bounds__(256) void heads_kernel(const float *__restrict__ Z3
     }
   }
   if (partial) {
-    for (int d = 32; d > 0; d >>= 1) lm += __shfl_xor(lm, d, 64);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = lm;
-    __syncthreads();
-    if (threadIdx.x == 0) partial[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    const float t = block_sum_f32<256>(lm, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
   }
 }
 
-__global__ __launch_bounds__(256) void loss_final_kernel(const double *__restrict__ partial, int nb, double inv_n,
+__global__ __launch_bounds__(256) void loss_final_kernel(const float *__restrict__ partial, int nb, float inv_n,
                                                          float *__restrict__ loss) {
-  __shared__ double sh[4];
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < nb; i += 256) acc += partial[i];
-  for (int d = 32; d > 0; d >>= 1) acc += __shfl_xor(acc, d, 64);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) loss[0] = float(((sh[0] + sh[1]) + (sh[2] + sh[3])) * inv_n);
+  __shared__ float sh[4];
+  CompSum acc;
+  for (int i = threadIdx.x; i < nb; i += 256) acc.add(partial[i]);
+  const float t = block_sum_f32<256>(acc.value(), sh);
+  if (threadIdx.x == 0) loss[0] = t * inv_n;
 }
 
 int check_net(const fgs_mlp *net) {
@@ -402,17 +398,17 @@ extern "C" int fgs_mlp_heads(const float *z3, int32_t rows, int64_t n, const flo
   if (target && (!dz3 || !dz3t || !loss || !ws || !ws->ptr)) return fail(FGS_E_INVALID, "training needs gradient, loss and workspace");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int nb = int((uint64_t(rows) + 255) / 256);
-  double *partial = nullptr;
+  float *partial = nullptr;
   if (target) {
-    ws->needed = uint64_t(nb) * sizeof(double);
+    ws->needed = uint64_t(nb) * sizeof(float);
     if (ws->bytes < ws->needed) return fail(FGS_E_CAPACITY, "workspace too small");
-    partial = static_cast<double *>(ws->ptr);
+    partial = static_cast<float *>(ws->ptr);
   }
   heads_kernel<<<nb, 256, 0, s>>>(z3, 32, n, rows, base_log_scale, target, params_out, target ? dz3 : nullptr,
                                   dz3t, partial);
   FGS_LAUNCH_CHECK("heads_kernel");
   if (target) {
-    loss_final_kernel<<<1, 256, 0, s>>>(partial, nb, 1.0 / double(n), loss);
+    loss_final_kernel<<<1, 256, 0, s>>>(partial, nb, float(1.0 / double(n)), loss);
     FGS_LAUNCH_CHECK("loss_final_kernel");
   }
   return FGS_OK;

@@ -13,7 +13,7 @@
 //
 // Two kernels over 32x32 output tiles with a 5-pixel halo staged in LDS,
 // each a separable (horizontal then vertical) 11-tap pass:
-//   stats kernel: the five statistics, SSIM (block partial sums, no atomics)
+//   stats kernel: the five statistics, 1 - SSIM (block partial sums, no atomics)
 //                 and the three G maps;
 //   grad kernel:  the windowed sums of the G maps and the gradient.
 // The 3D variant (the fitting loss of Eq. 6) is at the end of the file.
@@ -48,26 +48,15 @@ Window gaussian_window() {
   return win;
 }
 
-__device__ __forceinline__ double block_sum(double v, double *sh) {
-  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0) sh[wid] = v;
-  __syncthreads();
-  double t = 0.0;
-  if (threadIdx.x == 0)
-    for (int w = 0; w < kThreads / 64; ++w) t += sh[w];
-  return t;
-}
-
 __global__ __launch_bounds__(kThreads) void ssim_stats_kernel(const float *__restrict__ img,
                                                               const float *__restrict__ gt, int W, int H,
                                                               Window win, float c1, float c2,
                                                               float *__restrict__ g1, float *__restrict__ g2,
                                                               float *__restrict__ g3,
-                                                              double *__restrict__ partial) {
+                                                              float *__restrict__ partial) {
   __shared__ float sx[kH][kH + 1], sy[kH][kH + 1];
   __shared__ float hz[5][kH][kT + 1];
-  __shared__ double sh[kThreads / 64];
+  __shared__ float sh[kThreads / 64];
   const int x0 = blockIdx.x * kT, y0 = blockIdx.y * kT, v = blockIdx.z;
   const uint64_t off = uint64_t(v) * uint64_t(W) * uint64_t(H);
   for (int i = threadIdx.x; i < kH * kH; i += kThreads) {
@@ -94,7 +83,7 @@ __global__ __launch_bounds__(kThreads) void ssim_stats_kernel(const float *__res
     hz[0][r][c] = a; hz[1][r][c] = b; hz[2][r][c] = aa; hz[3][r][c] = bb; hz[4][r][c] = ab;
   }
   __syncthreads();
-  double acc = 0.0;
+  CompSum acc;
   for (int i = threadIdx.x; i < kT * kT; i += kThreads) {
     const int r = i / kT, c = i - r * kT;
     float m[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
@@ -111,7 +100,7 @@ __global__ __launch_bounds__(kThreads) void ssim_stats_kernel(const float *__res
     const float D = (m[2] - mx * mx) + (m[3] - my * my) + c2;
     const float CD = C * D;
     const float S = A * B / CD;
-    acc += double(S);
+    acc.add(1.f - S);
     const uint64_t q = off + uint64_t(gy) * W + gx;
     if (g1) {
       g1[q] = 2.f * my * (B - A) / CD - S * (2.f * mx / C - 2.f * mx / D);
@@ -119,7 +108,7 @@ __global__ __launch_bounds__(kThreads) void ssim_stats_kernel(const float *__res
       g3[q] = 2.f * A / CD;
     }
   }
-  const double t = block_sum(acc, sh);
+  const float t = block_sum_f32<kThreads>(acc.value(), sh);
   if (threadIdx.x == 0)
     partial[(uint64_t(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = t;
 }
@@ -170,13 +159,15 @@ __global__ __launch_bounds__(kThreads) void ssim_grad_kernel(const float *__rest
   }
 }
 
-__global__ __launch_bounds__(kThreads) void ssim_finish_kernel(const double *__restrict__ partial, int nb,
-                                                               double n, double scale, float *__restrict__ loss) {
-  __shared__ double sh[kThreads / 64];
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < nb; i += kThreads) acc += partial[i];
-  const double t = block_sum(acc, sh);
-  if (threadIdx.x == 0) loss[0] = float(scale * (1.0 - t / n));
+// The partial sums are of 1 - SSIM (no cancellation when SSIM is near 1):
+// loss = (scale / n) * their total.
+__global__ __launch_bounds__(kThreads) void ssim_finish_kernel(const float *__restrict__ partial, int nb,
+                                                               float scale_n, float *__restrict__ loss) {
+  __shared__ float sh[kThreads / 64];
+  CompSum acc;
+  for (int i = threadIdx.x; i < nb; i += kThreads) acc.add(partial[i]);
+  const float t = block_sum_f32<kThreads>(acc.value(), sh);
+  if (threadIdx.x == 0) loss[0] = scale_n * t;
 }
 
 }  // namespace
@@ -195,13 +186,13 @@ extern "C" int fgs_ssim_loss_grad(const float *img, const float *gt, int32_t W, 
   const uint64_t nb = uint64_t(grid.x) * grid.y * grid.z;
   Carver c(nullptr);
   uint64_t o_part, o_g;
-  c.take<double>(nb, &o_part);
+  c.take<float>(nb, &o_part);
   c.take<float>(grad ? 3 * n : 0, &o_g);
   ws->needed = c.used;
   if (!ws->ptr || ws->bytes < ws->needed) return fail(FGS_E_CAPACITY, "workspace too small");
   ws->kind = 0;
   char *b = static_cast<char *>(ws->ptr);
-  double *partial = reinterpret_cast<double *>(b + o_part);
+  float *partial = reinterpret_cast<float *>(b + o_part);
   float *g1 = grad ? reinterpret_cast<float *>(b + o_g) : nullptr;
   float *g2 = grad ? g1 + n : nullptr;
   float *g3 = grad ? g2 + n : nullptr;
@@ -209,7 +200,7 @@ extern "C" int fgs_ssim_loss_grad(const float *img, const float *gt, int32_t W, 
   hipStream_t s = static_cast<hipStream_t>(stream);
   ssim_stats_kernel<<<grid, kThreads, 0, s>>>(img, gt, W, H, win, c1, c2, g1, g2, g3, partial);
   FGS_LAUNCH_CHECK("ssim_stats_kernel");
-  ssim_finish_kernel<<<1, kThreads, 0, s>>>(partial, int(nb), double(n), double(scale), loss);
+  ssim_finish_kernel<<<1, kThreads, 0, s>>>(partial, int(nb), float(double(scale) / double(n)), loss);
   FGS_LAUNCH_CHECK("ssim_finish_kernel");
   if (grad) {
     ssim_grad_kernel<<<grid, kThreads, 0, s>>>(img, gt, W, H, win, g1, g2, g3, float(-double(scale) / double(n)),
@@ -271,9 +262,9 @@ __global__ __launch_bounds__(256) void sep_pass_kernel(const float *__restrict__
 
 // From the windowed statistics m[5][n]: SSIM partial sums and G maps g[3][n].
 __global__ __launch_bounds__(256) void ssim_map_kernel(const float *__restrict__ m, uint64_t n, float c1, float c2,
-                                                       float *__restrict__ g, double *__restrict__ partial) {
-  __shared__ double sh[kThreads / 64];
-  double acc = 0.0;
+                                                       float *__restrict__ g, float *__restrict__ partial) {
+  __shared__ float sh[kThreads / 64];
+  CompSum acc;
   for (uint64_t i = uint64_t(blockIdx.x) * kThreads + threadIdx.x; i < n; i += uint64_t(gridDim.x) * kThreads) {
     const float mx = m[i], my = m[n + i];
     const float A = fmaf(2.f * mx, my, c1);
@@ -282,14 +273,14 @@ __global__ __launch_bounds__(256) void ssim_map_kernel(const float *__restrict__
     const float D = (m[2 * n + i] - mx * mx) + (m[3 * n + i] - my * my) + c2;
     const float CD = C * D;
     const float S = A * B / CD;
-    acc += double(S);
+    acc.add(1.f - S);
     if (g) {
       g[i] = 2.f * my * (B - A) / CD - S * (2.f * mx / C - 2.f * mx / D);
       g[n + i] = -S / D;
       g[2 * n + i] = 2.f * A / CD;
     }
   }
-  const double t = block_sum(acc, sh);
+  const float t = block_sum_f32<kThreads>(acc.value(), sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
@@ -318,13 +309,13 @@ extern "C" int fgs_ssim3d_loss_grad(const float *vol, const float *gt, const int
   uint64_t o_a, o_b, o_part;
   c.take<float>(5 * n, &o_a);
   c.take<float>(5 * n, &o_b);
-  c.take<double>(uint64_t(nb), &o_part);
+  c.take<float>(uint64_t(nb), &o_part);
   ws->needed = c.used;
   if (!ws->ptr || ws->bytes < ws->needed) return fail(FGS_E_CAPACITY, "workspace too small");
   ws->kind = 0;
   char *b = static_cast<char *>(ws->ptr);
   float *ba = reinterpret_cast<float *>(b + o_a), *bb = reinterpret_cast<float *>(b + o_b);
-  double *partial = reinterpret_cast<double *>(b + o_part);
+  float *partial = reinterpret_cast<float *>(b + o_part);
   const Window win = gaussian_window();
   hipStream_t s = static_cast<hipStream_t>(stream);
   const unsigned g1 = grid_for(n, 256);
@@ -334,7 +325,7 @@ extern "C" int fgs_ssim3d_loss_grad(const float *vol, const float *gt, const int
   FGS_LAUNCH_CHECK("sep_pass_kernel");
   ssim_map_kernel<<<nb, kThreads, 0, s>>>(ba, n, c1, c2, grad ? bb : nullptr, partial);
   FGS_LAUNCH_CHECK("ssim_map_kernel");
-  ssim_finish_kernel<<<1, kThreads, 0, s>>>(partial, nb, double(n), double(scale), loss);
+  ssim_finish_kernel<<<1, kThreads, 0, s>>>(partial, nb, float(double(scale) / double(n)), loss);
   FGS_LAUNCH_CHECK("ssim_finish_kernel");
   if (grad) {
     sep_pass_kernel<3, false><<<g1, 256, 0, s>>>(bb, nullptr, nx, ny, nz, 0, win, ba);
