@@ -28,11 +28,19 @@ Parity status of each function (what pins it in ``tests/test_oracle_pins.py``):
   unperturbed support.
 * ``voxelize`` (Eq. 2, Sec. 3.3): pinned by the 3D mass closed form and
   brute force.
+* ``project_banded`` / ``voxelize_banded``: their first output is
+  ``project`` / ``voxelize`` (checked for equality); the band sum is pinned
+  by brute force on a small scene.
 * ``project_bwd`` / ``voxelize_bwd``: pinned by Richardson finite
   differences of the forward functions.
 * ``phantom_project`` / ``phantom_volume``: pinned by the sphere chord and
   by quadrature of the indicator.
 * ``bin_tiles``: pinned by the superset property against FP64 support pairs.
+* ``tiles.quad_min`` (the exact smallest Mahalanobis distance over a box),
+  ``tiles.vox_bin_tiles`` (voxel-tile binning) and
+  ``tiles.vox_support_tiles``: pinned by dense sampling, SciPy's bounded
+  minimiser, the isotropic closed form, a hand-computed binning and the
+  superset property (tests/test_culling_cpu.py).
 * ``l1_loss_grad``, ``adam_step``, ``psnr``: pinned by hand-computed values.
 * ``initialisation.fdk`` (FDK, Sec. 3.1): pinned by the reconstruction of
   uniform spheres and ellipsoids from their exact projections.
@@ -132,8 +140,10 @@ def splat_records(gs: dict, geom: dict, angles) -> dict:
                 culled=cul.astype(bool))
 
 
-def project(gs: dict, geom: dict, angles, kappa: float = KAPPA, brute: bool = False) -> np.ndarray:
-    """Method projection M for every pixel of every view: [V][H][W] float64."""
+def project(gs: dict, geom: dict, angles, kappa: float = KAPPA, brute: bool = False, tau: float = 0.0) -> np.ndarray:
+    """Method projection M for every pixel of every view: [V][H][W] float64.
+    tau > 0: the density-aware support d^2 <= min(kappa^2, 2 ln(w / tau))
+    (Sec. 3.5 boxes with the density factored in; w = rho mu the splat's peak)."""
     lib = _load()
     n, keep, p = _gauss_args(gs)
     ang, pa = _d(angles)
@@ -141,19 +151,20 @@ def project(gs: dict, geom: dict, angles, kappa: float = KAPPA, brute: bool = Fa
     img = np.zeros((V, geom["det_h"], geom["det_w"]))
     g, pg = _d(_geom_vec(geom))
     fn = lib.orc_project_brute if brute else lib.orc_project
-    fn(pg, ctypes.c_double(kappa), ctypes.c_int(V), pa, ctypes.c_long(n), *p,
+    fn(pg, ctypes.c_double(kappa), ctypes.c_double(tau), ctypes.c_int(V), pa, ctypes.c_long(n), *p,
        img.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     return img
 
 
-def project_points(gs: dict, geom: dict, angle: float, u, v, kappa: float = KAPPA) -> np.ndarray:
+def project_points(gs: dict, geom: dict, angle: float, u, v, kappa: float = KAPPA, tau: float = 0.0) -> np.ndarray:
     """M of one view at arbitrary detector points (pixel coordinates)."""
     lib = _load()
     n, keep, p = _gauss_args(gs)
     uu, pu = _d(u); vv, pv = _d(v)
     out = np.zeros(uu.shape[0])
     g, pg = _d(_geom_vec(geom))
-    lib.orc_project_points(pg, ctypes.c_double(kappa), ctypes.c_double(angle), ctypes.c_long(n), *p,
+    lib.orc_project_points(pg, ctypes.c_double(kappa), ctypes.c_double(tau), ctypes.c_double(angle),
+                           ctypes.c_long(n), *p,
                            ctypes.c_long(uu.shape[0]), pu, pv,
                            out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     return out
@@ -238,13 +249,14 @@ def rays(geom: dict, angle: float, u, v):
     return o.reshape(m, 3), d.reshape(m, 3)
 
 
-def field_points(gs: dict, x, kappa: float = float("inf")) -> np.ndarray:
-    """Density field sigma(x) (Eq. 2) at points x[m][3]; kappa=inf: no cutoff."""
+def field_points(gs: dict, x, kappa: float = float("inf"), tau: float = 0.0) -> np.ndarray:
+    """Density field sigma(x) (Eq. 2) at points x[m][3]; kappa=inf: no cutoff;
+    tau > 0: also d^2 <= 2 ln(rho / tau) (see project)."""
     lib = _load()
     n, keep, p = _gauss_args(gs)
     xx, px = _d(np.asarray(x).reshape(-1, 3))
     out = np.zeros(xx.shape[0])
-    lib.orc_field_points(ctypes.c_double(kappa), ctypes.c_long(n), *p, ctypes.c_long(xx.shape[0]), px,
+    lib.orc_field_points(ctypes.c_double(kappa), ctypes.c_double(tau), ctypes.c_long(n), *p, ctypes.c_long(xx.shape[0]), px,
                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     return out
 
@@ -268,19 +280,51 @@ def quadrature_points(gs: dict, geom: dict, angle: float, u, v, t_lo: float, t_h
     return out
 
 
+def project_banded(gs: dict, geom: dict, angles, band: float = 1e-3, kappa: float = KAPPA, tau: float = 0.0):
+    """(img, band_img): project() and, per pixel, the sum of the contributions
+    of the pairs with |d^2 - kappa^2| <= band (inside or just outside the
+    support). An evaluation whose support decisions differ from FP64 only on
+    such pairs stays within band_img of img, pixel by pixel."""
+    lib = _load()
+    n, keep, p = _gauss_args(gs)
+    ang, pa = _d(angles)
+    img = np.zeros((ang.shape[0], geom["det_h"], geom["det_w"]))
+    bimg = np.zeros_like(img)
+    g, pg = _d(_geom_vec(geom))
+    lib.orc_project_banded(pg, ctypes.c_double(kappa), ctypes.c_double(tau), ctypes.c_int(ang.shape[0]), pa,
+                           ctypes.c_long(n), *p,
+                           ctypes.c_double(band), _ptr(img), _ptr(bimg))
+    return img, bimg
+
+
 # ---------------------------------------------------------------- voxelizer
 
-def voxelize(gs: dict, grid: dict, kappa: float = KAPPA, brute: bool = False) -> np.ndarray:
-    """Density sum at voxel centres: [nz][ny][nx] float64."""
+def voxelize(gs: dict, grid: dict, kappa: float = KAPPA, brute: bool = False, tau: float = 0.0) -> np.ndarray:
+    """Density sum at voxel centres: [nz][ny][nx] float64; tau as in project
+    with the peak rho."""
     lib = _load()
     n, keep, p = _gauss_args(gs)
     nx, ny, nz = grid["dims"]
     vol = np.zeros((nz, ny, nx))
     gr, pgr = _d(_grid_vec(grid))
     fn = lib.orc_voxelize_brute if brute else lib.orc_voxelize
-    fn(ctypes.c_double(kappa), pgr, ctypes.c_long(n), *p,
+    fn(ctypes.c_double(kappa), ctypes.c_double(tau), pgr, ctypes.c_long(n), *p,
        vol.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     return vol
+
+
+def voxelize_banded(gs: dict, grid: dict, band: float = 1e-3, kappa: float = KAPPA, tau: float = 0.0):
+    """(vol, band_vol) as project_banded, for the voxelizer."""
+    lib = _load()
+    n, keep, p = _gauss_args(gs)
+    nx, ny, nz = grid["dims"]
+    vol = np.zeros((nz, ny, nx))
+    bvol = np.zeros_like(vol)
+    gr, pgr = _d(_grid_vec(grid))
+    lib.orc_voxelize_banded(ctypes.c_double(kappa), ctypes.c_double(tau), pgr, ctypes.c_long(n), *p,
+                            ctypes.c_double(band), _ptr(vol),
+                            _ptr(bvol))
+    return vol, bvol
 
 
 # ---------------------------------------------------------------- gradients
@@ -298,7 +342,7 @@ def _split11(a):
 
 
 def project_bwd(gs: dict, geom: dict, angles, grad_img, kappa: float = KAPPA, sel=None,
-                band: float = 0.0) -> dict:
+                band: float = 0.0, tau: float = 0.0) -> dict:
     """Gradient of sum(grad_img * M) w.r.t. mean, log_scale, quat, density of
     the Gaussians in ``sel`` (default all), support held fixed.
 
@@ -314,7 +358,8 @@ def project_bwd(gs: dict, geom: dict, angles, grad_img, kappa: float = KAPPA, se
     dm, dl, dq, dr = _bwd_out(sel.shape[0])
     babs = np.zeros((11, sel.shape[0]))
     g, pg = _d(_geom_vec(geom))
-    lib.orc_project_bwd(pg, ctypes.c_double(kappa), ctypes.c_int(ang.shape[0]), pa, ctypes.c_long(n), *p,
+    lib.orc_project_bwd(pg, ctypes.c_double(kappa), ctypes.c_double(tau), ctypes.c_int(ang.shape[0]), pa,
+                        ctypes.c_long(n), *p,
                         pgi, ctypes.c_long(sel.shape[0]), sel.ctypes.data_as(ctypes.POINTER(ctypes.c_long)),
                         _ptr(dm), _ptr(dl), _ptr(dq), _ptr(dr), ctypes.c_double(band), _ptr(babs))
     out = dict(mean=dm, log_scale=dl, quat=dq, density=dr)
@@ -323,7 +368,8 @@ def project_bwd(gs: dict, geom: dict, angles, grad_img, kappa: float = KAPPA, se
     return out
 
 
-def voxelize_bwd(gs: dict, grid: dict, grad_vol, kappa: float = KAPPA, sel=None, band: float = 0.0) -> dict:
+def voxelize_bwd(gs: dict, grid: dict, grad_vol, kappa: float = KAPPA, sel=None, band: float = 0.0,
+                 tau: float = 0.0) -> dict:
     """Gradient of sum(grad_vol * V); ``band`` as in project_bwd."""
     lib = _load()
     n, keep, p = _gauss_args(gs)
@@ -332,7 +378,7 @@ def voxelize_bwd(gs: dict, grid: dict, grad_vol, kappa: float = KAPPA, sel=None,
     sel = np.arange(n, dtype=np.int64) if sel is None else np.ascontiguousarray(sel, dtype=np.int64)
     dm, dl, dq, dr = _bwd_out(sel.shape[0])
     babs = np.zeros((11, sel.shape[0]))
-    lib.orc_voxelize_bwd(ctypes.c_double(kappa), pgr, ctypes.c_long(n), *p, pgv, ctypes.c_long(sel.shape[0]),
+    lib.orc_voxelize_bwd(ctypes.c_double(kappa), ctypes.c_double(tau), pgr, ctypes.c_long(n), *p, pgv, ctypes.c_long(sel.shape[0]),
                          sel.ctypes.data_as(ctypes.POINTER(ctypes.c_long)),
                          _ptr(dm), _ptr(dl), _ptr(dq), _ptr(dr), ctypes.c_double(band), _ptr(babs))
     out = dict(mean=dm, log_scale=dl, quat=dq, density=dr)
@@ -555,6 +601,7 @@ def psnr(vol, gt):
 
 from .initialisation import fdk, gradient_init, sampling_weights, trilinear  # noqa: E402,F401
 from . import mlp  # noqa: E402,F401
+from . import tiles  # noqa: E402,F401
 
 
 def rel_l2(a, b) -> float:

@@ -248,6 +248,24 @@ static void splat_box(const splat_t *S, double kappa, double box[4]) {
   box[2] = S->uv[1] - rv; box[3] = S->uv[1] + rv;
 }
 
+/* Support of one splat or voxel Gaussian whose contribution peaks at `peak`
+ * (w = rho mu for a splat, rho for the voxelizer). Sec. 3.2 keeps pairs with
+ * d^2 <= kappa^2; Sec. 3.5 bounds splats by boxes "with factored-in
+ * density", read here as also dropping the pairs whose contribution
+ * peak exp(-d^2/2) is below tau: d^2 <= min(kappa^2, 2 ln(peak / tau)), whose
+ * axis-aligned box shrinks as the peak falls. tau = 0: the kappa support.
+ * Returns the bound on d^2, or -1 when the Gaussian contributes nothing
+ * (peak <= tau). kappa may be infinite (no cut). */
+static double support_k2(double kappa, double tau, double peak) {
+  double k2 = kappa * kappa;
+  if (tau > 0.0) {
+    if (!(peak > tau)) return -1.0;
+    const double t = 2.0 * log(peak / tau);
+    if (t < k2) k2 = t;
+  }
+  return k2;
+}
+
 /* ------------------------------------------------------------------ */
 /* Exported: per-(view, Gaussian) splat records                        */
 /* ------------------------------------------------------------------ */
@@ -288,7 +306,7 @@ void orc_splat_records(const double *g, int n_views, const double *angles, long 
 
 /* Brute force: every pixel of every view sums over every Gaussian.
  * img[n_views][det_h][det_w]. */
-void orc_project_brute(const double *g, double kappa, int n_views, const double *angles, long n,
+void orc_project_brute(const double *g, double kappa, double tau, int n_views, const double *angles, long n,
                        const double *mean, const double *ls, const double *quat,
                        const double *dens, double *img) {
   int W = (int)g[3], H = (int)g[4];
@@ -308,8 +326,9 @@ void orc_project_brute(const double *g, double kappa, int n_views, const double 
         double acc = 0.0;
         for (long i = 0; i < n; ++i) {
           if (S[i].culled) continue;
+          const double k2i = support_k2(kappa, tau, S[i].w);
           double d2 = splat_d2(&S[i], x + 0.5, y + 0.5);
-          if (d2 <= kappa * kappa) acc += S[i].w * exp(-0.5 * d2);
+          if (k2i >= 0.0 && d2 <= k2i) acc += S[i].w * exp(-0.5 * d2);
         }
         out[(size_t)y * W + x] = acc;
       }
@@ -320,13 +339,18 @@ void orc_project_brute(const double *g, double kappa, int n_views, const double 
 /* Gaussian-major variant: each Gaussian visits only the pixels of its FP64
  * support box; the per-pixel test is the same as the brute force, so the
  * result is the same sum (in Gaussian order per pixel). Rows are split
- * across threads; each row sums its Gaussians in ascending index. */
-void orc_project(const double *g, double kappa, int n_views, const double *angles, long n,
-                 const double *mean, const double *ls, const double *quat,
-                 const double *dens, double *img) {
+ * across threads; each row sums its Gaussians in ascending index.
+ * With band_img != NULL, band_img receives per pixel the sum of the
+ * contributions w exp(-d^2/2) of the pairs with |d^2 - kappa^2| <= band
+ * (those inside the support are also in img): any evaluation whose support
+ * decision errs only on such pairs differs from img by at most band_img. */
+static void project_boxed(const double *g, double kappa, double tau, int n_views, const double *angles,
+                          long n, const double *mean, const double *ls, const double *quat,
+                          const double *dens, double band, double *img, double *band_img) {
   int W = (int)g[3], H = (int)g[4];
   splat_t *S = (splat_t *)malloc(sizeof(splat_t) * (size_t)n);
   double *box = (double *)malloc(sizeof(double) * 4 * (size_t)n);
+  double *k2s = (double *)malloc(sizeof(double) * (size_t)n);
   for (int v = 0; v < n_views; ++v) {
     view_t V;
     make_view(g, angles[v], &V);
@@ -335,16 +359,22 @@ void orc_project(const double *g, double kappa, int n_views, const double *angle
       gauss3 G;
       load_gauss(n, i, mean, ls, quat, dens, &G);
       project_gauss(&V, &G, &S[i]);
-      if (!S[i].culled) splat_box(&S[i], kappa, box + 4 * i);
+      k2s[i] = S[i].culled ? -1.0 : support_k2(kappa, tau, S[i].w);
+      if (k2s[i] >= 0.0) splat_box(&S[i], sqrt(k2s[i] + (band_img ? band : 0.0)), box + 4 * i);
     }
     double *out = img + (size_t)v * W * H;
+    double *bout = band_img ? band_img + (size_t)v * W * H : NULL;
 #pragma omp parallel for schedule(dynamic, 4)
     for (int y = 0; y < H; ++y) {
       double *row = out + (size_t)y * W;
+      double *brow = bout ? bout + (size_t)y * W : NULL;
       for (int x = 0; x < W; ++x) row[x] = 0.0;
+      if (brow)
+        for (int x = 0; x < W; ++x) brow[x] = 0.0;
       double yc = y + 0.5;
       for (long i = 0; i < n; ++i) {
-        if (S[i].culled) continue;
+        const double k2 = k2s[i];
+        if (k2 < 0.0) continue;
         const double *b = box + 4 * i;
         if (yc < b[2] || yc > b[3]) continue;
         int x0 = (int)floor(b[0] - 0.5), x1 = (int)ceil(b[1] - 0.5);
@@ -352,17 +382,31 @@ void orc_project(const double *g, double kappa, int n_views, const double *angle
         if (x1 > W - 1) x1 = W - 1;
         for (int x = x0; x <= x1; ++x) {
           double d2 = splat_d2(&S[i], x + 0.5, yc);
-          if (d2 <= kappa * kappa) row[x] += S[i].w * exp(-0.5 * d2);
+          if (d2 <= k2) row[x] += S[i].w * exp(-0.5 * d2);
+          if (brow && fabs(d2 - k2) <= band) brow[x] += S[i].w * exp(-0.5 * d2);
         }
       }
     }
   }
   free(S);
   free(box);
+  free(k2s);
+}
+
+void orc_project(const double *g, double kappa, double tau, int n_views, const double *angles, long n,
+                 const double *mean, const double *ls, const double *quat,
+                 const double *dens, double *img) {
+  project_boxed(g, kappa, tau, n_views, angles, n, mean, ls, quat, dens, 0.0, img, NULL);
+}
+
+void orc_project_banded(const double *g, double kappa, double tau, int n_views, const double *angles, long n,
+                        const double *mean, const double *ls, const double *quat,
+                        const double *dens, double band, double *img, double *band_img) {
+  project_boxed(g, kappa, tau, n_views, angles, n, mean, ls, quat, dens, band, img, band_img);
 }
 
 /* M of one view at arbitrary detector points (u, v), brute force. */
-void orc_project_points(const double *g, double kappa, double angle, long n, const double *mean,
+void orc_project_points(const double *g, double kappa, double tau, double angle, long n, const double *mean,
                         const double *ls, const double *quat, const double *dens, long npts,
                         const double *u, const double *v, double *out) {
   view_t V;
@@ -379,8 +423,9 @@ void orc_project_points(const double *g, double kappa, double angle, long n, con
     double acc = 0.0;
     for (long i = 0; i < n; ++i) {
       if (S[i].culled) continue;
+      const double k2i = support_k2(kappa, tau, S[i].w);
       double d2 = splat_d2(&S[i], u[k], v[k]);
-      if (d2 <= kappa * kappa) acc += S[i].w * exp(-0.5 * d2);
+      if (k2i >= 0.0 && d2 <= k2i) acc += S[i].w * exp(-0.5 * d2);
     }
     out[k] = acc;
   }
@@ -722,7 +767,7 @@ void orc_exact_bwd(const double *g, double kappa, int n_views, const double *ang
 
 /* sigma(x) at arbitrary points with the kappa support (kappa <= 0 or
  * infinite means no cutoff): x[3*npts]. */
-void orc_field_points(double kappa, long n, const double *mean, const double *ls,
+void orc_field_points(double kappa, double tau, long n, const double *mean, const double *ls,
                       const double *quat, const double *dens, long npts, const double *x,
                       double *out) {
   gauss3 *G = (gauss3 *)malloc(sizeof(gauss3) * (size_t)n);
@@ -731,7 +776,7 @@ void orc_field_points(double kappa, long n, const double *mean, const double *ls
     load_gauss(n, i, mean, ls, quat, dens, &G[i]);
     mat3_inv(G[i].Sig, A + 9 * i);
   }
-  int cut = kappa > 0 && isfinite(kappa);
+  const double kcut = (kappa > 0 && isfinite(kappa)) ? kappa : INFINITY;
 #pragma omp parallel for schedule(static)
   for (long k = 0; k < npts; ++k) {
     double acc = 0.0;
@@ -741,7 +786,8 @@ void orc_field_points(double kappa, long n, const double *mean, const double *ls
       double d2 = 0.0;
       for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b) d2 += dd[a] * Ai[3 * a + b] * dd[b];
-      if (!cut || d2 <= kappa * kappa) acc += G[i].rho * exp(-0.5 * d2);
+      const double k2i = support_k2(kcut, tau, G[i].rho);
+      if (k2i >= 0.0 && d2 <= k2i) acc += G[i].rho * exp(-0.5 * d2);
     }
     out[k] = acc;
   }
@@ -756,7 +802,7 @@ static void voxel_centre(const double *gr, long ix, long iy, long iz, double x[3
 }
 
 /* Brute force voxelizer: vol[nz][ny][nx]. */
-void orc_voxelize_brute(double kappa, const double *gr, long n, const double *mean,
+void orc_voxelize_brute(double kappa, double tau, const double *gr, long n, const double *mean,
                         const double *ls, const double *quat, const double *dens, double *vol) {
   long nx = (long)gr[6], ny = (long)gr[7], nz = (long)gr[8];
   long nv = nx * ny * nz;
@@ -764,7 +810,7 @@ void orc_voxelize_brute(double kappa, const double *gr, long n, const double *me
   for (long iz = 0; iz < nz; ++iz)
     for (long iy = 0; iy < ny; ++iy)
       for (long ix = 0; ix < nx; ++ix) voxel_centre(gr, ix, iy, iz, pts + 3 * ((iz * ny + iy) * nx + ix));
-  orc_field_points(kappa, n, mean, ls, quat, dens, nv, pts, vol);
+  orc_field_points(kappa, tau, n, mean, ls, quat, dens, nv, pts, vol);
   free(pts);
 }
 
@@ -781,27 +827,39 @@ static void vox_box(const double *gr, const gauss3 *G, double kappa, long lo[3],
   }
 }
 
-/* Box-limited voxelizer: each z-slice sums its Gaussians in ascending index. */
-void orc_voxelize(double kappa, const double *gr, long n, const double *mean, const double *ls,
-                  const double *quat, const double *dens, double *vol) {
+/* Box-limited voxelizer: each z-slice sums its Gaussians in ascending index.
+ * band_vol (optional) as band_img of project_boxed. */
+static void voxelize_boxed(double kappa, double tau, const double *gr, long n, const double *mean,
+                           const double *ls, const double *quat, const double *dens, double band, double *vol,
+                           double *band_vol) {
   long nx = (long)gr[6], ny = (long)gr[7], nz = (long)gr[8];
   gauss3 *G = (gauss3 *)malloc(sizeof(gauss3) * (size_t)n);
   double *A = (double *)malloc(sizeof(double) * 9 * (size_t)n);
   long *bx = (long *)malloc(sizeof(long) * 6 * (size_t)n);
+  double *k2s = (double *)malloc(sizeof(double) * (size_t)n);
 #pragma omp parallel for schedule(static)
   for (long i = 0; i < n; ++i) {
     load_gauss(n, i, mean, ls, quat, dens, &G[i]);
     mat3_inv(G[i].Sig, A + 9 * i);
-    vox_box(gr, &G[i], kappa, bx + 6 * i, bx + 6 * i + 3);
+    k2s[i] = support_k2(kappa, tau, G[i].rho);
+    if (k2s[i] >= 0.0) {
+      vox_box(gr, &G[i], sqrt(k2s[i] + (band_vol ? band : 0.0)), bx + 6 * i, bx + 6 * i + 3);
+    } else {
+      bx[6 * i + 2] = 1; bx[6 * i + 5] = 0;   /* empty z range */
+    }
   }
 #pragma omp parallel for schedule(dynamic, 1)
   for (long iz = 0; iz < nz; ++iz) {
     double *slab = vol + (size_t)iz * nx * ny;
+    double *bslab = band_vol ? band_vol + (size_t)iz * nx * ny : NULL;
     for (long k = 0; k < nx * ny; ++k) slab[k] = 0.0;
+    if (bslab)
+      for (long k = 0; k < nx * ny; ++k) bslab[k] = 0.0;
     for (long i = 0; i < n; ++i) {
       const long *lo = bx + 6 * i, *hi = bx + 6 * i + 3;
       if (iz < lo[2] || iz > hi[2]) continue;
       const double *Ai = A + 9 * i;
+      const double k2 = k2s[i];
       for (long iy = lo[1]; iy <= hi[1]; ++iy)
         for (long ix = lo[0]; ix <= hi[0]; ++ix) {
           double x[3];
@@ -810,13 +868,26 @@ void orc_voxelize(double kappa, const double *gr, long n, const double *mean, co
           double d2 = 0.0;
           for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b) d2 += dd[a] * Ai[3 * a + b] * dd[b];
-          if (d2 <= kappa * kappa) slab[iy * nx + ix] += G[i].rho * exp(-0.5 * d2);
+          if (d2 <= k2) slab[iy * nx + ix] += G[i].rho * exp(-0.5 * d2);
+          if (bslab && fabs(d2 - k2) <= band) bslab[iy * nx + ix] += G[i].rho * exp(-0.5 * d2);
         }
     }
   }
   free(G);
   free(A);
   free(bx);
+  free(k2s);
+}
+
+void orc_voxelize(double kappa, double tau, const double *gr, long n, const double *mean, const double *ls,
+                  const double *quat, const double *dens, double *vol) {
+  voxelize_boxed(kappa, tau, gr, n, mean, ls, quat, dens, 0.0, vol, NULL);
+}
+
+void orc_voxelize_banded(double kappa, double tau, const double *gr, long n, const double *mean,
+                         const double *ls, const double *quat, const double *dens, double band, double *vol,
+                         double *band_vol) {
+  voxelize_boxed(kappa, tau, gr, n, mean, ls, quat, dens, band, vol, band_vol);
 }
 
 /* ------------------------------------------------------------------ */
@@ -948,7 +1019,7 @@ static void pair_grad_abs(const view_t *V, const gauss3 *G, const splat_t *S, do
   acc11[10] += fabs(r1);
 }
 
-void orc_project_bwd(const double *g, double kappa, int n_views, const double *angles, long n,
+void orc_project_bwd(const double *g, double kappa, double tau, int n_views, const double *angles, long n,
                      const double *mean, const double *ls, const double *quat,
                      const double *dens, const double *grad_img, long n_sel, const long *sel,
                      double *dmean, double *dls, double *dq, double *drho, double band,
@@ -963,11 +1034,12 @@ void orc_project_bwd(const double *g, double kappa, int n_views, const double *a
     load_gauss(n, i, mean, ls, quat, dens, &G);
     double m3[3] = {0, 0, 0}, l3[3] = {0, 0, 0}, q4[4] = {0, 0, 0, 0}, r1 = 0.0;
     double babs[11] = {0};
-    double k2 = kappa * kappa;
     for (int v = 0; v < n_views; ++v) {
       splat_t S;
       project_gauss(&Vs[v], &G, &S);
       if (S.culled) continue;
+      const double k2 = support_k2(kappa, tau, S.w);
+      if (k2 < 0.0) continue;
       double box[4];
       splat_box(&S, sqrt(k2 + band), box);
       int x0 = (int)floor(box[0] - 0.5), x1 = (int)ceil(box[1] - 0.5);
@@ -1024,7 +1096,7 @@ static void voxel_chain(const gauss3 *G, const double A[9], double sr, const dou
   *r1 = sr;
 }
 
-void orc_voxelize_bwd(double kappa, const double *gr, long n, const double *mean, const double *ls,
+void orc_voxelize_bwd(double kappa, double tau, const double *gr, long n, const double *mean, const double *ls,
                       const double *quat, const double *dens, const double *grad_vol, long n_sel,
                       const long *sel, double *dmean, double *dls, double *dq, double *drho,
                       double band, double *band_abs) {
@@ -1037,7 +1109,15 @@ void orc_voxelize_bwd(double kappa, const double *gr, long n, const double *mean
     long lo[3], hi[3];
     load_gauss(n, i, mean, ls, quat, dens, &G);
     mat3_inv(G.Sig, A);
-    double k2 = kappa * kappa;
+    const double k2 = support_k2(kappa, tau, G.rho);
+    if (k2 < 0.0) {
+      for (int a = 0; a < 3; ++a) { dmean[a * n_sel + k] = 0.0; dls[a * n_sel + k] = 0.0; }
+      for (int c = 0; c < 4; ++c) dq[c * n_sel + k] = 0.0;
+      drho[k] = 0.0;
+      if (band_abs)
+        for (int c = 0; c < 11; ++c) band_abs[c * n_sel + k] = 0.0;
+      continue;
+    }
     vox_box(gr, &G, sqrt(k2 + band), lo, hi);
     double sr = 0.0, sp[3] = {0, 0, 0}, sA[9] = {0};
     double babs[11] = {0};

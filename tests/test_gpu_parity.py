@@ -416,6 +416,143 @@ def test_voxelize_backward_stored_equals_recomputed(fgs):
         assert torch.equal(x, y)
 
 
+def _vox_binning(fgs, gs, gr):
+    ws = fgs.Workspace(DEV)
+    fgs.voxelize(*args(dev(gs)), fgs.Grid.from_dict(gr), ws=ws)
+    torch.cuda.synchronize()
+    return {k: (v.cpu().numpy() if torch.is_tensor(v) else v) for k, v in fgs.binning_dump(ws).items()}
+
+
+def _mixed_boxes():
+    small = si.gaussians(400, 41)
+    large = si.gaussians(60, 42, log_scale_mean=math.log(0.15))
+    return {k: np.concatenate([small[k], large[k]], axis=-1) for k in small}, si.grid(96)
+
+
+def _ragged_crop():
+    return si.gaussians(900, 15), dict(origin=(-0.31, -0.2, -0.45), spacing=(0.0125, 0.015, 0.011),
+                                       dims=(40, 29, 37))
+
+
+def _clear_of_thresholds():
+    # a scene with no decision near a threshold (checked in the test): the
+    # whole binning must then be bit-exact
+    return si.gaussians(700, 68, log_scale_mean=math.log(0.04)), si.grid(64)
+
+
+_VOX_CASES = dict(mixed_boxes=_mixed_boxes, ragged_crop=_ragged_crop, clear_of_thresholds=_clear_of_thresholds)
+
+
+@pytest.mark.parametrize("case", list(_VOX_CASES))
+def test_voxel_binning_matches_integer_reference(fgs, case):
+    """The voxelizer's integer work against the oracle's FP64 binning
+    (oracle.tiles.vox_bin_tiles): per-Gaussian key counts and tile
+    rectangles, per-tile lists (stable: ascending Gaussian), sorted keys and
+    tile starts, for every Gaussian none of whose decisions lies within
+    rounding of its threshold (a box edge at a tile boundary, a tile at the
+    culling threshold); bit-exact throughout when there is none. The mixed
+    case holds rectangles of at most 512 tiles (whose hit ballots the count
+    pass keeps) and larger ones (whose emission repeats the exact test)."""
+    gs, gr = _VOX_CASES[case]()
+    d = _vox_binning(fgs, gs, gr)
+    b = oracle.tiles.vox_bin_tiles(gs, gr)
+    if case == "clear_of_thresholds":
+        assert not b["ambiguous"].any()
+    n = gs["density"].shape[0]
+    amb = b["ambiguous"]
+    print(f"{case}: {d['n_pairs']} keys, {int(amb.sum())} of {n} Gaussians near a threshold", flush=True)
+    assert d["n_records"] == n and d["n_tiles"] == int(np.prod(b["tiles"]))
+    off = d["offset"].astype(np.int64)
+    gcount = np.diff(off)
+    np.testing.assert_array_equal(gcount[~amb], b["count"][~amb])
+    nz = ~amb & (gcount > 0)
+    np.testing.assert_array_equal(d["rect"][nz, :6].astype(np.int64) & 0xffff, b["rect"][nz])
+    if case == "mixed_boxes":
+        ntiles = np.prod(b["rect"][:, 3:] - b["rect"][:, :3] + 1, axis=1)
+        assert (ntiles > 512).sum() >= 10 and (ntiles <= 512).sum() >= 300
+    skeys = d["sorted_keys"].astype(np.int64)
+    start = d["tile_start"].astype(np.int64)
+    K, T = d["n_pairs"], d["n_tiles"]
+    assert start[0] == 0 and start[T] == K and np.all(np.diff(start) >= 0)
+    gauss = np.searchsorted(off, d["sorted_vals"].astype(np.int64), side="right") - 1
+    amb_ids = set(np.nonzero(amb)[0].tolist())
+    for t in range(T):
+        lo, hi = start[t], start[t + 1]
+        assert np.all(skeys[lo:hi] == t)
+        gl = gauss[lo:hi]
+        assert np.all(np.diff(gl) > 0), t
+        ol = b["sorted_gauss"][b["tile_start"][t]:b["tile_start"][t + 1]]
+        assert [x for x in gl.tolist() if x not in amb_ids] == [x for x in ol.tolist() if x not in amb_ids], t
+    if not amb.any():
+        np.testing.assert_array_equal(skeys, b["sorted_keys"])
+        np.testing.assert_array_equal(start, b["tile_start"])
+        np.testing.assert_array_equal(d["sorted_vals"].astype(np.int64), b["sorted_slots"])
+        np.testing.assert_array_equal(off, b["offset"])
+
+
+@pytest.mark.parametrize("case", list(_VOX_CASES))
+def test_voxel_binning_covers_support(fgs, case):
+    """Every (voxel, Gaussian) pair with FP64 d^2 <= 9 - 1e-3 has its tile in
+    the Gaussian's list (oracle.tiles.vox_support_tiles, brute force over the
+    voxels of each Gaussian's box)."""
+    gs, gr = _VOX_CASES[case]()
+    d = _vox_binning(fgs, gs, gr)
+    off = d["offset"].astype(np.int64)
+    gauss = np.searchsorted(off, d["sorted_vals"].astype(np.int64), side="right") - 1
+    skeys = d["sorted_keys"].astype(np.int64)
+    n = gs["density"].shape[0]
+    listed = [set() for _ in range(n)]
+    for g_, k_ in zip(gauss.tolist(), skeys.tolist()):
+        listed[g_].add(k_)
+    sup = oracle.tiles.vox_support_tiles(gs, gr, margin=1e-3)
+    missing = [i for i in range(n) if not sup[i] <= listed[i]]
+    assert not missing, missing[:10]
+    assert sum(len(s) for s in sup) > 1000
+
+
+def test_near_plane_cull(fgs):
+    """Gaussians at or behind the near plane (camera depth <= 0.01) are left
+    out of a view, with zero gradient; one just in front of it (depth 0.03,
+    a splat wider than the detector) and ordinary ones are kept. Image and
+    gradients against the oracle, which culls by the same rule."""
+    base = si.gaussians(200, 51)
+    # view 0 looks along -x from the source at (1.5, 0, 0): depth = 1.5 - x
+    extra_x = np.array([1.495, 1.5, 1.62, 1.47, 1.0], dtype=np.float32)   # depths .005, 0, -.12, .03, .5
+    k = extra_x.size
+    ext = dict(mean=np.stack([extra_x, np.array([0.0, 0.01, -0.02, 0.004, 0.05]),
+                              np.array([0.0, -0.01, 0.02, 0.003, -0.04])]).astype(np.float32),
+               log_scale=np.full((3, k), math.log(0.02), np.float32),
+               quat=np.tile(np.array([[1.0], [0.0], [0.0], [0.0]], np.float32), (1, k)),
+               density=np.full(k, 0.5, np.float32))
+    gs = {key: np.ascontiguousarray(np.concatenate([base[key], ext[key]], axis=-1)) for key in base}
+    gd = si.geometry(64)
+    ang = np.array([0.0, 0.4, 2.0], dtype=np.float32)
+    geom = fgs.Geometry.from_dict(gd, ang)
+    t = dev(gs)
+    img = fgs.project_views(*args(t), geom).cpu().numpy()
+    rec = oracle.splat_records(gs, gd, ang)
+    n = 200 + k
+    assert rec["culled"][n - k:n - k + 3].all() and not rec["culled"][n - 2:n].any()
+    ref = oracle.project(gs, gd, ang)
+    assert rel(img, ref) < TOL
+    c = si.normals((3, 64, 64), 52)
+    g = fgs.project_views_backward(*args(t), geom, torch.from_numpy(c).to(DEV))
+    gref = oracle.project_bwd(gs, gd, ang, c.astype(np.float64), band=BAND)
+    errs = grads_rel(g, gref)
+    assert max(errs.values()) < TOL, errs
+    # view 0 alone: the three culled Gaussians contribute nothing and get
+    # exactly zero gradient; the one just in front of the plane does not
+    g0 = fgs.project_views_backward(*args(t), geom, torch.from_numpy(c[:1].copy()).to(DEV), 0, 1)
+    for gg in g0:
+        a_ = gg.detach().cpu().numpy()
+        assert np.all(a_[..., n - k:n - k + 3] == 0.0)
+        assert np.any(a_[..., n - 2] != 0.0)
+    img0 = fgs.project_views(*args(t), geom, 0, 1).cpu().numpy()
+    keep = {key: np.ascontiguousarray(np.delete(gs[key], [n - k, n - k + 1, n - k + 2], axis=-1)) for key in gs}
+    img0_kept = fgs.project_views(*args(dev(keep)), geom, 0, 1).cpu().numpy()
+    assert rel(img0, img0_kept) < 1e-6
+
+
 # ------------------------------------------------------------------ losses, optimiser, phantom
 
 def test_l1_psnr_adam(fgs):
@@ -495,6 +632,45 @@ def test_full_size_projection_sampled(fgs, scan_case):
         xs = rng.integers(0, 512, 600)
         ref = oracle.project_points(gs, gd, float(ang[v]), xs + 0.5, ys + 0.5)
         assert rel(img[v, ys, xs], ref) < TOL, v
+
+
+def _check_every_element(got, ref, band, what):
+    """Element by element: |got - ref| <= 1e-4 max|ref| everywhere, and
+    within 1e-5 max|ref| of the bracket that support decisions near the
+    cutoff allow (band: the FP64 contributions of the pairs with
+    |d^2 - 9| <= 1e-3, which FP32 may put on either side); relative L2 <= 1e-4."""
+    err = np.abs(got.astype(np.float64) - ref)
+    top = np.abs(ref).max()
+    beyond = np.maximum(err - band, 0.0)
+    print(f"{what}: max |diff| {err.max() / top:.2e} of max|ref|, beyond the band {beyond.max() / top:.2e}; "
+          f"rel-L2 {rel(got, ref):.2e}; {np.count_nonzero(band)} elements touch the band", flush=True)
+    assert err.max() <= 1e-4 * top, what
+    assert beyond.max() <= 1e-5 * top, what
+    assert rel(got, ref) < TOL, what
+
+
+def test_full_size_whole_views_every_pixel(fgs, scan_case):
+    """Three complete 512x512 views (the first, a middle and the last) of the
+    75-view call the benchmark times, every pixel against the oracle."""
+    cfg, gs, gd, ang = scan_case
+    geom = fgs.Geometry.from_dict(gd, ang)
+    img = fgs.project_views(*args(dev(gs)), geom).cpu().numpy()
+    for v in (0, 41, 74):
+        ref, band = oracle.project_banded(gs, gd, ang[v:v + 1])
+        _check_every_element(img[v], ref[0], band[0], f"view {v}")
+
+
+def test_full_size_voxel_slab_every_voxel(fgs, scan_case):
+    """An 8-slice slab (z = 124..131) of the 256^3 volume that one voxelize
+    call over the whole grid writes, every voxel against the oracle."""
+    cfg, gs, gd, ang = scan_case
+    gr = si.grid(cfg["vol"])
+    vol = fgs.voxelize(*args(dev(gs)), fgs.Grid.from_dict(gr)).cpu().numpy()
+    h = gr["spacing"][0]
+    slab = dict(origin=(gr["origin"][0], gr["origin"][1], gr["origin"][2] + 124 * h), spacing=gr["spacing"],
+                dims=(cfg["vol"], cfg["vol"], 8))
+    ref, band = oracle.voxelize_banded(gs, slab)
+    _check_every_element(vol[124:132], ref, band, "slab z 124-131")
 
 
 def test_full_size_projection_gradients_sampled(fgs, scan_case):

@@ -161,6 +161,80 @@ def test_splat_mass_closed_form():
     assert img3.sum() == pytest.approx(full * (1 - math.exp(-4.5)), rel=2e-3)
 
 
+def test_density_aware_support_closed_forms():
+    """Density-aware support (Sec. 3.5 boxes with the density factored in):
+    a pair counts only while its contribution w exp(-d^2/2) >= tau. For one
+    splat whose cut 2 ln(w / tau) lies below kappa^2 the pixel sum is then
+    2 pi sqrt(det S^) (w - tau); for one voxel Gaussian it is
+    rho (2 pi)^(3/2) sqrt(det S) P(chi2_3 <= 2 ln(rho / tau)), with
+    P(chi2_3 <= r^2) = erf(r / sqrt 2) - sqrt(2 / pi) r exp(-r^2 / 2).
+    A Gaussian whose peak is below tau contributes nothing."""
+    g = one([0.05, -0.03, 0.02], np.log([0.03, 0.05, 0.04]), [0.9, 0.2, -0.3, 0.1], 0.8)
+    geom = si.geometry(256, mode="cone")
+    ang = 0.4
+    rec = oracle.splat_records(g, geom, [ang])
+    a, b, c = rec["shat"][0]
+    w = rec["w"][0]
+    tau = 0.05 * w
+    assert 2 * math.log(w / tau) < 9.0
+    img = oracle.project(g, geom, [ang], tau=tau)
+    assert img.sum() == pytest.approx(2 * math.pi * math.sqrt(a * c - b * b) * (w - tau), rel=2e-3)
+    assert img[img > 0].min() >= tau * (1 - 1e-12)
+    assert not oracle.project(g, geom, [ang], tau=1.01 * w).any()
+    # tau small enough that kappa = 3 still binds: unchanged
+    np.testing.assert_array_equal(oracle.project(g, geom, [ang], tau=1e-3 * w), oracle.project(g, geom, [ang]))
+
+    ls = np.log([0.03, 0.045, 0.035])
+    gv = one([0.02, -0.01, 0.03], ls, [0.3, -0.5, 0.7, 0.2], 0.9)
+    grid = si.grid(64)
+    h3 = np.prod(grid["spacing"])
+    tau_v = 0.9 * math.exp(-0.5 * 5.0)           # cut at d^2 = 5
+    r = math.sqrt(5.0)
+    inside = math.erf(r / math.sqrt(2)) - math.sqrt(2 / math.pi) * r * math.exp(-0.5 * r * r)
+    full = 0.9 * (2 * math.pi) ** 1.5 * math.exp(ls.sum())
+    v = oracle.voxelize(gv, grid, tau=tau_v)
+    assert v.sum() * h3 == pytest.approx(full * inside, rel=5e-3)
+    assert not oracle.voxelize(gv, grid, tau=0.95).any()
+
+
+def test_density_aware_support_reduces_to_a_smaller_kappa():
+    """For one Gaussian in one view the density-aware support is the plain
+    support with kappa_eff^2 = 2 ln(w / tau) (w = rho mu from the splat
+    records; rho for the voxelizer): images, volumes and gradients equal
+    those of kappa_eff with no density term; brute force equals the box
+    variants; several Gaussians sum their own supports."""
+    g = one([0.05, -0.03, 0.02], np.log([0.04, 0.06, 0.05]), [0.9, 0.2, -0.3, 0.1], 0.8)
+    geom = si.geometry(64, mode="cone")
+    ang = [1.1]
+    w = oracle.splat_records(g, geom, ang)["w"][0]
+    tau = 0.1 * w
+    keff = math.sqrt(2 * math.log(w / tau))
+    np.testing.assert_array_equal(oracle.project(g, geom, ang, tau=tau), oracle.project(g, geom, ang, kappa=keff))
+    c = np.random.default_rng(4).normal(size=(1, 64, 64))
+    ga = oracle.project_bwd(g, geom, ang, c, tau=tau)
+    gb = oracle.project_bwd(g, geom, ang, c, kappa=keff)
+    for k in ga:
+        np.testing.assert_array_equal(ga[k], gb[k])
+    grid = si.grid(40)
+    keff_v = math.sqrt(2 * math.log(0.8 / 0.2))
+    np.testing.assert_array_equal(oracle.voxelize(g, grid, tau=0.2), oracle.voxelize(g, grid, kappa=keff_v))
+    cv = np.random.default_rng(5).normal(size=(40, 40, 40))
+    va = oracle.voxelize_bwd(g, grid, cv, tau=0.2)
+    vb = oracle.voxelize_bwd(g, grid, cv, kappa=keff_v)
+    for k in va:
+        np.testing.assert_array_equal(va[k], vb[k])
+    gs = si.gaussians(200, 33, log_scale_mean=math.log(0.05))
+    ang3 = si.angles(3)
+    tau = 0.02
+    np.testing.assert_allclose(oracle.project(gs, geom, ang3, tau=tau), oracle.project(gs, geom, ang3, tau=tau, brute=True),
+                               rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(oracle.voxelize(gs, grid, tau=0.3), oracle.voxelize(gs, grid, tau=0.3, brute=True),
+                               rtol=1e-13, atol=1e-15)
+    split = oracle.project(subset(gs, np.arange(0, 90)), geom, ang3, tau=tau) + \
+        oracle.project(subset(gs, np.arange(90, 200)), geom, ang3, tau=tau)
+    np.testing.assert_allclose(split, oracle.project(gs, geom, ang3, tau=tau), rtol=1e-12, atol=1e-14)
+
+
 def test_projection_brute_force_equals_box_variant():
     gs = si.gaussians(300, 11)
     geom = si.geometry(48, mode="cone")
@@ -171,6 +245,41 @@ def test_projection_brute_force_equals_box_variant():
 
 
 # --------------------------------------------------------------- Eq. 2, Sec. 3.3
+
+def test_banded_projection_and_voxelization():
+    """The banded variants return project()/voxelize() unchanged, and their
+    band sums equal a brute-force sum over the pairs with |d^2 - 9| <= band
+    (from the per-record conics); perturbing kappa^2 by less than the band
+    moves no pixel or voxel by more than its band sum."""
+    gs = si.gaussians(120, 31, log_scale_mean=math.log(0.06))
+    gd = si.geometry(40, 36)
+    ang = si.angles(3)
+    band = 0.05
+    img, bimg = oracle.project_banded(gs, gd, ang, band=band)
+    np.testing.assert_array_equal(img, oracle.project(gs, gd, ang))
+    rec = oracle.splat_records(gs, gd, ang)
+    ys, xs = np.mgrid[0:36, 0:40] + 0.5
+    want = np.zeros_like(bimg)
+    for r in range(3 * 120):
+        if rec["culled"][r]:
+            continue
+        du, dv = xs - rec["uv"][r, 0], ys - rec["uv"][r, 1]
+        c0, c1, c2 = rec["conic"][r]
+        d2 = c0 * du * du + 2 * c1 * du * dv + c2 * dv * dv
+        want[r // 120] += np.where(np.abs(d2 - 9.0) <= band, rec["w"][r] * np.exp(-0.5 * d2), 0.0)
+    np.testing.assert_allclose(bimg, want, rtol=1e-12, atol=1e-15)
+    assert np.count_nonzero(bimg) > 100
+    for k2 in (9.0 - 0.9 * band, 9.0 + 0.9 * band):
+        moved = oracle.project(gs, gd, ang, kappa=math.sqrt(k2))
+        assert np.all(np.abs(moved - img) <= bimg + 1e-12)
+    gr = dict(origin=(-0.5, -0.45, -0.4), spacing=(1 / 24, 0.9 / 20, 0.8 / 22), dims=(24, 20, 22))
+    vol, bvol = oracle.voxelize_banded(gs, gr, band=band)
+    np.testing.assert_array_equal(vol, oracle.voxelize(gs, gr))
+    assert np.count_nonzero(bvol) > 100
+    for k2 in (9.0 - 0.9 * band, 9.0 + 0.9 * band):
+        moved = oracle.voxelize(gs, gr, kappa=math.sqrt(k2), brute=True)
+        assert np.all(np.abs(moved - vol) <= bvol + 1e-12)
+
 
 def test_voxel_mass_closed_form():
     """Sum of voxel values times voxel volume = rho (2 pi)^(3/2) sqrt(det S)
