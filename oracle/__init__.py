@@ -93,6 +93,14 @@ def _load():
     return _lib
 
 
+def set_threads(n: int) -> int:
+    """Threads of the oracle's parallel loops (0: all host cores); returns the
+    count now in force. Timing control only."""
+    lib = _load()
+    lib.orc_set_threads(ctypes.c_int(int(n)))
+    return int(lib.orc_max_threads())
+
+
 def _d(a):
     a = np.ascontiguousarray(a, dtype=np.float64)
     return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))

@@ -51,8 +51,14 @@
  * quat[4][n] (w, x, y, z; normalised here), density[n].
  */
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* Thread count of the parallel loops (timing at one thread and at all
+ * host cores); no arithmetic. */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : omp_get_num_procs()); }
+int orc_max_threads(void) { return omp_get_max_threads(); }
 
 #define TWO_PI 6.283185307179586476925286766559
 

@@ -17,6 +17,11 @@ the rasterizer does on the detector. The binning written out here:
   d^2 <= kappa^2 * slack (slack 1.001, a Mahalanobis radius 0.05% larger),
   reaches a point of the tile's voxel-centre box [8t, 8t + 7]^3: the
   smallest d^2 over the box, an exact convex minimisation (quad_min);
+* with the density-aware support (tau > 0; Sec. 3.5 boxes with the density
+  factored in) Gaussian i keeps d^2 <= k2_i = min(kappa^2, 2 ln(rho_i / tau))
+  and is dropped when rho_i <= tau: its half-extents are sqrt(k2_i)
+  sqrt(Sigma_aa) / h_a and its tile test d^2 <= k2_i + kappa^2 (slack - 1)
+  (the same widening as at the kappa support);
 * keys are tile ids (tz * nty + ty) * ntx + tx, emitted Gaussian by
   Gaussian in row-major order inside the rectangle (x fastest); a stable
   sort by key leaves each tile's list in ascending Gaussian index.
@@ -87,20 +92,35 @@ def quad_min(A, lo, hi) -> np.ndarray:
     return best
 
 
-def _voxel_frame(gs: dict, grid: dict, kappa: float):
+def support_k2(kappa: float, tau: float, peak) -> np.ndarray:
+    """Per Gaussian, the bound on d^2 of its support: kappa^2, or with the
+    density-aware support (tau > 0) min(kappa^2, 2 ln(peak / tau)); -1 where
+    peak <= tau (the Gaussian contributes nothing)."""
+    peak = np.asarray(peak, dtype=np.float64)
+    k2 = np.full(peak.shape, kappa * kappa)
+    if tau > 0:
+        with np.errstate(divide="ignore", invalid="ignore"):
+            k2 = np.where(peak > tau, np.minimum(k2, 2.0 * np.log(peak / tau)), -1.0)
+    return k2
+
+
+def _voxel_frame(gs: dict, grid: dict, kappa: float, tau: float = 0.0):
     """Centres in voxel-index coordinates [n][3], half-extents in voxels
-    [n][3], inverse covariances in voxel-index units [n][3][3]."""
+    [n][3], inverse covariances in voxel-index units [n][3][3], and the
+    per-Gaussian support bound on d^2 [n] (support_k2)."""
     h = np.asarray(grid["spacing"], dtype=np.float64)
     o = np.asarray(grid["origin"], dtype=np.float64)
     p = np.asarray(gs["mean"], dtype=np.float64).T
     c = (p - o) / h - 0.5
     S = covariances(gs) / (h[:, None] * h[None, :])
-    r = kappa * np.sqrt(np.diagonal(S, axis1=1, axis2=2))
-    return c, r, np.linalg.inv(S)
+    k2 = support_k2(kappa, tau, np.asarray(gs["density"], dtype=np.float64))
+    r = np.sqrt(np.maximum(k2, 0.0))[:, None] * np.sqrt(np.diagonal(S, axis1=1, axis2=2))
+    return c, r, np.linalg.inv(S), k2
 
 
 def vox_bin_tiles(gs: dict, grid: dict, kappa: float = 3.0, tile: int = 8, slack: float = 1.001,
-                  band_edge: float = 1e-3, band_cull: float = 1e-4) -> dict:
+                  band_edge: float = 1e-3, band_cull: float = 1e-4, tau: float = 0.0,
+                  band_tau: float = 1e-5) -> dict:
     """The voxel-tile lists of the module docstring.
 
     Returns rect[n][6] (tx0, ty0, tz0, tx1, ty1, tz1; all -1 when empty),
@@ -112,18 +132,23 @@ def vox_bin_tiles(gs: dict, grid: dict, kappa: float = 3.0, tile: int = 8, slack
     within band_edge voxels of a tile boundary, or a tile whose smallest d^2
     is within band_cull * kappa^2 * slack of kappa^2 * slack. Both bands are
     many times the FP32 rounding of those quantities at the sizes here
-    (coordinates below 2^12 voxels, forms of a few hundred)."""
+    (coordinates below 2^12 voxels, forms of a few hundred). With tau > 0 a
+    Gaussian whose density is within a relative band_tau of tau is
+    ambiguous too (FP32 decides whether it is dropped)."""
     dims = np.asarray(grid["dims"], dtype=np.int64)
     nt = (dims + tile - 1) // tile
-    c, r, A = _voxel_frame(gs, grid, kappa)
+    c, r, A, k2 = _voxel_frame(gs, grid, kappa, tau)
     n = c.shape[0]
     lo_e, hi_e = c - r, c + r
     t0 = np.maximum(np.floor_divide(np.floor(lo_e), tile), 0).astype(np.int64)
     t1 = np.minimum(np.floor_divide(np.floor(hi_e), tile), nt - 1).astype(np.int64)
     near = lambda x: np.abs(x / tile - np.round(x / tile)) * tile < band_edge
     amb = np.any(near(lo_e) | near(hi_e), axis=1)
-    empty = np.any(t0 > t1, axis=1)
-    thr = kappa * kappa * slack
+    if tau > 0:
+        rho = np.asarray(gs["density"], dtype=np.float64)
+        amb |= np.abs(rho - tau) <= band_tau * tau
+    empty = np.any(t0 > t1, axis=1) | (k2 < 0)
+    widen = kappa * kappa * (slack - 1.0)
     rect = np.full((n, 6), -1, dtype=np.int64)
     lists = []
     for i in range(n):
@@ -136,7 +161,8 @@ def vox_bin_tiles(gs: dict, grid: dict, kappa: float = 3.0, tile: int = 8, slack
         tx, ty, tz = tx.ravel(), ty.ravel(), tz.ravel()          # row-major, x fastest
         blo = np.stack([tx, ty, tz], axis=1) * tile - c[i]
         m = quad_min(np.broadcast_to(A[i], (tx.size, 3, 3)), blo, blo + (tile - 1))
-        amb[i] |= bool(np.any(np.abs(m - thr) <= band_cull * thr))
+        thr = k2[i] + widen
+        amb[i] |= bool(np.any(np.abs(m - thr) <= band_cull * kappa * kappa * slack))
         hit = m <= thr
         lists.append(((tz[hit] * nt[1] + ty[hit]) * nt[0] + tx[hit]).astype(np.int64))
     count = np.array([len(l) for l in lists], dtype=np.int64)
@@ -153,15 +179,20 @@ def vox_bin_tiles(gs: dict, grid: dict, kappa: float = 3.0, tile: int = 8, slack
                 tiles=tuple(int(t) for t in nt), ambiguous=amb)
 
 
-def vox_support_tiles(gs: dict, grid: dict, kappa: float = 3.0, tile: int = 8, margin: float = 1e-3) -> list:
+def vox_support_tiles(gs: dict, grid: dict, kappa: float = 3.0, tile: int = 8, margin: float = 1e-3,
+                      tau: float = 0.0) -> list:
     """Per Gaussian, the set of tile ids holding a voxel centre of the grid
-    with d^2 <= kappa^2 - margin (brute force over the voxels of its FP64
-    box, widened by one voxel)."""
+    with d^2 <= k2_i - margin, k2_i its support bound (support_k2; kappa^2
+    when tau = 0), by brute force over the voxels of its FP64 box, widened
+    by one voxel."""
     dims = np.asarray(grid["dims"], dtype=np.int64)
     nt = (dims + tile - 1) // tile
-    c, r, A = _voxel_frame(gs, grid, kappa)
+    c, r, A, k2 = _voxel_frame(gs, grid, kappa, tau)
     out = []
     for i in range(c.shape[0]):
+        if k2[i] < 0:
+            out.append(set())
+            continue
         lo = np.maximum(np.floor(c[i] - r[i]).astype(np.int64) - 1, 0)
         hi = np.minimum(np.ceil(c[i] + r[i]).astype(np.int64) + 1, dims - 1)
         if np.any(lo > hi):
@@ -170,7 +201,7 @@ def vox_support_tiles(gs: dict, grid: dict, kappa: float = 3.0, tile: int = 8, m
         z, y, x = np.meshgrid(np.arange(lo[2], hi[2] + 1), np.arange(lo[1], hi[1] + 1),
                               np.arange(lo[0], hi[0] + 1), indexing="ij")
         d = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1) - c[i]
-        inside = np.einsum("ki,ij,kj->k", d, A[i], d) <= kappa * kappa - margin
+        inside = np.einsum("ki,ij,kj->k", d, A[i], d) <= k2[i] - margin
         t = ((z.ravel()[inside] // tile) * nt[1] + y.ravel()[inside] // tile) * nt[0] + x.ravel()[inside] // tile
         out.append(set(t.tolist()))
     return out

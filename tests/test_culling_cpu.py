@@ -216,3 +216,50 @@ def test_vox_bin_tiles_superset_of_support():
     for t in range(len(st) - 1):
         assert np.all(sk[st[t]:st[t + 1]] == t)
         assert np.all(np.diff(sg[st[t]:st[t + 1]]) > 0)
+
+
+def test_vox_bin_tiles_density_aware_support():
+    """The density-aware support (tau > 0): for a hand-picked isotropic
+    Gaussian (sigma 2 voxels, rho = 1) and tau = exp(-2), the support is
+    d^2 <= 2 ln(1 / tau) = 4, i.e. a radius of 2 sigma = 4 voxels, so the
+    box spans voxels 6.25..14.25, 16.5..24.5, 29..37 (tiles 0..1, 2..3,
+    3..4). A Gaussian with rho <= tau gets no tile. For the random scene,
+    every brute-force support tile is listed, the lists are a subset of the
+    kappa lists, and a tau far below every density reproduces them."""
+    import synth_inputs as si
+    h = 1.0 / 64
+    c = np.array([10.25, 20.5, 33.0])
+    gs = dict(mean=np.repeat(((c + 0.5) * h - 0.5).reshape(3, 1), 2, axis=1),
+              log_scale=np.full((3, 2), np.log(2 * h)), quat=np.array([[1.0, 1.0], [0, 0], [0, 0], [0, 0]]),
+              density=np.array([1.0, 0.1]))
+    gr = dict(origin=(-0.5, -0.5, -0.5), spacing=(h, h, h), dims=(64, 64, 64))
+    tau = np.exp(-2.0)
+    b = tiles.vox_bin_tiles(gs, gr, tau=tau)
+    assert b["rect"][0].tolist() == [0, 2, 3, 1, 3, 4]
+    assert b["count"][1] == 0 and b["rect"][1].tolist() == [-1] * 6
+    want = []
+    for tz in range(3, 5):
+        for ty in range(2, 4):
+            for tx in range(0, 2):
+                lo = np.array([tx, ty, tz]) * 8.0
+                d = np.maximum(np.maximum(lo - c, c - (lo + 7)), 0.0)
+                if (d ** 2).sum() <= 16.0 + 36.0 * 0.001:
+                    want.append((tz * 8 + ty) * 8 + tx)
+    assert b["emit_keys"].tolist() == want
+
+    gs = si.gaussians(300, 78, log_scale_mean=np.log(0.05))
+    gr = dict(origin=(-0.5, -0.45, -0.5), spacing=(1 / 40, 1 / 36, 1 / 44), dims=(40, 35, 44))
+    b0 = tiles.vox_bin_tiles(gs, gr)
+    bt = tiles.vox_bin_tiles(gs, gr, tau=0.2)
+    sup = tiles.vox_support_tiles(gs, gr, tau=0.2)
+    rho = gs["density"].astype(np.float64)
+    for i in range(300):
+        lt = set(bt["emit_keys"][bt["offset"][i]:bt["offset"][i + 1]].tolist())
+        l0 = set(b0["emit_keys"][b0["offset"][i]:b0["offset"][i + 1]].tolist())
+        assert sup[i] <= lt <= l0, i
+        if rho[i] <= 0.2:
+            assert not lt
+    assert bt["count"].sum() < 0.8 * b0["count"].sum()
+    tiny = tiles.vox_bin_tiles(gs, gr, tau=1e-6)   # 2 ln(rho / tau) > 9 for every rho >= 0.1
+    np.testing.assert_array_equal(tiny["emit_keys"], b0["emit_keys"])
+    np.testing.assert_array_equal(tiny["rect"], b0["rect"])
