@@ -201,6 +201,23 @@ int fgs_project_views_fwd(const fgs_gaussians *g, const fgs_geom *geom, int32_t 
                           int32_t view_count, const fgs_opts *opts, float *img,
                           fgs_workspace *ws, void *stream);
 
+/* For callers that cannot allocate device memory or hand over a workspace
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): fgs_project_views_fwd with the same arguments and results,
+ * minus the workspace. The lists, records and partial images live in a
+ * fixed 64 MiB device array inside the library, one per GPU, held from the
+ * first call on that GPU until the process ends; the call allocates nothing
+ * (no hipMalloc, no allocating library routine). 64 MiB holds one 512 x 512
+ * view of about 50,000 Gaussians; a call that needs more returns
+ * FGS_E_CAPACITY (the message names the bytes needed) before writing img,
+ * and cannot be retried with more room: split the views or use
+ * fgs_project_views_fwd. Every call on a GPU uses that GPU's one array:
+ * calls that overlap on one GPU (other streams, other host threads) race
+ * and must be serialised by the caller. No lists are left for a backward.
+ * Synchronisation: as fgs_project_views_fwd (one wait for the pair count). */
+int fgs_project_views_fwd_noalloc(const fgs_gaussians *g, const fgs_geom *geom, int32_t view_begin,
+                                  int32_t view_count, const fgs_opts *opts, float *img, void *stream);
+
 /* Backward of fgs_project_views_fwd: given grad_img[view_count][det_h][det_w]
  * (device) = dL/dimg, writes dL/d(mean, log_scale, quat, density) summed
  * over the views (overwritten). Per (tile, Gaussian) pair the pixel sums

@@ -89,6 +89,8 @@ P = ctypes.POINTER
 SIGNATURES = {
     "fgs_project_views_fwd": [P(fgs_gaussians), P(fgs_geom), ctypes.c_int32, ctypes.c_int32,
                               P(fgs_opts), _vp, P(fgs_workspace), _vp],
+    "fgs_project_views_fwd_noalloc": [P(fgs_gaussians), P(fgs_geom), ctypes.c_int32, ctypes.c_int32,
+                                      P(fgs_opts), _vp, _vp],
     "fgs_project_views_bwd": [P(fgs_gaussians), P(fgs_geom), ctypes.c_int32, ctypes.c_int32,
                               P(fgs_opts), _vp, P(fgs_gaussian_grads), P(fgs_workspace), _vp],
     "fgs_voxelize_fwd": [P(fgs_gaussians), P(fgs_grid), P(fgs_opts), _vp, P(fgs_workspace), _vp],
