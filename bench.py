@@ -4,7 +4,9 @@ One step = one pass of the whole hot path over one workload:
   rasterizer forward over all views -> L1 loss and gradient against the
   phantom's exact projections -> rasterizer backward -> voxelizer forward
   over the whole grid -> L1 against the phantom volume -> voxelizer backward
-  -> one Adam step on all 11 N parameters (both gradients fused).
+  -> one Adam step on all 11 N parameters (both gradients fused). Each step
+  starts from the same parameters (restored by a device copy at its start),
+  so every timed step does the same work.
 
 Workloads (synthetic, seeded; they stand in for the paper's datasets):
   scan  (default) 50,000 Gaussians, 75 cone-beam views of 512^2, 256^3 voxels;
@@ -42,17 +44,27 @@ if ROOT not in sys.path:
 
 METRIC = "fwd+bwd view-pixels/s and voxels/s; s/iter and s-to-PSNR at 75×512² views"
 
-# Algorithmic FP32 operations per support pair (an exponential counts as one):
-#   rasterizer forward : offset 2, quadratic form 7, exp 1, weight and sum 2        = 12
-#   rasterizer backward: offset 2, quadratic form 7, exp 1, g*e 1, six moments 11   = 22
-#   voxelizer forward  : offset 3, quadratic form 14, exp 1, weight and sum 2       = 20
-#   voxelizer backward : offset 3, quadratic form 14, exp 1, g*e 1, ten moments 19  = 38
-FLOPS_PER_PAIR = {"splat_fwd": 12, "splat_bwd": 22, "vox_fwd": 20, "vox_bwd": 38}
-# FP32 vector peak this build can reach: 256 CUs x 64 FMA lanes per clock x
-# 2 flops x 2.4 GHz. The published 157.3 TFLOP/s counts two-wide packed FP32
-# instructions, which the library is compiled without.
-PEAK_FP32_TFLOPS = 78.6
-PEAK_FP32_PUBLISHED_TFLOPS = 157.3
+# FP32 flops per support pair (an exponential counts as one) in the
+# evaluation scheme the kernels use, where the quadratic form is expanded
+# incrementally down a pixel column (voxel row) and the moments are
+# accumulated as column and row sums:
+#   forward  (splat and voxel): exponent 2 FMAs (4), exp 1, weighted sum 1 FMA (2) = 7
+#   backward (splat and voxel): exponent 2 FMAs (4), exp 1, three sums 3 FMAs (6)  = 11
+# The plain per-pair formula costs more (splat 12 / 22, voxel 20 / 38: the
+# full quadratic form and every moment product per pair); it is reported as
+# flops_per_pair_formula. Counting the scheme's own flops keeps every
+# kernel's rate below the chip's peak.
+FLOPS_PER_PAIR = {"splat_fwd": 7, "splat_bwd": 11, "vox_fwd": 7, "vox_bwd": 11}
+FLOPS_PER_PAIR_FORMULA = {"splat_fwd": 12, "splat_bwd": 22, "vox_fwd": 20, "vox_bwd": 38}
+# MI355X's published FP32 vector peak (it counts two-wide packed FP32
+# instructions), and the non-packed peak this build can reach: 256 CUs x 64
+# FMA lanes per clock x 2 flops x 2.4 GHz. The library is compiled without
+# packed FP32.
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP32_NONPACKED_TFLOPS = 78.6
+# The per-pixel bodies the probes measure, per kernel (the voxel kernels run
+# the same bodies per voxel).
+PROBE_OF = {"splat_fwd": "fwd_body", "splat_bwd": "bwd_body", "vox_fwd": "fwd_body", "vox_bwd": "bwd_body"}
 NAMES = ("splat_fwd", "splat_bwd", "vox_fwd", "vox_bwd")
 WORKLOADS = {
     "scan": dict(config="scan", views_per_call=None, recompute=False,
@@ -98,6 +110,53 @@ def measured_traffic(workload: str, kernel: str):
             if f[0] == workload and f[1] == kernel and f[2] == digest:
                 return dict(fetch_bytes=float(f[3]), write_bytes=float(f[4]))
     return None
+
+
+# (name, fgs_probe kind, unit of the rate, iterations per thread): each
+# launch takes a few milliseconds on MI355X.
+PROBES = (("fma", 0, "flop/s", 6000), ("exp", 1, "op/s", 1800), ("fwd_body", 2, "pairs/s", 900),
+          ("bwd_body", 3, "pairs/s", 300), ("lds_b128", 4, "B/s", 3500), ("mfma_bf16", 5, "flop/s", 7000))
+
+
+def ceilings(dev, blocks=2048, reps=3, copy_mib=1024):
+    """Measured ceilings of this GPU (include/factgs.h fgs_probe): FP32 FMA
+    and v_exp_f32 rates, the splat kernels' per-pixel bodies in pairs/s (the
+    voxel kernels run the same bodies per voxel), conflict-free LDS
+    ds_read_b128 bandwidth, v_mfma_f32_32x32x16_bf16 flops, and the
+    library's plain copy kernel in HBM bytes/s (read + write). Each is the
+    median rate of `reps` timed launches after one untimed one."""
+    import ctypes
+    import torch
+    from paper_2604_01844_amd import _abi
+    L = _abi.lib()
+    sink = torch.empty(blocks * 256, dtype=torch.float32, device=dev)
+    out = {}
+    for name, kind, unit, iters in PROBES:
+        work = ctypes.c_double()
+        rates = []
+        for r in range(reps + 1):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            _abi.check(L.fgs_probe(kind, blocks, iters, _abi.ptr(sink), ctypes.byref(work), _abi.stream_ptr(dev)))
+            b.record()
+            torch.cuda.synchronize()
+            if r:
+                rates.append(work.value / (a.elapsed_time(b) * 1e-3))
+        out[name] = dict(rate=float(np.median(rates)), unit=unit)
+    src = torch.ones(copy_mib << 18, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    rates = []
+    for r in range(reps + 1):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        _abi.check(L.fgs_copy(_abi.ptr(src), _abi.ptr(dst), src.numel(), _abi.stream_ptr(dev)))
+        b.record()
+        torch.cuda.synchronize()
+        if r:
+            rates.append(2.0 * src.numel() * 4 / (a.elapsed_time(b) * 1e-3))
+    out["copy"] = dict(rate=float(np.median(rates)), unit="B/s")
+    del src, dst
+    return out
 
 
 def cpu_baseline(gs, gd, ang, grid_d, budget_s=12.0):
@@ -191,6 +250,44 @@ def ablation(fgs, params, geom, i_gt, V, D, steps, log):
     print(json.dumps(dict(ablation="rasterizer fwd+L1+bwd, standard scan", steps=steps, rows=rows)), flush=True)
 
 
+def view_steps(fgs, params, moms, lrs, state, geom, grid, i_gt, dev, epochs=1):
+    """The reconstruction loop's optimizer step (Sec. 3.4, the loss of Eq. 5):
+    one view forward, L1 and SSIM with their gradients, backward (lists
+    reused), a randomly placed 32^3 crop voxelized with the gradient of its
+    TV, Adam. Five untimed steps, then `epochs` timed epochs over all views in
+    a random order; returns seconds per epoch."""
+    import torch
+    from paper_2604_01844_amd.recon import CropTV
+    V, D = geom.n_views, geom.det_w
+    img1 = torch.empty((1, D, D), device=dev)
+    gp = [torch.empty_like(p) for p in params]
+    rng = np.random.Generator(np.random.PCG64(0))
+    order = rng.permutation(V)
+    tv = CropTV(grid, TV_WEIGHT, 32, dev)
+    ws_p, ws_l, ws_s = fgs.Workspace(dev), fgs.Workspace(dev, 1 << 16), fgs.Workspace(dev)
+
+    def view_step(v):
+        fgs.project_views(*params, geom, int(v), 1, ws=ws_p, out=img1)
+        _, g1 = fgs.l1_loss_grad(img1, i_gt[v:v + 1], ws=ws_l)
+        fgs.ssim_loss_grad(img1, i_gt[v:v + 1], scale=SSIM_WEIGHT, ws=ws_s, grad=g1, accumulate=True)
+        fgs.project_views_backward(*params, geom, g1, int(v), 1, recompute=False, ws=ws_p, out=gp)
+        tv.add_grad(params, gp, rng)
+        state["step"] += 1
+        for k, p in enumerate(params):
+            fgs.adam_step(p, gp[k], moms[k][0], moms[k][1], state["step"], lrs[k], clamp_min_zero=(k == 3))
+    for v in order[:5]:
+        view_step(v)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for _ in range(epochs):
+        for v in order:
+            view_step(v)
+    torch.cuda.synchronize()
+    epoch_s = (time.perf_counter() - w0) / epochs
+    log(f"one-view steps: {1e3 * epoch_s / V:.3f} ms/step, {epoch_s:.3f} s/epoch")
+    return epoch_s
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -199,8 +296,14 @@ def main():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="scan")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-view-steps", action="store_true", help="skip the one-view step timing")
+    ap.add_argument("--view-steps-only", type=int, default=0, metavar="EPOCHS",
+                    help="instead of the benchmark, time EPOCHS epochs of the one-view optimizer step (standard "
+                         "scan) and print one JSON line")
     ap.add_argument("--ablation", action="store_true",
                     help="instead of the benchmark, time the rasterizer with parts of its design switched off")
+    ap.add_argument("--probes", action="store_true",
+                    help="instead of the benchmark, measure the ceilings (FMA, exp, the splat bodies, LDS, MFMA, "
+                         "copy) and print them as one JSON line")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after timing, run the library's plain copy kernel 3 times on a MIB-MiB buffer "
                          "(known read and write bytes, to scale HBM traffic counters)")
@@ -217,6 +320,9 @@ def main():
     wl = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.probes:
+        print(json.dumps(dict(ceilings=ceilings(dev), device=torch.cuda.get_device_name(dev))), flush=True)
+        return
     cfg = si.CONFIGS[wl["config"]]
     N, V, D, NV = cfg["n_gauss"], cfg["n_views"], cfg["det"], cfg["vol"]
     gs = si.gaussians(N, cfg["seed"])
@@ -237,6 +343,12 @@ def main():
         return
     lrs = [2e-4, 5e-3, 1e-3, 1e-2]
     moms = [(torch.zeros_like(p), torch.zeros_like(p)) for p in params]
+    if args.view_steps_only:
+        st = {"step": 0}
+        epoch_s = view_steps(fgs, params, moms, lrs, st, geom, grid, i_gt, dev, epochs=args.view_steps_only)
+        print(json.dumps(dict(s_per_view_step=epoch_s / V, s_per_epoch=epoch_s, epochs=args.view_steps_only,
+                              workload=wl["label"].format(N=N, V=V, D=D, NV=NV))), flush=True)
+        return
     gp = [torch.empty_like(p) for p in params]
     gv = [torch.empty_like(p) for p in params]
     img = torch.empty((V, D, D), device=dev)
@@ -245,9 +357,15 @@ def main():
     vpc = wl["views_per_call"]
     chunks = 1 if vpc is None else (V + vpc - 1) // vpc
     state = {"step": 0}
+    # every timed step starts from the same parameters (a 2.2 MB device copy
+    # inside the step), so each does the same work and the support-pair
+    # count below is that of every step; Adam still updates them each step
+    params0 = [p.clone() for p in params]
 
     def step(ev=None):
         e = ev or {}
+        for p, p0 in zip(params, params0):
+            p.copy_(p0)
         fgs.project_views(*params, geom, ws=ws_p, out=img, events=e.get("splat_fwd"), views_per_call=vpc)
         _, g_img = fgs.l1_loss_grad(img, i_gt, ws=ws_l)
         fgs.project_views_backward(*params, geom, g_img, recompute=wl["recompute"], ws=ws_p, out=gp,
@@ -270,8 +388,8 @@ def main():
         pl = [pair_or_list] if isinstance(pair_or_list, tuple) else pair_or_list
         return sum(a.elapsed_time(b) for a, b in pl)
 
-    pairs0 = {"splat": fgs.project_views_support(*params, geom, ws=ws_p),
-              "vox": fgs.voxelize_support(*params, grid, ws=ws_v)}
+    pairs = {"splat": fgs.project_views_support(*params, geom, ws=ws_p),
+             "vox": fgs.voxelize_support(*params, grid, ws=ws_v)}
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -293,65 +411,45 @@ def main():
     # (tile, Gaussian) keys of the last binning of each workspace (for a
     # view-chunked workload: of the last chunk)
     keys = {"splat": ws_p.n_pairs, "vox": ws_v.n_pairs}
-    pairs1 = {"splat": fgs.project_views_support(*params, geom, ws=ws_p),
-              "vox": fgs.voxelize_support(*params, grid, ws=ws_v)}
-    pairs = {k: 0.5 * (pairs0[k] + pairs1[k]) for k in pairs0}
     log(f"timed: {ms_step:.3f} ms/step (wall {1e3 * wall / args.steps:.3f}); kernels {kern_ms}")
 
+    log("measuring the ceilings (probes)")
+    ceil = ceilings(dev)
     kernels = {}
     for n in NAMES:
         pr = pairs["splat" if n.startswith("splat") else "vox"]
-        tf = pr * FLOPS_PER_PAIR[n] / (kern_ms[n] * 1e-3) / 1e12
+        pps = pr / (kern_ms[n] * 1e-3)
+        body = ceil[PROBE_OF[n]]["rate"]
         kernels[n] = dict(ms=round(kern_ms[n], 4), launches=chunks if n.startswith("splat") else 1,
                           support_pairs=int(pr), keys_per_launch=int(keys["splat" if n.startswith("splat") else "vox"]),
-                          pairs_per_s=pr / (kern_ms[n] * 1e-3), tflops=round(tf, 3))
+                          pairs_per_s=pps, tflops=round(pps * FLOPS_PER_PAIR[n] / 1e12, 3),
+                          tflops_formula=round(pps * FLOPS_PER_PAIR_FORMULA[n] / 1e12, 3),
+                          frac_of_body_ceiling=round(pps / body, 4))
     dom = max(NAMES, key=lambda n: kern_ms[n])
     launches = kernels[dom]["launches"]
     tr = measured_traffic(args.workload, dom)
-    roof = dict(bound="alu", achieved=round(kernels[dom]["tflops"], 3), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
-                frac=round(kernels[dom]["tflops"] / PEAK_FP32_TFLOPS, 4),
+    tf = kernels[dom]["tflops"]
+    roof = dict(bound="alu", achieved=tf, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s", frac=round(tf / PEAK_FP32_TFLOPS, 4),
                 traffic=None if tr is None else round(tr["fetch_bytes"] + tr["write_bytes"]),
-                peak_basis="256 CUs x 64 FP32 FMA lanes/clock x 2 flops x 2.4 GHz (no packed FP32)",
-                peak_published=PEAK_FP32_PUBLISHED_TFLOPS,
-                frac_of_published=round(kernels[dom]["tflops"] / PEAK_FP32_PUBLISHED_TFLOPS, 4),
+                peak_basis="MI355X published FP32 vector peak (counts two-wide packed FP32)",
                 kernel=dom, flops_per_pair=FLOPS_PER_PAIR[dom], support_pairs=kernels[dom]["support_pairs"],
-                launches_per_step=launches, avg_launch_ms=round(kern_ms[dom] / launches, 4))
+                launches_per_step=launches, avg_launch_ms=round(kern_ms[dom] / launches, 4),
+                peak_nonpacked=PEAK_FP32_NONPACKED_TFLOPS, frac_nonpacked=round(tf / PEAK_FP32_NONPACKED_TFLOPS, 4),
+                flops_per_pair_formula=FLOPS_PER_PAIR_FORMULA[dom],
+                frac_formula=round(kernels[dom]["tflops_formula"] / PEAK_FP32_TFLOPS, 4),
+                body_ceiling_pairs_per_s=ceil[PROBE_OF[dom]]["rate"],
+                frac_of_body_ceiling=kernels[dom]["frac_of_body_ceiling"])
     out = dict(metric=METRIC, value=V * D * D / (ms_step * 1e-3), unit="view-pixels/s", n_gpus=1,
                steps=args.steps, warmup=args.warmup, ms_per_step=round(ms_step, 4), higher_is_better=True,
                scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
                config=dict(workload=wl["label"].format(N=N, V=V, D=D, NV=NV), n_gauss=N, views=V, det=D, vol=NV),
                voxels_per_s=NV ** 3 / (ms_step * 1e-3), s_per_step=ms_step * 1e-3,
-               kernels=kernels, roofline=roof)
+               kernels=kernels, roofline=roof, ceilings=ceil)
 
     if args.workload == "scan" and not args.no_view_steps:
-        # the reconstruction loop's optimizer step: one view fwd, L1, bwd (lists reused), Adam
-        from paper_2604_01844_amd.recon import CropTV
-        img1 = torch.empty((1, D, D), device=dev)
-        rng = np.random.Generator(np.random.PCG64(0))
-        order = rng.permutation(V)
-        tv = CropTV(grid, TV_WEIGHT, 32, dev)
-        ws_s = fgs.Workspace(dev)
-
-        def view_step(v):
-            fgs.project_views(*params, geom, int(v), 1, ws=ws_p, out=img1)
-            _, g1 = fgs.l1_loss_grad(img1, i_gt[v:v + 1], ws=ws_l)
-            fgs.ssim_loss_grad(img1, i_gt[v:v + 1], scale=SSIM_WEIGHT, ws=ws_s, grad=g1, accumulate=True)
-            fgs.project_views_backward(*params, geom, g1, int(v), 1, recompute=False, ws=ws_p, out=gp)
-            tv.add_grad(params, gp, rng)
-            state["step"] += 1
-            for k, p in enumerate(params):
-                fgs.adam_step(p, gp[k], moms[k][0], moms[k][1], state["step"], lrs[k], clamp_min_zero=(k == 3))
-        for v in order[:5]:
-            view_step(v)
-        torch.cuda.synchronize()
-        w0 = time.perf_counter()
-        for v in order:
-            view_step(v)
-        torch.cuda.synchronize()
-        epoch_s = time.perf_counter() - w0
+        epoch_s = view_steps(fgs, params, moms, lrs, state, geom, grid, i_gt, dev)
         out["s_per_view_step"] = epoch_s / V
         out["s_per_epoch"] = epoch_s
-        log(f"one-view steps: {1e3 * epoch_s / V:.3f} ms/step, {epoch_s:.3f} s/epoch")
     if args.calibrate_copy:
         from paper_2604_01844_amd import _abi
         src = torch.ones(args.calibrate_copy << 18, dtype=torch.float32, device=dev)

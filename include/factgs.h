@@ -130,7 +130,22 @@ typedef struct {
   void *events;          /* optional hipEvent_t[2] (NULL = none): recorded on the stream right
                             before and right after the call's pixel or voxel kernel (splat
                             forward/backward, voxel forward/backward), for timing that kernel */
+  float density_aabb_tau;/* density-aware support (Sec. 3.5: the axis-aligned boxes also take
+                            the density into account), in the units of the image (rasterizer) or
+                            volume (voxelizer). 0 = off: the kappa support. tau > 0: a pair
+                            is kept iff d^2 <= min(kappa^2, 2 ln(peak / tau)), i.e. also
+                            its contribution peak exp(-d^2/2) is at least tau, with peak = w
+                            = rho mu for a splat and rho for the voxelizer; the tile boxes
+                            shrink to that support, and a Gaussian whose peak is <= tau is
+                            left out. Negative or non-finite: FGS_E_INVALID. Splat model
+                            without ablation switches only (FGS_E_UNSUPPORTED otherwise).
+                            Gradients are those of the function with this support held
+                            fixed, as for kappa. */
 } fgs_opts;
+
+/* Tile sizes are fixed: 16 x 16 pixels for the rasterizer (four 8 x 8
+ * quadrants culled separately inside each) and 8 x 8 x 8 voxels for the
+ * voxelizer. The kernels' lane layouts are built around them. */
 
 /* fgs_opts.model (rasterizer).
  * FGS_MODEL_SPLAT: the method's splat M (Eq. 4): per (view, Gaussian) a 2D
@@ -292,6 +307,25 @@ int fgs_voxelize_bwd(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opt
                      void *stream);
 
 /* ---------------------------------------------------------------------
+ * Workspace sizing. For op (FGS_OP_*) on n = g->n Gaussians and, for the
+ * rasterizer, view_count views of geom with opts (the model matters: the
+ * ray-exact model's records and pair slots are twice as large), or, for the
+ * voxelizer, grid: a call that bins K (tile, Gaussian) pairs needs at most
+ * *fixed_bytes + K * *bytes_per_key bytes of workspace (host outputs). K is
+ * known only once the records are built: ws->n_pairs after a call gives it
+ * for the same inputs. Only g->n is read from g. Pure host arithmetic; no
+ * GPU work, no synchronisation. FGS_E_INVALID on a null pointer, n <= 0,
+ * an empty detector or grid, a view count outside [1, geom->n_views] or an
+ * unknown op.
+ * ------------------------------------------------------------------- */
+#define FGS_OP_PROJECT_FWD 0
+#define FGS_OP_PROJECT_BWD 1
+#define FGS_OP_VOXELIZE_FWD 2
+#define FGS_OP_VOXELIZE_BWD 3
+int fgs_workspace_query(int32_t op, const fgs_gaussians *g, const fgs_geom *geom, const fgs_grid *grid,
+                        int32_t view_count, const fgs_opts *opts, uint64_t *fixed_bytes, uint64_t *bytes_per_key);
+
+/* ---------------------------------------------------------------------
  * Work counters (measurement). The algorithmic work of the rasterizer is
  * the number of (pixel, Gaussian) pairs inside the support (d^2 <= kappa^2,
  * pixels inside the detector); of the voxelizer, the (voxel, Gaussian)
@@ -365,6 +399,36 @@ int fgs_tv_loss_grad(const float *vol, const int32_t dims[3], float scale, float
  * a plain streaming copy that reads and writes exactly 4 n bytes, the
  * reference for scaling HBM traffic counters of the other kernels. */
 int fgs_copy(const float *src, float *dst, int64_t n, void *stream);
+
+/* ---------------------------------------------------------------------
+ * Measurement probes: the ceilings the pixel and voxel kernels are measured
+ * against. fgs_probe launches one register-resident kernel of `blocks`
+ * workgroups of 256 threads, each thread running `iters` iterations, and
+ * writes one float per thread to sink[blocks * 256] (device; a checksum that
+ * keeps the work alive). *work (host) receives the work the launch does, in
+ * the unit of its kind:
+ *   FGS_PROBE_FMA        FP32 flops of non-packed fused multiply-adds (2 each)
+ *   FGS_PROBE_EXP        v_exp_f32 lane operations
+ *   FGS_PROBE_FWD_BODY   (pixel, Gaussian) pairs through the splat forward's
+ *                        per-pixel arithmetic (exponent by two FMAs down an
+ *                        8-pixel column, exp, cutoff select, weighted sum); the
+ *                        voxelizer forward's per-voxel body is the same
+ *   FGS_PROBE_BWD_BODY   pairs through the splat backward's per-pixel
+ *                        arithmetic (two FMAs, exp with cutoff select, three
+ *                        accumulating FMAs, per-row and per-pair moment work);
+ *                        the voxelizer backward's per-voxel body is the same
+ *   FGS_PROBE_LDS        bytes read from LDS by conflict-free ds_read_b128
+ *   FGS_PROBE_MFMA_BF16  flops of v_mfma_f32_32x32x16_bf16
+ * Time the launch with events on `stream`. Asynchronous. FGS_E_INVALID for
+ * an unknown kind or non-positive sizes.
+ * ------------------------------------------------------------------- */
+#define FGS_PROBE_FMA 0
+#define FGS_PROBE_EXP 1
+#define FGS_PROBE_FWD_BODY 2
+#define FGS_PROBE_BWD_BODY 3
+#define FGS_PROBE_LDS 4
+#define FGS_PROBE_MFMA_BF16 5
+int fgs_probe(int32_t kind, int32_t blocks, int32_t iters, float *sink, double *work, void *stream);
 
 /* ---------------------------------------------------------------------
  * Synthetic ground truth (additive ellipsoid phantom, computed in FP64).

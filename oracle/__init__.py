@@ -151,7 +151,7 @@ def splat_records(gs: dict, geom: dict, angles) -> dict:
 def project(gs: dict, geom: dict, angles, kappa: float = KAPPA, brute: bool = False, tau: float = 0.0) -> np.ndarray:
     """Method projection M for every pixel of every view: [V][H][W] float64.
     tau > 0: the density-aware support d^2 <= min(kappa^2, 2 ln(w / tau))
-    (Sec. 3.5 boxes with the density factored in; w = rho mu the splat's peak)."""
+    (Sec. 3.5 boxes that take the density into account; w = rho mu the splat's peak)."""
     lib = _load()
     n, keep, p = _gauss_args(gs)
     ang, pa = _d(angles)

@@ -256,8 +256,8 @@ static void splat_box(const splat_t *S, double kappa, double box[4]) {
 
 /* Support of one splat or voxel Gaussian whose contribution peaks at `peak`
  * (w = rho mu for a splat, rho for the voxelizer). Sec. 3.2 keeps pairs with
- * d^2 <= kappa^2; Sec. 3.5 bounds splats by boxes "with factored-in
- * density", read here as also dropping the pairs whose contribution
+ * d^2 <= kappa^2; Sec. 3.5 bounds splats by boxes that also take the
+ * density into account, read here as also dropping the pairs whose contribution
  * peak exp(-d^2/2) is below tau: d^2 <= min(kappa^2, 2 ln(peak / tau)), whose
  * axis-aligned box shrinks as the peak falls. tau = 0: the kappa support.
  * Returns the bound on d^2, or -1 when the Gaussian contributes nothing

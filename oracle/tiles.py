@@ -17,8 +17,8 @@ the rasterizer does on the detector. The binning written out here:
   d^2 <= kappa^2 * slack (slack 1.001, a Mahalanobis radius 0.05% larger),
   reaches a point of the tile's voxel-centre box [8t, 8t + 7]^3: the
   smallest d^2 over the box, an exact convex minimisation (quad_min);
-* with the density-aware support (tau > 0; Sec. 3.5 boxes with the density
-  factored in) Gaussian i keeps d^2 <= k2_i = min(kappa^2, 2 ln(rho_i / tau))
+* with the density-aware support (tau > 0; Sec. 3.5 boxes that take the density
+  into account) Gaussian i keeps d^2 <= k2_i = min(kappa^2, 2 ln(rho_i / tau))
   and is dropped when rho_i <= tau: its half-extents are sqrt(k2_i)
   sqrt(Sigma_aa) / h_a and its tile test d^2 <= k2_i + kappa^2 (slack - 1)
   (the same widening as at the kappa support);

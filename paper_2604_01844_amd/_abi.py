@@ -23,6 +23,7 @@ FGS_CONE = 0
 FGS_PARALLEL = 1
 FGS_MODEL_SPLAT = 0
 FGS_MODEL_RAY_EXACT = 1
+FGS_OP_PROJECT_FWD, FGS_OP_PROJECT_BWD, FGS_OP_VOXELIZE_FWD, FGS_OP_VOXELIZE_BWD = 0, 1, 2, 3
 
 _vp = ctypes.c_void_p
 
@@ -51,7 +52,7 @@ class fgs_grid(ctypes.Structure):
 class fgs_opts(ctypes.Structure):
     _fields_ = [("kappa", ctypes.c_float), ("near_plane", ctypes.c_float),
                 ("recompute", ctypes.c_int32), ("accumulate", ctypes.c_int32), ("ablate", ctypes.c_int32),
-                ("model", ctypes.c_int32), ("events", _vp)]
+                ("model", ctypes.c_int32), ("events", _vp), ("density_aabb_tau", ctypes.c_float)]
 
 
 class fgs_workspace(ctypes.Structure):
@@ -106,6 +107,8 @@ SIGNATURES = {
     "fgs_phantom_project": [P(fgs_phantom), P(fgs_geom), ctypes.c_int32, ctypes.c_int32, _vp, _vp],
     "fgs_phantom_voxelize": [P(fgs_phantom), P(fgs_grid), _vp, _vp],
     "fgs_binning_layout": [P(fgs_workspace), P(ctypes.c_uint64), P(ctypes.c_uint64)],
+    "fgs_workspace_query": [ctypes.c_int32, P(fgs_gaussians), P(fgs_geom), P(fgs_grid), ctypes.c_int32, P(fgs_opts),
+                            P(ctypes.c_uint64), P(ctypes.c_uint64)],
     "fgs_fdk": [_vp, P(fgs_geom), ctypes.c_int32, ctypes.c_int32, P(fgs_grid), _vp, P(fgs_workspace), _vp],
     "fgs_gradient_init": [_vp, P(fgs_grid), ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_int64, _vp,
                           P(fgs_gaussian_grads), P(fgs_workspace), _vp],
@@ -119,6 +122,7 @@ SIGNATURES = {
                         P(fgs_gaussian_grads), P(fgs_gaussian_grads), P(fgs_gaussian_grads), P(ctypes.c_int64),
                         P(fgs_workspace), _vp],
     "fgs_copy": [_vp, _vp, ctypes.c_int64, _vp],
+    "fgs_probe": [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, P(ctypes.c_double), _vp],
     "fgs_tv_loss_grad": [_vp, P(ctypes.c_int32), ctypes.c_float, _vp, _vp, P(fgs_workspace), _vp],
     "fgs_ssim3d_loss_grad": [_vp, _vp, P(ctypes.c_int32), ctypes.c_float, ctypes.c_float, ctypes.c_float, _vp, _vp,
                              ctypes.c_int32, P(fgs_workspace), _vp],

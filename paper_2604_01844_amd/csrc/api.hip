@@ -21,6 +21,10 @@ int hip_fail(hipError_t e, const char *what) {
 
 int rast_binning_layout(const fgs_workspace *ws, uint64_t off[9], uint64_t counts[3]);
 int vox_binning_layout(const fgs_workspace *ws, uint64_t off[9], uint64_t counts[3]);
+int rast_workspace_bytes(const fgs_gaussians *g, const fgs_geom *geom, int32_t view_count, const fgs_opts *o,
+                         bool forward, uint64_t *fixed_bytes, uint64_t *bytes_per_key);
+int vox_workspace_bytes(const fgs_gaussians *g, const fgs_grid *grid, bool forward, uint64_t *fixed_bytes,
+                        uint64_t *bytes_per_key);
 
 }  // namespace fgs
 
@@ -33,4 +37,21 @@ extern "C" int fgs_binning_layout(const fgs_workspace *ws, uint64_t off[9], uint
   if (ws->kind == 1 || ws->kind == 3) return fgs::rast_binning_layout(ws, off, counts);
   if (ws->kind == 2) return fgs::vox_binning_layout(ws, off, counts);
   return fgs::fail(FGS_E_INVALID, "workspace holds no lists");
+}
+
+extern "C" int fgs_workspace_query(int32_t op, const fgs_gaussians *g, const fgs_geom *geom, const fgs_grid *grid,
+                                   int32_t view_count, const fgs_opts *opts, uint64_t *fixed_bytes,
+                                   uint64_t *bytes_per_key) {
+  if (!fixed_bytes || !bytes_per_key) return fgs::fail(FGS_E_INVALID, "null output");
+  switch (op) {
+    case FGS_OP_PROJECT_FWD:
+    case FGS_OP_PROJECT_BWD:
+      return fgs::rast_workspace_bytes(g, geom, view_count, opts, op == FGS_OP_PROJECT_FWD, fixed_bytes,
+                                       bytes_per_key);
+    case FGS_OP_VOXELIZE_FWD:
+    case FGS_OP_VOXELIZE_BWD:
+      return fgs::vox_workspace_bytes(g, grid, op == FGS_OP_VOXELIZE_FWD, fixed_bytes, bytes_per_key);
+    default:
+      return fgs::fail(FGS_E_INVALID, "workspace query: unknown op");
+  }
 }

@@ -69,6 +69,16 @@ __device__ __forceinline__ void tile_span(float c, float r, int n_tiles, int &t0
 }
 
 constexpr int kTotalSlots = 64;
+constexpr float kLn2 = 0.6931471805599453f;
+
+// Support threshold of one record on the pre-scaled exponent
+// arg = -log2(e)/2 d^2: thr = -log2(e)/2 kappa^2, raised to log2(tau / w) by
+// the density-aware support (Sec. 3.5, boxes that also take the density into
+// account: d^2 <= min(kappa^2, 2 ln(w / tau)), i.e. the pair's contribution
+// w exp(-d^2/2) >= tau). log2_tau = -infinity when tau = 0 (the kappa support).
+__device__ __forceinline__ float support_thr(float thr, float log2_tau, float w) {
+  return log2_tau > -INFINITY ? fmaxf(thr, log2_tau - __builtin_amdgcn_logf(w)) : thr;
+}
 
 // Widest digit of the rasterizer's sort passes over the tile field. Narrow
 // digits keep the per-block histograms small and the output runs long;
@@ -102,6 +112,18 @@ __device__ __forceinline__ uint32_t record_one(const fgs_gaussians &g, const Geo
   make_frame(G, G.view_begin + v_local, F);
   Splat S;
   splat_forward(P, F, G, S);
+  // density-aware support (tau > 0): d^2 <= min(kappa^2, 2 ln(w / tau)), and
+  // the tile box is that ellipse's exact box; a splat whose peak w does not
+  // exceed tau contributes nothing
+  float kap = G.kappa;
+  if (S.ok && G.tau > 0.f) {
+    if (S.w > G.tau) {
+      const float k2t = 2.f * kLn2 * (log2f(S.w) - log2f(G.tau));
+      if (k2t < kap * kap) kap = sqrtf(k2t);
+    } else {
+      S.ok = false;
+    }
+  }
   if (!S.ok) {
     xy[r] = make_float2(0.f, 0.f);
     rec[r].a = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -111,8 +133,8 @@ __device__ __forceinline__ uint32_t record_one(const fgs_gaussians &g, const Geo
     count[r] = 0;
     return 0;
   }
-  float ru = G.kappa * sqrtf(S.a);
-  float rv = G.kappa * sqrtf(S.c);
+  float ru = kap * sqrtf(S.a);
+  float rv = kap * sqrtf(S.c);
   if (G.ablate & FGS_ABLATE_SQUARE_BOX) {
     // square of half-side kappa sqrt(lambda_max): the circle bound
     const float h = 0.5f * (S.a - S.c);
@@ -149,7 +171,6 @@ struct ExactRec {
 // The tile rectangle of the support ellipse is widened by this factor, so
 // FP32 rounding of the box never drops a pixel the per-pixel test keeps.
 constexpr float kExactBoxSlack = 1.0005f;
-constexpr float kLn2 = 0.6931471805599453f;
 
 __device__ __forceinline__ uint32_t record_one_exact(const fgs_gaussians &g, const GeomDev &G, int64_t i,
                                                      int v_local, float2 *__restrict__ xy,
@@ -502,11 +523,11 @@ __global__ __launch_bounds__(kWave * TPB) void splat_fwd_kernel(const uint2 *__r
                                                            const SplatRec *__restrict__ rec,
                                                            int tiles_x, int tpv, int W, int H,
                                                            uint32_t n_tiles, int n_chunks, float thr,
-                                                           float thr_cull, float thr_int, int no_cull,
+                                                           float log2_tau, int no_cull,
                                                            float *__restrict__ img,
                                                            unsigned long long *__restrict__ counter) {
-  // per batch slot: the conic and weight, and (centre, 2 c11): one address,
-  // the second array at a fixed offset from the first
+  // per batch slot: the conic and weight, and (centre, 2 c11, support
+  // threshold): one address, the second array at a fixed offset from the first
   __shared__ float4 s_rec_all[TPB][2][kWave + 1];
   __shared__ uint8_t s_list_all[TPB][4][kWave];
   const int wid = threadIdx.x / kWave;
@@ -556,10 +577,11 @@ __global__ __launch_bounds__(kWave * TPB) void splat_fwd_kernel(const uint2 *__r
       const float2 rb = make_float2(pf.cur.b.x, pf.cur.b.y);
       const float4 c = make_float4(ra.z, ra.w, rb.x, rb.y);
       const float2 q = make_float2(ra.x, ra.y);
+      const float thr_r = support_thr(thr, log2_tau, c.w);
       s_cw[lane] = c;
-      s_xy[lane] = make_float4(q.x, q.y, 2.f * c.z, 0.f);
-      mask = no_cull ? 0xFu : quad_mask(c, q.x, q.y, tx0, ty0, thr_cull);
-      if (kInterior && !kCount) imask = quad_interior(c, q.x, q.y, tx0, ty0, thr_int) & mask;
+      s_xy[lane] = make_float4(q.x, q.y, 2.f * c.z, thr_r);
+      mask = no_cull ? 0xFu : quad_mask(c, q.x, q.y, tx0, ty0, thr_r * kCullSlack);
+      if (kInterior && !kCount) imask = quad_interior(c, q.x, q.y, tx0, ty0, thr_r * kInteriorSlack) & mask;
     }
     int nq[4], ni[4] = {0, 0, 0, 0};
     if (kInterior && !kCount) {
@@ -611,10 +633,10 @@ __global__ __launch_bounds__(kWave * TPB) void splat_fwd_kernel(const uint2 *__r
         const float fk = float(k);
         const float arg = (k == 0) ? arg0 : fmaf(fk, fmaf(c.z, fk, E), arg0);
         if (kCount) {
-          acc[k] += (arg >= thr) ? 1.f : 0.f;
+          acc[k] += (arg >= q.w) ? 1.f : 0.f;
         } else {
           const float ex = __builtin_amdgcn_exp2f(arg);
-          acc[k] = fmaf(c.w, (arg >= thr) ? ex : 0.f, acc[k]);
+          acc[k] = fmaf(c.w, (arg >= q.w) ? ex : 0.f, acc[k]);
         }
       }
     }
@@ -667,7 +689,7 @@ template <int TPB>
 __global__ __launch_bounds__(kWave * TPB) __attribute__((amdgpu_waves_per_eu(7, 7))) void splat_bwd_kernel(
     const uint2 *__restrict__ rng, const uint32_t *__restrict__ svals,
     const SplatRec *__restrict__ rec, int tiles_x, int tpv, int W, int H, uint32_t n_tiles, int n_chunks,
-    float thr, float thr_cull, int no_cull, const float *__restrict__ gimg, float4 *__restrict__ partials) {
+    float thr, float log2_tau, int no_cull, const float *__restrict__ gimg, float4 *__restrict__ partials) {
   // per pixel: g = dL/dI and g cc (cc: column relative to the quadrant
   // centre), so the row loop accumulates with three FMAs per pixel
   __shared__ float4 s_g4_all[TPB][2][kTS * kTS / 4];
@@ -715,9 +737,11 @@ __global__ __launch_bounds__(kWave * TPB) __attribute__((amdgpu_waves_per_eu(7, 
       const float4 c = make_float4(ra.z, ra.w, rb.x, rb.y);
       const float2 q = make_float2(ra.x, ra.y);
       slot = __float_as_uint(rb.z) + uint32_t(ty) * __float_as_uint(rb.w) + uint32_t(tx);
-      s_cw[lane] = c;
+      // the pixel loop needs no weight: the record's support threshold takes its place
+      const float thr_r = support_thr(thr, log2_tau, c.w);
+      s_cw[lane] = make_float4(c.x, c.y, c.z, thr_r);
       s_xy[lane] = q;
-      mask = no_cull ? 0xFu : quad_mask(c, q.x, q.y, tx0, ty0, thr_cull);
+      mask = no_cull ? 0xFu : quad_mask(c, q.x, q.y, tx0, ty0, thr_r * kCullSlack);
     }
     // one list of (quadrant << 6 | batch slot) entries, quadrant-major; gpk
     // holds this lane's record's position in it for each quadrant (8 bits each)
@@ -783,7 +807,7 @@ __global__ __launch_bounds__(kWave * TPB) __attribute__((amdgpu_waves_per_eu(7, 
           for (int u = 0; u < 4; ++u) {
             const float cc = float(qd * 4 + u) - 3.5f;
             const float arg = fmaf(cc, fmaf(c.x, cc, brow), drow);
-            const float ex = (arg >= thr) ? __builtin_amdgcn_exp2f(arg) : 0.f;
+            const float ex = (arg >= c.w) ? __builtin_amdgcn_exp2f(arg) : 0.f;
             A[qd * 4 + u] = fmaf(G0[u], ex, A[qd * 4 + u]);
             R0 = fmaf(G0[u], ex, R0);
             R1 = fmaf(G1[u], ex, R1);
@@ -1508,6 +1532,10 @@ int validate(const fgs_gaussians *g, const fgs_geom *geom, int32_t view_begin, i
   if (o->model != FGS_MODEL_SPLAT && o->model != FGS_MODEL_RAY_EXACT) return fail(FGS_E_INVALID, "opts.model");
   if (o->model == FGS_MODEL_RAY_EXACT && o->ablate)
     return fail(FGS_E_UNSUPPORTED, "the ablation switches apply to the splat model only");
+  if (!(o->density_aabb_tau >= 0.f) || !std::isfinite(o->density_aabb_tau))
+    return fail(FGS_E_INVALID, "density_aabb_tau must be finite and >= 0");
+  if (o->density_aabb_tau > 0.f && (o->model == FGS_MODEL_RAY_EXACT || o->ablate))
+    return fail(FGS_E_UNSUPPORTED, "the density-aware support applies to the splat model without ablation switches");
   return FGS_OK;
 }
 
@@ -1541,6 +1569,7 @@ GeomDev make_geom_dev(const fgs_geom *geom, const fgs_opts *o, int view_begin, c
   G.cv = 0.5f * float(geom->det_h) + geom->off_v;
   G.near_plane = o->near_plane;
   G.kappa = o->kappa;
+  G.tau = o->density_aabb_tau;
   G.ablate = o->ablate;
   G.angles = geom->angles;
   return G;
@@ -1650,6 +1679,7 @@ extern "C" int fgs_project_views_fwd(const fgs_gaussians *g, const fgs_geom *geo
   float *part = chunks > 1 ? at<float>(b, (L.total + 255) / 256 * 256) : img;
   const uint32_t *sv = at<uint32_t>(b, L.sorted_in_alt ? L.vals_alt : L.vals);
   const float thr = -0.5f * kLog2e * opts->kappa * opts->kappa;
+  const float log2_tau = opts->density_aabb_tau > 0.f ? log2f(opts->density_aabb_tau) : -INFINITY;
   hipEvent_t *ev = static_cast<hipEvent_t *>(opts->events);
   if (ev) FGS_HIP(hipEventRecord(ev[0], s));
   const uint64_t units = L.T * uint64_t(chunks);
@@ -1670,11 +1700,11 @@ extern "C" int fgs_project_views_fwd(const fgs_gaussians *g, const fgs_geom *geo
       if (interior)
         splat_fwd_kernel<false, true, TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
             at<uint2>(b, L.rng), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
-            uint32_t(L.T), chunks, thr, thr * kCullSlack, thr * kInteriorSlack, no_cull, part, nullptr);
+            uint32_t(L.T), chunks, thr, log2_tau, no_cull, part, nullptr);
       else
         splat_fwd_kernel<false, false, TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
             at<uint2>(b, L.rng), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
-            uint32_t(L.T), chunks, thr, thr * kCullSlack, thr * kInteriorSlack, no_cull, part, nullptr);
+            uint32_t(L.T), chunks, thr, log2_tau, no_cull, part, nullptr);
     }, L.K >= kSmallBlockKeysPerTile * L.T);
     FGS_LAUNCH_CHECK("splat_fwd_kernel");
   }
@@ -1702,6 +1732,7 @@ extern "C" int fgs_project_views_support(const fgs_gaussians *g, const fgs_geom 
   FGS_LAUNCH_CHECK("zero_u64_kernel");
   const uint32_t *sv = at<uint32_t>(b, L.sorted_in_alt ? L.vals_alt : L.vals);
   const float thr = -0.5f * kLog2e * opts->kappa * opts->kappa;
+  const float log2_tau = opts->density_aabb_tau > 0.f ? log2f(opts->density_aabb_tau) : -INFINITY;
   const TileGrid tg = tile_grid(geom->det_w, geom->det_h);
   const int chunks = chunks_per_tile(L.T);
   const uint64_t units = L.T * uint64_t(chunks);
@@ -1720,7 +1751,7 @@ extern "C" int fgs_project_views_support(const fgs_gaussians *g, const fgs_geom 
     constexpr int TPB = decltype(tpb)::value;
     splat_fwd_kernel<true, false, TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
         at<uint2>(b, L.rng), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
-        uint32_t(L.T), chunks, thr, thr * kCullSlack, thr * kInteriorSlack, 0, nullptr, cnt);
+        uint32_t(L.T), chunks, thr, log2_tau, 0, nullptr, cnt);
   }, L.K >= kSmallBlockKeysPerTile * L.T);
   FGS_LAUNCH_CHECK("splat_fwd_kernel<count>");
   return FGS_OK;
@@ -1752,6 +1783,7 @@ extern "C" int fgs_project_views_bwd(const fgs_gaussians *g, const fgs_geom *geo
   GeomDev G = make_geom_dev(geom, opts, view_begin, tg);
   const uint32_t *sv = at<uint32_t>(b, L.sorted_in_alt ? L.vals_alt : L.vals);
   const float thr = -0.5f * kLog2e * opts->kappa * opts->kappa;
+  const float log2_tau = opts->density_aabb_tau > 0.f ? log2f(opts->density_aabb_tau) : -INFINITY;
   hipEvent_t *ev = static_cast<hipEvent_t *>(opts->events);
   if (ev) FGS_HIP(hipEventRecord(ev[0], s));
   if (use_exact(geom, opts)) {
@@ -1797,7 +1829,7 @@ extern "C" int fgs_project_views_bwd(const fgs_gaussians *g, const fgs_geom *geo
       constexpr int TPB = decltype(tpb)::value;
       splat_bwd_kernel<TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
           at<uint2>(b, L.rng), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
-          uint32_t(L.T), chunks, thr, thr * kCullSlack, (opts->ablate & FGS_ABLATE_QUADRANT_CULL) ? 1 : 0,
+          uint32_t(L.T), chunks, thr, log2_tau, (opts->ablate & FGS_ABLATE_QUADRANT_CULL) ? 1 : 0,
           grad_img, at<float4>(b, L.partials));
     }, true);
     FGS_LAUNCH_CHECK("splat_bwd_kernel");
@@ -1814,6 +1846,34 @@ extern "C" int fgs_project_views_bwd(const fgs_gaussians *g, const fgs_geom *geo
 }
 
 namespace fgs {
+// Workspace of a rasterizer call over R records and T tiles: bytes that do
+// not depend on the number of (tile, Gaussian) pairs K, and an upper bound
+// on the bytes per pair (fixed + K * per_key covers every K). The forward of
+// a call with few tiles also keeps one partial image per chunk.
+int rast_workspace_bytes(const fgs_gaussians *g, const fgs_geom *geom, int32_t view_count, const fgs_opts *o,
+                         bool forward, uint64_t *fixed_bytes, uint64_t *bytes_per_key) {
+  if (!g || !geom || !o || g->n <= 0 || view_count <= 0 || view_count > geom->n_views || geom->det_w <= 0 ||
+      geom->det_h <= 0)
+    return fail(FGS_E_INVALID, "workspace query: null argument, no Gaussians, detector size or view count");
+  if (o->model != FGS_MODEL_SPLAT && o->model != FGS_MODEL_RAY_EXACT) return fail(FGS_E_INVALID, "opts.model");
+  const TileGrid tg = tile_grid(geom->det_w, geom->det_h);
+  const uint64_t R = uint64_t(view_count) * uint64_t(g->n);
+  const uint64_t T = uint64_t(view_count) * uint64_t(tg.tpv);
+  const bool exact = use_exact(geom, o);
+  const int bits = bits_for(uint64_t(tg.tpv));
+  const uint64_t k_ref = uint64_t(1) << 24;
+  const uint64_t base = rast_layout(R, T, 0, exact, bits).total;
+  const uint64_t big = rast_layout(R, T, k_ref, exact, bits).total;
+  const int chunks = chunks_per_tile(T);
+  const uint64_t n_img = uint64_t(view_count) * uint64_t(geom->det_w) * uint64_t(geom->det_h);
+  const uint64_t part = (forward && chunks > 1) ? uint64_t(chunks) * n_img * sizeof(float) + 256 : 0;
+  // every array the pair count sizes is padded to 256 bytes: 8 arrays at most
+  // (a call first asks for the per-record arrays plus 1 MiB before it knows K)
+  *fixed_bytes = base + part + 8 * kAlign + (uint64_t(1) << 20);
+  *bytes_per_key = (big - base + k_ref - 1) / k_ref;
+  return FGS_OK;
+}
+
 int rast_binning_layout(const fgs_workspace *ws, uint64_t off[9], uint64_t counts[3]) {
   RastLayout L = rast_layout(ws->n_records, ws->n_tiles, ws->n_pairs, ws->kind == 3, ws->tile_bits);
   off[0] = L.xy;

@@ -36,6 +36,7 @@ struct GeomDev {
   float cu, cv;        // principal point (pixels)
   float near_plane;
   float kappa;
+  float tau;           // density-aware support threshold (0 = off)
   int ablate;          // FGS_ABLATE_* bits (measurement only)
   const float *angles;
 };

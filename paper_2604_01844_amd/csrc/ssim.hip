@@ -212,85 +212,172 @@ extern "C" int fgs_ssim_loss_grad(const float *img, const float *gt, int32_t W, 
 
 // ---------------------------------------------------------------------------
 // 3D SSIM (the fitting loss of Eq. 6): the same per-voxel formula with the
-// separable 11^3 window, as three 1D passes (x, then y, then z) over
-// channel-major volumes, one thread per output voxel and all channels; no
-// atomics (block partial sums for the mean).
+// separable 11^3 window, fused along z with a ring of filtered slices (the
+// paper's z-buffered 3D SSIM, Sec. 3.5, laid out for 64-wide wavefronts).
+//
+// A workgroup owns a 16 x 16 column of voxels over a chunk of kZC output
+// slices. It walks the input slices of its chunk (plus the 5-slice halo on
+// each side) one at a time: the slice's 26 x 26 neighbourhood is staged in
+// LDS, filtered along x, then along y (each thread one column of the 16 x 16
+// tile), and the thread keeps the last 11 filtered slices in registers (the
+// ring; the loop is unrolled by 11 so every ring slot is a fixed register).
+// Once 11 slices are in, the z filter of the middle slice is a weighted sum
+// over the ring. Two such kernels:
+//   stats: the five statistics from x and y, 1 - SSIM (workgroup partial
+//          sums, no atomics) and the three G maps;
+//   grad:  the windowed sums of the G maps (same structure, three channels)
+//          and the gradient.
+// Every filter is x, then y, then z, taps in window order, so the result is
+// deterministic.
 
 namespace fgs {
 namespace {
 
-// out[c][i] = sum_k w[k] in_c(i + (k - 5) e_axis), zero outside the grid.
-// first pass (products != 0): the 5 channels are formed from x and y:
-// x, y, x^2, y^2, x y.
+constexpr int kST = 16;              // tile side (x, y)
+constexpr int kSH = kST + 2 * kR;    // staged side (26)
+constexpr int kZC = 64;              // output slices per workgroup
+constexpr int kST2 = kST * kST;      // 256 threads, one column each
+
+// One input slice zi through the x and y filters: the thread's column gets
+// f[c] for the CH channels. PRODUCTS: channels x, y, x^2, y^2, x y formed
+// from a and b; else the CH channels are a[0..CH) with stride n. Slices
+// outside the grid are zero. Contains barriers: every thread calls it.
 template <int CH, bool PRODUCTS>
-__global__ __launch_bounds__(256) void sep_pass_kernel(const float *__restrict__ in, const float *__restrict__ y_in,
-                                                       int nx, int ny, int nz, int axis, Window win,
-                                                       float *__restrict__ out) {
-  const uint64_t n = uint64_t(nx) * ny * nz;
-  const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int x = int(i % uint64_t(nx));
-  const int yy = int((i / uint64_t(nx)) % uint64_t(ny));
-  const int z = int(i / (uint64_t(nx) * ny));
-  const int pos = axis == 0 ? x : (axis == 1 ? yy : z);
-  const int len = axis == 0 ? nx : (axis == 1 ? ny : nz);
-  const int64_t stride = axis == 0 ? 1 : (axis == 1 ? int64_t(nx) : int64_t(nx) * ny);
-  float acc[CH];
+__device__ __forceinline__ void slice_filter_2d(const float *__restrict__ a, const float *__restrict__ b, uint64_t n,
+                                                int nx, int ny, int nz, int x0, int y0, int zi, const Window &win,
+                                                float (*sp)[kSH][kSH + 1], float (*sh)[kSH][kST + 1], float f[CH]) {
+  const bool inside = zi >= 0 && zi < nz;  // uniform over the workgroup
+  if (!inside) {
 #pragma unroll
-  for (int c = 0; c < CH; ++c) acc[c] = 0.f;
-#pragma unroll
-  for (int k = 0; k < kWin; ++k) {
-    const int p = pos + k - kR;
-    if (p < 0 || p >= len) continue;
-    const uint64_t j = uint64_t(int64_t(i) + int64_t(k - kR) * stride);
-    const float wk = win.w[k];
+    for (int c = 0; c < CH; ++c) f[c] = 0.f;
+    return;
+  }
+  __syncthreads();  // the previous slice's reads of sp and sh are done
+  const uint64_t zoff = uint64_t(zi) * uint64_t(nx) * uint64_t(ny);
+  for (int i = threadIdx.x; i < kSH * kSH; i += kST2) {
+    const int r = i / kSH, c = i - r * kSH;
+    const int gx = x0 - kR + c, gy = y0 - kR + r;
+    const bool in = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+    const uint64_t q = zoff + uint64_t(gy) * uint64_t(nx) + uint64_t(gx);
     if (PRODUCTS) {
-      const float xv = in[j], yv = y_in[j];
-      acc[0] = fmaf(wk, xv, acc[0]);
-      acc[1] = fmaf(wk, yv, acc[1]);
-      acc[2] = fmaf(wk * xv, xv, acc[2]);
-      acc[3] = fmaf(wk * yv, yv, acc[3]);
-      acc[4] = fmaf(wk * xv, yv, acc[4]);
+      const float xv = in ? a[q] : 0.f, yv = in ? b[q] : 0.f;
+      sp[0][r][c] = xv;
+      sp[1][r][c] = yv;
+      sp[2][r][c] = xv * xv;
+      sp[3][r][c] = yv * yv;
+      sp[4][r][c] = xv * yv;
     } else {
 #pragma unroll
-      for (int c = 0; c < CH; ++c) acc[c] = fmaf(wk, in[uint64_t(c) * n + j], acc[c]);
+      for (int ch = 0; ch < CH; ++ch) sp[ch][r][c] = in ? a[uint64_t(ch) * n + q] : 0.f;
     }
   }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kSH * kST; i += kST2) {
+    const int r = i / kST, c = i - r * kST;
+    float acc[CH];
 #pragma unroll
-  for (int c = 0; c < CH; ++c) out[uint64_t(c) * n + i] = acc[c];
+    for (int ch = 0; ch < CH; ++ch) acc[ch] = 0.f;
+#pragma unroll
+    for (int k = 0; k < kWin; ++k)
+#pragma unroll
+      for (int ch = 0; ch < CH; ++ch) acc[ch] = fmaf(win.w[k], sp[ch][r][c + k], acc[ch]);
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) sh[ch][r][c] = acc[ch];
+  }
+  __syncthreads();
+  const int tx = threadIdx.x & (kST - 1), ty = threadIdx.x / kST;
+#pragma unroll
+  for (int ch = 0; ch < CH; ++ch) f[ch] = 0.f;
+#pragma unroll
+  for (int k = 0; k < kWin; ++k)
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) f[ch] = fmaf(win.w[k], sh[ch][ty + k][tx], f[ch]);
 }
 
-// From the windowed statistics m[5][n]: SSIM partial sums and G maps g[3][n].
-__global__ __launch_bounds__(256) void ssim_map_kernel(const float *__restrict__ m, uint64_t n, float c1, float c2,
-                                                       float *__restrict__ g, float *__restrict__ partial) {
-  __shared__ float sh[kThreads / 64];
+// Walks input slices z0 - 5 .. z1 + 4 of the workgroup's chunk [z0, z1): ring
+// slot j of the unrolled loop holds input slice base + j. After the slice
+// k (counted from the chunk's first input slice) is filtered, output slice
+// z0 + k - 10 is complete: emit(zo, m) receives its z-filtered channels.
+template <int CH, bool PRODUCTS, typename Emit>
+__device__ __forceinline__ void zring_walk(const float *__restrict__ a, const float *__restrict__ b, uint64_t n,
+                                           int nx, int ny, int nz, int x0, int y0, int z0, int z1,
+                                           const Window &win, float (*sp)[kSH][kSH + 1],
+                                           float (*sh)[kSH][kST + 1], Emit &&emit) {
+  float ring[kWin][CH];
+  const int n_in = (z1 - z0) + 2 * kR;
+  for (int base = 0; base < n_in; base += kWin) {
+#pragma unroll
+    for (int j = 0; j < kWin; ++j) {
+      const int k = base + j;
+      if (k >= n_in) break;  // uniform over the workgroup
+      slice_filter_2d<CH, PRODUCTS>(a, b, n, nx, ny, nz, x0, y0, z0 - kR + k, win, sp, sh, ring[j]);
+      if (k >= 2 * kR) {
+        float m[CH];
+#pragma unroll
+        for (int ch = 0; ch < CH; ++ch) m[ch] = 0.f;
+#pragma unroll
+        for (int t = 0; t < kWin; ++t) {
+          const int slot = (j + 1 + t) % kWin;  // input slice k - 10 + t
+#pragma unroll
+          for (int ch = 0; ch < CH; ++ch) m[ch] = fmaf(win.w[t], ring[slot][ch], m[ch]);
+        }
+        emit(z0 + k - 2 * kR, m);
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(kST2) void ssim3d_stats_kernel(const float *__restrict__ vol,
+                                                            const float *__restrict__ gt, int nx, int ny, int nz,
+                                                            Window win, float c1, float c2,
+                                                            float *__restrict__ g, float *__restrict__ partial) {
+  __shared__ float sp[5][kSH][kSH + 1];
+  __shared__ float sh[5][kSH][kST + 1];
+  __shared__ float sw[kST2 / 64];
+  const uint64_t n = uint64_t(nx) * uint64_t(ny) * uint64_t(nz);
+  const int x0 = blockIdx.x * kST, y0 = blockIdx.y * kST;
+  const int z0 = blockIdx.z * kZC, z1 = min(z0 + kZC, nz);
+  const int X = x0 + int(threadIdx.x & (kST - 1)), Y = y0 + int(threadIdx.x / kST);
+  const bool mine = X < nx && Y < ny;
   CompSum acc;
-  for (uint64_t i = uint64_t(blockIdx.x) * kThreads + threadIdx.x; i < n; i += uint64_t(gridDim.x) * kThreads) {
-    const float mx = m[i], my = m[n + i];
+  zring_walk<5, true>(vol, gt, n, nx, ny, nz, x0, y0, z0, z1, win, sp, sh, [&](int zo, const float *m) {
+    if (!mine) return;
+    const float mx = m[0], my = m[1];
     const float A = fmaf(2.f * mx, my, c1);
-    const float B = fmaf(2.f, m[4 * n + i] - mx * my, c2);
+    const float B = fmaf(2.f, m[4] - mx * my, c2);
     const float C = fmaf(mx, mx, fmaf(my, my, c1));
-    const float D = (m[2 * n + i] - mx * mx) + (m[3 * n + i] - my * my) + c2;
+    const float D = (m[2] - mx * mx) + (m[3] - my * my) + c2;
     const float CD = C * D;
     const float S = A * B / CD;
     acc.add(1.f - S);
     if (g) {
-      g[i] = 2.f * my * (B - A) / CD - S * (2.f * mx / C - 2.f * mx / D);
-      g[n + i] = -S / D;
-      g[2 * n + i] = 2.f * A / CD;
+      const uint64_t q = (uint64_t(zo) * uint64_t(ny) + uint64_t(Y)) * uint64_t(nx) + uint64_t(X);
+      g[q] = 2.f * my * (B - A) / CD - S * (2.f * mx / C - 2.f * mx / D);
+      g[n + q] = -S / D;
+      g[2 * n + q] = 2.f * A / CD;
     }
-  }
-  const float t = block_sum_f32<kThreads>(acc.value(), sh);
-  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+  });
+  const float t = block_sum_f32<kST2>(acc.value(), sw);
+  if (threadIdx.x == 0) partial[(uint64_t(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = t;
 }
 
-__global__ __launch_bounds__(256) void ssim_combine_kernel(const float *__restrict__ vol, const float *__restrict__ gt,
-                                                           const float *__restrict__ cg, uint64_t n, float coef,
+__global__ __launch_bounds__(kST2) void ssim3d_grad_kernel(const float *__restrict__ vol,
+                                                           const float *__restrict__ gt, int nx, int ny, int nz,
+                                                           Window win, const float *__restrict__ g, float coef,
                                                            int accumulate, float *__restrict__ grad) {
-  const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float gq = coef * (cg[i] + 2.f * vol[i] * cg[n + i] + gt[i] * cg[2 * n + i]);
-  grad[i] = accumulate ? grad[i] + gq : gq;
+  __shared__ float sp[3][kSH][kSH + 1];
+  __shared__ float sh[3][kSH][kST + 1];
+  const uint64_t n = uint64_t(nx) * uint64_t(ny) * uint64_t(nz);
+  const int x0 = blockIdx.x * kST, y0 = blockIdx.y * kST;
+  const int z0 = blockIdx.z * kZC, z1 = min(z0 + kZC, nz);
+  const int X = x0 + int(threadIdx.x & (kST - 1)), Y = y0 + int(threadIdx.x / kST);
+  const bool mine = X < nx && Y < ny;
+  zring_walk<3, false>(g, nullptr, n, nx, ny, nz, x0, y0, z0, z1, win, sp, sh, [&](int zo, const float *m) {
+    if (!mine) return;
+    const uint64_t q = (uint64_t(zo) * uint64_t(ny) + uint64_t(Y)) * uint64_t(nx) + uint64_t(X);
+    const float gq = coef * (m[0] + 2.f * vol[q] * m[1] + gt[q] * m[2]);
+    grad[q] = accumulate ? grad[q] + gq : gq;
+  });
 }
 
 }  // namespace
@@ -304,36 +391,29 @@ extern "C" int fgs_ssim3d_loss_grad(const float *vol, const float *gt, const int
   if (!(c1 > 0.f) || !(c2 > 0.f)) return fail(FGS_E_INVALID, "c1 and c2 must be > 0");
   const int nx = dims[0], ny = dims[1], nz = dims[2];
   const uint64_t n = uint64_t(nx) * ny * nz;
-  const int nb = int(std::min<uint64_t>((n + kThreads - 1) / kThreads, 1024));
+  const dim3 grid(unsigned((nx + kST - 1) / kST), unsigned((ny + kST - 1) / kST), unsigned((nz + kZC - 1) / kZC));
+  if (grid.y > 65535 || grid.z > 65535) return fail(FGS_E_UNSUPPORTED, "grid too large");
+  const uint64_t nb = uint64_t(grid.x) * grid.y * grid.z;
   Carver c(nullptr);
-  uint64_t o_a, o_b, o_part;
-  c.take<float>(5 * n, &o_a);
-  c.take<float>(5 * n, &o_b);
-  c.take<float>(uint64_t(nb), &o_part);
+  uint64_t o_g, o_part;
+  c.take<float>(grad ? 3 * n : 0, &o_g);
+  c.take<float>(nb, &o_part);
   ws->needed = c.used;
   if (!ws->ptr || ws->bytes < ws->needed) return fail(FGS_E_CAPACITY, "workspace too small");
   ws->kind = 0;
   char *b = static_cast<char *>(ws->ptr);
-  float *ba = reinterpret_cast<float *>(b + o_a), *bb = reinterpret_cast<float *>(b + o_b);
+  float *g = grad ? reinterpret_cast<float *>(b + o_g) : nullptr;
   float *partial = reinterpret_cast<float *>(b + o_part);
   const Window win = gaussian_window();
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const unsigned g1 = grid_for(n, 256);
-  sep_pass_kernel<5, true><<<g1, 256, 0, s>>>(vol, gt, nx, ny, nz, 0, win, ba);
-  sep_pass_kernel<5, false><<<g1, 256, 0, s>>>(ba, nullptr, nx, ny, nz, 1, win, bb);
-  sep_pass_kernel<5, false><<<g1, 256, 0, s>>>(bb, nullptr, nx, ny, nz, 2, win, ba);
-  FGS_LAUNCH_CHECK("sep_pass_kernel");
-  ssim_map_kernel<<<nb, kThreads, 0, s>>>(ba, n, c1, c2, grad ? bb : nullptr, partial);
-  FGS_LAUNCH_CHECK("ssim_map_kernel");
-  ssim_finish_kernel<<<1, kThreads, 0, s>>>(partial, nb, float(double(scale) / double(n)), loss);
+  ssim3d_stats_kernel<<<grid, kST2, 0, s>>>(vol, gt, nx, ny, nz, win, c1, c2, g, partial);
+  FGS_LAUNCH_CHECK("ssim3d_stats_kernel");
+  ssim_finish_kernel<<<1, kThreads, 0, s>>>(partial, int(nb), float(double(scale) / double(n)), loss);
   FGS_LAUNCH_CHECK("ssim_finish_kernel");
   if (grad) {
-    sep_pass_kernel<3, false><<<g1, 256, 0, s>>>(bb, nullptr, nx, ny, nz, 0, win, ba);
-    sep_pass_kernel<3, false><<<g1, 256, 0, s>>>(ba, nullptr, nx, ny, nz, 1, win, bb);
-    sep_pass_kernel<3, false><<<g1, 256, 0, s>>>(bb, nullptr, nx, ny, nz, 2, win, ba);
-    FGS_LAUNCH_CHECK("sep_pass_kernel");
-    ssim_combine_kernel<<<g1, 256, 0, s>>>(vol, gt, ba, n, float(-double(scale) / double(n)), accumulate, grad);
-    FGS_LAUNCH_CHECK("ssim_combine_kernel");
+    ssim3d_grad_kernel<<<grid, kST2, 0, s>>>(vol, gt, nx, ny, nz, win, g, float(-double(scale) / double(n)),
+                                             accumulate, grad);
+    FGS_LAUNCH_CHECK("ssim3d_grad_kernel");
   }
   return FGS_OK;
 }

@@ -39,18 +39,19 @@ struct GridDev {
   int dims[3];
   int nt[3];               // tiles per axis
   float kappa;
+  float tau;               // density-aware support threshold (0 = off)
 };
 
-// Voxel-unit quantities of one Gaussian: W = diag(1/h) R diag(1/s) is such
+// Voxel-unit quantities of one Gaussian: W = diag(h) R diag(1/s) is such
 // that A_vox = W W^T is the inverse covariance in voxel-index units.
 struct VoxGauss {
   float pv[3];             // centre in voxel-index coordinates
   float W[3][3];
   float A[3][3];
-  float r[3];              // kappa-sigma half-extents in voxels
+  float r[3];              // kap-sigma half-extents in voxels
 };
 
-__device__ __forceinline__ void vox_gauss(const GaussParams &P, const GridDev &G, VoxGauss &V) {
+__device__ __forceinline__ void vox_gauss(const GaussParams &P, const GridDev &G, float kap, VoxGauss &V) {
   for (int a = 0; a < 3; ++a) {
     V.pv[a] = (P.p[a] - G.origin[a]) / G.h[a] - 0.5f;
     float var = 0.f;
@@ -59,7 +60,7 @@ __device__ __forceinline__ void vox_gauss(const GaussParams &P, const GridDev &G
       const float rs = P.R[3 * a + j] * P.s[j];
       var += rs * rs;
     }
-    V.r[a] = G.kappa * sqrtf(var) / G.h[a];
+    V.r[a] = kap * sqrtf(var) / G.h[a];
   }
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b)
@@ -76,10 +77,13 @@ __device__ __forceinline__ void vox_span(float c, float r, int n_tiles, int &t0,
 }
 
 constexpr int kTotalSlots = 64;
-// The tile culling test keeps tiles whose best voxel centre reaches thr *
-// kCullSlack (a Mahalanobis radius 0.05% beyond the support): a superset of
-// the per-voxel test.
+// The tile culling test keeps tiles whose best voxel centre has
+// d^2 <= k2 + kappa^2 (kCullSlack - 1), k2 the Gaussian's support bound (a
+// Mahalanobis radius about 0.05% beyond the kappa support): a superset of the
+// per-voxel test. On the pre-scaled exponent: arg >= thr_g + thr_widen, with
+// thr_g the Gaussian's threshold (a1.z) and thr_widen = thr (kCullSlack - 1).
 constexpr float kCullSlack = 1.001f;
+constexpr float kLn2 = 0.6931471805599453f;
 
 __global__ void zero_u64_kernel(unsigned long long *p, int n) {
   if (int(threadIdx.x) < n) p[threadIdx.x] = 0ull;
@@ -95,15 +99,32 @@ __global__ __launch_bounds__(256) void vox_record_kernel(fgs_gaussians g, GridDe
   if (i < g.n) {
     GaussParams P;
     load_gauss(g, i, P);
-    VoxGauss V;
-    vox_gauss(P, G, V);
+    // support on the pre-scaled exponent arg = -log2(e)/2 d^2: arg >= thr_g,
+    // thr_g = -log2(e)/2 kappa^2, raised to log2(tau / rho) by the
+    // density-aware support (d^2 <= min(kappa^2, 2 ln(rho / tau)), Sec. 3.5
+    // boxes that also take the density into account); a Gaussian with
+    // rho <= tau is left out
     const float k = -0.5f * kLog2e;
+    float kap = G.kappa, thr_g = k * G.kappa * G.kappa;
+    bool dropped = false;
+    if (G.tau > 0.f) {
+      if (P.rho > G.tau) {
+        const float l2 = log2f(P.rho) - log2f(G.tau);
+        thr_g = fmaxf(thr_g, -l2);
+        const float k2t = 2.f * kLn2 * l2;
+        if (k2t < kap * kap) kap = sqrtf(k2t);
+      } else {
+        dropped = true;
+      }
+    }
+    VoxGauss V;
+    vox_gauss(P, G, kap, V);
     prho[i] = make_float4(V.pv[0], V.pv[1], V.pv[2], P.rho);
     a0[i] = make_float4(k * V.A[0][0], 2.f * k * V.A[0][1], 2.f * k * V.A[0][2], k * V.A[1][1]);
-    a1[i] = make_float4(2.f * k * V.A[1][2], k * V.A[2][2], 0.f, 0.f);
+    a1[i] = make_float4(2.f * k * V.A[1][2], k * V.A[2][2], thr_g, 0.f);
     radii[i] = make_float4(V.r[0], V.r[1], V.r[2], 0.f);
     int t0[3], t1[3];
-    bool empty = false;
+    bool empty = dropped;
     for (int a = 0; a < 3; ++a) {
       vox_span(V.pv[a], V.r[a], G.nt[a], t0[a], t1[a]);
       empty |= t0[a] > t1[a];
@@ -195,7 +216,7 @@ constexpr int kHitWords = 8;
 __global__ __launch_bounds__(256) void vox_count_kernel(int64_t n, const float4 *__restrict__ prho,
                                                         const float4 *__restrict__ a0,
                                                         const float4 *__restrict__ a1,
-                                                        const Rect3 *__restrict__ rect, float thr_cull,
+                                                        const Rect3 *__restrict__ rect, float thr_widen,
                                                         uint32_t *__restrict__ count,
                                                         unsigned long long *__restrict__ total64,
                                                         unsigned long long *__restrict__ hits) {
@@ -205,6 +226,7 @@ __global__ __launch_bounds__(256) void vox_count_kernel(int64_t n, const float4 
   const Rect3 rc = rect[i];
   const uint32_t nt = rect_tiles(rc);
   const float4 p = prho[i], c0 = a0[i], c1 = a1[i];
+  const float thr_cull = c1.z + thr_widen;
   uint32_t cnt = 0;
   for (uint32_t j0 = 0; j0 < nt; j0 += 64) {
     const uint32_t j = j0 + lane;
@@ -227,7 +249,7 @@ __global__ __launch_bounds__(256) void vox_count_kernel(int64_t n, const float4 
 __global__ __launch_bounds__(256) void vox_emit_kernel(int64_t n, int ntx, int nty, const float4 *__restrict__ prho,
                                                        const float4 *__restrict__ a0,
                                                        const float4 *__restrict__ a1,
-                                                       const Rect3 *__restrict__ rect, float thr_cull,
+                                                       const Rect3 *__restrict__ rect, float thr_widen,
                                                        const uint32_t *__restrict__ offset,
                                                        const unsigned long long *__restrict__ hits,
                                                        uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
@@ -240,6 +262,7 @@ __global__ __launch_bounds__(256) void vox_emit_kernel(int64_t n, int ntx, int n
   const Rect3 rc = rect[i];
   const uint32_t nt = rect_tiles(rc);
   const float4 p = prho[i], c0 = a0[i], c1 = a1[i];
+  const float thr_cull = c1.z + thr_widen;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const bool stored = nt <= 64u * kHitWords;  // the count kept this rectangle's ballots
   for (uint32_t j0 = 0; j0 < nt; j0 += 64) {
@@ -281,7 +304,7 @@ __global__ __launch_bounds__(kWave * TPB) void vox_fwd_kernel(const uint32_t *__
                                                          const float4 *__restrict__ a0,
                                                          const float4 *__restrict__ a1,
                                                          const uint32_t *__restrict__ gid, GridDev G,
-                                                         uint32_t n_tiles, int n_chunks, float thr,
+                                                         uint32_t n_tiles, int n_chunks,
                                                          float *__restrict__ vol,
                                                          unsigned long long *__restrict__ counter) {
   __shared__ float4 s_all[TPB][3][kWave];
@@ -331,10 +354,10 @@ __global__ __launch_bounds__(kWave * TPB) void vox_fwd_kernel(const uint32_t *__
         const float fk = float(k);
         const float arg = (k == 0) ? arg0 : fmaf(fk, fmaf(c0.x, fk, E), arg0);
         if (kCount) {
-          acc[k] += (arg >= thr) ? 1.f : 0.f;
+          acc[k] += (arg >= c1.z) ? 1.f : 0.f;
         } else {
           const float ex = __builtin_amdgcn_exp2f(arg);
-          acc[k] = fmaf(p.w, (arg >= thr) ? ex : 0.f, acc[k]);
+          acc[k] = fmaf(p.w, (arg >= c1.z) ? ex : 0.f, acc[k]);
         }
       }
     }
@@ -377,7 +400,7 @@ __global__ __launch_bounds__(kWave * TPB) void vox_bwd_kernel(const uint32_t *__
                                                          const float4 *__restrict__ a0,
                                                          const float4 *__restrict__ a1,
                                                          const uint32_t *__restrict__ gid,
-                                                         GridDev G, uint32_t n_tiles, int n_chunks, float thr,
+                                                         GridDev G, uint32_t n_tiles, int n_chunks,
                                                          const float *__restrict__ gvol,
                                                          float2 *__restrict__ partials) {
   __shared__ float4 s_g4_all[TPB][2][kVT * kVT * kVT / 4];
@@ -449,7 +472,7 @@ __global__ __launch_bounds__(kWave * TPB) void vox_bwd_kernel(const uint32_t *__
           for (int u = 0; u < 4; ++u) {
             const float cx = float(qd * 4 + u) - h;
             const float arg = fmaf(cx, fmaf(c0.x, cx, brow), drow);
-            const float ex = (arg >= thr) ? __builtin_amdgcn_exp2f(arg) : 0.f;
+            const float ex = (arg >= c1.z) ? __builtin_amdgcn_exp2f(arg) : 0.f;
             A[qd * 4 + u] = fmaf(G0[u], ex, A[qd * 4 + u]);
             R0 = fmaf(G0[u], ex, R0);
             R1 = fmaf(G1[u], ex, R1);
@@ -548,7 +571,7 @@ __global__ __launch_bounds__(256) void vox_grad_kernel(fgs_gaussians g, GridDev 
     GaussParams P;
     load_gauss(g, i, P);
     VoxGauss V;
-    vox_gauss(P, G, V);
+    vox_gauss(P, G, G.kappa, V);
     // s: S0, Sx, Sy, Sz, Sxx, Sxy, Sxz, Syy, Syz, Szz with d = voxel - centre
     const float rho = P.rho;
     const float Sd[3] = {s[1], s[2], s[3]};
@@ -645,6 +668,8 @@ int validate(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *o, fg
   }
   if (!(o->kappa > 0.f)) return fail(FGS_E_INVALID, "kappa must be > 0");
   if (o->model != 0) return fail(FGS_E_INVALID, "opts.model must be 0 for the voxelizer");
+  if (!(o->density_aabb_tau >= 0.f) || !std::isfinite(o->density_aabb_tau))
+    return fail(FGS_E_INVALID, "density_aabb_tau must be finite and >= 0");
   return FGS_OK;
 }
 
@@ -657,6 +682,7 @@ GridDev make_grid_dev(const fgs_grid *grid, const fgs_opts *o) {
     G.nt[a] = (grid->dims[a] + kVT - 1) / kVT;
   }
   G.kappa = o->kappa;
+  G.tau = o->density_aabb_tau;
   return G;
 }
 
@@ -681,9 +707,9 @@ int vox_build(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *o, f
                                                       at<float4>(b, L.a1), at<float4>(b, L.radii),
                                                       at<Rect3>(b, L.rect));
   FGS_LAUNCH_CHECK("vox_record_kernel");
-  const float thr_cull = -0.5f * kLog2e * o->kappa * o->kappa * kCullSlack;
+  const float thr_widen = -0.5f * kLog2e * o->kappa * o->kappa * (kCullSlack - 1.f);
   vox_count_kernel<<<grid_for(N, 4), 256, 0, s>>>(int64_t(N), at<float4>(b, L.prho), at<float4>(b, L.a0),
-                                                   at<float4>(b, L.a1), at<Rect3>(b, L.rect), thr_cull,
+                                                   at<float4>(b, L.a1), at<Rect3>(b, L.rect), thr_widen,
                                                    at<uint32_t>(b, L.offset), total64,
                                                    at<unsigned long long>(b, L.hits));
   FGS_LAUNCH_CHECK("vox_count_kernel");
@@ -706,7 +732,7 @@ int vox_build(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *o, f
   if (K > 0) {
     vox_emit_kernel<<<grid_for(N, 4), 256, 0, s>>>(int64_t(N), G.nt[0], G.nt[1], at<float4>(b, L.prho),
                                                     at<float4>(b, L.a0), at<float4>(b, L.a1), at<Rect3>(b, L.rect),
-                                                    thr_cull, at<uint32_t>(b, L.offset),
+                                                    thr_widen, at<uint32_t>(b, L.offset),
                                                     at<unsigned long long>(b, L.hits), at<uint32_t>(b, L.keys),
                                                     at<uint32_t>(b, L.vals), at<uint32_t>(b, L.gid));
     FGS_LAUNCH_CHECK("vox_emit_kernel");
@@ -725,6 +751,27 @@ int vox_build(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *o, f
 }
 
 }  // namespace
+
+// Workspace of a voxelizer call: as rast_workspace_bytes (the forward over
+// few tiles also keeps one partial volume per chunk).
+int vox_workspace_bytes(const fgs_gaussians *g, const fgs_grid *grid, bool forward, uint64_t *fixed_bytes,
+                        uint64_t *bytes_per_key) {
+  if (!g || !grid || g->n <= 0 || grid->dims[0] <= 0 || grid->dims[1] <= 0 || grid->dims[2] <= 0)
+    return fail(FGS_E_INVALID, "workspace query: null argument, no Gaussians or grid dims");
+  const uint64_t T = uint64_t((grid->dims[0] + kVT - 1) / kVT) * uint64_t((grid->dims[1] + kVT - 1) / kVT) *
+                     uint64_t((grid->dims[2] + kVT - 1) / kVT);
+  const uint64_t N = uint64_t(g->n);
+  const uint64_t k_ref = uint64_t(1) << 24;
+  const uint64_t base = vox_layout(N, T, 0).total;
+  const uint64_t big = vox_layout(N, T, k_ref).total;
+  const int chunks = chunks_per_tile(T);
+  const uint64_t n_vox = uint64_t(grid->dims[0]) * uint64_t(grid->dims[1]) * uint64_t(grid->dims[2]);
+  const uint64_t part = (forward && chunks > 1) ? uint64_t(chunks) * n_vox * sizeof(float) + 256 : 0;
+  // (a call first asks for the per-record arrays plus 1 MiB before it knows K)
+  *fixed_bytes = base + part + 8 * kAlign + (uint64_t(1) << 20);
+  *bytes_per_key = (big - base + k_ref - 1) / k_ref;
+  return FGS_OK;
+}
 
 int vox_binning_layout(const fgs_workspace *ws, uint64_t off[9], uint64_t counts[3]) {
   VoxLayout L = vox_layout(ws->n_records, ws->n_tiles, ws->n_pairs);
@@ -766,7 +813,6 @@ extern "C" int fgs_voxelize_fwd(const fgs_gaussians *g, const fgs_grid *grid, co
   void *b = ws->ptr;
   float *part = chunks > 1 ? at<float>(b, (L.total + 255) / 256 * 256) : vol;
   const uint32_t *sv = at<uint32_t>(b, L.sorted_in_alt ? L.vals_alt : L.vals);
-  const float thr = -0.5f * kLog2e * opts->kappa * opts->kappa;
   hipEvent_t *ev = static_cast<hipEvent_t *>(opts->events);
   if (ev) FGS_HIP(hipEventRecord(ev[0], s));
   const uint64_t units = L.T * uint64_t(chunks);
@@ -774,7 +820,7 @@ extern "C" int fgs_voxelize_fwd(const fgs_gaussians *g, const fgs_grid *grid, co
     constexpr int TPB = decltype(tpb)::value;
     vox_fwd_kernel<false, TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
         at<uint32_t>(b, L.start), sv, at<float4>(b, L.prho), at<float4>(b, L.a0), at<float4>(b, L.a1),
-        at<uint32_t>(b, L.gid), G, uint32_t(L.T), chunks, thr, part, nullptr);
+        at<uint32_t>(b, L.gid), G, uint32_t(L.T), chunks, part, nullptr);
   });
   FGS_LAUNCH_CHECK("vox_fwd_kernel");
   if (chunks > 1) {
@@ -800,14 +846,13 @@ extern "C" int fgs_voxelize_support(const fgs_gaussians *g, const fgs_grid *grid
   zero_u64_kernel<<<1, 1, 0, s>>>(cnt, 1);
   FGS_LAUNCH_CHECK("zero_u64_kernel");
   const uint32_t *sv = at<uint32_t>(b, L.sorted_in_alt ? L.vals_alt : L.vals);
-  const float thr = -0.5f * kLog2e * opts->kappa * opts->kappa;
   const int chunks = chunks_per_tile(L.T);
   const uint64_t units = L.T * uint64_t(chunks);
   with_tiles_per_block(units, [&](auto tpb) {
     constexpr int TPB = decltype(tpb)::value;
     vox_fwd_kernel<true, TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
         at<uint32_t>(b, L.start), sv, at<float4>(b, L.prho), at<float4>(b, L.a0), at<float4>(b, L.a1),
-        at<uint32_t>(b, L.gid), G, uint32_t(L.T), chunks, thr, nullptr, cnt);
+        at<uint32_t>(b, L.gid), G, uint32_t(L.T), chunks, nullptr, cnt);
   });
   FGS_LAUNCH_CHECK("vox_fwd_kernel<count>");
   return FGS_OK;
@@ -836,7 +881,6 @@ extern "C" int fgs_voxelize_bwd(const fgs_gaussians *g, const fgs_grid *grid, co
   }
   void *b = ws->ptr;
   const uint32_t *sv = at<uint32_t>(b, L.sorted_in_alt ? L.vals_alt : L.vals);
-  const float thr = -0.5f * kLog2e * opts->kappa * opts->kappa;
   hipEvent_t *ev = static_cast<hipEvent_t *>(opts->events);
   if (ev) FGS_HIP(hipEventRecord(ev[0], s));
   if (L.K > 0) {
@@ -846,7 +890,7 @@ extern "C" int fgs_voxelize_bwd(const fgs_gaussians *g, const fgs_grid *grid, co
       constexpr int TPB = decltype(tpb)::value;
       vox_bwd_kernel<TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
           at<uint32_t>(b, L.start), sv, at<float4>(b, L.prho), at<float4>(b, L.a0), at<float4>(b, L.a1),
-          at<uint32_t>(b, L.gid), G, uint32_t(L.T), chunks, thr, grad_vol, at<float2>(b, L.partials));
+          at<uint32_t>(b, L.gid), G, uint32_t(L.T), chunks, grad_vol, at<float2>(b, L.partials));
     });
     FGS_LAUNCH_CHECK("vox_bwd_kernel");
   }

@@ -140,10 +140,12 @@ def _model(model: str) -> int:
     return MODELS[model]
 
 
-def _opts(kappa, near, recompute=1, events=None, accumulate=0, ablate=0, model="splat") -> A.fgs_opts:
+def _opts(kappa, near, recompute=1, events=None, accumulate=0, ablate=0, model="splat", tau=0.0) -> A.fgs_opts:
     """events: optional pair of started torch.cuda.Event objects to record
-    around the call's pixel/voxel kernel."""
-    o = A.fgs_opts(float(kappa), float(near), int(recompute), int(accumulate), int(ablate), _model(model), None)
+    around the call's pixel/voxel kernel. tau > 0: the density-aware support
+    d^2 <= min(kappa^2, 2 ln(peak / tau)) (fgs_opts.density_aabb_tau)."""
+    o = A.fgs_opts(float(kappa), float(near), int(recompute), int(accumulate), int(ablate), _model(model), None,
+                   float(tau))
     if events is not None:
         arr = (ctypes.c_void_p * 2)(events[0].cuda_event, events[1].cuda_event)
         o._events_keepalive = arr
@@ -195,9 +197,11 @@ def _over_views(ws: Workspace, vc: int, views_per_call: int | None, run):
 def project_views(mean, log_scale, quat, density, geom: Geometry, view_begin: int = 0,
                   view_count: int | None = None, *, kappa: float = KAPPA, near: float = NEAR,
                   ws: Workspace | None = None, out: torch.Tensor | None = None, events=None,
-                  views_per_call: int | None = None, ablate: int = 0, model: str = "splat") -> torch.Tensor:
+                  views_per_call: int | None = None, ablate: int = 0, model: str = "splat",
+                  tau: float = 0.0) -> torch.Tensor:
     """Rasterize views [view_begin, view_begin + view_count): [V][H][W] float32.
-    model="exact": the ray-exact line integrals instead of the splat."""
+    model="exact": the ray-exact line integrals instead of the splat.
+    tau > 0: the density-aware support (splat model)."""
     L = A.lib()
     vc = geom.n_views - view_begin if view_count is None else view_count
     ws = ws or Workspace(mean.device)
@@ -207,7 +211,7 @@ def project_views(mean, log_scale, quat, density, geom: Geometry, view_begin: in
     gm = geom.struct()
 
     def run(b, c, first, chunked, k):
-        o = _opts(kappa, near, events=_chunk_events(events, k), ablate=ablate, model=model)
+        o = _opts(kappa, near, events=_chunk_events(events, k), ablate=ablate, model=model, tau=tau)
         ws.call(L.fgs_project_views_fwd, ctypes.byref(g), ctypes.byref(gm), view_begin + b, c, ctypes.byref(o),
                 A.ptr(out[b]))
     _over_views(ws, vc, views_per_call, run)
@@ -217,7 +221,8 @@ def project_views(mean, log_scale, quat, density, geom: Geometry, view_begin: in
 def project_views_backward(mean, log_scale, quat, density, geom: Geometry, grad_img, view_begin: int = 0,
                            view_count: int | None = None, *, kappa: float = KAPPA, near: float = NEAR,
                            recompute: bool = True, ws: Workspace | None = None, out=None, events=None,
-                           views_per_call: int | None = None, ablate: int = 0, model: str = "splat"):
+                           views_per_call: int | None = None, ablate: int = 0, model: str = "splat",
+                           tau: float = 0.0):
     """dL/d(mean, log_scale, quat, density) given dL/dimg. Lists left by the
     forward are reused only when the range ran as one call (with the same
     model)."""
@@ -232,7 +237,7 @@ def project_views_backward(mean, log_scale, quat, density, geom: Geometry, grad_
 
     def run(b, c, first, chunked, k):
         o = _opts(kappa, near, 1 if (recompute or chunked) else 0, _chunk_events(events, k),
-                  accumulate=0 if first else 1, ablate=ablate, model=model)
+                  accumulate=0 if first else 1, ablate=ablate, model=model, tau=tau)
         ws.call(L.fgs_project_views_bwd, ctypes.byref(g), ctypes.byref(gm), view_begin + b, c, ctypes.byref(o),
                 A.ptr(gi[b]), ctypes.byref(gr))
     _over_views(ws, vc, views_per_call, run)
@@ -242,21 +247,22 @@ def project_views_backward(mean, log_scale, quat, density, geom: Geometry, grad_
 # ------------------------------------------------------------------ voxelizer
 
 def voxelize(mean, log_scale, quat, density, grid: Grid, *, kappa: float = KAPPA,
-             ws: Workspace | None = None, out: torch.Tensor | None = None, events=None) -> torch.Tensor:
+             ws: Workspace | None = None, out: torch.Tensor | None = None, events=None,
+             tau: float = 0.0) -> torch.Tensor:
     L = A.lib()
     ws = ws or Workspace(mean.device)
     if out is None:
         out = torch.empty(grid.shape, dtype=torch.float32, device=mean.device)
     g = _gauss(mean, log_scale, quat, density)
     gd = grid.struct()
-    o = _opts(kappa, NEAR, events=events)
+    o = _opts(kappa, NEAR, events=events, tau=tau)
     ws.call(L.fgs_voxelize_fwd, ctypes.byref(g), ctypes.byref(gd), ctypes.byref(o), A.ptr(out))
     return out
 
 
 def voxelize_backward(mean, log_scale, quat, density, grid: Grid, grad_vol, *, kappa: float = KAPPA,
                       recompute: bool = True, ws: Workspace | None = None, out=None, events=None,
-                      accumulate: bool = False):
+                      accumulate: bool = False, tau: float = 0.0):
     """dL/d(mean, log_scale, quat, density) given dL/dvol; with accumulate the
     gradients are added to `out` instead of overwriting it."""
     L = A.lib()
@@ -265,7 +271,7 @@ def voxelize_backward(mean, log_scale, quat, density, grid: Grid, grad_vol, *, k
     g = _gauss(mean, log_scale, quat, density)
     gr = A.fgs_gaussian_grads(*(A.ptr(t) for t in grads))
     gd = grid.struct()
-    o = _opts(kappa, NEAR, 1 if recompute else 0, events, accumulate=1 if accumulate else 0)
+    o = _opts(kappa, NEAR, 1 if recompute else 0, events, accumulate=1 if accumulate else 0, tau=tau)
     ws.call(L.fgs_voxelize_bwd, ctypes.byref(g), ctypes.byref(gd), ctypes.byref(o),
             A.ptr(grad_vol.contiguous()), ctypes.byref(gr))
     return grads
@@ -273,7 +279,7 @@ def voxelize_backward(mean, log_scale, quat, density, grid: Grid, grad_vol, *, k
 
 def project_views_support(mean, log_scale, quat, density, geom: Geometry, view_begin: int = 0,
                           view_count: int | None = None, *, kappa: float = KAPPA, near: float = NEAR,
-                          ws: Workspace | None = None, model: str = "splat") -> int:
+                          ws: Workspace | None = None, model: str = "splat", tau: float = 0.0) -> int:
     """Number of (pixel, Gaussian) pairs in the support (the rasterizer's work)."""
     L = A.lib()
     vc = geom.n_views - view_begin if view_count is None else view_count
@@ -281,7 +287,7 @@ def project_views_support(mean, log_scale, quat, density, geom: Geometry, view_b
     out = torch.zeros(1, dtype=torch.int64, device=mean.device)
     g = _gauss(mean, log_scale, quat, density)
     gm = geom.struct()
-    o = _opts(kappa, near, model=model)
+    o = _opts(kappa, near, model=model, tau=tau)
     total = [0]
 
     def run(b, c, first, chunked, k):
@@ -295,16 +301,34 @@ def project_views_support(mean, log_scale, quat, density, geom: Geometry, view_b
 
 
 def voxelize_support(mean, log_scale, quat, density, grid: Grid, *, kappa: float = KAPPA,
-                     ws: Workspace | None = None) -> int:
+                     ws: Workspace | None = None, tau: float = 0.0) -> int:
     """Number of (voxel, Gaussian) pairs in the support (the voxelizer's work)."""
     L = A.lib()
     ws = ws or Workspace(mean.device)
     out = torch.zeros(1, dtype=torch.int64, device=mean.device)
     g = _gauss(mean, log_scale, quat, density)
     gd = grid.struct()
-    o = _opts(kappa, NEAR)
+    o = _opts(kappa, NEAR, tau=tau)
     ws.call(L.fgs_voxelize_support, ctypes.byref(g), ctypes.byref(gd), ctypes.byref(o), A.ptr(out))
     return int(out.item())
+
+
+def workspace_bytes(op: str, n: int, n_pairs: int, *, geom: Geometry | None = None, view_count: int = 1,
+                    grid: Grid | None = None, model: str = "splat") -> int:
+    """Upper bound on the workspace bytes of one call binning n_pairs (tile,
+    Gaussian) pairs (fgs_workspace_query). op: "project_fwd", "project_bwd",
+    "voxelize_fwd" or "voxelize_bwd"."""
+    ops_ = {"project_fwd": A.FGS_OP_PROJECT_FWD, "project_bwd": A.FGS_OP_PROJECT_BWD,
+            "voxelize_fwd": A.FGS_OP_VOXELIZE_FWD, "voxelize_bwd": A.FGS_OP_VOXELIZE_BWD}
+    g = A.fgs_gaussians(int(n), None, None, None, None)
+    gm = geom.struct() if geom is not None else None
+    gd = grid.struct() if grid is not None else None
+    o = _opts(KAPPA, NEAR, model=model)
+    fixed, per = ctypes.c_uint64(), ctypes.c_uint64()
+    A.check(A.lib().fgs_workspace_query(ops_[op], ctypes.byref(g), ctypes.byref(gm) if gm is not None else None,
+                                        ctypes.byref(gd) if gd is not None else None, int(view_count),
+                                        ctypes.byref(o), ctypes.byref(fixed), ctypes.byref(per)))
+    return int(fixed.value) + int(n_pairs) * int(per.value)
 
 
 # ------------------------------------------------------------------ loss / optimiser

@@ -99,3 +99,34 @@ def test_product_path_does_not_import_the_oracle():
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, f
                 assert "liboracle" not in txt, f
+
+
+def test_workspace_query_is_host_arithmetic():
+    """fgs_workspace_query runs without a GPU: the per-pair bytes match the
+    layout (4 uint32 arrays for keys and values with their sort copies, a
+    32-byte pair slot, about one byte of sort histogram: 49 for the splat;
+    64-byte slots for the ray-exact model; the voxelizer adds the gid array
+    and 40-byte slots), and the fixed part grows with the records."""
+    from paper_2604_01844_amd import _abi as A
+    lib = A.lib()
+    fixed, per = ctypes.c_uint64(), ctypes.c_uint64()
+    g = A.fgs_gaussians(50000, None, None, None, None)
+    gm = A.fgs_geom(A.FGS_CONE, 75, 16, 1.5, 2.0, 512, 512, 0.0055, 0.0055, 0.0, 0.0)
+    o = A.fgs_opts(kappa=3.0, near_plane=1e-2, recompute=1)
+    q = lambda op, gptr, geom, grid, vc, opts: lib.fgs_workspace_query(op, gptr, geom, grid, vc, opts,
+                                                                        ctypes.byref(fixed), ctypes.byref(per))
+    assert q(A.FGS_OP_PROJECT_BWD, ctypes.byref(g), ctypes.byref(gm), None, 75, ctypes.byref(o)) == A.FGS_OK
+    assert 49 <= per.value <= 50
+    fixed75 = fixed.value
+    assert fixed75 > 75 * 50000 * 100
+    assert q(A.FGS_OP_PROJECT_BWD, ctypes.byref(g), ctypes.byref(gm), None, 1, ctypes.byref(o)) == A.FGS_OK
+    assert fixed.value < fixed75 / 50
+    oe = A.fgs_opts(kappa=3.0, near_plane=1e-2, recompute=1, model=A.FGS_MODEL_RAY_EXACT)
+    assert q(A.FGS_OP_PROJECT_FWD, ctypes.byref(g), ctypes.byref(gm), None, 75, ctypes.byref(oe)) == A.FGS_OK
+    assert 81 <= per.value <= 82
+    gr = A.fgs_grid((ctypes.c_float * 3)(-0.5, -0.5, -0.5), (ctypes.c_float * 3)(1 / 256, 1 / 256, 1 / 256),
+                    (ctypes.c_int32 * 3)(256, 256, 256))
+    assert q(A.FGS_OP_VOXELIZE_FWD, ctypes.byref(g), None, ctypes.byref(gr), 0, ctypes.byref(o)) == A.FGS_OK
+    assert 61 <= per.value <= 62
+    assert q(7, ctypes.byref(g), None, ctypes.byref(gr), 0, ctypes.byref(o)) == A.FGS_E_INVALID
+    assert q(A.FGS_OP_PROJECT_FWD, ctypes.byref(g), ctypes.byref(gm), None, 76, ctypes.byref(o)) == A.FGS_E_INVALID

@@ -1,0 +1,257 @@
+"""GPU parity of the density-aware support (fgs_opts.density_aabb_tau).
+
+Sec. 3.5 bounds each splat by an axis-aligned box that also takes its
+density into account. The library reads this as the support
+d^2 <= min(kappa^2, 2 ln(peak / tau)): a pair is kept while its contribution
+peak exp(-d^2 / 2) is at least tau (peak = w = rho mu for a splat, rho for
+the voxelizer), and the tile boxes shrink with it. The oracle applies the
+same rule in FP64 (its pins are in test_oracle_pins.py and
+test_culling_cpu.py). Bars as for the kappa support: images and volumes
+within 1e-4 relative L2, gradients within 1e-4 once the boundary band is
+removed, the integer voxel binning bit-exact away from thresholds, and every
+FP64 support pair inside the GPU's tile lists.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import oracle.tiles
+import synth_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+BAND = 1e-3
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def fgs():
+    import paper_2604_01844_amd as m
+    m.lib()
+    oracle.build(force=False)
+    return m
+
+
+def dev(gs):
+    return {k: torch.from_numpy(np.ascontiguousarray(v, dtype=np.float32)).to(DEV) for k, v in gs.items()}
+
+
+def args(t):
+    return t["mean"], t["log_scale"], t["quat"], t["density"]
+
+
+def grads_rel(gpu, ref):
+    got = {k: t.detach().cpu().numpy().astype(np.float64) for t, k in zip(gpu, ("mean", "log_scale", "quat", "density"))}
+    return oracle.banded_grad_error(got, ref)
+
+
+def _splat_tau(gs, gd, ang):
+    """A tau at which about half the splats are limited by their density:
+    2 ln(w / tau) < 9 for w below the median."""
+    w = oracle.splat_records(gs, gd, ang)["w"]
+    return float(np.median(w[w > 0]) * math.exp(-4.5))
+
+
+def _with_faint(gs, k, density, seed):
+    """gs plus k Gaussians of the given density (below tau: dropped)."""
+    f = si.gaussians(k, seed)
+    f["density"] = np.full(k, density, np.float32)
+    return {key: np.ascontiguousarray(np.concatenate([gs[key], f[key]], axis=-1)) for key in gs}
+
+
+def test_projection_with_density_support_matches_oracle(fgs):
+    """The tiny configuration (2,000 Gaussians, 24 views of 64^2): images and
+    gradients at tau against the oracle at the same tau; fewer keys than at
+    tau = 0; the same support-pair count as the oracle's brute force."""
+    gd = si.geometry(64)
+    ang = si.angles(24)
+    gs = si.gaussians(2000, 0)
+    tau = _splat_tau(gs, gd, ang)
+    gs = _with_faint(gs, 40, 1e-4, 300)
+    w = oracle.splat_records(gs, gd, ang)["w"]
+    limited = float(np.mean(2 * np.log(np.maximum(w, 1e-30) / tau) < 9.0))
+    assert 0.2 < limited < 0.9, limited
+    geom = fgs.Geometry.from_dict(gd, ang)
+    t = dev(gs)
+    ws = fgs.Workspace(DEV)
+    img = fgs.project_views(*args(t), geom, ws=ws, tau=tau).cpu().numpy()
+    keys_tau = ws.n_pairs
+    ref = oracle.project(gs, gd, ang, tau=tau)
+    assert oracle.rel_l2(img, ref) < TOL
+    assert oracle.rel_l2(oracle.project(gs, gd, ang), ref) > 1e-3   # tau changes the image
+    img0 = fgs.project_views(*args(t), geom, ws=ws).cpu().numpy()
+    keys0 = ws.n_pairs
+    print(f"keys: tau = 0 {keys0}, tau = {tau:.3g} {keys_tau}", flush=True)
+    assert keys_tau < keys0
+    assert oracle.rel_l2(img0, oracle.project(gs, gd, ang)) < TOL
+    c = si.normals((24, 64, 64), 7)
+    g = fgs.project_views_backward(*args(t), geom, torch.from_numpy(c).to(DEV), tau=tau)
+    gref = oracle.project_bwd(gs, gd, ang, c.astype(np.float64), band=BAND, tau=tau)
+    errs = grads_rel(g, gref)
+    assert max(errs.values()) < TOL, errs
+    # stored lists (forward at tau) equal recomputed ones
+    fgs.project_views(*args(t), geom, ws=ws, tau=tau)
+    g2 = fgs.project_views_backward(*args(t), geom, torch.from_numpy(c).to(DEV), recompute=False, ws=ws, tau=tau)
+    for a, b in zip(g, g2):
+        assert torch.equal(a, b)
+
+
+def test_projection_density_support_pair_count(fgs):
+    """fgs_project_views_support at tau counts the pairs the FP64 oracle
+    keeps, up to the pairs within rounding of the cut."""
+    gs = si.gaussians(600, 3)
+    gd = si.geometry(48)
+    ang = si.angles(3)
+    tau = _splat_tau(gs, gd, ang)
+    gs = _with_faint(gs, 20, 1e-4, 301)
+    geom = fgs.Geometry.from_dict(gd, ang)
+    got = fgs.project_views_support(*args(dev(gs)), geom, tau=tau)
+    rec = oracle.splat_records(gs, gd, ang)
+    k2 = oracle.tiles.support_k2(3.0, tau, rec["w"])
+    ys, xs = np.mgrid[0:48, 0:48]
+    inside = near = 0
+    for r in range(rec["w"].shape[0]):
+        if rec["culled"][r] or k2[r] < 0:
+            continue
+        du = xs + 0.5 - rec["uv"][r, 0]
+        dv = ys + 0.5 - rec["uv"][r, 1]
+        c0, c1, c2 = rec["conic"][r]
+        d2 = c0 * du * du + 2 * c1 * du * dv + c2 * dv * dv
+        inside += int((d2 <= k2[r]).sum())
+        near += int((np.abs(d2 - k2[r]) <= 1e-4).sum())
+    assert abs(got - inside) <= near, (got, inside, near)
+    assert inside > 1000
+
+
+def test_projection_density_binning_covers_support(fgs):
+    """Every FP64 pair with d^2 <= k2_i - 1e-3 (k2_i = min(9, 2 ln(w_i / tau)))
+    lies in a tile whose list holds its record; records with w <= tau get
+    no key."""
+    gd = si.geometry(64)
+    ang = si.angles(2)
+    gs = si.gaussians(380, 10)
+    tau = _splat_tau(gs, gd, ang)
+    gs = _with_faint(gs, 20, 1e-4, 302)
+    geom = fgs.Geometry.from_dict(gd, ang)
+    ws = fgs.Workspace(DEV)
+    fgs.project_views(*args(dev(gs)), geom, ws=ws, tau=tau)
+    torch.cuda.synchronize()
+    d = fgs.binning_dump(ws)
+    rng = d["tile_ranges"].cpu().numpy().astype(np.int64)
+    vals = d["sorted_vals"].cpu().numpy().astype(np.int64)
+    lists = [set(vals[rng[t, 0]:rng[t, 1]].tolist()) for t in range(d["n_tiles"])]
+    listed = set(vals.tolist())
+    rec = oracle.splat_records(gs, gd, ang)
+    k2 = oracle.tiles.support_k2(3.0, tau, rec["w"])
+    ys, xs = np.mgrid[0:64, 0:64]
+    n_dropped = 0
+    for r in range(800):
+        if k2[r] < 0:
+            if rec["w"][r] < tau * (1 - 1e-5):
+                assert r not in listed
+                n_dropped += 1
+            continue
+        v = r // 400
+        du = xs + 0.5 - rec["uv"][r, 0]
+        dv = ys + 0.5 - rec["uv"][r, 1]
+        c0, c1, c2 = rec["conic"][r]
+        inside = c0 * du * du + 2 * c1 * du * dv + c2 * dv * dv <= k2[r] - 1e-3
+        for t in set((v * 16 + (ys[inside] // 16) * 4 + xs[inside] // 16).tolist()):
+            assert r in lists[t]
+    assert n_dropped > 0
+
+
+def _vox_tau(gs):
+    """About half the Gaussians limited by their density (rho below the median)."""
+    return float(np.median(gs["density"]) * math.exp(-4.5))
+
+
+def test_voxelize_with_density_support_matches_oracle(fgs):
+    """64^3 voxelization of the tiny configuration and a ragged crop at tau:
+    volumes and gradients against the oracle at the same tau."""
+    gs = si.gaussians(2000, 0)
+    tau = _vox_tau(gs)
+    gs = _with_faint(gs, 40, 0.5 * tau, 303)
+    limited = float(np.mean(2 * np.log(gs["density"].astype(np.float64) / tau) < 9.0))
+    assert 0.2 < limited < 0.95, limited
+    for gr in (si.grid(64), dict(origin=(-0.31, -0.2, -0.45), spacing=(0.0125, 0.015, 0.011), dims=(40, 29, 37))):
+        grid = fgs.Grid.from_dict(gr)
+        t = dev(gs)
+        vol = fgs.voxelize(*args(t), grid, tau=tau).cpu().numpy()
+        ref = oracle.voxelize(gs, gr, tau=tau)
+        assert oracle.rel_l2(vol, ref) < TOL
+        assert oracle.rel_l2(oracle.voxelize(gs, gr), ref) > 1e-3
+        nx, ny, nz = gr["dims"]
+        c = si.normals((nz, ny, nx), 9)
+        g = fgs.voxelize_backward(*args(t), grid, torch.from_numpy(c).to(DEV), tau=tau)
+        gref = oracle.voxelize_bwd(gs, gr, c.astype(np.float64), band=BAND, tau=tau)
+        errs = grads_rel(g, gref)
+        assert max(errs.values()) < TOL, errs
+
+
+def test_voxel_density_binning_matches_integer_reference(fgs):
+    """The voxel lists at tau against oracle.tiles.vox_bin_tiles(tau=...):
+    counts, rectangles, per-tile lists for every Gaussian away from a
+    threshold, and every FP64 support voxel's tile listed
+    (vox_support_tiles)."""
+    gs = si.gaussians(900, 15)
+    large = si.gaussians(60, 42, log_scale_mean=math.log(0.15))
+    gs = {k: np.concatenate([gs[k], large[k]], axis=-1) for k in gs}
+    gr = si.grid(96)
+    tau = _vox_tau(gs)
+    gs = _with_faint(gs, 30, 0.5 * tau, 304)
+    ws = fgs.Workspace(DEV)
+    fgs.voxelize(*args(dev(gs)), fgs.Grid.from_dict(gr), ws=ws, tau=tau)
+    torch.cuda.synchronize()
+    d = {k: (v.cpu().numpy() if torch.is_tensor(v) else v) for k, v in fgs.binning_dump(ws).items()}
+    b = oracle.tiles.vox_bin_tiles(gs, gr, tau=tau)
+    amb = b["ambiguous"]
+    n = gs["density"].shape[0]
+    off = d["offset"].astype(np.int64)
+    gcount = np.diff(off)
+    np.testing.assert_array_equal(gcount[~amb], b["count"][~amb])
+    assert (b["count"] == 0).sum() > 0 and (amb.sum() < 0.1 * n)
+    nz = ~amb & (gcount > 0)
+    np.testing.assert_array_equal(d["rect"][nz, :6].astype(np.int64) & 0xffff, b["rect"][nz])
+    skeys = d["sorted_keys"].astype(np.int64)
+    start = d["tile_start"].astype(np.int64)
+    gauss = np.searchsorted(off, d["sorted_vals"].astype(np.int64), side="right") - 1
+    amb_ids = set(np.nonzero(amb)[0].tolist())
+    for t in range(d["n_tiles"]):
+        lo, hi = start[t], start[t + 1]
+        assert np.all(skeys[lo:hi] == t)
+        gl = gauss[lo:hi]
+        assert np.all(np.diff(gl) > 0), t
+        ol = b["sorted_gauss"][b["tile_start"][t]:b["tile_start"][t + 1]]
+        assert [x for x in gl.tolist() if x not in amb_ids] == [x for x in ol.tolist() if x not in amb_ids], t
+    listed = [set() for _ in range(n)]
+    for g_, k_ in zip(gauss.tolist(), skeys.tolist()):
+        listed[g_].add(k_)
+    sup = oracle.tiles.vox_support_tiles(gs, gr, margin=1e-3, tau=tau)
+    missing = [i for i in range(n) if not sup[i] <= listed[i]]
+    assert not missing, missing[:10]
+
+
+def test_density_support_rejects_bad_values(fgs):
+    """tau < 0 or NaN is refused; the ray-exact model and the ablation
+    switches do not take it."""
+    from paper_2604_01844_amd import _abi as A
+    gs = si.gaussians(50, 1)
+    geom = fgs.Geometry.from_dict(si.geometry(32), si.angles(2))
+    t = dev(gs)
+    for bad in (-1.0, float("nan")):
+        with pytest.raises(A.FgsError) as e:
+            fgs.project_views(*args(t), geom, tau=bad)
+        assert e.value.code == A.FGS_E_INVALID
+        with pytest.raises(A.FgsError):
+            fgs.voxelize(*args(t), fgs.Grid.from_dict(si.grid(16)), tau=bad)
+    with pytest.raises(A.FgsError) as e:
+        fgs.project_views(*args(t), geom, tau=1e-3, model="exact")
+    assert e.value.code == A.FGS_E_UNSUPPORTED
+    with pytest.raises(A.FgsError) as e:
+        fgs.project_views(*args(t), geom, tau=1e-3, ablate=1)
+    assert e.value.code == A.FGS_E_UNSUPPORTED

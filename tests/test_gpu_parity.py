@@ -139,6 +139,40 @@ def test_capacity_protocol(fgs):
     assert rel(out.cpu().numpy(), oracle.project(gs, gd, si.angles(8))) < TOL
 
 
+@pytest.mark.parametrize("views, det, model", [(8, 64, "splat"), (1, 200, "splat"), (3, 96, "exact")])
+def test_workspace_query_bounds_the_need(fgs, views, det, model):
+    """fgs_workspace_query: fixed + pairs * per-pair bytes is at least what a
+    call with that many pairs asks for (forward, backward, voxelizer), both
+    for calls with many tiles and for chunked one-view calls."""
+    gs = si.gaussians(3000, 4)
+    geom = fgs.Geometry.from_dict(si.geometry(det), si.angles(views))
+    t = dev(gs)
+    ws = fgs.Workspace(DEV)
+    fgs.project_views(*args(t), geom, ws=ws, model=model)
+    need = int(ws.s.needed)
+    assert need <= fgs.workspace_bytes("project_fwd", 3000, ws.n_pairs, geom=geom, view_count=views, model=model)
+    fgs.project_views_backward(*args(t), geom, torch.zeros((views, det, det), device=DEV), ws=ws, model=model)
+    assert int(ws.s.needed) <= fgs.workspace_bytes("project_bwd", 3000, ws.n_pairs, geom=geom, view_count=views,
+                                                   model=model)
+    for gr in (si.grid(48), dict(origin=(-0.2, -0.1, 0.0), spacing=(0.01, 0.01, 0.01), dims=(32, 32, 32))):
+        grid = fgs.Grid.from_dict(gr)
+        wv = fgs.Workspace(DEV)
+        fgs.voxelize(*args(t), grid, ws=wv)
+        assert int(wv.s.needed) <= fgs.workspace_bytes("voxelize_fwd", 3000, wv.n_pairs, grid=grid)
+    # a workspace of exactly the bound takes the call without a retry
+    exact = fgs.Workspace(DEV)
+    exact.buf = torch.empty(fgs.workspace_bytes("project_fwd", 3000, ws.n_pairs, geom=geom, view_count=views,
+                                                model=model), dtype=torch.uint8, device=DEV)
+    exact.s.ptr, exact.s.bytes = exact.buf.data_ptr(), exact.buf.numel()
+    from paper_2604_01844_amd import _abi as A
+    g = A.fgs_gaussians(3000, *(A.ptr(x) for x in args(t)))
+    gm = geom.struct()
+    o = fgs.ops._opts(3.0, 1e-2, model=model)
+    img = torch.empty((views, det, det), device=DEV)
+    assert A.lib().fgs_project_views_fwd(ctypes.byref(g), ctypes.byref(gm), 0, views, ctypes.byref(o), A.ptr(img),
+                                         ctypes.byref(exact.s), A.stream_ptr()) == A.FGS_OK
+
+
 # ------------------------------------------------------------------ binning
 
 def _ambiguous(c64, r64, band=2e-3):
@@ -635,16 +669,16 @@ def test_full_size_projection_sampled(fgs, scan_case):
 
 
 def _check_every_element(got, ref, band, what):
-    """Element by element: |got - ref| <= 1e-4 max|ref| everywhere, and
-    within 1e-5 max|ref| of the bracket that support decisions near the
-    cutoff allow (band: the FP64 contributions of the pairs with
-    |d^2 - 9| <= 1e-3, which FP32 may put on either side); relative L2 <= 1e-4."""
+    """Element by element: within 1e-5 max|ref| of the bracket that support
+    decisions near the cutoff allow (band: the FP64 contributions of the
+    pairs with |d^2 - 9| <= 1e-3, which FP32 may put on either side; one such
+    pair of a dense Gaussian moves a voxel by up to e^-4.5 rho, which can
+    exceed 1e-4 max|ref|), and relative L2 <= 1e-4 overall."""
     err = np.abs(got.astype(np.float64) - ref)
     top = np.abs(ref).max()
     beyond = np.maximum(err - band, 0.0)
     print(f"{what}: max |diff| {err.max() / top:.2e} of max|ref|, beyond the band {beyond.max() / top:.2e}; "
           f"rel-L2 {rel(got, ref):.2e}; {np.count_nonzero(band)} elements touch the band", flush=True)
-    assert err.max() <= 1e-4 * top, what
     assert beyond.max() <= 1e-5 * top, what
     assert rel(got, ref) < TOL, what
 
@@ -798,8 +832,11 @@ def test_ssim_loss_grad_matches_oracle(fgs, shape):
     np.testing.assert_allclose(acc.cpu().numpy(), (base + g).cpu().numpy(), rtol=1e-6, atol=1e-9)
 
 
-@pytest.mark.parametrize("shape", [(20, 24, 28), (1, 9, 13)])
+@pytest.mark.parametrize("shape", [(20, 24, 28), (1, 9, 13), (150, 37, 21), (70, 16, 33), (9, 40, 17)])
 def test_ssim3d_loss_grad_matches_oracle(fgs, shape):
+    """[nz][ny][nx] volumes: one and several z-chunks of the fused kernel (64
+    output slices each, the last one ragged), fewer slices than the window,
+    and x/y extents that are not multiples of its 16 x 16 tiles."""
     x = np.abs(si.normals(shape, 97)) * 0.5
     y = np.abs(si.normals(shape, 98)) * 0.5
     xd, yd = torch.from_numpy(x).to(DEV), torch.from_numpy(y).to(DEV)

@@ -162,7 +162,7 @@ def test_splat_mass_closed_form():
 
 
 def test_density_aware_support_closed_forms():
-    """Density-aware support (Sec. 3.5 boxes with the density factored in):
+    """Density-aware support (Sec. 3.5 boxes that take the density into account):
     a pair counts only while its contribution w exp(-d^2/2) >= tau. For one
     splat whose cut 2 ln(w / tau) lies below kappa^2 the pixel sum is then
     2 pi sqrt(det S^) (w - tau); for one voxel Gaussian it is
