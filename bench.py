@@ -288,6 +288,36 @@ def view_steps(fgs, params, moms, lrs, state, geom, grid, i_gt, dev, epochs=1):
     return epoch_s
 
 
+def fit_steps(fgs, si, dev, steps=30, ssim_weight=0.2):
+    """The volume-fitting step (Sec. 3.6): 200,000 Gaussians placed by
+    gradient sampling on a seeded 256^3 phantom, then per step the whole grid
+    voxelized, the loss, the voxelizer backward and Adam. Timed with the L1
+    term alone and with the full loss of Eq. 6 (L1 + ssim_weight (1 - 3D
+    SSIM)); milliseconds per step, medians of three runs of `steps` steps."""
+    import torch
+    from paper_2604_01844_amd import recon
+    cfg = si.CONFIGS["fit"]
+    grid = fgs.Grid.from_dict(si.grid(cfg["vol"]))
+    ph = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in si.phantom(cfg["n_ell"],
+                                                                                       cfg["phantom_seed"]).items()}
+    v_gt = fgs.phantom_voxelize(ph, grid)
+    out = dict(n_gauss=cfg["n_gauss"], vol=cfg["vol"], steps=steps, ssim_weight=ssim_weight)
+    for name, w in (("ms_per_step_l1", 0.0), ("ms_per_step_eq6", ssim_weight)):
+        runs = []
+        for _ in range(3):
+            n = cfg["n_gauss"]
+            model = recon.init_from_volume(v_gt, grid, n, si.uniforms(4 * n, cfg["seed"]).reshape(4, n))
+            recon.fit_volume(model, v_gt, grid, iters=3, adam=recon.FIT_ADAM, eval_every=3, ssim_weight=w)
+            # the loop's own clock (synchronised, evaluation excluded)
+            h = recon.fit_volume(model, v_gt, grid, iters=steps, adam=recon.FIT_ADAM, eval_every=10 ** 9,
+                                 ssim_weight=w)
+            runs.append(h.seconds[-1] * 1e3 / steps)
+        out[name] = float(np.median(runs))
+    log(f"fitting step (200k Gaussians, 256^3): {out['ms_per_step_l1']:.3f} ms with L1, "
+        f"{out['ms_per_step_eq6']:.3f} ms with Eq. 6")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -296,6 +326,7 @@ def main():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="scan")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-view-steps", action="store_true", help="skip the one-view step timing")
+    ap.add_argument("--no-fit", action="store_true", help="skip the volume-fitting step timing")
     ap.add_argument("--view-steps-only", type=int, default=0, metavar="EPOCHS",
                     help="instead of the benchmark, time EPOCHS epochs of the one-view optimizer step (standard "
                          "scan) and print one JSON line")
@@ -450,6 +481,8 @@ def main():
         epoch_s = view_steps(fgs, params, moms, lrs, state, geom, grid, i_gt, dev)
         out["s_per_view_step"] = epoch_s / V
         out["s_per_epoch"] = epoch_s
+    if args.workload == "scan" and not args.no_fit:
+        out["fit_step"] = fit_steps(fgs, si, dev)
     if args.calibrate_copy:
         from paper_2604_01844_amd import _abi
         src = torch.ones(args.calibrate_copy << 18, dtype=torch.float32, device=dev)
