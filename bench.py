@@ -159,18 +159,46 @@ def ceilings(dev, blocks=2048, reps=3, copy_mib=1024):
     return out
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (/proc/cpuinfo), or the platform's."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(gs, gd, ang, grid_d, budget_s=12.0):
     """Time the FP64 oracle on a bounded sample of one step and scale it to the
     whole step: whole views of the rasterizer forward+backward over all
     Gaussians (about half the budget), 8-slice slabs of the voxelizer forward
     from the middle of the grid outwards, and the voxelizer backward of
-    chunks of 1000 Gaussians (a quarter each)."""
+    chunks of 1000 Gaussians (a quarter each), on all the host's threads;
+    then a smaller sample of the same parts on one thread."""
     import oracle
     oracle.build(force=False)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    oracle.set_threads(cores)
+    out = _oracle_sample(gs, gd, ang, grid_d, budget_s, cores)
+    oracle.set_threads(1)
+    try:
+        one = _oracle_sample(gs, gd, ang, grid_d, budget_s / 3, 1)
+    finally:
+        oracle.set_threads(cores)
+    out["one_thread"] = dict(value=one["value"], seconds_per_step=one["seconds_per_step"], sample=one["sample"])
+    out["cpu_model"] = cpu_model()
+    return out
+
+
+def _oracle_sample(gs, gd, ang, grid_d, budget_s, cores):
+    import oracle
     n_views = len(ang)
     nx, ny, nz = grid_d["dims"]
     n = gs["density"].shape[0]
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     c1 = np.ones((1, gd["det_h"], gd["det_w"])) / (gd["det_h"] * gd["det_w"])
     t_proj, nv = 0.0, 0
     while nv < n_views and (nv == 0 or t_proj < 0.5 * budget_s):
@@ -254,38 +282,36 @@ def view_steps(fgs, params, moms, lrs, state, geom, grid, i_gt, dev, epochs=1):
     """The reconstruction loop's optimizer step (Sec. 3.4, the loss of Eq. 5):
     one view forward, L1 and SSIM with their gradients, backward (lists
     reused), a randomly placed 32^3 crop voxelized with the gradient of its
-    TV, Adam. Five untimed steps, then `epochs` timed epochs over all views in
-    a random order; returns seconds per epoch."""
+    TV, Adam, issued as one library call per step (fgs_recon_step, lists at
+    a fixed capacity so no step waits for the GPU). Five untimed steps, then
+    `epochs` timed epochs over all views in a random order; returns seconds
+    per epoch and the number of capacity overflows seen (steps that binned
+    nothing)."""
     import torch
-    from paper_2604_01844_amd.recon import CropTV
-    V, D = geom.n_views, geom.det_w
-    img1 = torch.empty((1, D, D), device=dev)
-    gp = [torch.empty_like(p) for p in params]
+    from paper_2604_01844_amd import recon
+    V = geom.n_views
+    model = recon.GaussianModel(*params)
+    model.m = [mv[0] for mv in moms]
+    model.v = [mv[1] for mv in moms]
+    model.step = state["step"]
+    adam = recon.AdamConfig(lr_mean=lrs[0], lr_log_scale=lrs[1], lr_quat=lrs[2], lr_density=lrs[3])
     rng = np.random.Generator(np.random.PCG64(0))
     order = rng.permutation(V)
-    tv = CropTV(grid, TV_WEIGHT, 32, dev)
-    ws_p, ws_l, ws_s = fgs.Workspace(dev), fgs.Workspace(dev, 1 << 16), fgs.Workspace(dev)
-
-    def view_step(v):
-        fgs.project_views(*params, geom, int(v), 1, ws=ws_p, out=img1)
-        _, g1 = fgs.l1_loss_grad(img1, i_gt[v:v + 1], ws=ws_l)
-        fgs.ssim_loss_grad(img1, i_gt[v:v + 1], scale=SSIM_WEIGHT, ws=ws_s, grad=g1, accumulate=True)
-        fgs.project_views_backward(*params, geom, g1, int(v), 1, recompute=False, ws=ws_p, out=gp)
-        tv.add_grad(params, gp, rng)
-        state["step"] += 1
-        for k, p in enumerate(params):
-            fgs.adam_step(p, gp[k], moms[k][0], moms[k][1], state["step"], lrs[k], clamp_min_zero=(k == 3))
+    tv = recon.CropTV(grid, TV_WEIGHT, 32, dev)
+    stepper = recon.ViewStep(model, geom, adam, ssim_weight=SSIM_WEIGHT, tv=tv)
     for v in order[:5]:
-        view_step(v)
+        stepper(int(v), i_gt[v], rng)
     torch.cuda.synchronize()
     w0 = time.perf_counter()
     for _ in range(epochs):
         for v in order:
-            view_step(v)
+            stepper(int(v), i_gt[v], rng)
     torch.cuda.synchronize()
     epoch_s = (time.perf_counter() - w0) / epochs
-    log(f"one-view steps: {1e3 * epoch_s / V:.3f} ms/step, {epoch_s:.3f} s/epoch")
-    return epoch_s
+    state["step"] = model.step
+    overflows = stepper.check_overflow()
+    log(f"one-view steps: {1e3 * epoch_s / V:.3f} ms/step, {epoch_s:.3f} s/epoch, {overflows} capacity overflows")
+    return epoch_s, overflows
 
 
 def fit_steps(fgs, si, dev, steps=30, ssim_weight=0.2):
@@ -318,6 +344,133 @@ def fit_steps(fgs, si, dev, steps=30, ssim_weight=0.2):
     return out
 
 
+def _timed(fn, reps=7):
+    """Median milliseconds of `reps` runs of fn() after one untimed run,
+    each bracketed by events on the current stream."""
+    import torch
+    fn()
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    return float(np.median(ts))
+
+
+def fig3_sweep(fgs, si, dev):
+    """Kernel scaling in the manner of the paper's Fig. 3 (Sec. 3.5, kernel
+    evaluation): isotropic Gaussians (sigma 0.02, no rotation, centres uniform
+    in the unit cube, densities U(0.1, 1)), one view per rasterizer call.
+    (a) 20,000 Gaussians on detectors of 256^2 ... 2048^2 and grids of
+    64^3 ... 512^3; (b) about 10^6 pixels (1024^2) or voxels (100^3) with
+    10^3 ... 10^6 Gaussians. Milliseconds per image (volume) for the forward
+    and the backward, and power-law fits t = a x^b over each series."""
+    import torch
+    rng = np.random.Generator(np.random.PCG64(31))
+
+    def scene(n):
+        g = dict(mean=rng.uniform(-0.5, 0.5, (3, n)).astype(np.float32),
+                 log_scale=np.full((3, n), np.log(0.02), np.float32),
+                 quat=np.tile(np.array([[1.0], [0.0], [0.0], [0.0]], np.float32), (1, n)),
+                 density=rng.uniform(0.1, 1.0, n).astype(np.float32))
+        return [torch.from_numpy(np.ascontiguousarray(g[k])).to(dev) for k in ("mean", "log_scale", "quat", "density")]
+
+    def raster(params, det):
+        geom = fgs.Geometry.from_dict(si.geometry(det), np.zeros(1, np.float32), dev)
+        ws = fgs.Workspace(dev)
+        img = torch.empty((1, det, det), device=dev)
+        c = torch.from_numpy(si.normals((1, det, det), 5)).to(dev)
+        grads = [torch.empty_like(p) for p in params]
+        fwd = _timed(lambda: fgs.project_views(*params, geom, ws=ws, out=img))
+        bwd = _timed(lambda: fgs.project_views_backward(*params, geom, c, recompute=False, ws=ws, out=grads))
+        return fwd, bwd
+
+    def voxel(params, nv):
+        grid = fgs.Grid.from_dict(si.grid(nv))
+        ws = fgs.Workspace(dev)
+        vol = torch.empty(grid.shape, device=dev)
+        c = torch.from_numpy(si.normals(grid.shape, 6)).to(dev)
+        grads = [torch.empty_like(p) for p in params]
+        fwd = _timed(lambda: fgs.voxelize(*params, grid, ws=ws, out=vol))
+        bwd = _timed(lambda: fgs.voxelize_backward(*params, grid, c, recompute=False, ws=ws, out=grads))
+        return fwd, bwd
+
+    def fit(xs, ts):
+        b, la = np.polyfit(np.log(xs), np.log(ts), 1)
+        return dict(a=float(np.exp(la)), b=float(b))
+
+    rows = []
+    p20 = scene(20000)
+    for det in (256, 512, 1024, 2048):
+        f, b = raster(p20, det)
+        rows.append(dict(series="a_raster", n_gauss=20000, pixels=det * det, fwd_ms=f, bwd_ms=b))
+    for nv in (64, 128, 256, 512):
+        f, b = voxel(p20, nv)
+        rows.append(dict(series="a_voxel", n_gauss=20000, voxels=nv ** 3, fwd_ms=f, bwd_ms=b))
+    for n in (1000, 10000, 100000, 1000000):
+        p = scene(n)
+        f, b = raster(p, 1024)
+        rows.append(dict(series="b_raster", n_gauss=n, pixels=1024 * 1024, fwd_ms=f, bwd_ms=b))
+        f, b = voxel(p, 100)
+        rows.append(dict(series="b_voxel", n_gauss=n, voxels=100 ** 3, fwd_ms=f, bwd_ms=b))
+    fits = {}
+    for series, xkey in (("a_raster", "pixels"), ("a_voxel", "voxels"), ("b_raster", "n_gauss"),
+                         ("b_voxel", "n_gauss")):
+        r = [x for x in rows if x["series"] == series]
+        for ph in ("fwd_ms", "bwd_ms"):
+            fits[f"{series}_{ph}"] = fit([x[xkey] for x in r], [x[ph] for x in r])
+        log(f"fig3 {series}: " + ", ".join(f"{x[xkey]}: {x['fwd_ms']:.3f}/{x['bwd_ms']:.3f} ms" for x in r))
+    return dict(rows=rows, fits=fits)
+
+
+def s_to_psnr(si, dev, epochs=40, levels=(30.0, 35.0, 38.0)):
+    """Seconds-to-PSNR of the reconstruction loop on the standard scan's
+    phantom (40 ellipsoids, seed 101; 75 views of 512^2): FDK at 128^3,
+    50,000 Gaussians by FDK-gradient sampling (Sec. 3.1), then one view per
+    optimiser step with the loss of Eq. 5 (L1, SSIM and the crop's TV). The
+    clock covers FDK, the initialisation and the steps; the PSNR (256^3,
+    peak = max of the phantom) is evaluated after every epoch outside it."""
+    import torch
+    from paper_2604_01844_amd import learned_init as li, ops, recon
+    sc = li.Scanner(li.ScanConfig(), dev)
+    cfg = si.CONFIGS["scan"]
+    ph = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in si.phantom(cfg["n_ell"],
+                                                                                       cfg["phantom_seed"]).items()}
+    proj = ops.phantom_project(ph, sc.geom)
+    vol_gt = ops.phantom_voxelize(ph, sc.eval_grid)
+    r = li.run_arm(sc, "fdk_gradient", cfg["phantom_seed"], epochs=epochs, adam=recon.AdamConfig(lr_density=2e-3),
+                   proj=proj, vol_gt=vol_gt)
+    h = r.history
+    out = dict(init="FDK-gradient sampling", loss="Eq. 5: L1 + 0.25 SSIM + 0.05 crop TV", epochs=epochs,
+               init_s=r.init_s, psnr_initial=h.psnr[0], psnr_final=h.psnr[-1], seconds_total=h.seconds[-1],
+               capacity_overflows=h.overflows,
+               to_psnr={f"{lv:g}": dict(s=r.seconds_to(lv), epochs=r.epochs_to(lv)) for lv in levels})
+    log(f"s-to-PSNR: {h.psnr[0]:.2f} dB at start, {h.psnr[-1]:.2f} dB after {epochs} epochs "
+        f"({h.seconds[-1]:.2f} s); " + ", ".join(f"{k} dB at {v['s']} s" for k, v in out["to_psnr"].items()))
+    return out
+
+
+def scaling_subrun(steps=3, warmup=1):
+    """The scaling workload (500,000 Gaussians, 50 views of 2048^2, 512^3) in
+    a child process of this script, so its 40 GB of workspace is freed
+    before and after; returns its JSON line."""
+    import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), "--workload", "scale", "--steps", str(steps), "--warmup",
+           str(warmup), "--no-cpu-baseline", "--no-fit", "--no-scale", "--no-psnr"]
+    log("scaling workload: " + " ".join(cmd[1:]))
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
+    sys.stderr.write(r.stderr)
+    if r.returncode != 0:
+        raise RuntimeError(f"scaling workload run failed ({r.returncode})")
+    line = [l for l in r.stdout.splitlines() if l.startswith("{")][-1]
+    d = json.loads(line)
+    keep = ("value", "unit", "ms_per_step", "steps", "warmup", "voxels_per_s", "config", "kernels", "roofline")
+    return {k: d[k] for k in keep if k in d}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -327,6 +480,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-view-steps", action="store_true", help="skip the one-view step timing")
     ap.add_argument("--no-fit", action="store_true", help="skip the volume-fitting step timing")
+    ap.add_argument("--no-scale", action="store_true", help="skip the scaling-workload run")
+    ap.add_argument("--no-psnr", action="store_true", help="skip the seconds-to-PSNR run")
+    ap.add_argument("--fig3", action="store_true",
+                    help="instead of the benchmark, run the kernel scaling sweep of the paper's Fig. 3 and print "
+                         "one JSON line with power-law fits")
     ap.add_argument("--view-steps-only", type=int, default=0, metavar="EPOCHS",
                     help="instead of the benchmark, time EPOCHS epochs of the one-view optimizer step (standard "
                          "scan) and print one JSON line")
@@ -354,6 +512,9 @@ def main():
     if args.probes:
         print(json.dumps(dict(ceilings=ceilings(dev), device=torch.cuda.get_device_name(dev))), flush=True)
         return
+    if args.fig3:
+        print(json.dumps(dict(fig3=fig3_sweep(fgs, si, dev))), flush=True)
+        return
     cfg = si.CONFIGS[wl["config"]]
     N, V, D, NV = cfg["n_gauss"], cfg["n_views"], cfg["det"], cfg["vol"]
     gs = si.gaussians(N, cfg["seed"])
@@ -376,8 +537,9 @@ def main():
     moms = [(torch.zeros_like(p), torch.zeros_like(p)) for p in params]
     if args.view_steps_only:
         st = {"step": 0}
-        epoch_s = view_steps(fgs, params, moms, lrs, st, geom, grid, i_gt, dev, epochs=args.view_steps_only)
+        epoch_s, ovf = view_steps(fgs, params, moms, lrs, st, geom, grid, i_gt, dev, epochs=args.view_steps_only)
         print(json.dumps(dict(s_per_view_step=epoch_s / V, s_per_epoch=epoch_s, epochs=args.view_steps_only,
+                              capacity_overflows=ovf,
                               workload=wl["label"].format(N=N, V=V, D=D, NV=NV))), flush=True)
         return
     gp = [torch.empty_like(p) for p in params]
@@ -478,11 +640,14 @@ def main():
                kernels=kernels, roofline=roof, ceilings=ceil)
 
     if args.workload == "scan" and not args.no_view_steps:
-        epoch_s = view_steps(fgs, params, moms, lrs, state, geom, grid, i_gt, dev)
+        epoch_s, ovf = view_steps(fgs, params, moms, lrs, state, geom, grid, i_gt, dev)
         out["s_per_view_step"] = epoch_s / V
         out["s_per_epoch"] = epoch_s
+        out["view_step_capacity_overflows"] = ovf
     if args.workload == "scan" and not args.no_fit:
         out["fit_step"] = fit_steps(fgs, si, dev)
+    if args.workload == "scan" and not args.no_psnr:
+        out["s_to_psnr"] = s_to_psnr(si, dev)
     if args.calibrate_copy:
         from paper_2604_01844_amd import _abi
         src = torch.ones(args.calibrate_copy << 18, dtype=torch.float32, device=dev)
@@ -494,6 +659,9 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a bounded sample (cpu_baseline)")
         out["cpu_baseline"] = cpu_baseline(gs, gd, ang, grid_d)
+    if args.workload == "scan" and not args.no_scale:
+        torch.cuda.synchronize()
+        out["scaling_workload"] = scaling_subrun()
     print(json.dumps(out), flush=True)
 
 

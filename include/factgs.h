@@ -185,6 +185,21 @@ typedef struct {
   int32_t kind;          /* out: 0 none, 1 rasterizer lists (splat model), 2 voxelizer lists,
                             3 rasterizer lists (ray-exact model) */
   int32_t tile_bits;     /* out: rasterizer: width of the tile field of its keys */
+  uint64_t key_capacity; /* in: 0 = the rasterizer and voxelizer calls read the number of
+                            (tile, Gaussian) pairs back and size the lists by it (one wait on
+                            the stream per call). > 0 (below 2^32) = they lay the lists out for
+                            at most this many pairs and keep the count on the device: no wait,
+                            so a sequence of calls can be captured in a HIP graph. ws->needed
+                            and ws->n_pairs then describe the capacity (the call returns
+                            FGS_E_CAPACITY before any GPU work if bytes is too small for it).
+                            A call whose pairs exceed it bins nothing (its image or volume is
+                            zero, its gradient contribution zero) and reports that through
+                            `overflow`. A backward that reuses the lists must see the same
+                            capacity. */
+  uint32_t *overflow;    /* in, used with key_capacity > 0 (may be NULL): device uint32[2] that
+                            the caller zeroes; a call that overflows sets overflow[0] = 1 and
+                            raises overflow[1] to the pairs it needed (at most 2^32 - 1). Never
+                            cleared by the library. */
 } fgs_workspace;
 
 /* Additive ellipsoid phantom: sum_e amp_e * [x inside ellipsoid e]. Used to
@@ -207,7 +222,8 @@ typedef struct {
  * each record's axis-aligned tile rectangle); stable LSD radix sort; per-tile
  * ranges; per-tile splat. Per pixel the sum runs over its tile's list in
  * ascending Gaussian index (deterministic, bit-reproducible).
- * Synchronisation: waits on `stream` once to read the pair count.
+ * Synchronisation: waits on `stream` once to read the pair count, unless
+ * ws->key_capacity > 0 (then not at all).
  * Workspace: if ws->bytes < ws->needed the call returns FGS_E_CAPACITY with
  * ws->needed set and no output written; grow and retry. The workspace then
  * holds the lists the backward can reuse (opts.recompute = 0).
@@ -243,6 +259,52 @@ int fgs_project_views_fwd_noalloc(const fgs_gaussians *g, const fgs_geom *geom, 
 int fgs_project_views_bwd(const fgs_gaussians *g, const fgs_geom *geom, int32_t view_begin,
                           int32_t view_count, const fgs_opts *opts, const float *grad_img,
                           fgs_gaussian_grads *out, fgs_workspace *ws, void *stream);
+
+/* ---------------------------------------------------------------------
+ * One optimiser step of the reconstruction loop (Sec. 3.4: one view per
+ * step, the loss of Eq. 5), composed in the library so that a step is one
+ * host call.
+ * ------------------------------------------------------------------- */
+typedef struct {
+  float ssim_weight;     /* weight of the SSIM term of Eq. 5 (0 = L1 only) */
+  float ssim_c1, ssim_c2;/* SSIM constants (0.01^2, 0.03^2 for unit dynamic range) */
+  float tv_weight;       /* weight of the crop's TV term (0 = none) */
+  float lr[4];           /* Adam learning rates: mean, log-scale, quaternion, density */
+  float beta1, beta2, eps;
+  int32_t step;          /* Adam step count of this step (>= 1): bias correction */
+} fgs_step_params;
+
+typedef struct {
+  float *img;            /* device [det_h][det_w]: the rendered view (overwritten) */
+  float *grad_img;       /* device [det_h][det_w]: dL/dimg (overwritten) */
+  float *crop_vol;       /* device crop voxels (with a crop): its voxelization */
+  float *crop_grad;      /* device crop voxels (with a crop): dTV/dvol */
+  float *loss;           /* device [3]: L1 term, SSIM term (with ssim_weight > 0), TV term (with
+                            a crop); entries of absent terms are left as they are */
+} fgs_step_buffers;
+
+/* Renders view `view` of geom from the n Gaussians in `params` (device SoA,
+ * updated in place), takes the L1 term of Eq. 5 against gt[det_h][det_w]
+ * (device) plus ssim_weight times its SSIM term, backpropagates through the
+ * rasterizer (fgs_project_views_bwd over the forward's lists); with a crop
+ * grid and tv_weight > 0, voxelizes the crop, takes tv_weight times its TV
+ * and adds the voxelizer backward of that term to the gradient; then one
+ * Adam step (fgs_adam_step's arithmetic, densities clamped at 0) on all
+ * parameters with moments m, v (device, same layout, updated in place).
+ * `grad` (device, same layout) receives the step's gradient. opts: kappa,
+ * near plane, model, density_aabb_tau of the rasterizer (the crop's
+ * voxelizer takes kappa only); opts->events must be NULL. Workspaces: the
+ * rasterizer's (its lists are left there), the crop voxelizer's, and one
+ * for the loss terms (12 bytes per pixel and a few KiB). With key_capacity
+ * > 0 in ws_proj and ws_crop the step never waits for the GPU.
+ * Same error protocol as the calls it makes: on FGS_E_CAPACITY grow the
+ * named workspace and retry; on any error the parameters and moments are
+ * unchanged (scratch buffers may have been written). */
+int fgs_recon_step(fgs_gaussians_out *params, fgs_gaussian_grads *m, fgs_gaussian_grads *v,
+                   fgs_gaussian_grads *grad, int64_t n, const fgs_geom *geom, int32_t view, const float *gt,
+                   const fgs_grid *crop, const fgs_opts *opts, const fgs_step_params *sp,
+                   const fgs_step_buffers *buf, fgs_workspace *ws_proj, fgs_workspace *ws_crop,
+                   fgs_workspace *ws_loss, void *stream);
 
 /* ---------------------------------------------------------------------
  * Adaptive density control (Sec. 3.4: the loss gradient prunes, clones or

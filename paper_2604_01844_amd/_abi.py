@@ -58,7 +58,8 @@ class fgs_opts(ctypes.Structure):
 class fgs_workspace(ctypes.Structure):
     _fields_ = [("ptr", _vp), ("bytes", ctypes.c_uint64), ("needed", ctypes.c_uint64),
                 ("n_pairs", ctypes.c_uint64), ("n_records", ctypes.c_uint64),
-                ("n_tiles", ctypes.c_uint64), ("kind", ctypes.c_int32), ("tile_bits", ctypes.c_int32)]
+                ("n_tiles", ctypes.c_uint64), ("kind", ctypes.c_int32), ("tile_bits", ctypes.c_int32),
+                ("key_capacity", ctypes.c_uint64), ("overflow", _vp)]
 
 
 class fgs_adc_params(ctypes.Structure):
@@ -85,6 +86,16 @@ class fgs_mlp_grads(ctypes.Structure):
     _fields_ = [("dw1", _vp), ("db1", _vp), ("dw2", _vp), ("db2", _vp), ("dw3", _vp), ("db3", _vp)]
 
 
+class fgs_step_params(ctypes.Structure):
+    _fields_ = [("ssim_weight", ctypes.c_float), ("ssim_c1", ctypes.c_float), ("ssim_c2", ctypes.c_float),
+                ("tv_weight", ctypes.c_float), ("lr", ctypes.c_float * 4), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("step", ctypes.c_int32)]
+
+
+class fgs_step_buffers(ctypes.Structure):
+    _fields_ = [("img", _vp), ("grad_img", _vp), ("crop_vol", _vp), ("crop_grad", _vp), ("loss", _vp)]
+
+
 P = ctypes.POINTER
 # (name, argtypes) of every symbol declared in include/factgs.h
 SIGNATURES = {
@@ -92,6 +103,9 @@ SIGNATURES = {
                               P(fgs_opts), _vp, P(fgs_workspace), _vp],
     "fgs_project_views_fwd_noalloc": [P(fgs_gaussians), P(fgs_geom), ctypes.c_int32, ctypes.c_int32,
                                       P(fgs_opts), _vp, _vp],
+    "fgs_recon_step": [P(fgs_gaussian_grads), P(fgs_gaussian_grads), P(fgs_gaussian_grads), P(fgs_gaussian_grads),
+                       ctypes.c_int64, P(fgs_geom), ctypes.c_int32, _vp, P(fgs_grid), P(fgs_opts), P(fgs_step_params),
+                       P(fgs_step_buffers), P(fgs_workspace), P(fgs_workspace), P(fgs_workspace), _vp],
     "fgs_project_views_bwd": [P(fgs_gaussians), P(fgs_geom), ctypes.c_int32, ctypes.c_int32,
                               P(fgs_opts), _vp, P(fgs_gaussian_grads), P(fgs_workspace), _vp],
     "fgs_voxelize_fwd": [P(fgs_gaussians), P(fgs_grid), P(fgs_opts), _vp, P(fgs_workspace), _vp],

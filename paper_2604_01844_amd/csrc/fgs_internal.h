@@ -138,10 +138,22 @@ inline int sort_passes(uint64_t n, int bits, int max_bits = kSortMaxBits) {
 // Stable LSD radix sort of (key, value) uint32 pairs on the low `bits` bits
 // of the key. Input in keys/vals; the sorted result ends in the buffers
 // returned through out_keys/out_vals (either the inputs or the alternates).
+// n_dev (may be null): a device word holding the number of pairs, at most
+// n; the launches are sized for n and sort only that many (no host wait).
 uint64_t sort_scratch_words(uint64_t n);
 int radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
                      uint64_t n, int bits, uint32_t *scratch, uint32_t **out_keys,
-                     uint32_t **out_vals, hipStream_t s, int max_bits = kSortMaxBits);
+                     uint32_t **out_vals, hipStream_t s, int max_bits = kSortMaxBits,
+                     const uint32_t *n_dev = nullptr);
+
+// Pair count of a binning from its kTotalSlots 64-bit partial totals:
+// count[0] = the total if it is at most cap, else 0 (nothing is binned);
+// count[1] = 1 if the total exceeds cap, else 0. With cap > 0 and a non-null
+// `overflow` (device uint32[2]), an excess also sets overflow[0] = 1 and
+// raises overflow[1] to the total (clamped to 2^32 - 1). One wave.
+constexpr int kTotalSlots = 64;
+int pair_count(const unsigned long long *total64, uint64_t cap, uint32_t *count, uint32_t *overflow,
+               hipStream_t s);
 
 inline int bits_for(uint64_t n_values) {  // bits needed to hold 0 .. n_values - 1
   int b = 0;

@@ -68,7 +68,6 @@ __device__ __forceinline__ void tile_span(float c, float r, int n_tiles, int &t0
   t1 = min(jhi >> 4, n_tiles - 1);
 }
 
-constexpr int kTotalSlots = 64;
 constexpr float kLn2 = 0.6931471805599453f;
 
 // Support threshold of one record on the pre-scaled exponent
@@ -86,6 +85,15 @@ __device__ __forceinline__ float support_thr(float thr, float log2_tau, float w)
 // pass by ~0.3 ms per standard-scan step, and two 7-bit passes (16384 tiles)
 // beat three 5-bit ones.
 constexpr int kRastSortBits = 7;
+// Up to this many pairs (a single view or a few) the tile field, at most 10
+// bits, is sorted in one pass: with few keys per workgroup-tile the second
+// pass's histogram, scan and scatter launches cost more than the wider
+// digit's ranking.
+constexpr uint64_t kOnePassKeys = uint64_t(4) << 20;
+
+inline int rast_sort_bits(uint64_t K, int tile_bits) {
+  return (K <= kOnePassKeys && tile_bits <= kSortMaxBits) ? kSortMaxBits : kRastSortBits;
+}
 
 // What the pixel kernels read per (tile, Gaussian) pair, packed in one
 // 32-byte line: a = (u, v, pre-scaled conic c00, c01), b = (c11, w, base,
@@ -246,7 +254,9 @@ __global__ __launch_bounds__(kEmitBlock) void emit_kernel(uint64_t R, int64_t n,
                                                           const uint32_t *__restrict__ offset,
                                                           uint32_t *__restrict__ keys,
                                                           uint32_t *__restrict__ vals, float *__restrict__ base_field,
-                                                          uint32_t base_stride) {
+                                                          uint32_t base_stride, const uint32_t *__restrict__ kdev) {
+  // nothing to emit: no pairs, or more than the lists were laid out for
+  if (kdev[0] == 0u) return;
   __shared__ uint32_t s_off[kEmitBlock + 1];
   __shared__ ushort4 s_rect[kEmitBlock];
   const uint64_t r0 = uint64_t(blockIdx.x) * kEmitBlock;
@@ -304,8 +314,10 @@ __global__ __launch_bounds__(256) void zero_ranges_kernel(uint2 *__restrict__ rn
 // lanes 0 and 63); only the keys just outside its span are loaded twice.
 constexpr int kRangeItems = 16;
 
-__global__ __launch_bounds__(256) void ranges_kernel(const uint32_t *__restrict__ skeys, uint64_t K, int tile_bits,
+__global__ __launch_bounds__(256) void ranges_kernel(const uint32_t *__restrict__ skeys, uint64_t K_cap,
+                                                     const uint32_t *__restrict__ kdev, int tile_bits,
                                                      uint32_t tpv, uint2 *__restrict__ rng) {
+  const uint64_t K = min(K_cap, uint64_t(kdev[0]));
   const int lane = threadIdx.x & (kWave - 1);
   const uint64_t base = ((uint64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6) * uint64_t(kWave * kRangeItems);
   if (base >= K) return;  // uniform over the wave
@@ -336,6 +348,127 @@ __global__ __launch_bounds__(256) void ranges_kernel(const uint32_t *__restrict_
       if (next != kv) rng[tile].y = uint32_t(k + 1);
     }
   }
+}
+
+// ---------------------------------------------------------------- work units
+//
+// Calls with few tiles (a single view: 1024 tiles of 512^2) cannot fill the
+// chip with one wave per tile, and their list lengths vary widely (on a
+// standard-scan view from 0 to about 3,500 keys). Their lists are split into
+// contiguous pieces of at least kUnitKeys keys (more when a list would need
+// more than kMaxUnits pieces), one wave each, so the units are of nearly
+// equal size whatever the spread; an empty tile gets one unit (the forward
+// still writes its zero pixels). first[t] is the first unit of tile t
+// (first[T] = the number of units), tile[u] the tile of unit u. The forward
+// writes each unit's 16 x 16 partial sums to its own slot, and every pixel
+// then adds its tile's units in order, so the result is deterministic.
+constexpr uint32_t kUnitKeys = 128;
+constexpr uint32_t kMaxUnits = 32;
+
+__device__ __forceinline__ uint32_t unit_keys(uint32_t len) {
+  const uint32_t per = (len + kMaxUnits - 1) / kMaxUnits;
+  return max(kUnitKeys, (per + kWave - 1) / kWave * kWave);
+}
+
+__device__ __forceinline__ uint32_t units_of(uint32_t len) {
+  return len == 0 ? 1u : (len + unit_keys(len) - 1) / unit_keys(len);
+}
+
+// Units of a call, or first == null: a fixed number of strided chunks per tile.
+struct Units {
+  const uint32_t *first;   // [T + 1]
+  const uint32_t *tile;    // [cap]
+  uint32_t cap;            // units the launch covers (an upper bound)
+};
+
+// Units that T tiles holding K pairs can need: sum over tiles of
+// ceil(len / kUnitKeys) + 1 at most.
+inline uint64_t units_bound(uint64_t T, uint64_t K) { return T + (K + kUnitKeys - 1) / kUnitKeys; }
+
+// The unit of this wave in a launch over U.cap units, false past the units
+// of the call. The launch is sized for the bound, which at a fixed key
+// capacity can be twice the units there are; the XCD-aware order is taken
+// over the blocks that hold units, so that they spread over all XCDs rather
+// than filling the lower ones while the upper ones get the empty blocks.
+template <int TPB>
+__device__ __forceinline__ bool unit_of_wave(const Units &U, uint32_t n_tiles, int wid, uint32_t &unit) {
+  const uint32_t nu = min(U.first[n_tiles], U.cap);
+  const uint32_t nb = (nu + uint32_t(TPB) - 1) / uint32_t(TPB);
+  if (blockIdx.x >= nb) return false;
+  unit = uint32_t(__builtin_amdgcn_readfirstlane(int(xcd_block(blockIdx.x, nb) * uint32_t(TPB) + uint32_t(wid))));
+  return unit < nu;
+}
+
+// One workgroup of 1024 threads, T <= 8192 tiles (8 per thread).
+__global__ __launch_bounds__(1024) void unit_offsets_kernel(const uint2 *__restrict__ rng, uint32_t T, uint32_t cap,
+                                                           uint32_t *__restrict__ first, uint32_t *__restrict__ tile) {
+  __shared__ uint32_t wsum[16];
+  const uint32_t per = (T + 1023u) / 1024u;
+  const uint32_t t0 = threadIdx.x * per;
+  uint32_t cnt[8];
+  uint32_t s = 0;
+#pragma unroll
+  for (uint32_t j = 0; j < 8; ++j) {
+    const uint32_t t = t0 + j;
+    cnt[j] = (j < per && t < T) ? units_of(rng[t].y - rng[t].x) : 0u;
+    s += cnt[j];
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t x = s;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  uint32_t base = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    base += k < w ? wsum[k] : 0u;
+    tot += wsum[k];
+  }
+  base += x - s;
+  if (threadIdx.x == 0) first[T] = tot;
+#pragma unroll
+  for (uint32_t j = 0; j < 8; ++j) {
+    const uint32_t t = t0 + j;
+    if (j < per && t < T) {
+      first[t] = base;
+      for (uint32_t u = 0; u < cnt[j]; ++u)
+        if (base + u < cap) tile[base + u] = t;
+      base += cnt[j];
+    }
+  }
+}
+
+// img[v][y][x] = sum over the units u of the pixel's tile, in order, of
+// part[u][y % 16][x % 16] (each unit's 16 x 16 partial sums)
+__global__ __launch_bounds__(256) void sum_units_kernel(const float *__restrict__ part, const uint32_t *__restrict__ first,
+                                                        int tiles_x, int tpv, int W, int H, uint64_t n_img,
+                                                        float *__restrict__ img) {
+  const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n_img) return;
+  const uint64_t wh = uint64_t(W) * uint64_t(H);
+  const uint32_t v = uint32_t(i / wh);
+  const uint32_t p = uint32_t(i - uint64_t(v) * wh);
+  const uint32_t y = p / uint32_t(W), x = p - y * uint32_t(W);
+  const uint32_t t = v * uint32_t(tpv) + (y / kTS) * uint32_t(tiles_x) + x / kTS;
+  const uint32_t lp = (y % kTS) * kTS + (x % kTS);
+  const uint32_t u0 = first[t], u1 = first[t + 1];
+  const float *q = part + uint64_t(u0) * (kTS * kTS) + lp;
+  const uint32_t nu = u1 - u0;
+  float acc = q[0];
+  // eight loads in flight at a time, added in unit order
+  for (uint32_t u = 1; u < nu; u += 8) {
+    float x[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) x[j] = u + j < nu ? q[uint64_t(u + j) * (kTS * kTS)] : 0.f;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (u + j < nu) acc += x[j];
+  }
+  img[i] = acc;
 }
 
 // ---------------------------------------------------------------- quadrants
@@ -517,12 +650,14 @@ __device__ __forceinline__ void set_null_record(float4 *s_cw, float2 *s_xy) {
 
 // kCount = true: instead of the image, count the (pixel, Gaussian) pairs in
 // the support whose pixel lies on the detector (the algorithmic work).
-template <bool kCount, bool kInterior, int TPB>
-__global__ __launch_bounds__(kWave * TPB) void splat_fwd_kernel(const uint2 *__restrict__ rng,
+// kTau: the density-aware support (per-record thresholds, read with each
+// pair); without it the pixel loop compares with the kernel argument.
+template <bool kCount, bool kInterior, int TPB, bool kTau>
+__global__ __launch_bounds__(kWave * TPB) __attribute__((amdgpu_waves_per_eu(8, 8))) void splat_fwd_kernel(const uint2 *__restrict__ rng,
                                                            const uint32_t *__restrict__ svals,
                                                            const SplatRec *__restrict__ rec,
                                                            int tiles_x, int tpv, int W, int H,
-                                                           uint32_t n_tiles, int n_chunks, float thr,
+                                                           uint32_t n_tiles, int n_chunks, Units U, float thr,
                                                            float log2_tau, int no_cull,
                                                            float *__restrict__ img,
                                                            unsigned long long *__restrict__ counter) {
@@ -534,17 +669,35 @@ __global__ __launch_bounds__(kWave * TPB) void splat_fwd_kernel(const uint2 *__r
   float4 *s_cw = s_rec_all[wid][0];
   float4 *s_xy = s_rec_all[wid][1];
   uint8_t(*s_list)[kWave] = s_list_all[wid];
-  // work unit = (tile, chunk): chunk c takes batches c, c + n_chunks, ... of
-  // the tile's list and writes its own partial image (n_chunks > 1)
-  const uint32_t unit = xcd_block(blockIdx.x, gridDim.x) * TPB + wid;
-  if (unit >= n_tiles * uint32_t(n_chunks)) return;
-  const uint32_t tile = unit / uint32_t(n_chunks);
-  const uint32_t chunk = unit - tile * uint32_t(n_chunks);
+  // work unit: a piece of a tile's list (U.first), or (tile, chunk) where
+  // chunk c takes batches c, c + n_chunks, ...; each writes its own partial
+  // image when there are several per tile
+  // everything about the unit is the same across the wave (scalar registers)
+  uint32_t unit, tile, chunk, b_first, b_end, stride;
+  if (U.first) {
+    if (!unit_of_wave<TPB>(U, n_tiles, wid, unit)) return;
+    tile = uint32_t(__builtin_amdgcn_readfirstlane(int(U.tile[unit])));
+    chunk = unit - U.first[tile];
+    const uint32_t lo = rng[tile].x, hi = rng[tile].y, per = unit_keys(hi - lo);
+    b_first = lo + chunk * per;
+    b_end = min(hi, b_first + per);
+    stride = kWave;
+  } else {
+    unit = uint32_t(__builtin_amdgcn_readfirstlane(int(xcd_block(blockIdx.x, gridDim.x) * TPB + wid)));
+    if (unit >= n_tiles * uint32_t(n_chunks)) return;
+    tile = unit / uint32_t(n_chunks);
+    chunk = unit - tile * uint32_t(n_chunks);
+    b_first = rng[tile].x + chunk * kWave;
+    b_end = rng[tile].y;
+    stride = kWave * uint32_t(n_chunks);
+  }
+  b_first = uint32_t(__builtin_amdgcn_readfirstlane(int(b_first)));
+  b_end = uint32_t(__builtin_amdgcn_readfirstlane(int(b_end)));
+  chunk = uint32_t(__builtin_amdgcn_readfirstlane(int(chunk)));
   const uint32_t v_local = tile / uint32_t(tpv);
   const uint32_t t = tile - v_local * uint32_t(tpv);
   const int ty = int(t) / tiles_x;
   const int tx = int(t) - ty * tiles_x;
-  const uint32_t rt = tile;
   const int lane = threadIdx.x & (kWave - 1);
   // 16-lane group grp owns quadrant grp. Its two 8-lane halves take two pairs
   // of the quadrant's list at a time (entries i and i + 1), each lane a
@@ -564,11 +717,10 @@ __global__ __launch_bounds__(kWave * TPB) void splat_fwd_kernel(const uint2 *__r
   float acc[kFwdRows];
 #pragma unroll
   for (int k = 0; k < kFwdRows; ++k) acc[k] = 0.f;
-  const uint32_t b0 = rng[rt].x, e = rng[rt].y;
-  const uint32_t stride = kWave * uint32_t(n_chunks);
+  const uint32_t e = b_end;
   BatchPrefetch<SplatRec> pf;
-  pf.start(svals, rec, b0 + chunk * kWave, stride, e, lane);
-  for (uint32_t b = b0 + chunk * kWave; b < e; b += stride) {
+  pf.start(svals, rec, b_first, stride, e, lane);
+  for (uint32_t b = b_first; b < e; b += stride) {
     const uint32_t m = min(uint32_t(kWave), e - b);
     pf.advance(svals, rec, b, stride, e, lane);
     uint32_t mask = 0, imask = 0;
@@ -632,11 +784,12 @@ __global__ __launch_bounds__(kWave * TPB) void splat_fwd_kernel(const uint2 *__r
       for (int k = 0; k < kFwdRows; ++k) {
         const float fk = float(k);
         const float arg = (k == 0) ? arg0 : fmaf(fk, fmaf(c.z, fk, E), arg0);
+        const float cut = kTau ? q.w : thr;
         if (kCount) {
-          acc[k] += (arg >= q.w) ? 1.f : 0.f;
+          acc[k] += (arg >= cut) ? 1.f : 0.f;
         } else {
           const float ex = __builtin_amdgcn_exp2f(arg);
-          acc[k] = fmaf(c.w, (arg >= q.w) ? ex : 0.f, acc[k]);
+          acc[k] = fmaf(c.w, (arg >= cut) ? ex : 0.f, acc[k]);
         }
       }
     }
@@ -659,6 +812,13 @@ __global__ __launch_bounds__(kWave * TPB) void splat_fwd_kernel(const uint2 *__r
 #pragma unroll
   for (int k = 0; k < kFwdRows; ++k) acc[k] += __shfl_down(acc[k], 8, kWave);
   if (half) return;
+  if (U.first) {
+    // the unit's own 16 x 16 slot; every pixel is written
+    float *slot = img + uint64_t(unit) * (kTS * kTS);
+#pragma unroll
+    for (int k = 0; k < kFwdRows; ++k) slot[(row0 + k) * kTS + col] = acc[k];
+    return;
+  }
   float *out = img + (uint64_t(chunk) * (n_tiles / uint32_t(tpv)) + v_local) * uint64_t(W) * uint64_t(H);
 #pragma unroll
   for (int k = 0; k < kFwdRows; ++k) {
@@ -685,11 +845,14 @@ __device__ __forceinline__ float bperm(int src_lane, float v) {
 // the pair's six sums to the pair's emission slot: no atomics, and the
 // summation order is fixed. 72 registers (7 waves per SIMD): at 64 the
 // round loop spilled, and 72 measured 2% faster on 512^2 views.
-template <int TPB>
+// kTau: the density-aware support, whose per-record threshold the pixel
+// loop reads from LDS; without it the loop compares with the kernel argument.
+template <int TPB, bool kTau>
 __global__ __launch_bounds__(kWave * TPB) __attribute__((amdgpu_waves_per_eu(7, 7))) void splat_bwd_kernel(
     const uint2 *__restrict__ rng, const uint32_t *__restrict__ svals,
     const SplatRec *__restrict__ rec, int tiles_x, int tpv, int W, int H, uint32_t n_tiles, int n_chunks,
-    float thr, float log2_tau, int no_cull, const float *__restrict__ gimg, float4 *__restrict__ partials) {
+    Units U, float thr, float log2_tau, int no_cull, const float *__restrict__ gimg,
+    float2 *__restrict__ partials) {
   // per pixel: g = dL/dI and g cc (cc: column relative to the quadrant
   // centre), so the row loop accumulates with three FMAs per pixel
   __shared__ float4 s_g4_all[TPB][2][kTS * kTS / 4];
@@ -702,17 +865,40 @@ __global__ __launch_bounds__(kWave * TPB) __attribute__((amdgpu_waves_per_eu(7, 
   float4 *s_cw = s_cw_all[wid];
   float2 *s_xy = s_xy_all[wid];
   uint8_t *s_cat = s_cat_all[wid];
-  // work unit = (tile, chunk): chunk c takes batches c, c + n_chunks, ...
-  // (each pair's sums go to its own slot, so chunks are independent)
-  const uint32_t unit = xcd_block(blockIdx.x, gridDim.x) * TPB + wid;
-  if (unit >= n_tiles * uint32_t(n_chunks)) return;
-  const uint32_t tile = unit / uint32_t(n_chunks);
-  const uint32_t chunk = unit - tile * uint32_t(n_chunks);
-  const uint32_t v_local = tile / uint32_t(tpv);
-  const uint32_t t = tile - v_local * uint32_t(tpv);
+  // work unit: a piece of a tile's list (U.first, tiles in row order), or
+  // (tile, chunk) where chunk c takes batches c, c + n_chunks, ... (each
+  // pair's sums go to its own slot, so units are independent). Everything
+  // about the unit is the same across the wave (kept in scalar registers).
+  uint32_t unit, rt, v_local, b_first, b_end, stride;
   int tx, ty;
-  tile_of(t, tiles_x, tpv / tiles_x, tx, ty);
-  const uint32_t rt = v_local * uint32_t(tpv) + uint32_t(ty * tiles_x + tx);
+  if (U.first) {
+    if (!unit_of_wave<TPB>(U, n_tiles, wid, unit)) return;
+    rt = uint32_t(__builtin_amdgcn_readfirstlane(int(U.tile[unit])));
+    const uint32_t chunk = unit - U.first[rt];
+    v_local = rt / uint32_t(tpv);
+    const uint32_t t = rt - v_local * uint32_t(tpv);
+    ty = int(t) / tiles_x;
+    tx = int(t) - ty * tiles_x;
+    const uint32_t lo = rng[rt].x, hi = rng[rt].y, per = unit_keys(hi - lo);
+    b_first = lo + chunk * per;
+    b_end = min(hi, b_first + per);
+    stride = kWave;
+    if (b_first >= b_end) return;  // an empty tile: nothing to write
+  } else {
+    unit = uint32_t(__builtin_amdgcn_readfirstlane(int(xcd_block(blockIdx.x, gridDim.x) * TPB + wid)));
+    if (unit >= n_tiles * uint32_t(n_chunks)) return;
+    const uint32_t tile = unit / uint32_t(n_chunks);
+    const uint32_t chunk = unit - tile * uint32_t(n_chunks);
+    v_local = tile / uint32_t(tpv);
+    const uint32_t t = tile - v_local * uint32_t(tpv);
+    tile_of(t, tiles_x, tpv / tiles_x, tx, ty);
+    rt = v_local * uint32_t(tpv) + uint32_t(ty * tiles_x + tx);
+    b_first = rng[rt].x + chunk * kWave;
+    b_end = rng[rt].y;
+    stride = kWave * uint32_t(n_chunks);
+  }
+  b_first = uint32_t(__builtin_amdgcn_readfirstlane(int(b_first)));
+  b_end = uint32_t(__builtin_amdgcn_readfirstlane(int(b_end)));
   const int lane = threadIdx.x & (kWave - 1);
   const float *gv = gimg + uint64_t(v_local) * uint64_t(W) * uint64_t(H);
   for (int p = lane; p < kTS * kTS; p += kWave) {
@@ -727,8 +913,8 @@ __global__ __launch_bounds__(kWave * TPB) __attribute__((amdgpu_waves_per_eu(7, 
   wave_lds_sync();
   const float tx0 = float(tx * kTS) + 0.5f, ty0 = float(ty * kTS) + 0.5f;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const uint32_t b0 = rng[rt].x, e = rng[rt].y;
-  for (uint32_t b = b0 + chunk * kWave; b < e; b += kWave * uint32_t(n_chunks)) {
+  const uint32_t e = b_end;
+  for (uint32_t b = b_first; b < e; b += stride) {
     const uint32_t m = min(uint32_t(kWave), e - b);
     uint32_t mask = 0, slot = 0;
     if (uint32_t(lane) < m) {
@@ -807,7 +993,7 @@ __global__ __launch_bounds__(kWave * TPB) __attribute__((amdgpu_waves_per_eu(7, 
           for (int u = 0; u < 4; ++u) {
             const float cc = float(qd * 4 + u) - 3.5f;
             const float arg = fmaf(cc, fmaf(c.x, cc, brow), drow);
-            const float ex = (arg >= c.w) ? __builtin_amdgcn_exp2f(arg) : 0.f;
+            const float ex = (arg >= (kTau ? c.w : thr)) ? __builtin_amdgcn_exp2f(arg) : 0.f;
             A[qd * 4 + u] = fmaf(G0[u], ex, A[qd * 4 + u]);
             R0 = fmaf(G0[u], ex, R0);
             R1 = fmaf(G1[u], ex, R1);
@@ -856,8 +1042,10 @@ __global__ __launch_bounds__(kWave * TPB) __attribute__((amdgpu_waves_per_eu(7, 
       base += P;
     }
     if (uint32_t(lane) < m) {
-      partials[2 * uint64_t(slot) + 0] = make_float4(tot[0], tot[1], tot[2], tot[3]);
-      partials[2 * uint64_t(slot) + 1] = make_float4(tot[4], tot[5], 0.f, 0.f);
+      // the pair's six sums: a 24-byte slot
+      partials[3 * uint64_t(slot) + 0] = make_float2(tot[0], tot[1]);
+      partials[3 * uint64_t(slot) + 1] = make_float2(tot[2], tot[3]);
+      partials[3 * uint64_t(slot) + 2] = make_float2(tot[4], tot[5]);
     }
     wave_lds_sync();
   }
@@ -947,37 +1135,48 @@ __global__ __launch_bounds__(256) void fill_zero_kernel(float *__restrict__ p, u
 constexpr int kGradLanes = 8;
 constexpr int kGradUnroll = 4;
 
+template <int RPB>
 __global__ __launch_bounds__(256) void record_grad_kernel(fgs_gaussians g, GeomDev G,
                                                           const uint32_t *__restrict__ offset,
-                                                          const float4 *__restrict__ partials,
+                                                          const float2 *__restrict__ partials,
                                                           const float *__restrict__ acc6, uint64_t R,
+                                                          const uint32_t *__restrict__ kdev,
                                                           float *__restrict__ grad_rec) {
-  __shared__ float s_sum[256][7];
+  __shared__ float s_sum[RPB][7];
+  __shared__ uint32_t s_off[RPB + 1];
+  // kdev[1]: the lists overflowed their capacity and hold nothing
+  const bool none = kdev[1] != 0u;
   const int t = threadIdx.x;
-  const int64_t i0 = int64_t(blockIdx.x) * 256;
+  const int64_t i0 = int64_t(blockIdx.x) * RPB;
   const int v_local = blockIdx.y;
   const uint64_t rbase = uint64_t(v_local) * uint64_t(g.n);
+  // the block's RPB + 1 offsets in one coalesced read (offset has R + 1 entries)
+  for (int j = t; j <= RPB; j += 256)
+    if (i0 + j <= g.n) s_off[j] = offset[rbase + uint64_t(i0 + j)];
+  __syncthreads();
   const int li = t % kGradLanes;
-  for (int idx = t / kGradLanes; idx < 256 && !acc6; idx += 256 / kGradLanes) {
+  for (int idx = t / kGradLanes; idx < RPB && !acc6; idx += 256 / kGradLanes) {
+    if (i0 + idx >= g.n || none) break;
+    const uint32_t o = s_off[idx], end = s_off[idx + 1];
+    if (o == end) continue;  // the whole lane group agrees: no pairs, nothing to sum
     float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    if (i0 + idx < g.n) {
-      const uint64_t r = rbase + uint64_t(i0 + idx);
-      const uint32_t o = offset[r], end = offset[r + 1];
+    {
       // kGradUnroll slots' loads in flight at a time; summed in slot order
       for (uint32_t p = o + li; p < end; p += kGradUnroll * kGradLanes) {
-        float4 a[kGradUnroll];
-        float2 b[kGradUnroll];
+        float2 a[kGradUnroll], b[kGradUnroll], c[kGradUnroll];
 #pragma unroll
         for (int u = 0; u < kGradUnroll; ++u) {
           const uint32_t pp = p + uint32_t(u * kGradLanes);
-          a[u] = pp < end ? partials[2 * uint64_t(pp) + 0] : make_float4(0.f, 0.f, 0.f, 0.f);
-          b[u] = pp < end ? *reinterpret_cast<const float2 *>(&partials[2 * uint64_t(pp) + 1]) : make_float2(0.f, 0.f);
+          const float2 z = make_float2(0.f, 0.f);
+          a[u] = pp < end ? partials[3 * uint64_t(pp) + 0] : z;
+          b[u] = pp < end ? partials[3 * uint64_t(pp) + 1] : z;
+          c[u] = pp < end ? partials[3 * uint64_t(pp) + 2] : z;
         }
 #pragma unroll
         for (int u = 0; u < kGradUnroll; ++u) {
           if (p + uint32_t(u * kGradLanes) >= end) break;
-          acc[0] += a[u].x; acc[1] += a[u].y; acc[2] += a[u].z;
-          acc[3] += a[u].w; acc[4] += b[u].x; acc[5] += b[u].y;
+          acc[0] += a[u].x; acc[1] += a[u].y; acc[2] += b[u].x;
+          acc[3] += b[u].y; acc[4] += c[u].x; acc[5] += c[u].y;
         }
       }
     }
@@ -991,10 +1190,10 @@ __global__ __launch_bounds__(256) void record_grad_kernel(fgs_gaussians g, GeomD
   }
   __syncthreads();
   const int64_t i = i0 + t;
-  if (i >= g.n) return;
+  if (t >= RPB || i >= g.n) return;
   const uint64_t r = rbase + uint64_t(i);
   float out[11];
-  if (offset[r] == offset[r + 1]) {
+  if (none || s_off[t] == s_off[t + 1]) {
 #pragma unroll
     for (int c = 0; c < 11; ++c) grad_rec[uint64_t(c) * R + r] = 0.f;
     return;
@@ -1389,8 +1588,10 @@ __global__ __launch_bounds__(kWave * TPB) void splat_bwd_exact_kernel(
 __global__ __launch_bounds__(256) void record_grad_exact_kernel(fgs_gaussians g, GeomDev G,
                                                                 const uint32_t *__restrict__ offset,
                                                                 const float4 *__restrict__ partials, uint64_t R,
+                                                                const uint32_t *__restrict__ kdev,
                                                                 float *__restrict__ grad_rec) {
   __shared__ float s_sum[256][kExactSums + 1];
+  const bool none = kdev[1] != 0u;
   const int t = threadIdx.x;
   const int64_t i0 = int64_t(blockIdx.x) * 256;
   const int v_local = blockIdx.y;
@@ -1400,7 +1601,7 @@ __global__ __launch_bounds__(256) void record_grad_exact_kernel(fgs_gaussians g,
     float acc[kExactSums];
 #pragma unroll
     for (int c = 0; c < kExactSums; ++c) acc[c] = 0.f;
-    if (i0 + idx < g.n) {
+    if (i0 + idx < g.n && !none) {
       const uint64_t r = rbase + uint64_t(i0 + idx);
       const uint32_t o = offset[r], end = offset[r + 1];
       for (uint32_t p = o + li; p < end; p += kGradLanes) {
@@ -1426,7 +1627,7 @@ __global__ __launch_bounds__(256) void record_grad_exact_kernel(fgs_gaussians g,
   if (i >= g.n) return;
   const uint64_t r = rbase + uint64_t(i);
   float out[11];
-  bool zero = offset[r] == offset[r + 1];
+  bool zero = none || offset[r] == offset[r + 1];
   ExactSplat X;
   GaussParams P;
   ViewFrame F;
@@ -1454,10 +1655,10 @@ __global__ __launch_bounds__(256) void record_grad_exact_kernel(fgs_gaussians g,
 struct RastLayout {
   uint64_t R, T, K;
   // byte offsets
-  uint64_t total64, xy, radii, rect, offset, rec, scan_scratch, rng, grad_rec;
+  uint64_t total64, kdev, xy, radii, rect, offset, rec, scan_scratch, rng, grad_rec;
   uint64_t fixed_end;
-  uint64_t keys, vals, keys_alt, vals_alt, sort_scratch, partials;
-  uint64_t total;
+  uint64_t keys, vals, keys_alt, vals_alt, sort_scratch, partials, ufirst, utile, uslots;
+  uint64_t total, n_units;
   bool sorted_in_alt;
 };
 
@@ -1469,6 +1670,7 @@ RastLayout rast_layout(uint64_t R, uint64_t T, uint64_t K, bool exact, int tile_
   L.K = K;
   Carver c(nullptr);
   c.take<unsigned long long>(kTotalSlots, &L.total64);
+  c.take<uint32_t>(4, &L.kdev);
   c.take<float2>(R, &L.xy);
   c.take<float2>(R, &L.radii);
   c.take<ushort4>(R, &L.rect);
@@ -1486,10 +1688,16 @@ RastLayout rast_layout(uint64_t R, uint64_t T, uint64_t K, bool exact, int tile_
   c.take<uint32_t>(K, &L.keys_alt);
   c.take<uint32_t>(K, &L.vals_alt);
   c.take<uint32_t>(sort_scratch_words(K), &L.sort_scratch);
-  c.take<float4>((exact ? 4 : 2) * K, &L.partials);
+  // per pair: the splat backward's six sums (24 bytes), the ray-exact one's 13 (64-byte slots)
+  c.take<float>((exact ? 16 : 6) * K, &L.partials);
+  L.n_units = units_bound(T, K);
+  c.take<uint32_t>(T + 1, &L.ufirst);
+  c.take<uint32_t>(L.n_units, &L.utile);
+  // the forward's 16 x 16 partial sums per work unit (calls with few tiles)
+  c.take<float>(!exact && chunks_per_tile(T) > 1 ? L.n_units * uint64_t(kTS * kTS) : 0, &L.uslots);
   L.total = c.used;
   const int bits = tile_bits;
-  const int passes = sort_passes(K, bits, kRastSortBits);
+  const int passes = sort_passes(K, bits, rast_sort_bits(K, bits));
   L.sorted_in_alt = (passes & 1) != 0;
   return L;
 }
@@ -1497,6 +1705,27 @@ RastLayout rast_layout(uint64_t R, uint64_t T, uint64_t K, bool exact, int tile_
 struct TileGrid {
   int tiles_x, tiles_y, tpv;
 };
+
+// Calls with few tiles split each list into work units (splat model) or a
+// fixed number of strided chunks (ray-exact model); the forward keeps one
+// partial image per piece index or chunk. Large calls take one wave per tile.
+inline bool use_units(uint64_t T, bool exact) { return !exact && chunks_per_tile(T) > 1; }
+
+// Bytes of the forward's partial images after the lists: one per chunk for
+// the ray-exact model with few tiles (the splat model's units have slots in
+// the lists' layout), none otherwise.
+inline uint64_t forward_partial_bytes(uint64_t T, bool exact, uint64_t n_img) {
+  const int c = chunks_per_tile(T);
+  return (exact && c > 1) ? uint64_t(c) * n_img * sizeof(float) + 256 : 0;
+}
+
+template <typename T>
+T *at(void *base, uint64_t off);
+
+Units make_units(const RastLayout &L, void *b, bool on) {
+  if (!on) return Units{nullptr, nullptr, 0u};
+  return Units{at<uint32_t>(b, L.ufirst), at<uint32_t>(b, L.utile), uint32_t(L.n_units)};
+}
 
 TileGrid tile_grid(int det_w, int det_h) {
   TileGrid t;
@@ -1587,9 +1816,20 @@ int build_lists(const fgs_gaussians *g, const fgs_geom *geom, int32_t view_begin
   if (T >= 0xffffffffull || R >= 0xffffffffull) return fail(FGS_E_UNSUPPORTED, "too many tiles or records in one call");
   const bool exact = use_exact(geom, o);
   const int tile_bits = bits_for(uint64_t(tg.tpv));
-  RastLayout L = rast_layout(R, T, 0, exact, tile_bits);
+  // key_capacity > 0: the lists are laid out for that many pairs and the
+  // pair count stays on the device (no wait); else it is read back first
+  const uint64_t cap = ws->key_capacity;
+  if (cap >= 0xffffffffull) return fail(FGS_E_UNSUPPORTED, "key_capacity must be below 2^32");
+  RastLayout L = rast_layout(R, T, cap, exact, tile_bits);
   ws->kind = 0;
-  if (!ws->ptr || ws->bytes < L.fixed_end + (uint64_t(1) << 20)) {
+  if (cap > 0) {
+    ws->needed = L.total + extra_bytes;
+    ws->n_pairs = cap;
+    ws->n_records = R;
+    ws->n_tiles = T;
+    ws->tile_bits = tile_bits;
+    if (!ws->ptr || ws->bytes < ws->needed) return fail(FGS_E_CAPACITY, "workspace too small for key_capacity pairs");
+  } else if (!ws->ptr || ws->bytes < L.fixed_end + (uint64_t(1) << 20)) {
     ws->needed = L.fixed_end + (uint64_t(64) << 20);
     return fail(FGS_E_CAPACITY, "workspace too small for the per-record arrays");
   }
@@ -1610,41 +1850,52 @@ int build_lists(const fgs_gaussians *g, const fgs_geom *geom, int32_t view_begin
   FGS_LAUNCH_CHECK("record_kernel");
   int st = exclusive_scan_u32(at<uint32_t>(b, L.offset), R, at<uint32_t>(b, L.scan_scratch), s);
   if (st != FGS_OK) return st;
-  unsigned long long slots[kTotalSlots];
-  FGS_HIP(hipMemcpyAsync(slots, total64, sizeof(slots), hipMemcpyDeviceToHost, s));
-  FGS_HIP(hipStreamSynchronize(s));
-  unsigned long long K64 = 0;
-  for (int i = 0; i < kTotalSlots; ++i) K64 += slots[i];
-  if (K64 >= 0xffffffffull)
-    return fail(FGS_E_UNSUPPORTED, "more than 2^32 (tile, Gaussian) pairs in one call; split the views");
-  const uint64_t K = K64;
-  L = rast_layout(R, T, K, exact, tile_bits);
-  ws->needed = L.total + extra_bytes;
-  ws->n_pairs = K;
-  ws->n_records = R;
-  ws->n_tiles = T;
-  ws->tile_bits = tile_bits;
-  if (ws->bytes < L.total + extra_bytes) return fail(FGS_E_CAPACITY, "workspace too small for the tile lists");
-  if (K > 0) {
+  uint32_t *kdev = at<uint32_t>(b, L.kdev);
+  if (cap == 0) {
+    unsigned long long slots[kTotalSlots];
+    FGS_HIP(hipMemcpyAsync(slots, total64, sizeof(slots), hipMemcpyDeviceToHost, s));
+    FGS_HIP(hipStreamSynchronize(s));
+    unsigned long long K64 = 0;
+    for (int i = 0; i < kTotalSlots; ++i) K64 += slots[i];
+    if (K64 >= 0xffffffffull)
+      return fail(FGS_E_UNSUPPORTED, "more than 2^32 (tile, Gaussian) pairs in one call; split the views");
+    const uint64_t K = K64;
+    L = rast_layout(R, T, K, exact, tile_bits);
+    ws->needed = L.total + extra_bytes;
+    ws->n_pairs = K;
+    ws->n_records = R;
+    ws->n_tiles = T;
+    ws->tile_bits = tile_bits;
+    if (ws->bytes < L.total + extra_bytes) return fail(FGS_E_CAPACITY, "workspace too small for the tile lists");
+  }
+  // the device copy of the pair count (0 if it exceeds the capacity)
+  st = pair_count(total64, cap > 0 ? cap : L.K, kdev, cap > 0 ? ws->overflow : nullptr, s);
+  if (st != FGS_OK) return st;
+  if (L.K > 0) {
     emit_kernel<<<grid_for(R, kEmitBlock), kEmitBlock, 0, s>>>(R, g->n, tg.tiles_x, tile_bits, at<ushort4>(b, L.rect),
                                                   at<uint32_t>(b, L.offset), at<uint32_t>(b, L.keys),
                                                   at<uint32_t>(b, L.vals),
                                                   exact ? &at<ExactRec>(b, L.rec)->d.y : &at<SplatRec>(b, L.rec)->b.z,
-                                                  exact ? 16u : 8u);
+                                                  exact ? 16u : 8u, kdev);
     FGS_LAUNCH_CHECK("emit_kernel");
   }
   uint32_t *sk, *sv;
   st = radix_sort_pairs(at<uint32_t>(b, L.keys), at<uint32_t>(b, L.vals), at<uint32_t>(b, L.keys_alt),
-                        at<uint32_t>(b, L.vals_alt), K, tile_bits, at<uint32_t>(b, L.sort_scratch),
-                        &sk, &sv, s, kRastSortBits);
+                        at<uint32_t>(b, L.vals_alt), L.K, tile_bits, at<uint32_t>(b, L.sort_scratch),
+                        &sk, &sv, s, rast_sort_bits(L.K, tile_bits), cap > 0 ? kdev : nullptr);
   if (st != FGS_OK) return st;
   zero_ranges_kernel<<<grid_for(T, 256), 256, 0, s>>>(at<uint2>(b, L.rng), T);
   FGS_LAUNCH_CHECK("zero_ranges_kernel");
-  if (K > 0) {
-    const uint64_t waves = (K + uint64_t(kWave * kRangeItems) - 1) / uint64_t(kWave * kRangeItems);
-    ranges_kernel<<<grid_for(waves * kWave, 256), 256, 0, s>>>(sk, K, tile_bits, uint32_t(tg.tpv),
+  if (L.K > 0) {
+    const uint64_t waves = (L.K + uint64_t(kWave * kRangeItems) - 1) / uint64_t(kWave * kRangeItems);
+    ranges_kernel<<<grid_for(waves * kWave, 256), 256, 0, s>>>(sk, L.K, kdev, tile_bits, uint32_t(tg.tpv),
                                                                at<uint2>(b, L.rng));
     FGS_LAUNCH_CHECK("ranges_kernel");
+  }
+  if (use_units(T, exact)) {
+    unit_offsets_kernel<<<1, 1024, 0, s>>>(at<uint2>(b, L.rng), uint32_t(T), uint32_t(L.n_units),
+                                           at<uint32_t>(b, L.ufirst), at<uint32_t>(b, L.utile));
+    FGS_LAUNCH_CHECK("unit_offsets_kernel");
   }
   ws->kind = exact ? 3 : 1;
   *Lout = L;
@@ -1668,22 +1919,24 @@ extern "C" int fgs_project_views_fwd(const fgs_gaussians *g, const fgs_geom *geo
   hipStream_t s = static_cast<hipStream_t>(stream);
   const TileGrid tg = tile_grid(geom->det_w, geom->det_h);
   const uint64_t T = uint64_t(view_count) * uint64_t(tg.tpv);
+  const bool exact = use_exact(geom, opts);
   const int chunks = chunks_per_tile(T);
   const uint64_t n_img = uint64_t(view_count) * uint64_t(geom->det_w) * uint64_t(geom->det_h);
-  // partial images of the chunks, after the lists (only when chunked)
-  const uint64_t part_bytes = chunks > 1 ? uint64_t(chunks) * n_img * sizeof(float) + 256 : 0;
+  // the ray-exact model's partial images of the chunks, after the lists
+  const uint64_t part_bytes = forward_partial_bytes(T, exact, n_img);
   RastLayout L;
   st = build_lists(g, geom, view_begin, view_count, opts, ws, s, &L, part_bytes);
   if (st != FGS_OK) return st;
   void *b = ws->ptr;
-  float *part = chunks > 1 ? at<float>(b, (L.total + 255) / 256 * 256) : img;
+  float *part = part_bytes ? at<float>(b, (L.total + 255) / 256 * 256)
+                           : (use_units(T, exact) ? at<float>(b, L.uslots) : img);
   const uint32_t *sv = at<uint32_t>(b, L.sorted_in_alt ? L.vals_alt : L.vals);
   const float thr = -0.5f * kLog2e * opts->kappa * opts->kappa;
   const float log2_tau = opts->density_aabb_tau > 0.f ? log2f(opts->density_aabb_tau) : -INFINITY;
   hipEvent_t *ev = static_cast<hipEvent_t *>(opts->events);
   if (ev) FGS_HIP(hipEventRecord(ev[0], s));
-  const uint64_t units = L.T * uint64_t(chunks);
-  if (use_exact(geom, opts)) {
+  if (exact) {
+    const uint64_t units = L.T * uint64_t(chunks);
     const ExactCam cam = exact_cam(make_geom_dev(geom, opts, view_begin, tg));
     with_tiles_per_block(units, [&](auto tpb) {
       constexpr int TPB = decltype(tpb)::value;
@@ -1692,25 +1945,37 @@ extern "C" int fgs_project_views_fwd(const fgs_gaussians *g, const fgs_geom *geo
           uint32_t(L.T), chunks, thr, thr * kCullSlack, cam, part, nullptr);
     });
     FGS_LAUNCH_CHECK("splat_fwd_exact_kernel");
+    if (part_bytes) {
+      st = sum_chunks(part, chunks, n_img, img, s);
+      if (st != FGS_OK) return st;
+    }
   } else {
+    const Units U = make_units(L, b, use_units(T, false));
+    const uint64_t units = U.first ? L.n_units : L.T;
     const int no_cull = (opts->ablate & FGS_ABLATE_QUADRANT_CULL) ? 1 : 0;
     const bool interior = L.K >= kInteriorKeysPerRecord * L.R;
+    const bool tau = opts->density_aabb_tau > 0.f;
     with_tiles_per_block(units, [&](auto tpb) {
       constexpr int TPB = decltype(tpb)::value;
-      if (interior)
-        splat_fwd_kernel<false, true, TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
+      if (tau)
+        splat_fwd_kernel<false, false, TPB, true><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
             at<uint2>(b, L.rng), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
-            uint32_t(L.T), chunks, thr, log2_tau, no_cull, part, nullptr);
+            uint32_t(L.T), 1, U, thr, log2_tau, no_cull, part, nullptr);
+      else if (interior)
+        splat_fwd_kernel<false, true, TPB, false><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
+            at<uint2>(b, L.rng), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
+            uint32_t(L.T), 1, U, thr, log2_tau, no_cull, part, nullptr);
       else
-        splat_fwd_kernel<false, false, TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
+        splat_fwd_kernel<false, false, TPB, false><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
             at<uint2>(b, L.rng), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
-            uint32_t(L.T), chunks, thr, log2_tau, no_cull, part, nullptr);
+            uint32_t(L.T), 1, U, thr, log2_tau, no_cull, part, nullptr);
     }, L.K >= kSmallBlockKeysPerTile * L.T);
     FGS_LAUNCH_CHECK("splat_fwd_kernel");
-  }
-  if (chunks > 1) {
-    st = sum_chunks(part, chunks, n_img, img, s);
-    if (st != FGS_OK) return st;
+    if (U.first) {
+      sum_units_kernel<<<grid_for(n_img, 256), 256, 0, s>>>(part, U.first, tg.tiles_x, tg.tpv, geom->det_w,
+                                                             geom->det_h, n_img, img);
+      FGS_LAUNCH_CHECK("sum_units_kernel");
+    }
   }
   if (ev) FGS_HIP(hipEventRecord(ev[1], s));
   return FGS_OK;
@@ -1747,11 +2012,18 @@ extern "C" int fgs_project_views_support(const fgs_gaussians *g, const fgs_geom 
     FGS_LAUNCH_CHECK("splat_fwd_exact_kernel<count>");
     return FGS_OK;
   }
-  with_tiles_per_block(units, [&](auto tpb) {
+  const Units U = make_units(L, b, use_units(L.T, false));
+  const uint64_t sunits = U.first ? L.n_units : L.T;
+  with_tiles_per_block(sunits, [&](auto tpb) {
     constexpr int TPB = decltype(tpb)::value;
-    splat_fwd_kernel<true, false, TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
-        at<uint2>(b, L.rng), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
-        uint32_t(L.T), chunks, thr, log2_tau, 0, nullptr, cnt);
+    if (opts->density_aabb_tau > 0.f)
+      splat_fwd_kernel<true, false, TPB, true><<<grid_for(sunits, TPB), kWave * TPB, 0, s>>>(
+          at<uint2>(b, L.rng), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
+          uint32_t(L.T), 1, U, thr, log2_tau, 0, nullptr, cnt);
+    else
+      splat_fwd_kernel<true, false, TPB, false><<<grid_for(sunits, TPB), kWave * TPB, 0, s>>>(
+          at<uint2>(b, L.rng), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
+          uint32_t(L.T), 1, U, thr, log2_tau, 0, nullptr, cnt);
   }, L.K >= kSmallBlockKeysPerTile * L.T);
   FGS_LAUNCH_CHECK("splat_fwd_kernel<count>");
   return FGS_OK;
@@ -1802,7 +2074,7 @@ extern "C" int fgs_project_views_bwd(const fgs_gaussians *g, const fgs_geom *geo
     if (ev) FGS_HIP(hipEventRecord(ev[1], s));
     dim3 rgrid(grid_for(uint64_t(g->n), 256), unsigned(view_count));
     record_grad_exact_kernel<<<rgrid, 256, 0, s>>>(*g, G, at<uint32_t>(b, L.offset), at<float4>(b, L.partials), R,
-                                                   at<float>(b, L.grad_rec));
+                                                   at<uint32_t>(b, L.kdev), at<float>(b, L.grad_rec));
     FGS_LAUNCH_CHECK("record_grad_exact_kernel");
     view_sum_kernel<<<grid_for(uint64_t(g->n), 256), 256, 0, s>>>(g->n, view_count, at<float>(b, L.grad_rec),
                                                                   *out, opts->accumulate);
@@ -1812,7 +2084,7 @@ extern "C" int fgs_project_views_bwd(const fgs_gaussians *g, const fgs_geom *geo
   float *acc6 = nullptr;
   if (opts->ablate & FGS_ABLATE_PER_PIXEL_BWD) {
     // the records' accumulators take the place of the pair slots
-    if (8 * L.K < 6 * R) return fail(FGS_E_UNSUPPORTED, "per-pixel backward ablation: too few pairs");
+    if (L.K < R) return fail(FGS_E_UNSUPPORTED, "per-pixel backward ablation: too few pairs");
     acc6 = at<float>(b, L.partials);
     fill_zero_kernel<<<grid_for(6 * R, 256), 256, 0, s>>>(acc6, 6 * R);
     FGS_LAUNCH_CHECK("fill_zero_kernel");
@@ -1823,21 +2095,36 @@ extern "C" int fgs_project_views_bwd(const fgs_gaussians *g, const fgs_geom *geo
       FGS_LAUNCH_CHECK("splat_bwd_pixel_kernel");
     }
   } else if (L.K > 0) {
-    const int chunks = chunks_per_tile(L.T);
-    const uint64_t units = L.T * uint64_t(chunks);
+    const Units U = make_units(L, b, use_units(L.T, false));
+    const int chunks = U.first ? 1 : chunks_per_tile(L.T);
+    const uint64_t units = U.first ? L.n_units : L.T * uint64_t(chunks);
     with_tiles_per_block(units, [&](auto tpb) {
       constexpr int TPB = decltype(tpb)::value;
-      splat_bwd_kernel<TPB><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
-          at<uint2>(b, L.rng), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
-          uint32_t(L.T), chunks, thr, log2_tau, (opts->ablate & FGS_ABLATE_QUADRANT_CULL) ? 1 : 0,
-          grad_img, at<float4>(b, L.partials));
+      if (opts->density_aabb_tau > 0.f)
+        splat_bwd_kernel<TPB, true><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
+            at<uint2>(b, L.rng), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
+            uint32_t(L.T), chunks, U, thr, log2_tau, (opts->ablate & FGS_ABLATE_QUADRANT_CULL) ? 1 : 0,
+            grad_img, at<float2>(b, L.partials));
+      else
+        splat_bwd_kernel<TPB, false><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
+            at<uint2>(b, L.rng), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
+            uint32_t(L.T), chunks, U, thr, log2_tau, (opts->ablate & FGS_ABLATE_QUADRANT_CULL) ? 1 : 0,
+            grad_img, at<float2>(b, L.partials));
     }, true);
     FGS_LAUNCH_CHECK("splat_bwd_kernel");
   }
   if (ev) FGS_HIP(hipEventRecord(ev[1], s));
-  dim3 rgrid(grid_for(uint64_t(g->n), 256), unsigned(view_count));
-  record_grad_kernel<<<rgrid, 256, 0, s>>>(*g, G, at<uint32_t>(b, L.offset), at<float4>(b, L.partials), acc6, R,
-                                           at<float>(b, L.grad_rec));
+  // few records (one view): 64 records per block, so that the blocks cover
+  // the chip; the sums are the same either way
+  if (uint64_t(grid_for(uint64_t(g->n), 256)) * uint64_t(view_count) < 2048) {
+    dim3 rgrid(grid_for(uint64_t(g->n), 64), unsigned(view_count));
+    record_grad_kernel<64><<<rgrid, 256, 0, s>>>(*g, G, at<uint32_t>(b, L.offset), at<float2>(b, L.partials), acc6,
+                                                 R, at<uint32_t>(b, L.kdev), at<float>(b, L.grad_rec));
+  } else {
+    dim3 rgrid(grid_for(uint64_t(g->n), 256), unsigned(view_count));
+    record_grad_kernel<256><<<rgrid, 256, 0, s>>>(*g, G, at<uint32_t>(b, L.offset), at<float2>(b, L.partials), acc6,
+                                                  R, at<uint32_t>(b, L.kdev), at<float>(b, L.grad_rec));
+  }
   FGS_LAUNCH_CHECK("record_grad_kernel");
   view_sum_kernel<<<grid_for(uint64_t(g->n), 256), 256, 0, s>>>(g->n, view_count, at<float>(b, L.grad_rec),
                                                                 *out, opts->accumulate);
@@ -1864,9 +2151,8 @@ int rast_workspace_bytes(const fgs_gaussians *g, const fgs_geom *geom, int32_t v
   const uint64_t k_ref = uint64_t(1) << 24;
   const uint64_t base = rast_layout(R, T, 0, exact, bits).total;
   const uint64_t big = rast_layout(R, T, k_ref, exact, bits).total;
-  const int chunks = chunks_per_tile(T);
   const uint64_t n_img = uint64_t(view_count) * uint64_t(geom->det_w) * uint64_t(geom->det_h);
-  const uint64_t part = (forward && chunks > 1) ? uint64_t(chunks) * n_img * sizeof(float) + 256 : 0;
+  const uint64_t part = forward ? forward_partial_bytes(T, exact, n_img) : 0;
   // every array the pair count sizes is padded to 256 bytes: 8 arrays at most
   // (a call first asks for the per-record arrays plus 1 MiB before it knows K)
   *fixed_bytes = base + part + 8 * kAlign + (uint64_t(1) << 20);

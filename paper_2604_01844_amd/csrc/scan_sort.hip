@@ -22,6 +22,9 @@ constexpr int kItems = 16;
 constexpr int kTile = kThreads * kItems;  // 4096
 constexpr int kWaves = kThreads / 64;
 constexpr int kMaxBins = 1 << kSortMaxBits;
+// Scans of at most this many tiles of kTile values let each block sum the
+// tile totals before it instead of scanning them in a launch of their own.
+constexpr uint64_t kSelfPrefixTiles = 4096;
 
 // Exclusive scan of one value per thread across the 256-thread block.
 template <typename T>
@@ -63,15 +66,27 @@ __global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const T *__restri
   if (threadIdx.x == 0) partial[blockIdx.x] = total;
 }
 
-// Scans one tile in LDS; adds the scanned tile offset (partial, may be null
-// for a single tile). The last tile writes the grand total to data[n].
+// Scans one tile in LDS; adds the tile's offset. partial (may be null for a
+// single tile): with self_prefix, the tiles' sums, of which each block adds
+// up those before it (one launch fewer; used for few tiles); else the
+// already scanned tile offsets. The last tile writes the grand total to
+// data[n].
 template <typename T>
 __global__ __launch_bounds__(kThreads) void scan_apply_kernel(T *__restrict__ data, uint64_t n,
                                                               const T *__restrict__ partial,
-                                                              uint32_t n_tiles) {
+                                                              uint32_t n_tiles, int self_prefix) {
   __shared__ T tile[kTile + kTile / 32];
   __shared__ T wsum[kWaves];
+  __shared__ T s_pre;
   const uint64_t base = uint64_t(blockIdx.x) * kTile;
+  if (partial && self_prefix) {
+    T acc = 0;
+    for (uint32_t k = threadIdx.x; k < blockIdx.x; k += kThreads) acc += partial[k];
+    T tot;
+    block_exclusive_scan(acc, wsum, tot);
+    if (threadIdx.x == 0) s_pre = tot;
+    __syncthreads();
+  }
   // padded index: one spare word every 32 to spread the strided reads over banks
   auto pad = [](int i) { return i + (i >> 5); };
 #pragma unroll
@@ -90,7 +105,7 @@ __global__ __launch_bounds__(kThreads) void scan_apply_kernel(T *__restrict__ da
   }
   T total;
   T run = block_exclusive_scan(s, wsum, total);
-  const T off = partial ? partial[blockIdx.x] : T(0);
+  const T off = partial ? (self_prefix ? s_pre : partial[blockIdx.x]) : T(0);
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
     tile[pad(threadIdx.x * kItems + j)] = run + off;
@@ -111,13 +126,21 @@ __global__ __launch_bounds__(kThreads) void scan_apply_kernel(T *__restrict__ da
 // NB: the widest digit the kernel is built for (its LDS tables hold 2^NB
 // bins); each pass runs the smallest build (6, 9 or 10 bits) that holds its
 // digit, which needs the least LDS.
+// n_dev (may be null): the number of pairs on the device, at most n; the
+// grid is sized for n and tiles past the device count hold nothing.
+__device__ __forceinline__ uint64_t pair_count(uint64_t n, const uint32_t *n_dev) {
+  return n_dev ? min(n, uint64_t(*n_dev)) : n;
+}
+
 template <int NB>
 __global__ __launch_bounds__(kThreads) void rs_hist_kernel(const uint32_t *__restrict__ keys,
-                                                           uint64_t n, int shift, uint32_t mask,
+                                                           uint64_t n_cap, const uint32_t *__restrict__ n_dev,
+                                                           int shift, uint32_t mask,
                                                            uint32_t *__restrict__ hist,
                                                            uint32_t n_tiles) {
   constexpr int kBins = 1 << NB;
   __shared__ uint32_t h[kBins];
+  const uint64_t n = pair_count(n_cap, n_dev);
   for (int i = threadIdx.x; i < kBins; i += kThreads) h[i] = 0;
   __syncthreads();
   const uint64_t base = uint64_t(blockIdx.x) * kTile;
@@ -145,9 +168,10 @@ __global__ __launch_bounds__(kThreads) void rs_hist_kernel(const uint32_t *__res
 // each digit's run, so the global writes are coalesced.
 template <int NB>
 __global__ __launch_bounds__(kThreads) void rs_scatter_kernel(
-    const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in, uint64_t n,
-    int shift, int nbits, const uint32_t *__restrict__ hist_scanned, uint32_t n_tiles,
-    uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out) {
+    const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in, uint64_t n_cap,
+    const uint32_t *__restrict__ n_dev, int shift, int nbits, const uint32_t *__restrict__ hist_scanned,
+    uint32_t n_tiles, uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out) {
+  const uint64_t n = pair_count(n_cap, n_dev);
   constexpr int kBins = 1 << NB;
   __shared__ uint32_t cnt[kWaves][kBins];
   __shared__ uint32_t s_local[kBins];     // tile-local start of each digit's run
@@ -246,7 +270,7 @@ __global__ __launch_bounds__(kThreads) void rs_scatter_kernel(
   }
   __syncthreads();
   const uint64_t tbase = uint64_t(blockIdx.x) * kTile;
-  const int nt = int(min(uint64_t(kTile), n - tbase));
+  const int nt = tbase < n ? int(min(uint64_t(kTile), n - tbase)) : 0;
   for (int i = threadIdx.x; i < nt; i += kThreads) {
     const uint32_t key = s_keys[i];
     const uint32_t d = (key >> shift) & mask;
@@ -259,7 +283,31 @@ __global__ __launch_bounds__(kThreads) void rs_scatter_kernel(
 template <typename T>
 __global__ void set_zero_kernel(T *p) { *p = T(0); }
 
+__global__ __launch_bounds__(64) void pair_count_kernel(const unsigned long long *__restrict__ total64, uint64_t cap,
+                                                       uint32_t *__restrict__ count, uint32_t *__restrict__ overflow) {
+  unsigned long long v = total64[threadIdx.x];
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+  if (threadIdx.x == 0) {
+    const bool over = v > cap;
+    count[0] = over ? 0u : uint32_t(v);
+    count[1] = over ? 1u : 0u;
+    if (over && overflow) {
+      overflow[0] = 1u;
+      atomicMax(overflow + 1, uint32_t(v < 0xffffffffull ? v : 0xffffffffull));
+    }
+  }
+}
+
 }  // namespace
+
+int pair_count(const unsigned long long *total64, uint64_t cap, uint32_t *count, uint32_t *overflow,
+               hipStream_t s) {
+  static_assert(kTotalSlots == 64, "one wave sums the slots");
+  pair_count_kernel<<<1, 64, 0, s>>>(total64, cap, count, overflow);
+  FGS_LAUNCH_CHECK("pair_count_kernel");
+  return FGS_OK;
+}
 
 uint64_t scan_scratch_words(uint64_t n) {
   // in units of 64-bit words, enough for both element widths
@@ -283,7 +331,7 @@ static int exclusive_scan(T *data, uint64_t n, T *scratch, hipStream_t s) {
   }
   const uint64_t tiles = (n + kTile - 1) / kTile;
   if (tiles == 1) {
-    scan_apply_kernel<T><<<1, kThreads, 0, s>>>(data, n, nullptr, 1);
+    scan_apply_kernel<T><<<1, kThreads, 0, s>>>(data, n, nullptr, 1, 0);
     FGS_LAUNCH_CHECK("scan_apply_kernel");
     return FGS_OK;
   }
@@ -292,9 +340,14 @@ static int exclusive_scan(T *data, uint64_t n, T *scratch, hipStream_t s) {
   T *rest = scratch + align_up((tiles + 1) * sizeof(T)) / sizeof(T);
   scan_reduce_kernel<T><<<unsigned(tiles), kThreads, 0, s>>>(data, n, partial);
   FGS_LAUNCH_CHECK("scan_reduce_kernel");
-  int st = exclusive_scan<T>(partial, tiles, rest, s);
-  if (st != FGS_OK) return st;
-  scan_apply_kernel<T><<<unsigned(tiles), kThreads, 0, s>>>(data, n, partial, unsigned(tiles));
+  // few tiles: each block adds up the sums before it (two launches in all);
+  // many: the sums are scanned first
+  const int self_prefix = tiles <= kSelfPrefixTiles ? 1 : 0;
+  if (!self_prefix) {
+    int st = exclusive_scan<T>(partial, tiles, rest, s);
+    if (st != FGS_OK) return st;
+  }
+  scan_apply_kernel<T><<<unsigned(tiles), kThreads, 0, s>>>(data, n, partial, unsigned(tiles), self_prefix);
   FGS_LAUNCH_CHECK("scan_apply_kernel");
   return FGS_OK;
 }
@@ -315,7 +368,7 @@ uint64_t sort_scratch_words(uint64_t n) {
 
 int radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
                      uint64_t n, int bits, uint32_t *scratch, uint32_t **out_keys,
-                     uint32_t **out_vals, hipStream_t s, int max_bits) {
+                     uint32_t **out_vals, hipStream_t s, int max_bits, const uint32_t *n_dev) {
   *out_keys = keys;
   *out_vals = vals;
   if (n <= 1 || bits <= 0) return FGS_OK;
@@ -331,20 +384,23 @@ int radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_
     const int nb = (bits - shift < per) ? (bits - shift) : per;
     const uint32_t mask = (1u << nb) - 1u;
     if (nb > 9)
-      rs_hist_kernel<10><<<unsigned(tiles), kThreads, 0, s>>>(ki, n, shift, mask, table, unsigned(tiles));
+      rs_hist_kernel<10><<<unsigned(tiles), kThreads, 0, s>>>(ki, n, n_dev, shift, mask, table, unsigned(tiles));
     else if (nb > 6)
-      rs_hist_kernel<9><<<unsigned(tiles), kThreads, 0, s>>>(ki, n, shift, mask, table, unsigned(tiles));
+      rs_hist_kernel<9><<<unsigned(tiles), kThreads, 0, s>>>(ki, n, n_dev, shift, mask, table, unsigned(tiles));
     else
-      rs_hist_kernel<6><<<unsigned(tiles), kThreads, 0, s>>>(ki, n, shift, mask, table, unsigned(tiles));
+      rs_hist_kernel<6><<<unsigned(tiles), kThreads, 0, s>>>(ki, n, n_dev, shift, mask, table, unsigned(tiles));
     FGS_LAUNCH_CHECK("rs_hist_kernel");
     int st = exclusive_scan_u32(table, uint64_t(mask + 1) * tiles, scan_tmp, s);
     if (st != FGS_OK) return st;
     if (nb > 9)
-      rs_scatter_kernel<10><<<unsigned(tiles), kThreads, 0, s>>>(ki, vi, n, shift, nb, table, unsigned(tiles), ko, vo);
+      rs_scatter_kernel<10><<<unsigned(tiles), kThreads, 0, s>>>(ki, vi, n, n_dev, shift, nb, table, unsigned(tiles),
+                                                                 ko, vo);
     else if (nb > 6)
-      rs_scatter_kernel<9><<<unsigned(tiles), kThreads, 0, s>>>(ki, vi, n, shift, nb, table, unsigned(tiles), ko, vo);
+      rs_scatter_kernel<9><<<unsigned(tiles), kThreads, 0, s>>>(ki, vi, n, n_dev, shift, nb, table, unsigned(tiles),
+                                                                 ko, vo);
     else
-      rs_scatter_kernel<6><<<unsigned(tiles), kThreads, 0, s>>>(ki, vi, n, shift, nb, table, unsigned(tiles), ko, vo);
+      rs_scatter_kernel<6><<<unsigned(tiles), kThreads, 0, s>>>(ki, vi, n, n_dev, shift, nb, table, unsigned(tiles),
+                                                                 ko, vo);
     FGS_LAUNCH_CHECK("rs_scatter_kernel");
     uint32_t *t;
     t = ki; ki = ko; ko = t;

@@ -76,7 +76,6 @@ __device__ __forceinline__ void vox_span(float c, float r, int n_tiles, int &t0,
   t1 = min(static_cast<int>(floorf(hi)) >> 3, n_tiles - 1);
 }
 
-constexpr int kTotalSlots = 64;
 // The tile culling test keeps tiles whose best voxel centre has
 // d^2 <= k2 + kappa^2 (kCullSlack - 1), k2 the Gaussian's support bound (a
 // Mahalanobis radius about 0.05% beyond the kappa support): a superset of the
@@ -253,7 +252,9 @@ __global__ __launch_bounds__(256) void vox_emit_kernel(int64_t n, int ntx, int n
                                                        const uint32_t *__restrict__ offset,
                                                        const unsigned long long *__restrict__ hits,
                                                        uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
-                                                       uint32_t *__restrict__ gid) {
+                                                       uint32_t *__restrict__ gid, const uint32_t *__restrict__ kdev) {
+  // nothing to emit: no pairs, or more than the lists were laid out for
+  if (kdev[0] == 0u) return;
   const int64_t i = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (i >= n) return;
@@ -286,8 +287,10 @@ __global__ __launch_bounds__(256) void vox_emit_kernel(int64_t n, int ntx, int n
   }
 }
 
-__global__ __launch_bounds__(256) void vox_ranges_kernel(const uint32_t *__restrict__ skeys, uint64_t K,
-                                                         uint32_t T, uint32_t *__restrict__ start) {
+__global__ __launch_bounds__(256) void vox_ranges_kernel(const uint32_t *__restrict__ skeys, uint64_t K_cap,
+                                                         const uint32_t *__restrict__ kdev, uint32_t T,
+                                                         uint32_t *__restrict__ start) {
+  const uint64_t K = min(K_cap, uint64_t(kdev[0]));
   const uint64_t k = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (k > K) return;
   const int64_t prev = (k == 0) ? -1 : int64_t(skeys[k - 1]);
@@ -527,17 +530,26 @@ constexpr int kGradLanes = 32;
 __global__ __launch_bounds__(256) void vox_grad_kernel(fgs_gaussians g, GridDev G,
                                                        const uint32_t *__restrict__ offset,
                                                        const float2 *__restrict__ partials,
+                                                       const uint32_t *__restrict__ kdev,
                                                        fgs_gaussian_grads out, int accumulate) {
   __shared__ float s_sum[kGradGauss][11];
+  __shared__ uint32_t s_off[kGradGauss + 1];
+  // kdev[1]: the lists overflowed their capacity and hold nothing
+  const bool none = kdev[1] != 0u;
   const int t = threadIdx.x;
   const int64_t i0 = int64_t(blockIdx.x) * kGradGauss;
+  // the block's offsets in one coalesced read (offset has n + 1 entries)
+  if (t <= kGradGauss && i0 + t <= g.n) s_off[t] = offset[i0 + t];
+  __syncthreads();
   const int li = t % kGradLanes;
   for (int idx = t / kGradLanes; idx < kGradGauss; idx += 256 / kGradLanes) {
+    if (i0 + idx >= g.n || none) break;
+    const uint32_t o = s_off[idx], end = s_off[idx + 1];
+    if (o == end) continue;  // the whole lane group agrees: no pairs, nothing to sum
     float acc[10];
 #pragma unroll
     for (int c = 0; c < 10; ++c) acc[c] = 0.f;
-    if (i0 + idx < g.n) {
-      const uint32_t o = offset[i0 + idx], end = offset[i0 + idx + 1];
+    {
       for (uint32_t q = o + li; q < end; q += kGradLanes) {
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
@@ -560,7 +572,9 @@ __global__ __launch_bounds__(256) void vox_grad_kernel(fgs_gaussians g, GridDev 
   const int64_t i = i0 + t;
   if (i >= g.n) return;
   const int64_t n = g.n;
-  const uint32_t o = offset[i], end = offset[i + 1];
+  const uint32_t o = s_off[t], end = none ? o : s_off[t + 1];
+  // a Gaussian with no pair adds nothing: when accumulating, leave it alone
+  if (accumulate && o == end) return;
   float s[10];
 #pragma unroll
   for (int c = 0; c < 10; ++c) s[c] = s_sum[t][c];
@@ -614,7 +628,7 @@ __global__ __launch_bounds__(256) void vox_grad_kernel(fgs_gaussians g, GridDev 
 
 struct VoxLayout {
   uint64_t N, T, K;
-  uint64_t total64, prho, radii, rect, offset, a0, a1, scan_scratch, start, hits;
+  uint64_t total64, kdev, prho, radii, rect, offset, a0, a1, scan_scratch, start, hits;
   uint64_t fixed_end;
   uint64_t keys, vals, keys_alt, vals_alt, gid, sort_scratch, partials;
   uint64_t total;
@@ -628,6 +642,7 @@ VoxLayout vox_layout(uint64_t N, uint64_t T, uint64_t K) {
   L.K = K;
   Carver c(nullptr);
   c.take<unsigned long long>(kTotalSlots, &L.total64);
+  c.take<uint32_t>(4, &L.kdev);
   c.take<float4>(N, &L.prho);
   c.take<float4>(N, &L.radii);
   c.take<Rect3>(N, &L.rect);
@@ -693,9 +708,18 @@ int vox_build(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *o, f
   const uint64_t T = uint64_t(G.nt[0]) * G.nt[1] * G.nt[2];
   if (T >= 0xffffffffull) return fail(FGS_E_UNSUPPORTED, "too many voxel tiles");
   const uint64_t N = uint64_t(g->n);
-  VoxLayout L = vox_layout(N, T, 0);
+  // key_capacity > 0: lists laid out for that many pairs, count kept on the device
+  const uint64_t cap = ws->key_capacity;
+  if (cap >= 0xffffffffull) return fail(FGS_E_UNSUPPORTED, "key_capacity must be below 2^32");
+  VoxLayout L = vox_layout(N, T, cap);
   ws->kind = 0;
-  if (!ws->ptr || ws->bytes < L.fixed_end + (uint64_t(1) << 20)) {
+  if (cap > 0) {
+    ws->needed = L.total + extra_bytes;
+    ws->n_pairs = cap;
+    ws->n_records = N;
+    ws->n_tiles = T;
+    if (!ws->ptr || ws->bytes < ws->needed) return fail(FGS_E_CAPACITY, "workspace too small for key_capacity pairs");
+  } else if (!ws->ptr || ws->bytes < L.fixed_end + (uint64_t(1) << 20)) {
     ws->needed = L.fixed_end + (uint64_t(64) << 20);
     return fail(FGS_E_CAPACITY, "workspace too small for the per-Gaussian arrays");
   }
@@ -715,34 +739,40 @@ int vox_build(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *o, f
   FGS_LAUNCH_CHECK("vox_count_kernel");
   int st = exclusive_scan_u32(at<uint32_t>(b, L.offset), N, at<uint32_t>(b, L.scan_scratch), s);
   if (st != FGS_OK) return st;
-  unsigned long long slots[kTotalSlots];
-  FGS_HIP(hipMemcpyAsync(slots, total64, sizeof(slots), hipMemcpyDeviceToHost, s));
-  FGS_HIP(hipStreamSynchronize(s));
-  unsigned long long K64 = 0;
-  for (int i = 0; i < kTotalSlots; ++i) K64 += slots[i];
-  if (K64 >= 0xffffffffull)
-    return fail(FGS_E_UNSUPPORTED, "more than 2^32 (tile, Gaussian) pairs; split the grid into slabs");
-  const uint64_t K = K64;
-  L = vox_layout(N, T, K);
-  ws->needed = L.total + extra_bytes;
-  ws->n_pairs = K;
-  ws->n_records = N;
-  ws->n_tiles = T;
-  if (ws->bytes < L.total + extra_bytes) return fail(FGS_E_CAPACITY, "workspace too small for the tile lists");
+  uint32_t *kdev = at<uint32_t>(b, L.kdev);
+  if (cap == 0) {
+    unsigned long long slots[kTotalSlots];
+    FGS_HIP(hipMemcpyAsync(slots, total64, sizeof(slots), hipMemcpyDeviceToHost, s));
+    FGS_HIP(hipStreamSynchronize(s));
+    unsigned long long K64 = 0;
+    for (int i = 0; i < kTotalSlots; ++i) K64 += slots[i];
+    if (K64 >= 0xffffffffull)
+      return fail(FGS_E_UNSUPPORTED, "more than 2^32 (tile, Gaussian) pairs; split the grid into slabs");
+    const uint64_t K = K64;
+    L = vox_layout(N, T, K);
+    ws->needed = L.total + extra_bytes;
+    ws->n_pairs = K;
+    ws->n_records = N;
+    ws->n_tiles = T;
+    if (ws->bytes < L.total + extra_bytes) return fail(FGS_E_CAPACITY, "workspace too small for the tile lists");
+  }
+  st = pair_count(total64, cap > 0 ? cap : L.K, kdev, cap > 0 ? ws->overflow : nullptr, s);
+  if (st != FGS_OK) return st;
+  const uint64_t K = L.K;
   if (K > 0) {
     vox_emit_kernel<<<grid_for(N, 4), 256, 0, s>>>(int64_t(N), G.nt[0], G.nt[1], at<float4>(b, L.prho),
                                                     at<float4>(b, L.a0), at<float4>(b, L.a1), at<Rect3>(b, L.rect),
                                                     thr_widen, at<uint32_t>(b, L.offset),
                                                     at<unsigned long long>(b, L.hits), at<uint32_t>(b, L.keys),
-                                                    at<uint32_t>(b, L.vals), at<uint32_t>(b, L.gid));
+                                                    at<uint32_t>(b, L.vals), at<uint32_t>(b, L.gid), kdev);
     FGS_LAUNCH_CHECK("vox_emit_kernel");
   }
   uint32_t *sk, *sv;
   st = radix_sort_pairs(at<uint32_t>(b, L.keys), at<uint32_t>(b, L.vals), at<uint32_t>(b, L.keys_alt),
                         at<uint32_t>(b, L.vals_alt), K, bits_for(T), at<uint32_t>(b, L.sort_scratch),
-                        &sk, &sv, s);
+                        &sk, &sv, s, kSortMaxBits, cap > 0 ? kdev : nullptr);
   if (st != FGS_OK) return st;
-  vox_ranges_kernel<<<grid_for(K + 1, 256), 256, 0, s>>>(sk, K, uint32_t(T), at<uint32_t>(b, L.start));
+  vox_ranges_kernel<<<grid_for(K + 1, 256), 256, 0, s>>>(sk, K, kdev, uint32_t(T), at<uint32_t>(b, L.start));
   FGS_LAUNCH_CHECK("vox_ranges_kernel");
   ws->kind = 2;
   *Lout = L;
@@ -896,7 +926,8 @@ extern "C" int fgs_voxelize_bwd(const fgs_gaussians *g, const fgs_grid *grid, co
   }
   if (ev) FGS_HIP(hipEventRecord(ev[1], s));
   vox_grad_kernel<<<grid_for(uint64_t(g->n), kGradGauss), 256, 0, s>>>(*g, G, at<uint32_t>(b, L.offset),
-                                                                at<float2>(b, L.partials), *out,
+                                                                at<float2>(b, L.partials),
+                                                                at<uint32_t>(b, L.kdev), *out,
                                                                 opts->accumulate);
   FGS_LAUNCH_CHECK("vox_grad_kernel");
   return FGS_OK;

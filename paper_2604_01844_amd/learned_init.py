@@ -41,6 +41,20 @@ from .mlp import InitMLP, canonical_targets
 # PSNR levels (dB) at which both arms' seconds and epochs are also reported.
 LEVELS = (30.0, 35.0, 38.0)
 
+# Weights of the SSIM and crop-TV terms of Eq. 5 in the reconstruction runs
+# (the paper prints none; the same as the benchmark's one-view step).
+SSIM_WEIGHT = 0.25
+TV_WEIGHT = 0.05
+
+
+def eq5_loop(sc: "Scanner", eq5: bool = True) -> dict:
+    """Keyword arguments of recon.reconstruct for the loss of Eq. 5: L1, plus
+    SSIM_WEIGHT (1 - SSIM) of the view and TV_WEIGHT TV of a random 32^3 crop
+    of the reconstruction grid (eq5=False: L1 only)."""
+    if not eq5:
+        return {}
+    return dict(ssim_weight=SSIM_WEIGHT, tv=recon.CropTV(sc.eval_grid, TV_WEIGHT, 32, sc.device))
+
 
 @dataclass
 class ScanConfig:
@@ -157,10 +171,11 @@ class ArmResult:
 
 
 def run_arm(sc: Scanner, arm: str, seed: int, *, epochs: int, adam: recon.AdamConfig, net: InitMLP | None = None,
-            target_psnr: float | None = None, proj=None, vol_gt=None) -> ArmResult:
+            target_psnr: float | None = None, proj=None, vol_gt=None, eq5: bool = True) -> ArmResult:
     """Reconstruct phantom `seed` from its projections with one
-    initialisation; the clock covers FDK, the initialisation and the
-    optimisation (evaluation excluded)."""
+    initialisation and the loss of Eq. 5 (eq5=False: L1 only); the clock
+    covers FDK, the initialisation and the optimisation (evaluation
+    excluded)."""
     if proj is None or vol_gt is None:
         ph = sc.phantom(seed)
         proj = sc.project(ph)
@@ -178,7 +193,8 @@ def run_arm(sc: Scanner, arm: str, seed: int, *, epochs: int, adam: recon.AdamCo
     torch.cuda.synchronize()
     t_init = time.perf_counter() - t0
     hist = recon.reconstruct(model, proj, sc.geom, epochs=epochs, adam=adam, vol_gt=vol_gt, eval_grid=sc.eval_grid,
-                             eval_every=1, target_psnr=target_psnr, seed=seed, t_offset=t_init, eval_at_start=True)
+                             eval_every=1, target_psnr=target_psnr, seed=seed, t_offset=t_init, eval_at_start=True,
+                             **eq5_loop(sc, eq5))
     return ArmResult(t_init, hist)
 
 
@@ -275,6 +291,16 @@ def main(argv=None):
     def level_stat(lv, arm, key):
         v = [r["levels"][f"{lv:g}"][arm][key] for r in rows if r["levels"][f"{lv:g}"][arm][key] is not None]
         return dict(mean=float(np.mean(v)) if v else None, reached=len(v), of=len(rows))
+    def paired(key):
+        """Per-phantom learned - baseline differences of `key`, over the
+        phantoms both arms reached (a paired comparison on the same scan)."""
+        d = [r["learned"][key] - r["fdk_gradient"][key] for r in rows
+             if r["learned"][key] is not None and r["fdk_gradient"][key] is not None]
+        only = sum(1 for r in rows if (r["learned"][key] is None) != (r["fdk_gradient"][key] is None))
+        return dict(mean=float(np.mean(d)) if d else None, std=float(np.std(d)) if d else None,
+                    learned_faster=int(sum(x < 0 for x in d)), both_reached=len(d),
+                    learned_only=sum(1 for r in rows if r["learned"][key] is not None and r["fdk_gradient"][key] is None),
+                    one_arm_only=only, of=len(rows))
     summary = dict(
         pairs=a.pairs, pair_seconds=t_pairs, fit_psnr_mean=float(np.mean([p.fit_psnr for p in pairs])),
         train_epochs=a.train_epochs, train_steps=a.train_epochs * a.pairs, train_seconds=t_train,
@@ -282,6 +308,9 @@ def main(argv=None):
         arms={arm: {k: stat(arm, k) for k in ("s_to_target", "epochs_to_target", "psnr0", "psnr_final")}
               for arm in ("fdk_gradient", "learned")},
         tau_iter=dict(mean=float(np.mean(taus)) if taus else None, reached=len(taus), of=len(rows)),
+        paired=dict(s_to_target=paired("s_to_target"), epochs_to_target=paired("epochs_to_target"),
+                    psnr0=paired("psnr0"), psnr_final=paired("psnr_final")),
+        loss="Eq. 5: L1 + %g (1 - SSIM) + %g TV of a 32^3 crop" % (SSIM_WEIGHT, TV_WEIGHT),
         levels={f"{lv:g}": {arm: {k: level_stat(lv, arm, k) for k in ("s", "epochs")}
                             for arm in ("fdk_gradient", "learned")} for lv in LEVELS},
         per_phantom=rows)

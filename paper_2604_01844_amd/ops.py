@@ -81,6 +81,7 @@ class Workspace:
     def __init__(self, device="cuda", nbytes: int = 0):
         self.device = torch.device(device)
         self.buf = None
+        self.overflow_buf = None
         self.s = A.fgs_workspace()
         if nbytes:
             self.ensure(nbytes)
@@ -92,6 +93,27 @@ class Workspace:
             self.s.kind = 0
         self.s.ptr = self.buf.data_ptr()
         self.s.bytes = self.buf.numel()
+
+    def set_capacity(self, pairs: int):
+        """Lay the lists out for at most `pairs` (tile, Gaussian) pairs and keep
+        the pair count on the device (no host wait per call; key_capacity in
+        include/factgs.h). A call that needs more bins nothing and is recorded
+        in a device overflow word, read with overflowed()."""
+        if self.overflow_buf is None:
+            self.overflow_buf = torch.zeros(2, dtype=torch.int32, device=self.device)
+        self.s.key_capacity = int(pairs)
+        self.s.overflow = self.overflow_buf.data_ptr()
+        self.s.kind = 0
+
+    def overflowed(self, reset: bool = True):
+        """(any call overflowed since the last reset, largest pair count it
+        needed); waits for the stream. With reset, clears the record."""
+        if self.overflow_buf is None:
+            return False, 0
+        f, need = (int(x) for x in self.overflow_buf.tolist())
+        if reset and f:
+            self.overflow_buf.zero_()
+        return bool(f), need & 0xffffffff
 
     def call(self, fn, *args):
         """Call fn(*args, &ws, stream), growing the workspace on FGS_E_CAPACITY."""

@@ -28,12 +28,14 @@ Fitting follows Sec. 3.6 with the L1 term of Eq. 6:
 """
 from __future__ import annotations
 
+import ctypes
 import time
 from dataclasses import dataclass, field
 
 import numpy as np
 import torch
 
+from . import _abi as A
 from . import ops
 
 
@@ -129,6 +131,7 @@ class History:
     seconds: list = field(default_factory=list)   # optimisation clock (evaluation excluded)
     psnr: list = field(default_factory=list)
     loss: list = field(default_factory=list)
+    overflows: int = 0                            # step-capacity overflows seen (ViewStep)
 
     def seconds_to(self, target: float):
         for s, p in zip(self.seconds, self.psnr):
@@ -179,6 +182,92 @@ class CropTV:
         return loss
 
 
+class ViewStep:
+    """One optimiser step of the reconstruction loop as a single library call
+    (fgs_recon_step): forward of one view, L1 (+ SSIM) of Eq. 5, backward,
+    the optional crop TV, Adam on all parameters.
+
+    The rasterizer and crop workspaces run with a fixed key capacity, so no
+    step waits for the GPU: the rasterizer's is `key_margin` times the pairs
+    of view 0 at construction, the crop's `crop_keys`. A step whose pairs
+    exceed its capacity bins nothing (a zero image, no gradient from it);
+    check_overflow() (which waits for the GPU) reports that and raises the
+    capacity for the steps after it."""
+
+    def __init__(self, model: GaussianModel, geom: ops.Geometry, adam: AdamConfig, *, ssim_weight: float = 0.0,
+                 tv: "CropTV | None" = None, kappa: float = ops.KAPPA, near: float = ops.NEAR,
+                 key_margin: float = 2.0, crop_keys: int = 1 << 18):
+        dev = model.params[0].device
+        self.model, self.geom, self.adam, self.tv = model, geom, adam, tv
+        self.H, self.W = geom.det_h, geom.det_w
+        self.img = torch.empty((self.H, self.W), device=dev)
+        self.grad_img = torch.empty_like(self.img)
+        self.loss = torch.zeros(3, device=dev)
+        self.ws_proj = ops.Workspace(dev)
+        self.ws_crop = ops.Workspace(dev)
+        self.ws_loss = ops.Workspace(dev, 12 * self.H * self.W + (1 << 16))
+        ops.project_views(*model.params, geom, 0, 1, kappa=kappa, near=near, ws=self.ws_proj)
+        self.ws_proj.set_capacity(int(key_margin * self.ws_proj.n_pairs) + 4096)
+        if tv is not None:
+            self.ws_crop.set_capacity(crop_keys)
+        self.opts = ops._opts(kappa, near)
+        self.gm = geom.struct()
+        self.sp = A.fgs_step_params(float(ssim_weight), ops.SSIM_C1, ops.SSIM_C2,
+                                    float(tv.weight) if tv is not None else 0.0, (ctypes.c_float * 4)(*adam.lrs()),
+                                    adam.beta1, adam.beta2, adam.eps, 0)
+        self._bound = None
+
+    def _bind(self):
+        m = self.model
+        key = tuple(t.data_ptr() for t in (*m.params, *m.m, *m.v, *m.grads))
+        if key != self._bound:
+            self._p = A.fgs_gaussian_grads(*(A.ptr(t) for t in m.params))
+            self._m = A.fgs_gaussian_grads(*(A.ptr(t) for t in m.m))
+            self._v = A.fgs_gaussian_grads(*(A.ptr(t) for t in m.v))
+            self._g = A.fgs_gaussian_grads(*(A.ptr(t) for t in m.grads))
+            self._bound = key
+        tv = self.tv
+        self._buf = A.fgs_step_buffers(A.ptr(self.img), A.ptr(self.grad_img),
+                                       A.ptr(tv.vol) if tv is not None else None,
+                                       A.ptr(tv.grad) if tv is not None else None, A.ptr(self.loss))
+
+    def __call__(self, view: int, gt_view, rng=None):
+        """Step on view `view` against gt_view[H][W] (device, contiguous); rng
+        places the crop. Returns the device loss terms [L1, SSIM, TV]."""
+        self._bind()
+        m = self.model
+        crop = self.tv.crop(rng).struct() if self.tv is not None else None
+        self.sp.step = m.step + 1
+        L = A.lib()
+        stream = A.stream_ptr(self.img.device)
+        for _ in range(6):
+            code = L.fgs_recon_step(ctypes.byref(self._p), ctypes.byref(self._m), ctypes.byref(self._v),
+                                    ctypes.byref(self._g), m.n, ctypes.byref(self.gm), int(view), A.ptr(gt_view),
+                                    ctypes.byref(crop) if crop is not None else None, ctypes.byref(self.opts),
+                                    ctypes.byref(self.sp), ctypes.byref(self._buf), ctypes.byref(self.ws_proj.s),
+                                    ctypes.byref(self.ws_crop.s), ctypes.byref(self.ws_loss.s), stream)
+            if code != A.FGS_E_CAPACITY:
+                A.check(code)
+                m.step += 1
+                return self.loss
+            for w in (self.ws_proj, self.ws_loss, self.ws_crop):
+                if w.buf is None or int(w.s.needed) > w.buf.numel():
+                    w.ensure(max(int(w.s.needed), 1 << 20))
+        raise A.FgsError(A.FGS_E_CAPACITY, "step workspaces did not converge")
+
+    def check_overflow(self) -> int:
+        """Waits for the GPU. Number of workspaces whose capacity some step
+        since the last check exceeded (those steps binned nothing); each such
+        capacity is raised to 1.5 times the largest need seen."""
+        hit = 0
+        for w in (self.ws_proj, self.ws_crop):
+            f, need = w.overflowed()
+            if f:
+                hit += 1
+                w.set_capacity(int(1.5 * need) + 4096)
+        return hit
+
+
 def reconstruct(model: GaussianModel, proj_gt, geom: ops.Geometry, *, epochs: int, adam: AdamConfig,
                 vol_gt=None, eval_grid: ops.Grid | None = None, eval_every: int = 1,
                 target_psnr: float | None = None, seed: int = 0, clock_start: float | None = None,
@@ -209,11 +298,17 @@ def reconstruct(model: GaussianModel, proj_gt, geom: ops.Geometry, *, epochs: in
         if target_psnr is not None and hist.psnr[-1] >= target_psnr:
             return hist
         torch.cuda.synchronize()
-    t0 = time.perf_counter() if clock_start is None else clock_start
     dens = _Densifier(model, adc, dev) if adc is not None else None
+    # without density control a step is one library call that never waits
+    stepper = ViewStep(model, geom, adam, ssim_weight=ssim_weight, tv=tv) if dens is None else None
+    if stepper is not None and clock_start is None:
+        torch.cuda.synchronize()
+    t0 = time.perf_counter() if clock_start is None else clock_start
     for ep in range(1, epochs + 1):
-        loss_sum = 0.0
         for v in rng.permutation(V):
+            if stepper is not None:
+                loss = stepper(int(v), proj_gt[v], rng)[0:1]
+                continue
             ops.project_views(*model.params, geom, int(v), 1, ws=ws_p, out=img)
             loss, g = ops.l1_loss_grad(img, proj_gt[v:v + 1], ws=ws_l)
             if ssim_weight > 0:
@@ -236,6 +331,8 @@ def reconstruct(model: GaussianModel, proj_gt, geom: ops.Geometry, *, epochs: in
             hist.seconds.append(t_run)
             hist.psnr.append(p)
             hist.loss.append(float(loss.item()))
+            if stepper is not None:
+                hist.overflows += stepper.check_overflow()
             if target_psnr is not None and p >= target_psnr:
                 break
             torch.cuda.synchronize()

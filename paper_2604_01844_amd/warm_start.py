@@ -17,7 +17,7 @@ import torch
 import synth_inputs as si
 
 from . import ops, recon
-from .learned_init import LEVELS, ArmResult, Scanner, ScanConfig, iteration_ratio, run_arm
+from .learned_init import LEVELS, ArmResult, Scanner, ScanConfig, eq5_loop, iteration_ratio, run_arm
 
 
 def prior_phantom(sc: Scanner, seed: int) -> dict:
@@ -48,6 +48,7 @@ def run_warm(sc: Scanner, seed: int, *, epochs: int, adam: recon.AdamConfig, pro
     model = warm_model(sc, prior, u, fit_iters=fit_iters)
     torch.cuda.synchronize()
     t_init = time.perf_counter() - t0
+    loop = {**eq5_loop(sc), **loop}
     hist = recon.reconstruct(model, proj, sc.geom, epochs=epochs, adam=adam, vol_gt=vol_gt, eval_grid=sc.eval_grid,
                              eval_every=1, target_psnr=target_psnr, seed=seed, t_offset=t_init, eval_at_start=True,
                              **loop)

@@ -694,6 +694,32 @@ def test_full_size_whole_views_every_pixel(fgs, scan_case):
         _check_every_element(img[v], ref[0], band[0], f"view {v}")
 
 
+def test_full_size_single_view_calls_every_pixel(fgs, scan_case):
+    """One-view calls of the standard scan (the reconstruction loop's unit:
+    1024 tiles, lists split into work units of about 128 keys), with the
+    pair count read back and at a fixed key capacity: every pixel against
+    the oracle, the two calls bit-identical; their backward equals the
+    batched call's for that view."""
+    cfg, gs, gd, ang = scan_case
+    geom = fgs.Geometry.from_dict(gd, ang)
+    t = dev(gs)
+    for v in (7, 52):
+        ws = fgs.Workspace(DEV)
+        img = fgs.project_views(*args(t), geom, v, 1, ws=ws).cpu().numpy()
+        ref, band = oracle.project_banded(gs, gd, ang[v:v + 1])
+        _check_every_element(img[0], ref[0], band[0], f"single view {v}")
+        wc = fgs.Workspace(DEV)
+        wc.set_capacity(int(1.3 * ws.n_pairs))
+        img_c = fgs.project_views(*args(t), geom, v, 1, ws=wc).cpu().numpy()
+        assert np.array_equal(img, img_c)
+        c = torch.from_numpy(si.normals((1, 512, 512), 40 + v)).to(DEV)
+        g1 = fgs.project_views_backward(*args(t), geom, c, v, 1, recompute=False, ws=wc)
+        g2 = fgs.project_views_backward(*args(t), geom, c, v, 1, recompute=True)
+        for x, y in zip(g1, g2):
+            assert torch.equal(x, y)
+        assert wc.overflowed() == (False, 0)
+
+
 def test_full_size_voxel_slab_every_voxel(fgs, scan_case):
     """An 8-slice slab (z = 124..131) of the 256^3 volume that one voxelize
     call over the whole grid writes, every voxel against the oracle."""

@@ -1,0 +1,158 @@
+"""The one-call optimiser step (fgs_recon_step) and the fixed key capacity
+(fgs_workspace.key_capacity) against the separate library calls they
+compose.
+
+The step issues the same kernels on the same inputs as the separate calls
+(forward, L1, SSIM, backward, crop voxelization, TV, voxelizer backward,
+Adam), so after a few steps from the same state the parameters, moments and
+gradients must be bit-identical. With a fixed capacity the lists are the
+same as with a read-back pair count; a call that needs more pairs than its
+capacity bins nothing, reports it, and leaves no gradient behind.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def fgs():
+    import paper_2604_01844_amd as m
+    m.lib()
+    return m
+
+
+def _scene(fgs, n=3000, views=8, det=128, vol=64):
+    gs = si.gaussians(n, 21)
+    geom = fgs.Geometry.from_dict(si.geometry(det), si.angles(views), DEV)
+    grid = fgs.Grid.from_dict(si.grid(vol))
+    ph = {k: torch.from_numpy(np.ascontiguousarray(v)).to(DEV) for k, v in si.phantom(10, 105).items()}
+    gt = fgs.phantom_project(ph, geom)
+    return gs, geom, grid, gt
+
+
+def _model(fgs, gs):
+    from paper_2604_01844_amd import recon
+    t = [torch.from_numpy(np.ascontiguousarray(gs[k], dtype=np.float32)).to(DEV)
+         for k in ("mean", "log_scale", "quat", "density")]
+    return recon.GaussianModel(*t)
+
+
+@pytest.mark.parametrize("ssim, tv_weight", [(0.0, 0.0), (0.25, 0.05)])
+def test_native_step_equals_separate_calls(fgs, ssim, tv_weight):
+    from paper_2604_01844_amd import recon
+    gs, geom, grid, gt = _scene(fgs)
+    adam = recon.AdamConfig()
+    views = [3, 1, 6, 0, 5]
+    a, b = _model(fgs, gs), _model(fgs, gs)
+    tv_a = recon.CropTV(grid, tv_weight, 32, DEV) if tv_weight else None
+    tv_b = recon.CropTV(grid, tv_weight, 32, DEV) if tv_weight else None
+    step = recon.ViewStep(a, geom, adam, ssim_weight=ssim, tv=tv_a)
+    rng_a = np.random.Generator(np.random.PCG64(7))
+    for v in views:
+        step(v, gt[v], rng_a)
+    rng_b = np.random.Generator(np.random.PCG64(7))
+    ws_p, ws_l, ws_s = fgs.Workspace(DEV), fgs.Workspace(DEV, 1 << 16), fgs.Workspace(DEV)
+    img = torch.empty((1, geom.det_h, geom.det_w), device=DEV)
+    for v in views:
+        fgs.project_views(*b.params, geom, v, 1, ws=ws_p, out=img)
+        _, g = fgs.l1_loss_grad(img, gt[v:v + 1], ws=ws_l)
+        if ssim:
+            fgs.ssim_loss_grad(img, gt[v:v + 1], scale=ssim, ws=ws_s, grad=g, accumulate=True)
+        fgs.project_views_backward(*b.params, geom, g, v, 1, recompute=False, ws=ws_p, out=b.grads)
+        if tv_b is not None:
+            tv_b.add_grad(b.params, b.grads, rng_b)
+        b.adam(adam)
+    torch.cuda.synchronize()
+    assert step.check_overflow() == 0
+    for name, xa, xb in (("params", a.params, b.params), ("m", a.m, b.m), ("v", a.v, b.v),
+                         ("grads", a.grads, b.grads)):
+        for k, (ta, tb) in enumerate(zip(xa, xb)):
+            assert torch.equal(ta, tb), (name, k, float((ta - tb).abs().max()))
+    assert a.step == b.step == len(views)
+    assert float(step.img.abs().max()) > 0
+
+
+def test_fixed_capacity_lists_equal_read_back_lists(fgs):
+    """Rasterizer and voxelizer forward/backward with key_capacity set (no
+    wait) give the same images, volumes and gradients as with the pair count
+    read back, and the same sorted lists."""
+    gs, geom, grid, gt = _scene(fgs, views=4)
+    t = [torch.from_numpy(np.ascontiguousarray(gs[k], dtype=np.float32)).to(DEV)
+         for k in ("mean", "log_scale", "quat", "density")]
+    ws0 = fgs.Workspace(DEV)
+    img0 = fgs.project_views(*t, geom, ws=ws0)
+    K = ws0.n_pairs
+    d0 = fgs.binning_dump(ws0)
+    c = torch.from_numpy(si.normals((4, 128, 128), 3)).to(DEV)
+    g0 = fgs.project_views_backward(*t, geom, c, recompute=False, ws=ws0)
+    wsc = fgs.Workspace(DEV)
+    wsc.set_capacity(int(K * 1.7) + 123)
+    img1 = fgs.project_views(*t, geom, ws=wsc)
+    d1 = fgs.binning_dump(wsc)
+    g1 = fgs.project_views_backward(*t, geom, c, recompute=False, ws=wsc)
+    assert torch.equal(img0, img1)
+    for x, y in zip(g0, g1):
+        assert torch.equal(x, y)
+    for key in ("sorted_keys", "sorted_vals"):
+        assert torch.equal(d0[key][:K], d1[key][:K]), key
+    assert torch.equal(d0["tile_ranges"], d1["tile_ranges"])
+    assert wsc.overflowed() == (False, 0)
+    wv0, wv1 = fgs.Workspace(DEV), fgs.Workspace(DEV)
+    vol0 = fgs.voxelize(*t, grid, ws=wv0)
+    wv1.set_capacity(wv0.n_pairs + 1)
+    vol1 = fgs.voxelize(*t, grid, ws=wv1)
+    assert torch.equal(vol0, vol1)
+    cv = torch.from_numpy(si.normals((64, 64, 64), 4)).to(DEV)
+    for x, y in zip(fgs.voxelize_backward(*t, grid, cv, recompute=False, ws=wv0),
+                    fgs.voxelize_backward(*t, grid, cv, recompute=False, ws=wv1)):
+        assert torch.equal(x, y)
+    assert wv1.overflowed() == (False, 0)
+
+
+def test_capacity_overflow_bins_nothing_and_reports(fgs):
+    """Capacities below the pairs needed: the forward renders zero, the
+    backward gives zero gradients, the voxelizer likewise, and the overflow
+    words hold the pairs needed; an overflowed first optimiser step leaves
+    the parameters where they were (zero gradient, zero moments)."""
+    from paper_2604_01844_amd import recon
+    gs, geom, grid, gt = _scene(fgs, views=2)
+    t = [torch.from_numpy(np.ascontiguousarray(gs[k], dtype=np.float32)).to(DEV)
+         for k in ("mean", "log_scale", "quat", "density")]
+    ws0 = fgs.Workspace(DEV)
+    fgs.project_views(*t, geom, ws=ws0)
+    K = ws0.n_pairs
+    ws = fgs.Workspace(DEV)
+    ws.set_capacity(K // 3)
+    img = fgs.project_views(*t, geom, ws=ws)
+    assert float(img.abs().max()) == 0.0
+    c = torch.from_numpy(si.normals((2, 128, 128), 5)).to(DEV)
+    for x in fgs.project_views_backward(*t, geom, c, recompute=False, ws=ws):
+        assert float(x.abs().max()) == 0.0
+    assert ws.overflowed() == (True, K)
+    assert ws.overflowed() == (False, 0)          # the read cleared it
+    wv0 = fgs.Workspace(DEV)
+    fgs.voxelize(*t, grid, ws=wv0)
+    wv = fgs.Workspace(DEV)
+    wv.set_capacity(max(1, wv0.n_pairs // 2))
+    assert float(fgs.voxelize(*t, grid, ws=wv).abs().max()) == 0.0
+    assert wv.overflowed() == (True, wv0.n_pairs)
+    model = _model(fgs, gs)
+    before = [p.clone() for p in model.params]
+    step = recon.ViewStep(model, geom, recon.AdamConfig())
+    step.ws_proj.set_capacity(100)
+    step(0, gt[0])
+    torch.cuda.synchronize()
+    for p, q in zip(model.params, before):
+        assert torch.equal(p, q)
+    assert step.check_overflow() == 1
+    assert int(step.ws_proj.s.key_capacity) > K // 2
+    step(1, gt[1])
+    torch.cuda.synchronize()
+    assert step.check_overflow() == 0
+    assert any(not torch.equal(p, q) for p, q in zip(model.params, before))
