@@ -220,8 +220,12 @@ typedef struct {
  * Pipeline: per-(view, Gaussian) splat records; tile counts, exclusive scan
  * and key emission (keys = view * tiles_per_view + tile, row-major inside
  * each record's axis-aligned tile rectangle); stable LSD radix sort; per-tile
- * ranges; per-tile splat. Per pixel the sum runs over its tile's list in
- * ascending Gaussian index (deterministic, bit-reproducible).
+ * ranges; per-tile splat. Per pixel the sum runs over its tile's list (in
+ * ascending Gaussian index after the stable sort) in an order fixed by the
+ * list and the launch shape alone: each 8-lane half of a quadrant group
+ * takes alternate entries, the interior variant takes a batch's interior
+ * pairs first, a few-tile call sums its work units' partials in unit order.
+ * No atomics: deterministic and bit-reproducible for a given call shape.
  * Synchronisation: waits on `stream` once to read the pair count, unless
  * ws->key_capacity > 0 (then not at all).
  * Workspace: if ws->bytes < ws->needed the call returns FGS_E_CAPACITY with

@@ -653,7 +653,7 @@ __device__ __forceinline__ void set_null_record(float4 *s_cw, float2 *s_xy) {
 // kTau: the density-aware support (per-record thresholds, read with each
 // pair); without it the pixel loop compares with the kernel argument.
 template <bool kCount, bool kInterior, int TPB, bool kTau>
-__global__ __launch_bounds__(kWave * TPB) __attribute__((amdgpu_waves_per_eu(8, 8))) void splat_fwd_kernel(const uint2 *__restrict__ rng,
+__global__ __launch_bounds__(kWave * TPB) void splat_fwd_kernel(const uint2 *__restrict__ rng,
                                                            const uint32_t *__restrict__ svals,
                                                            const SplatRec *__restrict__ rec,
                                                            int tiles_x, int tpv, int W, int H,

@@ -421,7 +421,15 @@ __global__ __launch_bounds__(256) void sum_chunks_kernel(const float *__restrict
   const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   float acc = part[i];
-  for (int c = 1; c < chunks; ++c) acc += part[uint64_t(c) * n + i];
+  // eight loads in flight at a time, added in chunk order
+  for (int c = 1; c < chunks; c += 8) {
+    float x[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) x[j] = c + j < chunks ? part[uint64_t(c + j) * n + i] : 0.f;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (c + j < chunks) acc += x[j];
+  }
   out[i] = acc;
 }
 

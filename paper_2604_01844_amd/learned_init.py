@@ -137,6 +137,33 @@ def train(pairs: list, *, epochs: int, lr: float = 1e-3, seed: int = 0, net: Ini
     return net, losses
 
 
+def loss_terms(net: InitMLP, pairs: list) -> dict:
+    """The training loss over `pairs` split into its three terms, each
+    summed over the Gaussians it covers and divided by all of them (so the
+    three add up to the loss): density (rho - rho_t)^2; log-scale
+    |s - s_t|^2 and rotation 1 - (q . q_t)^2 over the live targets
+    (rho_t > 1e-3). Beside the network's: what simple predictors leave, the
+    mean target density, the placement's nearest-neighbour scale and the
+    identity rotation (a uniformly random rotation leaves 0.75 per live
+    Gaussian). A diagnostic, computed with torch from the network's outputs."""
+    grid = ops.Grid.from_dict(si.grid(pairs[0].fdk.shape[-1]))
+    acc = {k: 0.0 for k in ("density", "log_scale", "rotation", "density_mean_target", "log_scale_nn_rule",
+                            "rotation_identity", "live_fraction")}
+    for p in pairs:
+        d, ls, q = net.predict(p.fdk, grid, 1.0, p.mean, norm_max=p.fdk_max, base_log_scale=p.base)
+        t = p.target.double()
+        live = (t[:, 0] > 1e-3).double()
+        n = float(t.shape[0])
+        acc["density"] += float(((d.double() - t[:, 0]) ** 2).sum()) / n
+        acc["log_scale"] += float((live * ((ls.double().T - t[:, 1:4]) ** 2).sum(1)).sum()) / n
+        acc["rotation"] += float((live * (1 - (q.double().T * t[:, 4:8]).sum(1) ** 2)).sum()) / n
+        acc["density_mean_target"] += float(((t[:, 0] - t[:, 0].mean()) ** 2).sum()) / n
+        acc["log_scale_nn_rule"] += float((live * ((p.base.double()[:, None] - t[:, 1:4]) ** 2).sum(1)).sum()) / n
+        acc["rotation_identity"] += float((live * (1 - t[:, 4] ** 2)).sum()) / n
+        acc["live_fraction"] += float(live.sum()) / n
+    return {k: v / len(pairs) for k, v in acc.items()}
+
+
 def fdk_gradient_model(sc: Scanner, vfdk, uniforms, weighting: str = "gradient") -> recon.GaussianModel:
     """Sec. 3.1's initialisation from the FDK volume (weighting="intensity":
     the intensity-sampling baseline)."""
@@ -260,6 +287,8 @@ def main(argv=None):
     ap.add_argument("--held-out", type=int, default=10)
     ap.add_argument("--epochs", type=int, default=150)
     ap.add_argument("--calibration-epochs", type=int, default=100)
+    ap.add_argument("--train-only", action="store_true",
+                    help="make the pairs and train the network; report the loss per epoch and stop")
     a = ap.parse_args(argv)
     log = lambda m: print(f"[learned-init] {m}", file=sys.stderr, flush=True)
     dev = torch.device("cuda:0")
@@ -277,6 +306,13 @@ def main(argv=None):
     net, losses = train(pairs, epochs=a.train_epochs, lr=a.lr, seed=0, device=dev, log=log)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    terms = loss_terms(net, pairs)
+    log(f"loss terms after training: {terms}")
+    if a.train_only:
+        print(json.dumps(dict(pairs=a.pairs, pair_seconds=t_pairs, train_epochs=a.train_epochs,
+                              train_steps=a.train_epochs * a.pairs, train_seconds=t_train, lr=a.lr,
+                              train_loss=losses, loss_terms=terms)), flush=True)
+        return
     target = calibrate_target(sc, epochs=a.calibration_epochs, adam=adam)
     log(f"target PSNR {target} dB")
     rows = compare(sc, net, range(2000, 2000 + a.held_out), target_psnr=target, epochs=a.epochs, adam=adam, log=log)
@@ -304,7 +340,8 @@ def main(argv=None):
     summary = dict(
         pairs=a.pairs, pair_seconds=t_pairs, fit_psnr_mean=float(np.mean([p.fit_psnr for p in pairs])),
         train_epochs=a.train_epochs, train_steps=a.train_epochs * a.pairs, train_seconds=t_train,
-        train_loss_first=losses[0], train_loss_last=losses[-1], target_psnr=target, epochs=a.epochs,
+        train_loss_first=losses[0], train_loss_last=losses[-1], train_loss=losses, loss_terms=terms,
+        target_psnr=target, epochs=a.epochs,
         arms={arm: {k: stat(arm, k) for k in ("s_to_target", "epochs_to_target", "psnr0", "psnr_final")}
               for arm in ("fdk_gradient", "learned")},
         tau_iter=dict(mean=float(np.mean(taus)) if taus else None, reached=len(taus), of=len(rows)),

@@ -19,6 +19,14 @@ def test_learned_init_gains_over_fdk_gradient_init():
     assert min(p.fit_psnr for p in pairs) > 40.0
     net, losses = L.train(pairs, epochs=30, lr=3e-3, seed=0, device=DEV)
     assert np.isfinite(losses).all() and losses[-1] < 0.9 * losses[0]
+    # the three terms add up to the training loss, and the network beats the
+    # simple predictors on density and scale
+    terms = L.loss_terms(net, pairs[:8])
+    total = terms["density"] + terms["log_scale"] + terms["rotation"]
+    print(f"loss terms {terms}")
+    assert 0.7 * losses[-1] < total < 1.2 * losses[-1]
+    assert terms["density"] < terms["density_mean_target"]
+    assert terms["log_scale"] < terms["log_scale_nn_rule"]
     adam = recon.AdamConfig(lr_density=2e-3)
     epochs = 30
     cold = L.run_arm(sc, "fdk_gradient", 2000, epochs=epochs, adam=adam)

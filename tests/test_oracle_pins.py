@@ -1114,3 +1114,42 @@ def test_ssim3d_identity_brute_force_and_finite_differences():
         xm_ = x.copy(); xm_[idx] -= h
         fd = (oracle.ssim3d_loss_grad(xp_, y, scale=0.3)[0] - oracle.ssim3d_loss_grad(xm_, y, scale=0.3)[0]) / (2 * h)
         assert fd == pytest.approx(g[idx], rel=1e-5, abs=1e-12)
+
+
+def test_scaling_workload_gradients_match_central_differences_64_gaussians():
+    """The 64 Gaussians the scaling workload's gradient test samples (of
+    500,000; 2048^2 detector, F ~ 1450 px), two views, support frozen (kappa
+    = 8 puts the cutoff far below the step's effect): the analytic gradient
+    of <c, M> against FP64 central differences with h = 1e-3, Richardson-
+    extrapolated with h / 2. M is a sum over Gaussians, so each Gaussian's
+    differences are taken with it alone in the scene."""
+    full = si.gaussians(500000, 2)
+    sel = np.random.default_rng(16).choice(500000, 64, replace=False)
+    gs = {k: np.ascontiguousarray(v[..., sel], dtype=np.float64) for k, v in full.items()}
+    geom = si.geometry(2048)
+    ang = [0.0, 2.2]
+    c = np.random.default_rng(9).normal(size=(2, 2048, 2048))
+    ana = oracle.project_bwd(gs, geom, ang, c, kappa=8.0)
+    h = 1e-3
+    for key in ("mean", "log_scale", "quat", "density"):
+        num = np.zeros_like(gs[key])
+        for i in range(64):
+            one = subset(gs, [i])
+            # the weighted sum over the pixels the Gaussian reaches (its
+            # footprint plus a margin far wider than a step can move it)
+            nz = np.nonzero(oracle.project(one, geom, ang, kappa=8.0))
+            box = tuple(slice(max(a.min() - 16, 0), a.max() + 17) for a in nz)
+            cb = c.reshape(2, 2048, 2048)[box]
+            for j in range(one[key].shape[0] if one[key].ndim == 2 else 1):
+                def f(step):
+                    g2 = {k: v.copy() for k, v in one.items()}
+                    g2[key].reshape(-1)[j] += step
+                    return float(np.sum(cb * oracle.project(g2, geom, ang, kappa=8.0)[box]))
+                d1 = (f(h) - f(-h)) / (2 * h)
+                d2 = (f(h / 2) - f(-h / 2)) / h
+                if one[key].ndim == 2:
+                    num[j, i] = (4 * d2 - d1) / 3
+                else:
+                    num[i] = (4 * d2 - d1) / 3
+        err = np.linalg.norm(ana[key] - num) / np.linalg.norm(num)
+        assert err < 1e-6, (key, err)
