@@ -238,51 +238,86 @@ constexpr int kSH = kST + 2 * kR;    // staged side (26)
 constexpr int kZC = 64;              // output slices per workgroup
 constexpr int kST2 = kST * kST;      // 256 threads, one column each
 
-// One input slice zi through the x and y filters: the thread's column gets
-// f[c] for the CH channels. PRODUCTS: channels x, y, x^2, y^2, x y formed
-// from a and b; else the CH channels are a[0..CH) with stride n. Slices
-// outside the grid are zero. Contains barriers: every thread calls it.
-template <int CH, bool PRODUCTS>
-__device__ __forceinline__ void slice_filter_2d(const float *__restrict__ a, const float *__restrict__ b, uint64_t n,
-                                                int nx, int ny, int nz, int x0, int y0, int zi, const Window &win,
-                                                float (*sp)[kSH][kSH + 1], float (*sh)[kSH][kST + 1], float f[CH]) {
-  const bool inside = zi >= 0 && zi < nz;  // uniform over the workgroup
-  if (!inside) {
+// The staged neighbourhood of one input slice, held in registers between its
+// global loads and its LDS stores: each thread loads kLoads of the slice's
+// 26 x 26 positions (IN input arrays each), so that the loads of the next
+// slice are in flight while the current one is filtered.
+constexpr int kLoads = (kSH * kSH + kST2 - 1) / kST2;  // 3
+
+template <int IN>
+struct SliceRegs {
+  float v[kLoads][IN];
+};
+
+// Global loads of input slice zi (zero outside the grid). IN = 2: arrays a
+// and b; else the IN channels a[0..IN) with stride n.
+template <int IN>
+__device__ __forceinline__ void slice_load(const float *__restrict__ a, const float *__restrict__ b, uint64_t n,
+                                           int nx, int ny, int nz, int x0, int y0, int zi, SliceRegs<IN> &r) {
+  const bool zin = zi >= 0 && zi < nz;
+  const uint64_t zoff = uint64_t(zin ? zi : 0) * uint64_t(nx) * uint64_t(ny);
 #pragma unroll
-    for (int c = 0; c < CH; ++c) f[c] = 0.f;
-    return;
+  for (int l = 0; l < kLoads; ++l) {
+    const int i = int(threadIdx.x) + l * kST2;
+    const int rr = i / kSH, c = i - rr * kSH;
+    const int gx = x0 - kR + c, gy = y0 - kR + rr;
+    const bool in = zin && i < kSH * kSH && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+    const uint64_t q = zoff + uint64_t(in ? gy : 0) * uint64_t(nx) + uint64_t(in ? gx : 0);
+#pragma unroll
+    for (int ch = 0; ch < IN; ++ch) {
+      const float *src = (IN == 2 && ch == 1) ? b : a + (IN == 2 ? 0 : uint64_t(ch) * n);
+      r.v[l][ch] = in ? src[q] : 0.f;
+    }
   }
+}
+
+// One staged slice through the x and y filters: the thread's column gets
+// f[c] for the CH channels. PRODUCTS: channels x, y, x^2, y^2, x y formed
+// from the two loaded arrays; else the CH loaded channels. Contains
+// barriers: every thread calls it.
+template <int CH, bool PRODUCTS, int IN>
+__device__ __forceinline__ void slice_filter_2d(const SliceRegs<IN> &r, const Window &win,
+                                                float (*sp)[kSH][kSH + 1], float (*sh)[kSH][kST + 1], float f[CH]) {
   __syncthreads();  // the previous slice's reads of sp and sh are done
-  const uint64_t zoff = uint64_t(zi) * uint64_t(nx) * uint64_t(ny);
-  for (int i = threadIdx.x; i < kSH * kSH; i += kST2) {
-    const int r = i / kSH, c = i - r * kSH;
-    const int gx = x0 - kR + c, gy = y0 - kR + r;
-    const bool in = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-    const uint64_t q = zoff + uint64_t(gy) * uint64_t(nx) + uint64_t(gx);
-    if (PRODUCTS) {
-      const float xv = in ? a[q] : 0.f, yv = in ? b[q] : 0.f;
-      sp[0][r][c] = xv;
-      sp[1][r][c] = yv;
-      sp[2][r][c] = xv * xv;
-      sp[3][r][c] = yv * yv;
-      sp[4][r][c] = xv * yv;
-    } else {
 #pragma unroll
-      for (int ch = 0; ch < CH; ++ch) sp[ch][r][c] = in ? a[uint64_t(ch) * n + q] : 0.f;
+  for (int l = 0; l < kLoads; ++l) {
+    const int i = int(threadIdx.x) + l * kST2;
+    if (i < kSH * kSH) {
+      const int rr = i / kSH, c = i - rr * kSH;
+      if (PRODUCTS) {
+        const float xv = r.v[l][0], yv = r.v[l][IN - 1];
+        sp[0][rr][c] = xv;
+        sp[1][rr][c] = yv;
+        sp[2][rr][c] = xv * xv;
+        sp[3][rr][c] = yv * yv;
+        sp[4][rr][c] = xv * yv;
+      } else {
+#pragma unroll
+        for (int ch = 0; ch < CH; ++ch) sp[ch][rr][c] = r.v[l][ch < IN ? ch : 0];
+      }
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < kSH * kST; i += kST2) {
-    const int r = i / kST, c = i - r * kST;
-    float acc[CH];
+  // x filter: thread t < 208 takes row t / 8 and the two neighbouring
+  // outputs c0, c0 + 1 (c0 = 2 (t % 8)), which share 10 of their 11 inputs:
+  // 12 LDS reads per channel for two outputs
+  if (threadIdx.x < kSH * kST / 2) {
+    const int rr = int(threadIdx.x) / (kST / 2), c0 = 2 * (int(threadIdx.x) % (kST / 2));
+    // one channel at a time (the ring already holds 11 CH registers)
+#pragma unroll 1
+    for (int ch = 0; ch < CH; ++ch) {
+      float v[kWin + 1];
 #pragma unroll
-    for (int ch = 0; ch < CH; ++ch) acc[ch] = 0.f;
+      for (int j = 0; j <= kWin; ++j) v[j] = sp[ch][rr][c0 + j];
+      float a0 = 0.f, a1 = 0.f;
 #pragma unroll
-    for (int k = 0; k < kWin; ++k)
-#pragma unroll
-      for (int ch = 0; ch < CH; ++ch) acc[ch] = fmaf(win.w[k], sp[ch][r][c + k], acc[ch]);
-#pragma unroll
-    for (int ch = 0; ch < CH; ++ch) sh[ch][r][c] = acc[ch];
+      for (int k = 0; k < kWin; ++k) {
+        a0 = fmaf(win.w[k], v[k], a0);
+        a1 = fmaf(win.w[k], v[k + 1], a1);
+      }
+      sh[ch][rr][c0] = a0;
+      sh[ch][rr][c0 + 1] = a1;
+    }
   }
   __syncthreads();
   const int tx = threadIdx.x & (kST - 1), ty = threadIdx.x / kST;
@@ -295,22 +330,27 @@ __device__ __forceinline__ void slice_filter_2d(const float *__restrict__ a, con
 }
 
 // Walks input slices z0 - 5 .. z1 + 4 of the workgroup's chunk [z0, z1): ring
-// slot j of the unrolled loop holds input slice base + j. After the slice
-// k (counted from the chunk's first input slice) is filtered, output slice
-// z0 + k - 10 is complete: emit(zo, m) receives its z-filtered channels.
-template <int CH, bool PRODUCTS, typename Emit>
+// slot j of the unrolled loop holds input slice base + j. The loads of slice
+// k + 1 are issued before slice k is filtered. After the slice k (counted
+// from the chunk's first input slice) is filtered, output slice z0 + k - 10
+// is complete: emit(zo, m) receives its z-filtered channels.
+template <int CH, bool PRODUCTS, int IN, typename Emit>
 __device__ __forceinline__ void zring_walk(const float *__restrict__ a, const float *__restrict__ b, uint64_t n,
                                            int nx, int ny, int nz, int x0, int y0, int z0, int z1,
                                            const Window &win, float (*sp)[kSH][kSH + 1],
                                            float (*sh)[kSH][kST + 1], Emit &&emit) {
   float ring[kWin][CH];
   const int n_in = (z1 - z0) + 2 * kR;
+  SliceRegs<IN> cur, nxt;
+  slice_load<IN>(a, b, n, nx, ny, nz, x0, y0, z0 - kR, cur);
   for (int base = 0; base < n_in; base += kWin) {
 #pragma unroll
     for (int j = 0; j < kWin; ++j) {
       const int k = base + j;
       if (k >= n_in) break;  // uniform over the workgroup
-      slice_filter_2d<CH, PRODUCTS>(a, b, n, nx, ny, nz, x0, y0, z0 - kR + k, win, sp, sh, ring[j]);
+      if (k + 1 < n_in) slice_load<IN>(a, b, n, nx, ny, nz, x0, y0, z0 - kR + k + 1, nxt);
+      slice_filter_2d<CH, PRODUCTS, IN>(cur, win, sp, sh, ring[j]);
+      cur = nxt;
       if (k >= 2 * kR) {
         float m[CH];
 #pragma unroll
@@ -340,7 +380,7 @@ __global__ __launch_bounds__(kST2) void ssim3d_stats_kernel(const float *__restr
   const int X = x0 + int(threadIdx.x & (kST - 1)), Y = y0 + int(threadIdx.x / kST);
   const bool mine = X < nx && Y < ny;
   CompSum acc;
-  zring_walk<5, true>(vol, gt, n, nx, ny, nz, x0, y0, z0, z1, win, sp, sh, [&](int zo, const float *m) {
+  zring_walk<5, true, 2>(vol, gt, n, nx, ny, nz, x0, y0, z0, z1, win, sp, sh, [&](int zo, const float *m) {
     if (!mine) return;
     const float mx = m[0], my = m[1];
     const float A = fmaf(2.f * mx, my, c1);
@@ -372,7 +412,7 @@ __global__ __launch_bounds__(kST2) void ssim3d_grad_kernel(const float *__restri
   const int z0 = blockIdx.z * kZC, z1 = min(z0 + kZC, nz);
   const int X = x0 + int(threadIdx.x & (kST - 1)), Y = y0 + int(threadIdx.x / kST);
   const bool mine = X < nx && Y < ny;
-  zring_walk<3, false>(g, nullptr, n, nx, ny, nz, x0, y0, z0, z1, win, sp, sh, [&](int zo, const float *m) {
+  zring_walk<3, false, 3>(g, nullptr, n, nx, ny, nz, x0, y0, z0, z1, win, sp, sh, [&](int zo, const float *m) {
     if (!mine) return;
     const uint64_t q = (uint64_t(zo) * uint64_t(ny) + uint64_t(Y)) * uint64_t(nx) + uint64_t(X);
     const float gq = coef * (m[0] + 2.f * vol[q] * m[1] + gt[q] * m[2]);

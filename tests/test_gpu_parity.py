@@ -474,7 +474,40 @@ def _clear_of_thresholds():
     return si.gaussians(700, 68, log_scale_mean=math.log(0.04)), si.grid(64)
 
 
-_VOX_CASES = dict(mixed_boxes=_mixed_boxes, ragged_crop=_ragged_crop, clear_of_thresholds=_clear_of_thresholds)
+def _crop_64_tiles():
+    # a 32^3 crop of the 256^3 grid (the reconstruction loop's TV crop): 64 tiles
+    return si.gaussians(6000, 69), dict(origin=(-0.1, -0.12, -0.05), spacing=(1 / 256,) * 3, dims=(32, 32, 32))
+
+
+def _ragged_27_tiles():
+    return si.gaussians(4500, 70), dict(origin=(-0.2, 0.05, -0.1), spacing=(0.011, 0.009, 0.013), dims=(20, 24, 17))
+
+
+_VOX_CASES = dict(mixed_boxes=_mixed_boxes, ragged_crop=_ragged_crop, clear_of_thresholds=_clear_of_thresholds,
+                  crop_64_tiles=_crop_64_tiles, ragged_27_tiles=_ragged_27_tiles)
+
+
+@pytest.mark.parametrize("case", ["crop_64_tiles", "ragged_27_tiles"])
+def test_voxelize_small_grids(fgs, case):
+    """Grids of at most 64 tiles (a 6-bit sort, lists split into 16 chunks
+    per tile): volume and gradients against the oracle, and the stored
+    lists' backward equal to the recomputed one."""
+    gs, gr = _VOX_CASES[case]()
+    t = dev(gs)
+    grid = fgs.Grid.from_dict(gr)
+    ws = fgs.Workspace(DEV)
+    vol = fgs.voxelize(*args(t), grid, ws=ws)
+    assert ws.n_pairs > 1000
+    assert rel(vol.cpu().numpy(), oracle.voxelize(gs, gr)) < TOL
+    nz, ny, nx = gr["dims"][2], gr["dims"][1], gr["dims"][0]
+    c = si.normals((nz, ny, nx), 71)
+    ct = torch.from_numpy(c).to(DEV)
+    g = fgs.voxelize_backward(*args(t), grid, ct, recompute=False, ws=ws)
+    ref = oracle.voxelize_bwd(gs, gr, c.astype(np.float64), band=BAND)
+    errs = grads_rel(g, ref)
+    assert max(errs.values()) < TOL, errs
+    for x, y in zip(g, fgs.voxelize_backward(*args(t), grid, ct, recompute=True)):
+        assert torch.equal(x, y)
 
 
 @pytest.mark.parametrize("case", list(_VOX_CASES))

@@ -142,6 +142,18 @@ def test_capacity_overflow_bins_nothing_and_reports(fgs):
     wv.set_capacity(max(1, wv0.n_pairs // 2))
     assert float(fgs.voxelize(*t, grid, ws=wv).abs().max()) == 0.0
     assert wv.overflowed() == (True, wv0.n_pairs)
+    # a 32^3 crop (64 tiles) the same way
+    crop = fgs.Grid.from_dict(dict(origin=(-0.1, -0.1, -0.1), spacing=(1 / 256,) * 3, dims=(32, 32, 32)))
+    wc0, wc = fgs.Workspace(DEV), fgs.Workspace(DEV)
+    assert float(fgs.voxelize(*t, crop, ws=wc0).abs().max()) > 0.0
+    wc.set_capacity(max(1, wc0.n_pairs // 2))
+    assert float(fgs.voxelize(*t, crop, ws=wc).abs().max()) == 0.0
+    cc = torch.from_numpy(si.normals((32, 32, 32), 6)).to(DEV)
+    for x in fgs.voxelize_backward(*t, crop, cc, recompute=False, ws=wc):
+        assert float(x.abs().max()) == 0.0
+    assert wc.overflowed() == (True, wc0.n_pairs)
+    wc.set_capacity(wc0.n_pairs)
+    assert torch.equal(fgs.voxelize(*t, crop, ws=wc), fgs.voxelize(*t, crop, ws=wc0))
     model = _model(fgs, gs)
     before = [p.clone() for p in model.params]
     step = recon.ViewStep(model, geom, recon.AdamConfig())
