@@ -852,7 +852,7 @@ __global__ __launch_bounds__(kWave * TPB) __attribute__((amdgpu_waves_per_eu(7, 
     const uint2 *__restrict__ rng, const uint32_t *__restrict__ svals,
     const SplatRec *__restrict__ rec, int tiles_x, int tpv, int W, int H, uint32_t n_tiles, int n_chunks,
     Units U, float thr, float log2_tau, int no_cull, const float *__restrict__ gimg,
-    float2 *__restrict__ partials) {
+    float4 *__restrict__ partials) {
   // per pixel: g = dL/dI and g cc (cc: column relative to the quadrant
   // centre), so the row loop accumulates with three FMAs per pixel
   __shared__ float4 s_g4_all[TPB][2][kTS * kTS / 4];
@@ -1042,10 +1042,8 @@ __global__ __launch_bounds__(kWave * TPB) __attribute__((amdgpu_waves_per_eu(7, 
       base += P;
     }
     if (uint32_t(lane) < m) {
-      // the pair's six sums: a 24-byte slot
-      partials[3 * uint64_t(slot) + 0] = make_float2(tot[0], tot[1]);
-      partials[3 * uint64_t(slot) + 1] = make_float2(tot[2], tot[3]);
-      partials[3 * uint64_t(slot) + 2] = make_float2(tot[4], tot[5]);
+      partials[2 * uint64_t(slot) + 0] = make_float4(tot[0], tot[1], tot[2], tot[3]);
+      partials[2 * uint64_t(slot) + 1] = make_float4(tot[4], tot[5], 0.f, 0.f);
     }
     wave_lds_sync();
   }
@@ -1138,7 +1136,7 @@ constexpr int kGradUnroll = 4;
 template <int RPB>
 __global__ __launch_bounds__(256) void record_grad_kernel(fgs_gaussians g, GeomDev G,
                                                           const uint32_t *__restrict__ offset,
-                                                          const float2 *__restrict__ partials,
+                                                          const float4 *__restrict__ partials,
                                                           const float *__restrict__ acc6, uint64_t R,
                                                           const uint32_t *__restrict__ kdev,
                                                           float *__restrict__ grad_rec) {
@@ -1163,20 +1161,19 @@ __global__ __launch_bounds__(256) void record_grad_kernel(fgs_gaussians g, GeomD
     {
       // kGradUnroll slots' loads in flight at a time; summed in slot order
       for (uint32_t p = o + li; p < end; p += kGradUnroll * kGradLanes) {
-        float2 a[kGradUnroll], b[kGradUnroll], c[kGradUnroll];
+        float4 a[kGradUnroll];
+        float2 b[kGradUnroll];
 #pragma unroll
         for (int u = 0; u < kGradUnroll; ++u) {
           const uint32_t pp = p + uint32_t(u * kGradLanes);
-          const float2 z = make_float2(0.f, 0.f);
-          a[u] = pp < end ? partials[3 * uint64_t(pp) + 0] : z;
-          b[u] = pp < end ? partials[3 * uint64_t(pp) + 1] : z;
-          c[u] = pp < end ? partials[3 * uint64_t(pp) + 2] : z;
+          a[u] = pp < end ? partials[2 * uint64_t(pp) + 0] : make_float4(0.f, 0.f, 0.f, 0.f);
+          b[u] = pp < end ? *reinterpret_cast<const float2 *>(&partials[2 * uint64_t(pp) + 1]) : make_float2(0.f, 0.f);
         }
 #pragma unroll
         for (int u = 0; u < kGradUnroll; ++u) {
           if (p + uint32_t(u * kGradLanes) >= end) break;
-          acc[0] += a[u].x; acc[1] += a[u].y; acc[2] += b[u].x;
-          acc[3] += b[u].y; acc[4] += c[u].x; acc[5] += c[u].y;
+          acc[0] += a[u].x; acc[1] += a[u].y; acc[2] += a[u].z;
+          acc[3] += a[u].w; acc[4] += b[u].x; acc[5] += b[u].y;
         }
       }
     }
@@ -1688,8 +1685,11 @@ RastLayout rast_layout(uint64_t R, uint64_t T, uint64_t K, bool exact, int tile_
   c.take<uint32_t>(K, &L.keys_alt);
   c.take<uint32_t>(K, &L.vals_alt);
   c.take<uint32_t>(sort_scratch_words(K), &L.sort_scratch);
-  // per pair: the splat backward's six sums (24 bytes), the ray-exact one's 13 (64-byte slots)
-  c.take<float>((exact ? 16 : 6) * K, &L.partials);
+  // per pair: the splat backward's six sums in a 32-byte slot (two aligned
+  // 16-byte stores; 24-byte slots straddle lines and measured 1.5x the
+  // backward's HBM writes, and a slower record gradient), the ray-exact
+  // one's 13 in a 64-byte slot
+  c.take<float>((exact ? 16 : 8) * K, &L.partials);
   L.n_units = units_bound(T, K);
   c.take<uint32_t>(T + 1, &L.ufirst);
   c.take<uint32_t>(L.n_units, &L.utile);
@@ -2104,12 +2104,12 @@ extern "C" int fgs_project_views_bwd(const fgs_gaussians *g, const fgs_geom *geo
         splat_bwd_kernel<TPB, true><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
             at<uint2>(b, L.rng), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
             uint32_t(L.T), chunks, U, thr, log2_tau, (opts->ablate & FGS_ABLATE_QUADRANT_CULL) ? 1 : 0,
-            grad_img, at<float2>(b, L.partials));
+            grad_img, at<float4>(b, L.partials));
       else
         splat_bwd_kernel<TPB, false><<<grid_for(units, TPB), kWave * TPB, 0, s>>>(
             at<uint2>(b, L.rng), sv, at<SplatRec>(b, L.rec), tg.tiles_x, tg.tpv, geom->det_w, geom->det_h,
             uint32_t(L.T), chunks, U, thr, log2_tau, (opts->ablate & FGS_ABLATE_QUADRANT_CULL) ? 1 : 0,
-            grad_img, at<float2>(b, L.partials));
+            grad_img, at<float4>(b, L.partials));
     }, true);
     FGS_LAUNCH_CHECK("splat_bwd_kernel");
   }
@@ -2118,11 +2118,11 @@ extern "C" int fgs_project_views_bwd(const fgs_gaussians *g, const fgs_geom *geo
   // the chip; the sums are the same either way
   if (uint64_t(grid_for(uint64_t(g->n), 256)) * uint64_t(view_count) < 2048) {
     dim3 rgrid(grid_for(uint64_t(g->n), 64), unsigned(view_count));
-    record_grad_kernel<64><<<rgrid, 256, 0, s>>>(*g, G, at<uint32_t>(b, L.offset), at<float2>(b, L.partials), acc6,
+    record_grad_kernel<64><<<rgrid, 256, 0, s>>>(*g, G, at<uint32_t>(b, L.offset), at<float4>(b, L.partials), acc6,
                                                  R, at<uint32_t>(b, L.kdev), at<float>(b, L.grad_rec));
   } else {
     dim3 rgrid(grid_for(uint64_t(g->n), 256), unsigned(view_count));
-    record_grad_kernel<256><<<rgrid, 256, 0, s>>>(*g, G, at<uint32_t>(b, L.offset), at<float2>(b, L.partials), acc6,
+    record_grad_kernel<256><<<rgrid, 256, 0, s>>>(*g, G, at<uint32_t>(b, L.offset), at<float4>(b, L.partials), acc6,
                                                   R, at<uint32_t>(b, L.kdev), at<float>(b, L.grad_rec));
   }
   FGS_LAUNCH_CHECK("record_grad_kernel");
