@@ -278,15 +278,16 @@ def ablation(fgs, params, geom, i_gt, V, D, steps, log):
     print(json.dumps(dict(ablation="rasterizer fwd+L1+bwd, standard scan", steps=steps, rows=rows)), flush=True)
 
 
-def view_steps(fgs, params, moms, lrs, state, geom, grid, i_gt, dev, epochs=1):
+def view_steps(fgs, params, moms, lrs, state, geom, grid, i_gt, dev, epochs=1, graphs=True):
     """The reconstruction loop's optimizer step (Sec. 3.4, the loss of Eq. 5):
     one view forward, L1 and SSIM with their gradients, backward (lists
     reused), a randomly placed 32^3 crop voxelized with the gradient of its
-    TV, Adam, issued as one library call per step (fgs_recon_step, lists at
-    a fixed capacity so no step waits for the GPU). Five untimed steps, then
-    `epochs` timed epochs over all views in a random order; returns seconds
-    per epoch and the number of capacity overflows seen (steps that binned
-    nothing)."""
+    TV, Adam, with lists at a fixed capacity so no step waits for the GPU.
+    graphs=True: each view's step is captured once in a HIP graph during an
+    untimed epoch and replayed (one small kernel and one graph launch per
+    step); graphs=False: one fgs_recon_step call per step. Then `epochs`
+    timed epochs over all views in a random order; returns seconds per epoch
+    and the number of capacity overflows seen (steps that binned nothing)."""
     import torch
     from paper_2604_01844_amd import recon
     V = geom.n_views
@@ -298,10 +299,14 @@ def view_steps(fgs, params, moms, lrs, state, geom, grid, i_gt, dev, epochs=1):
     rng = np.random.Generator(np.random.PCG64(0))
     order = rng.permutation(V)
     tv = recon.CropTV(grid, TV_WEIGHT, 32, dev)
-    stepper = recon.ViewStep(model, geom, adam, ssim_weight=SSIM_WEIGHT, tv=tv)
-    for v in order[:5]:
+    stepper = recon.ViewStep(model, geom, adam, ssim_weight=SSIM_WEIGHT, tv=tv, graphs=graphs)
+    # one untimed epoch (with graphs: each view's step captured once)
+    torch.cuda.synchronize()
+    c0 = time.perf_counter()
+    for v in order:
         stepper(int(v), i_gt[v], rng)
     torch.cuda.synchronize()
+    log(f"first epoch{' (with the graph captures)' if graphs else ''}: {time.perf_counter() - c0:.3f} s")
     w0 = time.perf_counter()
     for _ in range(epochs):
         for v in order:
@@ -538,8 +543,11 @@ def main():
     if args.view_steps_only:
         st = {"step": 0}
         epoch_s, ovf = view_steps(fgs, params, moms, lrs, st, geom, grid, i_gt, dev, epochs=args.view_steps_only)
-        print(json.dumps(dict(s_per_view_step=epoch_s / V, s_per_epoch=epoch_s, epochs=args.view_steps_only,
-                              capacity_overflows=ovf,
+        epoch_d, ovf_d = view_steps(fgs, params, moms, lrs, st, geom, grid, i_gt, dev, epochs=args.view_steps_only,
+                                    graphs=False)
+        print(json.dumps(dict(s_per_view_step=epoch_s / V, s_per_epoch=epoch_s,
+                              s_per_view_step_direct=epoch_d / V, epochs=args.view_steps_only,
+                              capacity_overflows=ovf + ovf_d,
                               workload=wl["label"].format(N=N, V=V, D=D, NV=NV))), flush=True)
         return
     gp = [torch.empty_like(p) for p in params]
@@ -641,9 +649,11 @@ def main():
 
     if args.workload == "scan" and not args.no_view_steps:
         epoch_s, ovf = view_steps(fgs, params, moms, lrs, state, geom, grid, i_gt, dev)
+        epoch_d, ovf_d = view_steps(fgs, params, moms, lrs, state, geom, grid, i_gt, dev, graphs=False)
         out["s_per_view_step"] = epoch_s / V
         out["s_per_epoch"] = epoch_s
-        out["view_step_capacity_overflows"] = ovf
+        out["s_per_view_step_direct"] = epoch_d / V
+        out["view_step_capacity_overflows"] = ovf + ovf_d
     if args.workload == "scan" and not args.no_fit:
         out["fit_step"] = fit_steps(fgs, si, dev)
     if args.workload == "scan" and not args.no_psnr:

@@ -285,6 +285,10 @@ typedef struct {
   float *crop_grad;      /* device crop voxels (with a crop): dTV/dvol */
   float *loss;           /* device [3]: L1 term, SSIM term (with ssim_weight > 0), TV term (with
                             a crop); entries of absent terms are left as they are */
+  float *params;         /* device [8], caller-owned: the step's per-call values (crop origin,
+                            Adam's bias corrections), written by the step's first kernel and
+                            read by the rest; one block per stepper (calls on one stream
+                            may share it, concurrent steps may not) */
 } fgs_step_buffers;
 
 /* Renders view `view` of geom from the n Gaussians in `params` (device SoA,
@@ -309,6 +313,37 @@ int fgs_recon_step(fgs_gaussians_out *params, fgs_gaussian_grads *m, fgs_gaussia
                    const fgs_grid *crop, const fgs_opts *opts, const fgs_step_params *sp,
                    const fgs_step_buffers *buf, fgs_workspace *ws_proj, fgs_workspace *ws_crop,
                    fgs_workspace *ws_loss, void *stream);
+
+/* The same step of one view captured in a HIP graph and replayed, for loops
+ * that take many steps per view (400 epochs of 75 views in Sec. 4): a step
+ * is then one small kernel (the per-call values into buf->params) and one
+ * graph launch instead of about forty kernel launches.
+ *
+ * fgs_step_graph_capture takes fgs_recon_step's arguments (all of them
+ * fixed for the graph's life: buffers, workspaces and their capacities,
+ * view, gt, the loss weights, learning rates and crop dims), records the
+ * step on a private stream without running it, and returns a graph.
+ * Requires key_capacity > 0 in ws_proj and, with a crop, in ws_crop (a
+ * captured step may not wait for the GPU). Errors as fgs_recon_step (on
+ * FGS_E_CAPACITY grow the named workspace and capture again); no graph is
+ * returned on error.
+ * fgs_step_graph_launch runs one step of the captured view on `stream`:
+ * sp->step (Adam's step count) and crop->origin may change from launch to
+ * launch, nothing else is read from sp and crop (crop dims must equal the
+ * captured ones). The result is the one fgs_recon_step gives with the same
+ * values, bit for bit. Asynchronous; launches on one stream run in order.
+ * fgs_step_graph_destroy frees the graph (NULL: no-op); it must not be
+ * running. Graphs hold the device pointers they were captured with: free or
+ * reallocate none of them (or change a workspace's capacity) while a graph
+ * that uses them exists. */
+typedef struct fgs_step_graph fgs_step_graph;
+int fgs_step_graph_capture(fgs_gaussians_out *params, fgs_gaussian_grads *m, fgs_gaussian_grads *v,
+                           fgs_gaussian_grads *grad, int64_t n, const fgs_geom *geom, int32_t view,
+                           const float *gt, const fgs_grid *crop, const fgs_opts *opts,
+                           const fgs_step_params *sp, const fgs_step_buffers *buf, fgs_workspace *ws_proj,
+                           fgs_workspace *ws_crop, fgs_workspace *ws_loss, fgs_step_graph **out);
+int fgs_step_graph_launch(fgs_step_graph *graph, const fgs_step_params *sp, const fgs_grid *crop, void *stream);
+int fgs_step_graph_destroy(fgs_step_graph *graph);
 
 /* ---------------------------------------------------------------------
  * Adaptive density control (Sec. 3.4: the loss gradient prunes, clones or

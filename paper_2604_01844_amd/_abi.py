@@ -93,7 +93,8 @@ class fgs_step_params(ctypes.Structure):
 
 
 class fgs_step_buffers(ctypes.Structure):
-    _fields_ = [("img", _vp), ("grad_img", _vp), ("crop_vol", _vp), ("crop_grad", _vp), ("loss", _vp)]
+    _fields_ = [("img", _vp), ("grad_img", _vp), ("crop_vol", _vp), ("crop_grad", _vp), ("loss", _vp),
+                ("params", _vp)]
 
 
 P = ctypes.POINTER
@@ -106,6 +107,12 @@ SIGNATURES = {
     "fgs_recon_step": [P(fgs_gaussian_grads), P(fgs_gaussian_grads), P(fgs_gaussian_grads), P(fgs_gaussian_grads),
                        ctypes.c_int64, P(fgs_geom), ctypes.c_int32, _vp, P(fgs_grid), P(fgs_opts), P(fgs_step_params),
                        P(fgs_step_buffers), P(fgs_workspace), P(fgs_workspace), P(fgs_workspace), _vp],
+    "fgs_step_graph_capture": [P(fgs_gaussian_grads), P(fgs_gaussian_grads), P(fgs_gaussian_grads),
+                               P(fgs_gaussian_grads), ctypes.c_int64, P(fgs_geom), ctypes.c_int32, _vp, P(fgs_grid),
+                               P(fgs_opts), P(fgs_step_params), P(fgs_step_buffers), P(fgs_workspace),
+                               P(fgs_workspace), P(fgs_workspace), P(_vp)],
+    "fgs_step_graph_launch": [_vp, P(fgs_step_params), P(fgs_grid), _vp],
+    "fgs_step_graph_destroy": [_vp],
     "fgs_project_views_bwd": [P(fgs_gaussians), P(fgs_geom), ctypes.c_int32, ctypes.c_int32,
                               P(fgs_opts), _vp, P(fgs_gaussian_grads), P(fgs_workspace), _vp],
     "fgs_voxelize_fwd": [P(fgs_gaussians), P(fgs_grid), P(fgs_opts), _vp, P(fgs_workspace), _vp],

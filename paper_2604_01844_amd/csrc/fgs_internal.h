@@ -55,6 +55,15 @@ __device__ __forceinline__ int upper_index(const uint32_t *off, int n, uint32_t 
 // out[i] = sum over c = 0..chunks-1 (in order) of part[c * n + i].
 int sum_chunks(const float *part, int chunks, uint64_t n, float *out, hipStream_t s);
 
+// fgs_voxelize_fwd / fgs_voxelize_bwd with the grid origin (3 floats) read on
+// the device from origin_dev when it is not null (grid->origin is then not
+// read by the kernels): a step captured in a graph can move its crop between
+// replays. The tile layout depends on grid->dims and spacing only.
+int vox_forward(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *opts, float *vol, fgs_workspace *ws,
+                hipStream_t s, const float *origin_dev);
+int vox_backward(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *opts, const float *grad_vol,
+                 fgs_gaussian_grads *out, fgs_workspace *ws, hipStream_t s, const float *origin_dev);
+
 // XCD-aware block order. MI355X has 8 XCDs, each with its own L2, and hands
 // out consecutive workgroups round-robin over them. Renumbering so that XCD x
 // takes the x-th contiguous eighth of the blocks keeps neighbouring tiles,

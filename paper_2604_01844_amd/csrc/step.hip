@@ -6,19 +6,39 @@
 //   optionally a crop of the grid voxelized, its TV gradient and the
 //   voxelizer backward added in -> one Adam launch over all 11 N parameters.
 // With key_capacity set in both rasterizer and crop workspaces nothing in the
-// step waits for the GPU, so the host runs ahead and a sequence of steps can
-// be captured in a HIP graph.
+// step waits for the GPU, so the host runs ahead.
+//
+// The values that change from step to step of one view (the crop's origin
+// and Adam's bias corrections) are written by one small kernel into a device
+// block (fgs_step_buffers.params) that the rest of the step reads. The rest
+// can therefore be captured once per view in a HIP graph
+// (fgs_step_graph_capture) and replayed for every later step of that view
+// (fgs_step_graph_launch): the replay runs the same kernels on the same
+// values as the direct call, and saves the per-kernel launch cost.
 #include <cmath>
+#include <new>
 
 #include "fgs_internal.h"
 
 namespace fgs {
 namespace {
 
+// The step's per-call values, in the device block: crop origin (3), Adam's
+// bias corrections 1 - beta1^t and 1 - beta2^t (2), three spare words.
+constexpr int kStepParams = 8;
+struct StepVals {
+  float v[kStepParams];
+};
+
+__global__ void set_step_params_kernel(float *__restrict__ blk, StepVals s) {
+  if (threadIdx.x < kStepParams) blk[threadIdx.x] = s.v[threadIdx.x];
+}
+
 // Adam (with bias correction) on the four parameter groups in one launch:
 // blockIdx.y is the parameter row (3 mean, 3 log-scale, 4 quaternion, 1
 // density rows of n values); density is clamped at zero. The arithmetic is
-// that of fgs_adam_step, so the result is the same bit for bit.
+// that of fgs_adam_step, so the result is the same bit for bit. The bias
+// corrections are read from the step block.
 struct AdamGroups {
   float *p[4];
   const float *g[4];
@@ -27,9 +47,10 @@ struct AdamGroups {
 };
 
 __global__ __launch_bounds__(256) void adam_groups_kernel(AdamGroups A, uint64_t n, float b1, float b2, float eps,
-                                                          float c1, float c2) {
+                                                          const float *__restrict__ blk) {
   const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const float c1 = blk[3], c2 = blk[4];
   const int row = blockIdx.y;
   const int grp = row < 3 ? 0 : (row < 6 ? 1 : (row < 10 ? 2 : 3));
   const int first = grp == 0 ? 0 : (grp == 1 ? 3 : (grp == 2 ? 6 : 10));
@@ -47,70 +68,98 @@ __global__ __launch_bounds__(256) void adam_groups_kernel(AdamGroups A, uint64_t
   p[j] = x;
 }
 
-}  // namespace
-}  // namespace fgs
+struct StepArgs {
+  fgs_gaussians_out *params;
+  fgs_gaussian_grads *m, *v, *grad;
+  int64_t n;
+  const fgs_geom *geom;
+  int32_t view;
+  const float *gt;
+  const fgs_grid *crop;
+  const fgs_opts *opts;
+  const fgs_step_params *sp;
+  const fgs_step_buffers *buf;
+  fgs_workspace *ws_proj, *ws_crop, *ws_loss;
+};
 
-using namespace fgs;
-
-extern "C" int fgs_recon_step(fgs_gaussians_out *params, fgs_gaussian_grads *m, fgs_gaussian_grads *v,
-                              fgs_gaussian_grads *grad, int64_t n, const fgs_geom *geom, int32_t view,
-                              const float *gt, const fgs_grid *crop, const fgs_opts *opts,
-                              const fgs_step_params *sp, const fgs_step_buffers *buf, fgs_workspace *ws_proj,
-                              fgs_workspace *ws_crop, fgs_workspace *ws_loss, void *stream) {
-  if (!params || !m || !v || !grad || !geom || !gt || !opts || !sp || !buf || !ws_proj || !ws_loss)
+int check_args(const StepArgs &a) {
+  if (!a.params || !a.m || !a.v || !a.grad || !a.geom || !a.gt || !a.opts || !a.sp || !a.buf || !a.ws_proj ||
+      !a.ws_loss)
     return fail(FGS_E_INVALID, "null argument");
-  if (!params->mean || !params->log_scale || !params->quat || !params->density || !m->mean || !m->log_scale ||
-      !m->quat || !m->density || !v->mean || !v->log_scale || !v->quat || !v->density || !grad->mean ||
-      !grad->log_scale || !grad->quat || !grad->density)
+  const fgs_gaussians_out *P = a.params;
+  if (!P->mean || !P->log_scale || !P->quat || !P->density || !a.m->mean || !a.m->log_scale || !a.m->quat ||
+      !a.m->density || !a.v->mean || !a.v->log_scale || !a.v->quat || !a.v->density || !a.grad->mean ||
+      !a.grad->log_scale || !a.grad->quat || !a.grad->density)
     return fail(FGS_E_INVALID, "null parameter, moment or gradient array");
-  if (n <= 0 || view < 0 || view >= geom->n_views || sp->step < 1) return fail(FGS_E_INVALID, "n, view or step");
-  if (!buf->img || !buf->grad_img || !buf->loss) return fail(FGS_E_INVALID, "null image buffers");
-  const bool tv = crop && sp->tv_weight > 0.f;
-  if (tv && (!ws_crop || !buf->crop_vol || !buf->crop_grad)) return fail(FGS_E_INVALID, "crop without buffers");
-  if (opts->events) return fail(FGS_E_INVALID, "timing events are not taken by the step");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const fgs_gaussians g{n, params->mean, params->log_scale, params->quat, params->density};
-  const int64_t n_pix = int64_t(geom->det_w) * int64_t(geom->det_h);
+  if (a.n <= 0 || a.view < 0 || a.view >= a.geom->n_views || a.sp->step < 1)
+    return fail(FGS_E_INVALID, "n, view or step");
+  if (!a.buf->img || !a.buf->grad_img || !a.buf->loss || !a.buf->params)
+    return fail(FGS_E_INVALID, "null image, loss or step-parameter buffer");
+  const bool tv = a.crop && a.sp->tv_weight > 0.f;
+  if (tv && (!a.ws_crop || !a.buf->crop_vol || !a.buf->crop_grad))
+    return fail(FGS_E_INVALID, "crop without buffers");
+  if (a.opts->events) return fail(FGS_E_INVALID, "timing events are not taken by the step");
+  return FGS_OK;
+}
 
+StepVals step_vals(const StepArgs &a) {
+  StepVals s{};
+  const bool tv = a.crop && a.sp->tv_weight > 0.f;
+  for (int k = 0; k < 3; ++k) s.v[k] = tv ? a.crop->origin[k] : 0.f;
+  s.v[3] = float(1.0 - std::pow(double(a.sp->beta1), double(a.sp->step)));
+  s.v[4] = float(1.0 - std::pow(double(a.sp->beta2), double(a.sp->step)));
+  return s;
+}
+
+// Everything after the step block is written: reads the crop origin and the
+// bias corrections from buf->params.
+int step_body(const StepArgs &a, hipStream_t s) {
+  void *stream = static_cast<void *>(s);
+  const fgs_step_params *sp = a.sp;
+  const fgs_step_buffers *buf = a.buf;
+  const fgs_gaussians g{a.n, a.params->mean, a.params->log_scale, a.params->quat, a.params->density};
+  const int64_t n_pix = int64_t(a.geom->det_w) * int64_t(a.geom->det_h);
   // 1. forward of the view, 2. the loss of Eq. 5 and its gradient image
-  fgs_opts of = *opts;
+  fgs_opts of = *a.opts;
   of.recompute = 1;
   of.accumulate = 0;
-  int st = fgs_project_views_fwd(&g, geom, view, 1, &of, buf->img, ws_proj, stream);
+  int st = fgs_project_views_fwd(&g, a.geom, a.view, 1, &of, buf->img, a.ws_proj, stream);
   if (st != FGS_OK) return st;
-  st = fgs_l1_loss_grad(buf->img, gt, n_pix, 1, buf->loss, buf->grad_img, ws_loss, stream);
+  st = fgs_l1_loss_grad(buf->img, a.gt, n_pix, 1, buf->loss, buf->grad_img, a.ws_loss, stream);
   if (st != FGS_OK) return st;
   if (sp->ssim_weight > 0.f) {
-    st = fgs_ssim_loss_grad(buf->img, gt, geom->det_w, geom->det_h, 1, sp->ssim_c1, sp->ssim_c2, sp->ssim_weight,
-                            buf->loss + 1, buf->grad_img, 1, ws_loss, stream);
+    st = fgs_ssim_loss_grad(buf->img, a.gt, a.geom->det_w, a.geom->det_h, 1, sp->ssim_c1, sp->ssim_c2,
+                            sp->ssim_weight, buf->loss + 1, buf->grad_img, 1, a.ws_loss, stream);
     if (st != FGS_OK) return st;
   }
   // 3. backward over the forward's lists
   fgs_opts ob = of;
   ob.recompute = 0;
-  st = fgs_project_views_bwd(&g, geom, view, 1, &ob, buf->grad_img, grad, ws_proj, stream);
+  st = fgs_project_views_bwd(&g, a.geom, a.view, 1, &ob, buf->grad_img, a.grad, a.ws_proj, stream);
   if (st != FGS_OK) return st;
-  // 4. the crop's TV prior, its gradient added to the rasterizer's
-  if (tv) {
+  // 4. the crop's TV prior, its gradient added to the rasterizer's; the
+  // crop's origin is the block's
+  if (a.crop && sp->tv_weight > 0.f) {
     fgs_opts ov{};
-    ov.kappa = opts->kappa;
-    ov.near_plane = opts->near_plane;
+    ov.kappa = a.opts->kappa;
+    ov.near_plane = a.opts->near_plane;
     ov.recompute = 1;
-    st = fgs_voxelize_fwd(&g, crop, &ov, buf->crop_vol, ws_crop, stream);
+    st = vox_forward(&g, a.crop, &ov, buf->crop_vol, a.ws_crop, s, buf->params);
     if (st != FGS_OK) return st;
-    st = fgs_tv_loss_grad(buf->crop_vol, crop->dims, sp->tv_weight, buf->loss + 2, buf->crop_grad, ws_loss, stream);
+    st = fgs_tv_loss_grad(buf->crop_vol, a.crop->dims, sp->tv_weight, buf->loss + 2, buf->crop_grad, a.ws_loss,
+                          stream);
     if (st != FGS_OK) return st;
     ov.recompute = 0;
     ov.accumulate = 1;
-    st = fgs_voxelize_bwd(&g, crop, &ov, buf->crop_grad, grad, ws_crop, stream);
+    st = vox_backward(&g, a.crop, &ov, buf->crop_grad, a.grad, a.ws_crop, s, buf->params);
     if (st != FGS_OK) return st;
   }
   // 5. Adam on all parameters, one launch
   AdamGroups A;
-  float *P[4] = {params->mean, params->log_scale, params->quat, params->density};
-  const float *G[4] = {grad->mean, grad->log_scale, grad->quat, grad->density};
-  float *M[4] = {m->mean, m->log_scale, m->quat, m->density};
-  float *V[4] = {v->mean, v->log_scale, v->quat, v->density};
+  float *P[4] = {a.params->mean, a.params->log_scale, a.params->quat, a.params->density};
+  const float *G[4] = {a.grad->mean, a.grad->log_scale, a.grad->quat, a.grad->density};
+  float *M[4] = {a.m->mean, a.m->log_scale, a.m->quat, a.m->density};
+  float *V[4] = {a.v->mean, a.v->log_scale, a.v->quat, a.v->density};
   for (int k = 0; k < 4; ++k) {
     A.p[k] = P[k];
     A.g[k] = G[k];
@@ -118,10 +167,123 @@ extern "C" int fgs_recon_step(fgs_gaussians_out *params, fgs_gaussian_grads *m, 
     A.v[k] = V[k];
     A.lr[k] = sp->lr[k];
   }
-  const float c1 = float(1.0 - std::pow(double(sp->beta1), double(sp->step)));
-  const float c2 = float(1.0 - std::pow(double(sp->beta2), double(sp->step)));
-  adam_groups_kernel<<<dim3(grid_for(uint64_t(n), 256), 11), 256, 0, s>>>(A, uint64_t(n), sp->beta1, sp->beta2,
-                                                                          sp->eps, c1, c2);
+  adam_groups_kernel<<<dim3(grid_for(uint64_t(a.n), 256), 11), 256, 0, s>>>(A, uint64_t(a.n), sp->beta1,
+                                                                            sp->beta2, sp->eps, buf->params);
   FGS_LAUNCH_CHECK("adam_groups_kernel");
+  return FGS_OK;
+}
+
+int set_params(float *blk, const StepVals &v, hipStream_t s) {
+  set_step_params_kernel<<<1, 64, 0, s>>>(blk, v);
+  FGS_LAUNCH_CHECK("set_step_params_kernel");
+  return FGS_OK;
+}
+
+}  // namespace
+}  // namespace fgs
+
+using namespace fgs;
+
+// A captured step of one view: the instantiated graph of step_body and what
+// a launch must match.
+struct fgs_step_graph {
+  hipGraphExec_t exec;
+  float *params;
+  int32_t view;
+  int32_t crop_dims[3];
+  int has_crop;
+};
+
+extern "C" int fgs_recon_step(fgs_gaussians_out *params, fgs_gaussian_grads *m, fgs_gaussian_grads *v,
+                              fgs_gaussian_grads *grad, int64_t n, const fgs_geom *geom, int32_t view,
+                              const float *gt, const fgs_grid *crop, const fgs_opts *opts,
+                              const fgs_step_params *sp, const fgs_step_buffers *buf, fgs_workspace *ws_proj,
+                              fgs_workspace *ws_crop, fgs_workspace *ws_loss, void *stream) {
+  const StepArgs a{params, m, v, grad, n, geom, view, gt, crop, opts, sp, buf, ws_proj, ws_crop, ws_loss};
+  int st = check_args(a);
+  if (st != FGS_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  st = set_params(buf->params, step_vals(a), s);
+  if (st != FGS_OK) return st;
+  return step_body(a, s);
+}
+
+extern "C" int fgs_step_graph_capture(fgs_gaussians_out *params, fgs_gaussian_grads *m, fgs_gaussian_grads *v,
+                                      fgs_gaussian_grads *grad, int64_t n, const fgs_geom *geom, int32_t view,
+                                      const float *gt, const fgs_grid *crop, const fgs_opts *opts,
+                                      const fgs_step_params *sp, const fgs_step_buffers *buf,
+                                      fgs_workspace *ws_proj, fgs_workspace *ws_crop, fgs_workspace *ws_loss,
+                                      fgs_step_graph **out) {
+  if (!out) return fail(FGS_E_INVALID, "null output");
+  *out = nullptr;
+  const StepArgs a{params, m, v, grad, n, geom, view, gt, crop, opts, sp, buf, ws_proj, ws_crop, ws_loss};
+  int st = check_args(a);
+  if (st != FGS_OK) return st;
+  const bool tv = crop && sp->tv_weight > 0.f;
+  // a captured step may not wait for the GPU: both list sets need a fixed capacity
+  if (ws_proj->key_capacity == 0 || (tv && ws_crop->key_capacity == 0))
+    return fail(FGS_E_INVALID, "graph capture needs key_capacity set in the rasterizer and crop workspaces");
+  hipStream_t cs;
+  FGS_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    return hip_fail(e, "hipStreamBeginCapture");
+  }
+  st = step_body(a, cs);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(cs, &graph);
+  (void)hipStreamDestroy(cs);
+  if (st != FGS_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return hip_fail(e, "hipStreamEndCapture");
+  }
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+  fgs_step_graph *gph = new (std::nothrow) fgs_step_graph{};
+  if (!gph) {
+    (void)hipGraphExecDestroy(exec);
+    return fail(FGS_E_INVALID, "out of host memory");
+  }
+  gph->exec = exec;
+  gph->params = buf->params;
+  gph->view = view;
+  gph->has_crop = tv ? 1 : 0;
+  for (int k = 0; k < 3; ++k) gph->crop_dims[k] = tv ? crop->dims[k] : 0;
+  *out = gph;
+  return FGS_OK;
+}
+
+extern "C" int fgs_step_graph_launch(fgs_step_graph *gph, const fgs_step_params *sp, const fgs_grid *crop,
+                                     void *stream) {
+  if (!gph || !sp) return fail(FGS_E_INVALID, "null argument");
+  if (sp->step < 1) return fail(FGS_E_INVALID, "step must be >= 1");
+  if (gph->has_crop) {
+    if (!crop) return fail(FGS_E_INVALID, "the captured step has a crop: pass one");
+    for (int k = 0; k < 3; ++k)
+      if (crop->dims[k] != gph->crop_dims[k]) return fail(FGS_E_INVALID, "crop dims differ from the captured ones");
+  }
+  StepVals vals{};
+  for (int k = 0; k < 3; ++k) vals.v[k] = gph->has_crop ? crop->origin[k] : 0.f;
+  vals.v[3] = float(1.0 - std::pow(double(sp->beta1), double(sp->step)));
+  vals.v[4] = float(1.0 - std::pow(double(sp->beta2), double(sp->step)));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int st = set_params(gph->params, vals, s);
+  if (st != FGS_OK) return st;
+  FGS_HIP(hipGraphLaunch(gph->exec, s));
+  return FGS_OK;
+}
+
+extern "C" int fgs_step_graph_destroy(fgs_step_graph *gph) {
+  if (!gph) return FGS_OK;
+  hipError_t e = hipGraphExecDestroy(gph->exec);
+  delete gph;
+  if (e != hipSuccess) return hip_fail(e, "hipGraphExecDestroy");
   return FGS_OK;
 }

@@ -35,6 +35,7 @@ struct __align__(16) Rect3 {
 
 struct GridDev {
   float origin[3];
+  const float *origin_dev;  // device copy of the origin read instead of origin[] (null: off)
   float h[3];
   int dims[3];
   int nt[3];               // tiles per axis
@@ -53,7 +54,8 @@ struct VoxGauss {
 
 __device__ __forceinline__ void vox_gauss(const GaussParams &P, const GridDev &G, float kap, VoxGauss &V) {
   for (int a = 0; a < 3; ++a) {
-    V.pv[a] = (P.p[a] - G.origin[a]) / G.h[a] - 0.5f;
+    const float o = G.origin_dev ? G.origin_dev[a] : G.origin[a];
+    V.pv[a] = (P.p[a] - o) / G.h[a] - 0.5f;
     float var = 0.f;
     for (int j = 0; j < 3; ++j) {
       V.W[a][j] = G.h[a] * P.R[3 * a + j] / P.s[j];
@@ -698,13 +700,16 @@ GridDev make_grid_dev(const fgs_grid *grid, const fgs_opts *o) {
   }
   G.kappa = o->kappa;
   G.tau = o->density_aabb_tau;
+  G.origin_dev = nullptr;
   return G;
 }
 
 // extra_bytes: room the caller needs after the lists (partial volumes).
 int vox_build(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *o, fgs_workspace *ws,
-              hipStream_t s, VoxLayout *Lout, GridDev *Gout, uint64_t extra_bytes = 0) {
-  const GridDev G = make_grid_dev(grid, o);
+              hipStream_t s, VoxLayout *Lout, GridDev *Gout, uint64_t extra_bytes = 0,
+              const float *origin_dev = nullptr) {
+  GridDev G = make_grid_dev(grid, o);
+  G.origin_dev = origin_dev;
   const uint64_t T = uint64_t(G.nt[0]) * G.nt[1] * G.nt[2];
   if (T >= 0xffffffffull) return fail(FGS_E_UNSUPPORTED, "too many voxel tiles");
   const uint64_t N = uint64_t(g->n);
@@ -822,14 +827,13 @@ int vox_binning_layout(const fgs_workspace *ws, uint64_t off[9], uint64_t counts
 
 }  // namespace fgs
 
-using namespace fgs;
+namespace fgs {
 
-extern "C" int fgs_voxelize_fwd(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *opts,
-                                float *vol, fgs_workspace *ws, void *stream) {
+int vox_forward(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *opts, float *vol, fgs_workspace *ws,
+                hipStream_t s, const float *origin_dev) {
   int st = validate(g, grid, opts, ws);
   if (st != FGS_OK) return st;
   if (!vol) return fail(FGS_E_INVALID, "null volume");
-  hipStream_t s = static_cast<hipStream_t>(stream);
   const uint64_t n_tiles = uint64_t((grid->dims[0] + kVT - 1) / kVT) * uint64_t((grid->dims[1] + kVT - 1) / kVT) *
                            uint64_t((grid->dims[2] + kVT - 1) / kVT);
   const int chunks = chunks_per_tile(n_tiles);
@@ -838,7 +842,7 @@ extern "C" int fgs_voxelize_fwd(const fgs_gaussians *g, const fgs_grid *grid, co
   const uint64_t part_bytes = chunks > 1 ? uint64_t(chunks) * n_vox * sizeof(float) + 256 : 0;
   VoxLayout L;
   GridDev G;
-  st = vox_build(g, grid, opts, ws, s, &L, &G, part_bytes);
+  st = vox_build(g, grid, opts, ws, s, &L, &G, part_bytes, origin_dev);
   if (st != FGS_OK) return st;
   void *b = ws->ptr;
   float *part = chunks > 1 ? at<float>(b, (L.total + 255) / 256 * 256) : vol;
@@ -859,6 +863,15 @@ extern "C" int fgs_voxelize_fwd(const fgs_gaussians *g, const fgs_grid *grid, co
   }
   if (ev) FGS_HIP(hipEventRecord(ev[1], s));
   return FGS_OK;
+}
+
+}  // namespace fgs
+
+using namespace fgs;
+
+extern "C" int fgs_voxelize_fwd(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *opts,
+                                float *vol, fgs_workspace *ws, void *stream) {
+  return vox_forward(g, grid, opts, vol, ws, static_cast<hipStream_t>(stream), nullptr);
 }
 
 extern "C" int fgs_voxelize_support(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *opts,
@@ -888,21 +901,22 @@ extern "C" int fgs_voxelize_support(const fgs_gaussians *g, const fgs_grid *grid
   return FGS_OK;
 }
 
-extern "C" int fgs_voxelize_bwd(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *opts,
-                                const float *grad_vol, fgs_gaussian_grads *out, fgs_workspace *ws,
-                                void *stream) {
+namespace fgs {
+
+int vox_backward(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *opts, const float *grad_vol,
+                 fgs_gaussian_grads *out, fgs_workspace *ws, hipStream_t s, const float *origin_dev) {
   int st = validate(g, grid, opts, ws);
   if (st != FGS_OK) return st;
   if (!grad_vol || !out || !out->mean || !out->log_scale || !out->quat || !out->density)
     return fail(FGS_E_INVALID, "null gradient buffer");
-  hipStream_t s = static_cast<hipStream_t>(stream);
   VoxLayout L;
   GridDev G;
   if (opts->recompute) {
-    st = vox_build(g, grid, opts, ws, s, &L, &G);
+    st = vox_build(g, grid, opts, ws, s, &L, &G, 0, origin_dev);
     if (st != FGS_OK) return st;
   } else {
     G = make_grid_dev(grid, opts);
+    G.origin_dev = origin_dev;
     const uint64_t T = uint64_t(G.nt[0]) * G.nt[1] * G.nt[2];
     if (ws->kind != 2 || ws->n_records != uint64_t(g->n) || ws->n_tiles != T || !ws->ptr)
       return fail(FGS_E_INVALID, "workspace does not hold this call's voxelizer lists");
@@ -931,4 +945,12 @@ extern "C" int fgs_voxelize_bwd(const fgs_gaussians *g, const fgs_grid *grid, co
                                                                 opts->accumulate);
   FGS_LAUNCH_CHECK("vox_grad_kernel");
   return FGS_OK;
+}
+
+}  // namespace fgs
+
+extern "C" int fgs_voxelize_bwd(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *opts,
+                                const float *grad_vol, fgs_gaussian_grads *out, fgs_workspace *ws,
+                                void *stream) {
+  return vox_backward(g, grid, opts, grad_vol, out, ws, static_cast<hipStream_t>(stream), nullptr);
 }

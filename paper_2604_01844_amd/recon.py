@@ -192,17 +192,25 @@ class ViewStep:
     of view 0 at construction, the crop's `crop_keys`. A step whose pairs
     exceed its capacity bins nothing (a zero image, no gradient from it);
     check_overflow() (which waits for the GPU) reports that and raises the
-    capacity for the steps after it."""
+    capacity for the steps after it.
+
+    graphs=True: each view's step is captured once in a HIP graph
+    (fgs_step_graph_capture) and replayed on later steps of that view
+    (fgs_step_graph_launch), with the same result bit for bit and without the
+    per-kernel launch cost. The graphs are dropped and captured again when a
+    workspace is reallocated, a capacity changes or the model's tensors move
+    (adaptive density control), or another gt tensor is passed for a view."""
 
     def __init__(self, model: GaussianModel, geom: ops.Geometry, adam: AdamConfig, *, ssim_weight: float = 0.0,
                  tv: "CropTV | None" = None, kappa: float = ops.KAPPA, near: float = ops.NEAR,
-                 key_margin: float = 2.0, crop_keys: int = 1 << 18):
+                 key_margin: float = 2.0, crop_keys: int = 1 << 18, graphs: bool = True):
         dev = model.params[0].device
         self.model, self.geom, self.adam, self.tv = model, geom, adam, tv
         self.H, self.W = geom.det_h, geom.det_w
         self.img = torch.empty((self.H, self.W), device=dev)
         self.grad_img = torch.empty_like(self.img)
         self.loss = torch.zeros(3, device=dev)
+        self.params_blk = torch.zeros(8, device=dev)
         self.ws_proj = ops.Workspace(dev)
         self.ws_crop = ops.Workspace(dev)
         self.ws_loss = ops.Workspace(dev, 12 * self.H * self.W + (1 << 16))
@@ -215,7 +223,23 @@ class ViewStep:
         self.sp = A.fgs_step_params(float(ssim_weight), ops.SSIM_C1, ops.SSIM_C2,
                                     float(tv.weight) if tv is not None else 0.0, (ctypes.c_float * 4)(*adam.lrs()),
                                     adam.beta1, adam.beta2, adam.eps, 0)
+        self.use_graphs = graphs
+        self._graphs = {}       # view -> (graph handle, gt pointer)
         self._bound = None
+
+    def _drop_graphs(self):
+        L = A.lib()
+        for h, _ in self._graphs.values():
+            A.check(L.fgs_step_graph_destroy(h))
+        self._graphs = {}
+
+    def __del__(self):
+        try:
+            if self._graphs:
+                torch.cuda.synchronize()
+                self._drop_graphs()
+        except Exception:
+            pass
 
     def _bind(self):
         m = self.model
@@ -225,11 +249,53 @@ class ViewStep:
             self._m = A.fgs_gaussian_grads(*(A.ptr(t) for t in m.m))
             self._v = A.fgs_gaussian_grads(*(A.ptr(t) for t in m.v))
             self._g = A.fgs_gaussian_grads(*(A.ptr(t) for t in m.grads))
+            if self._bound is not None and self._graphs:
+                torch.cuda.synchronize()
+                self._drop_graphs()
             self._bound = key
         tv = self.tv
         self._buf = A.fgs_step_buffers(A.ptr(self.img), A.ptr(self.grad_img),
                                        A.ptr(tv.vol) if tv is not None else None,
-                                       A.ptr(tv.grad) if tv is not None else None, A.ptr(self.loss))
+                                       A.ptr(tv.grad) if tv is not None else None, A.ptr(self.loss),
+                                       A.ptr(self.params_blk))
+
+    def _args(self, view, gt_view, crop):
+        m = self.model
+        return (ctypes.byref(self._p), ctypes.byref(self._m), ctypes.byref(self._v), ctypes.byref(self._g), m.n,
+                ctypes.byref(self.gm), int(view), A.ptr(gt_view), ctypes.byref(crop) if crop is not None else None,
+                ctypes.byref(self.opts), ctypes.byref(self.sp), ctypes.byref(self._buf),
+                ctypes.byref(self.ws_proj.s), ctypes.byref(self.ws_crop.s), ctypes.byref(self.ws_loss.s))
+
+    def _grow(self) -> bool:
+        """Grows the workspaces a call asked more of; True if any moved."""
+        moved = False
+        for w in (self.ws_proj, self.ws_loss, self.ws_crop):
+            if w.buf is None or int(w.s.needed) > w.buf.numel():
+                w.ensure(max(int(w.s.needed), 1 << 20))
+                moved = True
+        if moved and self._graphs:
+            torch.cuda.synchronize()
+            self._drop_graphs()
+        return moved
+
+    def _graph(self, view: int, gt_view, crop):
+        hit = self._graphs.get(view)
+        if hit is not None and hit[1] == gt_view.data_ptr():
+            return hit[0]
+        if hit is not None:
+            torch.cuda.synchronize()
+            A.check(A.lib().fgs_step_graph_destroy(hit[0]))
+            del self._graphs[view]
+        L = A.lib()
+        for _ in range(6):
+            h = ctypes.c_void_p()
+            code = L.fgs_step_graph_capture(*self._args(view, gt_view, crop), ctypes.byref(h))
+            if code != A.FGS_E_CAPACITY:
+                A.check(code)
+                self._graphs[view] = (h, gt_view.data_ptr())
+                return h
+            self._grow()
+        raise A.FgsError(A.FGS_E_CAPACITY, "step workspaces did not converge")
 
     def __call__(self, view: int, gt_view, rng=None):
         """Step on view `view` against gt_view[H][W] (device, contiguous); rng
@@ -240,31 +306,34 @@ class ViewStep:
         self.sp.step = m.step + 1
         L = A.lib()
         stream = A.stream_ptr(self.img.device)
+        if self.use_graphs:
+            h = self._graph(view, gt_view, crop)
+            A.check(L.fgs_step_graph_launch(h, ctypes.byref(self.sp),
+                                            ctypes.byref(crop) if crop is not None else None, stream))
+            m.step += 1
+            return self.loss
         for _ in range(6):
-            code = L.fgs_recon_step(ctypes.byref(self._p), ctypes.byref(self._m), ctypes.byref(self._v),
-                                    ctypes.byref(self._g), m.n, ctypes.byref(self.gm), int(view), A.ptr(gt_view),
-                                    ctypes.byref(crop) if crop is not None else None, ctypes.byref(self.opts),
-                                    ctypes.byref(self.sp), ctypes.byref(self._buf), ctypes.byref(self.ws_proj.s),
-                                    ctypes.byref(self.ws_crop.s), ctypes.byref(self.ws_loss.s), stream)
+            code = L.fgs_recon_step(*self._args(view, gt_view, crop), stream)
             if code != A.FGS_E_CAPACITY:
                 A.check(code)
                 m.step += 1
                 return self.loss
-            for w in (self.ws_proj, self.ws_loss, self.ws_crop):
-                if w.buf is None or int(w.s.needed) > w.buf.numel():
-                    w.ensure(max(int(w.s.needed), 1 << 20))
+            self._grow()
         raise A.FgsError(A.FGS_E_CAPACITY, "step workspaces did not converge")
 
     def check_overflow(self) -> int:
         """Waits for the GPU. Number of workspaces whose capacity some step
         since the last check exceeded (those steps binned nothing); each such
-        capacity is raised to 1.5 times the largest need seen."""
+        capacity is raised to 1.5 times the largest need seen (which drops
+        the captured graphs)."""
         hit = 0
         for w in (self.ws_proj, self.ws_crop):
             f, need = w.overflowed()
             if f:
                 hit += 1
                 w.set_capacity(int(1.5 * need) + 4096)
+        if hit and self._graphs:
+            self._drop_graphs()
         return hit
 
 
@@ -272,12 +341,14 @@ def reconstruct(model: GaussianModel, proj_gt, geom: ops.Geometry, *, epochs: in
                 vol_gt=None, eval_grid: ops.Grid | None = None, eval_every: int = 1,
                 target_psnr: float | None = None, seed: int = 0, clock_start: float | None = None,
                 t_offset: float = 0.0, eval_at_start: bool = False, tv: CropTV | None = None,
-                ssim_weight: float = 0.0, adc: ADCConfig | None = None) -> History:
+                ssim_weight: float = 0.0, adc: ADCConfig | None = None, graphs: bool = True) -> History:
     """Optimise `model` against projections proj_gt[V][H][W] (GPU), one view
     per step. If vol_gt/eval_grid are given, PSNR is evaluated every
     `eval_every` epochs (and before the first step with eval_at_start),
     outside the clock, and the loop stops at target_psnr. The clock starts
-    at t_offset seconds (time already spent, e.g. on the initialisation)."""
+    at t_offset seconds (time already spent, e.g. on the initialisation).
+    graphs: each view's step is captured in a HIP graph on its first step and
+    replayed after (ViewStep); the captures are inside the clock."""
     dev = proj_gt.device
     V = proj_gt.shape[0]
     ws_p, ws_l, ws_v = ops.Workspace(dev), ops.Workspace(dev, 1 << 16), ops.Workspace(dev)
@@ -300,7 +371,7 @@ def reconstruct(model: GaussianModel, proj_gt, geom: ops.Geometry, *, epochs: in
         torch.cuda.synchronize()
     dens = _Densifier(model, adc, dev) if adc is not None else None
     # without density control a step is one library call that never waits
-    stepper = ViewStep(model, geom, adam, ssim_weight=ssim_weight, tv=tv) if dens is None else None
+    stepper = ViewStep(model, geom, adam, ssim_weight=ssim_weight, tv=tv, graphs=graphs) if dens is None else None
     if stepper is not None and clock_start is None:
         torch.cuda.synchronize()
     t0 = time.perf_counter() if clock_start is None else clock_start

@@ -43,8 +43,8 @@ def _model(fgs, gs):
     return recon.GaussianModel(*t)
 
 
-@pytest.mark.parametrize("ssim, tv_weight", [(0.0, 0.0), (0.25, 0.05)])
-def test_native_step_equals_separate_calls(fgs, ssim, tv_weight):
+@pytest.mark.parametrize("ssim, tv_weight, graphs", [(0.0, 0.0, False), (0.25, 0.05, False), (0.25, 0.05, True)])
+def test_native_step_equals_separate_calls(fgs, ssim, tv_weight, graphs):
     from paper_2604_01844_amd import recon
     gs, geom, grid, gt = _scene(fgs)
     adam = recon.AdamConfig()
@@ -52,7 +52,7 @@ def test_native_step_equals_separate_calls(fgs, ssim, tv_weight):
     a, b = _model(fgs, gs), _model(fgs, gs)
     tv_a = recon.CropTV(grid, tv_weight, 32, DEV) if tv_weight else None
     tv_b = recon.CropTV(grid, tv_weight, 32, DEV) if tv_weight else None
-    step = recon.ViewStep(a, geom, adam, ssim_weight=ssim, tv=tv_a)
+    step = recon.ViewStep(a, geom, adam, ssim_weight=ssim, tv=tv_a, graphs=graphs)
     rng_a = np.random.Generator(np.random.PCG64(7))
     for v in views:
         step(v, gt[v], rng_a)
@@ -168,3 +168,49 @@ def test_capacity_overflow_bins_nothing_and_reports(fgs):
     torch.cuda.synchronize()
     assert step.check_overflow() == 0
     assert any(not torch.equal(p, q) for p, q in zip(model.params, before))
+
+
+def test_graph_replays_equal_direct_steps(fgs):
+    """Steps replayed from per-view HIP graphs (fgs_step_graph_launch) give
+    the parameters, moments and gradients of the same steps issued directly
+    (fgs_recon_step), bit for bit, after every step: views replayed several
+    times, the crop moved and Adam's step advanced between replays, with
+    other eager GPU work and synchronisations in between."""
+    from paper_2604_01844_amd import recon
+    gs, geom, grid, gt = _scene(fgs)
+    adam = recon.AdamConfig()
+    a, b = _model(fgs, gs), _model(fgs, gs)
+    sa = recon.ViewStep(a, geom, adam, ssim_weight=0.25, tv=recon.CropTV(grid, 0.05, 32, DEV), graphs=True)
+    sb = recon.ViewStep(b, geom, adam, ssim_weight=0.25, tv=recon.CropTV(grid, 0.05, 32, DEV), graphs=False)
+    ra = np.random.Generator(np.random.PCG64(11))
+    rb = np.random.Generator(np.random.PCG64(11))
+    other = torch.zeros(4096, device=DEV)
+    for k, v in enumerate([2, 5, 2, 2, 7, 5, 2, 7]):
+        sa(v, gt[v], ra)
+        other.add_(float(k))                     # eager work between replays
+        sb(v, gt[v], rb)
+        torch.cuda.synchronize()
+        for name, xa, xb in (("params", a.params, b.params), ("m", a.m, b.m), ("v", a.v, b.v),
+                             ("grads", a.grads, b.grads)):
+            for j, (ta, tb) in enumerate(zip(xa, xb)):
+                assert torch.equal(ta, tb), (k, v, name, j, float((ta - tb).abs().max()))
+        assert torch.equal(sa.loss, sb.loss), k
+    assert sorted(sa._graphs) == [2, 5, 7]
+    assert float(other[0]) == sum(range(8))
+    assert sa.check_overflow() == 0 and sb.check_overflow() == 0
+
+
+def test_graph_capture_needs_fixed_capacity(fgs):
+    """A captured step may not wait for the GPU: capture without key_capacity
+    in the rasterizer workspace is refused before anything is recorded."""
+    import ctypes
+    from paper_2604_01844_amd import recon, _abi as A
+    gs, geom, grid, gt = _scene(fgs, views=2)
+    st = recon.ViewStep(_model(fgs, gs), geom, recon.AdamConfig(), graphs=True)
+    st._bind()
+    st.ws_proj.s.key_capacity = 0
+    st.sp.step = 1
+    h = ctypes.c_void_p()
+    code = A.lib().fgs_step_graph_capture(*st._args(0, gt[0], None), ctypes.byref(h))
+    assert code == A.FGS_E_INVALID and not h.value
+    assert "key_capacity" in A.lib().fgs_last_error().decode()
