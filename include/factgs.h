@@ -474,7 +474,7 @@ int fgs_psnr(const float *vol, const float *ref, int64_t n, float peak, float *o
  * constants c1, c2 > 0 (0.01^2 and 0.03^2 for unit dynamic range). If grad
  * != NULL it receives scale * d(1 - mean SSIM)/d img, added to its contents
  * when accumulate != 0 (e.g. onto the L1 gradient), else overwriting them.
- * Workspace: 12 bytes per pixel (with grad) plus 4 per 32x32 tile. */
+ * Workspace: 12 bytes per pixel (with grad) plus 4 per 16x16 tile. */
 int fgs_ssim_loss_grad(const float *img, const float *gt, int32_t W, int32_t H, int32_t n_views, float c1,
                        float c2, float scale, float *loss, float *grad, int32_t accumulate, fgs_workspace *ws,
                        void *stream);

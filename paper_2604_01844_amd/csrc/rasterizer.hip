@@ -1133,13 +1133,32 @@ __global__ __launch_bounds__(256) void fill_zero_kernel(float *__restrict__ p, u
 constexpr int kGradLanes = 8;
 constexpr int kGradUnroll = 4;
 
-template <int RPB>
+// A record's 11 gradient components: to grad_rec[c][r] (summed over the
+// views afterwards), or, for a one-view call (kDirect), straight into the
+// output arrays (added to them with accumulate), as view_sum_kernel would.
+struct GradSink {
+  float *__restrict__ grad_rec;
+  uint64_t R;
+  fgs_gaussian_grads out;
+  int accumulate;
+  template <bool kDirect>
+  __device__ __forceinline__ void put(int c, uint64_t r, int64_t i, int64_t n, float val) const {
+    if constexpr (!kDirect) {
+      grad_rec[uint64_t(c) * R + r] = val;
+    } else {
+      float *d = c < 3 ? out.mean + c * n : (c < 6 ? out.log_scale + (c - 3) * n
+                                                   : (c < 10 ? out.quat + (c - 6) * n : out.density));
+      d[i] = accumulate ? d[i] + val : val;
+    }
+  }
+};
+
+template <int RPB, bool kDirect>
 __global__ __launch_bounds__(256) void record_grad_kernel(fgs_gaussians g, GeomDev G,
                                                           const uint32_t *__restrict__ offset,
                                                           const float4 *__restrict__ partials,
                                                           const float *__restrict__ acc6, uint64_t R,
-                                                          const uint32_t *__restrict__ kdev,
-                                                          float *__restrict__ grad_rec) {
+                                                          const uint32_t *__restrict__ kdev, GradSink sink) {
   __shared__ float s_sum[RPB][7];
   __shared__ uint32_t s_off[RPB + 1];
   // kdev[1]: the lists overflowed their capacity and hold nothing
@@ -1192,7 +1211,7 @@ __global__ __launch_bounds__(256) void record_grad_kernel(fgs_gaussians g, GeomD
   float out[11];
   if (none || s_off[t] == s_off[t + 1]) {
 #pragma unroll
-    for (int c = 0; c < 11; ++c) grad_rec[uint64_t(c) * R + r] = 0.f;
+    for (int c = 0; c < 11; ++c) sink.put<kDirect>(c, r, i, g.n, 0.f);
     return;
   }
   float sums[6];
@@ -1206,14 +1225,14 @@ __global__ __launch_bounds__(256) void record_grad_kernel(fgs_gaussians g, GeomD
   splat_forward(P, F, G, S);
   if (!S.ok) {
 #pragma unroll
-    for (int c = 0; c < 11; ++c) grad_rec[uint64_t(c) * R + r] = 0.f;
+    for (int c = 0; c < 11; ++c) sink.put<kDirect>(c, r, i, g.n, 0.f);
     return;
   }
   // moments are relative to the pixel coordinate frame: the sums use
   // (pixel - centre); the kernel's pre-scaled conic is undone here
   splat_backward(P, F, G, S, sums, out);
 #pragma unroll
-  for (int c = 0; c < 11; ++c) grad_rec[uint64_t(c) * R + r] = out[c];
+  for (int c = 0; c < 11; ++c) sink.put<kDirect>(c, r, i, g.n, out[c]);
 }
 
 __global__ __launch_bounds__(256) void view_sum_kernel(int64_t n, int views,
@@ -2116,19 +2135,29 @@ extern "C" int fgs_project_views_bwd(const fgs_gaussians *g, const fgs_geom *geo
   if (ev) FGS_HIP(hipEventRecord(ev[1], s));
   // few records (one view): 64 records per block, so that the blocks cover
   // the chip; the sums are the same either way
+  // one view: the records' gradients go straight to the output (the sum
+  // over one view is the identity), without view_sum_kernel
+  const GradSink sink{at<float>(b, L.grad_rec), R, *out, opts->accumulate};
+  const bool direct = view_count == 1;
+  auto launch = [&](auto rpb, auto dir) {
+    constexpr int RPB = decltype(rpb)::value;
+    dim3 rgrid(grid_for(uint64_t(g->n), RPB), unsigned(view_count));
+    record_grad_kernel<RPB, decltype(dir)::value><<<rgrid, 256, 0, s>>>(
+        *g, G, at<uint32_t>(b, L.offset), at<float4>(b, L.partials), acc6, R, at<uint32_t>(b, L.kdev), sink);
+  };
+  using I64 = std::integral_constant<int, 64>;
+  using I256 = std::integral_constant<int, 256>;
   if (uint64_t(grid_for(uint64_t(g->n), 256)) * uint64_t(view_count) < 2048) {
-    dim3 rgrid(grid_for(uint64_t(g->n), 64), unsigned(view_count));
-    record_grad_kernel<64><<<rgrid, 256, 0, s>>>(*g, G, at<uint32_t>(b, L.offset), at<float4>(b, L.partials), acc6,
-                                                 R, at<uint32_t>(b, L.kdev), at<float>(b, L.grad_rec));
+    if (direct) launch(I64(), std::true_type()); else launch(I64(), std::false_type());
   } else {
-    dim3 rgrid(grid_for(uint64_t(g->n), 256), unsigned(view_count));
-    record_grad_kernel<256><<<rgrid, 256, 0, s>>>(*g, G, at<uint32_t>(b, L.offset), at<float4>(b, L.partials), acc6,
-                                                  R, at<uint32_t>(b, L.kdev), at<float>(b, L.grad_rec));
+    if (direct) launch(I256(), std::true_type()); else launch(I256(), std::false_type());
   }
   FGS_LAUNCH_CHECK("record_grad_kernel");
-  view_sum_kernel<<<grid_for(uint64_t(g->n), 256), 256, 0, s>>>(g->n, view_count, at<float>(b, L.grad_rec),
-                                                                *out, opts->accumulate);
-  FGS_LAUNCH_CHECK("view_sum_kernel");
+  if (view_count > 1) {
+    view_sum_kernel<<<grid_for(uint64_t(g->n), 256), 256, 0, s>>>(g->n, view_count, at<float>(b, L.grad_rec),
+                                                                  *out, opts->accumulate);
+    FGS_LAUNCH_CHECK("view_sum_kernel");
+  }
   return FGS_OK;
 }
 

@@ -11,7 +11,7 @@
 // where G1, G2, G3 are dSSIM/d(mx, E[x^2], E[xy]) (the window is symmetric,
 // so the adjoint of the windowed sum is the windowed sum).
 //
-// Two kernels over 32x32 output tiles with a 5-pixel halo staged in LDS,
+// Two kernels over 16x16 output tiles with a 5-pixel halo staged in LDS,
 // each a separable (horizontal then vertical) 11-tap pass:
 //   stats kernel: the five statistics, 1 - SSIM (block partial sums, no atomics)
 //                 and the three G maps;
@@ -27,8 +27,8 @@ namespace {
 
 constexpr int kR = 5;              // window radius
 constexpr int kWin = 2 * kR + 1;   // 11 taps
-constexpr int kT = 32;             // output tile side
-constexpr int kH = kT + 2 * kR;    // staged side (42)
+constexpr int kT = 16;             // output tile side (16: 1,024 workgroups per 512^2 view)
+constexpr int kH = kT + 2 * kR;    // staged side (26)
 constexpr int kThreads = 256;
 
 struct Window {
