@@ -22,8 +22,11 @@ TOL = 1e-4
 # Gradients: pairs within BAND of the support boundary d^2 = 9 have no unique
 # answer (the hard cutoff is discontinuous there; FP32 and FP64 may decide
 # differently). The oracle leaves them out and reports their absolute
-# contribution; the GPU must match the rest to TOL.
-BAND = 1e-3
+# contribution; the GPU must match the rest to TOL. 1e-5 is about ten FP32
+# ulps of 9: the kernels' d^2 carries the rounding of the projection and the
+# conic, a few ulps (every gradient test also passes at this band on the GPU,
+# and was run with 1e-3 and 1e-4 before).
+BAND = 1e-5
 DEV = "cuda"
 
 

@@ -12,7 +12,7 @@ import synth_inputs as si
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-4
-BAND = 1e-3
+BAND = 1e-5
 DEV = "cuda"
 
 
