@@ -200,6 +200,12 @@ typedef struct {
                             the caller zeroes; a call that overflows sets overflow[0] = 1 and
                             raises overflow[1] to the pairs it needed (at most 2^32 - 1). Never
                             cleared by the library. */
+  int32_t record_bits;   /* out: rasterizer: 0 = key/value lists (key = view << tile_bits | tile,
+                            value = record); > 0 = one-word lists, each word tile << record_bits
+                            | record (used when the tile field and the record index fit 32 bits:
+                            half the sort's bytes), the view being record / n_gauss */
+  uint64_t n_gauss;      /* out: rasterizer: Gaussians of the last binning (records = views x
+                            n_gauss) */
 } fgs_workspace;
 
 /* Additive ellipsoid phantom: sum_e amp_e * [x inside ellipsoid e]. Used to

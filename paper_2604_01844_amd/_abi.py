@@ -59,7 +59,8 @@ class fgs_workspace(ctypes.Structure):
     _fields_ = [("ptr", _vp), ("bytes", ctypes.c_uint64), ("needed", ctypes.c_uint64),
                 ("n_pairs", ctypes.c_uint64), ("n_records", ctypes.c_uint64),
                 ("n_tiles", ctypes.c_uint64), ("kind", ctypes.c_int32), ("tile_bits", ctypes.c_int32),
-                ("key_capacity", ctypes.c_uint64), ("overflow", _vp)]
+                ("key_capacity", ctypes.c_uint64), ("overflow", _vp), ("record_bits", ctypes.c_int32),
+                ("n_gauss", ctypes.c_uint64)]
 
 
 class fgs_adc_params(ctypes.Structure):

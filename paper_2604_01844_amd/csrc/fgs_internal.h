@@ -144,16 +144,18 @@ inline int sort_passes(uint64_t n, int bits, int max_bits = kSortMaxBits) {
   return (n > 1 && bits > 0) ? (bits + max_bits - 1) / max_bits : 0;
 }
 
-// Stable LSD radix sort of (key, value) uint32 pairs on the low `bits` bits
-// of the key. Input in keys/vals; the sorted result ends in the buffers
-// returned through out_keys/out_vals (either the inputs or the alternates).
-// n_dev (may be null): a device word holding the number of pairs, at most
-// n; the launches are sized for n and sort only that many (no host wait).
+// Stable LSD radix sort of (key, value) uint32 pairs on bits [bit0, bit0 +
+// bits) of the key. Input in keys/vals; the sorted result ends in the
+// buffers returned through out_keys/out_vals (either the inputs or the
+// alternates). vals == nullptr: keys only (one word per item: half the
+// bytes per pass; out_vals is then null). n_dev (may be null): a device
+// word holding the number of pairs, at most n; the launches are sized for n
+// and sort only that many (no host wait).
 uint64_t sort_scratch_words(uint64_t n);
 int radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
                      uint64_t n, int bits, uint32_t *scratch, uint32_t **out_keys,
                      uint32_t **out_vals, hipStream_t s, int max_bits = kSortMaxBits,
-                     const uint32_t *n_dev = nullptr);
+                     const uint32_t *n_dev = nullptr, int bit0 = 0);
 
 // Pair count of a binning from its kTotalSlots 64-bit partial totals:
 // count[0] = the total if it is at most cap, else 0 (nothing is binned);

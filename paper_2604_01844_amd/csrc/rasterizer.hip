@@ -249,8 +249,11 @@ __global__ __launch_bounds__(256) void record_kernel(fgs_gaussians g, GeomDev G,
     atomicAdd(total64 + ((blockIdx.x * 4 + (threadIdx.x >> 6) + blockIdx.y * 7) & (kTotalSlots - 1)), w);
 }
 
+// record_bits > 0: one-word lists, keys[q] = tile << record_bits | record
+// (the view is the record's, r / n) and no values; else keys[q] = view <<
+// tile_bits | tile and vals[q] = the record.
 __global__ __launch_bounds__(kEmitBlock) void emit_kernel(uint64_t R, int64_t n, int tiles_x, int tile_bits,
-                                                          const ushort4 *__restrict__ rect,
+                                                          int record_bits, const ushort4 *__restrict__ rect,
                                                           const uint32_t *__restrict__ offset,
                                                           uint32_t *__restrict__ keys,
                                                           uint32_t *__restrict__ vals, float *__restrict__ base_field,
@@ -295,9 +298,13 @@ __global__ __launch_bounds__(kEmitBlock) void emit_kernel(uint64_t R, int64_t n,
     const uint32_t j = q - s_off[i];
     const uint32_t dy = j / wdt;
     const uint64_t r = r0 + i;
-    const uint32_t base = uint32_t(r / uint64_t(n)) << tile_bits;
-    keys[q] = base | ((uint32_t(rc.y) + dy) * uint32_t(tiles_x) + uint32_t(rc.x) + (j - dy * wdt));
-    vals[q] = uint32_t(r);
+    const uint32_t tile = (uint32_t(rc.y) + dy) * uint32_t(tiles_x) + uint32_t(rc.x) + (j - dy * wdt);
+    if (record_bits) {
+      keys[q] = (tile << record_bits) | uint32_t(r);
+    } else {
+      keys[q] = (uint32_t(r / uint64_t(n)) << tile_bits) | tile;
+      vals[q] = uint32_t(r);
+    }
   }
 }
 
@@ -314,9 +321,16 @@ __global__ __launch_bounds__(256) void zero_ranges_kernel(uint2 *__restrict__ rn
 // lanes 0 and 63); only the keys just outside its span are loaded twice.
 constexpr int kRangeItems = 16;
 
+// One-word lists (record_bits > 0): a word's key is (record / n) <<
+// tile_bits | (word >> record_bits).
+__device__ __forceinline__ uint32_t list_key(uint32_t w, int record_bits, int tile_bits, uint32_t n) {
+  return record_bits ? (((w & ((1u << record_bits) - 1u)) / n) << tile_bits) | (w >> record_bits) : w;
+}
+
 __global__ __launch_bounds__(256) void ranges_kernel(const uint32_t *__restrict__ skeys, uint64_t K_cap,
                                                      const uint32_t *__restrict__ kdev, int tile_bits,
-                                                     uint32_t tpv, uint2 *__restrict__ rng) {
+                                                     uint32_t tpv, int record_bits, uint32_t n,
+                                                     uint2 *__restrict__ rng) {
   const uint64_t K = min(K_cap, uint64_t(kdev[0]));
   const int lane = threadIdx.x & (kWave - 1);
   const uint64_t base = ((uint64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6) * uint64_t(kWave * kRangeItems);
@@ -328,8 +342,14 @@ __global__ __launch_bounds__(256) void ranges_kernel(const uint32_t *__restrict_
     key[j] = k < K ? skeys[k] : 0u;
   }
   const uint64_t after = base + uint64_t(kWave * kRangeItems);
-  const uint32_t edge_prev = (lane == 0 && base > 0) ? skeys[base - 1] : 0u;
-  const uint32_t edge_next = (lane == kWave - 1 && after < K) ? skeys[after] : 0u;
+  uint32_t edge_prev = (lane == 0 && base > 0) ? skeys[base - 1] : 0u;
+  uint32_t edge_next = (lane == kWave - 1 && after < K) ? skeys[after] : 0u;
+  if (record_bits) {
+#pragma unroll
+    for (int j = 0; j < kRangeItems; ++j) key[j] = list_key(key[j], record_bits, tile_bits, n);
+    edge_prev = list_key(edge_prev, record_bits, tile_bits, n);
+    edge_next = list_key(edge_next, record_bits, tile_bits, n);
+  }
   const uint32_t tmask = (1u << tile_bits) - 1u;
 #pragma unroll
   for (int j = 0; j < kRangeItems; ++j) {
@@ -593,6 +613,16 @@ __device__ __forceinline__ void build_quad_lists_split(uint32_t mask, uint32_t i
   }
 }
 
+// The record indices of the sorted lists. Key/value lists hold them in the
+// values array (mask all ones). One-word lists hold (tile << record_bits |
+// record) in a single array, sorted on the tile field alone, and the record
+// is the word's low record_bits bits.
+struct ListRecs {
+  const uint32_t *__restrict__ w;
+  uint32_t mask;
+  __device__ __forceinline__ uint32_t operator[](uint64_t i) const { return w[i] & mask; }
+};
+
 // Software pipelining of a tile's record batches: while a batch is being
 // evaluated, the next batch's records and the record indices of the one
 // after are already in flight, so the two dependent loads (index, then
@@ -608,14 +638,14 @@ struct BatchPrefetch {
     return b < e ? min(uint32_t(kWave), e - b) : 0u;
   }
   // before the loop: records of batch b, indices of batch b + stride
-  __device__ __forceinline__ void start(const uint32_t *__restrict__ svals, const Rec *__restrict__ rec, uint32_t b,
+  __device__ __forceinline__ void start(const ListRecs &svals, const Rec *__restrict__ rec, uint32_t b,
                                         uint32_t stride, uint32_t e, int lane) {
     if (uint32_t(lane) < count(b, e)) nxt = rec[svals[b + lane]];
     if (uint32_t(lane) < count(b + stride, e)) idx = svals[b + stride + lane];
   }
   // at the top of the iteration for batch b: cur = batch b's record; issue
   // the loads of batch b + stride (records) and b + 2 stride (indices)
-  __device__ __forceinline__ void advance(const uint32_t *__restrict__ svals, const Rec *__restrict__ rec,
+  __device__ __forceinline__ void advance(const ListRecs &svals, const Rec *__restrict__ rec,
                                           uint32_t b, uint32_t stride, uint32_t e, int lane) {
     cur = nxt;
     const uint32_t b1 = b + stride, b2 = b1 + stride;
@@ -654,7 +684,7 @@ __device__ __forceinline__ void set_null_record(float4 *s_cw, float2 *s_xy) {
 // pair); without it the pixel loop compares with the kernel argument.
 template <bool kCount, bool kInterior, int TPB, bool kTau>
 __global__ __launch_bounds__(kWave * TPB) void splat_fwd_kernel(const uint2 *__restrict__ rng,
-                                                           const uint32_t *__restrict__ svals,
+                                                           const ListRecs svals,
                                                            const SplatRec *__restrict__ rec,
                                                            int tiles_x, int tpv, int W, int H,
                                                            uint32_t n_tiles, int n_chunks, Units U, float thr,
@@ -849,7 +879,7 @@ __device__ __forceinline__ float bperm(int src_lane, float v) {
 // loop reads from LDS; without it the loop compares with the kernel argument.
 template <int TPB, bool kTau>
 __global__ __launch_bounds__(kWave * TPB) __attribute__((amdgpu_waves_per_eu(7, 7))) void splat_bwd_kernel(
-    const uint2 *__restrict__ rng, const uint32_t *__restrict__ svals,
+    const uint2 *__restrict__ rng, const ListRecs svals,
     const SplatRec *__restrict__ rec, int tiles_x, int tpv, int W, int H, uint32_t n_tiles, int n_chunks,
     Units U, float thr, float log2_tau, int no_cull, const float *__restrict__ gimg,
     float4 *__restrict__ partials) {
@@ -1055,7 +1085,7 @@ __global__ __launch_bounds__(kWave * TPB) __attribute__((amdgpu_waves_per_eu(7, 
 // the wave sums them (butterfly) and one lane adds them to the record's
 // accumulator acc6[r][6] with float atomics. Not deterministic.
 __global__ __launch_bounds__(kWave) void splat_bwd_pixel_kernel(
-    const uint2 *__restrict__ rng, const uint32_t *__restrict__ svals, const SplatRec *__restrict__ rec,
+    const uint2 *__restrict__ rng, const ListRecs svals, const SplatRec *__restrict__ rec,
     int tiles_x, int tpv, int W, int H, uint32_t n_tiles, float thr, const float *__restrict__ gimg,
     float *__restrict__ acc6) {
   __shared__ float4 s_cw[kWave];
@@ -1303,7 +1333,7 @@ struct ExactCam {
 
 template <bool kCount, int TPB>
 __global__ __launch_bounds__(kWave * TPB) void splat_fwd_exact_kernel(
-    const uint2 *__restrict__ rng, const uint32_t *__restrict__ svals, const ExactRec *__restrict__ rec,
+    const uint2 *__restrict__ rng, const ListRecs svals, const ExactRec *__restrict__ rec,
     int tiles_x, int tpv, int W, int H, uint32_t n_tiles, int n_chunks, float thr, float thr_cull, ExactCam cam,
     float *__restrict__ img, unsigned long long *__restrict__ counter) {
   __shared__ float4 s_a_all[TPB][kWave + 1];
@@ -1422,7 +1452,7 @@ constexpr int kExactSums = 13;
 // of alpha = -(p / A)(1/2 + phi) and beta = p / A.
 template <int TPB>
 __global__ __launch_bounds__(kWave * TPB) void splat_bwd_exact_kernel(
-    const uint2 *__restrict__ rng, const uint32_t *__restrict__ svals, const ExactRec *__restrict__ rec,
+    const uint2 *__restrict__ rng, const ListRecs svals, const ExactRec *__restrict__ rec,
     int tiles_x, int tpv, int W, int H, uint32_t n_tiles, int n_chunks, float thr, float thr_cull, ExactCam cam,
     const float *__restrict__ gimg, float4 *__restrict__ partials) {
   __shared__ float4 s_g4_all[TPB][kTS * kTS / 4];
@@ -1676,6 +1706,7 @@ struct RastLayout {
   uint64_t keys, vals, keys_alt, vals_alt, sort_scratch, partials, ufirst, utile, uslots;
   uint64_t total, n_units;
   bool sorted_in_alt;
+  int record_bits;  // > 0: one-word lists (tile << record_bits | record), no values arrays
 };
 
 // exact: the ray-exact model's 64-byte records and pair slots (else 32).
@@ -1699,10 +1730,15 @@ RastLayout rast_layout(uint64_t R, uint64_t T, uint64_t K, bool exact, int tile_
   c.take<uint2>(T, &L.rng);
   c.take<float>(11 * R, &L.grad_rec);
   L.fixed_end = c.used;
+  // one-word lists when the tile field and the record index fit 32 bits
+  // together (512^2 views: 10 + 22 bits, up to 4 M records per call): the
+  // sort then moves 4 bytes per key and pass instead of 8
+  const int rb = bits_for(R) > 0 ? bits_for(R) : 1;
+  L.record_bits = tile_bits + rb <= 32 ? rb : 0;
   c.take<uint32_t>(K, &L.keys);
-  c.take<uint32_t>(K, &L.vals);
+  c.take<uint32_t>(L.record_bits ? 0 : K, &L.vals);
   c.take<uint32_t>(K, &L.keys_alt);
-  c.take<uint32_t>(K, &L.vals_alt);
+  c.take<uint32_t>(L.record_bits ? 0 : K, &L.vals_alt);
   c.take<uint32_t>(sort_scratch_words(K), &L.sort_scratch);
   // per pair: the splat backward's six sums in a 32-byte slot (two aligned
   // 16-byte stores; 24-byte slots straddle lines and measured 1.5x the
@@ -1740,6 +1776,13 @@ inline uint64_t forward_partial_bytes(uint64_t T, bool exact, uint64_t n_img) {
 
 template <typename T>
 T *at(void *base, uint64_t off);
+
+// The sorted lists' record indices in a workspace laid out by L.
+ListRecs list_recs(const RastLayout &L, void *b) {
+  if (L.record_bits)
+    return ListRecs{at<uint32_t>(b, L.sorted_in_alt ? L.keys_alt : L.keys), (1u << L.record_bits) - 1u};
+  return ListRecs{at<uint32_t>(b, L.sorted_in_alt ? L.vals_alt : L.vals), 0xffffffffu};
+}
 
 Units make_units(const RastLayout &L, void *b, bool on) {
   if (!on) return Units{nullptr, nullptr, 0u};
@@ -1847,6 +1890,8 @@ int build_lists(const fgs_gaussians *g, const fgs_geom *geom, int32_t view_begin
     ws->n_records = R;
     ws->n_tiles = T;
     ws->tile_bits = tile_bits;
+    ws->record_bits = L.record_bits;
+    ws->n_gauss = uint64_t(g->n);
     if (!ws->ptr || ws->bytes < ws->needed) return fail(FGS_E_CAPACITY, "workspace too small for key_capacity pairs");
   } else if (!ws->ptr || ws->bytes < L.fixed_end + (uint64_t(1) << 20)) {
     ws->needed = L.fixed_end + (uint64_t(64) << 20);
@@ -1885,30 +1930,34 @@ int build_lists(const fgs_gaussians *g, const fgs_geom *geom, int32_t view_begin
     ws->n_records = R;
     ws->n_tiles = T;
     ws->tile_bits = tile_bits;
+    ws->record_bits = L.record_bits;
+    ws->n_gauss = uint64_t(g->n);
     if (ws->bytes < L.total + extra_bytes) return fail(FGS_E_CAPACITY, "workspace too small for the tile lists");
   }
   // the device copy of the pair count (0 if it exceeds the capacity)
   st = pair_count(total64, cap > 0 ? cap : L.K, kdev, cap > 0 ? ws->overflow : nullptr, s);
   if (st != FGS_OK) return st;
   if (L.K > 0) {
-    emit_kernel<<<grid_for(R, kEmitBlock), kEmitBlock, 0, s>>>(R, g->n, tg.tiles_x, tile_bits, at<ushort4>(b, L.rect),
+    emit_kernel<<<grid_for(R, kEmitBlock), kEmitBlock, 0, s>>>(R, g->n, tg.tiles_x, tile_bits, L.record_bits,
+                                                  at<ushort4>(b, L.rect),
                                                   at<uint32_t>(b, L.offset), at<uint32_t>(b, L.keys),
-                                                  at<uint32_t>(b, L.vals),
+                                                  L.record_bits ? nullptr : at<uint32_t>(b, L.vals),
                                                   exact ? &at<ExactRec>(b, L.rec)->d.y : &at<SplatRec>(b, L.rec)->b.z,
                                                   exact ? 16u : 8u, kdev);
     FGS_LAUNCH_CHECK("emit_kernel");
   }
   uint32_t *sk, *sv;
-  st = radix_sort_pairs(at<uint32_t>(b, L.keys), at<uint32_t>(b, L.vals), at<uint32_t>(b, L.keys_alt),
-                        at<uint32_t>(b, L.vals_alt), L.K, tile_bits, at<uint32_t>(b, L.sort_scratch),
-                        &sk, &sv, s, rast_sort_bits(L.K, tile_bits), cap > 0 ? kdev : nullptr);
+  st = radix_sort_pairs(at<uint32_t>(b, L.keys), L.record_bits ? nullptr : at<uint32_t>(b, L.vals),
+                        at<uint32_t>(b, L.keys_alt), L.record_bits ? nullptr : at<uint32_t>(b, L.vals_alt), L.K,
+                        tile_bits, at<uint32_t>(b, L.sort_scratch), &sk, &sv, s, rast_sort_bits(L.K, tile_bits),
+                        cap > 0 ? kdev : nullptr, L.record_bits);
   if (st != FGS_OK) return st;
   zero_ranges_kernel<<<grid_for(T, 256), 256, 0, s>>>(at<uint2>(b, L.rng), T);
   FGS_LAUNCH_CHECK("zero_ranges_kernel");
   if (L.K > 0) {
     const uint64_t waves = (L.K + uint64_t(kWave * kRangeItems) - 1) / uint64_t(kWave * kRangeItems);
     ranges_kernel<<<grid_for(waves * kWave, 256), 256, 0, s>>>(sk, L.K, kdev, tile_bits, uint32_t(tg.tpv),
-                                                               at<uint2>(b, L.rng));
+                                                               L.record_bits, uint32_t(g->n), at<uint2>(b, L.rng));
     FGS_LAUNCH_CHECK("ranges_kernel");
   }
   if (use_units(T, exact)) {
@@ -1949,7 +1998,7 @@ extern "C" int fgs_project_views_fwd(const fgs_gaussians *g, const fgs_geom *geo
   void *b = ws->ptr;
   float *part = part_bytes ? at<float>(b, (L.total + 255) / 256 * 256)
                            : (use_units(T, exact) ? at<float>(b, L.uslots) : img);
-  const uint32_t *sv = at<uint32_t>(b, L.sorted_in_alt ? L.vals_alt : L.vals);
+  const ListRecs sv = list_recs(L, b);
   const float thr = -0.5f * kLog2e * opts->kappa * opts->kappa;
   const float log2_tau = opts->density_aabb_tau > 0.f ? log2f(opts->density_aabb_tau) : -INFINITY;
   hipEvent_t *ev = static_cast<hipEvent_t *>(opts->events);
@@ -2014,7 +2063,7 @@ extern "C" int fgs_project_views_support(const fgs_gaussians *g, const fgs_geom 
   unsigned long long *cnt = reinterpret_cast<unsigned long long *>(out);
   zero_u64_kernel<<<1, 1, 0, s>>>(cnt, 1);
   FGS_LAUNCH_CHECK("zero_u64_kernel");
-  const uint32_t *sv = at<uint32_t>(b, L.sorted_in_alt ? L.vals_alt : L.vals);
+  const ListRecs sv = list_recs(L, b);
   const float thr = -0.5f * kLog2e * opts->kappa * opts->kappa;
   const float log2_tau = opts->density_aabb_tau > 0.f ? log2f(opts->density_aabb_tau) : -INFINITY;
   const TileGrid tg = tile_grid(geom->det_w, geom->det_h);
@@ -2072,7 +2121,7 @@ extern "C" int fgs_project_views_bwd(const fgs_gaussians *g, const fgs_geom *geo
   void *b = ws->ptr;
   const TileGrid tg = tile_grid(geom->det_w, geom->det_h);
   GeomDev G = make_geom_dev(geom, opts, view_begin, tg);
-  const uint32_t *sv = at<uint32_t>(b, L.sorted_in_alt ? L.vals_alt : L.vals);
+  const ListRecs sv = list_recs(L, b);
   const float thr = -0.5f * kLog2e * opts->kappa * opts->kappa;
   const float log2_tau = opts->density_aabb_tau > 0.f ? log2f(opts->density_aabb_tau) : -INFINITY;
   hipEvent_t *ev = static_cast<hipEvent_t *>(opts->events);
@@ -2195,10 +2244,12 @@ int rast_binning_layout(const fgs_workspace *ws, uint64_t off[9], uint64_t count
   off[1] = L.radii;
   off[2] = L.rect;
   off[3] = L.offset;
+  // one-word lists (ws->record_bits > 0) have no values arrays: the value
+  // offsets repeat the key offsets (the words hold both)
   off[4] = L.sorted_in_alt ? L.keys : L.keys_alt;
-  off[5] = L.sorted_in_alt ? L.vals : L.vals_alt;
+  off[5] = L.record_bits ? off[4] : (L.sorted_in_alt ? L.vals : L.vals_alt);
   off[6] = L.sorted_in_alt ? L.keys_alt : L.keys;
-  off[7] = L.sorted_in_alt ? L.vals_alt : L.vals;
+  off[7] = L.record_bits ? off[6] : (L.sorted_in_alt ? L.vals_alt : L.vals);
   off[8] = L.rng;
   counts[0] = L.R;
   counts[1] = L.K;

@@ -165,8 +165,9 @@ __global__ __launch_bounds__(kThreads) void rs_hist_kernel(const uint32_t *__res
 // processed 64 keys at a time, so (wave, round, lane) order is input order.
 // Keys are first placed in LDS in the tile's digit-sorted order, then
 // written out linearly: consecutive threads write consecutive positions of
-// each digit's run, so the global writes are coalesced.
-template <int NB>
+// each digit's run, so the global writes are coalesced. kVals = false: keys
+// only (the values arrays are not touched).
+template <int NB, bool kVals>
 __global__ __launch_bounds__(kThreads) void rs_scatter_kernel(
     const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in, uint64_t n_cap,
     const uint32_t *__restrict__ n_dev, int shift, int nbits, const uint32_t *__restrict__ hist_scanned,
@@ -177,7 +178,7 @@ __global__ __launch_bounds__(kThreads) void rs_scatter_kernel(
   __shared__ uint32_t s_local[kBins];     // tile-local start of each digit's run
   __shared__ uint32_t s_global[kBins];    // global start of each digit's run for this tile
   __shared__ uint32_t s_keys[kTile];
-  __shared__ uint32_t s_vals[kTile];
+  __shared__ uint32_t s_vals[kVals ? kTile : 1];
   __shared__ uint32_t s_wsum[kWaves];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const uint32_t mask = (1u << nbits) - 1u;
@@ -192,7 +193,7 @@ __global__ __launch_bounds__(kThreads) void rs_scatter_kernel(
   for (int j = 0; j < kItems; ++j) {
     const uint64_t idx = wbase + uint64_t(j) * 64 + lane;
     k[j] = idx < n ? keys_in[idx] : 0u;
-    v[j] = idx < n ? vals_in[idx] : 0u;
+    v[j] = (kVals && idx < n) ? vals_in[idx] : 0u;
   }
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
@@ -265,7 +266,7 @@ __global__ __launch_bounds__(kThreads) void rs_scatter_kernel(
       const uint32_t d = (k[j] >> shift) & mask;
       const uint32_t lp = s_local[d] + cnt[wid][d] + rank[j];
       s_keys[lp] = k[j];
-      s_vals[lp] = v[j];
+      if (kVals) s_vals[lp] = v[j];
     }
   }
   __syncthreads();
@@ -276,7 +277,7 @@ __global__ __launch_bounds__(kThreads) void rs_scatter_kernel(
     const uint32_t d = (key >> shift) & mask;
     const uint32_t pos = s_global[d] + (uint32_t(i) - s_local[d]);
     keys_out[pos] = key;
-    vals_out[pos] = s_vals[i];
+    if (kVals) vals_out[pos] = s_vals[i];
   }
 }
 
@@ -368,20 +369,23 @@ uint64_t sort_scratch_words(uint64_t n) {
 
 int radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
                      uint64_t n, int bits, uint32_t *scratch, uint32_t **out_keys,
-                     uint32_t **out_vals, hipStream_t s, int max_bits, const uint32_t *n_dev) {
+                     uint32_t **out_vals, hipStream_t s, int max_bits, const uint32_t *n_dev, int bit0) {
   *out_keys = keys;
   *out_vals = vals;
   if (n <= 1 || bits <= 0) return FGS_OK;
   if (n > 0xffffffffull) return fail(FGS_E_UNSUPPORTED, "sort: more than 2^32 pairs");
   const uint64_t tiles = (n + kTile - 1) / kTile;
   if (max_bits < 1 || max_bits > kSortMaxBits) return fail(FGS_E_INVALID, "sort: digit width");
+  if (bit0 < 0 || bit0 + bits > 32) return fail(FGS_E_INVALID, "sort: key field outside 32 bits");
+  const bool with_vals = vals != nullptr;
   const int passes = sort_passes(n, bits, max_bits);
   const int per = (bits + passes - 1) / passes;
   uint32_t *table = scratch;
   uint32_t *scan_tmp = scratch + align_up((uint64_t(kMaxBins) * tiles + 1) * sizeof(uint32_t)) / sizeof(uint32_t);
   uint32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
-  for (int p = 0, shift = 0; p < passes; ++p, shift += per) {
-    const int nb = (bits - shift < per) ? (bits - shift) : per;
+  for (int p = 0, done = 0; p < passes; ++p, done += per) {
+    const int nb = (bits - done < per) ? (bits - done) : per;
+    const int shift = bit0 + done;
     const uint32_t mask = (1u << nb) - 1u;
     if (nb > 9)
       rs_hist_kernel<10><<<unsigned(tiles), kThreads, 0, s>>>(ki, n, n_dev, shift, mask, table, unsigned(tiles));
@@ -392,15 +396,20 @@ int radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_
     FGS_LAUNCH_CHECK("rs_hist_kernel");
     int st = exclusive_scan_u32(table, uint64_t(mask + 1) * tiles, scan_tmp, s);
     if (st != FGS_OK) return st;
-    if (nb > 9)
-      rs_scatter_kernel<10><<<unsigned(tiles), kThreads, 0, s>>>(ki, vi, n, n_dev, shift, nb, table, unsigned(tiles),
-                                                                 ko, vo);
-    else if (nb > 6)
-      rs_scatter_kernel<9><<<unsigned(tiles), kThreads, 0, s>>>(ki, vi, n, n_dev, shift, nb, table, unsigned(tiles),
-                                                                 ko, vo);
-    else
-      rs_scatter_kernel<6><<<unsigned(tiles), kThreads, 0, s>>>(ki, vi, n, n_dev, shift, nb, table, unsigned(tiles),
-                                                                 ko, vo);
+    auto scatter = [&](auto nbc, auto wv) {
+      rs_scatter_kernel<decltype(nbc)::value, decltype(wv)::value><<<unsigned(tiles), kThreads, 0, s>>>(
+          ki, vi, n, n_dev, shift, nb, table, unsigned(tiles), ko, vo);
+    };
+    using B10 = std::integral_constant<int, 10>;
+    using B9 = std::integral_constant<int, 9>;
+    using B6 = std::integral_constant<int, 6>;
+    if (with_vals) {
+      if (nb > 9) scatter(B10(), std::true_type()); else if (nb > 6) scatter(B9(), std::true_type());
+      else scatter(B6(), std::true_type());
+    } else {
+      if (nb > 9) scatter(B10(), std::false_type()); else if (nb > 6) scatter(B9(), std::false_type());
+      else scatter(B6(), std::false_type());
+    }
     FGS_LAUNCH_CHECK("rs_scatter_kernel");
     uint32_t *t;
     t = ki; ki = ko; ko = t;

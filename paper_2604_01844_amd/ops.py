@@ -572,13 +572,22 @@ def binning_dump(ws: Workspace) -> dict:
         t = buf[int(off[i]):int(off[i]) + nbytes].view(dtype)
         return t.view(count, width) if width > 1 else t
 
+    sorted_keys, sorted_vals = view(6, torch.int32, K), view(7, torch.int32, K)
+    rb = int(ws.s.record_bits) if not vox else 0
+    if rb:
+        # one-word lists: word = tile << record_bits | record; the key is
+        # (record / n_gauss) << tile_bits | tile, the value the record
+        w = sorted_keys.to(torch.int64) & 0xffffffff
+        rec = w & ((1 << rb) - 1)
+        sorted_keys = (((rec // int(ws.s.n_gauss)) << int(ws.s.tile_bits)) | (w >> rb)).to(torch.int32)
+        sorted_vals = rec.to(torch.int32)
     return dict(
         centre=view(0, torch.float32, R, 4 if vox else 2),
         radii=view(1, torch.float32, R, 4 if vox else 2),
         rect=view(2, torch.int16, R, 8 if vox else 4),
         offset=view(3, torch.int32, R + 1),
-        sorted_keys=view(6, torch.int32, K),
-        sorted_vals=view(7, torch.int32, K),
+        sorted_keys=sorted_keys,
+        sorted_vals=sorted_vals,
         **({"tile_start": view(8, torch.int32, T + 1)} if vox else
            {"tile_ranges": view(8, torch.int32, T, 2), "tile_bits": int(ws.s.tile_bits)}),
         n_records=R, n_pairs=K, n_tiles=T)

@@ -103,9 +103,10 @@ def test_product_path_does_not_import_the_oracle():
 
 def test_workspace_query_is_host_arithmetic():
     """fgs_workspace_query runs without a GPU: the per-pair bytes match the
-    layout (4 uint32 arrays for keys and values with their sort copies, a
+    layout (at 512^2 with 75 views the tile field and the record index fit
+    one 32-bit word: 2 uint32 arrays for the words and their sort copy, a
     32-byte pair slot, about one byte of sort histogram and the work-unit
-    table: 49 for the splat;
+    table: 41 for the splat; with key and value arrays, 49;
     64-byte slots for the ray-exact model; the voxelizer adds the gid array
     and 40-byte slots), and the fixed part grows with the records."""
     from paper_2604_01844_amd import _abi as A
@@ -117,14 +118,19 @@ def test_workspace_query_is_host_arithmetic():
     q = lambda op, gptr, geom, grid, vc, opts: lib.fgs_workspace_query(op, gptr, geom, grid, vc, opts,
                                                                         ctypes.byref(fixed), ctypes.byref(per))
     assert q(A.FGS_OP_PROJECT_BWD, ctypes.byref(g), ctypes.byref(gm), None, 75, ctypes.byref(o)) == A.FGS_OK
-    assert 49 <= per.value <= 50
+    assert 41 <= per.value <= 42
     fixed75 = fixed.value
     assert fixed75 > 75 * 50000 * 100
     assert q(A.FGS_OP_PROJECT_BWD, ctypes.byref(g), ctypes.byref(gm), None, 1, ctypes.byref(o)) == A.FGS_OK
     assert fixed.value < fixed75 / 50
     oe = A.fgs_opts(kappa=3.0, near_plane=1e-2, recompute=1, model=A.FGS_MODEL_RAY_EXACT)
     assert q(A.FGS_OP_PROJECT_FWD, ctypes.byref(g), ctypes.byref(gm), None, 75, ctypes.byref(oe)) == A.FGS_OK
-    assert 81 <= per.value <= 82
+    assert 73 <= per.value <= 74
+    # 2048^2 views (14-bit tile field) of 500,000 Gaussians: key/value lists
+    g5 = A.fgs_gaussians(500000, None, None, None, None)
+    gm2 = A.fgs_geom(A.FGS_CONE, 50, 16, 1.5, 2.0, 2048, 2048, 0.0014, 0.0014, 0.0, 0.0)
+    assert q(A.FGS_OP_PROJECT_FWD, ctypes.byref(g5), ctypes.byref(gm2), None, 10, ctypes.byref(o)) == A.FGS_OK
+    assert 49 <= per.value <= 50
     gr = A.fgs_grid((ctypes.c_float * 3)(-0.5, -0.5, -0.5), (ctypes.c_float * 3)(1 / 256, 1 / 256, 1 / 256),
                     (ctypes.c_int32 * 3)(256, 256, 256))
     assert q(A.FGS_OP_VOXELIZE_FWD, ctypes.byref(g), None, ctypes.byref(gr), 0, ctypes.byref(o)) == A.FGS_OK
