@@ -696,7 +696,10 @@ int fgs_reduce_max(const float *x, int64_t n, float *out, fgs_workspace *ws, voi
  * Records are r = local_view * n + i (voxelizer: r = i). Rasterizer keys are
  * local_view << ws->tile_bits | tile, sorted by tile and then view (each
  * key's pairs contiguous, in ascending record order); voxelizer keys are the
- * tile index, sorted ascending.
+ * tile index, sorted ascending. Rasterizer workspaces with ws->record_bits > 0
+ * hold one-word lists instead: off[4] and off[5] (off[6] and off[7]) both
+ * name the emitted (sorted) words tile << record_bits | r, from which the key
+ * is (r / ws->n_gauss) << tile_bits | tile and the value r.
  * ------------------------------------------------------------------- */
 int fgs_binning_layout(const fgs_workspace *ws, uint64_t off[9], uint64_t counts[3]);
 
