@@ -309,8 +309,13 @@ typedef struct {
  * near plane, model, density_aabb_tau of the rasterizer (the crop's
  * voxelizer takes kappa only); opts->events must be NULL. Workspaces: the
  * rasterizer's (its lists are left there), the crop voxelizer's, and one
- * for the loss terms (12 bytes per pixel and a few KiB). With key_capacity
- * > 0 in ws_proj and ws_crop the step never waits for the GPU.
+ * for the loss terms (with SSIM 12 bytes per pixel, plus 8 bytes per 16 x 16
+ * detector tile and 8 KiB; ws_loss->needed gives the figure). With
+ * key_capacity > 0 in ws_proj and ws_crop the step never waits for the GPU.
+ * The gradient is the one the separate calls give (fgs_l1_loss_grad, then
+ * fgs_ssim_loss_grad accumulating, ...) bit for bit; the reported loss
+ * terms are the same sums added up in another order (the L1 term per
+ * 16 x 16 tile when SSIM is on), so they can differ in the last bits.
  * Same error protocol as the calls it makes: on FGS_E_CAPACITY grow the
  * named workspace and retry; on any error the parameters and moments are
  * unchanged (scratch buffers may have been written). */

@@ -36,9 +36,9 @@ inline int chunks_per_tile(uint64_t n_tiles) {
   return int(c < 16 ? c : 16);
 }
 
-// Key emission is block-cooperative: a block of kEmitBlock threads takes
-// kEmitBlock consecutive records and writes their keys (which are contiguous
-// after the scan) in coalesced rounds of kEmitBlock, each thread finding its
+// Key emission is block-cooperative: a block of kEmitBlock threads takes up
+// to kEmitBlock consecutive records and writes their keys (which are
+// contiguous after the scan) in coalesced rounds, each thread finding its
 // key's record by binary search over the block's offsets in LDS.
 constexpr int kEmitBlock = 256;
 
@@ -157,14 +157,34 @@ int radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_
                      uint32_t **out_vals, hipStream_t s, int max_bits = kSortMaxBits,
                      const uint32_t *n_dev = nullptr, int bit0 = 0);
 
-// Pair count of a binning from its kTotalSlots 64-bit partial totals:
-// count[0] = the total if it is at most cap, else 0 (nothing is binned);
-// count[1] = 1 if the total exceeds cap, else 0. With cap > 0 and a non-null
-// `overflow` (device uint32[2]), an excess also sets overflow[0] = 1 and
-// raises overflow[1] to the total (clamped to 2^32 - 1). One wave.
-constexpr int kTotalSlots = 64;
-int pair_count(const unsigned long long *total64, uint64_t cap, uint32_t *count, uint32_t *overflow,
-               hipStream_t s);
+// Exclusive scan of a binning's per-record key counts (n values, each
+// tile of 4096 summing below 2^32; count[n] = the 32-bit total) that also
+// gives its pair count without a host wait: *total = the 64-bit sum;
+// pairs[0] = the sum if it is at most cap, else 0 (nothing is binned);
+// pairs[1] = 1 if the sum exceeds cap, else 0. A non-null `overflow` (device
+// uint32[2]) on an excess: overflow[0] = 1 and overflow[1] raised to the sum
+// (clamped to 2^32 - 1). scratch: scan_scratch_words(n) words.
+int scan_counts(uint32_t *count, uint64_t n, uint32_t *scratch, uint64_t cap, unsigned long long *total,
+                uint32_t *pairs, uint32_t *overflow, hipStream_t s);
+
+// Loss terms of the optimiser step that leave their per-block partial sums
+// for one later reduction (the step adds them up in its Adam launch):
+// loss_blocks(n): the partial sums of the L1 or TV term over n values (at
+// most kLossBlocks); l1_partials: the L1 term of Eq. 5, grad = sign(img -
+// gt) * inv_p; tv_partials: the crop TV term with its gradient (scale / n
+// per sign); ssim_l1_partials: the SSIM term of one W x H view (partials
+// per 16 x 16 tile, ssim_tiles of them) with, for l1_inv_p > 0, the L1 term
+// fused in (its partials per tile too), grad = L1 + SSIM gradient written
+// (not added); gmaps: 3 W H floats of scratch.
+constexpr int kLossBlocks = 1024;
+int loss_blocks(uint64_t n);
+int l1_partials(const float *img, const float *gt, uint64_t n, float inv_p, float *grad, float *partial,
+                hipStream_t s);
+int tv_partials(const float *vol, const int32_t dims[3], float scale, float *grad, float *partial,
+                hipStream_t s);
+uint64_t ssim_tiles(int32_t W, int32_t H);
+int ssim_l1_partials(const float *img, const float *gt, int32_t W, int32_t H, float c1, float c2, float scale,
+                     float l1_inv_p, float *grad, float *gmaps, float *part_ssim, float *part_l1, hipStream_t s);
 
 inline int bits_for(uint64_t n_values) {  // bits needed to hold 0 .. n_values - 1
   int b = 0;

@@ -13,7 +13,7 @@ namespace fgs {
 namespace {
 
 constexpr int kRedThreads = 256;
-constexpr int kRedBlocks = 1024;
+constexpr int kRedBlocks = kLossBlocks;
 
 // partial[b] = sum over this block's grid-stride share of |img - gt|; grad
 // written alongside.
@@ -129,6 +129,25 @@ int launch_l1(const float *img, const float *gt, int64_t n_per_view, int32_t n_v
 }
 
 }  // namespace
+
+int loss_blocks(uint64_t n) { return reduce_blocks(n); }
+
+int l1_partials(const float *img, const float *gt, uint64_t n, float inv_p, float *grad, float *partial,
+                hipStream_t s) {
+  l1_kernel<<<reduce_blocks(n), kRedThreads, 0, s>>>(img, gt, n, inv_p, grad, partial);
+  FGS_LAUNCH_CHECK("l1_kernel");
+  return FGS_OK;
+}
+
+int tv_partials(const float *vol, const int32_t dims[3], float scale, float *grad, float *partial,
+                hipStream_t s) {
+  const uint64_t n = uint64_t(dims[0]) * dims[1] * dims[2];
+  tv_kernel<<<reduce_blocks(n), kRedThreads, 0, s>>>(vol, dims[0], dims[1], dims[2],
+                                                     float(double(scale) / double(n)), grad, partial);
+  FGS_LAUNCH_CHECK("tv_kernel");
+  return FGS_OK;
+}
+
 }  // namespace fgs
 
 using namespace fgs;

@@ -231,27 +231,21 @@ __global__ __launch_bounds__(256) void record_kernel(fgs_gaussians g, GeomDev G,
                                                      void *__restrict__ rec,
                                                      float2 *__restrict__ radii,
                                                      ushort4 *__restrict__ rect,
-                                                     uint32_t *__restrict__ count,
-                                                     unsigned long long *__restrict__ total64) {
+                                                     uint32_t *__restrict__ count) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  uint32_t cnt = 0;
-  if (i < g.n) {
-    if (kExact)
-      cnt = record_one_exact(g, G, i, int(blockIdx.y), xy, static_cast<ExactRec *>(rec), radii, rect, count);
-    else
-      cnt = record_one(g, G, i, int(blockIdx.y), xy, static_cast<SplatRec *>(rec), radii, rect, count);
-  }
-  // 64-bit pair total (detects a 32-bit scan overflow): one atomic per wave,
-  // spread over kTotalSlots addresses to keep contention low
-  unsigned long long w = cnt;
-  for (int d = 32; d > 0; d >>= 1) w += __shfl_xor(w, d, 64);
-  if ((threadIdx.x & 63) == 0 && w)
-    atomicAdd(total64 + ((blockIdx.x * 4 + (threadIdx.x >> 6) + blockIdx.y * 7) & (kTotalSlots - 1)), w);
+  if (i >= g.n) return;
+  if (kExact)
+    record_one_exact(g, G, i, int(blockIdx.y), xy, static_cast<ExactRec *>(rec), radii, rect, count);
+  else
+    record_one(g, G, i, int(blockIdx.y), xy, static_cast<SplatRec *>(rec), radii, rect, count);
 }
 
 // record_bits > 0: one-word lists, keys[q] = tile << record_bits | record
 // (the view is the record's, r / n) and no values; else keys[q] = view <<
 // tile_bits | tile and vals[q] = the record.
+// RPB records per block (kEmitBlock or fewer: calls with few records take
+// fewer per block, so that more waves share the keys).
+template <int RPB>
 __global__ __launch_bounds__(kEmitBlock) void emit_kernel(uint64_t R, int64_t n, int tiles_x, int tile_bits,
                                                           int record_bits, const ushort4 *__restrict__ rect,
                                                           const uint32_t *__restrict__ offset,
@@ -260,10 +254,11 @@ __global__ __launch_bounds__(kEmitBlock) void emit_kernel(uint64_t R, int64_t n,
                                                           uint32_t base_stride, const uint32_t *__restrict__ kdev) {
   // nothing to emit: no pairs, or more than the lists were laid out for
   if (kdev[0] == 0u) return;
-  __shared__ uint32_t s_off[kEmitBlock + 1];
-  __shared__ ushort4 s_rect[kEmitBlock];
-  const uint64_t r0 = uint64_t(blockIdx.x) * kEmitBlock;
-  const int nr = int(min(uint64_t(kEmitBlock), R - r0));
+  static_assert(RPB <= kEmitBlock, "one record per thread at most");
+  __shared__ uint32_t s_off[RPB + 1];
+  __shared__ ushort4 s_rect[RPB];
+  const uint64_t r0 = uint64_t(blockIdx.x) * RPB;
+  const int nr = int(min(uint64_t(RPB), R - r0));
   const int t = threadIdx.x;
   if (t < nr) {
     const uint64_t r = r0 + t;
@@ -327,11 +322,42 @@ __device__ __forceinline__ uint32_t list_key(uint32_t w, int record_bits, int ti
   return record_bits ? (((w & ((1u << record_bits) - 1u)) / n) << tile_bits) | (w >> record_bits) : w;
 }
 
+// Every tile's range [x, y) of the sorted list, (0, 0) for a tile without
+// keys. The list is in (tile, view) order (the sort is on the tile field and
+// stable, and records ascend with the view), so a key's rank in that order
+// is tile * V + view for V = T / tpv views. The grid clears the tiles of the
+// ranks before the first key's and after the last key's (all T with no keys
+// on the device); the first key of each run clears those of the ranks
+// between the previous run's and its own.
+__device__ __forceinline__ uint32_t rank_tile(uint32_t q, uint32_t V, uint32_t tpv) {
+  const uint32_t tt = V == 1u ? q : q / V;
+  return (q - tt * V) * tpv + tt;
+}
+
 __global__ __launch_bounds__(256) void ranges_kernel(const uint32_t *__restrict__ skeys, uint64_t K_cap,
                                                      const uint32_t *__restrict__ kdev, int tile_bits,
-                                                     uint32_t tpv, int record_bits, uint32_t n,
+                                                     uint32_t tpv, int record_bits, uint32_t n, uint64_t T,
                                                      uint2 *__restrict__ rng) {
   const uint64_t K = min(K_cap, uint64_t(kdev[0]));
+  const uint32_t V = uint32_t(T / tpv);
+  const uint32_t tmask = (1u << tile_bits) - 1u;
+  {
+    uint32_t lo = uint32_t(T), hi = uint32_t(T);  // ranks [0, lo) and [hi, T) have no keys
+    if (K > 0) {
+      uint32_t f = skeys[0], l = skeys[K - 1];
+      if (record_bits) {
+        f = list_key(f, record_bits, tile_bits, n);
+        l = list_key(l, record_bits, tile_bits, n);
+      }
+      lo = (f & tmask) * V + (f >> tile_bits);
+      hi = (l & tmask) * V + (l >> tile_bits) + 1u;
+    }
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < lo; q += stride)
+      rng[rank_tile(q, V, tpv)] = make_uint2(0u, 0u);
+    for (uint32_t q = hi + blockIdx.x * blockDim.x + threadIdx.x; q < uint32_t(T); q += stride)
+      rng[rank_tile(q, V, tpv)] = make_uint2(0u, 0u);
+  }
   const int lane = threadIdx.x & (kWave - 1);
   const uint64_t base = ((uint64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6) * uint64_t(kWave * kRangeItems);
   if (base >= K) return;  // uniform over the wave
@@ -350,7 +376,6 @@ __global__ __launch_bounds__(256) void ranges_kernel(const uint32_t *__restrict_
     edge_prev = list_key(edge_prev, record_bits, tile_bits, n);
     edge_next = list_key(edge_next, record_bits, tile_bits, n);
   }
-  const uint32_t tmask = (1u << tile_bits) - 1u;
 #pragma unroll
   for (int j = 0; j < kRangeItems; ++j) {
     const uint64_t k = base + uint64_t(j) * kWave + lane;
@@ -364,7 +389,13 @@ __global__ __launch_bounds__(256) void ranges_kernel(const uint32_t *__restrict_
     if (k < K) {
       if (k + 1 == K) next = ~kv;
       const uint32_t tile = (kv >> tile_bits) * tpv + (kv & tmask);
-      if (prev != kv) rng[tile].x = uint32_t(k);
+      const uint32_t rank = (kv & tmask) * V + (kv >> tile_bits);
+      if (prev != kv) {
+        rng[tile].x = uint32_t(k);
+        if (k > 0)
+          for (uint32_t q = (prev & tmask) * V + (prev >> tile_bits) + 1u; q < rank; ++q)
+            rng[rank_tile(q, V, tpv)] = make_uint2(0u, 0u);
+      }
       if (next != kv) rng[tile].y = uint32_t(k + 1);
     }
   }
@@ -1716,7 +1747,7 @@ RastLayout rast_layout(uint64_t R, uint64_t T, uint64_t K, bool exact, int tile_
   L.T = T;
   L.K = K;
   Carver c(nullptr);
-  c.take<unsigned long long>(kTotalSlots, &L.total64);
+  c.take<unsigned long long>(1, &L.total64);
   c.take<uint32_t>(4, &L.kdev);
   c.take<float2>(R, &L.xy);
   c.take<float2>(R, &L.radii);
@@ -1900,27 +1931,26 @@ int build_lists(const fgs_gaussians *g, const fgs_geom *geom, int32_t view_begin
   GeomDev G = make_geom_dev(geom, o, view_begin, tg);
   void *b = ws->ptr;
   unsigned long long *total64 = at<unsigned long long>(b, L.total64);
-  zero_u64_kernel<<<1, kTotalSlots, 0, s>>>(total64, kTotalSlots);
-  FGS_LAUNCH_CHECK("zero_u64_kernel");
   dim3 rgrid(grid_for(uint64_t(g->n), 256), unsigned(view_count));
   if (exact)
     record_kernel<true><<<rgrid, 256, 0, s>>>(*g, G, at<float2>(b, L.xy), at<void>(b, L.rec),
                                               at<float2>(b, L.radii), at<ushort4>(b, L.rect),
-                                              at<uint32_t>(b, L.offset), total64);
+                                              at<uint32_t>(b, L.offset));
   else
     record_kernel<false><<<rgrid, 256, 0, s>>>(*g, G, at<float2>(b, L.xy), at<void>(b, L.rec),
                                                at<float2>(b, L.radii), at<ushort4>(b, L.rect),
-                                               at<uint32_t>(b, L.offset), total64);
+                                               at<uint32_t>(b, L.offset));
   FGS_LAUNCH_CHECK("record_kernel");
-  int st = exclusive_scan_u32(at<uint32_t>(b, L.offset), R, at<uint32_t>(b, L.scan_scratch), s);
-  if (st != FGS_OK) return st;
+  // offsets, the 64-bit pair total and the device pair count (0 past the
+  // capacity) in one scan
   uint32_t *kdev = at<uint32_t>(b, L.kdev);
+  int st = scan_counts(at<uint32_t>(b, L.offset), R, at<uint32_t>(b, L.scan_scratch),
+                       cap > 0 ? cap : uint64_t(0xfffffffeull), total64, kdev, cap > 0 ? ws->overflow : nullptr, s);
+  if (st != FGS_OK) return st;
   if (cap == 0) {
-    unsigned long long slots[kTotalSlots];
-    FGS_HIP(hipMemcpyAsync(slots, total64, sizeof(slots), hipMemcpyDeviceToHost, s));
-    FGS_HIP(hipStreamSynchronize(s));
     unsigned long long K64 = 0;
-    for (int i = 0; i < kTotalSlots; ++i) K64 += slots[i];
+    FGS_HIP(hipMemcpyAsync(&K64, total64, sizeof(K64), hipMemcpyDeviceToHost, s));
+    FGS_HIP(hipStreamSynchronize(s));
     if (K64 >= 0xffffffffull)
       return fail(FGS_E_UNSUPPORTED, "more than 2^32 (tile, Gaussian) pairs in one call; split the views");
     const uint64_t K = K64;
@@ -1934,16 +1964,21 @@ int build_lists(const fgs_gaussians *g, const fgs_geom *geom, int32_t view_begin
     ws->n_gauss = uint64_t(g->n);
     if (ws->bytes < L.total + extra_bytes) return fail(FGS_E_CAPACITY, "workspace too small for the tile lists");
   }
-  // the device copy of the pair count (0 if it exceeds the capacity)
-  st = pair_count(total64, cap > 0 ? cap : L.K, kdev, cap > 0 ? ws->overflow : nullptr, s);
-  if (st != FGS_OK) return st;
   if (L.K > 0) {
-    emit_kernel<<<grid_for(R, kEmitBlock), kEmitBlock, 0, s>>>(R, g->n, tg.tiles_x, tile_bits, L.record_bits,
-                                                  at<ushort4>(b, L.rect),
-                                                  at<uint32_t>(b, L.offset), at<uint32_t>(b, L.keys),
-                                                  L.record_bits ? nullptr : at<uint32_t>(b, L.vals),
-                                                  exact ? &at<ExactRec>(b, L.rec)->d.y : &at<SplatRec>(b, L.rec)->b.z,
-                                                  exact ? 16u : 8u, kdev);
+    auto emit = [&](auto rpb) {
+      constexpr int RPB = decltype(rpb)::value;
+      emit_kernel<RPB><<<grid_for(R, RPB), kEmitBlock, 0, s>>>(R, g->n, tg.tiles_x, tile_bits, L.record_bits,
+          at<ushort4>(b, L.rect),
+          at<uint32_t>(b, L.offset), at<uint32_t>(b, L.keys),
+          L.record_bits ? nullptr : at<uint32_t>(b, L.vals),
+          exact ? &at<ExactRec>(b, L.rec)->d.y : &at<SplatRec>(b, L.rec)->b.z,
+          exact ? 16u : 8u, kdev);
+    };
+    // a call of fewer than 256 K records: 64 records per block
+    if (R < (uint64_t(1) << 18))
+      emit(std::integral_constant<int, 64>());
+    else
+      emit(std::integral_constant<int, kEmitBlock>());
     FGS_LAUNCH_CHECK("emit_kernel");
   }
   uint32_t *sk, *sv;
@@ -1952,13 +1987,14 @@ int build_lists(const fgs_gaussians *g, const fgs_geom *geom, int32_t view_begin
                         tile_bits, at<uint32_t>(b, L.sort_scratch), &sk, &sv, s, rast_sort_bits(L.K, tile_bits),
                         cap > 0 ? kdev : nullptr, L.record_bits);
   if (st != FGS_OK) return st;
-  zero_ranges_kernel<<<grid_for(T, 256), 256, 0, s>>>(at<uint2>(b, L.rng), T);
-  FGS_LAUNCH_CHECK("zero_ranges_kernel");
   if (L.K > 0) {
     const uint64_t waves = (L.K + uint64_t(kWave * kRangeItems) - 1) / uint64_t(kWave * kRangeItems);
     ranges_kernel<<<grid_for(waves * kWave, 256), 256, 0, s>>>(sk, L.K, kdev, tile_bits, uint32_t(tg.tpv),
-                                                               L.record_bits, uint32_t(g->n), at<uint2>(b, L.rng));
+                                                               L.record_bits, uint32_t(g->n), T, at<uint2>(b, L.rng));
     FGS_LAUNCH_CHECK("ranges_kernel");
+  } else {
+    zero_ranges_kernel<<<grid_for(T, 256), 256, 0, s>>>(at<uint2>(b, L.rng), T);
+    FGS_LAUNCH_CHECK("zero_ranges_kernel");
   }
   if (use_units(T, exact)) {
     unit_offsets_kernel<<<1, 1024, 0, s>>>(at<uint2>(b, L.rng), uint32_t(T), uint32_t(L.n_units),

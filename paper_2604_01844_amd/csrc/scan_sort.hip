@@ -66,18 +66,46 @@ __global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const T *__restri
   if (threadIdx.x == 0) partial[blockIdx.x] = total;
 }
 
+// The pair count of a binning, taken from the scan of its per-record key
+// counts (count == null: none). total: the 64-bit sum of the counts;
+// count[0] = that sum if it is at most cap, else 0 (nothing is binned);
+// count[1] = 1 if it exceeds cap, else 0; with a non-null overflow (device
+// uint32[2]) an excess also sets overflow[0] = 1 and raises overflow[1] to
+// the sum (clamped to 2^32 - 1).
+struct CountOut {
+  uint64_t cap;
+  unsigned long long *total;
+  uint32_t *count;
+  uint32_t *overflow;
+};
+
+__device__ __forceinline__ void write_count(const CountOut &co, unsigned long long v) {
+  const bool over = v > co.cap;
+  co.total[0] = v;
+  co.count[0] = over ? 0u : uint32_t(v);
+  co.count[1] = over ? 1u : 0u;
+  if (over && co.overflow) {
+    co.overflow[0] = 1u;
+    atomicMax(co.overflow + 1, uint32_t(v < 0xffffffffull ? v : 0xffffffffull));
+  }
+}
+
 // Scans one tile in LDS; adds the tile's offset. partial (may be null for a
 // single tile): with self_prefix, the tiles' sums, of which each block adds
 // up those before it (one launch fewer; used for few tiles); else the
 // already scanned tile offsets. The last tile writes the grand total to
-// data[n].
+// data[n] and, with co.count, the 64-bit total and the pair count: it adds
+// up every tile's sum in 64 bits (a scanned offset table gives them as
+// differences of neighbours, exact while one tile's sum fits 32 bits), so
+// a 32-bit wrap of the offsets is detected.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void scan_apply_kernel(T *__restrict__ data, uint64_t n,
                                                               const T *__restrict__ partial,
-                                                              uint32_t n_tiles, int self_prefix) {
+                                                              uint32_t n_tiles, int self_prefix, CountOut co) {
   __shared__ T tile[kTile + kTile / 32];
   __shared__ T wsum[kWaves];
   __shared__ T s_pre;
+  __shared__ unsigned long long s_before64;
   const uint64_t base = uint64_t(blockIdx.x) * kTile;
   if (partial && self_prefix) {
     T acc = 0;
@@ -85,6 +113,19 @@ __global__ __launch_bounds__(kThreads) void scan_apply_kernel(T *__restrict__ da
     T tot;
     block_exclusive_scan(acc, wsum, tot);
     if (threadIdx.x == 0) s_pre = tot;
+    __syncthreads();
+  }
+  const bool count_here = co.count && blockIdx.x == n_tiles - 1;
+  if (count_here) {
+    // 64-bit sum of the tiles before this one
+    __shared__ unsigned long long w64[kWaves];
+    unsigned long long a64 = 0;
+    if (partial)
+      for (uint32_t k = threadIdx.x; k < blockIdx.x; k += kThreads)
+        a64 += self_prefix ? (unsigned long long)partial[k] : (unsigned long long)T(partial[k + 1] - partial[k]);
+    unsigned long long tot64;
+    block_exclusive_scan(a64, w64, tot64);
+    if (threadIdx.x == 0) s_before64 = tot64;
     __syncthreads();
   }
   // padded index: one spare word every 32 to spread the strided reads over banks
@@ -118,7 +159,10 @@ __global__ __launch_bounds__(kThreads) void scan_apply_kernel(T *__restrict__ da
     uint64_t idx = base + li;
     if (idx < n) data[idx] = tile[pad(li)];
   }
-  if (blockIdx.x == n_tiles - 1 && threadIdx.x == 0) data[n] = off + total;
+  if (blockIdx.x == n_tiles - 1 && threadIdx.x == 0) {
+    data[n] = off + total;
+    if (count_here) write_count(co, s_before64 + (unsigned long long)total);
+  }
 }
 
 // ------------------------------------------------------------- radix sort
@@ -173,6 +217,8 @@ __global__ __launch_bounds__(kThreads) void rs_scatter_kernel(
     const uint32_t *__restrict__ n_dev, int shift, int nbits, const uint32_t *__restrict__ hist_scanned,
     uint32_t n_tiles, uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out) {
   const uint64_t n = pair_count(n_cap, n_dev);
+  // a tile past the device count (a grid sized for the capacity) moves nothing
+  if (uint64_t(blockIdx.x) * kTile >= n) return;
   constexpr int kBins = 1 << NB;
   __shared__ uint32_t cnt[kWaves][kBins];
   __shared__ uint32_t s_local[kBins];     // tile-local start of each digit's run
@@ -282,33 +328,12 @@ __global__ __launch_bounds__(kThreads) void rs_scatter_kernel(
 }
 
 template <typename T>
-__global__ void set_zero_kernel(T *p) { *p = T(0); }
-
-__global__ __launch_bounds__(64) void pair_count_kernel(const unsigned long long *__restrict__ total64, uint64_t cap,
-                                                       uint32_t *__restrict__ count, uint32_t *__restrict__ overflow) {
-  unsigned long long v = total64[threadIdx.x];
-#pragma unroll
-  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
-  if (threadIdx.x == 0) {
-    const bool over = v > cap;
-    count[0] = over ? 0u : uint32_t(v);
-    count[1] = over ? 1u : 0u;
-    if (over && overflow) {
-      overflow[0] = 1u;
-      atomicMax(overflow + 1, uint32_t(v < 0xffffffffull ? v : 0xffffffffull));
-    }
-  }
+__global__ void set_zero_kernel(T *p, CountOut co) {
+  *p = T(0);
+  if (co.count) write_count(co, 0ull);
 }
 
 }  // namespace
-
-int pair_count(const unsigned long long *total64, uint64_t cap, uint32_t *count, uint32_t *overflow,
-               hipStream_t s) {
-  static_assert(kTotalSlots == 64, "one wave sums the slots");
-  pair_count_kernel<<<1, 64, 0, s>>>(total64, cap, count, overflow);
-  FGS_LAUNCH_CHECK("pair_count_kernel");
-  return FGS_OK;
-}
 
 uint64_t scan_scratch_words(uint64_t n) {
   // in units of 64-bit words, enough for both element widths
@@ -323,16 +348,16 @@ uint64_t scan_scratch_words(uint64_t n) {
 }
 
 template <typename T>
-static int exclusive_scan(T *data, uint64_t n, T *scratch, hipStream_t s) {
+static int exclusive_scan(T *data, uint64_t n, T *scratch, hipStream_t s, CountOut co = CountOut{}) {
   if (n == 0) {
     // total of an empty array (a kernel, not a memset node, so the call can be captured)
-    set_zero_kernel<T><<<1, 1, 0, s>>>(data);
+    set_zero_kernel<T><<<1, 1, 0, s>>>(data, co);
     FGS_LAUNCH_CHECK("set_zero_kernel");
     return FGS_OK;
   }
   const uint64_t tiles = (n + kTile - 1) / kTile;
   if (tiles == 1) {
-    scan_apply_kernel<T><<<1, kThreads, 0, s>>>(data, n, nullptr, 1, 0);
+    scan_apply_kernel<T><<<1, kThreads, 0, s>>>(data, n, nullptr, 1, 0, co);
     FGS_LAUNCH_CHECK("scan_apply_kernel");
     return FGS_OK;
   }
@@ -348,13 +373,18 @@ static int exclusive_scan(T *data, uint64_t n, T *scratch, hipStream_t s) {
     int st = exclusive_scan<T>(partial, tiles, rest, s);
     if (st != FGS_OK) return st;
   }
-  scan_apply_kernel<T><<<unsigned(tiles), kThreads, 0, s>>>(data, n, partial, unsigned(tiles), self_prefix);
+  scan_apply_kernel<T><<<unsigned(tiles), kThreads, 0, s>>>(data, n, partial, unsigned(tiles), self_prefix, co);
   FGS_LAUNCH_CHECK("scan_apply_kernel");
   return FGS_OK;
 }
 
 int exclusive_scan_u32(uint32_t *data, uint64_t n, uint32_t *scratch, hipStream_t s) {
   return exclusive_scan<uint32_t>(data, n, scratch, s);
+}
+
+int scan_counts(uint32_t *count, uint64_t n, uint32_t *scratch, uint64_t cap, unsigned long long *total,
+                uint32_t *pairs, uint32_t *overflow, hipStream_t s) {
+  return exclusive_scan<uint32_t>(count, n, scratch, s, CountOut{cap, total, pairs, overflow});
 }
 
 int exclusive_scan_u64(uint64_t *data, uint64_t n, uint32_t *scratch, hipStream_t s) {

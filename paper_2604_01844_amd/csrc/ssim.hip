@@ -53,7 +53,8 @@ __global__ __launch_bounds__(kThreads) void ssim_stats_kernel(const float *__res
                                                               Window win, float c1, float c2,
                                                               float *__restrict__ g1, float *__restrict__ g2,
                                                               float *__restrict__ g3,
-                                                              float *__restrict__ partial) {
+                                                              float *__restrict__ partial,
+                                                              float *__restrict__ partial_l1) {
   __shared__ float sx[kH][kH + 1], sy[kH][kH + 1];
   __shared__ float hz[5][kH][kT + 1];
   __shared__ float sh[kThreads / 64];
@@ -83,7 +84,7 @@ __global__ __launch_bounds__(kThreads) void ssim_stats_kernel(const float *__res
     hz[0][r][c] = a; hz[1][r][c] = b; hz[2][r][c] = aa; hz[3][r][c] = bb; hz[4][r][c] = ab;
   }
   __syncthreads();
-  CompSum acc;
+  CompSum acc, acc1;
   for (int i = threadIdx.x; i < kT * kT; i += kThreads) {
     const int r = i / kT, c = i - r * kT;
     float m[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
@@ -101,6 +102,7 @@ __global__ __launch_bounds__(kThreads) void ssim_stats_kernel(const float *__res
     const float CD = C * D;
     const float S = A * B / CD;
     acc.add(1.f - S);
+    if (partial_l1) acc1.add(fabsf(sx[r + kR][c + kR] - sy[r + kR][c + kR]));
     const uint64_t q = off + uint64_t(gy) * W + gx;
     if (g1) {
       g1[q] = 2.f * my * (B - A) / CD - S * (2.f * mx / C - 2.f * mx / D);
@@ -108,9 +110,14 @@ __global__ __launch_bounds__(kThreads) void ssim_stats_kernel(const float *__res
       g3[q] = 2.f * A / CD;
     }
   }
+  const uint64_t blk = (uint64_t(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
   const float t = block_sum_f32<kThreads>(acc.value(), sh);
-  if (threadIdx.x == 0)
-    partial[(uint64_t(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = t;
+  if (threadIdx.x == 0) partial[blk] = t;
+  if (partial_l1) {
+    __shared__ float sh1[kThreads / 64];  // its own: thread 0 may still read sh
+    const float t1 = block_sum_f32<kThreads>(acc1.value(), sh1);
+    if (threadIdx.x == 0) partial_l1[blk] = t1;
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void ssim_grad_kernel(const float *__restrict__ img,
@@ -118,7 +125,8 @@ __global__ __launch_bounds__(kThreads) void ssim_grad_kernel(const float *__rest
                                                              Window win, const float *__restrict__ g1,
                                                              const float *__restrict__ g2,
                                                              const float *__restrict__ g3, float coef,
-                                                             int accumulate, float *__restrict__ grad) {
+                                                             int accumulate, float l1_inv_p,
+                                                             float *__restrict__ grad) {
   __shared__ float sg[3][kH][kH + 1];
   __shared__ float hz[3][kH][kT + 1];
   const int x0 = blockIdx.x * kT, y0 = blockIdx.y * kT, v = blockIdx.z;
@@ -154,8 +162,16 @@ __global__ __launch_bounds__(kThreads) void ssim_grad_kernel(const float *__rest
 #pragma unroll
       for (int j = 0; j < 3; ++j) a[j] = fmaf(win.w[k], hz[j][r + k][c], a[j]);
     const uint64_t q = off + uint64_t(gy) * W + gx;
-    const float gq = coef * (a[0] + 2.f * img[q] * a[1] + gt[q] * a[2]);
-    grad[q] = accumulate ? grad[q] + gq : gq;
+    const float xq = img[q], yq = gt[q];
+    // what the gradient is added to: the image already there, the L1
+    // term's sign(x - y) / n_per_view (l1_inv_p > 0; the value the L1
+    // kernel writes), or nothing; one rounding in every case
+    float base = accumulate ? grad[q] : 0.f;
+    if (l1_inv_p > 0.f) {
+      const float d = xq - yq;
+      base = (d > 0.f) ? l1_inv_p : ((d < 0.f) ? -l1_inv_p : 0.f);
+    }
+    grad[q] = fmaf(coef, a[0] + 2.f * xq * a[1] + yq * a[2], base);
   }
 }
 
@@ -171,6 +187,25 @@ __global__ __launch_bounds__(kThreads) void ssim_finish_kernel(const float *__re
 }
 
 }  // namespace
+
+uint64_t ssim_tiles(int32_t W, int32_t H) {
+  return uint64_t((W + kT - 1) / kT) * uint64_t((H + kT - 1) / kT);
+}
+
+int ssim_l1_partials(const float *img, const float *gt, int32_t W, int32_t H, float c1, float c2, float scale,
+                     float l1_inv_p, float *grad, float *gmaps, float *part_ssim, float *part_l1, hipStream_t s) {
+  const uint64_t n = uint64_t(W) * uint64_t(H);
+  const dim3 grid(unsigned((W + kT - 1) / kT), unsigned((H + kT - 1) / kT), 1u);
+  const Window win = gaussian_window();
+  ssim_stats_kernel<<<grid, kThreads, 0, s>>>(img, gt, W, H, win, c1, c2, gmaps, gmaps + n, gmaps + 2 * n,
+                                              part_ssim, part_l1);
+  FGS_LAUNCH_CHECK("ssim_stats_kernel");
+  ssim_grad_kernel<<<grid, kThreads, 0, s>>>(img, gt, W, H, win, gmaps, gmaps + n, gmaps + 2 * n,
+                                             float(-double(scale) / double(n)), 0, l1_inv_p, grad);
+  FGS_LAUNCH_CHECK("ssim_grad_kernel");
+  return FGS_OK;
+}
+
 }  // namespace fgs
 
 using namespace fgs;
@@ -198,13 +233,13 @@ extern "C" int fgs_ssim_loss_grad(const float *img, const float *gt, int32_t W, 
   float *g3 = grad ? g2 + n : nullptr;
   const Window win = gaussian_window();
   hipStream_t s = static_cast<hipStream_t>(stream);
-  ssim_stats_kernel<<<grid, kThreads, 0, s>>>(img, gt, W, H, win, c1, c2, g1, g2, g3, partial);
+  ssim_stats_kernel<<<grid, kThreads, 0, s>>>(img, gt, W, H, win, c1, c2, g1, g2, g3, partial, nullptr);
   FGS_LAUNCH_CHECK("ssim_stats_kernel");
   ssim_finish_kernel<<<1, kThreads, 0, s>>>(partial, int(nb), float(double(scale) / double(n)), loss);
   FGS_LAUNCH_CHECK("ssim_finish_kernel");
   if (grad) {
     ssim_grad_kernel<<<grid, kThreads, 0, s>>>(img, gt, W, H, win, g1, g2, g3, float(-double(scale) / double(n)),
-                                               accumulate, grad);
+                                               accumulate, 0.f, grad);
     FGS_LAUNCH_CHECK("ssim_grad_kernel");
   }
   return FGS_OK;

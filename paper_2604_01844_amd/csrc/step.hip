@@ -15,6 +15,7 @@
 // (fgs_step_graph_capture) and replayed for every later step of that view
 // (fgs_step_graph_launch): the replay runs the same kernels on the same
 // values as the direct call, and saves the per-kernel launch cost.
+#include <algorithm>
 #include <cmath>
 #include <new>
 
@@ -46,8 +47,31 @@ struct AdamGroups {
   float lr[4];
 };
 
+// The loss terms of the step (L1, SSIM, TV): out[k] = scale[k] * the sum of
+// part[k]'s nb[k] per-block partial sums, for the terms with a non-null part.
+struct LossFinish {
+  const float *part[3];
+  int nb[3];
+  float scale[3];
+  float *out;
+};
+
+// Blocks (x, 0..10) run Adam; in the extra row, block k < 3 adds up loss
+// term k (their values are for reporting; nothing in the step reads them).
+constexpr int kAdamRows = 11;
+
 __global__ __launch_bounds__(256) void adam_groups_kernel(AdamGroups A, uint64_t n, float b1, float b2, float eps,
-                                                          const float *__restrict__ blk) {
+                                                          const float *__restrict__ blk, LossFinish F) {
+  if (blockIdx.y == kAdamRows) {
+    const int k = int(blockIdx.x);
+    if (k >= 3 || !F.part[k]) return;
+    __shared__ float sh[256 / 64];
+    CompSum acc;
+    for (int i = threadIdx.x; i < F.nb[k]; i += 256) acc.add(F.part[k][i]);
+    const float t = block_sum_f32<256>(acc.value(), sh);
+    if (threadIdx.x == 0) F.out[k] = F.scale[k] * t;
+    return;
+  }
   const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float c1 = blk[3], c2 = blk[4];
@@ -82,6 +106,26 @@ struct StepArgs {
   fgs_workspace *ws_proj, *ws_crop, *ws_loss;
 };
 
+// The loss workspace of a step, in floats: the SSIM term's partial sums
+// (one per 16 x 16 tile), the L1 term's (per tile with SSIM, else per
+// reduction block), the TV term's, then the SSIM gradient's three maps.
+struct LossParts {
+  uint64_t ssim, l1, tv, gmaps, total, n_tiles;
+};
+
+LossParts loss_parts(const StepArgs &a) {
+  LossParts P{};
+  const uint64_t n_pix = uint64_t(a.geom->det_w) * uint64_t(a.geom->det_h);
+  P.n_tiles = ssim_tiles(a.geom->det_w, a.geom->det_h);
+  auto up = [](uint64_t x) { return (x + 63) / 64 * 64; };  // 256-byte steps
+  P.ssim = 0;
+  P.l1 = up(P.n_tiles);
+  P.tv = P.l1 + up(std::max<uint64_t>(P.n_tiles, kLossBlocks));
+  P.gmaps = P.tv + up(kLossBlocks);
+  P.total = P.gmaps + (a.sp->ssim_weight > 0.f ? 3 * n_pix : 0);
+  return P;
+}
+
 int check_args(const StepArgs &a) {
   if (!a.params || !a.m || !a.v || !a.grad || !a.geom || !a.gt || !a.opts || !a.sp || !a.buf || !a.ws_proj ||
       !a.ws_loss)
@@ -99,6 +143,12 @@ int check_args(const StepArgs &a) {
   if (tv && (!a.ws_crop || !a.buf->crop_vol || !a.buf->crop_grad))
     return fail(FGS_E_INVALID, "crop without buffers");
   if (a.opts->events) return fail(FGS_E_INVALID, "timing events are not taken by the step");
+  if (a.geom->det_w <= 0 || a.geom->det_h <= 0) return fail(FGS_E_INVALID, "detector size");
+  const LossParts LP = loss_parts(a);
+  a.ws_loss->needed = LP.total * sizeof(float);
+  if (!a.ws_loss->ptr || a.ws_loss->bytes < a.ws_loss->needed)
+    return fail(FGS_E_CAPACITY, "loss workspace too small");
+  a.ws_loss->kind = 0;
   return FGS_OK;
 }
 
@@ -125,13 +175,28 @@ int step_body(const StepArgs &a, hipStream_t s) {
   of.accumulate = 0;
   int st = fgs_project_views_fwd(&g, a.geom, a.view, 1, &of, buf->img, a.ws_proj, stream);
   if (st != FGS_OK) return st;
-  st = fgs_l1_loss_grad(buf->img, a.gt, n_pix, 1, buf->loss, buf->grad_img, a.ws_loss, stream);
-  if (st != FGS_OK) return st;
+  // the L1 term's gradient sign(x - y) / n_pix, with the SSIM term's added
+  // in the same kernel; the terms' partial sums wait for the Adam launch
+  const LossParts LP = loss_parts(a);
+  float *lp = static_cast<float *>(a.ws_loss->ptr);
+  LossFinish F{};
+  F.out = buf->loss;
+  const float inv_p = 1.f / float(n_pix);
   if (sp->ssim_weight > 0.f) {
-    st = fgs_ssim_loss_grad(buf->img, a.gt, a.geom->det_w, a.geom->det_h, 1, sp->ssim_c1, sp->ssim_c2,
-                            sp->ssim_weight, buf->loss + 1, buf->grad_img, 1, a.ws_loss, stream);
+    st = ssim_l1_partials(buf->img, a.gt, a.geom->det_w, a.geom->det_h, sp->ssim_c1, sp->ssim_c2, sp->ssim_weight,
+                          inv_p, buf->grad_img, lp + LP.gmaps, lp + LP.ssim, lp + LP.l1, s);
     if (st != FGS_OK) return st;
+    F.part[1] = lp + LP.ssim;
+    F.nb[1] = int(LP.n_tiles);
+    F.scale[1] = float(double(sp->ssim_weight) / double(n_pix));
+    F.nb[0] = int(LP.n_tiles);
+  } else {
+    st = l1_partials(buf->img, a.gt, uint64_t(n_pix), inv_p, buf->grad_img, lp + LP.l1, s);
+    if (st != FGS_OK) return st;
+    F.nb[0] = loss_blocks(uint64_t(n_pix));
   }
+  F.part[0] = lp + LP.l1;
+  F.scale[0] = float(1.0 / double(n_pix));
   // 3. backward over the forward's lists
   fgs_opts ob = of;
   ob.recompute = 0;
@@ -146,9 +211,12 @@ int step_body(const StepArgs &a, hipStream_t s) {
     ov.recompute = 1;
     st = vox_forward(&g, a.crop, &ov, buf->crop_vol, a.ws_crop, s, buf->params);
     if (st != FGS_OK) return st;
-    st = fgs_tv_loss_grad(buf->crop_vol, a.crop->dims, sp->tv_weight, buf->loss + 2, buf->crop_grad, a.ws_loss,
-                          stream);
+    st = tv_partials(buf->crop_vol, a.crop->dims, sp->tv_weight, buf->crop_grad, lp + LP.tv, s);
     if (st != FGS_OK) return st;
+    const uint64_t nc = uint64_t(a.crop->dims[0]) * a.crop->dims[1] * a.crop->dims[2];
+    F.part[2] = lp + LP.tv;
+    F.nb[2] = loss_blocks(nc);
+    F.scale[2] = float(double(sp->tv_weight) / double(nc));
     ov.recompute = 0;
     ov.accumulate = 1;
     st = vox_backward(&g, a.crop, &ov, buf->crop_grad, a.grad, a.ws_crop, s, buf->params);
@@ -167,8 +235,8 @@ int step_body(const StepArgs &a, hipStream_t s) {
     A.v[k] = V[k];
     A.lr[k] = sp->lr[k];
   }
-  adam_groups_kernel<<<dim3(grid_for(uint64_t(a.n), 256), 11), 256, 0, s>>>(A, uint64_t(a.n), sp->beta1,
-                                                                            sp->beta2, sp->eps, buf->params);
+  adam_groups_kernel<<<dim3(std::max(grid_for(uint64_t(a.n), 256), 3u), kAdamRows + 1), 256, 0, s>>>(
+      A, uint64_t(a.n), sp->beta1, sp->beta2, sp->eps, buf->params, F);
   FGS_LAUNCH_CHECK("adam_groups_kernel");
   return FGS_OK;
 }

@@ -219,7 +219,6 @@ __global__ __launch_bounds__(256) void vox_count_kernel(int64_t n, const float4 
                                                         const float4 *__restrict__ a1,
                                                         const Rect3 *__restrict__ rect, float thr_widen,
                                                         uint32_t *__restrict__ count,
-                                                        unsigned long long *__restrict__ total64,
                                                         unsigned long long *__restrict__ hits) {
   const int64_t i = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -237,10 +236,7 @@ __global__ __launch_bounds__(256) void vox_count_kernel(int64_t n, const float4 
     cnt += __popcll(bal);
     if (lane == 0 && nt <= 64u * kHitWords) hits[uint64_t(i) * kHitWords + j0 / 64] = bal;
   }
-  if (lane == 0) {
-    count[i] = cnt;
-    if (cnt) atomicAdd(total64 + (uint64_t(i) & (kTotalSlots - 1)), (unsigned long long)cnt);
-  }
+  if (lane == 0) count[i] = cnt;
 }
 
 // One wave per Gaussian: the keys of the tiles its support reaches, in
@@ -643,7 +639,7 @@ VoxLayout vox_layout(uint64_t N, uint64_t T, uint64_t K) {
   L.T = T;
   L.K = K;
   Carver c(nullptr);
-  c.take<unsigned long long>(kTotalSlots, &L.total64);
+  c.take<unsigned long long>(1, &L.total64);
   c.take<uint32_t>(4, &L.kdev);
   c.take<float4>(N, &L.prho);
   c.take<float4>(N, &L.radii);
@@ -730,8 +726,6 @@ int vox_build(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *o, f
   }
   void *b = ws->ptr;
   unsigned long long *total64 = at<unsigned long long>(b, L.total64);
-  zero_u64_kernel<<<1, kTotalSlots, 0, s>>>(total64, kTotalSlots);
-  FGS_LAUNCH_CHECK("zero_u64_kernel");
   vox_record_kernel<<<grid_for(N, 256), 256, 0, s>>>(*g, G, at<float4>(b, L.prho), at<float4>(b, L.a0),
                                                       at<float4>(b, L.a1), at<float4>(b, L.radii),
                                                       at<Rect3>(b, L.rect));
@@ -739,18 +733,18 @@ int vox_build(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *o, f
   const float thr_widen = -0.5f * kLog2e * o->kappa * o->kappa * (kCullSlack - 1.f);
   vox_count_kernel<<<grid_for(N, 4), 256, 0, s>>>(int64_t(N), at<float4>(b, L.prho), at<float4>(b, L.a0),
                                                    at<float4>(b, L.a1), at<Rect3>(b, L.rect), thr_widen,
-                                                   at<uint32_t>(b, L.offset), total64,
-                                                   at<unsigned long long>(b, L.hits));
+                                                   at<uint32_t>(b, L.offset), at<unsigned long long>(b, L.hits));
   FGS_LAUNCH_CHECK("vox_count_kernel");
-  int st = exclusive_scan_u32(at<uint32_t>(b, L.offset), N, at<uint32_t>(b, L.scan_scratch), s);
-  if (st != FGS_OK) return st;
+  // offsets, the 64-bit pair total and the device pair count (0 past the
+  // capacity) in one scan
   uint32_t *kdev = at<uint32_t>(b, L.kdev);
+  int st = scan_counts(at<uint32_t>(b, L.offset), N, at<uint32_t>(b, L.scan_scratch),
+                       cap > 0 ? cap : uint64_t(0xfffffffeull), total64, kdev, cap > 0 ? ws->overflow : nullptr, s);
+  if (st != FGS_OK) return st;
   if (cap == 0) {
-    unsigned long long slots[kTotalSlots];
-    FGS_HIP(hipMemcpyAsync(slots, total64, sizeof(slots), hipMemcpyDeviceToHost, s));
-    FGS_HIP(hipStreamSynchronize(s));
     unsigned long long K64 = 0;
-    for (int i = 0; i < kTotalSlots; ++i) K64 += slots[i];
+    FGS_HIP(hipMemcpyAsync(&K64, total64, sizeof(K64), hipMemcpyDeviceToHost, s));
+    FGS_HIP(hipStreamSynchronize(s));
     if (K64 >= 0xffffffffull)
       return fail(FGS_E_UNSUPPORTED, "more than 2^32 (tile, Gaussian) pairs; split the grid into slabs");
     const uint64_t K = K64;
@@ -761,8 +755,6 @@ int vox_build(const fgs_gaussians *g, const fgs_grid *grid, const fgs_opts *o, f
     ws->n_tiles = T;
     if (ws->bytes < L.total + extra_bytes) return fail(FGS_E_CAPACITY, "workspace too small for the tile lists");
   }
-  st = pair_count(total64, cap > 0 ? cap : L.K, kdev, cap > 0 ? ws->overflow : nullptr, s);
-  if (st != FGS_OK) return st;
   const uint64_t K = L.K;
   if (K > 0) {
     vox_emit_kernel<<<grid_for(N, 4), 256, 0, s>>>(int64_t(N), G.nt[0], G.nt[1], at<float4>(b, L.prho),

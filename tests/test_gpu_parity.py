@@ -262,6 +262,7 @@ def test_binning_ranges_across_sizes(fgs, n, w, h, views, seed):
         v, tt = divmod(t, tpv)
         lo, hi = rng[t]
         assert 0 <= lo <= hi <= d["n_pairs"]
+        assert hi > lo or lo == 0, t      # a tile without keys holds (0, 0)
         covered += hi - lo
         assert np.all(skeys[lo:hi] == (v << tb) | tt)
         gl = d["sorted_vals"][lo:hi].astype(np.int64)
@@ -486,21 +487,32 @@ def _ragged_27_tiles():
     return si.gaussians(4500, 70), dict(origin=(-0.2, 0.05, -0.1), spacing=(0.011, 0.009, 0.013), dims=(20, 24, 17))
 
 
+def _wide_64_tiles():
+    # 64 tiles over most of the volume: about 15 k keys (four sort tiles of
+    # 4096, the last ragged)
+    return si.gaussians(6000, 73), dict(origin=(-0.45, -0.43, -0.44), spacing=(0.025,) * 3, dims=(32, 32, 31))
+
+
+def _wide_64_tiles_dense():
+    # about 35 k keys over 64 tiles
+    return si.gaussians(14000, 74), dict(origin=(-0.45, -0.43, -0.44), spacing=(0.025,) * 3, dims=(32, 32, 31))
+
+
 _VOX_CASES = dict(mixed_boxes=_mixed_boxes, ragged_crop=_ragged_crop, clear_of_thresholds=_clear_of_thresholds,
-                  crop_64_tiles=_crop_64_tiles, ragged_27_tiles=_ragged_27_tiles)
+                  crop_64_tiles=_crop_64_tiles, ragged_27_tiles=_ragged_27_tiles, wide_64_tiles=_wide_64_tiles)
 
 
-@pytest.mark.parametrize("case", ["crop_64_tiles", "ragged_27_tiles"])
+@pytest.mark.parametrize("case", ["crop_64_tiles", "ragged_27_tiles", "wide_64_tiles", "wide_64_tiles_dense"])
 def test_voxelize_small_grids(fgs, case):
     """Grids of at most 64 tiles (a 6-bit sort, lists split into 16 chunks
     per tile): volume and gradients against the oracle, and the stored
     lists' backward equal to the recomputed one."""
-    gs, gr = _VOX_CASES[case]()
+    gs, gr = (_wide_64_tiles_dense if case == "wide_64_tiles_dense" else _VOX_CASES[case])()
     t = dev(gs)
     grid = fgs.Grid.from_dict(gr)
     ws = fgs.Workspace(DEV)
     vol = fgs.voxelize(*args(t), grid, ws=ws)
-    assert ws.n_pairs > 1000
+    assert ws.n_pairs > dict(wide_64_tiles=12000, wide_64_tiles_dense=24576).get(case, 1000)
     assert rel(vol.cpu().numpy(), oracle.voxelize(gs, gr)) < TOL
     nz, ny, nx = gr["dims"][2], gr["dims"][1], gr["dims"][0]
     c = si.normals((nz, ny, nx), 71)

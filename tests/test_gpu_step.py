@@ -61,15 +61,20 @@ def test_native_step_equals_separate_calls(fgs, ssim, tv_weight, graphs):
     img = torch.empty((1, geom.det_h, geom.det_w), device=DEV)
     for v in views:
         fgs.project_views(*b.params, geom, v, 1, ws=ws_p, out=img)
-        _, g = fgs.l1_loss_grad(img, gt[v:v + 1], ws=ws_l)
+        l1, g = fgs.l1_loss_grad(img, gt[v:v + 1], ws=ws_l)
+        losses = [float(l1)]
         if ssim:
-            fgs.ssim_loss_grad(img, gt[v:v + 1], scale=ssim, ws=ws_s, grad=g, accumulate=True)
+            ls, _ = fgs.ssim_loss_grad(img, gt[v:v + 1], scale=ssim, ws=ws_s, grad=g, accumulate=True)
+            losses.append(float(ls))
         fgs.project_views_backward(*b.params, geom, g, v, 1, recompute=False, ws=ws_p, out=b.grads)
         if tv_b is not None:
-            tv_b.add_grad(b.params, b.grads, rng_b)
+            losses.append(float(tv_b.add_grad(b.params, b.grads, rng_b)))
         b.adam(adam)
     torch.cuda.synchronize()
     assert step.check_overflow() == 0
+    # the last step's loss terms: the same sums, added up in another order
+    got = step.loss.cpu().numpy()[:len(losses)]
+    np.testing.assert_allclose(got, losses, rtol=2e-5, atol=0)
     for name, xa, xb in (("params", a.params, b.params), ("m", a.m, b.m), ("v", a.v, b.v),
                          ("grads", a.grads, b.grads)):
         for k, (ta, tb) in enumerate(zip(xa, xb)):
