@@ -325,10 +325,11 @@ __device__ __forceinline__ uint32_t list_key(uint32_t w, int record_bits, int ti
 // Every tile's range [x, y) of the sorted list, (0, 0) for a tile without
 // keys. The list is in (tile, view) order (the sort is on the tile field and
 // stable, and records ascend with the view), so a key's rank in that order
-// is tile * V + view for V = T / tpv views. The grid clears the tiles of the
-// ranks before the first key's and after the last key's (all T with no keys
-// on the device); the first key of each run clears those of the ranks
-// between the previous run's and its own.
+// is tile * V + view for V = T / tpv views. The wave holding the first key
+// clears the tiles of the ranks before it, the wave holding the last key
+// those after it (the grid clears all T when the device holds no keys), and
+// the first key of each run those of the ranks between the previous run's
+// and its own.
 __device__ __forceinline__ uint32_t rank_tile(uint32_t q, uint32_t V, uint32_t tpv) {
   const uint32_t tt = V == 1u ? q : q / V;
   return (q - tt * V) * tpv + tt;
@@ -339,25 +340,13 @@ __global__ __launch_bounds__(256) void ranges_kernel(const uint32_t *__restrict_
                                                      uint32_t tpv, int record_bits, uint32_t n, uint64_t T,
                                                      uint2 *__restrict__ rng) {
   const uint64_t K = min(K_cap, uint64_t(kdev[0]));
+  if (K == 0) {
+    for (uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < T; t += uint64_t(gridDim.x) * blockDim.x)
+      rng[t] = make_uint2(0u, 0u);
+    return;
+  }
   const uint32_t V = uint32_t(T / tpv);
   const uint32_t tmask = (1u << tile_bits) - 1u;
-  {
-    uint32_t lo = uint32_t(T), hi = uint32_t(T);  // ranks [0, lo) and [hi, T) have no keys
-    if (K > 0) {
-      uint32_t f = skeys[0], l = skeys[K - 1];
-      if (record_bits) {
-        f = list_key(f, record_bits, tile_bits, n);
-        l = list_key(l, record_bits, tile_bits, n);
-      }
-      lo = (f & tmask) * V + (f >> tile_bits);
-      hi = (l & tmask) * V + (l >> tile_bits) + 1u;
-    }
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < lo; q += stride)
-      rng[rank_tile(q, V, tpv)] = make_uint2(0u, 0u);
-    for (uint32_t q = hi + blockIdx.x * blockDim.x + threadIdx.x; q < uint32_t(T); q += stride)
-      rng[rank_tile(q, V, tpv)] = make_uint2(0u, 0u);
-  }
   const int lane = threadIdx.x & (kWave - 1);
   const uint64_t base = ((uint64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6) * uint64_t(kWave * kRangeItems);
   if (base >= K) return;  // uniform over the wave
@@ -375,6 +364,22 @@ __global__ __launch_bounds__(256) void ranges_kernel(const uint32_t *__restrict_
     for (int j = 0; j < kRangeItems; ++j) key[j] = list_key(key[j], record_bits, tile_bits, n);
     edge_prev = list_key(edge_prev, record_bits, tile_bits, n);
     edge_next = list_key(edge_next, record_bits, tile_bits, n);
+  }
+  // the wave of the first key clears the ranks before it, the wave of the
+  // last key those after it
+  if (base == 0) {
+    const uint32_t f = uint32_t(__builtin_amdgcn_readfirstlane(int(key[0])));
+    const uint32_t lo = (f & tmask) * V + (f >> tile_bits);
+    for (uint32_t q = uint32_t(lane); q < lo; q += kWave) rng[rank_tile(q, V, tpv)] = make_uint2(0u, 0u);
+  }
+  if (K - 1 - base < uint64_t(kWave * kRangeItems)) {
+    const int jl = int((K - 1 - base) / kWave), ll = int((K - 1 - base) % kWave);
+    uint32_t l = 0;
+#pragma unroll
+    for (int j = 0; j < kRangeItems; ++j)
+      if (j == jl) l = uint32_t(__builtin_amdgcn_readlane(int(key[j]), ll));
+    const uint32_t hi = (l & tmask) * V + (l >> tile_bits) + 1u;
+    for (uint32_t q = hi + uint32_t(lane); q < uint32_t(T); q += kWave) rng[rank_tile(q, V, tpv)] = make_uint2(0u, 0u);
   }
 #pragma unroll
   for (int j = 0; j < kRangeItems; ++j) {
