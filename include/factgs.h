@@ -312,6 +312,10 @@ typedef struct {
  * for the loss terms (with SSIM 12 bytes per pixel, plus 8 bytes per 16 x 16
  * detector tile and 8 KiB; ws_loss->needed gives the figure). With
  * key_capacity > 0 in ws_proj and ws_crop the step never waits for the GPU.
+ * With a crop, its voxelization and TV run on a second stream that the
+ * library keeps per device, forked from `stream` after the step's first
+ * kernel and joined back before the voxelizer backward (HIP events), so
+ * they overlap with the view's forward and backward.
  * The gradient is the one the separate calls give (fgs_l1_loss_grad, then
  * fgs_ssim_loss_grad accumulating, ...) bit for bit; the reported loss
  * terms are the same sums added up in another order (the L1 term per
@@ -333,7 +337,9 @@ int fgs_recon_step(fgs_gaussians_out *params, fgs_gaussian_grads *m, fgs_gaussia
  * fgs_step_graph_capture takes fgs_recon_step's arguments (all of them
  * fixed for the graph's life: buffers, workspaces and their capacities,
  * view, gt, the loss weights, learning rates and crop dims), records the
- * step on a private stream without running it, and returns a graph.
+ * step without running it (three graphs: the crop branch, the view's
+ * forward, loss and backward, and the voxelizer backward with Adam), and
+ * returns a handle.
  * Requires key_capacity > 0 in ws_proj and, with a crop, in ws_crop (a
  * captured step may not wait for the GPU). Errors as fgs_recon_step (on
  * FGS_E_CAPACITY grow the named workspace and capture again); no graph is
@@ -343,6 +349,10 @@ int fgs_recon_step(fgs_gaussians_out *params, fgs_gaussian_grads *m, fgs_gaussia
  * launch, nothing else is read from sp and crop (crop dims must equal the
  * captured ones). The result is the one fgs_recon_step gives with the same
  * values, bit for bit. Asynchronous; launches on one stream run in order.
+ * Like fgs_recon_step with a crop, it runs the crop branch on the library's
+ * second stream of the device (forked from and joined back into `stream`
+ * with events); steps issued from several host threads at once are
+ * serialised while they are enqueued.
  * fgs_step_graph_destroy frees the graph (NULL: no-op); it must not be
  * running. Graphs hold the device pointers they were captured with: free or
  * reallocate none of them (or change a workspace's capacity) while a graph

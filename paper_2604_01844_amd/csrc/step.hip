@@ -5,18 +5,22 @@
 //   measured view, gradient image -> rasterizer backward (lists reused) ->
 //   optionally a crop of the grid voxelized, its TV gradient and the
 //   voxelizer backward added in -> one Adam launch over all 11 N parameters.
+// The crop's voxelization and TV run on a second stream beside the view's
+// forward and backward (they share no data until the voxelizer backward).
 // With key_capacity set in both rasterizer and crop workspaces nothing in the
 // step waits for the GPU, so the host runs ahead.
 //
 // The values that change from step to step of one view (the crop's origin
 // and Adam's bias corrections) are written by one small kernel into a device
 // block (fgs_step_buffers.params) that the rest of the step reads. The rest
-// can therefore be captured once per view in a HIP graph
-// (fgs_step_graph_capture) and replayed for every later step of that view
-// (fgs_step_graph_launch): the replay runs the same kernels on the same
+// can therefore be captured once per view in HIP graphs (fgs_step_graph_capture:
+// the crop branch, the view branch and the tail, one graph each) and replayed
+// for every later step of that view (fgs_step_graph_launch, the crop branch
+// again on the second stream): the replay runs the same kernels on the same
 // values as the direct call, and saves the per-kernel launch cost.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <new>
 
 #include "fgs_internal.h"
@@ -161,68 +165,117 @@ StepVals step_vals(const StepArgs &a) {
   return s;
 }
 
-// Everything after the step block is written: reads the crop origin and the
-// bias corrections from buf->params.
-int step_body(const StepArgs &a, hipStream_t s) {
+// The crop branch of a step (its binning, voxelization and TV) depends on
+// nothing the view's forward and backward compute, so it runs on a second
+// stream: forked from the step's stream once the step block is written,
+// joined before the voxelizer backward adds into the gradient that the
+// rasterizer backward has written. Its kernels are small and latency-bound,
+// so they overlap with the view's.
+struct Side {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+
+int side_create(Side &x) {
+  if (!x.s) FGS_HIP(hipStreamCreateWithFlags(&x.s, hipStreamNonBlocking));
+  if (!x.fork) FGS_HIP(hipEventCreateWithFlags(&x.fork, hipEventDisableTiming));
+  if (!x.join) FGS_HIP(hipEventCreateWithFlags(&x.join, hipEventDisableTiming));
+  return FGS_OK;
+}
+
+// The loss terms' sums the Adam launch finishes (positions from the
+// arguments alone).
+LossFinish loss_finish(const StepArgs &a) {
+  const LossParts LP = loss_parts(a);
+  float *lp = static_cast<float *>(a.ws_loss->ptr);
+  const fgs_step_params *sp = a.sp;
+  const int64_t n_pix = int64_t(a.geom->det_w) * int64_t(a.geom->det_h);
+  LossFinish F{};
+  F.out = a.buf->loss;
+  F.part[0] = lp + LP.l1;
+  F.scale[0] = float(1.0 / double(n_pix));
+  if (sp->ssim_weight > 0.f) {
+    F.nb[0] = int(LP.n_tiles);
+    F.part[1] = lp + LP.ssim;
+    F.nb[1] = int(LP.n_tiles);
+    F.scale[1] = float(double(sp->ssim_weight) / double(n_pix));
+  } else {
+    F.nb[0] = loss_blocks(uint64_t(n_pix));
+  }
+  if (a.crop && sp->tv_weight > 0.f) {
+    const uint64_t nc = uint64_t(a.crop->dims[0]) * a.crop->dims[1] * a.crop->dims[2];
+    F.part[2] = lp + LP.tv;
+    F.nb[2] = loss_blocks(nc);
+    F.scale[2] = float(double(sp->tv_weight) / double(nc));
+  }
+  return F;
+}
+
+fgs_opts crop_opts(const StepArgs &a, int recompute, int accumulate) {
+  fgs_opts ov{};
+  ov.kappa = a.opts->kappa;
+  ov.near_plane = a.opts->near_plane;
+  ov.recompute = recompute;
+  ov.accumulate = accumulate;
+  return ov;
+}
+
+fgs_gaussians gauss(const StepArgs &a) {
+  return fgs_gaussians{a.n, a.params->mean, a.params->log_scale, a.params->quat, a.params->density};
+}
+
+// The crop branch: the crop voxelized at the block's origin and the TV
+// term's gradient and partial sums (the TV prior of Eq. 5).
+int crop_branch(const StepArgs &a, hipStream_t sc) {
+  const fgs_gaussians g = gauss(a);
+  const fgs_opts ov = crop_opts(a, 1, 0);
+  int st = vox_forward(&g, a.crop, &ov, a.buf->crop_vol, a.ws_crop, sc, a.buf->params);
+  if (st != FGS_OK) return st;
+  const LossParts LP = loss_parts(a);
+  float *lp = static_cast<float *>(a.ws_loss->ptr);
+  return tv_partials(a.buf->crop_vol, a.crop->dims, a.sp->tv_weight, a.buf->crop_grad, lp + LP.tv, sc);
+}
+
+// The view branch: forward of the view, the loss of Eq. 5 (the L1 term's
+// gradient sign(x - y) / n_pix, with the SSIM term's added in the same
+// kernel; the terms' partial sums wait for the Adam launch), backward over
+// the forward's lists (writing the gradient).
+int view_branch(const StepArgs &a, hipStream_t s) {
   void *stream = static_cast<void *>(s);
   const fgs_step_params *sp = a.sp;
   const fgs_step_buffers *buf = a.buf;
-  const fgs_gaussians g{a.n, a.params->mean, a.params->log_scale, a.params->quat, a.params->density};
+  const fgs_gaussians g = gauss(a);
   const int64_t n_pix = int64_t(a.geom->det_w) * int64_t(a.geom->det_h);
-  // 1. forward of the view, 2. the loss of Eq. 5 and its gradient image
+  const LossParts LP = loss_parts(a);
+  float *lp = static_cast<float *>(a.ws_loss->ptr);
   fgs_opts of = *a.opts;
   of.recompute = 1;
   of.accumulate = 0;
   int st = fgs_project_views_fwd(&g, a.geom, a.view, 1, &of, buf->img, a.ws_proj, stream);
   if (st != FGS_OK) return st;
-  // the L1 term's gradient sign(x - y) / n_pix, with the SSIM term's added
-  // in the same kernel; the terms' partial sums wait for the Adam launch
-  const LossParts LP = loss_parts(a);
-  float *lp = static_cast<float *>(a.ws_loss->ptr);
-  LossFinish F{};
-  F.out = buf->loss;
   const float inv_p = 1.f / float(n_pix);
-  if (sp->ssim_weight > 0.f) {
+  if (sp->ssim_weight > 0.f)
     st = ssim_l1_partials(buf->img, a.gt, a.geom->det_w, a.geom->det_h, sp->ssim_c1, sp->ssim_c2, sp->ssim_weight,
                           inv_p, buf->grad_img, lp + LP.gmaps, lp + LP.ssim, lp + LP.l1, s);
-    if (st != FGS_OK) return st;
-    F.part[1] = lp + LP.ssim;
-    F.nb[1] = int(LP.n_tiles);
-    F.scale[1] = float(double(sp->ssim_weight) / double(n_pix));
-    F.nb[0] = int(LP.n_tiles);
-  } else {
+  else
     st = l1_partials(buf->img, a.gt, uint64_t(n_pix), inv_p, buf->grad_img, lp + LP.l1, s);
-    if (st != FGS_OK) return st;
-    F.nb[0] = loss_blocks(uint64_t(n_pix));
-  }
-  F.part[0] = lp + LP.l1;
-  F.scale[0] = float(1.0 / double(n_pix));
-  // 3. backward over the forward's lists
+  if (st != FGS_OK) return st;
   fgs_opts ob = of;
   ob.recompute = 0;
-  st = fgs_project_views_bwd(&g, a.geom, a.view, 1, &ob, buf->grad_img, a.grad, a.ws_proj, stream);
-  if (st != FGS_OK) return st;
-  // 4. the crop's TV prior, its gradient added to the rasterizer's; the
-  // crop's origin is the block's
+  return fgs_project_views_bwd(&g, a.geom, a.view, 1, &ob, buf->grad_img, a.grad, a.ws_proj, stream);
+}
+
+// The tail: the TV gradient through the voxelizer backward, added to the
+// rasterizer's (after both branches), then Adam on all parameters in one
+// launch, which also finishes the loss terms.
+int tail(const StepArgs &a, hipStream_t s) {
+  const fgs_step_params *sp = a.sp;
+  const fgs_gaussians g = gauss(a);
   if (a.crop && sp->tv_weight > 0.f) {
-    fgs_opts ov{};
-    ov.kappa = a.opts->kappa;
-    ov.near_plane = a.opts->near_plane;
-    ov.recompute = 1;
-    st = vox_forward(&g, a.crop, &ov, buf->crop_vol, a.ws_crop, s, buf->params);
-    if (st != FGS_OK) return st;
-    st = tv_partials(buf->crop_vol, a.crop->dims, sp->tv_weight, buf->crop_grad, lp + LP.tv, s);
-    if (st != FGS_OK) return st;
-    const uint64_t nc = uint64_t(a.crop->dims[0]) * a.crop->dims[1] * a.crop->dims[2];
-    F.part[2] = lp + LP.tv;
-    F.nb[2] = loss_blocks(nc);
-    F.scale[2] = float(double(sp->tv_weight) / double(nc));
-    ov.recompute = 0;
-    ov.accumulate = 1;
-    st = vox_backward(&g, a.crop, &ov, buf->crop_grad, a.grad, a.ws_crop, s, buf->params);
+    const fgs_opts ov = crop_opts(a, 0, 1);
+    int st = vox_backward(&g, a.crop, &ov, a.buf->crop_grad, a.grad, a.ws_crop, s, a.buf->params);
     if (st != FGS_OK) return st;
   }
-  // 5. Adam on all parameters, one launch
   AdamGroups A;
   float *P[4] = {a.params->mean, a.params->log_scale, a.params->quat, a.params->density};
   const float *G[4] = {a.grad->mean, a.grad->log_scale, a.grad->quat, a.grad->density};
@@ -236,10 +289,55 @@ int step_body(const StepArgs &a, hipStream_t s) {
     A.lr[k] = sp->lr[k];
   }
   adam_groups_kernel<<<dim3(std::max(grid_for(uint64_t(a.n), 256), 3u), kAdamRows + 1), 256, 0, s>>>(
-      A, uint64_t(a.n), sp->beta1, sp->beta2, sp->eps, buf->params, F);
+      A, uint64_t(a.n), sp->beta1, sp->beta2, sp->eps, a.buf->params, loss_finish(a));
   FGS_LAUNCH_CHECK("adam_groups_kernel");
   return FGS_OK;
 }
+
+// Makes s wait for the crop branch when the step returns early (an error,
+// e.g. a workspace to grow) after forking it.
+struct JoinOnExit {
+  hipStream_t s;
+  const Side *side = nullptr;
+  ~JoinOnExit() {
+    if (side) (void)hipStreamWaitEvent(s, side->join, 0);
+  }
+};
+
+// Everything after the step block is written (it reads the crop origin and
+// the bias corrections from buf->params). side (may be null): the crop
+// branch's stream and events, else the crop runs in line on s.
+int step_body(const StepArgs &a, hipStream_t s, const Side *side) {
+  const bool tv = a.crop && a.sp->tv_weight > 0.f;
+  JoinOnExit join_on_exit{s};
+  if (tv) {
+    hipStream_t sc = s;
+    if (side) {
+      FGS_HIP(hipEventRecord(side->fork, s));
+      FGS_HIP(hipStreamWaitEvent(side->s, side->fork, 0));
+      sc = side->s;
+    }
+    const int st = crop_branch(a, sc);
+    if (side) {
+      FGS_HIP(hipEventRecord(side->join, side->s));
+      join_on_exit.side = side;  // until the tail waits for it
+    }
+    if (st != FGS_OK) return st;
+  }
+  int st = view_branch(a, s);
+  if (st != FGS_OK) return st;
+  if (tv && side) {
+    join_on_exit.side = nullptr;
+    FGS_HIP(hipStreamWaitEvent(s, side->join, 0));
+  }
+  return tail(a, s);
+}
+
+// Direct steps share one side stream per device; the lock covers a step's
+// enqueueing, so the fork and join events of concurrent callers do not mix.
+constexpr int kMaxDevices = 64;
+std::mutex g_side_mu;
+Side g_side[kMaxDevices];
 
 int set_params(float *blk, const StepVals &v, hipStream_t s) {
   set_step_params_kernel<<<1, 64, 0, s>>>(blk, v);
@@ -252,15 +350,74 @@ int set_params(float *blk, const StepVals &v, hipStream_t s) {
 
 using namespace fgs;
 
-// A captured step of one view: the instantiated graph of step_body and what
-// a launch must match.
+// A captured step of one view: the instantiated graphs of its crop branch
+// (null without a crop), its view branch and its tail, and what a launch
+// must match. A launch runs the crop branch on the side stream beside the
+// view branch, as a direct step does.
 struct fgs_step_graph {
-  hipGraphExec_t exec;
+  hipGraphExec_t crop;
+  hipGraphExec_t view_branch;
+  hipGraphExec_t tail;
   float *params;
   int32_t view;
   int32_t crop_dims[3];
   int has_crop;
 };
+
+namespace {
+
+// Records fn(stream) into an instantiated graph, on a private stream.
+template <typename Fn>
+int capture(Fn &&fn, hipGraphExec_t *out) {
+  *out = nullptr;
+  hipStream_t cs;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    return hip_fail(e, "hipStreamBeginCapture");
+  }
+  const int st = fn(cs);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(cs, &graph);
+  (void)hipStreamDestroy(cs);
+  if (st != FGS_OK || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    // a capture cut short leaves its error as the runtime's last error,
+    // which the next launch check would report
+    (void)hipGetLastError();
+    return st != FGS_OK ? st : hip_fail(e, "hipStreamEndCapture");
+  }
+  e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    *out = nullptr;
+    return hip_fail(e, "hipGraphInstantiate");
+  }
+  return FGS_OK;
+}
+
+void destroy_execs(fgs_step_graph &g) {
+  if (g.crop) (void)hipGraphExecDestroy(g.crop);
+  if (g.view_branch) (void)hipGraphExecDestroy(g.view_branch);
+  if (g.tail) (void)hipGraphExecDestroy(g.tail);
+  g.crop = g.view_branch = g.tail = nullptr;
+}
+
+// The calling device's shared side stream, created on first use; the
+// caller holds g_side_mu.
+int device_side(Side **out) {
+  int dev = -1;
+  FGS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(FGS_E_UNSUPPORTED, "device ordinal beyond 63");
+  const int st = side_create(g_side[dev]);
+  if (st != FGS_OK) return st;
+  *out = &g_side[dev];
+  return FGS_OK;
+}
+
+}  // namespace
 
 extern "C" int fgs_recon_step(fgs_gaussians_out *params, fgs_gaussian_grads *m, fgs_gaussian_grads *v,
                               fgs_gaussian_grads *grad, int64_t n, const fgs_geom *geom, int32_t view,
@@ -271,9 +428,17 @@ extern "C" int fgs_recon_step(fgs_gaussians_out *params, fgs_gaussian_grads *m, 
   int st = check_args(a);
   if (st != FGS_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool tv = crop && sp->tv_weight > 0.f;
+  std::unique_lock<std::mutex> lock(g_side_mu, std::defer_lock);
+  Side *side = nullptr;
+  if (tv) {
+    lock.lock();
+    st = device_side(&side);
+    if (st != FGS_OK) return st;
+  }
   st = set_params(buf->params, step_vals(a), s);
   if (st != FGS_OK) return st;
-  return step_body(a, s);
+  return step_body(a, s, side);
 }
 
 extern "C" int fgs_step_graph_capture(fgs_gaussians_out *params, fgs_gaussian_grads *m, fgs_gaussian_grads *v,
@@ -291,35 +456,19 @@ extern "C" int fgs_step_graph_capture(fgs_gaussians_out *params, fgs_gaussian_gr
   // a captured step may not wait for the GPU: both list sets need a fixed capacity
   if (ws_proj->key_capacity == 0 || (tv && ws_crop->key_capacity == 0))
     return fail(FGS_E_INVALID, "graph capture needs key_capacity set in the rasterizer and crop workspaces");
-  hipStream_t cs;
-  FGS_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-  if (e != hipSuccess) {
-    (void)hipStreamDestroy(cs);
-    return hip_fail(e, "hipStreamBeginCapture");
-  }
-  st = step_body(a, cs);
-  hipGraph_t graph = nullptr;
-  e = hipStreamEndCapture(cs, &graph);
-  (void)hipStreamDestroy(cs);
+  fgs_step_graph G{};
+  if (tv) st = capture([&](hipStream_t cs) { return crop_branch(a, cs); }, &G.crop);
+  if (st == FGS_OK) st = capture([&](hipStream_t cs) { return view_branch(a, cs); }, &G.view_branch);
+  if (st == FGS_OK) st = capture([&](hipStream_t cs) { return tail(a, cs); }, &G.tail);
   if (st != FGS_OK) {
-    if (graph) (void)hipGraphDestroy(graph);
+    destroy_execs(G);
     return st;
   }
-  if (e != hipSuccess) {
-    if (graph) (void)hipGraphDestroy(graph);
-    return hip_fail(e, "hipStreamEndCapture");
-  }
-  hipGraphExec_t exec = nullptr;
-  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(graph);
-  if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
-  fgs_step_graph *gph = new (std::nothrow) fgs_step_graph{};
+  fgs_step_graph *gph = new (std::nothrow) fgs_step_graph(G);
   if (!gph) {
-    (void)hipGraphExecDestroy(exec);
+    destroy_execs(G);
     return fail(FGS_E_INVALID, "out of host memory");
   }
-  gph->exec = exec;
   gph->params = buf->params;
   gph->view = view;
   gph->has_crop = tv ? 1 : 0;
@@ -342,15 +491,36 @@ extern "C" int fgs_step_graph_launch(fgs_step_graph *gph, const fgs_step_params 
   vals.v[3] = float(1.0 - std::pow(double(sp->beta1), double(sp->step)));
   vals.v[4] = float(1.0 - std::pow(double(sp->beta2), double(sp->step)));
   hipStream_t s = static_cast<hipStream_t>(stream);
+  std::unique_lock<std::mutex> lock(g_side_mu, std::defer_lock);
+  Side *side = nullptr;
+  if (gph->has_crop) {
+    lock.lock();
+    const int st = device_side(&side);
+    if (st != FGS_OK) return st;
+  }
   int st = set_params(gph->params, vals, s);
   if (st != FGS_OK) return st;
-  FGS_HIP(hipGraphLaunch(gph->exec, s));
+  if (side) {
+    FGS_HIP(hipEventRecord(side->fork, s));
+    FGS_HIP(hipStreamWaitEvent(side->s, side->fork, 0));
+    FGS_HIP(hipGraphLaunch(gph->crop, side->s));
+    FGS_HIP(hipEventRecord(side->join, side->s));
+  }
+  const hipError_t e = hipGraphLaunch(gph->view_branch, s);
+  if (side) FGS_HIP(hipStreamWaitEvent(s, side->join, 0));
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  FGS_HIP(hipGraphLaunch(gph->tail, s));
   return FGS_OK;
 }
 
 extern "C" int fgs_step_graph_destroy(fgs_step_graph *gph) {
   if (!gph) return FGS_OK;
-  hipError_t e = hipGraphExecDestroy(gph->exec);
+  hipError_t e = hipSuccess;
+  for (hipGraphExec_t x : {gph->crop, gph->view_branch, gph->tail})
+    if (x) {
+      const hipError_t ex = hipGraphExecDestroy(x);
+      if (e == hipSuccess) e = ex;
+    }
   delete gph;
   if (e != hipSuccess) return hip_fail(e, "hipGraphExecDestroy");
   return FGS_OK;

@@ -205,6 +205,34 @@ def test_graph_replays_equal_direct_steps(fgs):
     assert sa.check_overflow() == 0 and sb.check_overflow() == 0
 
 
+def test_graph_capture_after_workspace_growth(fgs):
+    """Captures that stop on a workspace to grow, first in the crop branch
+    (which runs on a second stream), then in the view's forward, leave no
+    error behind: the capture after the growth succeeds and its replays
+    equal direct steps bit for bit."""
+    from paper_2604_01844_amd import recon
+    gs, geom, grid, gt = _scene(fgs)
+    adam = recon.AdamConfig()
+    a, b = _model(fgs, gs), _model(fgs, gs)
+    sa = recon.ViewStep(a, geom, adam, ssim_weight=0.25, tv=recon.CropTV(grid, 0.05, 32, DEV), graphs=True)
+    sb = recon.ViewStep(b, geom, adam, ssim_weight=0.25, tv=recon.CropTV(grid, 0.05, 32, DEV), graphs=False)
+    for st in (sa, sb):
+        st.ws_proj.set_capacity(int(st.ws_proj.s.key_capacity) * 16)
+        st.ws_crop.set_capacity(int(st.ws_crop.s.key_capacity) * 16)
+    ra = np.random.Generator(np.random.PCG64(12))
+    rb = np.random.Generator(np.random.PCG64(12))
+    for k, v in enumerate([1, 4, 1]):
+        sa(v, gt[v], ra)
+        sb(v, gt[v], rb)
+        torch.cuda.synchronize()
+        for name, xa, xb in (("params", a.params, b.params), ("m", a.m, b.m), ("v", a.v, b.v),
+                             ("grads", a.grads, b.grads)):
+            for j, (ta, tb) in enumerate(zip(xa, xb)):
+                assert torch.equal(ta, tb), (k, v, name, j)
+    assert sorted(sa._graphs) == [1, 4]
+    assert sa.check_overflow() == 0 and sb.check_overflow() == 0
+
+
 def test_graph_capture_needs_fixed_capacity(fgs):
     """A captured step may not wait for the GPU: capture without key_capacity
     in the rasterizer workspace is refused before anything is recorded."""
