@@ -331,8 +331,8 @@ int fgs_recon_step(fgs_gaussians_out *params, fgs_gaussian_grads *m, fgs_gaussia
 
 /* The same step of one view captured in a HIP graph and replayed, for loops
  * that take many steps per view (400 epochs of 75 views in Sec. 4): a step
- * is then one small kernel (the per-call values into buf->params) and one
- * graph launch instead of about forty kernel launches.
+ * is then one small kernel (the per-call values into buf->params) and three
+ * graph launches instead of about thirty-five kernel launches.
  *
  * fgs_step_graph_capture takes fgs_recon_step's arguments (all of them
  * fixed for the graph's life: buffers, workspaces and their capacities,
