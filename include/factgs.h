@@ -309,13 +309,15 @@ typedef struct {
  * near plane, model, density_aabb_tau of the rasterizer (the crop's
  * voxelizer takes kappa only); opts->events must be NULL. Workspaces: the
  * rasterizer's (its lists are left there), the crop voxelizer's, and one
- * for the loss terms (with SSIM 12 bytes per pixel, plus 8 bytes per 16 x 16
- * detector tile and 8 KiB; ws_loss->needed gives the figure). With
+ * for the loss terms (with SSIM 12 bytes per pixel, with a crop 44 bytes per
+ * Gaussian for the crop's gradient, plus 8 bytes per 16 x 16 detector tile
+ * and 8 KiB; ws_loss->needed gives the figure). With
  * key_capacity > 0 in ws_proj and ws_crop the step never waits for the GPU.
- * With a crop, its voxelization and TV run on a second stream that the
- * library keeps per device, forked from `stream` after the step's first
- * kernel and joined back before the voxelizer backward (HIP events), so
- * they overlap with the view's forward and backward.
+ * With a crop, its voxelization, TV and voxelizer backward (into the loss
+ * workspace) run on a second stream that the library keeps per device,
+ * forked from `stream` after the step's first kernel and joined back before
+ * Adam (HIP events), so they overlap with the view's forward and backward;
+ * Adam adds the two gradients.
  * The gradient is the one the separate calls give (fgs_l1_loss_grad, then
  * fgs_ssim_loss_grad accumulating, ...) bit for bit; the reported loss
  * terms are the same sums added up in another order (the L1 term per
@@ -338,8 +340,7 @@ int fgs_recon_step(fgs_gaussians_out *params, fgs_gaussian_grads *m, fgs_gaussia
  * fixed for the graph's life: buffers, workspaces and their capacities,
  * view, gt, the loss weights, learning rates and crop dims), records the
  * step without running it (three graphs: the crop branch, the view's
- * forward, loss and backward, and the voxelizer backward with Adam), and
- * returns a handle.
+ * forward, loss and backward, and Adam), and returns a handle.
  * Requires key_capacity > 0 in ws_proj and, with a crop, in ws_crop (a
  * captured step may not wait for the GPU). Errors as fgs_recon_step (on
  * FGS_E_CAPACITY grow the named workspace and capture again); no graph is

@@ -5,8 +5,9 @@
 //   measured view, gradient image -> rasterizer backward (lists reused) ->
 //   optionally a crop of the grid voxelized, its TV gradient and the
 //   voxelizer backward added in -> one Adam launch over all 11 N parameters.
-// The crop's voxelization and TV run on a second stream beside the view's
-// forward and backward (they share no data until the voxelizer backward).
+// The crop's voxelization, TV and voxelizer backward (into a gradient of
+// its own) run on a second stream beside the view's forward and backward;
+// Adam adds the two gradients.
 // With key_capacity set in both rasterizer and crop workspaces nothing in the
 // step waits for the GPU, so the host runs ahead.
 //
@@ -44,9 +45,12 @@ __global__ void set_step_params_kernel(float *__restrict__ blk, StepVals s) {
 // density rows of n values); density is clamped at zero. The arithmetic is
 // that of fgs_adam_step, so the result is the same bit for bit. The bias
 // corrections are read from the step block.
+// g2 (may be null): a second gradient, added to g (g + g2, written back to
+// g: the step's gradient) before the update.
 struct AdamGroups {
   float *p[4];
-  const float *g[4];
+  float *g[4];
+  const float *g2[4];
   float *m[4], *v[4];
   float lr[4];
 };
@@ -83,7 +87,11 @@ __global__ __launch_bounds__(256) void adam_groups_kernel(AdamGroups A, uint64_t
   const int grp = row < 3 ? 0 : (row < 6 ? 1 : (row < 10 ? 2 : 3));
   const int first = grp == 0 ? 0 : (grp == 1 ? 3 : (grp == 2 ? 6 : 10));
   const uint64_t j = uint64_t(row - first) * n + i;
-  const float gi = A.g[grp][j];
+  float gi = A.g[grp][j];
+  if (A.g2[grp]) {
+    gi = gi + A.g2[grp][j];
+    A.g[grp][j] = gi;
+  }
   float *m = A.m[grp], *v = A.v[grp], *p = A.p[grp];
   const float mi = b1 * m[j] + (1.f - b1) * gi;
   const float vi = b2 * v[j] + (1.f - b2) * gi * gi;
@@ -112,9 +120,10 @@ struct StepArgs {
 
 // The loss workspace of a step, in floats: the SSIM term's partial sums
 // (one per 16 x 16 tile), the L1 term's (per tile with SSIM, else per
-// reduction block), the TV term's, then the SSIM gradient's three maps.
+// reduction block), the TV term's, the SSIM gradient's three maps, and the
+// crop branch's parameter gradient.
 struct LossParts {
-  uint64_t ssim, l1, tv, gmaps, total, n_tiles;
+  uint64_t ssim, l1, tv, gmaps, cgrad, total, n_tiles;
 };
 
 LossParts loss_parts(const StepArgs &a) {
@@ -126,7 +135,9 @@ LossParts loss_parts(const StepArgs &a) {
   P.l1 = up(P.n_tiles);
   P.tv = P.l1 + up(std::max<uint64_t>(P.n_tiles, kLossBlocks));
   P.gmaps = P.tv + up(kLossBlocks);
-  P.total = P.gmaps + (a.sp->ssim_weight > 0.f ? 3 * n_pix : 0);
+  // then, with a crop, the crop branch's parameter gradient (11 n floats)
+  P.cgrad = P.gmaps + up(a.sp->ssim_weight > 0.f ? 3 * n_pix : 0);
+  P.total = P.cgrad + (a.crop && a.sp->tv_weight > 0.f ? 11 * uint64_t(a.n) : 0);
   return P;
 }
 
@@ -165,12 +176,12 @@ StepVals step_vals(const StepArgs &a) {
   return s;
 }
 
-// The crop branch of a step (its binning, voxelization and TV) depends on
-// nothing the view's forward and backward compute, so it runs on a second
-// stream: forked from the step's stream once the step block is written,
-// joined before the voxelizer backward adds into the gradient that the
-// rasterizer backward has written. Its kernels are small and latency-bound,
-// so they overlap with the view's.
+// The crop branch of a step (its binning, voxelization, TV and voxelizer
+// backward into a gradient of its own) depends on nothing the view's
+// forward and backward compute, so it runs on a second stream: forked from
+// the step's stream once the step block is written, joined before Adam adds
+// its gradient to the view's. Its kernels are small and latency-bound, so
+// they overlap with the view's.
 struct Side {
   hipStream_t s = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
@@ -224,8 +235,17 @@ fgs_gaussians gauss(const StepArgs &a) {
   return fgs_gaussians{a.n, a.params->mean, a.params->log_scale, a.params->quat, a.params->density};
 }
 
-// The crop branch: the crop voxelized at the block's origin and the TV
-// term's gradient and partial sums (the TV prior of Eq. 5).
+// The crop branch's parameter gradient, in the loss workspace.
+fgs_gaussian_grads crop_param_grad(const StepArgs &a) {
+  float *c = static_cast<float *>(a.ws_loss->ptr) + loss_parts(a).cgrad;
+  const uint64_t n = uint64_t(a.n);
+  return fgs_gaussian_grads{c, c + 3 * n, c + 6 * n, c + 10 * n};
+}
+
+// The crop branch: the crop voxelized at the block's origin, the TV term's
+// gradient and partial sums (the TV prior of Eq. 5), and the voxelizer
+// backward of that gradient into the branch's own parameter gradient (the
+// Adam launch adds it to the view's).
 int crop_branch(const StepArgs &a, hipStream_t sc) {
   const fgs_gaussians g = gauss(a);
   const fgs_opts ov = crop_opts(a, 1, 0);
@@ -233,7 +253,11 @@ int crop_branch(const StepArgs &a, hipStream_t sc) {
   if (st != FGS_OK) return st;
   const LossParts LP = loss_parts(a);
   float *lp = static_cast<float *>(a.ws_loss->ptr);
-  return tv_partials(a.buf->crop_vol, a.crop->dims, a.sp->tv_weight, a.buf->crop_grad, lp + LP.tv, sc);
+  st = tv_partials(a.buf->crop_vol, a.crop->dims, a.sp->tv_weight, a.buf->crop_grad, lp + LP.tv, sc);
+  if (st != FGS_OK) return st;
+  const fgs_opts ob = crop_opts(a, 0, 0);
+  fgs_gaussian_grads cg = crop_param_grad(a);
+  return vox_backward(&g, a.crop, &ob, a.buf->crop_grad, &cg, a.ws_crop, sc, a.buf->params);
 }
 
 // The view branch: forward of the view, the loss of Eq. 5 (the L1 term's
@@ -265,25 +289,24 @@ int view_branch(const StepArgs &a, hipStream_t s) {
   return fgs_project_views_bwd(&g, a.geom, a.view, 1, &ob, buf->grad_img, a.grad, a.ws_proj, stream);
 }
 
-// The tail: the TV gradient through the voxelizer backward, added to the
-// rasterizer's (after both branches), then Adam on all parameters in one
-// launch, which also finishes the loss terms.
+// The tail (after both branches): Adam on all parameters in one launch,
+// which adds the crop branch's gradient to the view's (the sum is the step's
+// gradient, written to grad: the one fgs_voxelize_bwd accumulating onto
+// the rasterizer's gives, bit for bit) and finishes the loss terms.
 int tail(const StepArgs &a, hipStream_t s) {
   const fgs_step_params *sp = a.sp;
-  const fgs_gaussians g = gauss(a);
-  if (a.crop && sp->tv_weight > 0.f) {
-    const fgs_opts ov = crop_opts(a, 0, 1);
-    int st = vox_backward(&g, a.crop, &ov, a.buf->crop_grad, a.grad, a.ws_crop, s, a.buf->params);
-    if (st != FGS_OK) return st;
-  }
+  const bool tv = a.crop && sp->tv_weight > 0.f;
+  const fgs_gaussian_grads cg = tv ? crop_param_grad(a) : fgs_gaussian_grads{};
   AdamGroups A;
   float *P[4] = {a.params->mean, a.params->log_scale, a.params->quat, a.params->density};
-  const float *G[4] = {a.grad->mean, a.grad->log_scale, a.grad->quat, a.grad->density};
+  float *G[4] = {a.grad->mean, a.grad->log_scale, a.grad->quat, a.grad->density};
+  const float *G2[4] = {cg.mean, cg.log_scale, cg.quat, cg.density};
   float *M[4] = {a.m->mean, a.m->log_scale, a.m->quat, a.m->density};
   float *V[4] = {a.v->mean, a.v->log_scale, a.v->quat, a.v->density};
   for (int k = 0; k < 4; ++k) {
     A.p[k] = P[k];
     A.g[k] = G[k];
+    A.g2[k] = G2[k];
     A.m[k] = M[k];
     A.v[k] = V[k];
     A.lr[k] = sp->lr[k];

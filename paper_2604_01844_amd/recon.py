@@ -213,7 +213,7 @@ class ViewStep:
         self.params_blk = torch.zeros(8, device=dev)
         self.ws_proj = ops.Workspace(dev)
         self.ws_crop = ops.Workspace(dev)
-        self.ws_loss = ops.Workspace(dev, 12 * self.H * self.W + (1 << 16))
+        self.ws_loss = ops.Workspace(dev, 12 * self.H * self.W + 44 * model.n + (1 << 16))
         ops.project_views(*model.params, geom, 0, 1, kappa=kappa, near=near, ws=self.ws_proj)
         self.ws_proj.set_capacity(int(key_margin * self.ws_proj.n_pairs) + 4096)
         if tv is not None:
