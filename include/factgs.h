@@ -333,14 +333,15 @@ int fgs_recon_step(fgs_gaussians_out *params, fgs_gaussian_grads *m, fgs_gaussia
 
 /* The same step of one view captured in a HIP graph and replayed, for loops
  * that take many steps per view (400 epochs of 75 views in Sec. 4): a step
- * is then one small kernel (the per-call values into buf->params) and three
- * graph launches instead of about thirty-five kernel launches.
+ * is then two small kernels (the per-call values into buf->params, and
+ * Adam) and two graph launches instead of about thirty-five kernel launches.
  *
  * fgs_step_graph_capture takes fgs_recon_step's arguments (all of them
  * fixed for the graph's life: buffers, workspaces and their capacities,
  * view, gt, the loss weights, learning rates and crop dims), records the
- * step without running it (three graphs: the crop branch, the view's
- * forward, loss and backward, and Adam), and returns a handle.
+ * step without running it (two graphs, the crop branch and the view's
+ * forward, loss and backward, and the arguments of the Adam launch), and
+ * returns a handle.
  * Requires key_capacity > 0 in ws_proj and, with a crop, in ws_crop (a
  * captured step may not wait for the GPU). Errors as fgs_recon_step (on
  * FGS_E_CAPACITY grow the named workspace and capture again); no graph is

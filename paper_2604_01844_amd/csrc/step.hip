@@ -15,10 +15,11 @@
 // and Adam's bias corrections) are written by one small kernel into a device
 // block (fgs_step_buffers.params) that the rest of the step reads. The rest
 // can therefore be captured once per view in HIP graphs (fgs_step_graph_capture:
-// the crop branch, the view branch and the tail, one graph each) and replayed
-// for every later step of that view (fgs_step_graph_launch, the crop branch
-// again on the second stream): the replay runs the same kernels on the same
-// values as the direct call, and saves the per-kernel launch cost.
+// the crop branch and the view branch, one graph each, and the Adam launch's
+// arguments) and replayed for every later step of that view
+// (fgs_step_graph_launch, the crop branch again on the second stream): the
+// replay runs the same kernels on the same values as the direct call, and
+// saves the per-kernel launch cost.
 #include <algorithm>
 #include <cmath>
 #include <mutex>
@@ -292,30 +293,52 @@ int view_branch(const StepArgs &a, hipStream_t s) {
 // The tail (after both branches): Adam on all parameters in one launch,
 // which adds the crop branch's gradient to the view's (the sum is the step's
 // gradient, written to grad: the one fgs_voxelize_bwd accumulating onto
-// the rasterizer's gives, bit for bit) and finishes the loss terms.
-int tail(const StepArgs &a, hipStream_t s) {
+// the rasterizer's gives, bit for bit) and finishes the loss terms. Its
+// arguments depend on the step's arguments only, so a captured step keeps
+// them and launches the kernel itself.
+struct TailArgs {
+  AdamGroups A;
+  LossFinish F;
+  uint64_t n;
+  float b1, b2, eps;
+  const float *blk;
+};
+
+TailArgs tail_args(const StepArgs &a) {
   const fgs_step_params *sp = a.sp;
   const bool tv = a.crop && sp->tv_weight > 0.f;
   const fgs_gaussian_grads cg = tv ? crop_param_grad(a) : fgs_gaussian_grads{};
-  AdamGroups A;
+  TailArgs t{};
   float *P[4] = {a.params->mean, a.params->log_scale, a.params->quat, a.params->density};
   float *G[4] = {a.grad->mean, a.grad->log_scale, a.grad->quat, a.grad->density};
   const float *G2[4] = {cg.mean, cg.log_scale, cg.quat, cg.density};
   float *M[4] = {a.m->mean, a.m->log_scale, a.m->quat, a.m->density};
   float *V[4] = {a.v->mean, a.v->log_scale, a.v->quat, a.v->density};
   for (int k = 0; k < 4; ++k) {
-    A.p[k] = P[k];
-    A.g[k] = G[k];
-    A.g2[k] = G2[k];
-    A.m[k] = M[k];
-    A.v[k] = V[k];
-    A.lr[k] = sp->lr[k];
+    t.A.p[k] = P[k];
+    t.A.g[k] = G[k];
+    t.A.g2[k] = G2[k];
+    t.A.m[k] = M[k];
+    t.A.v[k] = V[k];
+    t.A.lr[k] = sp->lr[k];
   }
-  adam_groups_kernel<<<dim3(std::max(grid_for(uint64_t(a.n), 256), 3u), kAdamRows + 1), 256, 0, s>>>(
-      A, uint64_t(a.n), sp->beta1, sp->beta2, sp->eps, a.buf->params, loss_finish(a));
+  t.F = loss_finish(a);
+  t.n = uint64_t(a.n);
+  t.b1 = sp->beta1;
+  t.b2 = sp->beta2;
+  t.eps = sp->eps;
+  t.blk = a.buf->params;
+  return t;
+}
+
+int launch_tail(const TailArgs &t, hipStream_t s) {
+  adam_groups_kernel<<<dim3(std::max(grid_for(t.n, 256), 3u), kAdamRows + 1), 256, 0, s>>>(t.A, t.n, t.b1, t.b2,
+                                                                                           t.eps, t.blk, t.F);
   FGS_LAUNCH_CHECK("adam_groups_kernel");
   return FGS_OK;
 }
+
+int tail(const StepArgs &a, hipStream_t s) { return launch_tail(tail_args(a), s); }
 
 // Makes s wait for the crop branch when the step returns early (an error,
 // e.g. a workspace to grow) after forking it.
@@ -374,13 +397,13 @@ int set_params(float *blk, const StepVals &v, hipStream_t s) {
 using namespace fgs;
 
 // A captured step of one view: the instantiated graphs of its crop branch
-// (null without a crop), its view branch and its tail, and what a launch
-// must match. A launch runs the crop branch on the side stream beside the
+// (null without a crop) and its view branch, the tail's kernel arguments,
+// and what a launch must match. A launch runs the crop branch on the side stream beside the
 // view branch, as a direct step does.
 struct fgs_step_graph {
   hipGraphExec_t crop;
   hipGraphExec_t view_branch;
-  hipGraphExec_t tail;
+  fgs::TailArgs tail;
   float *params;
   int32_t view;
   int32_t crop_dims[3];
@@ -424,8 +447,7 @@ int capture(Fn &&fn, hipGraphExec_t *out) {
 void destroy_execs(fgs_step_graph &g) {
   if (g.crop) (void)hipGraphExecDestroy(g.crop);
   if (g.view_branch) (void)hipGraphExecDestroy(g.view_branch);
-  if (g.tail) (void)hipGraphExecDestroy(g.tail);
-  g.crop = g.view_branch = g.tail = nullptr;
+  g.crop = g.view_branch = nullptr;
 }
 
 // The calling device's shared side stream, created on first use; the
@@ -482,7 +504,7 @@ extern "C" int fgs_step_graph_capture(fgs_gaussians_out *params, fgs_gaussian_gr
   fgs_step_graph G{};
   if (tv) st = capture([&](hipStream_t cs) { return crop_branch(a, cs); }, &G.crop);
   if (st == FGS_OK) st = capture([&](hipStream_t cs) { return view_branch(a, cs); }, &G.view_branch);
-  if (st == FGS_OK) st = capture([&](hipStream_t cs) { return tail(a, cs); }, &G.tail);
+  G.tail = tail_args(a);
   if (st != FGS_OK) {
     destroy_execs(G);
     return st;
@@ -532,14 +554,13 @@ extern "C" int fgs_step_graph_launch(fgs_step_graph *gph, const fgs_step_params 
   const hipError_t e = hipGraphLaunch(gph->view_branch, s);
   if (side) FGS_HIP(hipStreamWaitEvent(s, side->join, 0));
   if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
-  FGS_HIP(hipGraphLaunch(gph->tail, s));
-  return FGS_OK;
+  return launch_tail(gph->tail, s);
 }
 
 extern "C" int fgs_step_graph_destroy(fgs_step_graph *gph) {
   if (!gph) return FGS_OK;
   hipError_t e = hipSuccess;
-  for (hipGraphExec_t x : {gph->crop, gph->view_branch, gph->tail})
+  for (hipGraphExec_t x : {gph->crop, gph->view_branch})
     if (x) {
       const hipError_t ex = hipGraphExecDestroy(x);
       if (e == hipSuccess) e = ex;
